@@ -1,0 +1,72 @@
+/*
+ * lp_oracle.h -- interface of the FP64 CPU reference (test infrastructure only).
+ * Used by the tests, the smoke check and the CPU-baseline leg of the benchmark;
+ * never by the product library.  See lp_oracle.c for the paper mapping.
+ */
+#ifndef LP_ORACLE_H
+#define LP_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { LPO_OK = 0, LPO_E_ARG = 1, LPO_E_CAPACITY = 2, LPO_E_NUMERIC = 3, LPO_E_NOMEM = 5 };
+
+enum {
+    LPO_FLAG_LIMITED = 1,      /* phi < 1: blended towards upwind */
+    LPO_FLAG_DEGENERATE = 2,   /* second-order fit rank deficient: linear fit, phi = 0 */
+    LPO_FLAG_VACUUM = 4,       /* half-ball completed by vacuum ghosts, phi = 0 */
+    LPO_FLAG_SUBSTITUTED = 8,  /* a half-ball fit failed: LW gradient used for that side */
+    LPO_FLAG_NUMERIC = 32      /* non-positive V or P after the update */
+};
+
+typedef struct {
+    int32_t dim;          /* 2 or 3 */
+    int32_t lw_cap;       /* 0 -> 54 (3D) / 32 (2D) */
+    int32_t uw_cap;       /* 0 -> 8, at most 64 */
+    int32_t max_nb;       /* neighbour-list capacity */
+    double gamma, cfl, kappa;
+    double est_eps;       /* estimator activity threshold */
+    double cond_max;      /* |R11|/|Rnn| above this: second-order fit rank deficient */
+    double uw_cond_max;   /* |R11|/|Rnn| above this: half-ball fit unusable */
+    double lo[3], hi[3];  /* box */
+    int32_t periodic[3];
+    int32_t wall_lo[3], wall_hi[3];
+    int32_t vacuum;       /* free boundary: vacuum ghosts complete half-balls */
+} lpo_cfg;
+
+double lpo_limiter(double r);
+double lpo_estimator_ratio(double sl, double sr);
+double lpo_lstsq_qrp(int k, int n, int nrhs, double *A, double *B, double *X);
+int lpo_lw_select(int dim, int k, const double *dxs, int cap, int *sel);
+void lpo_lw_rates(int dim, double gamma, double dt, const double *st, const double *grad,
+                  const double *hess, double *rate);
+void lpo_uw_rates(int dim, double gamma, const double *st, const double *dl, const double *dr,
+                  double *rate);
+int lpo_neighbors(const lpo_cfg *c, int64_t n, const double *x, const double *y, const double *z,
+                  const double *r, int32_t max_nb, int32_t *count, int32_t *idx);
+int lpo_gfd(const lpo_cfg *c, int64_t n, const double *x, const double *y, const double *z,
+            const double *r, int32_t nf, const double *const *f, double *deriv, uint8_t *status);
+double lpo_timestep(const lpo_cfg *c, int64_t n, const double *V, const double *P, const double *m);
+int lpo_step_subset(const lpo_cfg *c, int64_t n, const double *x, const double *y, const double *z,
+                    const double *V, const double *u, const double *v, const double *w,
+                    const double *P, const double *m, double dt_in, int64_t nsub, const int64_t *sub,
+                    double *ox, double *oy, double *oz, double *oV, double *ou, double *ov,
+                    double *ow, double *oP, double *ophi, uint8_t *oflags, double *dt_used,
+                    int64_t *n_ghost);
+int lpo_step(const lpo_cfg *c, int64_t n, double *x, double *y, double *z, double *V, double *u,
+             double *v, double *w, double *P, const double *m, double dt_in, double *phi,
+             uint8_t *flags, double *dt_used, int64_t *n_ghost);
+void lpo_conservation(const lpo_cfg *c, int64_t n, const double *V, const double *u, const double *v,
+                      const double *w, const double *P, const double *m, double *out);
+int lpo_particle_derivs(const lpo_cfg *c, int64_t n, const double *x, const double *y, const double *z,
+                        const double *V, const double *u, const double *v, const double *w,
+                        const double *P, int64_t i, const int32_t *list, int32_t k, double h, double s,
+                        double *grad, double *hess, double *dl, double *dr, int32_t *valid, double *phi,
+                        int32_t *flags);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,216 @@
+"""Seeded synthetic particle workloads (initial conditions only).
+
+This module builds particle sets and their initial states; it holds none of
+the method's arithmetic (no smoothing lengths, radii, time steps, fits or
+updates), so it can feed both the GPU library and the CPU oracle.  Every
+generator is deterministic in its seed (numpy PCG64).
+
+Workloads (γ = 1.4 everywhere):
+
+* ``pulse2d``   -- 2D pressure pulse, 64x64 jittered lattice on the periodic
+  unit square, ρ = 1, u = 0, p = 1 + 0.1 exp(-|x - ½|²/0.01), κ = 2.5.
+* ``sod3d``     -- 3D Sod shock tube on a jittered n³ lattice of [0,1]³,
+  (ρ, p) = (1, 1) for x < ½ and (0.125, 0.1) otherwise, mirror walls at
+  x = 0, 1, periodic in y and z, κ = 2.1.
+* ``vacuum3d``  -- 3D expansion into vacuum: equal-mass particles
+  rejection-sampled from ρ = exp(-|x|²/0.05) inside the ball of radius
+  √(0.05 ln 512), so ρ spans 512x and the particle spacing exactly 8x,
+  p = ρ^γ, u = 0, free boundary, κ = 2.2.
+* ``sedov3d``   -- 3D Sedov-type blast: jittered 2:1:1 lattice on
+  [0,2]x[0,1]², ρ = 1, p = 1e-5, energy 1 deposited as internal energy in the
+  27 lattice particles around the centre, periodic, κ = 2.1.
+* ``shear3d``   -- 3D shear layer: jittered n³ lattice of [0,1]³, periodic in
+  x, z, mirror walls at y = 0, 1, u_x = 0.5 tanh((y-½)/0.025),
+  u_y = 0.01 sin(2πx) exp(-((y-½)/0.05)²), ρ = 1.5 + 0.5 tanh((y-½)/0.025),
+  p = 2.5, κ = 2.1.
+
+Lattice particles sit at (i + ½)h plus a uniform jitter in (-0.2h, 0.2h) per
+coordinate; lattice masses are m = ρ(x) h^D so that every particle carries its
+own cell's mass.  The 2D workload runs at CFL 0.5; the 3D ones at CFL 0.2
+(the blended scheme's upwind part sums the 1D rates over the axes, which
+lowers its stable CFL number on scattered particles).  The Sod interface is
+spread over one particle spacing by a tanh profile.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+GAMMA = 1.4
+
+
+def base_config(name, dim, kappa, box_lo, box_hi, periodic, wall_lo=None, wall_hi=None, vacuum=False,
+                cfl=0.5, **extra):
+    d = dim
+    cfg = {
+        "name": name, "dim": d, "gamma": GAMMA, "cfl": cfl, "kappa": kappa,
+        "box_lo": list(box_lo), "box_hi": list(box_hi), "periodic": list(periodic),
+        "wall_lo": list(wall_lo or [False] * d), "wall_hi": list(wall_hi or [False] * d),
+        "vacuum": bool(vacuum), "max_nb": 128, "lw_cap": 0, "uw_cap": 0,
+        "est_eps": 1e-5, "cond_max": 1e12, "uw_cond_max": 1e2,
+    }
+    cfg.update(extra)
+    return cfg
+
+
+def jittered_lattice(shape, h, jitter=0.2, seed=0, origin=None):
+    """Points at (i + ½)h + U(-jitter h, jitter h) per coordinate, C order over shape."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = len(shape)
+    grids = np.meshgrid(*[np.arange(s, dtype=np.float64) for s in shape], indexing="ij")
+    idx = np.stack([g.reshape(-1) for g in grids], axis=1)
+    x = (idx + 0.5) * h
+    if jitter:
+        x = x + rng.uniform(-jitter * h, jitter * h, size=x.shape)
+    if origin is not None:
+        x = x + np.asarray(origin, dtype=np.float64)[None, :d]
+    return np.ascontiguousarray(x), idx.astype(np.int64)
+
+
+def _state(x, rho, u, p, m):
+    return {"x": np.ascontiguousarray(x, dtype=np.float64),
+            "u": np.ascontiguousarray(u, dtype=np.float64),
+            "V": np.ascontiguousarray(1.0 / rho, dtype=np.float64),
+            "P": np.ascontiguousarray(p, dtype=np.float64),
+            "m": np.ascontiguousarray(m, dtype=np.float64)}
+
+
+def pulse2d(n=64, seed=0, jitter=0.2, steps=10):
+    h = 1.0 / n
+    x, _ = jittered_lattice((n, n), h, jitter, seed)
+    rho = np.ones(x.shape[0])
+    r2 = ((x - 0.5) ** 2).sum(axis=1)
+    p = 1.0 + 0.1 * np.exp(-r2 / 0.01)
+    u = np.zeros_like(x)
+    m = rho * h * h
+    cfg = base_config("pulse2d", 2, 2.5, [0.0, 0.0], [1.0, 1.0], [True, True], steps=steps)
+    return cfg, _state(x, rho, u, p, m)
+
+
+def sod3d(n=64, seed=1, jitter=0.2, ny=None, nz=None, t_end=0.1, smooth=1.0):
+    """Sod tube along x; ny, nz (default n) set the periodic cross-section in cells of h = 1/n.
+
+    The initial jump at x = ½ is spread over ``smooth`` particle spacings by a
+    tanh profile (0 gives the sharp jump)."""
+    ny = n if ny is None else ny
+    nz = n if nz is None else nz
+    h = 1.0 / n
+    x, _ = jittered_lattice((n, ny, nz), h, jitter, seed)
+    if smooth > 0.0:
+        w = 0.5 * (1.0 + np.tanh((x[:, 0] - 0.5) / (smooth * h)))
+    else:
+        w = (x[:, 0] >= 0.5).astype(np.float64)
+    rho = 1.0 + (0.125 - 1.0) * w
+    p = 1.0 + (0.1 - 1.0) * w
+    u = np.zeros_like(x)
+    m = rho * h ** 3
+    cfg = base_config("sod3d", 3, 2.1, [0.0, 0.0, 0.0], [1.0, ny * h, nz * h], [False, True, True],
+                      wall_lo=[True, False, False], wall_hi=[True, False, False], t_end=t_end, cfl=0.2)
+    return cfg, _state(x, rho, u, p, m)
+
+
+def vacuum_ball_radius(a=0.05, ratio=512.0):
+    return math.sqrt(a * math.log(ratio))
+
+
+def vacuum3d(n_particles=2_097_152, seed=2, a=0.05, steps=20, box=1.0):
+    """Equal-mass particles rejection-sampled from ρ = exp(-|x|²/a) in the ball where ρ ≥ 1/512."""
+    R = vacuum_ball_radius(a)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    chunks = []
+    have = 0
+    while have < n_particles:
+        m = max(4096, int(1.3 * (n_particles - have) / 0.11) + 1024)
+        c = rng.uniform(-R, R, size=(m, 3))
+        r2 = (c * c).sum(axis=1)
+        keep = (r2 <= R * R) & (rng.uniform(0.0, 1.0, size=m) < np.exp(-r2 / a))
+        c = c[keep]
+        chunks.append(c)
+        have += c.shape[0]
+    x = np.concatenate(chunks, axis=0)[:n_particles]
+    r2 = (x * x).sum(axis=1)
+    rho = np.exp(-r2 / a)
+    z = R / math.sqrt(a)
+    total = 4.0 * math.pi * a ** 1.5 * (math.sqrt(math.pi) / 4.0 * math.erf(z) - 0.5 * z * math.exp(-z * z))
+    m = np.full(n_particles, total / n_particles)
+    p = rho ** GAMMA
+    u = np.zeros_like(x)
+    cfg = base_config("vacuum3d", 3, 2.2, [-box, -box, -box], [box, box, box], [False, False, False],
+                      vacuum=True, steps=steps, cfl=0.2, max_nb=256)
+    return cfg, _state(x, rho, u, p, m)
+
+
+def sedov3d(nx=256, seed=3, jitter=0.2, p_bg=1e-5, energy=1.0, steps=50):
+    ny = nz = nx // 2
+    h = 2.0 / nx
+    x, idx = jittered_lattice((nx, ny, nz), h, jitter, seed)
+    rho = np.ones(x.shape[0])
+    m = rho * h ** 3
+    p = np.full(x.shape[0], p_bg)
+    c = np.array([nx // 2, ny // 2, nz // 2])
+    hot = np.all(np.abs(idx - c[None, :]) <= 1, axis=1)
+    e = energy / (27.0 * m[hot])
+    p[hot] = (GAMMA - 1.0) * rho[hot] * e
+    u = np.zeros_like(x)
+    cfg = base_config("sedov3d", 3, 2.1, [0.0, 0.0, 0.0], [2.0, 1.0, 1.0], [True, True, True], steps=steps,
+                      cfl=0.2)
+    return cfg, _state(x, rho, u, p, m)
+
+
+def shear3d(n=256, seed=4, jitter=0.2, steps=100):
+    h = 1.0 / n
+    x, _ = jittered_lattice((n, n, n), h, jitter, seed)
+    y = x[:, 1]
+    t = np.tanh((y - 0.5) / 0.025)
+    u = np.zeros_like(x)
+    u[:, 0] = 0.5 * t
+    u[:, 1] = 0.01 * np.sin(2.0 * math.pi * x[:, 0]) * np.exp(-((y - 0.5) / 0.05) ** 2)
+    rho = 1.5 + 0.5 * t
+    p = np.full(x.shape[0], 2.5)
+    m = rho * h ** 3
+    cfg = base_config("shear3d", 3, 2.1, [0.0, 0.0, 0.0], [1.0, 1.0, 1.0], [True, False, True],
+                      wall_lo=[False, True, False], wall_hi=[False, True, False], steps=steps, cfl=0.2)
+    return cfg, _state(x, rho, u, p, m)
+
+
+def uniform_box(dim, n, seed=5, jitter=0.2, periodic=True, kappa=None, rho=1.0, p=1.0, u0=None):
+    """Jittered lattice with a constant state (optionally a constant velocity)."""
+    h = 1.0 / n
+    x, _ = jittered_lattice((n,) * dim, h, jitter, seed)
+    N = x.shape[0]
+    u = np.zeros_like(x)
+    if u0 is not None:
+        u[:] = np.asarray(u0, dtype=np.float64)[None, :dim]
+    rr = np.full(N, rho)
+    cfg = base_config("uniform%dd" % dim, dim, kappa or (2.5 if dim == 2 else 2.1), [0.0] * dim, [1.0] * dim,
+                      [periodic] * dim, cfl=0.5 if dim == 2 else 0.2)
+    return cfg, _state(x, rr, u, np.full(N, p), rr * h ** dim)
+
+
+def smooth_wave(dim, n, seed=6, jitter=0.2, amp=1e-2):
+    """Jittered periodic lattice with a smooth, fully 3D (or 2D) acoustic perturbation."""
+    h = 1.0 / n
+    x, _ = jittered_lattice((n,) * dim, h, jitter, seed)
+    N = x.shape[0]
+    ph = 2.0 * math.pi * x
+    s = np.sin(ph[:, 0])
+    for a in range(1, dim):
+        s = s + 0.5 * np.cos(ph[:, a] + 0.3 * a)
+    rho = 1.0 + amp * s
+    p = 1.0 + GAMMA * amp * s
+    u = np.zeros_like(x)
+    for a in range(dim):
+        u[:, a] = amp * np.sin(ph[:, (a + 1) % dim] + 0.7 * a)
+    cfg = base_config("wave%dd" % dim, dim, 2.5 if dim == 2 else 2.1, [0.0] * dim, [1.0] * dim, [True] * dim,
+                      cfl=0.5 if dim == 2 else 0.2)
+    return cfg, _state(x, rho, u, p, rho * h ** dim)
+
+
+WORKLOADS = {
+    "pulse2d": pulse2d,
+    "sod3d": sod3d,
+    "vacuum3d": vacuum3d,
+    "sedov3d": sedov3d,
+    "shear3d": shear3d,
+}

@@ -1,0 +1,132 @@
+"""Pins of the full oracle time step (Sec. 2.1 and Sec. 2.2 steps 1-6)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2206_11998_amd import workloads as W
+from tests import riemann
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_limiter_properties(oracle_lib):
+    lim = oracle_lib.limiter
+    assert lim(1.0) == 1.25  # exp(1 - sqrt(1)) = 1
+    assert lim(float("inf")) == 0.0
+    rs = np.linspace(1.0, 40.0, 2000)
+    v = np.array([lim(r) for r in rs])
+    assert np.all(np.diff(v) < 0)
+    assert abs(lim(1.5) - lim(1.5 + 1e-12)) < 3e-3
+    assert lim(1.5) < 1.0 < lim(1.49)  # the two branches meet just below one
+
+
+def test_estimator_ratio(oracle_lib):
+    q = oracle_lib.estimator_ratio
+    assert q(2.0, 2.0) == 1.0
+    assert q(1.0, -1.0) == float("inf") and q(0.0, 3.0) == float("inf")
+    rng = np.random.default_rng(0)
+    for a, b in rng.uniform(0.01, 10, size=(100, 2)):
+        assert q(a, b) == q(b, a) and q(a, b) >= 1.0 and q(-a, -b) == q(a, b)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_constant_state_is_bit_invariant(oracle_lib, dim):
+    """Pin P9: a uniform state stays bit-identical; particles translate by dt u."""
+    cfg, st = W.uniform_box(dim, 24 if dim == 2 else 10, u0=[0.3, -0.2, 0.1], p=1.7, rho=0.8)
+    new, info = oracle_lib.step(cfg, st)
+    assert info["status"] == 0
+    assert np.array_equal(new["V"], st["V"]) and np.array_equal(new["P"], st["P"])
+    assert np.array_equal(new["u"], st["u"])
+    dt = info["dt"]
+    x = st["x"] + dt * st["u"]
+    x = np.where(x >= 1.0, x - 1.0, np.where(x < 0.0, x + 1.0, x))
+    assert np.array_equal(new["x"], x)
+
+
+def test_timestep_rule(oracle_lib):
+    cfg, st = W.pulse2d()
+    h = np.sqrt(st["m"] * st["V"])
+    c = np.sqrt(cfg["gamma"] * st["P"] * st["V"])
+    assert oracle_lib.timestep(cfg, st) == cfg["cfl"] * np.min(h / c)
+
+
+def test_mass_and_count_conserved(oracle_lib):
+    cfg, st = W.pulse2d()
+    m0 = oracle_lib.conservation(cfg, st)[0]
+    s = st
+    for _ in range(3):
+        s, info = oracle_lib.step(cfg, s)
+        assert info["status"] == 0
+    assert s["V"].shape == st["V"].shape
+    assert oracle_lib.conservation(cfg, s)[0] == m0
+
+
+def _mirror_pair_lattice(n, seed):
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    half = []
+    for i in range(n // 2):
+        for j in range(n):
+            half.append(((i + 0.5) * h + rng.uniform(-0.2, 0.2) * h, (j + 0.5) * h + rng.uniform(-0.2, 0.2) * h))
+    half = np.array(half)
+    other = half.copy()
+    other[:, 0] = 1.0 - other[:, 0]
+    return np.concatenate([half, other]), half.shape[0]
+
+
+def test_mirror_symmetry(oracle_lib):
+    """x -> 1 - x symmetric data stays symmetric (catches left/right and sign slips)."""
+    x, nh = _mirror_pair_lattice(48, 3)
+    cfg, _ = W.pulse2d(n=48)
+    rho = 1.0 + 0.2 * np.exp(-((x[:, 0] - 0.5) ** 2 + (x[:, 1] - 0.4) ** 2) / 0.02)
+    p = rho ** 1.4
+    u = np.zeros_like(x)
+    u[:, 0] = 0.1 * np.sin(2 * np.pi * x[:, 0])
+    u[:, 1] = 0.05 * np.cos(2 * np.pi * x[:, 0])
+    st = {"x": x, "u": u, "V": 1 / rho, "P": p, "m": rho / 48 ** 2}
+    s = st
+    for _ in range(3):
+        s, info = oracle_lib.step(cfg, s)
+        assert info["status"] == 0
+    a, b = slice(0, nh), slice(nh, 2 * nh)
+    assert np.allclose(s["P"][a], s["P"][b], rtol=1e-11, atol=0)
+    assert np.allclose(s["V"][a], s["V"][b], rtol=1e-11, atol=0)
+    assert np.allclose(s["u"][a, 0], -s["u"][b, 0], rtol=0, atol=1e-12)
+    assert np.allclose(s["u"][a, 1], s["u"][b, 1], rtol=0, atol=1e-12)
+    assert np.allclose(s["x"][a, 0], 1.0 - s["x"][b, 0], rtol=0, atol=1e-12)
+    assert (info["flags"] & 1).sum() > 0  # the estimator did act
+
+
+def test_exact_riemann_solver_pin():
+    gold = json.load(open(os.path.join(GOLD, "sod_star.json")))
+    p, u = riemann.star_state(1.0, 0.0, 1.0, 0.125, 0.0, 0.1)
+    assert abs(p - gold["p_star"]) < 1e-5 and abs(u - gold["u_star"]) < 1e-5
+
+
+def _sod_l1(oracle_lib, n):
+    cfg, s = W.sod3d(n=n, ny=6, nz=6)
+    t, T = 0.0, 0.1
+    while t < T - 1e-14:
+        dt = min(oracle_lib.timestep(cfg, s), T - t)
+        s, info = oracle_lib.step(cfg, s, dt)
+        assert info["status"] == 0
+        t += dt
+    x = s["x"][:, 0]
+    ex = riemann.sample(x, T, 0.5, 1.0, 0.0, 1.0, 0.125, 0.0, 0.1)
+    rho = 1.0 / s["V"]
+    return np.mean(np.abs(rho - ex[:, 0])), np.mean(np.abs(s["P"] - ex[:, 2])), s
+
+
+def test_sod_converges_to_exact_solution(oracle_lib):
+    """Pin P10: the density and pressure L1 errors against the exact Riemann
+    solution shrink under refinement, and the wall ghosts keep the tube closed."""
+    e32 = _sod_l1(oracle_lib, 32)
+    e64 = _sod_l1(oracle_lib, 64)
+    e128 = _sod_l1(oracle_lib, 128)
+    assert e64[0] < 0.8 * e32[0] and e128[0] < 0.8 * e64[0]
+    assert e64[1] < 0.8 * e32[1] and e128[1] < 0.8 * e64[1]
+    assert e128[0] < 0.02
+    x = e128[2]["x"][:, 0]
+    assert x.min() > 0.0 and x.max() < 1.0
