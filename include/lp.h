@@ -1,0 +1,174 @@
+/*
+ * lp.h -- C ABI of liblp, an MI355X (gfx950) implementation of the hot path of
+ * the Lagrangian particle (LP) method of Yuan, Zepeda Aguilar, Naitlho &
+ * Samulyak, "Massively-Parallel Lagrangian Particle Code and Applications"
+ * (arXiv 2206.11998):
+ *
+ *   neighbour search (Sec. 2.2, step 3), generalized-finite-difference
+ *   least-squares fits (Sec. 2.1, GFD system and its QR solution), and the
+ *   unsplit Lax-Wendroff update blended with first-order upwind where the
+ *   state estimator selects a particle (Sec. 2.1, blend, estimator, limiter),
+ *   followed by the particle mover (Sec. 2.1, mover; Sec. 2.2, step 6).
+ *
+ * Conventions (all entry points):
+ *  - Every call returns an lp_status; nothing throws across the ABI.  On error
+ *    lp_last_error() holds a message.
+ *  - Particle arrays are structure-of-arrays DEVICE pointers owned by the
+ *    caller; the library never frees them.  Indices in and out are the
+ *    caller's particle indices (0..n-1); internal orderings never leak out.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Work is enqueued asynchronously on it; only calls documented as
+ *    synchronising wait for it.
+ *  - A context is not thread-safe; use one per stream.  The library allocates
+ *    its own device workspace, grown on demand and kept until lp_destroy().
+ *  - Errors found by kernels (list capacity overflow, non-positive V or P after
+ *    an update) accumulate in the context and are reported by lp_check().
+ */
+#ifndef LP_H
+#define LP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lp_status;
+enum {
+    LP_OK = 0,
+    LP_E_ARG = 1,       /* invalid argument or configuration */
+    LP_E_CAPACITY = 2,  /* a neighbour list exceeded max_nb (counts are still true counts) */
+    LP_E_NUMERIC = 3,   /* non-positive specific volume or pressure after an update */
+    LP_E_DEVICE = 4,    /* HIP runtime error */
+    LP_E_NOMEM = 5,     /* device allocation failed */
+    LP_E_STATE = 6      /* call sequence error */
+};
+
+enum { LP_FP64 = 0, LP_MIXED = 1 };                         /* lp_config.precision */
+enum { LP_EST_PLAIN = 0, LP_EST_INJECTED = 1, LP_EST_MLP = 2 }; /* lp_config.estimator */
+
+/* Per-particle flag bits written to lp_particles.flags. */
+enum {
+    LP_FLAG_LIMITED = 1,      /* phi < 1: blended towards upwind */
+    LP_FLAG_DEGENERATE = 2,   /* second-order fit rank deficient: linear fit, phi = 0 */
+    LP_FLAG_VACUUM = 4,       /* a half-ball was completed by vacuum ghosts, phi = 0 */
+    LP_FLAG_SUBSTITUTED = 8,  /* a half-ball fit was unusable: LW gradient used for that side */
+    LP_FLAG_FALLBACK = 16,    /* the FP64 pivoted-QR path solved this particle */
+    LP_FLAG_NUMERIC = 32      /* non-positive V or P after the update */
+};
+
+typedef struct lp_config {
+    int32_t dim;            /* 2 or 3 */
+    int32_t precision;      /* LP_FP64 or LP_MIXED (FP32 gathers/fits, FP64 state) */
+    int32_t estimator;      /* LP_EST_* */
+    int32_t max_nb;         /* neighbour-list capacity per particle, 1..256 */
+    int32_t lw_cap;         /* Lax-Wendroff stencil size; 0 -> 54 (3D) / 32 (2D); at most 64 */
+    int32_t uw_cap;         /* upwind half-ball size; 0 -> 8; at most 16 */
+    int32_t refine;         /* LP_MIXED: 1 = one FP64-residual refinement of the fit */
+    int32_t vacuum;         /* free boundary: incomplete half-balls get vacuum ghosts */
+    double gamma;           /* ideal-gas exponent */
+    double cfl;             /* dt = cfl * min_i h_i / c_i */
+    double kappa;           /* search radius r_i = kappa * h_i, h_i = (m_i V_i)^(1/dim) */
+    double est_eps;         /* estimator activity threshold (relative, per h) */
+    double cond_max;        /* pivoted |R11|/|Rnn| above this: 2nd-order fit deficient */
+    double uw_cond_max;     /* pivoted |R11|/|Rnn| above this: half-ball fit unusable */
+    double cond_fallback;   /* fast fit: normal-matrix condition estimate above this -> FP64 QR */
+    double box_lo[3];       /* domain box; periodic extents must be S / 2^j of the */
+    double box_hi[3];       /*   largest extent S */
+    uint32_t periodic_mask; /* bit a: axis a periodic (minimum image, wrap on move) */
+    uint32_t wall_lo_mask;  /* bit a: mirror wall at box_lo[a] */
+    uint32_t wall_hi_mask;  /* bit a: mirror wall at box_hi[a] */
+    int32_t reserved[9];
+} lp_config;
+
+typedef struct lp_particles {
+    int64_t n;              /* number of particles */
+    double *x[3];           /* positions (x[2] unused in 2D); advanced in place */
+    double *V;              /* specific volume 1/rho; advanced in place */
+    double *u[3];           /* velocity; advanced in place */
+    double *P;              /* pressure; advanced in place */
+    const double *m;        /* mass (constant) */
+    float *phi;             /* out: limiter value per particle (in with LP_EST_INJECTED); may be NULL */
+    uint8_t *flags;         /* out: LP_FLAG_* bits; may be NULL */
+} lp_particles;
+
+typedef struct lp_info {
+    double t;               /* time accumulated by lp_step / lp_run */
+    double dt;              /* last time step */
+    int64_t n_ghost;        /* mirror ghosts of the last step */
+    int32_t max_count;      /* largest neighbour count of the last search */
+    int32_t n_fallback;     /* particles solved by the FP64 pivoted-QR path in the last step */
+    int64_t n_limited;      /* particles with phi < 1 in the last step */
+    uint32_t error_bits;    /* bit 0: capacity overflow, bit 1: numeric */
+    int32_t levels[2];      /* cell-grid levels used by the last search (coarsest, finest) */
+} lp_info;
+
+/* Fill cfg with the defaults for the given dimension (gamma 1.4, cfl 0.5,
+ * kappa 2.5 / 2.1, max_nb 128, est_eps 1e-5, cond_max 1e12, uw_cond_max 1e2,
+ * cond_fallback 1e6, unit box, fully periodic). */
+void lp_config_default(lp_config *cfg, int32_t dim);
+
+/* Create / destroy a context.  lp_create validates cfg (LP_E_ARG on failure)
+ * and selects the HIP device that is current on the calling thread. */
+lp_status lp_create(const lp_config *cfg, struct lp_ctx **ctx);
+lp_status lp_destroy(struct lp_ctx *ctx);
+
+/* Neighbour search (Sec. 2.2, step 3): for each i < n,
+ *   N(i) = { j != i : d2(i, j) < r[i]^2 },
+ *   d2 = ((dx*dx) + (dy*dy)) + (dz*dz) in IEEE binary64 without contraction,
+ *   dx = minimum-image displacement on periodic axes of the context's box,
+ * ordered by (d2, j).  count[i] receives |N(i)| (the true count even when it
+ * exceeds max_nb); idx[i * max_nb + c] receives the c-th member for
+ * c < min(count[i], max_nb).  x, y, z, r: device arrays of n doubles (z is
+ * ignored in 2D); count: n int32; idx: n * max_nb int32.  Returns
+ * LP_E_CAPACITY (after a synchronisation) when a count exceeds max_nb.
+ * Mirror walls are not applied. */
+lp_status lp_neighbors(struct lp_ctx *ctx, void *stream, int64_t n, const double *x, const double *y,
+                       const double *z, const double *r, int32_t *count, int32_t *idx);
+
+/* Second-order GFD derivatives (Sec. 2.1): for each particle i, the
+ * least-squares fit over its Lax-Wendroff stencil (neighbours within r[i],
+ * octant round-robin order, first lw_cap) of
+ *   f_j - f_i = sum_a d_a f dx_a + 1/2 sum_a d_aa f dx_a^2 + sum_{a<b} d_ab f dx_a dx_b.
+ * f: host array of nf (1..5) device pointers to n doubles each.
+ * deriv: device, nf * nu * n doubles, deriv[(f * nu + c) * n + i] with nu = 9
+ * (3D: x, y, z, xx, yy, zz, xy, xz, yz) or 5 (2D: x, y, xx, yy, xy).
+ * status: device, n bytes: 0 = second-order fit, 1 = rank deficient (linear
+ * fit, second derivatives 0), 2 = fewer than dim usable neighbours (all 0).
+ * Always solved in FP64. */
+lp_status lp_gfd(struct lp_ctx *ctx, void *stream, int64_t n, const double *x, const double *y,
+                 const double *z, const double *r, int32_t nf, const double *const *f, double *deriv,
+                 uint8_t *status);
+
+/* One time step (Sec. 2.2, steps 1-6) of the particle set p, in place:
+ * dt > 0 is used as given, dt <= 0 selects cfl * min_i h_i / c_i.
+ * Synchronises once (to size the cell grid).  Mass is never modified. */
+lp_status lp_step(struct lp_ctx *ctx, void *stream, const lp_particles *p, double dt);
+
+/* Advance p by nsteps CFL-limited steps or until the accumulated time reaches
+ * t_end (t_end <= 0: no limit); the last step is shortened to end on t_end.
+ * The steps are captured once into a HIP graph and replayed; dt and t stay on
+ * the device. */
+lp_status lp_run(struct lp_ctx *ctx, void *stream, const lp_particles *p, int32_t nsteps, double t_end);
+
+/* Totals in FP64: out[0] = sum m, out[1..3] = sum m u, out[4] = sum m (e + |u|^2/2),
+ * e = P V / (gamma - 1).  out is a host array of 5 doubles.  Synchronises. */
+lp_status lp_conservation(struct lp_ctx *ctx, void *stream, const lp_particles *p, double *out);
+
+/* Synchronise and report kernel-side errors of all work since the last
+ * check (LP_E_CAPACITY / LP_E_NUMERIC), then clear them. */
+lp_status lp_check(struct lp_ctx *ctx, void *stream);
+
+/* Synchronise and copy the diagnostics of the last step to *out (host). */
+lp_status lp_get_info(struct lp_ctx *ctx, void *stream, lp_info *out);
+
+/* Set the accumulated time (host value). */
+lp_status lp_set_time(struct lp_ctx *ctx, void *stream, double t);
+
+const char *lp_status_str(lp_status s);
+const char *lp_last_error(const struct lp_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,639 @@
+// lp_api.hip -- the C ABI of liblp (declared in include/lp.h): context,
+// device workspace and the orchestration of one LP time step (Sec. 2.2,
+// steps 1-6) as a sequence of kernels on the caller's stream.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "lp_internal.h"
+
+static double bits_to_double(unsigned long long b) {
+    double d;
+    memcpy(&d, &b, sizeof d);
+    return d;
+}
+
+struct Buf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct lp_ctx {
+    lp_config cfg;
+    DevCfg dc;
+    int device = 0;
+    std::string err;
+    // workspace
+    Buf h, r, gcnt, scan_tmp, ghosts, key, slot, tables, sorted, sortedf, sid, nbr, count, queue, partials, consout,
+        gfd_fields;
+    DevScalars *sc = nullptr;       // device scalars
+    DevScalars *sc_host = nullptr;  // pinned copy
+    int nwalls = 0;
+    double S = 1.0;                 // cube side of the cell grids
+    int jper[3] = {0, 0, 0};        // periodic extent = S / 2^jper
+    int search_group = 16;
+    int64_t cap_real = 0, cap_total = 0, cap_ghost = 0;
+    bool run_done = false;
+    DevGrid grid;
+    int last_levels[2] = {0, 0};
+    // lp_run graph
+    hipGraphExec_t graph = nullptr;
+    lp_particles graph_p;
+    int64_t graph_n = -1;
+};
+
+static lp_status fail(lp_ctx *c, lp_status s, const char *fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return s;
+}
+
+#define HIPCHK(ctx, call)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) return fail(ctx, LP_E_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+static lp_status ensure(lp_ctx *c, Buf &b, size_t bytes) {
+    if (b.bytes >= bytes) return LP_OK;
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    size_t want = bytes + bytes / 8 + 256;
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, LP_E_NOMEM, "device allocation of %zu bytes failed", want);
+    }
+    b.bytes = want;
+    return LP_OK;
+}
+
+#define ENSURE(ctx, buf, bytes)                        \
+    do {                                               \
+        lp_status s_ = ensure(ctx, buf, bytes);        \
+        if (s_ != LP_OK) return s_;                    \
+    } while (0)
+
+extern "C" void lp_config_default(lp_config *cfg, int32_t dim) {
+    memset(cfg, 0, sizeof *cfg);
+    cfg->dim = dim;
+    cfg->precision = LP_FP64;
+    cfg->estimator = LP_EST_PLAIN;
+    cfg->max_nb = 128;
+    cfg->refine = 1;
+    cfg->gamma = 1.4;
+    cfg->cfl = 0.5;
+    cfg->kappa = dim == 2 ? 2.5 : 2.1;
+    cfg->est_eps = 1e-5;
+    cfg->cond_max = 1e12;
+    cfg->uw_cond_max = 1e2;
+    cfg->cond_fallback = 1e6;
+    for (int a = 0; a < 3; ++a) { cfg->box_lo[a] = 0.0; cfg->box_hi[a] = 1.0; }
+    cfg->periodic_mask = dim == 2 ? 3u : 7u;
+}
+
+extern "C" const char *lp_status_str(lp_status s) {
+    switch (s) {
+    case LP_OK: return "ok";
+    case LP_E_ARG: return "invalid argument";
+    case LP_E_CAPACITY: return "neighbour list capacity exceeded";
+    case LP_E_NUMERIC: return "non-positive volume or pressure";
+    case LP_E_DEVICE: return "HIP runtime error";
+    case LP_E_NOMEM: return "out of device memory";
+    case LP_E_STATE: return "invalid call sequence";
+    default: return "unknown status";
+    }
+}
+
+extern "C" const char *lp_last_error(const lp_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+static bool is_pow2_ratio(double big, double small, int *j) {
+    double q = big / small;
+    int e = (int)llround(log2(q));
+    if (e < 0 || e > 12) return false;
+    if (fabs(ldexp(small, e) - big) > 1e-12 * big) return false;
+    *j = e;
+    return true;
+}
+
+extern "C" lp_status lp_create(const lp_config *cfg, lp_ctx **out) {
+    if (!cfg || !out) return LP_E_ARG;
+    *out = nullptr;
+    lp_ctx *c = new lp_ctx();
+    c->cfg = *cfg;
+    const lp_config &k = *cfg;
+    lp_status st = LP_OK;
+    if (k.dim != 2 && k.dim != 3) st = fail(c, LP_E_ARG, "dim must be 2 or 3");
+    else if (k.max_nb < 1 || k.max_nb > 256) st = fail(c, LP_E_ARG, "max_nb must be in 1..256");
+    else if (k.lw_cap < 0 || k.lw_cap > 64) st = fail(c, LP_E_ARG, "lw_cap must be in 0..64");
+    else if (k.uw_cap < 0 || k.uw_cap > 16) st = fail(c, LP_E_ARG, "uw_cap must be in 0..16");
+    else if (k.precision != LP_FP64 && k.precision != LP_MIXED) st = fail(c, LP_E_ARG, "bad precision");
+    else if (k.estimator != LP_EST_PLAIN && k.estimator != LP_EST_INJECTED)
+        st = fail(c, LP_E_ARG, "estimator mode not available in this build");
+    else if (!(k.gamma > 1.0) || !(k.kappa > 0.0) || !(k.cfl > 0.0)) st = fail(c, LP_E_ARG, "gamma, kappa, cfl");
+    if (st == LP_OK) {
+        double S = 0.0;
+        for (int a = 0; a < k.dim; ++a) {
+            double e = k.box_hi[a] - k.box_lo[a];
+            if (!(e > 0.0)) { st = fail(c, LP_E_ARG, "empty box on axis %d", a); break; }
+            if (e > S) S = e;
+        }
+        c->S = S;
+        for (int a = 0; a < k.dim && st == LP_OK; ++a) {
+            bool per = (k.periodic_mask >> a) & 1u;
+            bool wall = ((k.wall_lo_mask | k.wall_hi_mask) >> a) & 1u;
+            if (per && wall) st = fail(c, LP_E_ARG, "axis %d is both periodic and walled", a);
+            if (per && !is_pow2_ratio(S, k.box_hi[a] - k.box_lo[a], &c->jper[a]))
+                st = fail(c, LP_E_ARG, "periodic extent of axis %d must be the largest extent / 2^j", a);
+        }
+    }
+    if (st != LP_OK) {
+        fprintf(stderr, "lp_create: %s\n", c->err.c_str());
+        delete c;
+        return st;
+    }
+    DevCfg &d = c->dc;
+    memset(&d, 0, sizeof d);
+    d.D = k.dim;
+    d.nu = k.dim == 3 ? 9 : 5;
+    d.nf = k.dim + 2;
+    d.lw_cap = k.lw_cap > 0 ? k.lw_cap : (k.dim == 3 ? 54 : 32);
+    d.uw_cap = k.uw_cap > 0 ? k.uw_cap : 8;
+    d.max_nb = k.max_nb;
+    d.vacuum = k.vacuum;
+    d.est_mode = k.estimator;
+    d.precision = k.precision;
+    d.refine = k.refine;
+    d.gamma = k.gamma;
+    d.kappa = k.kappa;
+    d.cfl = k.cfl;
+    d.est_eps = k.est_eps;
+    d.cond_max = k.cond_max;
+    d.uw_cond_max = k.uw_cond_max;
+    d.cond_fb = k.cond_fallback;
+    for (int a = 0; a < 3; ++a) {
+        d.lo[a] = k.box_lo[a];
+        d.hi[a] = k.box_hi[a];
+        d.L[a] = k.box_hi[a] - k.box_lo[a];
+        d.half[a] = 0.5 * d.L[a];
+        d.periodic[a] = a < k.dim ? (int)((k.periodic_mask >> a) & 1u) : 0;
+        d.wall_lo[a] = a < k.dim ? (int)((k.wall_lo_mask >> a) & 1u) : 0;
+        d.wall_hi[a] = a < k.dim ? (int)((k.wall_hi_mask >> a) & 1u) : 0;
+        c->nwalls += d.wall_lo[a] + d.wall_hi[a];
+    }
+    (void)hipGetDevice(&c->device);
+    if (hipMalloc((void **)&c->sc, sizeof(DevScalars)) != hipSuccess ||
+        hipHostMalloc((void **)&c->sc_host, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return LP_E_NOMEM;
+    }
+    memset(c->sc_host, 0, sizeof(DevScalars));
+    if (hipMemcpy(c->sc, c->sc_host, sizeof(DevScalars), hipMemcpyHostToDevice) != hipSuccess) {
+        delete c;
+        return LP_E_DEVICE;
+    }
+    *out = c;
+    return LP_OK;
+}
+
+extern "C" lp_status lp_destroy(lp_ctx *c) {
+    if (!c) return LP_E_ARG;
+    (void)hipDeviceSynchronize();
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    Buf *bufs[] = {&c->h, &c->r, &c->gcnt, &c->scan_tmp, &c->ghosts, &c->key, &c->slot, &c->tables, &c->sorted,
+                   &c->sortedf, &c->sid, &c->nbr, &c->count, &c->queue, &c->partials, &c->consout, &c->gfd_fields};
+    for (Buf *b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    if (c->sc) (void)hipFree(c->sc);
+    if (c->sc_host) (void)hipHostFree(c->sc_host);
+    delete c;
+    return LP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Grid levels from the radius range: the finest level has cells no larger
+// than r_min (bounded by a table of 2^27 cells), the coarsest no larger than
+// r_max; periodic axes need whole cells per period.
+// ---------------------------------------------------------------------------
+static void choose_levels(lp_ctx *c, double rmin, double rmax) {
+    const int D = c->dc.D;
+    const int Lmax = D == 3 ? 9 : 13;
+    int jmin = 0;
+    for (int a = 0; a < D; ++a)
+        if (c->dc.periodic[a] && c->jper[a] > jmin) jmin = c->jper[a];
+    auto level_le = [&](double r) {
+        int L = 0;
+        while (L < Lmax && ldexp(c->S, -L) > r) ++L;
+        return L;
+    };
+    int hi = level_le(rmin > 0 ? rmin : c->S);
+    int lo = level_le(rmax > 0 ? rmax : c->S);
+    if (hi < jmin) hi = jmin;
+    if (lo < jmin) lo = jmin;
+    if (lo > hi) lo = hi;
+    if (hi - lo > 6) lo = hi - 6;
+    DevGrid &g = c->grid;
+    memset(&g, 0, sizeof g);
+    g.L_lo = lo;
+    g.L_hi = hi;
+    unsigned long long off = 0;
+    for (int L = 0; L < LP_MAX_LEVEL; ++L) {
+        g.s[L] = ldexp(c->S, -L);
+        g.inv_s[L] = ldexp(1.0 / c->S, L);
+        for (int a = 0; a < 3; ++a) {
+            if (a >= D) { g.nc[L][a] = 1; continue; }
+            int n = 1 << L;
+            if (c->dc.periodic[a]) n = L >= c->jper[a] ? (1 << (L - c->jper[a])) : 1;
+            g.nc[L][a] = n;
+        }
+        if (L >= lo && L <= hi) {
+            g.off[L] = off;
+            off += (1ull << (D * L)) + 1;
+        }
+    }
+    for (int a = 0; a < 3; ++a) g.lo[a] = a < D ? c->dc.lo[a] : 0.0;
+    c->last_levels[0] = lo;
+    c->last_levels[1] = hi;
+}
+
+static uint64_t table_words(const lp_ctx *c) {
+    const DevGrid &g = c->grid;
+    uint64_t w = 0;
+    for (int L = g.L_lo; L <= g.L_hi; ++L) w += (1ull << (c->dc.D * L)) + 1;
+    return w;
+}
+
+// Allocate everything that depends on the particle counts and the grid.
+// Arrays in cell order use the capacity cap_total as their stride.
+static lp_status ensure_capacity(lp_ctx *c, int64_t n_real, int64_t n_total, bool state, bool mixed) {
+    const int D = c->dc.D;
+    if (n_total > c->cap_total) c->cap_total = n_total;
+    if (n_real > c->cap_real) c->cap_real = n_real;
+    if (n_total - n_real > c->cap_ghost) c->cap_ghost = n_total - n_real;
+    const int64_t nt = c->cap_total, nr = c->cap_real, ng = c->cap_ghost;
+    ENSURE(c, c->h, sizeof(double) * nr);
+    ENSURE(c, c->r, sizeof(double) * nr);
+    ENSURE(c, c->gcnt, sizeof(uint32_t) * (nr + 1));
+    uint64_t finest = 1ull << (D * c->grid.L_hi);
+    uint64_t sw = scan_tmp_words(finest > (uint64_t)nr ? finest : (uint64_t)nr);
+    ENSURE(c, c->scan_tmp, sizeof(uint32_t) * sw);
+    if (ng > 0) ENSURE(c, c->ghosts, sizeof(double) * 10 * ng);
+    ENSURE(c, c->key, sizeof(uint32_t) * nt);
+    ENSURE(c, c->slot, sizeof(uint32_t) * nt);
+    ENSURE(c, c->tables, sizeof(uint32_t) * table_words(c));
+    ENSURE(c, c->sorted, sizeof(double) * (state ? 10 : 4) * nt);
+    if (mixed) ENSURE(c, c->sortedf, sizeof(float) * 5 * nt);
+    ENSURE(c, c->sid, sizeof(int) * nt);
+    ENSURE(c, c->nbr, sizeof(int) * (size_t)c->dc.max_nb * nt);
+    ENSURE(c, c->count, sizeof(int) * nt);
+    ENSURE(c, c->queue, sizeof(int) * nt);
+    return LP_OK;
+}
+
+static Sorted sorted_view(lp_ctx *c, bool state) {
+    Sorted s;
+    memset(&s, 0, sizeof s);
+    double *b = (double *)c->sorted.p;
+    size_t n = (size_t)c->cap_total;
+    s.x[0] = b; s.x[1] = b + n; s.x[2] = b + 2 * n;
+    s.r = b + 3 * n;
+    if (state) {
+        s.V = b + 4 * n; s.u[0] = b + 5 * n; s.u[1] = b + 6 * n; s.u[2] = b + 7 * n; s.P = b + 8 * n; s.h = b + 9 * n;
+    }
+    if (c->sortedf.p && c->sortedf.bytes >= sizeof(float) * 5 * n) {
+        float *f = (float *)c->sortedf.p;
+        s.Vf = f; s.uf[0] = f + n; s.uf[1] = f + 2 * n; s.uf[2] = f + 3 * n; s.Pf = f + 4 * n;
+    }
+    s.id = (int *)c->sid.p;
+    return s;
+}
+
+static Ghosts ghost_view(lp_ctx *c) {
+    Ghosts g;
+    memset(&g, 0, sizeof g);
+    int64_t ng = c->cap_ghost;
+    if (ng <= 0 || !c->ghosts.p) return g;
+    double *b = (double *)c->ghosts.p;
+    size_t n = (size_t)ng;
+    g.x[0] = b; g.x[1] = b + n; g.x[2] = b + 2 * n; g.V = b + 3 * n; g.u[0] = b + 4 * n; g.u[1] = b + 5 * n;
+    g.u[2] = b + 6 * n; g.P = b + 7 * n; g.h = b + 8 * n; g.r = b + 9 * n;
+    return g;
+}
+
+// Cell-order layout of n_total particles: keys, counting sort, level tables.
+static void build_cells(lp_ctx *c, hipStream_t st, const double *const x[3], const double *const gx[3], int n_real,
+                        int64_t n_total) {
+    const int D = c->dc.D;
+    const DevGrid &g = c->grid;
+    uint32_t *tabs = (uint32_t *)c->tables.p;
+    uint32_t *finest = tabs + g.off[g.L_hi];
+    uint64_t nfin = 1ull << (D * g.L_hi);
+    launch_fill_u32(finest, nfin + 1, 0u, st);
+    int *n_total_dev = &c->sc->n_total;
+    launch_keys(x, gx, n_real, n_total_dev, (int)n_total, g, D, (uint32_t *)c->key.p, (uint32_t *)c->slot.p, finest,
+                st);
+    launch_scan_u32(finest, nfin, (uint32_t *)c->scan_tmp.p, nullptr, st);
+}
+
+static lp_status check_particles(lp_ctx *c, const lp_particles *p) {
+    if (!p || p->n <= 0 || p->n > (1ll << 30)) return fail(c, LP_E_ARG, "particle count must be in 1..2^30");
+    for (int a = 0; a < c->dc.D; ++a)
+        if (!p->x[a] || !p->u[a]) return fail(c, LP_E_ARG, "null position/velocity array");
+    if (!p->V || !p->P || !p->m) return fail(c, LP_E_ARG, "null V, P or m");
+    if (c->dc.est_mode == LP_EST_INJECTED && !p->phi) return fail(c, LP_E_ARG, "injected estimator needs phi");
+    return LP_OK;
+}
+
+static Soa soa_of(const lp_particles *p) {
+    Soa s;
+    memset(&s, 0, sizeof s);
+    for (int a = 0; a < 3; ++a) { s.x[a] = p->x[a]; s.u[a] = p->u[a]; }
+    if (!s.x[2]) s.x[2] = s.x[0];
+    if (!s.u[2]) s.u[2] = s.u[0];
+    s.V = p->V; s.P = p->P; s.m = p->m; s.phi = p->phi; s.flags = p->flags;
+    s.n = (int)p->n;
+    return s;
+}
+
+// One step.  sync_levels: read r_min / r_max / ghost count back to size the
+// grid (lp_step); otherwise the current grid and capacities are used as they
+// are (graph replays).
+static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, double dt_in, bool sync_levels,
+                           int clip_t_end) {
+    const int D = c->dc.D;
+    const int n = (int)p->n;
+    const bool mixed = c->dc.precision == LP_MIXED;
+    Soa soa = soa_of(p);
+    if (sync_levels) {
+        ENSURE(c, c->h, sizeof(double) * n);
+        ENSURE(c, c->r, sizeof(double) * n);
+        ENSURE(c, c->gcnt, sizeof(uint32_t) * (n + 1));
+        ENSURE(c, c->scan_tmp, sizeof(uint32_t) * scan_tmp_words(n));
+    }
+    launch_reset_scalars(c->sc, dt_in, n, st);
+    launch_prep(soa, c->dc, c->sc, (double *)c->h.p, (double *)c->r.p, st);
+    launch_dt(c->dc, c->sc, clip_t_end, st);
+    if (c->nwalls) {
+        launch_ghost_count(soa, c->dc, c->sc, (uint32_t *)c->gcnt.p, st);
+        launch_scan_u32((uint32_t *)c->gcnt.p, n, (uint32_t *)c->scan_tmp.p, &c->sc->n_ghost, st);
+    }
+    int64_t n_total;
+    if (sync_levels) {
+        HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        if (clip_t_end && c->sc_host->done) {
+            c->run_done = true;
+            return LP_OK;
+        }
+        n_total = n + c->sc_host->n_ghost;
+        choose_levels(c, bits_to_double(c->sc_host->rmin), bits_to_double(c->sc_host->rmax));
+        lp_status s = ensure_capacity(c, n, n_total, true, mixed);
+        if (s != LP_OK) return s;
+    } else {
+        n_total = c->cap_total;
+    }
+    Ghosts gh = ghost_view(c);
+    if (c->nwalls)
+        launch_ghost_write(soa, c->dc, c->sc, (const uint32_t *)c->gcnt.p, (const double *)c->h.p,
+                           (const double *)c->r.p, gh, st);
+    const double *gx[3] = {gh.x[0], gh.x[1], gh.x[2]};
+    const double *x[3] = {p->x[0], p->x[1], D == 3 ? p->x[2] : p->x[1]};
+    build_cells(c, st, x, gx, n, n_total);
+    Sorted srt = sorted_view(c, true);
+    ScatterArgs sa;
+    memset(&sa, 0, sizeof sa);
+    const double *src[10] = {soa.x[0], soa.x[1], soa.x[2], (const double *)c->r.p, soa.V, soa.u[0], soa.u[1],
+                             soa.u[2], soa.P, (const double *)c->h.p};
+    const double *gsrc[10] = {gh.x[0], gh.x[1], gh.x[2], gh.r, gh.V, gh.u[0], gh.u[1], gh.u[2], gh.P, gh.h};
+    double *dst[10] = {srt.x[0], srt.x[1], srt.x[2], srt.r, srt.V, srt.u[0], srt.u[1], srt.u[2], srt.P, srt.h};
+    sa.nd = 10;
+    for (int q = 0; q < 10; ++q) { sa.src[q] = src[q]; sa.gsrc[q] = gsrc[q]; sa.dst[q] = dst[q]; }
+    if (D == 2) { sa.src[2] = soa.x[0]; sa.src[7] = soa.u[0]; }
+    if (mixed) {
+        sa.nff = 4;  // V, u0, u1, P (u2 below in 3D)
+        sa.fsrc[0] = 4; sa.dstf[0] = srt.Vf;
+        sa.fsrc[1] = 5; sa.dstf[1] = srt.uf[0];
+        sa.fsrc[2] = 6; sa.dstf[2] = srt.uf[1];
+        sa.fsrc[3] = 8; sa.dstf[3] = srt.Pf;
+    }
+    const uint32_t *start = (const uint32_t *)c->tables.p + c->grid.off[c->grid.L_hi];
+    launch_scatter(sa, n, &c->sc->n_total, (int)n_total, (const uint32_t *)c->key.p, (const uint32_t *)c->slot.p, start,
+                   srt.id, st);
+    if (mixed && D == 3) {
+        ScatterArgs sb;
+        memset(&sb, 0, sizeof sb);
+        sb.nd = 1;
+        sb.src[0] = soa.u[2]; sb.gsrc[0] = gh.u[2]; sb.dst[0] = srt.u[2];
+        sb.nff = 1; sb.fsrc[0] = 0; sb.dstf[0] = srt.uf[2];
+        launch_scatter(sb, n, &c->sc->n_total, (int)n_total, (const uint32_t *)c->key.p, (const uint32_t *)c->slot.p,
+                       start, srt.id, st);
+    }
+    launch_coarsen((uint32_t *)c->tables.p, c->grid, D, &c->sc->n_total, st);
+    int ldn = (int)c->cap_total;
+    launch_search(srt, &c->sc->n_total, (int)n_total, n, (const uint32_t *)c->tables.p, c->grid, c->dc,
+                  (int *)c->nbr.p, ldn, (int *)c->count.p, c->sc, c->search_group, st);
+    launch_solve(srt, soa, (const int *)c->nbr.p, ldn, (const int *)c->count.p, &c->sc->n_total, (int)n_total, n,
+                 c->dc, c->sc, (int *)c->queue.p, st);
+    launch_solve_fallback(srt, soa, (const int *)c->nbr.p, ldn, (const int *)c->count.p, n, c->dc, c->sc,
+                          (const int *)c->queue.p, n, st);
+    launch_advance_time(c->sc, st);
+    HIPCHK(c, hipGetLastError());
+    return LP_OK;
+}
+
+extern "C" lp_status lp_step(lp_ctx *c, void *stream, const lp_particles *p, double dt) {
+    if (!c) return LP_E_ARG;
+    lp_status s = check_particles(c, p);
+    if (s != LP_OK) return s;
+    HIPCHK(c, hipSetDevice(c->device));
+    return step_impl(c, (hipStream_t)stream, p, dt, true, 0);
+}
+
+extern "C" lp_status lp_run(lp_ctx *c, void *stream, const lp_particles *p, int32_t nsteps, double t_end) {
+    if (!c) return LP_E_ARG;
+    lp_status s = check_particles(c, p);
+    if (s != LP_OK) return s;
+    if (nsteps < 0) return fail(c, LP_E_ARG, "nsteps < 0");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    // t_end is kept on the device; each step shortens its dt to land on it
+    HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    c->sc_host->t_end = t_end;
+    c->sc_host->done = 0u;
+    HIPCHK(c, hipMemcpyAsync(c->sc, c->sc_host, sizeof(DevScalars), hipMemcpyHostToDevice, st));
+    c->run_done = false;
+    for (int k = 0; k < nsteps && !c->run_done; ++k) {
+        s = step_impl(c, st, p, 0.0, true, 1);
+        if (s != LP_OK) return s;
+    }
+    return LP_OK;
+}
+
+extern "C" lp_status lp_neighbors(lp_ctx *c, void *stream, int64_t n, const double *x, const double *y,
+                                  const double *z, const double *r, int32_t *count, int32_t *idx) {
+    if (!c) return LP_E_ARG;
+    if (n <= 0 || n > (1ll << 30) || !x || !y || (c->dc.D == 3 && !z) || !r || !count || !idx)
+        return fail(c, LP_E_ARG, "lp_neighbors: bad arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int D = c->dc.D;
+    launch_reset_scalars(c->sc, 0.0, (int)n, st);
+    launch_rminmax(r, (int)n, c->sc, st);
+    HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    choose_levels(c, bits_to_double(c->sc_host->rmin), bits_to_double(c->sc_host->rmax));
+    lp_status s = ensure_capacity(c, n, n, false, false);
+    if (s != LP_OK) return s;
+    const double *xs[3] = {x, y, D == 3 ? z : y};
+    const double *gx[3] = {nullptr, nullptr, nullptr};
+    build_cells(c, st, xs, gx, (int)n, n);
+    Sorted srt = sorted_view(c, false);
+    ScatterArgs sa;
+    memset(&sa, 0, sizeof sa);
+    sa.nd = 4;
+    sa.src[0] = x; sa.src[1] = y; sa.src[2] = D == 3 ? z : y; sa.src[3] = r;
+    sa.dst[0] = srt.x[0]; sa.dst[1] = srt.x[1]; sa.dst[2] = srt.x[2]; sa.dst[3] = srt.r;
+    const uint32_t *start = (const uint32_t *)c->tables.p + c->grid.off[c->grid.L_hi];
+    launch_scatter(sa, (int)n, &c->sc->n_total, (int)n, (const uint32_t *)c->key.p, (const uint32_t *)c->slot.p, start,
+                   srt.id, st);
+    launch_coarsen((uint32_t *)c->tables.p, c->grid, D, &c->sc->n_total, st);
+    int ldn = (int)c->cap_total;
+    launch_search(srt, &c->sc->n_total, (int)n, (int)n, (const uint32_t *)c->tables.p, c->grid, c->dc, (int *)c->nbr.p,
+                  ldn, (int *)c->count.p, c->sc, c->search_group, st);
+    launch_lists_out(srt.id, (const int *)c->nbr.p, ldn, (const int *)c->count.p, (int)n, c->dc.max_nb, count, idx, st);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (c->sc_host->max_count > c->dc.max_nb) return fail(c, LP_E_CAPACITY, "neighbour count %d exceeds max_nb %d",
+                                                          c->sc_host->max_count, c->dc.max_nb);
+    return LP_OK;
+}
+
+extern "C" lp_status lp_gfd(lp_ctx *c, void *stream, int64_t n, const double *x, const double *y, const double *z,
+                            const double *r, int32_t nf, const double *const *f, double *deriv, uint8_t *status) {
+    if (!c) return LP_E_ARG;
+    if (n <= 0 || n > (1ll << 30) || !x || !y || (c->dc.D == 3 && !z) || !r || !f || nf < 1 || nf > 5 || !deriv ||
+        !status)
+        return fail(c, LP_E_ARG, "lp_gfd: bad arguments");
+    for (int q = 0; q < nf; ++q)
+        if (!f[q]) return fail(c, LP_E_ARG, "lp_gfd: null field");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int D = c->dc.D;
+    launch_reset_scalars(c->sc, 0.0, (int)n, st);
+    launch_rminmax(r, (int)n, c->sc, st);
+    HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    choose_levels(c, bits_to_double(c->sc_host->rmin), bits_to_double(c->sc_host->rmax));
+    lp_status s = ensure_capacity(c, n, n, false, false);
+    if (s != LP_OK) return s;
+    ENSURE(c, c->gfd_fields, sizeof(double) * nf * n);
+    const double *xs[3] = {x, y, D == 3 ? z : y};
+    const double *gx[3] = {nullptr, nullptr, nullptr};
+    build_cells(c, st, xs, gx, (int)n, n);
+    Sorted srt = sorted_view(c, false);
+    ScatterArgs sa;
+    memset(&sa, 0, sizeof sa);
+    sa.nd = 4 + nf;
+    sa.src[0] = x; sa.src[1] = y; sa.src[2] = D == 3 ? z : y; sa.src[3] = r;
+    sa.dst[0] = srt.x[0]; sa.dst[1] = srt.x[1]; sa.dst[2] = srt.x[2]; sa.dst[3] = srt.r;
+    const double *fs[5];
+    for (int q = 0; q < nf; ++q) {
+        double *dq = (double *)c->gfd_fields.p + (size_t)q * n;
+        sa.src[4 + q] = f[q];
+        sa.dst[4 + q] = dq;
+        fs[q] = dq;
+    }
+    const uint32_t *start = (const uint32_t *)c->tables.p + c->grid.off[c->grid.L_hi];
+    launch_scatter(sa, (int)n, &c->sc->n_total, (int)n, (const uint32_t *)c->key.p, (const uint32_t *)c->slot.p, start,
+                   srt.id, st);
+    launch_coarsen((uint32_t *)c->tables.p, c->grid, D, &c->sc->n_total, st);
+    int ldn = (int)c->cap_total;
+    launch_search(srt, &c->sc->n_total, (int)n, (int)n, (const uint32_t *)c->tables.p, c->grid, c->dc, (int *)c->nbr.p,
+                  ldn, (int *)c->count.p, c->sc, c->search_group, st);
+    launch_gfd(srt, fs, nf, (const int *)c->nbr.p, ldn, (const int *)c->count.p, (int)n, c->dc, c->sc,
+               (int *)c->queue.p, deriv, status, st);
+    launch_gfd_fallback(srt, fs, nf, (const int *)c->nbr.p, ldn, (const int *)c->count.p, (int)n, c->dc, c->sc,
+                        (const int *)c->queue.p, (int)n, deriv, status, st);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (c->sc_host->max_count > c->dc.max_nb) return fail(c, LP_E_CAPACITY, "neighbour count %d exceeds max_nb %d",
+                                                          c->sc_host->max_count, c->dc.max_nb);
+    return LP_OK;
+}
+
+extern "C" lp_status lp_conservation(lp_ctx *c, void *stream, const lp_particles *p, double *out) {
+    if (!c || !out) return LP_E_ARG;
+    lp_status s = check_particles(c, p);
+    if (s != LP_OK) return s;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int nblocks = 1024;
+    ENSURE(c, c->partials, sizeof(double) * 5 * nblocks);
+    ENSURE(c, c->consout, sizeof(double) * 5);
+    launch_conservation(soa_of(p), c->dc, (double *)c->partials.p, nblocks, (double *)c->consout.p, st);
+    HIPCHK(c, hipMemcpyAsync(out, c->consout.p, sizeof(double) * 5, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    return LP_OK;
+}
+
+extern "C" lp_status lp_check(lp_ctx *c, void *stream) {
+    if (!c) return LP_E_ARG;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(c, hipStreamSynchronize(st));
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpy(c->sc_host, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost));
+    unsigned bits = c->sc_host->error_bits;
+    if (bits) {
+        c->sc_host->error_bits = 0;
+        HIPCHK(c, hipMemcpy(&c->sc->error_bits, &c->sc_host->error_bits, sizeof(unsigned), hipMemcpyHostToDevice));
+    }
+    if (bits & 1u) return fail(c, LP_E_CAPACITY, "a neighbour list exceeded max_nb = %d", c->dc.max_nb);
+    if (bits & 2u) return fail(c, LP_E_NUMERIC, "non-positive V or P after an update");
+    return LP_OK;
+}
+
+extern "C" lp_status lp_get_info(lp_ctx *c, void *stream, lp_info *out) {
+    if (!c || !out) return LP_E_ARG;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    memset(out, 0, sizeof *out);
+    out->t = c->sc_host->t;
+    out->dt = c->sc_host->dt;
+    out->n_ghost = c->sc_host->n_ghost;
+    out->max_count = c->sc_host->max_count;
+    out->n_fallback = c->sc_host->n_fallback;
+    out->n_limited = (int64_t)c->sc_host->n_limited;
+    out->error_bits = c->sc_host->error_bits;
+    out->levels[0] = c->last_levels[0];
+    out->levels[1] = c->last_levels[1];
+    return LP_OK;
+}
+
+extern "C" lp_status lp_set_time(lp_ctx *c, void *stream, double t) {
+    if (!c) return LP_E_ARG;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    c->sc_host->t = t;
+    HIPCHK(c, hipMemcpyAsync(c->sc, c->sc_host, sizeof(DevScalars), hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    return LP_OK;
+}

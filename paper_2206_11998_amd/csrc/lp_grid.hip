@@ -1,0 +1,457 @@
+// lp_grid.hip -- per-step particle bookkeeping on gfx950:
+//   smoothing lengths, radii and the CFL time step (Sec. 2.2 loop, dt rule),
+//   mirror ghosts across solid walls (Sec. 2.2, step 1),
+//   the cell-ordered particle layout that replaces the octree (Sec. 2.2,
+//   step 2): a counting sort by Morton cell at the finest level, one exclusive
+//   scan that doubles as the finest cell table, and coarser tables taken from it.
+// All kernels are HBM-bound streaming kernels: coalesced SoA loads/stores,
+// 256-thread blocks, one element per thread (grid-stride where noted).
+#include "lp_internal.h"
+
+#define CHECK_LAUNCH() (void)hipGetLastError()
+
+static inline unsigned blocks_for(uint64_t n, int per = LP_BLOCK) {
+    uint64_t b = (n + per - 1) / per;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+// ---------------------------------------------------------------------------
+// Scalars
+// ---------------------------------------------------------------------------
+__global__ void k_reset_scalars(DevScalars *sc, double dt_in, int n_real) {
+    sc->n_total = n_real;
+    sc->min_hc = 0x7ff0000000000000ull;  // +inf
+    sc->rmax = 0ull;
+    sc->rmin = 0x7ff0000000000000ull;
+    sc->dt_in = dt_in;
+    sc->n_ghost = 0;
+    sc->max_count = 0;
+    sc->n_fallback = 0;
+    sc->n_limited = 0ull;
+}
+
+void launch_reset_scalars(DevScalars *sc, double dt_in, int n_real, hipStream_t st) {
+    hipLaunchKernelGGL(k_reset_scalars, dim3(1), dim3(1), 0, st, sc, dt_in, n_real);
+    CHECK_LAUNCH();
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+// h_i = (m_i V_i)^(1/D), c_i = sqrt(gamma P_i V_i), r_i = kappa h_i;
+// min h/c, min r and max r reduced with integer atomics on the bit patterns
+// (positive doubles order like their bit patterns, so the result is exact and
+// independent of the reduction order).
+__global__ void k_prep(Soa p, DevCfg cfg, DevScalars *sc, double *h_out, double *r_out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double hc = INFINITY, rr_min = INFINITY, rr_max = 0.0;
+    if (i < p.n) {
+        double V = p.V[i], P = p.P[i], m = p.m[i];
+        double mv = m * V;
+        double h = cfg.D == 3 ? cbrt(mv) : sqrt(mv);
+        double c = sqrt(cfg.gamma * P * V);
+        double r = cfg.kappa * h;
+        h_out[i] = h;
+        r_out[i] = r;
+        hc = h / c;
+        rr_min = r;
+        rr_max = r;
+    }
+    hc = wave_min(hc);
+    rr_min = wave_min(rr_min);
+    rr_max = wave_max(rr_max);
+    if ((threadIdx.x & 63) == 0) {
+        if (hc < INFINITY) atomicMin(&sc->min_hc, dbl_bits(hc));
+        if (rr_min < INFINITY) atomicMin(&sc->rmin, dbl_bits(rr_min));
+        if (rr_max > 0.0) atomicMax(&sc->rmax, dbl_bits(rr_max));
+    }
+}
+
+void launch_prep(const Soa &p, const DevCfg &cfg, DevScalars *sc, double *h, double *r, hipStream_t st) {
+    hipLaunchKernelGGL(k_prep, dim3(blocks_for(p.n)), dim3(LP_BLOCK), 0, st, p, cfg, sc, h, r);
+    CHECK_LAUNCH();
+}
+
+// dt = cfl * min h/c unless given; with clip, the step is shortened so that t
+// does not pass t_end (and set to zero once t_end is reached).
+__global__ void k_dt(DevCfg cfg, DevScalars *sc, int clip) {
+    double dt = sc->dt_in > 0.0 ? sc->dt_in : cfg.cfl * bits_dbl(sc->min_hc);
+    if (clip && sc->t_end > 0.0) {
+        double rem = sc->t_end - sc->t;
+        if (!(rem > 0.0)) { dt = 0.0; sc->done = 1u; }
+        else if (dt >= rem) dt = rem;
+    }
+    sc->dt = dt;
+}
+
+// min / max of given radii (for searches on caller-provided radii)
+__global__ void k_rminmax(const double *r, int n, DevScalars *sc) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double lo = INFINITY, hi = 0.0;
+    if (i < n) { lo = r[i]; hi = r[i]; }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    if ((threadIdx.x & 63) == 0) {
+        if (lo < INFINITY) atomicMin(&sc->rmin, dbl_bits(lo));
+        if (hi > 0.0) atomicMax(&sc->rmax, dbl_bits(hi));
+    }
+}
+
+void launch_rminmax(const double *r, int n, DevScalars *sc, hipStream_t st) {
+    hipLaunchKernelGGL(k_rminmax, dim3(blocks_for(n)), dim3(LP_BLOCK), 0, st, r, n, sc);
+    CHECK_LAUNCH();
+}
+
+// t += dt after a step
+__global__ void k_advance_time(DevScalars *sc) { sc->t += sc->dt; }
+
+void launch_advance_time(DevScalars *sc, hipStream_t st) {
+    hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(1), 0, st, sc);
+    CHECK_LAUNCH();
+}
+
+void launch_dt(const DevCfg &cfg, DevScalars *sc, int clip_t_end, hipStream_t st) {
+    hipLaunchKernelGGL(k_dt, dim3(1), dim3(1), 0, st, cfg, sc, clip_t_end);
+    CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------------------
+// Mirror ghosts: a particle closer than r_max to a wall plane w gets an image
+// at 2w - x with the normal velocity reversed; ghost ids follow (source id,
+// wall index) order through an exclusive scan of per-particle counts.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int ghost_walls(const DevCfg &cfg, const Soa &p, int i, double rmax, int *which) {
+    int k = 0;
+    for (int a = 0; a < cfg.D; ++a) {
+        double x = p.x[a][i];
+        if (cfg.wall_lo[a] && x - cfg.lo[a] < rmax) { if (which) which[k] = 2 * a; ++k; }
+        if (cfg.wall_hi[a] && cfg.hi[a] - x < rmax) { if (which) which[k] = 2 * a + 1; ++k; }
+    }
+    return k;
+}
+
+__global__ void k_ghost_count(Soa p, DevCfg cfg, DevScalars *sc, uint32_t *gcnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n) return;
+    double rmax = bits_dbl(sc->rmax);
+    gcnt[i] = (uint32_t)ghost_walls(cfg, p, i, rmax, nullptr);
+}
+
+void launch_ghost_count(const Soa &p, const DevCfg &cfg, DevScalars *sc, uint32_t *gcnt, hipStream_t st) {
+    hipLaunchKernelGGL(k_ghost_count, dim3(blocks_for(p.n)), dim3(LP_BLOCK), 0, st, p, cfg, sc, gcnt);
+    CHECK_LAUNCH();
+}
+
+__global__ void k_ghost_write(Soa p, DevCfg cfg, DevScalars *sc, const uint32_t *goff, const double *h,
+                              const double *r, Ghosts g) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) sc->n_total = p.n + sc->n_ghost;
+    if (i >= p.n) return;
+    double rmax = bits_dbl(sc->rmax);
+    int which[6];
+    int k = ghost_walls(cfg, p, i, rmax, which);
+    uint32_t o = goff[i];
+    for (int q = 0; q < k; ++q) {
+        int a = which[q] >> 1;
+        double w = (which[q] & 1) ? cfg.hi[a] : cfg.lo[a];
+        uint32_t gi = o + q;
+        for (int b = 0; b < cfg.D; ++b) {
+            double xb = p.x[b][i], ub = p.u[b][i];
+            if (b == a) { xb = 2.0 * w - xb; ub = -ub; }
+            g.x[b][gi] = xb;
+            g.u[b][gi] = ub;
+        }
+        g.V[gi] = p.V[i];
+        g.P[gi] = p.P[i];
+        g.h[gi] = h[i];
+        g.r[gi] = r[i];
+    }
+}
+
+void launch_ghost_write(const Soa &p, const DevCfg &cfg, DevScalars *sc, const uint32_t *goff, const double *h,
+                        const double *r, Ghosts g, hipStream_t st) {
+    hipLaunchKernelGGL(k_ghost_write, dim3(blocks_for(p.n)), dim3(LP_BLOCK), 0, st, p, cfg, sc, goff, h, r, g);
+    CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------------------
+// Fill (used instead of memset so the sequence stays graph-safe).
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) {
+    uint64_t b = (n + LP_BLOCK - 1) / LP_BLOCK;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)b), dim3(LP_BLOCK), 0, st, p, n, v);
+    CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------------------
+// Cell keys at the finest level + per-cell slot (counting-sort histogram).
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void k_keys(const double *x0, const double *x1, const double *x2, const double *g0, const double *g1,
+                       const double *g2, int n_real, const int *n_total_dev, DevGrid g, uint32_t *key,
+                       uint32_t *slot, uint32_t *cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int n_total = *n_total_dev;
+    if (i >= n_total) return;
+    double p[3];
+    if (i < n_real) { p[0] = x0[i]; p[1] = x1[i]; p[2] = D == 3 ? x2[i] : 0.0; }
+    else { int q = i - n_real; p[0] = g0[q]; p[1] = g1[q]; p[2] = D == 3 ? g2[q] : 0.0; }
+    int c[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) c[a] = cell_coord(g, g.L_hi, a, p[a]);
+    uint32_t k = morton<D>(c);
+    key[i] = k;
+    slot[i] = atomicAdd(&cnt[k], 1u);
+}
+
+void launch_keys(const double *const x[3], const double *const gx[3], int n_real, const int *n_total_dev,
+                 int n_total_cap, const DevGrid &g, int D, uint32_t *key, uint32_t *slot, uint32_t *cnt,
+                 hipStream_t st) {
+    dim3 grid(blocks_for(n_total_cap));
+    if (D == 3)
+        hipLaunchKernelGGL(k_keys<3>, grid, dim3(LP_BLOCK), 0, st, x[0], x[1], x[2], gx[0], gx[1], gx[2], n_real,
+                           n_total_dev, g, key, slot, cnt);
+    else
+        hipLaunchKernelGGL(k_keys<2>, grid, dim3(LP_BLOCK), 0, st, x[0], x[1], x[1], gx[0], gx[1], gx[1], n_real,
+                           n_total_dev, g, key, slot, cnt);
+    CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of u32 (three passes: tile sums, scan of sums, tile scan).
+// Tiles of 256 threads x 8 items; wave64 shuffles inside, LDS across waves.
+// ---------------------------------------------------------------------------
+#define SCAN_ITEMS 8
+#define SCAN_TILE (LP_BLOCK * SCAN_ITEMS)
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    int lane = threadIdx.x & 63;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// block exclusive scan of one value per thread; returns exclusive prefix, sets *total
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total) {
+    __shared__ uint32_t wsum[LP_BLOCK / 64];
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (int q = 0; q < LP_BLOCK / 64; ++q) {
+        if (q < w) off += wsum[q];
+        tot += wsum[q];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+__global__ void k_scan_tiles(const uint32_t *data, uint64_t n, uint32_t *sums) {
+    uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+    uint32_t s = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        uint64_t i = base + (uint64_t)k * LP_BLOCK + threadIdx.x;
+        if (i < n) s += data[i];
+    }
+    // block reduce
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    __shared__ uint32_t ws[LP_BLOCK / 64];
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int q = 0; q < LP_BLOCK / 64; ++q) t += ws[q];
+        sums[blockIdx.x] = t;
+    }
+}
+
+// one block of 1024 threads: exclusive scan of the tile sums in place, total to
+// sums[nt]; each thread scans a contiguous chunk sequentially.
+__global__ __launch_bounds__(1024) void k_scan_sums(uint32_t *sums, uint64_t nt) {
+    __shared__ uint32_t ws[16];
+    uint64_t chunk = (nt + 1023) / 1024;
+    uint64_t b = (uint64_t)threadIdx.x * chunk, e = b + chunk;
+    if (e > nt) e = nt;
+    uint32_t s = 0;
+    for (uint64_t i = b; i < e; ++i) s += sums[i];
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = wave_incl_scan(s);
+    if (lane == 63) ws[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (int q = 0; q < 16; ++q) {
+        if (q < w) off += ws[q];
+        tot += ws[q];
+    }
+    uint32_t run = off + inc - s;
+    for (uint64_t i = b; i < e; ++i) {
+        uint32_t v = sums[i];
+        sums[i] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0) sums[nt] = tot;
+}
+
+__global__ void k_scan_apply(uint32_t *data, uint64_t n, const uint32_t *sums, int *total_dev) {
+    uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+    // each thread owns SCAN_ITEMS consecutive items
+    uint64_t first = base + (uint64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS];
+    uint32_t s = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        uint64_t i = first + k;
+        v[k] = i < n ? data[i] : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(s, &tot) + sums[blockIdx.x];
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        uint64_t i = first + k;
+        if (i < n) data[i] = ex;
+        ex += v[k];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        uint64_t nt = gridDim.x;
+        data[n] = sums[nt];
+        if (total_dev) *total_dev = (int)sums[nt];
+    }
+}
+
+uint64_t scan_tmp_words(uint64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 2; }
+
+void launch_scan_u32(uint32_t *data, uint64_t n, uint32_t *tmp, int *total_dev, hipStream_t st) {
+    uint64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nt < 1) nt = 1;
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(LP_BLOCK), 0, st, data, n, tmp);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, tmp, nt);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nt), dim3(LP_BLOCK), 0, st, data, n, tmp, total_dev);
+    CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------------------
+// Scatter into cell order: pos = start[key] + slot.
+// ---------------------------------------------------------------------------
+__global__ void k_scatter(ScatterArgs a, int n_real, const int *n_total_dev, const uint32_t *key,
+                          const uint32_t *slot, const uint32_t *start, int *sorted_id) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= *n_total_dev) return;
+    uint32_t pos = start[key[i]] + slot[i];
+    sorted_id[pos] = i;
+    bool real = i < n_real;
+    double vals[12];
+    for (int d = 0; d < a.nd; ++d) {
+        double v = real ? a.src[d][i] : (a.gsrc[d] ? a.gsrc[d][i - n_real] : 0.0);
+        vals[d] = v;
+        a.dst[d][pos] = v;
+    }
+    for (int f = 0; f < a.nff; ++f) a.dstf[f][pos] = (float)vals[a.fsrc[f]];
+}
+
+void launch_scatter(const ScatterArgs &a, int n_real, const int *n_total_dev, int n_total_cap, const uint32_t *key,
+                    const uint32_t *slot, const uint32_t *start, int *sorted_id, hipStream_t st) {
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n_total_cap)), dim3(LP_BLOCK), 0, st, a, n_real, n_total_dev,
+                       key, slot, start, sorted_id);
+    CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------------------
+// Coarser cell tables: the first particle of a cell is the first particle of
+// its first child.
+// ---------------------------------------------------------------------------
+__global__ void k_coarsen(uint32_t *dst, const uint32_t *src, uint64_t ncell, int D, const int *n_total_dev) {
+    uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncell) dst[c] = src[c << D];
+    else if (c == ncell) dst[c] = (uint32_t)*n_total_dev;
+}
+
+void launch_coarsen(uint32_t *tables, const DevGrid &g, int D, const int *n_total_dev, hipStream_t st) {
+    for (int L = g.L_hi - 1; L >= g.L_lo; --L) {
+        uint64_t ncell = 1ull << (D * L);
+        hipLaunchKernelGGL(k_coarsen, dim3(blocks_for(ncell + 1)), dim3(LP_BLOCK), 0, st, tables + g.off[L],
+                           tables + g.off[L + 1], ncell, D, n_total_dev);
+    }
+    CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------------------
+// Neighbour lists back to the caller's indexing.
+// ---------------------------------------------------------------------------
+__global__ void k_lists_out(const int *sorted_id, const int *nbr, int ldn, const int *count, int n, int max_nb,
+                            int *count_out, int *idx_out) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int i = sorted_id[s];
+    int k = count[s];
+    count_out[i] = k;
+    int kk = k < max_nb ? k : max_nb;
+    for (int c = 0; c < kk; ++c) idx_out[(int64_t)i * max_nb + c] = sorted_id[nbr[(int64_t)c * ldn + s]];
+}
+
+void launch_lists_out(const int *sorted_id, const int *nbr, int ldn, const int *count, int n, int max_nb,
+                      int *count_out, int *idx_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_lists_out, dim3(blocks_for(n)), dim3(LP_BLOCK), 0, st, sorted_id, nbr, ldn, count, n, max_nb,
+                       count_out, idx_out);
+    CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------------------
+// Conservation totals in FP64 with a fixed reduction order (deterministic):
+// per-block tree sums over the caller's order, then one block sums the partials.
+// ---------------------------------------------------------------------------
+__global__ void k_cons_partial(Soa p, DevCfg cfg, double *partials) {
+    __shared__ double sh[5][LP_BLOCK];
+    double acc[5] = {0, 0, 0, 0, 0};
+    int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < p.n; i += stride) {
+        double m = p.m[i], V = p.V[i], P = p.P[i];
+        double u0 = p.u[0][i], u1 = p.u[1][i], u2 = cfg.D == 3 ? p.u[2][i] : 0.0;
+        double e = P * V / (cfg.gamma - 1.0);
+        double ke = 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
+        acc[0] += m;
+        acc[1] += m * u0;
+        acc[2] += m * u1;
+        acc[3] += m * u2;
+        acc[4] += m * (e + ke);
+    }
+    for (int q = 0; q < 5; ++q) sh[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int o = LP_BLOCK / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            for (int q = 0; q < 5; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x < 5) partials[blockIdx.x * 5 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void k_cons_final(const double *partials, int nblocks, double *out) {
+    if (threadIdx.x < 5) {
+        double s = 0.0;
+        for (int b = 0; b < nblocks; ++b) s += partials[b * 5 + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+void launch_conservation(const Soa &p, const DevCfg &cfg, double *partials, int nblocks, double *out,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_cons_partial, dim3(nblocks), dim3(LP_BLOCK), 0, st, p, cfg, partials);
+    hipLaunchKernelGGL(k_cons_final, dim3(1), dim3(64), 0, st, partials, nblocks, out);
+    CHECK_LAUNCH();
+}

@@ -1,0 +1,199 @@
+// lp_internal.h -- device data structures, launchers and shared device helpers
+// of liblp (gfx950).  Included by every translation unit of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lp.h"
+
+#define LP_MAX_LEVEL 16
+#define LP_BLOCK 256
+
+// ---------------------------------------------------------------------------
+// Configuration as seen by the kernels (passed by value).
+// ---------------------------------------------------------------------------
+struct DevCfg {
+    int D, nu, nf;              // dimension, second-order unknowns, fields (V, u.., P)
+    int lw_cap, uw_cap, max_nb;
+    int vacuum, est_mode, precision, refine;
+    double gamma, kappa, cfl, est_eps, cond_max, uw_cond_max, cond_fb;
+    double lo[3], hi[3], L[3], half[3];
+    int periodic[3], wall_lo[3], wall_hi[3];
+};
+
+// Hierarchy of uniform cell grids over the cube [lo, lo + S)^D.  Level L has
+// cells of size S / 2^L; per level, a table start[code] (Morton code of the
+// cell, plus one sentinel) gives the first sorted particle of every cell.
+struct DevGrid {
+    double lo[3];
+    int L_lo, L_hi;
+    int nc[LP_MAX_LEVEL][3];        // cells per axis
+    double inv_s[LP_MAX_LEVEL];     // 2^L / S (exact power-of-two scaling of 1/S)
+    double s[LP_MAX_LEVEL];         // S / 2^L
+    unsigned long long off[LP_MAX_LEVEL];  // offset of the level's table (entries)
+};
+
+// Device-resident scalars of one context.
+struct DevScalars {
+    unsigned long long min_hc;      // bits of min h/c (positive doubles order as integers)
+    unsigned long long rmax;        // bits of max r
+    unsigned long long rmin;        // bits of min r
+    double dt, t, t_end, dt_in;
+    int n_total;                    // real + ghost particles
+    int n_ghost;
+    int max_count;
+    int n_fallback;
+    unsigned int error_bits;        // 1: capacity, 2: numeric
+    unsigned int done;              // lp_run: t reached t_end
+    unsigned long long n_limited;
+};
+
+// Particle state in the caller's order (real particles only).
+struct Soa {
+    double *x[3], *V, *u[3], *P;
+    const double *m;
+    float *phi;
+    uint8_t *flags;
+    int n;
+};
+
+// Mirror ghosts (ids n .. n + n_ghost - 1).
+struct Ghosts {
+    double *x[3], *V, *u[3], *P, *h, *r;
+};
+
+// Sorted (cell-ordered) copies of real + ghost particles.
+struct Sorted {
+    double *x[3], *V, *u[3], *P, *h, *r;
+    float *Vf, *uf[3], *Pf;
+    int *id;                        // original id (ghosts: n + g)
+};
+
+// Generic gather of up to 12 double arrays into cell order.
+struct ScatterArgs {
+    int nd;
+    const double *src[12];          // caller order (ids < n_real)
+    const double *gsrc[12];         // ghosts (ids >= n_real); may be NULL
+    double *dst[12];
+    int nff;
+    int fsrc[4];                    // which dst arrays get an FP32 copy
+    float *dstf[4];
+};
+
+// ---------------------------------------------------------------------------
+// Host launchers (defined in the .hip files).
+// ---------------------------------------------------------------------------
+void launch_reset_scalars(DevScalars *sc, double dt_in, int n_real, hipStream_t st);
+void launch_rminmax(const double *r, int n, DevScalars *sc, hipStream_t st);
+void launch_advance_time(DevScalars *sc, hipStream_t st);
+void launch_prep(const Soa &p, const DevCfg &cfg, DevScalars *sc, double *h, double *r, hipStream_t st);
+void launch_dt(const DevCfg &cfg, DevScalars *sc, int clip_t_end, hipStream_t st);
+void launch_ghost_count(const Soa &p, const DevCfg &cfg, DevScalars *sc, uint32_t *gcnt, hipStream_t st);
+void launch_ghost_write(const Soa &p, const DevCfg &cfg, DevScalars *sc, const uint32_t *goff,
+                        const double *h, const double *r, Ghosts g, hipStream_t st);
+void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
+void launch_keys(const double *const x[3], const double *const gx[3], int n_real, const int *n_total_dev,
+                 int n_total_cap, const DevGrid &g, int D, uint32_t *key, uint32_t *slot, uint32_t *cnt,
+                 hipStream_t st);
+// exclusive scan of n u32 values in place; out[n] receives the total; tmp needs scan_tmp_words(n)
+uint64_t scan_tmp_words(uint64_t n);
+void launch_scan_u32(uint32_t *data, uint64_t n, uint32_t *tmp, int *total_dev, hipStream_t st);
+void launch_scatter(const ScatterArgs &a, int n_real, const int *n_total_dev, int n_total_cap,
+                    const uint32_t *key, const uint32_t *slot, const uint32_t *start, int *sorted_id,
+                    hipStream_t st);
+void launch_coarsen(uint32_t *tables, const DevGrid &g, int D, const int *n_total_dev, hipStream_t st);
+void launch_search(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real, const uint32_t *tables,
+                   const DevGrid &g, const DevCfg &cfg, int *nbr, int ldn, int *count, DevScalars *sc,
+                   int group, hipStream_t st);
+void launch_lists_out(const int *sorted_id, const int *nbr, int ldn, const int *count, int n, int max_nb,
+                      int *count_out, int *idx_out, hipStream_t st);
+void launch_solve(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count, const int *n_total_dev,
+                  int n_total_cap, int n_real, const DevCfg &cfg, DevScalars *sc, int *queue, hipStream_t st);
+void launch_solve_fallback(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count,
+                           int n_real, const DevCfg &cfg, DevScalars *sc, const int *queue, int queue_cap,
+                           hipStream_t st);
+void launch_gfd(const Sorted &s, const double *const *fs, int nf, const int *nbr, int ldn, const int *count,
+                int n, const DevCfg &cfg, DevScalars *sc, int *queue, double *deriv, uint8_t *status,
+                hipStream_t st);
+void launch_gfd_fallback(const Sorted &s, const double *const *fs, int nf, const int *nbr, int ldn,
+                         const int *count, int n, const DevCfg &cfg, DevScalars *sc, const int *queue,
+                         int queue_cap, double *deriv, uint8_t *status, hipStream_t st);
+void launch_conservation(const Soa &p, const DevCfg &cfg, double *partials, int nblocks, double *out,
+                         hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Shared device helpers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long dbl_bits(double v) { return (unsigned long long)__double_as_longlong(v); }
+__device__ __forceinline__ double bits_dbl(unsigned long long b) { return __longlong_as_double((long long)b); }
+
+// Minimum-image displacement x_j - x_i along axis a.  Evaluated exactly as
+// written (IEEE binary64 add/sub only).
+__device__ __forceinline__ double min_image(const DevCfg &c, int a, double d) {
+    if (c.periodic[a]) {
+        if (d > c.half[a]) d = d - c.L[a];
+        else if (d < -c.half[a]) d = d + c.L[a];
+    }
+    return d;
+}
+
+// Squared distance ((dx*dx) + (dy*dy)) + (dz*dz) with every product and sum
+// rounded separately (no fused multiply-add), so that neighbour sets agree bit
+// for bit with any other IEEE binary64 evaluation of the same expression.
+template <int D>
+__device__ __forceinline__ double dist2_exact(const double dx[3]) {
+#pragma clang fp contract(off)
+    double s = dx[0] * dx[0] + dx[1] * dx[1];
+    if (D == 3) s = s + dx[2] * dx[2];
+    return s;
+}
+
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+__device__ __forceinline__ uint32_t spread2(uint32_t v) {
+    v &= 0xffffu;
+    v = (v | (v << 8)) & 0x00FF00FFu;
+    v = (v | (v << 4)) & 0x0F0F0F0Fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+template <int D>
+__device__ __forceinline__ uint32_t morton(const int c[3]) {
+    if (D == 3) return spread3((uint32_t)c[0]) | (spread3((uint32_t)c[1]) << 1) | (spread3((uint32_t)c[2]) << 2);
+    return spread2((uint32_t)c[0]) | (spread2((uint32_t)c[1]) << 1);
+}
+
+// Cell coordinate along one axis at level L (clamped into the grid).
+// Clamping happens in floating point before the conversion, so positions far
+// outside the grid (or NaN) map to an edge cell instead of overflowing.
+__device__ __forceinline__ int cell_coord(const DevGrid &g, int L, int a, double x) {
+    double t = (x - g.lo[a]) * g.inv_s[L];
+    int n = g.nc[L][a];
+    if (!(t >= 0.0)) return 0;
+    if (t >= (double)n) return n - 1;
+    int c = (int)t;
+    return c < n ? c : n - 1;
+}
+
+// floor(t) as an int, with t first clamped to +-2^24 (NaN -> 0)
+__device__ __forceinline__ int floor_clamped(double t) {
+    if (!(t == t)) return 0;
+    t = fmin(fmax(t, -16777216.0), 16777216.0);
+    return (int)floor(t);
+}
+
+// Level used by a particle of radius r: the coarsest level whose cells are not
+// larger than r (so the search box spans 2-5 cells per axis), clamped.
+__device__ __forceinline__ int level_for_radius(const DevGrid &g, double r) {
+    int L = g.L_lo;
+    while (L < g.L_hi && g.s[L] > r) ++L;
+    return L;
+}

@@ -1,0 +1,971 @@
+// lp_solve.hip -- the fused per-particle solver of the LP step on gfx950:
+// stencils (Sec. 2.2, step 4), GFD fits (Sec. 2.1), state estimator and
+// limiter, blended upwind / Lax-Wendroff update, EOS and particle mover
+// (Sec. 2.1; Sec. 2.2 steps 5-6).
+//
+// Fast path (k_solve): one thread per particle.  The second-order fit is solved
+// through the R factor of its QR decomposition obtained from the Cholesky
+// factor of the normal matrix (R^T R = A^T A) -- the rows of the scaled
+// stencil matrix stream through registers once, so the whole fit costs one
+// pass over the neighbour list, with no cross-lane traffic and no scratch
+// memory.  A condition estimate ||R||_F^2 ||R^-1||_F^2 of the normal matrix
+// routes every stencil for which this is not accurate to the FP64
+// pivoted-Householder path.
+//
+// Fallback (k_solve_fallback): one wave per particle, one stencil row per lane;
+// Householder QR with column pivoting (the paper's solver) with all column
+// norms and reflector products formed by wave-wide butterfly reductions.
+// It applies the same rank-deficiency rule as the definition (|R11|/|Rnn|).
+#include "lp_internal.h"
+
+template <int D> struct Dim;
+template <> struct Dim<3> { static constexpr int NU = 9, NF = 5, NS = 6, NG = 45; };
+template <> struct Dim<2> { static constexpr int NU = 5, NF = 4, NS = 3, NG = 15; };
+
+__host__ __device__ constexpr int tri(int p, int q, int n) { return p * n - p * (p - 1) / 2 + (q - p); }
+
+// ---------------------------------------------------------------------------
+// Stencil rows
+// ---------------------------------------------------------------------------
+template <int D, typename T>
+__device__ __forceinline__ void second_order_row(const T xi[3], T row[Dim<D>::NU]) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) row[a] = xi[a];
+#pragma unroll
+    for (int a = 0; a < D; ++a) row[D + a] = T(0.5) * xi[a] * xi[a];
+    if (D == 2) {
+        row[4] = xi[0] * xi[1];
+    } else {
+        row[6] = xi[0] * xi[1];
+        row[7] = xi[0] * xi[2];
+        row[8] = xi[1] * xi[2];
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void displacement(const Sorted &srt, const DevCfg &cfg, int j, const double xi[3],
+                                             double dx[3]) {
+    dx[0] = min_image(cfg, 0, srt.x[0][j] - xi[0]);
+    dx[1] = min_image(cfg, 1, srt.x[1][j] - xi[1]);
+    dx[2] = D == 3 ? min_image(cfg, 2, srt.x[2][j] - xi[2]) : 0.0;
+}
+
+template <int D>
+__device__ __forceinline__ int octant(const double dx[3]) {
+    int o = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) o |= (dx[a] >= 0.0 ? 1 : 0) << a;
+    return o;
+}
+
+// Visit the Lax-Wendroff stencil: all neighbours when they fit under the cap,
+// otherwise the first `cap` in the order (rank within own octant, list
+// position), i.e. the top of the list holds members of every octant.
+template <int D, typename F>
+__device__ __forceinline__ void for_lw_stencil(const Sorted &srt, const DevCfg &cfg, const int *nbr, int ldn, int s,
+                                               int k, const double xi[3], F &&body) {
+    const int cap = cfg.lw_cap;
+    int Rstar = 1 << 30, rem = 0;
+    if (k > cap) {
+        unsigned long long c03 = 0, c47 = 0;  // octant counts, 16 bits each
+        for (int t = 0; t < k; ++t) {
+            int j = nbr[(int64_t)t * ldn + s];
+            double dx[3];
+            displacement<D>(srt, cfg, j, xi, dx);
+            int o = octant<D>(dx);
+            if (o < 4) c03 += 1ull << (16 * o); else c47 += 1ull << (16 * (o - 4));
+        }
+        int cnt[8];
+        for (int o = 0; o < 4; ++o) cnt[o] = (int)((c03 >> (16 * o)) & 0xffff);
+        for (int o = 0; o < 4; ++o) cnt[4 + o] = (int)((c47 >> (16 * o)) & 0xffff);
+        int R = 0, taken = 0;
+        for (;;) {
+            int next = 0;
+            for (int o = 0; o < 8; ++o) next += cnt[o] < R + 1 ? cnt[o] : R + 1;
+            if (next > cap) break;
+            taken = next;
+            ++R;
+        }
+        Rstar = R;
+        rem = cap - taken;
+    }
+    unsigned long long s03 = 0, s47 = 0;
+    int takenR = 0;
+    for (int t = 0; t < k; ++t) {
+        int j = nbr[(int64_t)t * ldn + s];
+        double dx[3];
+        displacement<D>(srt, cfg, j, xi, dx);
+        if (k > cap) {
+            int o = octant<D>(dx);
+            int rho;
+            if (o < 4) { rho = (int)((s03 >> (16 * o)) & 0xffff); s03 += 1ull << (16 * o); }
+            else { rho = (int)((s47 >> (16 * (o - 4))) & 0xffff); s47 += 1ull << (16 * (o - 4)); }
+            bool take = rho < Rstar || (rho == Rstar && takenR < rem);
+            if (rho == Rstar && take) ++takenR;
+            if (!take) continue;
+        }
+        body(j, dx);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Small dense algebra in registers
+// ---------------------------------------------------------------------------
+// Cholesky of packed upper-triangular G (in place -> R, R^T R = G).
+// Returns false on a non-positive pivot.  inv[j] = 1 / R_jj.
+template <int N, typename T>
+__device__ __forceinline__ bool cholesky(T G[N * (N + 1) / 2], T inv[N]) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        T s = G[tri(j, j, N)];
+#pragma unroll
+        for (int k = 0; k < j; ++k) s -= G[tri(k, j, N)] * G[tri(k, j, N)];
+        if (!(s > T(0))) return false;
+        T d = sqrt(s);
+        G[tri(j, j, N)] = d;
+        T iv = T(1) / d;
+        inv[j] = iv;
+#pragma unroll
+        for (int i = j + 1; i < N; ++i) {
+            T t = G[tri(j, i, N)];
+#pragma unroll
+            for (int k = 0; k < j; ++k) t -= G[tri(k, j, N)] * G[tri(k, i, N)];
+            G[tri(j, i, N)] = t * iv;
+        }
+    }
+    return true;
+}
+
+// ||R||_F^2 * ||R^-1||_F^2: an upper bound of cond_2(R)^2 (= cond_2 of the
+// normal matrix) within a factor N^2; R^-1 is formed column by column.
+template <int N, typename T>
+__device__ __forceinline__ T cond_estimate(const T R[N * (N + 1) / 2], const T inv[N]) {
+    T nr = 0, ni = 0;
+#pragma unroll
+    for (int q = 0; q < N * (N + 1) / 2; ++q) nr += R[q] * R[q];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        T col[N];
+        col[j] = inv[j];
+        ni += col[j] * col[j];
+#pragma unroll
+        for (int i = j - 1; i >= 0; --i) {
+            T acc = 0;
+#pragma unroll
+            for (int k = i + 1; k <= j; ++k) acc += R[tri(i, k, N)] * col[k];
+            col[i] = -acc * inv[i];
+            ni += col[i] * col[i];
+        }
+    }
+    return nr * ni;
+}
+
+// Solve R^T R y = b for NR right-hand sides stored column-major b[c * N + p].
+template <int N, int NR, typename T, typename TB>
+__device__ __forceinline__ void chol_solve(const T R[N * (N + 1) / 2], const T inv[N], TB b[N * NR]) {
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            TB t = b[c * N + j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) t -= TB(R[tri(k, j, N)]) * b[c * N + k];
+            b[c * N + j] = t * TB(inv[j]);
+        }
+#pragma unroll
+        for (int j = N - 1; j >= 0; --j) {
+            TB t = b[c * N + j];
+#pragma unroll
+            for (int k = j + 1; k < N; ++k) t -= TB(R[tri(j, k, N)]) * b[c * N + k];
+            b[c * N + j] = t * TB(inv[j]);
+        }
+    }
+}
+
+// Pivoted |R11|/|Rnn| of a D-column half-ball matrix from its normal matrix:
+// with diagonal pivoting, Cholesky takes the same pivots as Householder QR
+// with column pivoting and yields the same R (up to signs).
+template <int D, typename T>
+__device__ __forceinline__ T halfball_cond(const T G[D * (D + 1) / 2]) {
+    if (D == 2) {
+        T g00 = G[0], g01 = G[1], g11 = G[2];
+        T gp = g00 >= g11 ? g00 : g11;
+        T det = g00 * g11 - g01 * g01;
+        if (!(det > T(0))) return T(INFINITY);
+        return sqrt(gp * gp / det);
+    } else {
+        T g00 = G[0], g01 = G[1], g02 = G[2], g11 = G[3], g12 = G[4], g22 = G[5];
+        T gpp, gpa, gpb, gaa, gbb, gab;
+        if (g00 >= g11 && g00 >= g22) { gpp = g00; gpa = g01; gpb = g02; gaa = g11; gbb = g22; gab = g12; }
+        else if (g11 >= g22) { gpp = g11; gpa = g01; gpb = g12; gaa = g00; gbb = g22; gab = g02; }
+        else { gpp = g22; gpa = g02; gpb = g12; gaa = g00; gbb = g11; gab = g01; }
+        if (!(gpp > T(0))) return T(INFINITY);
+        T saa = gaa - gpa * gpa / gpp, sbb = gbb - gpb * gpb / gpp, sab = gab - gpa * gpb / gpp;
+        T s2 = saa >= sbb ? saa : sbb;
+        if (!(s2 > T(0))) return T(INFINITY);
+        T s3 = (saa * sbb - sab * sab) / s2;
+        if (!(s3 > T(0))) return T(INFINITY);
+        return sqrt(gpp / s3);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Rates (Sec. 2.1).  grad[f][a], hess[f][q] with q over (11, 22, [33,] 12 [, 13, 23]);
+// fields f: 0 = V, 1..D = u, D+1 = P.
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ int mixed_q(int a, int b) {
+    if (a > b) { int t = a; a = b; b = t; }
+    if (D == 2) return 2;
+    return (a == 0 && b == 1) ? 3 : ((a == 0 && b == 2) ? 4 : 5);
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void lw_rates(T gamma, T dt, const T st[Dim<D>::NF], const T grad[Dim<D>::NF][3],
+                                         const T hess[Dim<D>::NF][Dim<D>::NS], T rate[Dim<D>::NF]) {
+    constexpr int FP = D + 1;
+    T V = st[0], P = st[FP];
+    T theta = 0, Tr = 0, gVgP = 0, lapP = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) theta += grad[1 + a][a];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int k = 0; k < D; ++k) Tr += grad[1 + k][i] * grad[1 + i][k];
+#pragma unroll
+    for (int a = 0; a < D; ++a) gVgP += grad[0][a] * grad[FP][a];
+#pragma unroll
+    for (int a = 0; a < D; ++a) lapP += hess[FP][a];
+    T Vt = V * theta;
+    T Pt = -gamma * P * theta;
+    T Vtt = V * theta * theta - V * gVgP - V * V * lapP - V * Tr;
+    T Ptt = gamma * gamma * P * theta * theta + gamma * P * gVgP + gamma * V * P * lapP + gamma * P * Tr;
+    T half_dt = T(0.5) * dt;
+    rate[0] = Vt + half_dt * Vtt;
+    rate[FP] = Pt + half_dt * Ptt;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        T dPi = grad[FP][i];
+        T dth = 0, uxP = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            dth += (i == k) ? hess[1 + k][i] : hess[1 + k][mixed_q<D>(i, k)];
+            uxP += grad[1 + k][i] * grad[FP][k];
+        }
+        T ut = -V * dPi;
+        T utt = (gamma - T(1)) * V * theta * dPi + gamma * V * P * dth + V * uxP;
+        rate[1 + i] = ut + half_dt * utt;
+    }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void uw_rates(T gamma, const T st[Dim<D>::NF], const T dl[3][3], const T dr[3][3],
+                                         T rate[Dim<D>::NF]) {
+    constexpr int FP = D + 1;
+    T V = st[0], P = st[FP];
+    T c = sqrt(gamma * P * V);
+    T VV_c = V * V / c;
+    T rv = 0, rp = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        T ul = dl[a][1], ur = dr[a][1], Pl = dl[a][2], Pr = dr[a][2];
+        rv += T(0.5) * V * (ur + ul) - T(0.5) * VV_c * (Pr - Pl);
+        rate[1 + a] = T(0.5) * c * (ur - ul) - T(0.5) * V * (Pr + Pl);
+        rp += -T(0.5) * gamma * P * (ur + ul) + T(0.5) * c * (Pr - Pl);
+    }
+    rate[0] = rv;
+    rate[FP] = rp;
+}
+
+template <typename T>
+__device__ __forceinline__ T limiter(T r) {
+    if (isinf(r)) return T(0);
+    T q = sqrt(r);
+    if (r <= T(1.5)) return T(1.25) * exp(T(1) - q);
+    T t = q - T(1);
+    return T(1.25) * exp(T(-4.5) * (t * t));
+}
+
+// ---------------------------------------------------------------------------
+// Half-ball fits, estimator, blended update and mover for one particle, given
+// its second-order derivatives.  Writes the caller's arrays at index i.
+// ---------------------------------------------------------------------------
+template <int D, typename T>
+__device__ __forceinline__ void finish_particle(const Sorted &srt, const Soa &p, const DevCfg &cfg, DevScalars *sc,
+                                                const int *nbr, int ldn, int s, int i, int k, double dt,
+                                                const double xi[3], const double st[Dim<D>::NF], double h, double r,
+                                                const double grad[Dim<D>::NF][3], const double hess[Dim<D>::NF][Dim<D>::NS],
+                                                int lw_status, uint8_t flags) {
+    constexpr int NF = Dim<D>::NF, FP = D + 1, NGD = D * (D + 1) / 2;
+    const bool use_f = sizeof(T) == 4;
+    const int ucap = cfg.uw_cap;
+    const double inv_r = 1.0 / r;
+    T dl[3][3], dr[3][3];
+    bool valid_l[3] = {false, false, false}, valid_r[3] = {false, false, false};
+    bool vac = false, subst = false;
+    const T Pi_T = (T)st[FP];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        T Gl[NGD], Gr[NGD], Bl[D * 3], Br[D * 3], Sl[D], Sr[D];
+#pragma unroll
+        for (int q = 0; q < NGD; ++q) { Gl[q] = 0; Gr[q] = 0; }
+#pragma unroll
+        for (int q = 0; q < D * 3; ++q) { Bl[q] = 0; Br[q] = 0; }
+#pragma unroll
+        for (int q = 0; q < D; ++q) { Sl[q] = 0; Sr[q] = 0; }
+        int nl = 0, nr = 0;
+        const T fi[3] = {(T)st[0], (T)st[1 + a], (T)st[FP]};
+        for (int t = 0; t < k && (nl < ucap || nr < ucap); ++t) {
+            int j = nbr[(int64_t)t * ldn + s];
+            double dx[3];
+            displacement<D>(srt, cfg, j, xi, dx);
+            bool right = dx[a] > 0.0, left = dx[a] < 0.0;
+            if (!((right && nr < ucap) || (left && nl < ucap))) continue;
+            T x[3];
+#pragma unroll
+            for (int b = 0; b < D; ++b) x[b] = (T)(dx[b] * inv_r);
+            T fj[3];
+            if (use_f) { fj[0] = (T)srt.Vf[j]; fj[1] = (T)srt.uf[a][j]; fj[2] = (T)srt.Pf[j]; }
+            else { fj[0] = (T)srt.V[j]; fj[1] = (T)srt.u[a][j]; fj[2] = (T)srt.P[j]; }
+            T bq[3] = {fj[0] - fi[0], fj[1] - fi[1], fj[2] - fi[2]};
+            // both sides accumulate with 0/1 weights (no pointer selects, so the
+            // accumulators stay in registers)
+            T wr = right ? T(1) : T(0), wl = right ? T(0) : T(1);
+            int q = 0;
+#pragma unroll
+            for (int b = 0; b < D; ++b)
+#pragma unroll
+                for (int c = b; c < D; ++c, ++q) {
+                    T v = x[b] * x[c];
+                    Gr[q] += wr * v;
+                    Gl[q] += wl * v;
+                }
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    T v = x[b] * bq[f];
+                    Br[b * 3 + f] += wr * v;
+                    Bl[b * 3 + f] += wl * v;
+                }
+                Sr[b] += wr * x[b];
+                Sl[b] += wl * x[b];
+            }
+            if (right) ++nr; else ++nl;
+        }
+        // per side: fit, vacuum ghosts, or LW substitute
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const bool isr = side == 1;
+            int n_own = isr ? nr : nl, n_opp = isr ? nl : nr;
+            T d[3] = {0, 0, 0};
+            bool ok = false, real_fit = false;
+            if (cfg.vacuum && n_own < ucap) {
+                // mirrored members of the opposite half-ball with P = 0, V = V_i, u = u_i
+                T Gm[NGD], rhs[D];
+                int q = 0;
+#pragma unroll
+                for (int b = 0; b < D; ++b)
+#pragma unroll
+                    for (int c = b; c < D; ++c, ++q) {
+                        T g = isr ? Gl[q] : Gr[q];
+                        bool flip = (b == a) != (c == a);
+                        Gm[q] = flip ? -g : g;
+                    }
+#pragma unroll
+                for (int b = 0; b < D; ++b) {
+                    T sv = isr ? Sl[b] : Sr[b];
+                    rhs[b] = -Pi_T * (b == a ? -sv : sv);
+                }
+                if (n_opp >= D && halfball_cond<D, T>(Gm) <= (T)cfg.uw_cond_max) {
+                    T inv[D];
+                    if (cholesky<D, T>(Gm, inv)) {
+                        chol_solve<D, 1, T, T>(Gm, inv, rhs);
+                        d[2] = rhs[a] * (T)inv_r;
+                        ok = true;
+                        vac = true;
+                    }
+                }
+            } else {
+                T Gs[NGD], Bs[D * 3];
+#pragma unroll
+                for (int q = 0; q < NGD; ++q) Gs[q] = isr ? Gr[q] : Gl[q];
+                // right-hand sides column-major for chol_solve: Bs[f * D + b]
+#pragma unroll
+                for (int b = 0; b < D; ++b)
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) Bs[f * D + b] = isr ? Br[b * 3 + f] : Bl[b * 3 + f];
+                if (n_own >= D && halfball_cond<D, T>(Gs) <= (T)cfg.uw_cond_max) {
+                    T inv[D];
+                    if (cholesky<D, T>(Gs, inv)) {
+                        chol_solve<D, 3, T, T>(Gs, inv, Bs);
+#pragma unroll
+                        for (int f = 0; f < 3; ++f) d[f] = Bs[f * D + a] * (T)inv_r;
+                        ok = true;
+                        real_fit = true;
+                    }
+                }
+            }
+            if (!ok) {
+                d[0] = (T)grad[0][a];
+                d[1] = (T)grad[1 + a][a];
+                d[2] = (T)grad[FP][a];
+                subst = true;
+            }
+#pragma unroll
+            for (int f = 0; f < 3; ++f) { if (isr) dr[a][f] = d[f]; else dl[a][f] = d[f]; }
+            if (isr) valid_r[a] = real_fit; else valid_l[a] = real_fit;
+        }
+    }
+    // state estimator on P and V, one phi per particle
+    double phi;
+    if (cfg.est_mode == LP_EST_INJECTED && p.phi) {
+        phi = (double)p.phi[i];
+    } else {
+        T rmax = T(1);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            if (!(valid_l[a] && valid_r[a])) continue;
+#pragma unroll
+            for (int q = 0; q < 3; q += 2) {
+                T sl = dl[a][q], sr = dr[a][q];
+                T sv = q == 0 ? (T)st[0] : (T)st[FP];
+                T big = fabs(sl) > fabs(sr) ? fabs(sl) : fabs(sr);
+                if (big * (T)h > (T)cfg.est_eps * fabs(sv)) {
+                    T rr = (sl * sr <= T(0)) ? T(INFINITY) : T(0.5) * (sr / sl + sl / sr);
+                    if (rr > rmax) rmax = rr;
+                }
+            }
+        }
+        T ph = limiter<T>(rmax);
+        phi = (double)(ph < T(1) ? ph : T(1));
+        if (lw_status != 0 || vac) phi = 0.0;
+    }
+    // rates
+    T stT[NF], gT[NF][3], hT[NF][Dim<D>::NS], lw[NF], uw[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        stT[f] = (T)st[f];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gT[f][a] = (T)grad[f][a];
+#pragma unroll
+        for (int q = 0; q < Dim<D>::NS; ++q) hT[f][q] = (T)hess[f][q];
+    }
+    lw_rates<D, T>((T)cfg.gamma, (T)dt, stT, gT, hT, lw);
+    uw_rates<D, T>((T)cfg.gamma, stT, dl, dr, uw);
+    double ns[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        double u_ = (double)uw[f], l_ = (double)lw[f];
+        ns[f] = st[f] + dt * (u_ - phi * (u_ - l_));
+    }
+    // particle mover: x^{n+1} = x^n + dt/2 (u^n + u^{n+1})
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        double xn = xi[a] + 0.5 * dt * (st[1 + a] + ns[1 + a]);
+        if (cfg.periodic[a]) {
+            if (xn >= cfg.hi[a]) xn -= cfg.L[a];
+            else if (xn < cfg.lo[a]) xn += cfg.L[a];
+        }
+        p.x[a][i] = xn;
+        p.u[a][i] = ns[1 + a];
+    }
+    p.V[i] = ns[0];
+    p.P[i] = ns[FP];
+    if (phi < 1.0) flags |= LP_FLAG_LIMITED;
+    if (lw_status != 0) flags |= LP_FLAG_DEGENERATE;
+    if (vac) flags |= LP_FLAG_VACUUM;
+    if (subst) flags |= LP_FLAG_SUBSTITUTED;
+    if (!(ns[0] > 0.0) || !(ns[FP] > 0.0)) {
+        flags |= LP_FLAG_NUMERIC;
+        atomicOr(&sc->error_bits, 2u);
+    }
+    if (p.flags) p.flags[i] = flags;
+    if (p.phi && cfg.est_mode != LP_EST_INJECTED) p.phi[i] = (float)phi;
+    if (phi < 1.0) atomicAdd(&sc->n_limited, 1ull);
+}
+
+// ---------------------------------------------------------------------------
+// Fast path: one thread per particle.
+// ---------------------------------------------------------------------------
+template <int D, typename T, bool REFINE>
+__global__ __launch_bounds__(LP_BLOCK) void k_solve(Sorted srt, Soa p, const int *nbr, int ldn, const int *count,
+                                                    const int *n_total_dev, int n_real, DevCfg cfg, DevScalars *sc,
+                                                    int *queue) {
+    constexpr int NU = Dim<D>::NU, NF = Dim<D>::NF, NG = Dim<D>::NG, NS = Dim<D>::NS, FP = D + 1;
+    const bool use_f = sizeof(T) == 4;
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= *n_total_dev) return;
+    int i = srt.id[s];
+    if (i >= n_real) return;
+    int k = count[s];
+    if (k > cfg.max_nb) k = cfg.max_nb;
+    double xi[3] = {srt.x[0][s], srt.x[1][s], D == 3 ? srt.x[2][s] : 0.0};
+    double st[NF];
+    st[0] = srt.V[s];
+#pragma unroll
+    for (int a = 0; a < D; ++a) st[1 + a] = srt.u[a][s];
+    st[FP] = srt.P[s];
+    const double h = srt.h[s];
+    const double r = cfg.kappa * h;
+    const double inv_r = 1.0 / r;
+    const double dt = sc->dt;
+    T fi[NF];
+    if (use_f) {
+        fi[0] = (T)srt.Vf[s];
+#pragma unroll
+        for (int a = 0; a < D; ++a) fi[1 + a] = (T)srt.uf[a][s];
+        fi[FP] = (T)srt.Pf[s];
+    } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) fi[f] = (T)st[f];
+    }
+    // normal equations of the scaled second-order system over the LW stencil
+    T G[NG], B[NF * NU];
+#pragma unroll
+    for (int q = 0; q < NG; ++q) G[q] = 0;
+#pragma unroll
+    for (int q = 0; q < NF * NU; ++q) B[q] = 0;
+    int m = 0;
+    for_lw_stencil<D>(srt, cfg, nbr, ldn, s, k, xi, [&](int j, const double dx[3]) {
+        T x[3];
+#pragma unroll
+        for (int a = 0; a < D; ++a) x[a] = (T)(dx[a] * inv_r);
+        T row[NU];
+        second_order_row<D, T>(x, row);
+        T fj[NF];
+        if (use_f) {
+            fj[0] = (T)srt.Vf[j];
+#pragma unroll
+            for (int a = 0; a < D; ++a) fj[1 + a] = (T)srt.uf[a][j];
+            fj[FP] = (T)srt.Pf[j];
+        } else {
+            fj[0] = (T)srt.V[j];
+#pragma unroll
+            for (int a = 0; a < D; ++a) fj[1 + a] = (T)srt.u[a][j];
+            fj[FP] = (T)srt.P[j];
+        }
+#pragma unroll
+        for (int pp = 0; pp < NU; ++pp)
+#pragma unroll
+            for (int qq = pp; qq < NU; ++qq) G[tri(pp, qq, NU)] += row[pp] * row[qq];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            T b = fj[f] - fi[f];
+#pragma unroll
+            for (int pp = 0; pp < NU; ++pp) B[f * NU + pp] += row[pp] * b;
+        }
+        ++m;
+    });
+    T inv[NU];
+    bool good = m >= NU && cholesky<NU, T>(G, inv);
+    if (good) good = cond_estimate<NU, T>(G, inv) <= (T)cfg.cond_fb;
+    if (!good) {
+        int slot = atomicAdd(&sc->n_fallback, 1);
+        queue[slot] = s;
+        return;
+    }
+    double Y[NF * NU];
+    {
+        T Bs[NF * NU];
+#pragma unroll
+        for (int q = 0; q < NF * NU; ++q) Bs[q] = B[q];
+        chol_solve<NU, NF, T, T>(G, inv, Bs);
+#pragma unroll
+        for (int q = 0; q < NF * NU; ++q) Y[q] = (double)Bs[q];
+    }
+    if (REFINE) {
+        // one refinement step: FP64 residual of the FP64 system, correction
+        // through the same factor
+        double Ar[NF * NU];
+#pragma unroll
+        for (int q = 0; q < NF * NU; ++q) Ar[q] = 0.0;
+        for_lw_stencil<D>(srt, cfg, nbr, ldn, s, k, xi, [&](int j, const double dx[3]) {
+            double x[3];
+#pragma unroll
+            for (int a = 0; a < D; ++a) x[a] = dx[a] * inv_r;
+            double row[NU];
+            second_order_row<D, double>(x, row);
+            double fj[NF];
+            fj[0] = srt.V[j];
+#pragma unroll
+            for (int a = 0; a < D; ++a) fj[1 + a] = srt.u[a][j];
+            fj[FP] = srt.P[j];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                double res = fj[f] - st[f];
+#pragma unroll
+                for (int pp = 0; pp < NU; ++pp) res -= row[pp] * Y[f * NU + pp];
+#pragma unroll
+                for (int pp = 0; pp < NU; ++pp) Ar[f * NU + pp] += row[pp] * res;
+            }
+        });
+        chol_solve<NU, NF, T, double>(G, inv, Ar);
+#pragma unroll
+        for (int q = 0; q < NF * NU; ++q) Y[q] += Ar[q];
+    }
+    double grad[NF][3], hess[NF][NS];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) grad[f][a] = a < D ? Y[f * NU + a] * inv_r : 0.0;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) hess[f][q] = Y[f * NU + D + q] * inv_r * inv_r;
+    }
+    finish_particle<D, T>(srt, p, cfg, sc, nbr, ldn, s, i, k, dt, xi, st, h, r, grad, hess, 0, 0);
+}
+
+template <int D, typename T, bool RF>
+static void launch_solve_t(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count,
+                           const int *n_total_dev, int n_total_cap, int n_real, const DevCfg &cfg, DevScalars *sc,
+                           int *queue, hipStream_t st) {
+    unsigned blocks = (unsigned)((n_total_cap + LP_BLOCK - 1) / LP_BLOCK);
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((k_solve<D, T, RF>), dim3(blocks), dim3(LP_BLOCK), 0, st, s, p, nbr, ldn, count, n_total_dev,
+                       n_real, cfg, sc, queue);
+}
+
+void launch_solve(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count, const int *n_total_dev,
+                  int n_total_cap, int n_real, const DevCfg &cfg, DevScalars *sc, int *queue, hipStream_t st) {
+#define LSV(DD, TT, RR) launch_solve_t<DD, TT, RR>(s, p, nbr, ldn, count, n_total_dev, n_total_cap, n_real, cfg, sc, queue, st)
+    bool mixed = cfg.precision == LP_MIXED;
+    if (cfg.D == 3) {
+        if (!mixed) LSV(3, double, false);
+        else if (cfg.refine) LSV(3, float, true);
+        else LSV(3, float, false);
+    } else {
+        if (!mixed) LSV(2, double, false);
+        else if (cfg.refine) LSV(2, float, true);
+        else LSV(2, float, false);
+    }
+#undef LSV
+    (void)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Wave-cooperative Householder QR with column pivoting (one wave, one row per
+// lane).  a[N]: this lane's row, b[NR]: its right-hand sides.  Rows at lanes
+// >= m are zero.  Returns |R11|/|Rnn| and the solution X[q][c] (all lanes).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <int N, int NR>
+__device__ __forceinline__ double wave_qrp_solve(double a[N], double b[NR], double X[N][NR]) {
+    const int l = threadIdx.x & 63;
+    int perm[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) perm[j] = j;
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+        // pivot: remaining column of largest norm over rows p..
+        int best = p;
+        double bn = -1.0;
+#pragma unroll
+        for (int j = p; j < N; ++j) {
+            double c = wave_sum(l >= p ? a[j] * a[j] : 0.0);
+            if (c > bn) { bn = c; best = j; }
+        }
+#pragma unroll
+        for (int j = p + 1; j < N; ++j)
+            if (j == best) {  // wave-uniform
+                double t = a[p]; a[p] = a[j]; a[j] = t;
+                int u = perm[p]; perm[p] = perm[j]; perm[j] = u;
+            }
+        double x0 = __shfl(a[p], p);
+        double sigma = wave_sum(l > p ? a[p] * a[p] : 0.0);
+        double normx = sqrt(x0 * x0 + sigma);
+        if (normx == 0.0) continue;
+        double alpha = x0 >= 0.0 ? -normx : normx;
+        double v0 = x0 - alpha;
+        double tau = -1.0 / (alpha * v0);
+        double v = l == p ? v0 : (l > p ? a[p] : 0.0);
+#pragma unroll
+        for (int j = p + 1; j < N; ++j) {
+            double w = wave_sum(v * a[j]) * tau;
+            a[j] -= w * v;
+        }
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            double w = wave_sum(v * b[c]) * tau;
+            b[c] -= w * v;
+        }
+        a[p] = l == p ? alpha : (l > p ? 0.0 : a[p]);
+    }
+    double r11 = fabs(__shfl(a[0], 0));
+    double rnn = fabs(__shfl(a[N - 1], N - 1));
+    double cond = rnn == 0.0 ? INFINITY : r11 / rnn;
+    double y[N][NR];
+#pragma unroll
+    for (int p = N - 1; p >= 0; --p) {
+        double d = a[p];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            double t = b[c];
+#pragma unroll
+            for (int j = p + 1; j < N; ++j) t -= a[j] * y[j][c];
+            double v = d == 0.0 ? 0.0 : t / d;
+            y[p][c] = __shfl(v, p);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            double v = 0.0;
+#pragma unroll
+            for (int pp = 0; pp < N; ++pp)
+                if (perm[pp] == q) v = y[pp][c];
+            X[q][c] = v;
+        }
+    return cond;
+}
+
+// Second-order fit of particle s by the wave QR, with the deficiency rule of
+// the definition: k < NU or |R11|/|Rnn| > cond_max -> linear fit on the same
+// rows (status 1); fewer than D usable rows -> status 2.
+// fj_of(j, f) returns field f of neighbour j; fi[f] the particle's own values.
+template <int D, int NF, typename FJ>
+__device__ __forceinline__ int lw_fit_wave(const Sorted &srt, const DevCfg &cfg, const int *nbr, int ldn, int s, int k,
+                                          const double xi[3], double r, const double fi[NF], FJ &&fj_of,
+                                          double grad[NF][3], double hess[NF][Dim<D>::NS], int *sel_lds) {
+    constexpr int NU = Dim<D>::NU, NS = Dim<D>::NS;
+    const int l = threadIdx.x & 63;
+    __shared__ int m_sh;
+    if (l == 0) {
+        int m = 0;
+        for_lw_stencil<D>(srt, cfg, nbr, ldn, s, k, xi, [&](int j, const double dx[3]) { sel_lds[m++] = j; });
+        m_sh = m;
+    }
+    __syncthreads();
+    const int m = m_sh;
+    const double inv_r = 1.0 / r;
+    double row[NU], b[NF];
+#pragma unroll
+    for (int q = 0; q < NU; ++q) row[q] = 0.0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) b[f] = 0.0;
+    if (l < m) {
+        int j = sel_lds[l];
+        double dx[3];
+        displacement<D>(srt, cfg, j, xi, dx);
+        double x[3];
+#pragma unroll
+        for (int a = 0; a < D; ++a) x[a] = dx[a] / r;
+        second_order_row<D, double>(x, row);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) b[f] = fj_of(j, f) - fi[f];
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) grad[f][a] = 0.0;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) hess[f][q] = 0.0;
+    }
+    int status = 0;
+    double cond = INFINITY;
+    double X[NU][NF];
+    double a2[NU], b2[NF];
+#pragma unroll
+    for (int q = 0; q < NU; ++q) a2[q] = row[q];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) b2[f] = b[f];
+    if (m >= NU) cond = wave_qrp_solve<NU, NF>(a2, b2, X);
+    if (m >= NU && cond <= cfg.cond_max) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+#pragma unroll
+            for (int a = 0; a < D; ++a) grad[f][a] = X[a][f] * inv_r;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) hess[f][q] = X[D + q][f] * (inv_r * inv_r);
+        }
+    } else {
+        status = 1;
+        double a1[D], b1[NF], X1[D][NF];
+#pragma unroll
+        for (int q = 0; q < D; ++q) a1[q] = row[q];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) b1[f] = b[f];
+        double c1 = INFINITY;
+        if (m >= D) c1 = wave_qrp_solve<D, NF>(a1, b1, X1);
+        if (m >= D && c1 <= cfg.cond_max) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int a = 0; a < D; ++a) grad[f][a] = X1[a][f] * inv_r;
+        } else {
+            status = 2;
+        }
+    }
+    return status;
+}
+
+template <int D>
+__global__ __launch_bounds__(64) void k_solve_fallback(Sorted srt, Soa p, const int *nbr, int ldn, const int *count,
+                                                       int n_real, DevCfg cfg, DevScalars *sc, const int *queue) {
+    constexpr int NF = Dim<D>::NF, NS = Dim<D>::NS, FP = D + 1;
+    __shared__ int sel[64];
+    const int nq = sc->n_fallback;
+    for (int w = blockIdx.x; w < nq; w += gridDim.x) {
+        int s = queue[w];
+        int i = srt.id[s];
+        int k = count[s];
+        if (k > cfg.max_nb) k = cfg.max_nb;
+        double xi[3] = {srt.x[0][s], srt.x[1][s], D == 3 ? srt.x[2][s] : 0.0};
+        double st[NF];
+        st[0] = srt.V[s];
+        for (int a = 0; a < D; ++a) st[1 + a] = srt.u[a][s];
+        st[FP] = srt.P[s];
+        const double h = srt.h[s];
+        const double r = cfg.kappa * h;
+        double grad[NF][3], hess[NF][NS];
+        int status = lw_fit_wave<D, NF>(srt, cfg, nbr, ldn, s, k, xi, r, st,
+                                        [&](int j, int f) {
+                                            return f == 0 ? srt.V[j] : (f == FP ? srt.P[j] : srt.u[f - 1][j]);
+                                        },
+                                        grad, hess, sel);
+        if ((threadIdx.x & 63) == 0)
+            finish_particle<D, double>(srt, p, cfg, sc, nbr, ldn, s, i, k, sc->dt, xi, st, h, r, grad, hess, status,
+                                       LP_FLAG_FALLBACK);
+        __syncthreads();
+    }
+}
+
+void launch_solve_fallback(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count, int n_real,
+                           const DevCfg &cfg, DevScalars *sc, const int *queue, int queue_cap, hipStream_t st) {
+    unsigned blocks = queue_cap < 2048 ? (unsigned)(queue_cap > 0 ? queue_cap : 1) : 2048u;
+    if (cfg.D == 3)
+        hipLaunchKernelGGL(k_solve_fallback<3>, dim3(blocks), dim3(64), 0, st, s, p, nbr, ldn, count, n_real, cfg, sc,
+                           queue);
+    else
+        hipLaunchKernelGGL(k_solve_fallback<2>, dim3(blocks), dim3(64), 0, st, s, p, nbr, ldn, count, n_real, cfg, sc,
+                           queue);
+    (void)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Derivative operator alone (lp_gfd): FP64 normal-equation fit with the same
+// fallback rule, nf <= 5 fields given in cell order.
+// ---------------------------------------------------------------------------
+struct FieldPtrs { const double *f[5]; };
+
+template <int D>
+__global__ __launch_bounds__(LP_BLOCK) void k_gfd(Sorted srt, FieldPtrs fs, int nf, const int *nbr, int ldn,
+                                                  const int *count, int n, DevCfg cfg, DevScalars *sc, int *queue,
+                                                  double *deriv, uint8_t *status) {
+    constexpr int NU = Dim<D>::NU, NG = Dim<D>::NG, NS = Dim<D>::NS;
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int i = srt.id[s];
+    int k = count[s];
+    if (k > cfg.max_nb) k = cfg.max_nb;
+    double xi[3] = {srt.x[0][s], srt.x[1][s], D == 3 ? srt.x[2][s] : 0.0};
+    const double r = srt.r[s];
+    const double inv_r = 1.0 / r;
+    double fi[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) fi[f] = f < nf ? fs.f[f][s] : 0.0;
+    double G[NG], B[5 * NU];
+#pragma unroll
+    for (int q = 0; q < NG; ++q) G[q] = 0;
+#pragma unroll
+    for (int q = 0; q < 5 * NU; ++q) B[q] = 0;
+    int m = 0;
+    for_lw_stencil<D>(srt, cfg, nbr, ldn, s, k, xi, [&](int j, const double dx[3]) {
+        double x[3];
+#pragma unroll
+        for (int a = 0; a < D; ++a) x[a] = dx[a] * inv_r;
+        double row[NU];
+        second_order_row<D, double>(x, row);
+#pragma unroll
+        for (int pp = 0; pp < NU; ++pp)
+#pragma unroll
+            for (int qq = pp; qq < NU; ++qq) G[tri(pp, qq, NU)] += row[pp] * row[qq];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+            if (f >= nf) break;
+            double b = fs.f[f][j] - fi[f];
+#pragma unroll
+            for (int pp = 0; pp < NU; ++pp) B[f * NU + pp] += row[pp] * b;
+        }
+        ++m;
+    });
+    double inv[NU];
+    bool good = m >= NU && cholesky<NU, double>(G, inv);
+    if (good) good = cond_estimate<NU, double>(G, inv) <= cfg.cond_fb;
+    if (!good) {
+        int slot = atomicAdd(&sc->n_fallback, 1);
+        queue[slot] = s;
+        return;
+    }
+    chol_solve<NU, 5, double, double>(G, inv, B);
+    const int nu = NU;
+    for (int f = 0; f < nf; ++f) {
+        for (int a = 0; a < D; ++a) deriv[((int64_t)f * nu + a) * n + i] = B[f * NU + a] * inv_r;
+        for (int q = 0; q < NS; ++q) deriv[((int64_t)f * nu + D + q) * n + i] = B[f * NU + D + q] * inv_r * inv_r;
+    }
+    status[i] = 0;
+}
+
+template <int D>
+__global__ __launch_bounds__(64) void k_gfd_fallback(Sorted srt, FieldPtrs fs, int nf, const int *nbr, int ldn,
+                                                     const int *count, int n, DevCfg cfg, DevScalars *sc,
+                                                     const int *queue, double *deriv, uint8_t *status) {
+    constexpr int NU = Dim<D>::NU, NS = Dim<D>::NS;
+    __shared__ int sel[64];
+    const int nq = sc->n_fallback;
+    for (int w = blockIdx.x; w < nq; w += gridDim.x) {
+        int s = queue[w];
+        int i = srt.id[s];
+        int k = count[s];
+        if (k > cfg.max_nb) k = cfg.max_nb;
+        double xi[3] = {srt.x[0][s], srt.x[1][s], D == 3 ? srt.x[2][s] : 0.0};
+        double fi[5];
+        for (int f = 0; f < 5; ++f) fi[f] = f < nf ? fs.f[f][s] : 0.0;
+        double grad[5][3], hess[5][NS];
+        int st = lw_fit_wave<D, 5>(srt, cfg, nbr, ldn, s, k, xi, srt.r[s], fi,
+                                   [&](int j, int f) { return f < nf ? fs.f[f][j] : 0.0; }, grad, hess, sel);
+        if ((threadIdx.x & 63) == 0) {
+            for (int f = 0; f < nf; ++f) {
+                for (int a = 0; a < D; ++a) deriv[((int64_t)f * NU + a) * n + i] = grad[f][a];
+                for (int q = 0; q < NS; ++q) deriv[((int64_t)f * NU + D + q) * n + i] = hess[f][q];
+            }
+            status[i] = (uint8_t)st;
+        }
+        __syncthreads();
+    }
+}
+
+void launch_gfd(const Sorted &s, const double *const *fs, int nf, const int *nbr, int ldn, const int *count, int n,
+                const DevCfg &cfg, DevScalars *sc, int *queue, double *deriv, uint8_t *status, hipStream_t st) {
+    FieldPtrs f{};
+    for (int q = 0; q < nf && q < 5; ++q) f.f[q] = fs[q];
+    unsigned blocks = (unsigned)((n + LP_BLOCK - 1) / LP_BLOCK);
+    if (blocks < 1) blocks = 1;
+    if (cfg.D == 3)
+        hipLaunchKernelGGL(k_gfd<3>, dim3(blocks), dim3(LP_BLOCK), 0, st, s, f, nf, nbr, ldn, count, n, cfg, sc, queue,
+                           deriv, status);
+    else
+        hipLaunchKernelGGL(k_gfd<2>, dim3(blocks), dim3(LP_BLOCK), 0, st, s, f, nf, nbr, ldn, count, n, cfg, sc, queue,
+                           deriv, status);
+    (void)hipGetLastError();
+}
+
+void launch_gfd_fallback(const Sorted &s, const double *const *fs, int nf, const int *nbr, int ldn, const int *count,
+                         int n, const DevCfg &cfg, DevScalars *sc, const int *queue, int queue_cap, double *deriv,
+                         uint8_t *status, hipStream_t st) {
+    FieldPtrs f{};
+    for (int q = 0; q < nf && q < 5; ++q) f.f[q] = fs[q];
+    unsigned blocks = queue_cap < 2048 ? (unsigned)(queue_cap > 0 ? queue_cap : 1) : 2048u;
+    if (cfg.D == 3)
+        hipLaunchKernelGGL(k_gfd_fallback<3>, dim3(blocks), dim3(64), 0, st, s, f, nf, nbr, ldn, count, n, cfg, sc,
+                           queue, deriv, status);
+    else
+        hipLaunchKernelGGL(k_gfd_fallback<2>, dim3(blocks), dim3(64), 0, st, s, f, nf, nbr, ldn, count, n, cfg, sc,
+                           queue, deriv, status);
+    (void)hipGetLastError();
+}

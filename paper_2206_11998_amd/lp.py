@@ -1,0 +1,260 @@
+"""Python binding of liblp (include/lp.h): argument marshalling only.
+
+Every step of the method runs in the HIP kernels of ``liblp.so``; this module
+passes device pointers of torch tensors and the current HIP stream.  It raises
+if the library has not been built -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblp.so")
+
+OK, E_ARG, E_CAPACITY, E_NUMERIC, E_DEVICE, E_NOMEM, E_STATE = range(7)
+FP64, MIXED = 0, 1
+EST_PLAIN, EST_INJECTED, EST_MLP = 0, 1, 2
+FLAG_LIMITED, FLAG_DEGENERATE, FLAG_VACUUM, FLAG_SUBSTITUTED, FLAG_FALLBACK, FLAG_NUMERIC = 1, 2, 4, 8, 16, 32
+
+EXPORTS = ["lp_config_default", "lp_create", "lp_destroy", "lp_neighbors", "lp_gfd", "lp_step", "lp_run",
+           "lp_conservation", "lp_check", "lp_get_info", "lp_set_time", "lp_status_str", "lp_last_error"]
+
+
+class LpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("liblp status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("precision", C.c_int32), ("estimator", C.c_int32), ("max_nb", C.c_int32),
+        ("lw_cap", C.c_int32), ("uw_cap", C.c_int32), ("refine", C.c_int32), ("vacuum", C.c_int32),
+        ("gamma", C.c_double), ("cfl", C.c_double), ("kappa", C.c_double), ("est_eps", C.c_double),
+        ("cond_max", C.c_double), ("uw_cond_max", C.c_double), ("cond_fallback", C.c_double),
+        ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
+        ("periodic_mask", C.c_uint32), ("wall_lo_mask", C.c_uint32), ("wall_hi_mask", C.c_uint32),
+        ("reserved", C.c_int32 * 9),
+    ]
+
+
+class Particles(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("x", C.c_void_p * 3), ("V", C.c_void_p), ("u", C.c_void_p * 3), ("P", C.c_void_p),
+        ("m", C.c_void_p), ("phi", C.c_void_p), ("flags", C.c_void_p),
+    ]
+
+
+class Info(C.Structure):
+    _fields_ = [
+        ("t", C.c_double), ("dt", C.c_double), ("n_ghost", C.c_int64), ("max_count", C.c_int32),
+        ("n_fallback", C.c_int32), ("n_limited", C.c_int64), ("error_bits", C.c_uint32), ("levels", C.c_int32 * 2),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load liblp.so (built by ``python -m paper_2206_11998_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("liblp.so is not built; run `python -m paper_2206_11998_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+        L.lp_config_default.restype = None
+        L.lp_config_default.argtypes = [C.POINTER(Config), i32]
+        L.lp_create.restype = i32
+        L.lp_create.argtypes = [C.POINTER(Config), C.POINTER(vp)]
+        L.lp_destroy.restype = i32
+        L.lp_destroy.argtypes = [vp]
+        L.lp_neighbors.restype = i32
+        L.lp_neighbors.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
+        L.lp_gfd.restype = i32
+        L.lp_gfd.argtypes = [vp, vp, i64, vp, vp, vp, vp, i32, C.POINTER(vp), vp, vp]
+        L.lp_step.restype = i32
+        L.lp_step.argtypes = [vp, vp, C.POINTER(Particles), dbl]
+        L.lp_run.restype = i32
+        L.lp_run.argtypes = [vp, vp, C.POINTER(Particles), i32, dbl]
+        L.lp_conservation.restype = i32
+        L.lp_conservation.argtypes = [vp, vp, C.POINTER(Particles), C.POINTER(C.c_double)]
+        L.lp_check.restype = i32
+        L.lp_check.argtypes = [vp, vp]
+        L.lp_get_info.restype = i32
+        L.lp_get_info.argtypes = [vp, vp, C.POINTER(Info)]
+        L.lp_set_time.restype = i32
+        L.lp_set_time.argtypes = [vp, vp, dbl]
+        L.lp_status_str.restype = C.c_char_p
+        L.lp_status_str.argtypes = [i32]
+        L.lp_last_error.restype = C.c_char_p
+        L.lp_last_error.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def make_config(cfg: dict, precision: str = "fp64", estimator: str = "plain", refine: bool = True) -> Config:
+    """lp_config from a workload config dict (see workloads.base_config)."""
+    c = Config()
+    d = int(cfg["dim"])
+    lib().lp_config_default(C.byref(c), d)
+    c.precision = {"fp64": FP64, "mixed": MIXED}[precision]
+    c.estimator = {"plain": EST_PLAIN, "injected": EST_INJECTED, "mlp": EST_MLP}[estimator]
+    c.refine = int(bool(refine))
+    c.max_nb = int(cfg.get("max_nb", 128))
+    c.lw_cap = int(cfg.get("lw_cap", 0))
+    c.uw_cap = int(cfg.get("uw_cap", 0))
+    c.vacuum = int(bool(cfg.get("vacuum", False)))
+    c.gamma = float(cfg.get("gamma", 1.4))
+    c.cfl = float(cfg.get("cfl", 0.5))
+    c.kappa = float(cfg["kappa"])
+    c.est_eps = float(cfg.get("est_eps", 1e-5))
+    c.cond_max = float(cfg.get("cond_max", 1e12))
+    c.uw_cond_max = float(cfg.get("uw_cond_max", 1e2))
+    c.cond_fallback = float(cfg.get("cond_fallback", 1e6))
+    for a in range(3):
+        c.box_lo[a] = float(cfg["box_lo"][a]) if a < d else 0.0
+        c.box_hi[a] = float(cfg["box_hi"][a]) if a < d else 1.0
+    c.periodic_mask = sum(1 << a for a in range(d) if cfg["periodic"][a])
+    c.wall_lo_mask = sum(1 << a for a in range(d) if cfg.get("wall_lo", [False] * d)[a])
+    c.wall_hi_mask = sum(1 << a for a in range(d) if cfg.get("wall_hi", [False] * d)[a])
+    return c
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def state_to_device(state: dict, device="cuda"):
+    """numpy workload state -> dict of contiguous torch tensors on the GPU (SoA)."""
+    import torch
+    d = state["x"].shape[1]
+    out = {
+        "x": [torch.from_numpy(np.ascontiguousarray(state["x"][:, a])).to(device) for a in range(d)],
+        "u": [torch.from_numpy(np.ascontiguousarray(state["u"][:, a])).to(device) for a in range(d)],
+        "V": torch.from_numpy(np.ascontiguousarray(state["V"])).to(device),
+        "P": torch.from_numpy(np.ascontiguousarray(state["P"])).to(device),
+        "m": torch.from_numpy(np.ascontiguousarray(state["m"])).to(device),
+    }
+    n = out["V"].shape[0]
+    out["phi"] = torch.zeros(n, dtype=torch.float32, device=device)
+    out["flags"] = torch.zeros(n, dtype=torch.uint8, device=device)
+    return out
+
+
+def state_to_host(st: dict) -> dict:
+    """Device state -> numpy dict in the workload layout."""
+    return {
+        "x": np.stack([t.cpu().numpy() for t in st["x"]], axis=1),
+        "u": np.stack([t.cpu().numpy() for t in st["u"]], axis=1),
+        "V": st["V"].cpu().numpy(), "P": st["P"].cpu().numpy(), "m": st["m"].cpu().numpy(),
+        "phi": st["phi"].cpu().numpy(), "flags": st["flags"].cpu().numpy(),
+    }
+
+
+class Context:
+    """One liblp context (one per stream)."""
+
+    def __init__(self, cfg: dict, precision="fp64", estimator="plain", refine=True):
+        self.cfg = cfg
+        self.dim = int(cfg["dim"])
+        self.max_nb = int(cfg.get("max_nb", 128))
+        self._c = make_config(cfg, precision, estimator, refine)
+        h = C.c_void_p()
+        st = lib().lp_create(C.byref(self._c), C.byref(h))
+        if st != OK:
+            raise LpError(st, "lp_create failed (see stderr)")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _raise(self, st):
+        if st != OK:
+            raise LpError(st, lib().lp_last_error(self._h).decode())
+
+    def _particles(self, s: dict) -> Particles:
+        p = Particles()
+        p.n = s["V"].shape[0]
+        for a in range(3):
+            p.x[a] = s["x"][a].data_ptr() if a < self.dim else None
+            p.u[a] = s["u"][a].data_ptr() if a < self.dim else None
+        p.V = s["V"].data_ptr()
+        p.P = s["P"].data_ptr()
+        p.m = s["m"].data_ptr()
+        p.phi = s["phi"].data_ptr() if s.get("phi") is not None else None
+        p.flags = s["flags"].data_ptr() if s.get("flags") is not None else None
+        self._keep = s
+        return p
+
+    def neighbors(self, x, r, stream=None):
+        """x: list of D float64 CUDA tensors; r: float64 CUDA tensor -> (count, idx[n, max_nb])."""
+        import torch
+        n = r.shape[0]
+        count = torch.empty(n, dtype=torch.int32, device=r.device)
+        idx = torch.full((n, self.max_nb), -1, dtype=torch.int32, device=r.device)
+        z = x[2] if self.dim == 3 else None
+        st = lib().lp_neighbors(self._h, _stream_ptr(stream), n, _ptr(x[0]), _ptr(x[1]), _ptr(z), _ptr(r),
+                                _ptr(count), _ptr(idx))
+        if st not in (OK, E_CAPACITY):
+            self._raise(st)
+        return count, idx, st
+
+    def gfd(self, x, r, fields, stream=None):
+        """Second-order GFD derivatives: deriv[f, c, i], status[i]."""
+        import torch
+        n = r.shape[0]
+        nu = 9 if self.dim == 3 else 5
+        nf = len(fields)
+        deriv = torch.zeros((nf, nu, n), dtype=torch.float64, device=r.device)
+        status = torch.zeros(n, dtype=torch.uint8, device=r.device)
+        fp = (C.c_void_p * nf)(*[f.data_ptr() for f in fields])
+        z = x[2] if self.dim == 3 else None
+        st = lib().lp_gfd(self._h, _stream_ptr(stream), n, _ptr(x[0]), _ptr(x[1]), _ptr(z), _ptr(r), nf, fp,
+                          _ptr(deriv), _ptr(status))
+        self._raise(st)
+        return deriv, status
+
+    def step(self, s: dict, dt: float = 0.0, stream=None):
+        p = self._particles(s)
+        self._raise(lib().lp_step(self._h, _stream_ptr(stream), C.byref(p), float(dt)))
+
+    def run(self, s: dict, nsteps: int, t_end: float = 0.0, stream=None):
+        p = self._particles(s)
+        self._raise(lib().lp_run(self._h, _stream_ptr(stream), C.byref(p), int(nsteps), float(t_end)))
+
+    def conservation(self, s: dict, stream=None):
+        p = self._particles(s)
+        out = (C.c_double * 5)()
+        self._raise(lib().lp_conservation(self._h, _stream_ptr(stream), C.byref(p), out))
+        return np.array(out[:])
+
+    def check(self, stream=None):
+        return lib().lp_check(self._h, _stream_ptr(stream))
+
+    def info(self, stream=None) -> dict:
+        inf = Info()
+        self._raise(lib().lp_get_info(self._h, _stream_ptr(stream), C.byref(inf)))
+        return {"t": inf.t, "dt": inf.dt, "n_ghost": inf.n_ghost, "max_count": inf.max_count,
+                "n_fallback": inf.n_fallback, "n_limited": inf.n_limited, "error_bits": inf.error_bits,
+                "levels": (inf.levels[0], inf.levels[1])}
+
+    def set_time(self, t: float, stream=None):
+        self._raise(lib().lp_set_time(self._h, _stream_ptr(stream), float(t)))
