@@ -1,0 +1,190 @@
+"""Throughput of the LP time step on one MI355X.
+
+Workload: the 3D expansion into vacuum -- 2,097,152 equal-mass particles
+rejection-sampled from rho = exp(-|x|^2/0.05) (spacing varies 8x), kappa 2.2,
+CFL 0.2, free boundary -- one time step = neighbour search + GFD fits + blended
+update + mover for every particle.  Prints one JSON line: particle-updates/s of
+the mixed-precision step (FP32 fits with one FP64-residual refinement, FP64
+state), the FP64 step next to it, the relative L1 error of both against the
+CPU reference on a sample of particles, the roofline of the dominant kernel
+(timed with HIP events on the library's stream) and the CPU reference's own
+throughput on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-updates/s at 2M particles, mixed vs FP64 step; L1 err vs oracle"
+PEAK_ALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FP64, and FP32 without packed math)
+PEAK_HBM_GBS = 8000.0
+
+
+def flops_per_particle(k_lw, dim=3):
+    """Algorithmic flops of one particle update at LW stencil size k_lw:
+    second-order fit 20k + 2kn^2 - 2n^3/3 + R(4kn - 2n^2) + Rn^2 (n unknowns,
+    R right-hand sides), half-ball fits and the rest (rates, estimator, mover)."""
+    if dim == 3:
+        n, R, uw, rest = 9, 5, 2800.0, 300.0
+    else:
+        n, R, uw, rest = 5, 4, 1200.0, 300.0
+    k = np.asarray(k_lw, dtype=np.float64)
+    return 20 * k + 2 * k * n * n - 2.0 * n ** 3 / 3 + R * (4 * k * n - 2 * n * n) + R * n * n + uw + rest
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=2_097_152)
+    ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sample", type=int, default=0, help="particles in the CPU-reference sample (0: all)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only (the multi-GPU split is described, not built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2206_11998_amd import lp, workloads as W
+
+    def log(*a):
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+    t0 = time.time()
+    cfg, st = W.vacuum3d(n_particles=args.n)
+    n = st["V"].shape[0]
+    log("workload generated: %d particles in %.1fs" % (n, time.time() - t0))
+    rng = np.random.default_rng(1234)
+    sample = (np.arange(n) if args.sample <= 0 or args.sample >= n
+              else np.sort(rng.choice(n, size=args.sample, replace=False)))
+
+    precisions = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
+    results = {}
+    first_step = {}
+    for prec in precisions:
+        ctx = lp.Context(cfg, precision=prec)
+        # one step from the initial state for the accuracy check
+        dev = lp.state_to_device(st)
+        ctx.step(dev)
+        if ctx.check() != lp.OK:
+            raise RuntimeError(lp.lib().lp_last_error(ctx._h).decode())
+        first_step[prec] = {k: (v[sample] if v.ndim == 1 else v[sample]) for k, v in lp.state_to_host(dev).items()}
+        dt0 = ctx.info()["dt"]
+        # timed run from the initial state
+        dev = lp.state_to_device(st)
+        ctx.set_time(0.0)
+        for _ in range(args.warmup):
+            ctx.step(dev)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.step(dev)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        status = ctx.check()
+        info = ctx.info()
+        log(prec, "steps %d in %.3fs -> %.3f ms/step; stages %s; info %s" % (
+            args.steps, elapsed, 1e3 * elapsed / args.steps,
+            {k: "%.3f ms" % (v[0] / max(v[1], 1)) for k, v in prof.items()}, info))
+        results[prec] = {"elapsed": elapsed, "prof": prof, "status": status, "info": info, "dt0": dt0}
+        del dev
+        ctx.close()
+
+    # LW stencil sizes for the algorithmic flop count (state at the start of the timed run)
+    ctx = lp.Context(cfg)
+    d = lp.state_to_device(st)
+    h = (st["m"] * st["V"]) ** (1.0 / 3.0)
+    r = torch.from_numpy(cfg["kappa"] * h).cuda()
+    count, _, _ = ctx.neighbors(d["x"], r)
+    cap = 54
+    k_lw = np.minimum(count.cpu().numpy(), cap)
+    flops_launch = float(flops_per_particle(k_lw).sum())
+    ctx.close()
+    del d
+
+    # CPU reference on the sample: one step of the same input
+    l1 = {}
+    cpu = None
+    try:
+        import oracle
+        t1 = time.perf_counter()
+        ref, rinfo = oracle.step_subset(cfg, st, sample)
+        cpu_time = time.perf_counter() - t1
+        threads = oracle.num_threads()
+        log("cpu reference: %d particles in %.2fs with %d threads (status %d)" % (
+            len(sample), cpu_time, threads, rinfo["status"]))
+        cpu = {"value": len(sample) / cpu_time, "unit": "particle-updates/s", "cores": threads, "kind": "oracle",
+               "sample": "one step of %d randomly chosen particles of the %d-particle workload (global dt and "
+                         "bucket grid over all particles included)" % (len(sample), n)}
+        cvmax = np.sqrt(cfg["gamma"] * st["P"] * st["V"]).max()
+        for prec, got in first_step.items():
+            e = {}
+            for key in ("V", "P", "u", "x"):
+                a, b = got[key], ref[key]
+                den = np.abs(b).sum()
+                if key == "u":
+                    den = max(den, b.size * 1e-12 * cvmax)
+                e[key] = float(np.abs(a - b).sum() / den)
+            l1[prec] = e
+        if args.no_cpu_baseline:
+            cpu = None
+    except Exception as exc:  # the reference is optional on hosts without gcc
+        log("cpu reference unavailable:", repr(exc))
+
+    main_prec = precisions[0]
+    res = results[main_prec]
+    ms_step = 1e3 * res["elapsed"] / args.steps
+    value = n * args.steps / res["elapsed"]
+    solve_ms, solve_cnt = res["prof"]["solve"]
+    solve_avg = solve_ms / max(solve_cnt, 1)
+    achieved = flops_launch / (solve_avg * 1e-3) / 1e12 if solve_avg > 0 else None
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if main_prec == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "vacuum3d: %d equal-mass particles rejection-sampled from rho=exp(-r^2/0.05) "
+                               "in the ball rho>=1/512, p=rho^1.4, kappa 2.2, CFL 0.2, free boundary" % n,
+                   "n_particles": n, "precision": main_prec},
+        "roofline": {"bound": "alu", "kernel": "k_solve (fused fit + update)", "achieved": achieved,
+                     "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_ALU_TFLOPS if achieved else None, "traffic": None,
+                     "algorithmic_flops_per_launch": flops_launch, "avg_launch_ms": solve_avg,
+                     "mean_lw_stencil": float(k_lw.mean())},
+        "cpu_baseline": cpu,
+        "stages_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in res["prof"].items()},
+        "l1_vs_oracle": l1,
+    }
+    for prec in precisions[1:]:
+        r2 = results[prec]
+        s2 = r2["prof"]["solve"]
+        avg2 = s2[0] / max(s2[1], 1)
+        out[prec] = {"value": n * args.steps / r2["elapsed"], "ms_per_step": 1e3 * r2["elapsed"] / args.steps,
+                     "solve_avg_ms": avg2,
+                     "solve_tflops": flops_launch / (avg2 * 1e-3) / 1e12 if avg2 > 0 else None,
+                     "stages_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in r2["prof"].items()}}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -165,6 +165,17 @@ lp_status lp_get_info(struct lp_ctx *ctx, void *stream, lp_info *out);
 /* Set the accumulated time (host value). */
 lp_status lp_set_time(struct lp_ctx *ctx, void *stream, double t);
 
+/* Kernel timing with HIP events recorded on the caller's stream around each
+ * stage of lp_step / lp_run.  lp_profile(ctx, 1) starts recording (and clears
+ * earlier records), lp_profile(ctx, 0) stops.  lp_profile_read synchronises
+ * and writes, per stage, the summed milliseconds ms[q] and the number of
+ * timed launches count[q] (host arrays of LP_NSTAGES entries), then clears.
+ * Stages: 0 radii/dt/ghosts, 1 cell ordering, 2 neighbour search,
+ * 3 fused solver (fast path), 4 FP64 pivoted-QR fallback. */
+#define LP_NSTAGES 5
+lp_status lp_profile(struct lp_ctx *ctx, int32_t enable);
+lp_status lp_profile_read(struct lp_ctx *ctx, void *stream, double *ms, int64_t *count);
+
 const char *lp_status_str(lp_status s);
 const char *lp_last_error(const struct lp_ctx *ctx);
 

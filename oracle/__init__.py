@@ -58,6 +58,8 @@ def lib():
         i64p = C.POINTER(C.c_int64)
         u8p = C.POINTER(C.c_uint8)
         cp = C.POINTER(Cfg)
+        L.lpo_num_threads.restype = C.c_int
+        L.lpo_num_threads.argtypes = []
         L.lpo_limiter.restype = C.c_double
         L.lpo_limiter.argtypes = [C.c_double]
         L.lpo_estimator_ratio.restype = C.c_double
@@ -137,6 +139,10 @@ def _xyz(x, d):
     x = np.ascontiguousarray(x, dtype=np.float64)
     cols = [np.ascontiguousarray(x[:, a]) for a in range(d)]
     return cols + [None] * (3 - d)
+
+
+def num_threads() -> int:
+    return lib().lpo_num_threads()
 
 
 def limiter(r: float) -> float:

@@ -32,6 +32,19 @@
 
 #include "lp_oracle.h"
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int lpo_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 #define ORC_MAXN 9      /* unknowns of the 3D second-order fit */
 #define ORC_MAXF 5      /* fields V, u1..uD, P */
 

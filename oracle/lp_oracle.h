@@ -36,6 +36,7 @@ typedef struct {
     int32_t vacuum;       /* free boundary: vacuum ghosts complete half-balls */
 } lpo_cfg;
 
+int lpo_num_threads(void);
 double lpo_limiter(double r);
 double lpo_estimator_ratio(double sl, double sr);
 double lpo_lstsq_qrp(int k, int n, int nrhs, double *A, double *B, double *X);

@@ -40,6 +40,12 @@ struct lp_ctx {
     bool run_done = false;
     DevGrid grid;
     int last_levels[2] = {0, 0};
+    // stage timing
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    struct Rec { int stage; hipEvent_t a, b; };
+    std::vector<Rec> recs;
     // lp_run graph
     hipGraphExec_t graph = nullptr;
     lp_particles graph_p;
@@ -76,6 +82,25 @@ static lp_status ensure(lp_ctx *c, Buf &b, size_t bytes) {
     }
     b.bytes = want;
     return LP_OK;
+}
+
+static hipEvent_t next_event(lp_ctx *c) {
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[c->ev_used++];
+}
+
+// Mark the start (begin = true) or end of a timed stage on stream st.
+static void stage_mark(lp_ctx *c, hipStream_t st, int stage, bool begin) {
+    if (!c->profiling) return;
+    hipEvent_t e = next_event(c);
+    if (!e) return;
+    (void)hipEventRecord(e, st);
+    if (begin) c->recs.push_back({stage, e, nullptr});
+    else if (!c->recs.empty()) c->recs.back().b = e;
 }
 
 #define ENSURE(ctx, buf, bytes)                        \
@@ -211,6 +236,7 @@ extern "C" lp_status lp_destroy(lp_ctx *c) {
     if (!c) return LP_E_ARG;
     (void)hipDeviceSynchronize();
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     Buf *bufs[] = {&c->h, &c->r, &c->gcnt, &c->scan_tmp, &c->ghosts, &c->key, &c->slot, &c->tables, &c->sorted,
                    &c->sortedf, &c->sid, &c->nbr, &c->count, &c->queue, &c->partials, &c->consout, &c->gfd_fields};
     for (Buf *b : bufs)
@@ -381,6 +407,7 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
         ENSURE(c, c->gcnt, sizeof(uint32_t) * (n + 1));
         ENSURE(c, c->scan_tmp, sizeof(uint32_t) * scan_tmp_words(n));
     }
+    stage_mark(c, st, 0, true);
     launch_reset_scalars(c->sc, dt_in, n, st);
     launch_prep(soa, c->dc, c->sc, (double *)c->h.p, (double *)c->r.p, st);
     launch_dt(c->dc, c->sc, clip_t_end, st);
@@ -390,6 +417,7 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
     }
     int64_t n_total;
     if (sync_levels) {
+        stage_mark(c, st, 0, false);
         HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
         if (clip_t_end && c->sc_host->done) {
@@ -404,6 +432,7 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
         n_total = c->cap_total;
     }
     Ghosts gh = ghost_view(c);
+    stage_mark(c, st, 1, true);
     if (c->nwalls)
         launch_ghost_write(soa, c->dc, c->sc, (const uint32_t *)c->gcnt.p, (const double *)c->h.p,
                            (const double *)c->r.p, gh, st);
@@ -440,13 +469,20 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
                        start, srt.id, st);
     }
     launch_coarsen((uint32_t *)c->tables.p, c->grid, D, &c->sc->n_total, st);
+    stage_mark(c, st, 1, false);
     int ldn = (int)c->cap_total;
+    stage_mark(c, st, 2, true);
     launch_search(srt, &c->sc->n_total, (int)n_total, n, (const uint32_t *)c->tables.p, c->grid, c->dc,
                   (int *)c->nbr.p, ldn, (int *)c->count.p, c->sc, c->search_group, st);
+    stage_mark(c, st, 2, false);
+    stage_mark(c, st, 3, true);
     launch_solve(srt, soa, (const int *)c->nbr.p, ldn, (const int *)c->count.p, &c->sc->n_total, (int)n_total, n,
                  c->dc, c->sc, (int *)c->queue.p, st);
+    stage_mark(c, st, 3, false);
+    stage_mark(c, st, 4, true);
     launch_solve_fallback(srt, soa, (const int *)c->nbr.p, ldn, (const int *)c->count.p, n, c->dc, c->sc,
                           (const int *)c->queue.p, n, st);
+    stage_mark(c, st, 4, false);
     launch_advance_time(c->sc, st);
     HIPCHK(c, hipGetLastError());
     return LP_OK;
@@ -635,5 +671,33 @@ extern "C" lp_status lp_set_time(lp_ctx *c, void *stream, double t) {
     c->sc_host->t = t;
     HIPCHK(c, hipMemcpyAsync(c->sc, c->sc_host, sizeof(DevScalars), hipMemcpyHostToDevice, st));
     HIPCHK(c, hipStreamSynchronize(st));
+    return LP_OK;
+}
+
+extern "C" lp_status lp_profile(lp_ctx *c, int32_t enable) {
+    if (!c) return LP_E_ARG;
+    c->profiling = enable != 0;
+    if (c->profiling) {
+        c->recs.clear();
+        c->ev_used = 0;
+    }
+    return LP_OK;
+}
+
+extern "C" lp_status lp_profile_read(lp_ctx *c, void *stream, double *ms, int64_t *count) {
+    if (!c || !ms || !count) return LP_E_ARG;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+    for (int q = 0; q < LP_NSTAGES; ++q) { ms[q] = 0.0; count[q] = 0; }
+    for (const auto &r : c->recs) {
+        if (!r.b || r.stage < 0 || r.stage >= LP_NSTAGES) continue;
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+            ms[r.stage] += t;
+            count[r.stage] += 1;
+        }
+    }
+    c->recs.clear();
+    c->ev_used = 0;
     return LP_OK;
 }

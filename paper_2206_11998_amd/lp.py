@@ -20,7 +20,9 @@ EST_PLAIN, EST_INJECTED, EST_MLP = 0, 1, 2
 FLAG_LIMITED, FLAG_DEGENERATE, FLAG_VACUUM, FLAG_SUBSTITUTED, FLAG_FALLBACK, FLAG_NUMERIC = 1, 2, 4, 8, 16, 32
 
 EXPORTS = ["lp_config_default", "lp_create", "lp_destroy", "lp_neighbors", "lp_gfd", "lp_step", "lp_run",
-           "lp_conservation", "lp_check", "lp_get_info", "lp_set_time", "lp_status_str", "lp_last_error"]
+           "lp_conservation", "lp_check", "lp_get_info", "lp_set_time", "lp_profile", "lp_profile_read",
+           "lp_status_str", "lp_last_error"]
+STAGES = ["prep", "cells", "search", "solve", "fallback"]
 
 
 class LpError(RuntimeError):
@@ -88,6 +90,10 @@ def lib():
         L.lp_get_info.argtypes = [vp, vp, C.POINTER(Info)]
         L.lp_set_time.restype = i32
         L.lp_set_time.argtypes = [vp, vp, dbl]
+        L.lp_profile.restype = i32
+        L.lp_profile.argtypes = [vp, i32]
+        L.lp_profile_read.restype = i32
+        L.lp_profile_read.argtypes = [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.lp_status_str.restype = C.c_char_p
         L.lp_status_str.argtypes = [i32]
         L.lp_last_error.restype = C.c_char_p
@@ -258,3 +264,13 @@ class Context:
 
     def set_time(self, t: float, stream=None):
         self._raise(lib().lp_set_time(self._h, _stream_ptr(stream), float(t)))
+
+    def profile(self, enable: bool):
+        self._raise(lib().lp_profile(self._h, int(bool(enable))))
+
+    def profile_read(self, stream=None) -> dict:
+        """Per-stage summed milliseconds and launch counts since profiling started."""
+        ms = (C.c_double * len(STAGES))()
+        cnt = (C.c_int64 * len(STAGES))()
+        self._raise(lib().lp_profile_read(self._h, _stream_ptr(stream), ms, cnt))
+        return {name: (ms[q], cnt[q]) for q, name in enumerate(STAGES)}

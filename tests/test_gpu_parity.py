@@ -140,13 +140,13 @@ def test_step_wave3d_fp64(lp, oracle_lib):
 
 
 def test_step_sod_slab_fp64(lp, oracle_lib):
-    cfg, st = W.sod3d(n=64, ny=6, nz=6)
+    cfg, st = W.sod3d(n=64, ny=8, nz=8)
     got, ref, info, ctx = _run_both(lp, oracle_lib, cfg, st, 12, "fp64", 1e-10, "sod slab")
     assert ctx.info()["n_ghost"] == info["n_ghost"]
 
 
 def test_step_sod_slab_mixed(lp, oracle_lib):
-    cfg, st = W.sod3d(n=64, ny=6, nz=6)
+    cfg, st = W.sod3d(n=64, ny=8, nz=8)
     _run_both(lp, oracle_lib, cfg, st, 12, "mixed", 1e-4, "sod slab")
 
 
