@@ -47,6 +47,8 @@ def main():
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sample", type=int, default=0, help="particles in the CPU-reference sample (0: all)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run 5 device copies of 1 GiB (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only (the multi-GPU split is described, not built)",
@@ -55,6 +57,15 @@ def main():
 
     import torch
     from paper_2206_11998_amd import lp, workloads as W
+
+    if args.copy_calibration:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8, "copies": 5}))
+        return
 
     def log(*a):
         print("[bench]", *a, file=sys.stderr, flush=True)
