@@ -29,7 +29,8 @@ struct lp_ctx {
     std::string err;
     // workspace
     Buf h, r, gcnt, scan_tmp, ghosts, key, slot, tables, sorted, sortedf, sid, nbr, count, queue, partials, consout,
-        gfd_fields;
+        gfd_fields, hitd2, hitj;
+    int search_mode = 1;            // 1: LDS-tiled search + row sort, 0: lane group per particle
     DevScalars *sc = nullptr;       // device scalars
     DevScalars *sc_host = nullptr;  // pinned copy
     int nwalls = 0;
@@ -238,7 +239,8 @@ extern "C" lp_status lp_destroy(lp_ctx *c) {
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     Buf *bufs[] = {&c->h, &c->r, &c->gcnt, &c->scan_tmp, &c->ghosts, &c->key, &c->slot, &c->tables, &c->sorted,
-                   &c->sortedf, &c->sid, &c->nbr, &c->count, &c->queue, &c->partials, &c->consout, &c->gfd_fields};
+                   &c->sortedf, &c->sid, &c->nbr, &c->count, &c->queue, &c->partials, &c->consout, &c->gfd_fields,
+                   &c->hitd2, &c->hitj};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->sc) (void)hipFree(c->sc);
@@ -324,7 +326,22 @@ static lp_status ensure_capacity(lp_ctx *c, int64_t n_real, int64_t n_total, boo
     ENSURE(c, c->nbr, sizeof(int) * (size_t)c->dc.max_nb * nt);
     ENSURE(c, c->count, sizeof(int) * nt);
     ENSURE(c, c->queue, sizeof(int) * nt);
+    if (c->search_mode == 1) {
+        ENSURE(c, c->hitd2, sizeof(double) * (size_t)c->dc.max_nb * nt);
+        ENSURE(c, c->hitj, sizeof(int) * (size_t)c->dc.max_nb * nt);
+    }
     return LP_OK;
+}
+
+static void run_search(lp_ctx *c, const Sorted &srt, int64_t n_total, int n_real, hipStream_t st) {
+    int ldn = (int)c->cap_total;
+    if (c->search_mode == 1)
+        launch_search_tiles(srt, &c->sc->n_total, (int)n_total, n_real, (const uint32_t *)c->tables.p, c->grid,
+                            c->dc, (double *)c->hitd2.p, (int *)c->hitj.p, (int *)c->nbr.p, ldn, (int *)c->count.p,
+                            c->sc, st);
+    else
+        launch_search(srt, &c->sc->n_total, (int)n_total, n_real, (const uint32_t *)c->tables.p, c->grid, c->dc,
+                      (int *)c->nbr.p, ldn, (int *)c->count.p, c->sc, c->search_group, st);
 }
 
 static Sorted sorted_view(lp_ctx *c, bool state) {
@@ -472,8 +489,7 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
     stage_mark(c, st, 1, false);
     int ldn = (int)c->cap_total;
     stage_mark(c, st, 2, true);
-    launch_search(srt, &c->sc->n_total, (int)n_total, n, (const uint32_t *)c->tables.p, c->grid, c->dc,
-                  (int *)c->nbr.p, ldn, (int *)c->count.p, c->sc, c->search_group, st);
+    run_search(c, srt, n_total, n, st);
     stage_mark(c, st, 2, false);
     stage_mark(c, st, 3, true);
     launch_solve(srt, soa, (const int *)c->nbr.p, ldn, (const int *)c->count.p, &c->sc->n_total, (int)n_total, n,
@@ -546,8 +562,7 @@ extern "C" lp_status lp_neighbors(lp_ctx *c, void *stream, int64_t n, const doub
                    srt.id, st);
     launch_coarsen((uint32_t *)c->tables.p, c->grid, D, &c->sc->n_total, st);
     int ldn = (int)c->cap_total;
-    launch_search(srt, &c->sc->n_total, (int)n, (int)n, (const uint32_t *)c->tables.p, c->grid, c->dc, (int *)c->nbr.p,
-                  ldn, (int *)c->count.p, c->sc, c->search_group, st);
+    run_search(c, srt, n, (int)n, st);
     launch_lists_out(srt.id, (const int *)c->nbr.p, ldn, (const int *)c->count.p, (int)n, c->dc.max_nb, count, idx, st);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
@@ -597,8 +612,7 @@ extern "C" lp_status lp_gfd(lp_ctx *c, void *stream, int64_t n, const double *x,
                    srt.id, st);
     launch_coarsen((uint32_t *)c->tables.p, c->grid, D, &c->sc->n_total, st);
     int ldn = (int)c->cap_total;
-    launch_search(srt, &c->sc->n_total, (int)n, (int)n, (const uint32_t *)c->tables.p, c->grid, c->dc, (int *)c->nbr.p,
-                  ldn, (int *)c->count.p, c->sc, c->search_group, st);
+    run_search(c, srt, n, (int)n, st);
     launch_gfd(srt, fs, nf, (const int *)c->nbr.p, ldn, (const int *)c->count.p, (int)n, c->dc, c->sc,
                (int *)c->queue.p, deriv, status, st);
     launch_gfd_fallback(srt, fs, nf, (const int *)c->nbr.p, ldn, (const int *)c->count.p, (int)n, c->dc, c->sc,

@@ -106,6 +106,9 @@ void launch_coarsen(uint32_t *tables, const DevGrid &g, int D, const int *n_tota
 void launch_search(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real, const uint32_t *tables,
                    const DevGrid &g, const DevCfg &cfg, int *nbr, int ldn, int *count, DevScalars *sc,
                    int group, hipStream_t st);
+void launch_search_tiles(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real,
+                         const uint32_t *tables, const DevGrid &g, const DevCfg &cfg, double *hit_d2, int *hit_j,
+                         int *nbr, int ldn, int *count, DevScalars *sc, hipStream_t st);
 void launch_lists_out(const int *sorted_id, const int *nbr, int ldn, const int *count, int n, int max_nb,
                       int *count_out, int *idx_out, hipStream_t st);
 void launch_solve(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count, const int *n_total_dev,
@@ -188,6 +191,18 @@ __device__ __forceinline__ int floor_clamped(double t) {
     if (!(t == t)) return 0;
     t = fmin(fmax(t, -16777216.0), 16777216.0);
     return (int)floor(t);
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs of the chip, each with its
+// own L2.  Mapping block b to work item w so that every XCD gets one
+// contiguous range of work keeps spatially adjacent (cell-ordered) particles
+// -- and the neighbour data they share -- in the same L2.  Bijective for any
+// block count.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int X = 8;
+    int q = nb / X, rem = nb % X;
+    int xcd = b % X, idx = b / X;
+    return xcd * q + (xcd < rem ? xcd : rem) + idx;
 }
 
 // Level used by a particle of radius r: the coarsest level whose cells are not

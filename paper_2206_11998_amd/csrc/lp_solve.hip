@@ -494,7 +494,7 @@ __global__ __launch_bounds__(LP_BLOCK) void k_solve(Sorted srt, Soa p, const int
                                                     int *queue) {
     constexpr int NU = Dim<D>::NU, NF = Dim<D>::NF, NG = Dim<D>::NG, NS = Dim<D>::NS, FP = D + 1;
     const bool use_f = sizeof(T) == 4;
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= *n_total_dev) return;
     int i = srt.id[s];
     if (i >= n_real) return;

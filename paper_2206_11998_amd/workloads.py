@@ -110,6 +110,17 @@ def sod3d(n=64, seed=1, jitter=0.2, ny=None, nz=None, t_end=0.1, smooth=1.0):
     return cfg, _state(x, rho, u, p, m)
 
 
+def morton_keys(x, lo, side, bits):
+    """Morton (Z-order) key of each point on a 2^bits grid over the cube [lo, lo + side)^D."""
+    d = x.shape[1]
+    c = np.clip(((x - lo) / side * (1 << bits)).astype(np.int64), 0, (1 << bits) - 1)
+    key = np.zeros(x.shape[0], dtype=np.int64)
+    for b in range(bits):
+        for a in range(d):
+            key |= ((c[:, a] >> b) & 1) << (d * b + a)
+    return key
+
+
 def vacuum_ball_radius(a=0.05, ratio=512.0):
     return math.sqrt(a * math.log(ratio))
 
@@ -129,6 +140,9 @@ def vacuum3d(n_particles=2_097_152, seed=2, a=0.05, steps=20, box=1.0):
         chunks.append(c)
         have += c.shape[0]
     x = np.concatenate(chunks, axis=0)[:n_particles]
+    # store the particles along a space-filling (Morton) curve, as an LP code
+    # keeps its particle array (paper, Sec. 2.2)
+    x = x[np.argsort(morton_keys(x, -R, 2.0 * R, 10), kind="stable")]
     r2 = (x * x).sum(axis=1)
     rho = np.exp(-r2 / a)
     z = R / math.sqrt(a)
