@@ -29,7 +29,7 @@ struct lp_ctx {
     std::string err;
     // workspace
     Buf h, r, gcnt, scan_tmp, ghosts, key, slot, tables, sorted, sortedf, sid, nbr, count, queue, partials, consout,
-        gfd_fields, hitd2, hitj;
+        gfd_fields, hitd2, hitj, tflags, tlo, thi;
     int search_mode = 1;            // 1: LDS-tiled search + row sort, 0: lane group per particle
     DevScalars *sc = nullptr;       // device scalars
     DevScalars *sc_host = nullptr;  // pinned copy
@@ -240,7 +240,7 @@ extern "C" lp_status lp_destroy(lp_ctx *c) {
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     Buf *bufs[] = {&c->h, &c->r, &c->gcnt, &c->scan_tmp, &c->ghosts, &c->key, &c->slot, &c->tables, &c->sorted,
                    &c->sortedf, &c->sid, &c->nbr, &c->count, &c->queue, &c->partials, &c->consout, &c->gfd_fields,
-                   &c->hitd2, &c->hitj};
+                   &c->hitd2, &c->hitj, &c->tflags, &c->tlo, &c->thi};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->sc) (void)hipFree(c->sc);
@@ -329,6 +329,11 @@ static lp_status ensure_capacity(lp_ctx *c, int64_t n_real, int64_t n_total, boo
     if (c->search_mode == 1) {
         ENSURE(c, c->hitd2, sizeof(double) * (size_t)c->dc.max_nb * nt);
         ENSURE(c, c->hitj, sizeof(int) * (size_t)c->dc.max_nb * nt);
+        ENSURE(c, c->tflags, sizeof(uint32_t) * (nt + 1));
+        ENSURE(c, c->tlo, sizeof(int) * nt);
+        ENSURE(c, c->thi, sizeof(int) * nt);
+        uint64_t sw2 = scan_tmp_words((uint64_t)nt);
+        if (sw2 > sw) ENSURE(c, c->scan_tmp, sizeof(uint32_t) * sw2);
     }
     return LP_OK;
 }
@@ -338,7 +343,8 @@ static void run_search(lp_ctx *c, const Sorted &srt, int64_t n_total, int n_real
     if (c->search_mode == 1)
         launch_search_tiles(srt, &c->sc->n_total, (int)n_total, n_real, (const uint32_t *)c->tables.p, c->grid,
                             c->dc, (double *)c->hitd2.p, (int *)c->hitj.p, (int *)c->nbr.p, ldn, (int *)c->count.p,
-                            c->sc, st);
+                            c->sc, (const uint32_t *)c->key.p, (uint32_t *)c->tflags.p, (uint32_t *)c->scan_tmp.p,
+                            (int *)c->tlo.p, (int *)c->thi.p, &c->sc->n_tiles, st);
     else
         launch_search(srt, &c->sc->n_total, (int)n_total, n_real, (const uint32_t *)c->tables.p, c->grid, c->dc,
                       (int *)c->nbr.p, ldn, (int *)c->count.p, c->sc, c->search_group, st);

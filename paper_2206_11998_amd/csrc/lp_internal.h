@@ -46,6 +46,7 @@ struct DevScalars {
     int n_fallback;
     unsigned int error_bits;        // 1: capacity, 2: numeric
     unsigned int done;              // lp_run: t reached t_end
+    int n_tiles;                    // search tiles of the last search
     unsigned long long n_limited;
 };
 
@@ -108,7 +109,8 @@ void launch_search(const Sorted &s, const int *n_total_dev, int n_total_cap, int
                    int group, hipStream_t st);
 void launch_search_tiles(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real,
                          const uint32_t *tables, const DevGrid &g, const DevCfg &cfg, double *hit_d2, int *hit_j,
-                         int *nbr, int ldn, int *count, DevScalars *sc, hipStream_t st);
+                         int *nbr, int ldn, int *count, DevScalars *sc, const uint32_t *key, uint32_t *flags,
+                         uint32_t *scan_tmp, int *tile_lo, int *tile_hi, int *ntiles_dev, hipStream_t st);
 void launch_lists_out(const int *sorted_id, const int *nbr, int ldn, const int *count, int n, int max_nb,
                       int *count_out, int *idx_out, hipStream_t st);
 void launch_solve(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count, const int *n_total_dev,

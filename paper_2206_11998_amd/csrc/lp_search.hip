@@ -159,10 +159,53 @@ void launch_search(const Sorted &s, const int *n_total_dev, int n_total_cap, int
 #define CHUNK 1536
 #define MAXRUN 1024
 
+// Adaptive tiles: the coarsest cell holding at most TILE particles (the
+// octree leaf of the paper's step 2), split into runs of TILE when the finest
+// level is still fuller.  Every particle that starts a tile is flagged.
+__global__ void k_tile_flags(Sorted srt, const int *n_total_dev, int cap, const uint32_t *key,
+                             const uint32_t *tables, DevGrid g, int D, uint32_t *flag) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int n = *n_total_dev;
+    if (s >= cap) return;
+    if (s >= n) { flag[s] = 0u; return; }
+    uint32_t k = key[srt.id[s]];
+    uint32_t cs = 0, ce = 0;
+    for (int L = g.L_lo; L <= g.L_hi; ++L) {
+        uint32_t code = k >> (D * (g.L_hi - L));
+        const uint32_t *tab = tables + g.off[L];
+        cs = tab[code];
+        ce = tab[code + 1];
+        if (ce - cs <= TILE) break;
+    }
+    flag[s] = ((uint32_t)s - cs) % TILE == 0 ? 1u : 0u;
+    (void)ce;
+}
+
+__global__ void k_tile_list(Sorted srt, const int *n_total_dev, const uint32_t *key, const uint32_t *tables,
+                            DevGrid g, int D, const uint32_t *off, int *tile_lo, int *tile_hi) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int n = *n_total_dev;
+    if (s >= n) return;
+    if (off[s + 1] == off[s]) return;  // not a tile head
+    uint32_t k = key[srt.id[s]];
+    uint32_t ce = 0;
+    for (int L = g.L_lo; L <= g.L_hi; ++L) {
+        uint32_t code = k >> (D * (g.L_hi - L));
+        const uint32_t *tab = tables + g.off[L];
+        uint32_t cs = tab[code];
+        ce = tab[code + 1];
+        if (ce - cs <= TILE) break;
+    }
+    uint32_t e = (uint32_t)s + TILE < ce ? (uint32_t)s + TILE : ce;
+    tile_lo[off[s]] = s;
+    tile_hi[off[s]] = (int)e;
+}
+
 template <int D>
 __global__ __launch_bounds__(TILE) void k_search_tile(Sorted srt, const int *n_total_dev, int n_real,
                                                      const uint32_t *tables, DevGrid g, DevCfg cfg, double *hit_d2,
-                                                     int *hit_j, int *count, DevScalars *sc, int nblocks) {
+                                                     int *hit_j, int *count, DevScalars *sc, const int *tile_lo,
+                                                     const int *tile_hi, const int *ntiles_dev) {
     __shared__ double cx[CHUNK], cy[CHUNK], cz[CHUNK];
     __shared__ int cj[CHUNK];
     __shared__ uint32_t run_b[MAXRUN];
@@ -171,11 +214,17 @@ __global__ __launch_bounds__(TILE) void k_search_tile(Sorted srt, const int *n_t
     __shared__ int geo[8];
 
     const int t = threadIdx.x;
-    const int chunk = xcd_remap(blockIdx.x, nblocks);
-    const int s = chunk * TILE + t;
-    const int n_total = *n_total_dev;
-    const bool valid = s < n_total && srt.id[s] < n_real;
+    const int ntiles = *ntiles_dev;
+    // each block walks a contiguous range of tiles; ranges are XCD-contiguous
+    const int nb = gridDim.x;
+    const int b = xcd_remap(blockIdx.x, nb);
+    const int per = (ntiles + nb - 1) / nb;
+    const int t_begin = b * per;
+    const int t_end = t_begin + per < ntiles ? t_begin + per : ntiles;
     const int max_nb = cfg.max_nb;
+    for (int tile = t_begin; tile < t_end; ++tile) {
+    const int s = tile_lo[tile] + t;
+    const bool valid = s < tile_hi[tile] && srt.id[s] < n_real;
     double xi[3] = {0.0, 0.0, 0.0}, ri = 0.0;
     if (valid) {
         xi[0] = srt.x[0][s];
@@ -208,7 +257,8 @@ __global__ __launch_bounds__(TILE) void k_search_tile(Sorted srt, const int *n_t
         for (int a = 0; a < 3; ++a) { blo[a] = m[a]; bhi[a] = -m[3 + a]; }
         rmax = -m[6];
     }
-    if (!(rmax > 0.0)) return;  // block without real particles (uniform exit)
+    __syncthreads();
+    if (!(rmax > 0.0)) continue;  // tile without real particles (uniform)
     // cell level: the finest whose cell count over the box stays within MAXRUN
     int L = level_for_radius(g, rmax);
     int clo[3] = {0, 0, 0}, cn[3] = {1, 1, 1};
@@ -334,6 +384,8 @@ __global__ __launch_bounds__(TILE) void k_search_tile(Sorted srt, const int *n_t
     int wmax = valid ? cnt : 0;
     for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o));
     if ((t & 63) == 0 && wmax > 0) atomicMax(&sc->max_count, wmax);
+    __syncthreads();
+    }
 }
 
 // Rank every row of hits by (d2, original id) in LDS; G lanes per row.
@@ -382,15 +434,22 @@ __global__ __launch_bounds__(LP_BLOCK) void k_sort_rows(Sorted srt, const int *n
 
 void launch_search_tiles(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real,
                          const uint32_t *tables, const DevGrid &g, const DevCfg &cfg, double *hit_d2, int *hit_j,
-                         int *nbr, int ldn, int *count, DevScalars *sc, hipStream_t st) {
-    int nb = (n_total_cap + TILE - 1) / TILE;
-    if (nb < 1) nb = 1;
+                         int *nbr, int ldn, int *count, DevScalars *sc, const uint32_t *key, uint32_t *flags,
+                         uint32_t *scan_tmp, int *tile_lo, int *tile_hi, int *ntiles_dev, hipStream_t st) {
+    unsigned nbp = (unsigned)((n_total_cap + LP_BLOCK - 1) / LP_BLOCK);
+    if (nbp < 1) nbp = 1;
+    hipLaunchKernelGGL(k_tile_flags, dim3(nbp), dim3(LP_BLOCK), 0, st, s, n_total_dev, n_total_cap, key, tables, g,
+                       cfg.D, flags);
+    launch_scan_u32(flags, (uint64_t)n_total_cap, scan_tmp, ntiles_dev, st);
+    hipLaunchKernelGGL(k_tile_list, dim3(nbp), dim3(LP_BLOCK), 0, st, s, n_total_dev, key, tables, g, cfg.D, flags,
+                       tile_lo, tile_hi);
+    int nb = 2048;
     if (cfg.D == 3)
         hipLaunchKernelGGL(k_search_tile<3>, dim3(nb), dim3(TILE), 0, st, s, n_total_dev, n_real, tables, g, cfg,
-                           hit_d2, hit_j, count, sc, nb);
+                           hit_d2, hit_j, count, sc, tile_lo, tile_hi, ntiles_dev);
     else
         hipLaunchKernelGGL(k_search_tile<2>, dim3(nb), dim3(TILE), 0, st, s, n_total_dev, n_real, tables, g, cfg,
-                           hit_d2, hit_j, count, sc, nb);
+                           hit_d2, hit_j, count, sc, tile_lo, tile_hi, ntiles_dev);
     int G = 8;
     while ((size_t)(LP_BLOCK / G) * cfg.max_nb * 16 > 65536 && G < 64) G *= 2;
     int ppb = LP_BLOCK / G;
