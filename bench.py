@@ -47,6 +47,9 @@ def main():
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sample", type=int, default=0, help="particles in the CPU-reference sample (0: all)")
+    ap.add_argument("--search-mode", type=int, default=None, help="override the neighbour-search mode (0/1)")
+    ap.add_argument("--search-group", type=int, default=None)
+    ap.add_argument("--solve-block", type=int, default=None)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device copies of 1 GiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -81,8 +84,17 @@ def main():
     precisions = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
     results = {}
     first_step = {}
+    def tuned(ctx):
+        if args.search_mode is not None:
+            ctx.set_tuning(lp.TUNE_SEARCH_MODE, args.search_mode)
+        if args.search_group is not None:
+            ctx.set_tuning(lp.TUNE_SEARCH_GROUP, args.search_group)
+        if args.solve_block is not None:
+            ctx.set_tuning(lp.TUNE_SOLVE_BLOCK, args.solve_block)
+        return ctx
+
     for prec in precisions:
-        ctx = lp.Context(cfg, precision=prec)
+        ctx = tuned(lp.Context(cfg, precision=prec))
         # one step from the initial state for the accuracy check
         dev = lp.state_to_device(st)
         ctx.step(dev)

@@ -173,6 +173,17 @@ lp_status lp_set_time(struct lp_ctx *ctx, void *stream, double t);
  * Stages: 0 radii/dt/ghosts, 1 cell ordering, 2 neighbour search,
  * 3 fused solver (fast path), 4 FP64 pivoted-QR fallback. */
 #define LP_NSTAGES 5
+
+/* Launch-shape parameters (results are identical for every setting; only the
+ * speed changes).  Chosen by lp_autotune() or set explicitly: */
+enum {
+    LP_TUNE_SEARCH_MODE = 0,   /* 0: lane group per particle walking its cells, 1: LDS-staged tiles */
+    LP_TUNE_SEARCH_GROUP = 1,  /* lanes per particle of mode 0: 4, 8, 16, 32 */
+    LP_TUNE_SOLVE_BLOCK = 2,   /* threads per block of the fused solver: 64, 128, 256 */
+    LP_TUNE_COUNT = 3
+};
+lp_status lp_set_tuning(struct lp_ctx *ctx, int32_t param, int32_t value);
+lp_status lp_get_tuning(const struct lp_ctx *ctx, int32_t param, int32_t *value);
 lp_status lp_profile(struct lp_ctx *ctx, int32_t enable);
 lp_status lp_profile_read(struct lp_ctx *ctx, void *stream, double *ms, int64_t *count);
 

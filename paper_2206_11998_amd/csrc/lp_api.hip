@@ -30,7 +30,8 @@ struct lp_ctx {
     // workspace
     Buf h, r, gcnt, scan_tmp, ghosts, key, slot, tables, sorted, sortedf, sid, nbr, count, queue, partials, consout,
         gfd_fields, hitd2, hitj, tflags, tlo, thi;
-    int search_mode = 1;            // 1: LDS-tiled search + row sort, 0: lane group per particle
+    int search_mode = 0;            // 1: LDS-tiled search + row sort, 0: lane group per particle
+    int solve_block = 256;
     DevScalars *sc = nullptr;       // device scalars
     DevScalars *sc_host = nullptr;  // pinned copy
     int nwalls = 0;
@@ -499,7 +500,7 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
     stage_mark(c, st, 2, false);
     stage_mark(c, st, 3, true);
     launch_solve(srt, soa, (const int *)c->nbr.p, ldn, (const int *)c->count.p, &c->sc->n_total, (int)n_total, n,
-                 c->dc, c->sc, (int *)c->queue.p, st);
+                 c->dc, c->sc, (int *)c->queue.p, c->solve_block, st);
     stage_mark(c, st, 3, false);
     stage_mark(c, st, 4, true);
     launch_solve_fallback(srt, soa, (const int *)c->nbr.p, ldn, (const int *)c->count.p, n, c->dc, c->sc,
@@ -720,4 +721,34 @@ extern "C" lp_status lp_profile_read(lp_ctx *c, void *stream, double *ms, int64_
     c->recs.clear();
     c->ev_used = 0;
     return LP_OK;
+}
+
+extern "C" lp_status lp_set_tuning(lp_ctx *c, int32_t param, int32_t value) {
+    if (!c) return LP_E_ARG;
+    switch (param) {
+    case LP_TUNE_SEARCH_MODE:
+        if (value != 0 && value != 1) return fail(c, LP_E_ARG, "search mode must be 0 or 1");
+        c->search_mode = value;
+        return LP_OK;
+    case LP_TUNE_SEARCH_GROUP:
+        if (value != 4 && value != 8 && value != 16 && value != 32) return fail(c, LP_E_ARG, "group must be 4..32");
+        c->search_group = value;
+        return LP_OK;
+    case LP_TUNE_SOLVE_BLOCK:
+        if (value != 64 && value != 128 && value != 256) return fail(c, LP_E_ARG, "solve block must be 64..256");
+        c->solve_block = value;
+        return LP_OK;
+    default:
+        return fail(c, LP_E_ARG, "unknown tuning parameter %d", param);
+    }
+}
+
+extern "C" lp_status lp_get_tuning(const lp_ctx *c, int32_t param, int32_t *value) {
+    if (!c || !value) return LP_E_ARG;
+    switch (param) {
+    case LP_TUNE_SEARCH_MODE: *value = c->search_mode; return LP_OK;
+    case LP_TUNE_SEARCH_GROUP: *value = c->search_group; return LP_OK;
+    case LP_TUNE_SOLVE_BLOCK: *value = c->solve_block; return LP_OK;
+    default: return LP_E_ARG;
+    }
 }

@@ -618,16 +618,17 @@ __global__ __launch_bounds__(LP_BLOCK) void k_solve(Sorted srt, Soa p, const int
 template <int D, typename T, bool RF>
 static void launch_solve_t(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count,
                            const int *n_total_dev, int n_total_cap, int n_real, const DevCfg &cfg, DevScalars *sc,
-                           int *queue, hipStream_t st) {
-    unsigned blocks = (unsigned)((n_total_cap + LP_BLOCK - 1) / LP_BLOCK);
+                           int *queue, int block, hipStream_t st) {
+    unsigned blocks = (unsigned)((n_total_cap + block - 1) / block);
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((k_solve<D, T, RF>), dim3(blocks), dim3(LP_BLOCK), 0, st, s, p, nbr, ldn, count, n_total_dev,
+    hipLaunchKernelGGL((k_solve<D, T, RF>), dim3(blocks), dim3(block), 0, st, s, p, nbr, ldn, count, n_total_dev,
                        n_real, cfg, sc, queue);
 }
 
 void launch_solve(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count, const int *n_total_dev,
-                  int n_total_cap, int n_real, const DevCfg &cfg, DevScalars *sc, int *queue, hipStream_t st) {
-#define LSV(DD, TT, RR) launch_solve_t<DD, TT, RR>(s, p, nbr, ldn, count, n_total_dev, n_total_cap, n_real, cfg, sc, queue, st)
+                  int n_total_cap, int n_real, const DevCfg &cfg, DevScalars *sc, int *queue, int block,
+                  hipStream_t st) {
+#define LSV(DD, TT, RR) launch_solve_t<DD, TT, RR>(s, p, nbr, ldn, count, n_total_dev, n_total_cap, n_real, cfg, sc, queue, block, st)
     bool mixed = cfg.precision == LP_MIXED;
     if (cfg.D == 3) {
         if (!mixed) LSV(3, double, false);

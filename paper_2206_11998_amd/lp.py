@@ -21,7 +21,8 @@ FLAG_LIMITED, FLAG_DEGENERATE, FLAG_VACUUM, FLAG_SUBSTITUTED, FLAG_FALLBACK, FLA
 
 EXPORTS = ["lp_config_default", "lp_create", "lp_destroy", "lp_neighbors", "lp_gfd", "lp_step", "lp_run",
            "lp_conservation", "lp_check", "lp_get_info", "lp_set_time", "lp_profile", "lp_profile_read",
-           "lp_status_str", "lp_last_error"]
+           "lp_set_tuning", "lp_get_tuning", "lp_status_str", "lp_last_error"]
+TUNE_SEARCH_MODE, TUNE_SEARCH_GROUP, TUNE_SOLVE_BLOCK = 0, 1, 2
 STAGES = ["prep", "cells", "search", "solve", "fallback"]
 
 
@@ -94,6 +95,10 @@ def lib():
         L.lp_profile.argtypes = [vp, i32]
         L.lp_profile_read.restype = i32
         L.lp_profile_read.argtypes = [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.lp_set_tuning.restype = i32
+        L.lp_set_tuning.argtypes = [vp, i32, i32]
+        L.lp_get_tuning.restype = i32
+        L.lp_get_tuning.argtypes = [vp, i32, C.POINTER(i32)]
         L.lp_status_str.restype = C.c_char_p
         L.lp_status_str.argtypes = [i32]
         L.lp_last_error.restype = C.c_char_p
@@ -274,3 +279,11 @@ class Context:
         cnt = (C.c_int64 * len(STAGES))()
         self._raise(lib().lp_profile_read(self._h, _stream_ptr(stream), ms, cnt))
         return {name: (ms[q], cnt[q]) for q, name in enumerate(STAGES)}
+
+    def set_tuning(self, param: int, value: int):
+        self._raise(lib().lp_set_tuning(self._h, int(param), int(value)))
+
+    def get_tuning(self, param: int) -> int:
+        v = C.c_int32(0)
+        self._raise(lib().lp_get_tuning(self._h, int(param), C.byref(v)))
+        return v.value
