@@ -339,6 +339,9 @@ static lp_status ensure_capacity(lp_ctx *c, int64_t n_real, int64_t n_total, boo
     return LP_OK;
 }
 
+// list stride convention of nb_at(): > 0 column-major, < 0 row-major
+static int list_ldn(const lp_ctx *c) { return c->search_mode == 1 ? -c->dc.max_nb : (int)c->cap_total; }
+
 static void run_search(lp_ctx *c, const Sorted &srt, int64_t n_total, int n_real, hipStream_t st) {
     int ldn = (int)c->cap_total;
     if (c->search_mode == 1)
@@ -494,7 +497,7 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
     }
     launch_coarsen((uint32_t *)c->tables.p, c->grid, D, &c->sc->n_total, st);
     stage_mark(c, st, 1, false);
-    int ldn = (int)c->cap_total;
+    int ldn = list_ldn(c);
     stage_mark(c, st, 2, true);
     run_search(c, srt, n_total, n, st);
     stage_mark(c, st, 2, false);
@@ -568,7 +571,7 @@ extern "C" lp_status lp_neighbors(lp_ctx *c, void *stream, int64_t n, const doub
     launch_scatter(sa, (int)n, &c->sc->n_total, (int)n, (const uint32_t *)c->key.p, (const uint32_t *)c->slot.p, start,
                    srt.id, st);
     launch_coarsen((uint32_t *)c->tables.p, c->grid, D, &c->sc->n_total, st);
-    int ldn = (int)c->cap_total;
+    int ldn = list_ldn(c);
     run_search(c, srt, n, (int)n, st);
     launch_lists_out(srt.id, (const int *)c->nbr.p, ldn, (const int *)c->count.p, (int)n, c->dc.max_nb, count, idx, st);
     HIPCHK(c, hipGetLastError());
@@ -618,7 +621,7 @@ extern "C" lp_status lp_gfd(lp_ctx *c, void *stream, int64_t n, const double *x,
     launch_scatter(sa, (int)n, &c->sc->n_total, (int)n, (const uint32_t *)c->key.p, (const uint32_t *)c->slot.p, start,
                    srt.id, st);
     launch_coarsen((uint32_t *)c->tables.p, c->grid, D, &c->sc->n_total, st);
-    int ldn = (int)c->cap_total;
+    int ldn = list_ldn(c);
     run_search(c, srt, n, (int)n, st);
     launch_gfd(srt, fs, nf, (const int *)c->nbr.p, ldn, (const int *)c->count.p, (int)n, c->dc, c->sc,
                (int *)c->queue.p, deriv, status, st);

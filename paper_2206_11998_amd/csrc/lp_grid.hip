@@ -402,7 +402,7 @@ __global__ void k_lists_out(const int *sorted_id, const int *nbr, int ldn, const
     int k = count[s];
     count_out[i] = k;
     int kk = k < max_nb ? k : max_nb;
-    for (int c = 0; c < kk; ++c) idx_out[(int64_t)i * max_nb + c] = sorted_id[nbr[(int64_t)c * ldn + s]];
+    for (int c = 0; c < kk; ++c) idx_out[(int64_t)i * max_nb + c] = sorted_id[nb_at(nbr, ldn, s, c)];
 }
 
 void launch_lists_out(const int *sorted_id, const int *nbr, int ldn, const int *count, int n, int max_nb,

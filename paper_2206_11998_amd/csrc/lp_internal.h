@@ -208,6 +208,12 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return xcd * q + (xcd < rem ? xcd : rem) + idx;
 }
 
+// Neighbour-list element c of cell-order particle s.  ldn > 0: column-major
+// lists nbr[c * ldn + s]; ldn < 0: row-major lists nbr[s * (-ldn) + c].
+__device__ __forceinline__ int nb_at(const int *nbr, int ldn, int s, int c) {
+    return ldn > 0 ? nbr[(int64_t)c * ldn + s] : nbr[(int64_t)s * (-ldn) + c];
+}
+
 // Level used by a particle of radius r: the coarsest level whose cells are not
 // larger than r (so the search box spans 2-5 cells per axis), clamped.
 __device__ __forceinline__ int level_for_radius(const DevGrid &g, double r) {

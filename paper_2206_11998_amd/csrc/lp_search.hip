@@ -147,13 +147,9 @@ void launch_search(const Sorted &s, const int *n_total_dev, int n_total_cap, int
 }
 
 // ===========================================================================
-// Tiled search: a block takes 256 consecutive particles of the cell order (a
-// compact piece of the space-filling curve), finds the cells that cover the
-// union of their search balls, and streams the particles of those cells
-// through LDS in chunks.  Every thread tests its own particle against every
-// staged candidate -- LDS broadcast reads, no per-particle table lookups --
-// and appends hits (d2, j) to its row in a scratch list.  A second kernel
-// ranks each row by (d2, id) in LDS and writes the final list.
+// Tiled search: a block takes one tile -- the coarsest cell holding at most
+// 256 particles -- finds the cells that cover the union of its particles'
+// search balls, and streams the particles of those cells through LDS.
 // ===========================================================================
 #define TILE 256
 #define CHUNK 1536
@@ -201,21 +197,38 @@ __global__ void k_tile_list(Sorted srt, const int *n_total_dev, const uint32_t *
     tile_hi[off[s]] = (int)e;
 }
 
+// ===========================================================================
+// Wave per particle: the tile's halo is staged in LDS;
+// each wave then takes one particle at a time and its 64 lanes test 64 staged
+// candidates at once.  Hits are compacted with a ballot and appended to the
+// particle's row (contiguous, coalesced stores).  After the last chunk the same
+// wave reads each row back (L2-hot), ranks it by (d2, id) in LDS and writes the
+// final row.  Output layout: row-major nbr[s * max_nb + c].
+// ===========================================================================
+#define CHUNK2 1024
+#define SORTCAP 256
+
 template <int D>
-__global__ __launch_bounds__(TILE) void k_search_tile(Sorted srt, const int *n_total_dev, int n_real,
-                                                     const uint32_t *tables, DevGrid g, DevCfg cfg, double *hit_d2,
-                                                     int *hit_j, int *count, DevScalars *sc, const int *tile_lo,
-                                                     const int *tile_hi, const int *ntiles_dev) {
-    __shared__ double cx[CHUNK], cy[CHUNK], cz[CHUNK];
-    __shared__ int cj[CHUNK];
+__global__ __launch_bounds__(TILE) void k_search_tile2(Sorted srt, const int *n_total_dev, int n_real,
+                                                      const uint32_t *tables, DevGrid g, DevCfg cfg, double *hit_d2,
+                                                      int *hit_j, int *nbr, int *count, DevScalars *sc,
+                                                      const int *tile_lo, const int *tile_hi, const int *ntiles_dev) {
+    __shared__ double cx[CHUNK2], cy[CHUNK2], cz[CHUNK2];
+    __shared__ int cj[CHUNK2];
     __shared__ uint32_t run_b[MAXRUN];
     __shared__ uint32_t run_p[MAXRUN + 1];
     __shared__ double red[7][TILE / 64];
-    __shared__ int geo[8];
+    __shared__ int geo[2];
+    __shared__ uint32_t wsum[TILE / 64];
+    __shared__ int pcnt[TILE];
+    __shared__ double sd2[TILE / 64][SORTCAP];
+    __shared__ int sid[TILE / 64][SORTCAP];
+    __shared__ int sjj[TILE / 64][SORTCAP];
 
     const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const unsigned long long lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const int ntiles = *ntiles_dev;
-    // each block walks a contiguous range of tiles; ranges are XCD-contiguous
     const int nb = gridDim.x;
     const int b = xcd_remap(blockIdx.x, nb);
     const int per = (ntiles + nb - 1) / nb;
@@ -223,212 +236,203 @@ __global__ __launch_bounds__(TILE) void k_search_tile(Sorted srt, const int *n_t
     const int t_end = t_begin + per < ntiles ? t_begin + per : ntiles;
     const int max_nb = cfg.max_nb;
     for (int tile = t_begin; tile < t_end; ++tile) {
-    const int s = tile_lo[tile] + t;
-    const bool valid = s < tile_hi[tile] && srt.id[s] < n_real;
-    double xi[3] = {0.0, 0.0, 0.0}, ri = 0.0;
-    if (valid) {
-        xi[0] = srt.x[0][s];
-        xi[1] = srt.x[1][s];
-        if (D == 3) xi[2] = srt.x[2][s];
-        ri = srt.r[s];
-    }
-    // union of the search balls (per-axis box) and the largest radius
-    double v[7];
-    for (int a = 0; a < 3; ++a) {
-        v[a] = valid ? xi[a] - ri : INFINITY;
-        v[3 + a] = valid ? -(xi[a] + ri) : INFINITY;
-    }
-    v[6] = valid ? -ri : INFINITY;
-    for (int q = 0; q < 7; ++q) {
-        double w = v[q];
-        for (int o = 32; o > 0; o >>= 1) w = fmin(w, __shfl_xor(w, o));
-        v[q] = w;
-    }
-    if ((t & 63) == 0)
-        for (int q = 0; q < 7; ++q) red[q][t >> 6] = v[q];
-    __syncthreads();
-    double blo[3], bhi[3], rmax;
-    {
-        double m[7];
+        const int s0 = tile_lo[tile];
+        const int np = tile_hi[tile] - s0;
+        const int s = s0 + t;
+        const bool valid = t < np && srt.id[s] < n_real;
+        double ri = 0.0, xi[3] = {0.0, 0.0, 0.0};
+        if (valid) {
+            xi[0] = srt.x[0][s];
+            xi[1] = srt.x[1][s];
+            if (D == 3) xi[2] = srt.x[2][s];
+            ri = srt.r[s];
+        }
+        pcnt[t] = 0;
+        double v[7];
+        for (int a = 0; a < 3; ++a) {
+            v[a] = valid ? xi[a] - ri : INFINITY;
+            v[3 + a] = valid ? -(xi[a] + ri) : INFINITY;
+        }
+        v[6] = valid ? -ri : INFINITY;
         for (int q = 0; q < 7; ++q) {
-            m[q] = red[q][0];
-            for (int w = 1; w < TILE / 64; ++w) m[q] = fmin(m[q], red[q][w]);
+            double w = v[q];
+            for (int o = 32; o > 0; o >>= 1) w = fmin(w, __shfl_xor(w, o));
+            v[q] = w;
         }
-        for (int a = 0; a < 3; ++a) { blo[a] = m[a]; bhi[a] = -m[3 + a]; }
-        rmax = -m[6];
-    }
-    __syncthreads();
-    if (!(rmax > 0.0)) continue;  // tile without real particles (uniform)
-    // cell level: the finest whose cell count over the box stays within MAXRUN
-    int L = level_for_radius(g, rmax);
-    int clo[3] = {0, 0, 0}, cn[3] = {1, 1, 1};
-    for (;;) {
-        long long tot = 1;
-        for (int a = 0; a < D; ++a) {
-            int n = g.nc[L][a];
-            int lo = floor_clamped((blo[a] - g.lo[a]) * g.inv_s[L] - 1e-9);
-            int hi = floor_clamped((bhi[a] - g.lo[a]) * g.inv_s[L] + 1e-9);
-            if (cfg.periodic[a]) {
-                if (hi - lo + 1 >= n || hi < lo) { lo = 0; hi = n - 1; }
-            } else {
-                lo = lo < 0 ? 0 : (lo > n - 1 ? n - 1 : lo);
-                hi = hi > n - 1 ? n - 1 : (hi < 0 ? 0 : hi);
-            }
-            clo[a] = lo;
-            cn[a] = hi - lo + 1;
-            tot *= cn[a];
-        }
-        if (tot <= MAXRUN || L == g.L_lo) break;
-        --L;
-    }
-    const int ncells = cn[0] * cn[1] * (D == 3 ? cn[2] : 1);
-    const uint32_t *tab = tables + g.off[L];
-    const double r2 = ri * ri;
-    int cnt = 0;
-    double *myd2 = hit_d2 + (int64_t)s * max_nb;
-    int *myj = hit_j + (int64_t)s * max_nb;
-    __shared__ uint32_t wsum[TILE / 64];
-    // covering cells in batches of MAXRUN: runs of particles, prefix sums,
-    // then the candidates of the batch streamed through LDS
-    for (int cb = 0; cb < ncells; cb += MAXRUN) {
-        const int nrun = ncells - cb < MAXRUN ? ncells - cb : MAXRUN;
-        uint32_t mylen[MAXRUN / TILE];
-        uint32_t mysum = 0;
-        for (int k = 0; k < MAXRUN / TILE; ++k) {
-            int q = t * (MAXRUN / TILE) + k;
-            uint32_t len = 0;
-            if (q < nrun) {
-                int qq = cb + q;
-                int cc[3];
-                cc[0] = clo[0] + qq % cn[0];
-                cc[1] = clo[1] + (qq / cn[0]) % cn[1];
-                cc[2] = D == 3 ? clo[2] + qq / (cn[0] * cn[1]) : 0;
-                for (int a = 0; a < D; ++a)
-                    if (cfg.periodic[a]) {
-                        int n = g.nc[L][a];
-                        cc[a] = ((cc[a] % n) + n) % n;
-                    }
-                uint32_t code = morton<D>(cc);
-                uint32_t b = tab[code], e = tab[code + 1];
-                run_b[q] = b;
-                len = e - b;
-            }
-            mylen[k] = len;
-            mysum += len;
-        }
+        if (lane == 0)
+            for (int q = 0; q < 7; ++q) red[q][wave] = v[q];
+        __syncthreads();
+        double blo[3], bhi[3], rmax;
         {
-            uint32_t inc = mysum;
-            int lane = t & 63;
-            for (int o = 1; o < 64; o <<= 1) {
-                uint32_t y = __shfl_up(inc, o);
-                if (lane >= o) inc += y;
+            double m[7];
+            for (int q = 0; q < 7; ++q) {
+                m[q] = red[q][0];
+                for (int w = 1; w < TILE / 64; ++w) m[q] = fmin(m[q], red[q][w]);
             }
-            if (lane == 63) wsum[t >> 6] = inc;
-            __syncthreads();
-            uint32_t off = 0, tot = 0;
-            for (int w = 0; w < TILE / 64; ++w) {
-                if (w < (t >> 6)) off += wsum[w];
-                tot += wsum[w];
-            }
-            uint32_t run = off + inc - mysum;
-            for (int k = 0; k < MAXRUN / TILE; ++k) {
-                int q = t * (MAXRUN / TILE) + k;
-                run_p[q] = run;
-                run += mylen[k];
-            }
-            if (t == 0) { run_p[MAXRUN] = tot; geo[0] = (int)tot; }
+            for (int a = 0; a < 3; ++a) { blo[a] = m[a]; bhi[a] = -m[3 + a]; }
+            rmax = -m[6];
         }
         __syncthreads();
-        const int H = geo[0];
-        for (int base = 0; base < H; base += CHUNK) {
-            int m = H - base < CHUNK ? H - base : CHUNK;
-            for (int k = t; k < m; k += TILE) {
-                uint32_t gk = (uint32_t)(base + k);
-                // run containing gk: the last q with run_p[q] <= gk
-                int lo = 0, hi = nrun - 1;
-                while (lo < hi) {
-                    int mid = (lo + hi + 1) >> 1;
-                    if (run_p[mid] <= gk) lo = mid; else hi = mid - 1;
+        if (!(rmax > 0.0)) continue;  // uniform
+        int L = level_for_radius(g, rmax);
+        int clo[3] = {0, 0, 0}, cn[3] = {1, 1, 1};
+        for (;;) {
+            long long tot = 1;
+            for (int a = 0; a < D; ++a) {
+                int n = g.nc[L][a];
+                int lo = floor_clamped((blo[a] - g.lo[a]) * g.inv_s[L] - 1e-9);
+                int hi = floor_clamped((bhi[a] - g.lo[a]) * g.inv_s[L] + 1e-9);
+                if (cfg.periodic[a]) {
+                    if (hi - lo + 1 >= n || hi < lo) { lo = 0; hi = n - 1; }
+                } else {
+                    lo = lo < 0 ? 0 : (lo > n - 1 ? n - 1 : lo);
+                    hi = hi > n - 1 ? n - 1 : (hi < 0 ? 0 : hi);
                 }
-                int j = (int)(run_b[lo] + (gk - run_p[lo]));
-                cx[k] = srt.x[0][j];
-                cy[k] = srt.x[1][j];
-                cz[k] = D == 3 ? srt.x[2][j] : 0.0;
-                cj[k] = j;
+                clo[a] = lo;
+                cn[a] = hi - lo + 1;
+                tot *= cn[a];
             }
-            __syncthreads();
-            if (valid) {
-                for (int k = 0; k < m; ++k) {
-                    int j = cj[k];
-                    double dx[3];
-                    dx[0] = min_image(cfg, 0, cx[k] - xi[0]);
-                    dx[1] = min_image(cfg, 1, cy[k] - xi[1]);
-                    dx[2] = D == 3 ? min_image(cfg, 2, cz[k] - xi[2]) : 0.0;
-                    double d2 = dist2_exact<D>(dx);
-                    if (d2 < r2 && j != s) {
-                        if (cnt < max_nb) {
-                            myd2[cnt] = d2;
-                            myj[cnt] = j;
+            if (tot <= MAXRUN || L == g.L_lo) break;
+            --L;
+        }
+        const int ncells = cn[0] * cn[1] * (D == 3 ? cn[2] : 1);
+        const uint32_t *tab = tables + g.off[L];
+        for (int cb = 0; cb < ncells; cb += MAXRUN) {
+            const int nrun = ncells - cb < MAXRUN ? ncells - cb : MAXRUN;
+            uint32_t mylen[MAXRUN / TILE];
+            uint32_t mysum = 0;
+            for (int k = 0; k < MAXRUN / TILE; ++k) {
+                int q = t * (MAXRUN / TILE) + k;
+                uint32_t len = 0;
+                if (q < nrun) {
+                    int qq = cb + q;
+                    int cc[3];
+                    cc[0] = clo[0] + qq % cn[0];
+                    cc[1] = clo[1] + (qq / cn[0]) % cn[1];
+                    cc[2] = D == 3 ? clo[2] + qq / (cn[0] * cn[1]) : 0;
+                    for (int a = 0; a < D; ++a)
+                        if (cfg.periodic[a]) {
+                            int n = g.nc[L][a];
+                            cc[a] = ((cc[a] % n) + n) % n;
                         }
-                        ++cnt;
-                    }
+                    uint32_t code = morton<D>(cc);
+                    uint32_t bb = tab[code], ee = tab[code + 1];
+                    run_b[q] = bb;
+                    len = ee - bb;
                 }
+                mylen[k] = len;
+                mysum += len;
+            }
+            {
+                uint32_t inc = mysum;
+                for (int o = 1; o < 64; o <<= 1) {
+                    uint32_t y = __shfl_up(inc, o);
+                    if (lane >= o) inc += y;
+                }
+                if (lane == 63) wsum[wave] = inc;
+                __syncthreads();
+                uint32_t off = 0, tot = 0;
+                for (int w = 0; w < TILE / 64; ++w) {
+                    if (w < wave) off += wsum[w];
+                    tot += wsum[w];
+                }
+                uint32_t run = off + inc - mysum;
+                for (int k = 0; k < MAXRUN / TILE; ++k) {
+                    int q = t * (MAXRUN / TILE) + k;
+                    run_p[q] = run;
+                    run += mylen[k];
+                }
+                if (t == 0) { run_p[MAXRUN] = tot; geo[0] = (int)tot; }
             }
             __syncthreads();
-        }
-    }
-    if (valid) {
-        count[s] = cnt;
-        if (cnt > max_nb) atomicOr(&sc->error_bits, 1u);
-    }
-    int wmax = valid ? cnt : 0;
-    for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o));
-    if ((t & 63) == 0 && wmax > 0) atomicMax(&sc->max_count, wmax);
-    __syncthreads();
-    }
-}
-
-// Rank every row of hits by (d2, original id) in LDS; G lanes per row.
-template <int G>
-__global__ __launch_bounds__(LP_BLOCK) void k_sort_rows(Sorted srt, const int *n_total_dev, int n_real,
-                                                       const double *hit_d2, const int *hit_j, const int *count,
-                                                       int max_nb, int *nbr, int ldn, int nblocks) {
-    constexpr int PPB = LP_BLOCK / G;
-    extern __shared__ unsigned char smem[];
-    double *ld2 = reinterpret_cast<double *>(smem);
-    int *lid = reinterpret_cast<int *>(ld2 + PPB * max_nb);
-    int *lj = lid + PPB * max_nb;
-    const int lane = threadIdx.x % G;
-    const int grp = threadIdx.x / G;
-    const int s = xcd_remap(blockIdx.x, nblocks) * PPB + grp;
-    const bool active = s < *n_total_dev && srt.id[s] < n_real;
-    double *gd2 = ld2 + grp * max_nb;
-    int *gid = lid + grp * max_nb;
-    int *gj = lj + grp * max_nb;
-    int kk = 0;
-    if (active) {
-        int k = count[s];
-        kk = k < max_nb ? k : max_nb;
-        for (int e = lane; e < kk; e += G) {
-            int j = hit_j[(int64_t)s * max_nb + e];
-            gd2[e] = hit_d2[(int64_t)s * max_nb + e];
-            gj[e] = j;
-            gid[e] = srt.id[j];
-        }
-    }
-    __syncthreads();
-    if (active) {
-        for (int e = lane; e < kk; e += G) {
-            double de = gd2[e];
-            int ie = gid[e];
-            int rank = 0;
-            for (int f = 0; f < kk; ++f) {
-                double df = gd2[f];
-                int idf = gid[f];
-                rank += (df < de) || (df == de && idf < ie);
+            const int H = geo[0];
+            for (int base = 0; base < H; base += CHUNK2) {
+                const int m = H - base < CHUNK2 ? H - base : CHUNK2;
+                for (int k = t; k < m; k += TILE) {
+                    uint32_t gk = (uint32_t)(base + k);
+                    int lo = 0, hi = nrun - 1;
+                    while (lo < hi) {
+                        int mid = (lo + hi + 1) >> 1;
+                        if (run_p[mid] <= gk) lo = mid; else hi = mid - 1;
+                    }
+                    int j = (int)(run_b[lo] + (gk - run_p[lo]));
+                    cx[k] = srt.x[0][j];
+                    cy[k] = srt.x[1][j];
+                    cz[k] = D == 3 ? srt.x[2][j] : 0.0;
+                    cj[k] = j;
+                }
+                __syncthreads();
+                for (int p = wave; p < np; p += TILE / 64) {
+                    const int sp = s0 + p;
+                    if (srt.id[sp] >= n_real) continue;  // wave-uniform
+                    const double px = srt.x[0][sp], py = srt.x[1][sp], pz = D == 3 ? srt.x[2][sp] : 0.0;
+                    const double pr = srt.r[sp];
+                    const double pr2 = pr * pr;
+                    int c = pcnt[p];
+                    double *rd2 = hit_d2 + (int64_t)sp * max_nb;
+                    int *rj = hit_j + (int64_t)sp * max_nb;
+                    for (int k0 = 0; k0 < m; k0 += 64) {
+                        int k = k0 + lane;
+                        bool hit = false;
+                        double d2 = 0.0;
+                        int j = -1;
+                        if (k < m) {
+                            j = cj[k];
+                            double dx[3];
+                            dx[0] = min_image(cfg, 0, cx[k] - px);
+                            dx[1] = min_image(cfg, 1, cy[k] - py);
+                            dx[2] = D == 3 ? min_image(cfg, 2, cz[k] - pz) : 0.0;
+                            d2 = dist2_exact<D>(dx);
+                            hit = d2 < pr2 && j != sp;
+                        }
+                        unsigned long long mask = __ballot(hit);
+                        if (hit) {
+                            int pos = c + __popcll(mask & lt_mask);
+                            if (pos < max_nb) {
+                                rd2[pos] = d2;
+                                rj[pos] = j;
+                            }
+                        }
+                        c += __popcll(mask);
+                    }
+                    if (lane == 0) pcnt[p] = c;
+                }
+                __syncthreads();
             }
-            nbr[(int64_t)rank * ldn + s] = gj[e];
         }
+        // rank each row by (d2, id) and write it in order
+        for (int p = wave; p < np; p += TILE / 64) {
+            const int sp = s0 + p;
+            if (srt.id[sp] >= n_real) continue;  // wave-uniform
+            const int k = pcnt[p];
+            const int kk = k < max_nb ? k : max_nb;
+            for (int e = lane; e < kk; e += 64) {
+                int j = hit_j[(int64_t)sp * max_nb + e];
+                sd2[wave][e] = hit_d2[(int64_t)sp * max_nb + e];
+                sjj[wave][e] = j;
+                sid[wave][e] = srt.id[j];
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            for (int e = lane; e < kk; e += 64) {
+                double de = sd2[wave][e];
+                int ie = sid[wave][e];
+                int rank = 0;
+                for (int f = 0; f < kk; ++f) {
+                    double df = sd2[wave][f];
+                    int idf = sid[wave][f];
+                    rank += (df < de) || (df == de && idf < ie);
+                }
+                nbr[(int64_t)sp * max_nb + rank] = sjj[wave][e];
+            }
+            if (lane == 0) {
+                count[sp] = k;
+                if (k > max_nb) atomicOr(&sc->error_bits, 1u);
+                atomicMax(&sc->max_count, k);
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
     }
 }
 
@@ -445,20 +449,11 @@ void launch_search_tiles(const Sorted &s, const int *n_total_dev, int n_total_ca
                        tile_lo, tile_hi);
     int nb = 2048;
     if (cfg.D == 3)
-        hipLaunchKernelGGL(k_search_tile<3>, dim3(nb), dim3(TILE), 0, st, s, n_total_dev, n_real, tables, g, cfg,
-                           hit_d2, hit_j, count, sc, tile_lo, tile_hi, ntiles_dev);
+        hipLaunchKernelGGL(k_search_tile2<3>, dim3(nb), dim3(TILE), 0, st, s, n_total_dev, n_real, tables, g, cfg,
+                           hit_d2, hit_j, nbr, count, sc, tile_lo, tile_hi, ntiles_dev);
     else
-        hipLaunchKernelGGL(k_search_tile<2>, dim3(nb), dim3(TILE), 0, st, s, n_total_dev, n_real, tables, g, cfg,
-                           hit_d2, hit_j, count, sc, tile_lo, tile_hi, ntiles_dev);
-    int G = 8;
-    while ((size_t)(LP_BLOCK / G) * cfg.max_nb * 16 > 65536 && G < 64) G *= 2;
-    int ppb = LP_BLOCK / G;
-    int nb2 = (n_total_cap + ppb - 1) / ppb;
-    if (nb2 < 1) nb2 = 1;
-    size_t shm = (size_t)ppb * cfg.max_nb * 16;
-#define SR(GG) hipLaunchKernelGGL(k_sort_rows<GG>, dim3(nb2), dim3(LP_BLOCK), shm, st, s, n_total_dev, n_real, hit_d2, \
-                                  hit_j, count, cfg.max_nb, nbr, ldn, nb2)
-    if (G == 8) SR(8); else if (G == 16) SR(16); else if (G == 32) SR(32); else SR(64);
-#undef SR
+        hipLaunchKernelGGL(k_search_tile2<2>, dim3(nb), dim3(TILE), 0, st, s, n_total_dev, n_real, tables, g, cfg,
+                           hit_d2, hit_j, nbr, count, sc, tile_lo, tile_hi, ntiles_dev);
+    (void)ldn;
     (void)hipGetLastError();
 }

@@ -69,7 +69,7 @@ __device__ __forceinline__ void for_lw_stencil(const Sorted &srt, const DevCfg &
     if (k > cap) {
         unsigned long long c03 = 0, c47 = 0;  // octant counts, 16 bits each
         for (int t = 0; t < k; ++t) {
-            int j = nbr[(int64_t)t * ldn + s];
+            int j = nb_at(nbr, ldn, s, t);
             double dx[3];
             displacement<D>(srt, cfg, j, xi, dx);
             int o = octant<D>(dx);
@@ -92,7 +92,7 @@ __device__ __forceinline__ void for_lw_stencil(const Sorted &srt, const DevCfg &
     unsigned long long s03 = 0, s47 = 0;
     int takenR = 0;
     for (int t = 0; t < k; ++t) {
-        int j = nbr[(int64_t)t * ldn + s];
+        int j = nb_at(nbr, ldn, s, t);
         double dx[3];
         displacement<D>(srt, cfg, j, xi, dx);
         if (k > cap) {
@@ -316,7 +316,7 @@ __device__ __forceinline__ void finish_particle(const Sorted &srt, const Soa &p,
         int nl = 0, nr = 0;
         const T fi[3] = {(T)st[0], (T)st[1 + a], (T)st[FP]};
         for (int t = 0; t < k && (nl < ucap || nr < ucap); ++t) {
-            int j = nbr[(int64_t)t * ldn + s];
+            int j = nb_at(nbr, ldn, s, t);
             double dx[3];
             displacement<D>(srt, cfg, j, xi, dx);
             bool right = dx[a] > 0.0, left = dx[a] < 0.0;

@@ -25,9 +25,13 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def _nb_case(lp, oracle_lib, cfg, x, r, tag):
-    say("neighbors", tag, x.shape)
+SEARCH_MODES = [0, 1]
+
+
+def _nb_case(lp, oracle_lib, cfg, x, r, tag, mode=1):
+    say("neighbors", tag, x.shape, "search mode", mode)
     ctx = lp.Context(cfg)
+    ctx.set_tuning(lp.TUNE_SEARCH_MODE, mode)
     count, idx, st = ctx.neighbors([_dev(x[:, a]) for a in range(cfg["dim"])], _dev(r))
     assert st == lp.OK
     count = count.cpu().numpy()
@@ -41,33 +45,38 @@ def _nb_case(lp, oracle_lib, cfg, x, r, tag):
     ctx.close()
 
 
-def test_neighbors_pulse2d(lp, oracle_lib):
+@pytest.mark.parametrize("mode", SEARCH_MODES)
+def test_neighbors_pulse2d(lp, oracle_lib, mode):
     cfg, st = W.pulse2d()
-    _nb_case(lp, oracle_lib, cfg, st["x"], radii(cfg, st), "pulse2d")
+    _nb_case(lp, oracle_lib, cfg, st["x"], radii(cfg, st), "pulse2d", mode)
 
 
-def test_neighbors_lattice_ties(lp, oracle_lib):
+@pytest.mark.parametrize("mode", SEARCH_MODES)
+def test_neighbors_lattice_ties(lp, oracle_lib, mode):
     cfg, st = W.uniform_box(3, 12, jitter=0.0)
-    _nb_case(lp, oracle_lib, cfg, st["x"], radii(cfg, st), "exact lattice")
+    _nb_case(lp, oracle_lib, cfg, st["x"], radii(cfg, st), "exact lattice", mode)
 
 
-def test_neighbors_periodic_3d(lp, oracle_lib):
+@pytest.mark.parametrize("mode", SEARCH_MODES)
+def test_neighbors_periodic_3d(lp, oracle_lib, mode):
     cfg, st = W.uniform_box(3, 24, seed=3)
-    _nb_case(lp, oracle_lib, cfg, st["x"], radii(cfg, st), "jittered 24^3")
+    _nb_case(lp, oracle_lib, cfg, st["x"], radii(cfg, st), "jittered 24^3", mode)
 
 
-def test_neighbors_variable_radius(lp, oracle_lib):
+@pytest.mark.parametrize("mode", SEARCH_MODES)
+def test_neighbors_variable_radius(lp, oracle_lib, mode):
     cfg, st = W.vacuum3d(n_particles=150_000, seed=5)
-    _nb_case(lp, oracle_lib, cfg, st["x"], radii(cfg, st), "vacuum 150k")
+    _nb_case(lp, oracle_lib, cfg, st["x"], radii(cfg, st), "vacuum 150k", mode)
 
 
-def test_neighbors_outside_box_and_anisotropic(lp, oracle_lib):
+@pytest.mark.parametrize("mode", SEARCH_MODES)
+def test_neighbors_outside_box_and_anisotropic(lp, oracle_lib, mode):
     rng = np.random.default_rng(0)
     cfg = W.base_config("t", 3, 1.0, [0.0, 0.0, 0.0], [2.0, 1.0, 1.0], [True, False, True])
     x = rng.uniform([0, -0.2, 0], [2, 1.2, 1], size=(20000, 3))
     r = rng.uniform(0.02, 0.09, size=20000)
     cfg["max_nb"] = 256
-    _nb_case(lp, oracle_lib, cfg, x, r, "mixed box")
+    _nb_case(lp, oracle_lib, cfg, x, r, "mixed box", mode)
 
 
 def test_neighbors_capacity(lp):
@@ -105,9 +114,11 @@ def test_gfd_quadratic_and_oracle(lp, oracle_lib, dim):
             assert err <= 1e-10, (f, c, err)
 
 
-def _run_both(lp, oracle_lib, cfg, st, nsteps, precision, tol, tag, dt=None):
-    say("step", tag, precision, st["V"].shape[0], "particles", nsteps, "steps")
+def _run_both(lp, oracle_lib, cfg, st, nsteps, precision, tol, tag, dt=None, mode=None):
+    say("step", tag, precision, st["V"].shape[0], "particles", nsteps, "steps", "search mode", mode)
     ctx = lp.Context(cfg, precision=precision)
+    if mode is not None:
+        ctx.set_tuning(lp.TUNE_SEARCH_MODE, mode)
     dev = lp.state_to_device(st)
     ref = st
     for k in range(nsteps):
@@ -123,9 +134,10 @@ def _run_both(lp, oracle_lib, cfg, st, nsteps, precision, tol, tag, dt=None):
     return got, ref, info, ctx
 
 
-def test_step_pulse2d_fp64(lp, oracle_lib):
+@pytest.mark.parametrize("mode", SEARCH_MODES)
+def test_step_pulse2d_fp64(lp, oracle_lib, mode):
     cfg, st = W.pulse2d()
-    got, ref, info, ctx = _run_both(lp, oracle_lib, cfg, st, 10, "fp64", 1e-10, "pulse2d")
+    got, ref, info, ctx = _run_both(lp, oracle_lib, cfg, st, 10, "fp64", 1e-10, "pulse2d", mode=mode)
     assert np.array_equal(got["flags"] & 15, info["flags"] & 15)
 
 
@@ -150,9 +162,10 @@ def test_step_sod_slab_mixed(lp, oracle_lib):
     _run_both(lp, oracle_lib, cfg, st, 12, "mixed", 1e-4, "sod slab")
 
 
-def test_step_vacuum_fp64(lp, oracle_lib):
+@pytest.mark.parametrize("mode", SEARCH_MODES)
+def test_step_vacuum_fp64(lp, oracle_lib, mode):
     cfg, st = W.vacuum3d(n_particles=120_000, seed=9)
-    got, ref, info, ctx = _run_both(lp, oracle_lib, cfg, st, 2, "fp64", 1e-10, "vacuum 120k")
+    got, ref, info, ctx = _run_both(lp, oracle_lib, cfg, st, 2, "fp64", 1e-10, "vacuum 120k", mode=mode)
     assert (info["flags"] & 4).sum() > 0  # vacuum ghosts were used
 
 
