@@ -35,7 +35,8 @@ struct lp_ctx {
     DevScalars *sc = nullptr;       // device scalars
     DevScalars *sc_host = nullptr;  // pinned copy
     int nwalls = 0;
-    double S = 1.0;                 // cube side of the cell grids
+    double S = 1.0;                 // cube side from the box (periodic extents are S / 2^j)
+    double S_grid = 1.0;            // cube side used by the last grid
     int jper[3] = {0, 0, 0};        // periodic extent = S / 2^jper
     int search_group = 16;
     int64_t cap_real = 0, cap_total = 0, cap_ghost = 0;
@@ -255,15 +256,40 @@ extern "C" lp_status lp_destroy(lp_ctx *c) {
 // than r_min (bounded by a table of 2^27 cells), the coarsest no larger than
 // r_max; periodic axes need whole cells per period.
 // ---------------------------------------------------------------------------
+static double key_to_double(unsigned long long k) {
+    unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    return bits_to_double(b);
+}
+
+// Grid cube: with any periodic axis, the box-derived side S (periodic
+// extents are S / 2^j); otherwise the cube is fitted to the particles'
+// bounding box read back with the radii, so no level is wasted on empty space.
 static void choose_levels(lp_ctx *c, double rmin, double rmax) {
     const int D = c->dc.D;
     const int Lmax = D == 3 ? 9 : 13;
     int jmin = 0;
-    for (int a = 0; a < D; ++a)
+    bool any_periodic = false;
+    for (int a = 0; a < D; ++a) {
+        if (c->dc.periodic[a]) any_periodic = true;
         if (c->dc.periodic[a] && c->jper[a] > jmin) jmin = c->jper[a];
+    }
+    double S = c->S;
+    double glo[3] = {c->dc.lo[0], c->dc.lo[1], c->dc.lo[2]};
+    if (!any_periodic) {
+        double ext = 0.0;
+        for (int a = 0; a < D; ++a) {
+            double lo = key_to_double(c->sc_host->xlo[a]), hi = key_to_double(c->sc_host->xhi[a]);
+            if (!(hi >= lo)) { lo = c->dc.lo[a]; hi = c->dc.hi[a]; }
+            glo[a] = lo;
+            if (hi - lo > ext) ext = hi - lo;
+        }
+        if (!(ext > 0.0)) ext = c->S;
+        S = ext * (1.0 + 1e-9) + 1e-300;
+    }
+    c->S_grid = S;
     auto level_le = [&](double r) {
         int L = 0;
-        while (L < Lmax && ldexp(c->S, -L) > r) ++L;
+        while (L < Lmax && ldexp(S, -L) > r) ++L;
         return L;
     };
     int hi = level_le(rmin > 0 ? rmin : c->S);
@@ -278,8 +304,8 @@ static void choose_levels(lp_ctx *c, double rmin, double rmax) {
     g.L_hi = hi;
     unsigned long long off = 0;
     for (int L = 0; L < LP_MAX_LEVEL; ++L) {
-        g.s[L] = ldexp(c->S, -L);
-        g.inv_s[L] = ldexp(1.0 / c->S, L);
+        g.s[L] = ldexp(S, -L);
+        g.inv_s[L] = ldexp(1.0 / S, L);
         for (int a = 0; a < 3; ++a) {
             if (a >= D) { g.nc[L][a] = 1; continue; }
             int n = 1 << L;
@@ -291,7 +317,7 @@ static void choose_levels(lp_ctx *c, double rmin, double rmax) {
             off += (1ull << (D * L)) + 1;
         }
     }
-    for (int a = 0; a < 3; ++a) g.lo[a] = a < D ? c->dc.lo[a] : 0.0;
+    for (int a = 0; a < 3; ++a) g.lo[a] = a < D ? glo[a] : 0.0;
     c->last_levels[0] = lo;
     c->last_levels[1] = hi;
 }
@@ -552,7 +578,10 @@ extern "C" lp_status lp_neighbors(lp_ctx *c, void *stream, int64_t n, const doub
     hipStream_t st = (hipStream_t)stream;
     const int D = c->dc.D;
     launch_reset_scalars(c->sc, 0.0, (int)n, st);
-    launch_rminmax(r, (int)n, c->sc, st);
+    {
+        const double *xs[3] = {x, y, c->dc.D == 3 ? z : y};
+        launch_rminmax(r, xs, c->dc.D, (int)n, c->sc, st);
+    }
     HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     choose_levels(c, bits_to_double(c->sc_host->rmin), bits_to_double(c->sc_host->rmax));
@@ -594,7 +623,10 @@ extern "C" lp_status lp_gfd(lp_ctx *c, void *stream, int64_t n, const double *x,
     hipStream_t st = (hipStream_t)stream;
     const int D = c->dc.D;
     launch_reset_scalars(c->sc, 0.0, (int)n, st);
-    launch_rminmax(r, (int)n, c->sc, st);
+    {
+        const double *xs[3] = {x, y, c->dc.D == 3 ? z : y};
+        launch_rminmax(r, xs, c->dc.D, (int)n, c->sc, st);
+    }
     HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     choose_levels(c, bits_to_double(c->sc_host->rmin), bits_to_double(c->sc_host->rmax));

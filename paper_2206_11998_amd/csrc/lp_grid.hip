@@ -29,6 +29,7 @@ __global__ void k_reset_scalars(DevScalars *sc, double dt_in, int n_real) {
     sc->max_count = 0;
     sc->n_fallback = 0;
     sc->n_limited = 0ull;
+    for (int a = 0; a < 3; ++a) { sc->xlo[a] = ~0ull; sc->xhi[a] = 0ull; }
 }
 
 void launch_reset_scalars(DevScalars *sc, double dt_in, int n_real, hipStream_t st) {
@@ -43,6 +44,20 @@ __device__ __forceinline__ double wave_min(double v) {
 __device__ __forceinline__ double wave_max(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
     return v;
+}
+
+// bounding box of the positions (wave-reduced, then one atomic per wave)
+__device__ __forceinline__ void bbox_reduce(double *const x[3], int D, int i, int n, DevScalars *sc) {
+    for (int a = 0; a < D; ++a) {
+        double lo = INFINITY, hi = -INFINITY;
+        if (i < n) { lo = x[a][i]; hi = lo; }
+        lo = wave_min(lo);
+        hi = wave_max(hi);
+        if ((threadIdx.x & 63) == 0 && lo <= hi) {
+            atomicMin(&sc->xlo[a], dbl_key(lo));
+            atomicMax(&sc->xhi[a], dbl_key(hi));
+        }
+    }
 }
 
 // h_i = (m_i V_i)^(1/D), c_i = sqrt(gamma P_i V_i), r_i = kappa h_i;
@@ -72,6 +87,7 @@ __global__ void k_prep(Soa p, DevCfg cfg, DevScalars *sc, double *h_out, double 
         if (rr_min < INFINITY) atomicMin(&sc->rmin, dbl_bits(rr_min));
         if (rr_max > 0.0) atomicMax(&sc->rmax, dbl_bits(rr_max));
     }
+    bbox_reduce(p.x, cfg.D, i, p.n, sc);
 }
 
 void launch_prep(const Soa &p, const DevCfg &cfg, DevScalars *sc, double *h, double *r, hipStream_t st) {
@@ -92,7 +108,7 @@ __global__ void k_dt(DevCfg cfg, DevScalars *sc, int clip) {
 }
 
 // min / max of given radii (for searches on caller-provided radii)
-__global__ void k_rminmax(const double *r, int n, DevScalars *sc) {
+__global__ void k_rminmax(const double *r, double *x0, double *x1, double *x2, int D, int n, DevScalars *sc) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     double lo = INFINITY, hi = 0.0;
     if (i < n) { lo = r[i]; hi = r[i]; }
@@ -102,10 +118,13 @@ __global__ void k_rminmax(const double *r, int n, DevScalars *sc) {
         if (lo < INFINITY) atomicMin(&sc->rmin, dbl_bits(lo));
         if (hi > 0.0) atomicMax(&sc->rmax, dbl_bits(hi));
     }
+    double *const xs[3] = {x0, x1, x2};
+    bbox_reduce(xs, D, i, n, sc);
 }
 
-void launch_rminmax(const double *r, int n, DevScalars *sc, hipStream_t st) {
-    hipLaunchKernelGGL(k_rminmax, dim3(blocks_for(n)), dim3(LP_BLOCK), 0, st, r, n, sc);
+void launch_rminmax(const double *r, const double *const x[3], int D, int n, DevScalars *sc, hipStream_t st) {
+    hipLaunchKernelGGL(k_rminmax, dim3(blocks_for(n)), dim3(LP_BLOCK), 0, st, r, (double *)x[0], (double *)x[1],
+                       (double *)x[2], D, n, sc);
     CHECK_LAUNCH();
 }
 

@@ -47,6 +47,7 @@ struct DevScalars {
     unsigned int error_bits;        // 1: capacity, 2: numeric
     unsigned int done;              // lp_run: t reached t_end
     int n_tiles;                    // search tiles of the last search
+    unsigned long long xlo[3], xhi[3];  // bounding box of real particles (order-preserving keys)
     unsigned long long n_limited;
 };
 
@@ -86,7 +87,7 @@ struct ScatterArgs {
 // Host launchers (defined in the .hip files).
 // ---------------------------------------------------------------------------
 void launch_reset_scalars(DevScalars *sc, double dt_in, int n_real, hipStream_t st);
-void launch_rminmax(const double *r, int n, DevScalars *sc, hipStream_t st);
+void launch_rminmax(const double *r, const double *const x[3], int D, int n, DevScalars *sc, hipStream_t st);
 void launch_advance_time(DevScalars *sc, hipStream_t st);
 void launch_prep(const Soa &p, const DevCfg &cfg, DevScalars *sc, double *h, double *r, hipStream_t st);
 void launch_dt(const DevCfg &cfg, DevScalars *sc, int clip_t_end, hipStream_t st);
@@ -132,6 +133,11 @@ void launch_conservation(const Soa &p, const DevCfg &cfg, double *partials, int 
 // Shared device helpers.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ unsigned long long dbl_bits(double v) { return (unsigned long long)__double_as_longlong(v); }
+// Order-preserving map of any double to an unsigned key (for atomic min/max).
+__device__ __forceinline__ unsigned long long dbl_key(double v) {
+    unsigned long long b = dbl_bits(v);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
 __device__ __forceinline__ double bits_dbl(unsigned long long b) { return __longlong_as_double((long long)b); }
 
 // Minimum-image displacement x_j - x_i along axis a.  Evaluated exactly as

@@ -148,15 +148,15 @@ void launch_search(const Sorted &s, const int *n_total_dev, int n_total_cap, int
 
 // ===========================================================================
 // Tiled search: a block takes one tile -- the coarsest cell holding at most
-// 256 particles -- finds the cells that cover the union of its particles'
+// TLEAF particles -- finds the cells that cover the union of its particles'
 // search balls, and streams the particles of those cells through LDS.
 // ===========================================================================
-#define TILE 256
-#define CHUNK 1536
+#define TILE 256    // threads per block of the tiled search
+#define TLEAF 64    // particles per tile (leaf cell capacity)
 #define MAXRUN 1024
 
-// Adaptive tiles: the coarsest cell holding at most TILE particles (the
-// octree leaf of the paper's step 2), split into runs of TILE when the finest
+// Adaptive tiles: the coarsest cell holding at most TLEAF particles (the
+// octree leaf of the paper's step 2), split into runs of TLEAF when the finest
 // level is still fuller.  Every particle that starts a tile is flagged.
 __global__ void k_tile_flags(Sorted srt, const int *n_total_dev, int cap, const uint32_t *key,
                              const uint32_t *tables, DevGrid g, int D, uint32_t *flag) {
@@ -171,9 +171,9 @@ __global__ void k_tile_flags(Sorted srt, const int *n_total_dev, int cap, const 
         const uint32_t *tab = tables + g.off[L];
         cs = tab[code];
         ce = tab[code + 1];
-        if (ce - cs <= TILE) break;
+        if (ce - cs <= TLEAF) break;
     }
-    flag[s] = ((uint32_t)s - cs) % TILE == 0 ? 1u : 0u;
+    flag[s] = ((uint32_t)s - cs) % TLEAF == 0 ? 1u : 0u;
     (void)ce;
 }
 
@@ -190,23 +190,40 @@ __global__ void k_tile_list(Sorted srt, const int *n_total_dev, const uint32_t *
         const uint32_t *tab = tables + g.off[L];
         uint32_t cs = tab[code];
         ce = tab[code + 1];
-        if (ce - cs <= TILE) break;
+        if (ce - cs <= TLEAF) break;
     }
-    uint32_t e = (uint32_t)s + TILE < ce ? (uint32_t)s + TILE : ce;
+    uint32_t e = (uint32_t)s + TLEAF < ce ? (uint32_t)s + TLEAF : ce;
     tile_lo[off[s]] = s;
     tile_hi[off[s]] = (int)e;
 }
 
 // ===========================================================================
-// Wave per particle: the tile's halo is staged in LDS;
-// each wave then takes one particle at a time and its 64 lanes test 64 staged
-// candidates at once.  Hits are compacted with a ballot and appended to the
-// particle's row (contiguous, coalesced stores).  After the last chunk the same
-// wave reads each row back (L2-hot), ranks it by (d2, id) in LDS and writes the
-// final row.  Output layout: row-major nbr[s * max_nb + c].
+// Wave per particle: the tile's halo is staged in LDS; each wave then takes
+// one particle at a time and its 64 lanes test 64 staged candidates at once.
+// Hits are compacted with a ballot into the wave's LDS buffer, ranked there by
+// (d2, original id), and the row is written in order.  A halo larger than one
+// LDS chunk (rare) is streamed in chunks with the hits appended to a scratch
+// row in global memory instead.  Output layout: row-major nbr[s * max_nb + c].
 // ===========================================================================
-#define CHUNK2 1024
+#define CHUNK2 768
 #define SORTCAP 256
+#define TW (TILE / 64)
+
+template <int D>
+__device__ __forceinline__ void rank_and_write(const double *sd2, const int *sid, const int *sjj, int kk, int lane,
+                                               int *row) {
+    for (int e = lane; e < kk; e += 64) {
+        double de = sd2[e];
+        int ie = sid[e];
+        int rank = 0;
+        for (int f = 0; f < kk; ++f) {
+            double df = sd2[f];
+            int idf = sid[f];
+            rank += (df < de) || (df == de && idf < ie);
+        }
+        row[rank] = sjj[e];
+    }
+}
 
 template <int D>
 __global__ __launch_bounds__(TILE) void k_search_tile2(Sorted srt, const int *n_total_dev, int n_real,
@@ -214,16 +231,18 @@ __global__ __launch_bounds__(TILE) void k_search_tile2(Sorted srt, const int *n_
                                                       int *hit_j, int *nbr, int *count, DevScalars *sc,
                                                       const int *tile_lo, const int *tile_hi, const int *ntiles_dev) {
     __shared__ double cx[CHUNK2], cy[CHUNK2], cz[CHUNK2];
-    __shared__ int cj[CHUNK2];
+    __shared__ int cj[CHUNK2], cid[CHUNK2];
     __shared__ uint32_t run_b[MAXRUN];
     __shared__ uint32_t run_p[MAXRUN + 1];
-    __shared__ double red[7][TILE / 64];
+    __shared__ double red[7][TW];
     __shared__ int geo[2];
-    __shared__ uint32_t wsum[TILE / 64];
+    __shared__ uint32_t wsum[TW];
     __shared__ int pcnt[TILE];
-    __shared__ double sd2[TILE / 64][SORTCAP];
-    __shared__ int sid[TILE / 64][SORTCAP];
-    __shared__ int sjj[TILE / 64][SORTCAP];
+    __shared__ double tpx[TILE], tpy[TILE], tpz[TILE], tpr[TILE];
+    __shared__ int tpid[TILE];
+    __shared__ double sd2[TW][SORTCAP];
+    __shared__ int sid[TW][SORTCAP];
+    __shared__ int sjj[TW][SORTCAP];
 
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
@@ -239,13 +258,16 @@ __global__ __launch_bounds__(TILE) void k_search_tile2(Sorted srt, const int *n_
         const int s0 = tile_lo[tile];
         const int np = tile_hi[tile] - s0;
         const int s = s0 + t;
-        const bool valid = t < np && srt.id[s] < n_real;
+        bool valid = false;
         double ri = 0.0, xi[3] = {0.0, 0.0, 0.0};
-        if (valid) {
+        if (t < np) {
+            int id = srt.id[s];
+            valid = id < n_real;
             xi[0] = srt.x[0][s];
             xi[1] = srt.x[1][s];
             if (D == 3) xi[2] = srt.x[2][s];
             ri = srt.r[s];
+            tpx[t] = xi[0]; tpy[t] = xi[1]; tpz[t] = xi[2]; tpr[t] = ri; tpid[t] = id;
         }
         pcnt[t] = 0;
         double v[7];
@@ -267,7 +289,7 @@ __global__ __launch_bounds__(TILE) void k_search_tile2(Sorted srt, const int *n_
             double m[7];
             for (int q = 0; q < 7; ++q) {
                 m[q] = red[q][0];
-                for (int w = 1; w < TILE / 64; ++w) m[q] = fmin(m[q], red[q][w]);
+                for (int w = 1; w < TW; ++w) m[q] = fmin(m[q], red[q][w]);
             }
             for (int a = 0; a < 3; ++a) { blo[a] = m[a]; bhi[a] = -m[3 + a]; }
             rmax = -m[6];
@@ -297,6 +319,7 @@ __global__ __launch_bounds__(TILE) void k_search_tile2(Sorted srt, const int *n_
         }
         const int ncells = cn[0] * cn[1] * (D == 3 ? cn[2] : 1);
         const uint32_t *tab = tables + g.off[L];
+        bool in_lds = true;  // hits kept in LDS (single batch and single chunk)
         for (int cb = 0; cb < ncells; cb += MAXRUN) {
             const int nrun = ncells - cb < MAXRUN ? ncells - cb : MAXRUN;
             uint32_t mylen[MAXRUN / TILE];
@@ -332,7 +355,7 @@ __global__ __launch_bounds__(TILE) void k_search_tile2(Sorted srt, const int *n_
                 if (lane == 63) wsum[wave] = inc;
                 __syncthreads();
                 uint32_t off = 0, tot = 0;
-                for (int w = 0; w < TILE / 64; ++w) {
+                for (int w = 0; w < TW; ++w) {
                     if (w < wave) off += wsum[w];
                     tot += wsum[w];
                 }
@@ -346,6 +369,7 @@ __global__ __launch_bounds__(TILE) void k_search_tile2(Sorted srt, const int *n_
             }
             __syncthreads();
             const int H = geo[0];
+            if (ncells > MAXRUN || H > CHUNK2) in_lds = false;  // uniform
             for (int base = 0; base < H; base += CHUNK2) {
                 const int m = H - base < CHUNK2 ? H - base : CHUNK2;
                 for (int k = t; k < m; k += TILE) {
@@ -360,13 +384,13 @@ __global__ __launch_bounds__(TILE) void k_search_tile2(Sorted srt, const int *n_
                     cy[k] = srt.x[1][j];
                     cz[k] = D == 3 ? srt.x[2][j] : 0.0;
                     cj[k] = j;
+                    cid[k] = srt.id[j];
                 }
                 __syncthreads();
-                for (int p = wave; p < np; p += TILE / 64) {
+                for (int p = wave; p < np; p += TW) {
+                    if (tpid[p] >= n_real) continue;  // wave-uniform
                     const int sp = s0 + p;
-                    if (srt.id[sp] >= n_real) continue;  // wave-uniform
-                    const double px = srt.x[0][sp], py = srt.x[1][sp], pz = D == 3 ? srt.x[2][sp] : 0.0;
-                    const double pr = srt.r[sp];
+                    const double px = tpx[p], py = tpy[p], pz = tpz[p], pr = tpr[p];
                     const double pr2 = pr * pr;
                     int c = pcnt[p];
                     double *rd2 = hit_d2 + (int64_t)sp * max_nb;
@@ -388,49 +412,63 @@ __global__ __launch_bounds__(TILE) void k_search_tile2(Sorted srt, const int *n_
                         unsigned long long mask = __ballot(hit);
                         if (hit) {
                             int pos = c + __popcll(mask & lt_mask);
-                            if (pos < max_nb) {
+                            if (in_lds) {
+                                if (pos < max_nb) {
+                                    sd2[wave][pos] = d2;
+                                    sjj[wave][pos] = j;
+                                    sid[wave][pos] = cid[k];
+                                }
+                            } else if (pos < max_nb) {
                                 rd2[pos] = d2;
                                 rj[pos] = j;
                             }
                         }
                         c += __popcll(mask);
                     }
-                    if (lane == 0) pcnt[p] = c;
+                    if (in_lds) {
+                        // the halo fitted one chunk: the row is complete, rank it now
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                        const int kk = c < max_nb ? c : max_nb;
+                        rank_and_write<D>(sd2[wave], sid[wave], sjj[wave], kk, lane, nbr + (int64_t)sp * max_nb);
+                        if (lane == 0) {
+                            count[sp] = c;
+                            if (c > max_nb) atomicOr(&sc->error_bits, 1u);
+                            atomicMax(&sc->max_count, c);
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    } else if (lane == 0) {
+                        pcnt[p] = c;
+                    }
                 }
                 __syncthreads();
             }
         }
-        // rank each row by (d2, id) and write it in order
-        for (int p = wave; p < np; p += TILE / 64) {
-            const int sp = s0 + p;
-            if (srt.id[sp] >= n_real) continue;  // wave-uniform
-            const int k = pcnt[p];
-            const int kk = k < max_nb ? k : max_nb;
-            for (int e = lane; e < kk; e += 64) {
-                int j = hit_j[(int64_t)sp * max_nb + e];
-                sd2[wave][e] = hit_d2[(int64_t)sp * max_nb + e];
-                sjj[wave][e] = j;
-                sid[wave][e] = srt.id[j];
-            }
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            for (int e = lane; e < kk; e += 64) {
-                double de = sd2[wave][e];
-                int ie = sid[wave][e];
-                int rank = 0;
-                for (int f = 0; f < kk; ++f) {
-                    double df = sd2[wave][f];
-                    int idf = sid[wave][f];
-                    rank += (df < de) || (df == de && idf < ie);
+        if (!in_lds) {
+            // rows were appended in global memory: rank each one by (d2, id)
+            for (int p = wave; p < np; p += TW) {
+                if (tpid[p] >= n_real) continue;  // wave-uniform
+                const int sp = s0 + p;
+                const int k = pcnt[p];
+                const int kk = k < max_nb ? k : max_nb;
+                for (int e = lane; e < kk; e += 64) {
+                    int j = hit_j[(int64_t)sp * max_nb + e];
+                    sd2[wave][e] = hit_d2[(int64_t)sp * max_nb + e];
+                    sjj[wave][e] = j;
+                    sid[wave][e] = srt.id[j];
                 }
-                nbr[(int64_t)sp * max_nb + rank] = sjj[wave][e];
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                rank_and_write<D>(sd2[wave], sid[wave], sjj[wave], kk, lane, nbr + (int64_t)sp * max_nb);
+                if (lane == 0) {
+                    count[sp] = k;
+                    if (k > max_nb) atomicOr(&sc->error_bits, 1u);
+                    atomicMax(&sc->max_count, k);
+                }
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             }
-            if (lane == 0) {
-                count[sp] = k;
-                if (k > max_nb) atomicOr(&sc->error_bits, 1u);
-                atomicMax(&sc->max_count, k);
-            }
-            __builtin_amdgcn_wave_barrier();
         }
         __syncthreads();
     }
