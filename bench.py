@@ -49,6 +49,7 @@ def main():
     ap.add_argument("--sample", type=int, default=0, help="particles in the CPU-reference sample (0: all)")
     ap.add_argument("--search-mode", type=int, default=None, help="override the neighbour-search mode (0/1)")
     ap.add_argument("--search-group", type=int, default=None)
+    ap.add_argument("--max-nb", type=int, default=None, help="override the neighbour-list capacity")
     ap.add_argument("--solve-block", type=int, default=None)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device copies of 1 GiB (HBM counter calibration) and exit")
@@ -75,6 +76,8 @@ def main():
 
     t0 = time.time()
     cfg, st = W.vacuum3d(n_particles=args.n)
+    if args.max_nb:
+        cfg["max_nb"] = args.max_nb
     n = st["V"].shape[0]
     log("workload generated: %d particles in %.1fs" % (n, time.time() - t0))
     rng = np.random.default_rng(1234)

@@ -29,8 +29,8 @@ struct lp_ctx {
     std::string err;
     // workspace
     Buf h, r, gcnt, scan_tmp, ghosts, key, slot, tables, sorted, sortedf, sid, nbr, count, queue, partials, consout,
-        gfd_fields, hitd2, hitj, tflags, tlo, thi;
-    int search_mode = 0;            // 1: LDS-tiled search + row sort, 0: lane group per particle
+        gfd_fields, hitd2, hitj, tflags, tlo, thi, prep_part;
+    int search_mode = 0;            // 0: lane group per particle walking its cells, 1: LDS-staged tiles
     int solve_block = 256;
     DevScalars *sc = nullptr;       // device scalars
     DevScalars *sc_host = nullptr;  // pinned copy
@@ -242,7 +242,7 @@ extern "C" lp_status lp_destroy(lp_ctx *c) {
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     Buf *bufs[] = {&c->h, &c->r, &c->gcnt, &c->scan_tmp, &c->ghosts, &c->key, &c->slot, &c->tables, &c->sorted,
                    &c->sortedf, &c->sid, &c->nbr, &c->count, &c->queue, &c->partials, &c->consout, &c->gfd_fields,
-                   &c->hitd2, &c->hitj, &c->tflags, &c->tlo, &c->thi};
+                   &c->hitd2, &c->hitj, &c->tflags, &c->tlo, &c->thi, &c->prep_part};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->sc) (void)hipFree(c->sc);
@@ -459,10 +459,11 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
         ENSURE(c, c->r, sizeof(double) * n);
         ENSURE(c, c->gcnt, sizeof(uint32_t) * (n + 1));
         ENSURE(c, c->scan_tmp, sizeof(uint32_t) * scan_tmp_words(n));
+        ENSURE(c, c->prep_part, sizeof(double) * prep_partial_words(n));
     }
     stage_mark(c, st, 0, true);
     launch_reset_scalars(c->sc, dt_in, n, st);
-    launch_prep(soa, c->dc, c->sc, (double *)c->h.p, (double *)c->r.p, st);
+    launch_prep(soa, c->dc, c->sc, (double *)c->h.p, (double *)c->r.p, (double *)c->prep_part.p, st);
     launch_dt(c->dc, c->sc, clip_t_end, st);
     if (c->nwalls) {
         launch_ghost_count(soa, c->dc, c->sc, (uint32_t *)c->gcnt.p, st);

@@ -60,13 +60,13 @@ __device__ __forceinline__ void bbox_reduce(double *const x[3], int D, int i, in
     }
 }
 
-// h_i = (m_i V_i)^(1/D), c_i = sqrt(gamma P_i V_i), r_i = kappa h_i;
-// min h/c, min r and max r reduced with integer atomics on the bit patterns
-// (positive doubles order like their bit patterns, so the result is exact and
-// independent of the reduction order).
-__global__ void k_prep(Soa p, DevCfg cfg, DevScalars *sc, double *h_out, double *r_out) {
+// Per-block minima of (h/c, r, -r, x_a, -x_a) written to part[block * 9 + q];
+// k_prep_final folds the block results (order-free min, so exact).
+#define PREP_Q 9
+__global__ void k_prep(Soa p, DevCfg cfg, double *h_out, double *r_out, double *part) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double hc = INFINITY, rr_min = INFINITY, rr_max = 0.0;
+    double v[PREP_Q];
+    for (int q = 0; q < PREP_Q; ++q) v[q] = INFINITY;
     if (i < p.n) {
         double V = p.V[i], P = p.P[i], m = p.m[i];
         double mv = m * V;
@@ -75,25 +75,65 @@ __global__ void k_prep(Soa p, DevCfg cfg, DevScalars *sc, double *h_out, double 
         double r = cfg.kappa * h;
         h_out[i] = h;
         r_out[i] = r;
-        hc = h / c;
-        rr_min = r;
-        rr_max = r;
+        v[0] = h / c;
+        v[1] = r;
+        v[2] = -r;
+        for (int a = 0; a < cfg.D; ++a) {
+            double x = p.x[a][i];
+            v[3 + a] = x;
+            v[6 + a] = -x;
+        }
     }
-    hc = wave_min(hc);
-    rr_min = wave_min(rr_min);
-    rr_max = wave_max(rr_max);
-    if ((threadIdx.x & 63) == 0) {
-        if (hc < INFINITY) atomicMin(&sc->min_hc, dbl_bits(hc));
-        if (rr_min < INFINITY) atomicMin(&sc->rmin, dbl_bits(rr_min));
-        if (rr_max > 0.0) atomicMax(&sc->rmax, dbl_bits(rr_max));
+    __shared__ double red[PREP_Q][LP_BLOCK / 64];
+    for (int q = 0; q < PREP_Q; ++q) {
+        double w = wave_min(v[q]);
+        if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = w;
     }
-    bbox_reduce(p.x, cfg.D, i, p.n, sc);
+    __syncthreads();
+    if (threadIdx.x < PREP_Q) {
+        double w = red[threadIdx.x][0];
+        for (int k = 1; k < LP_BLOCK / 64; ++k) w = fmin(w, red[threadIdx.x][k]);
+        part[(int64_t)blockIdx.x * PREP_Q + threadIdx.x] = w;
+    }
 }
 
-void launch_prep(const Soa &p, const DevCfg &cfg, DevScalars *sc, double *h, double *r, hipStream_t st) {
-    hipLaunchKernelGGL(k_prep, dim3(blocks_for(p.n)), dim3(LP_BLOCK), 0, st, p, cfg, sc, h, r);
+__global__ void k_prep_final(const double *part, int nblocks, DevScalars *sc) {
+    __shared__ double red[PREP_Q][1024 / 64];
+    double v[PREP_Q];
+    for (int q = 0; q < PREP_Q; ++q) v[q] = INFINITY;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+        for (int q = 0; q < PREP_Q; ++q) v[q] = fmin(v[q], part[(int64_t)b * PREP_Q + q]);
+    for (int q = 0; q < PREP_Q; ++q) {
+        double w = wave_min(v[q]);
+        if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m[PREP_Q];
+        for (int q = 0; q < PREP_Q; ++q) {
+            m[q] = red[q][0];
+            for (int k = 1; k < (int)(blockDim.x / 64); ++k) m[q] = fmin(m[q], red[q][k]);
+        }
+        if (m[0] < INFINITY) sc->min_hc = dbl_bits(m[0]);
+        if (m[1] < INFINITY) sc->rmin = dbl_bits(m[1]);
+        if (m[2] < INFINITY) sc->rmax = dbl_bits(-m[2]);
+        for (int a = 0; a < 3; ++a)
+            if (m[3 + a] < INFINITY) {
+                sc->xlo[a] = dbl_key(m[3 + a]);
+                sc->xhi[a] = dbl_key(-m[6 + a]);
+            }
+    }
+}
+
+void launch_prep(const Soa &p, const DevCfg &cfg, DevScalars *sc, double *h, double *r, double *part,
+                 hipStream_t st) {
+    unsigned nb = blocks_for(p.n);
+    hipLaunchKernelGGL(k_prep, dim3(nb), dim3(LP_BLOCK), 0, st, p, cfg, h, r, part);
+    hipLaunchKernelGGL(k_prep_final, dim3(1), dim3(1024), 0, st, part, (int)nb, sc);
     CHECK_LAUNCH();
 }
+
+size_t prep_partial_words(int64_t n) { return (size_t)((n + LP_BLOCK - 1) / LP_BLOCK + 1) * PREP_Q; }
 
 // dt = cfl * min h/c unless given; with clip, the step is shortened so that t
 // does not pass t_end (and set to zero once t_end is reached).

@@ -89,7 +89,9 @@ struct ScatterArgs {
 void launch_reset_scalars(DevScalars *sc, double dt_in, int n_real, hipStream_t st);
 void launch_rminmax(const double *r, const double *const x[3], int D, int n, DevScalars *sc, hipStream_t st);
 void launch_advance_time(DevScalars *sc, hipStream_t st);
-void launch_prep(const Soa &p, const DevCfg &cfg, DevScalars *sc, double *h, double *r, hipStream_t st);
+void launch_prep(const Soa &p, const DevCfg &cfg, DevScalars *sc, double *h, double *r, double *part,
+                 hipStream_t st);
+size_t prep_partial_words(int64_t n);
 void launch_dt(const DevCfg &cfg, DevScalars *sc, int clip_t_end, hipStream_t st);
 void launch_ghost_count(const Soa &p, const DevCfg &cfg, DevScalars *sc, uint32_t *gcnt, hipStream_t st);
 void launch_ghost_write(const Soa &p, const DevCfg &cfg, DevScalars *sc, const uint32_t *goff,
