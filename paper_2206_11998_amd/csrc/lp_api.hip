@@ -29,7 +29,7 @@ struct lp_ctx {
     std::string err;
     // workspace
     Buf h, r, gcnt, scan_tmp, ghosts, key, slot, tables, sorted, sortedf, sid, nbr, count, queue, partials, consout,
-        gfd_fields, hitd2, hitj, tflags, tlo, thi, prep_part;
+        gfd_fields, hitd2, hitj, tflags, tlo, thi, prep_part, ovfq;
     int search_mode = 0;            // 0: lane group per particle walking its cells, 1: LDS-staged tiles
     int solve_block = 256;
     DevScalars *sc = nullptr;       // device scalars
@@ -242,7 +242,7 @@ extern "C" lp_status lp_destroy(lp_ctx *c) {
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     Buf *bufs[] = {&c->h, &c->r, &c->gcnt, &c->scan_tmp, &c->ghosts, &c->key, &c->slot, &c->tables, &c->sorted,
                    &c->sortedf, &c->sid, &c->nbr, &c->count, &c->queue, &c->partials, &c->consout, &c->gfd_fields,
-                   &c->hitd2, &c->hitj, &c->tflags, &c->tlo, &c->thi, &c->prep_part};
+                   &c->hitd2, &c->hitj, &c->tflags, &c->tlo, &c->thi, &c->prep_part, &c->ovfq};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->sc) (void)hipFree(c->sc);
@@ -353,6 +353,7 @@ static lp_status ensure_capacity(lp_ctx *c, int64_t n_real, int64_t n_total, boo
     ENSURE(c, c->nbr, sizeof(int) * (size_t)c->dc.max_nb * nt);
     ENSURE(c, c->count, sizeof(int) * nt);
     ENSURE(c, c->queue, sizeof(int) * nt);
+    ENSURE(c, c->ovfq, sizeof(int) * nt);
     if (c->search_mode == 1) {
         ENSURE(c, c->hitd2, sizeof(double) * (size_t)c->dc.max_nb * nt);
         ENSURE(c, c->hitj, sizeof(int) * (size_t)c->dc.max_nb * nt);
@@ -377,7 +378,7 @@ static void run_search(lp_ctx *c, const Sorted &srt, int64_t n_total, int n_real
                             (int *)c->tlo.p, (int *)c->thi.p, &c->sc->n_tiles, st);
     else
         launch_search(srt, &c->sc->n_total, (int)n_total, n_real, (const uint32_t *)c->tables.p, c->grid, c->dc,
-                      (int *)c->nbr.p, ldn, (int *)c->count.p, c->sc, c->search_group, st);
+                      (int *)c->nbr.p, ldn, (int *)c->count.p, c->sc, c->search_group, (int *)c->ovfq.p, st);
 }
 
 static Sorted sorted_view(lp_ctx *c, bool state) {

@@ -28,6 +28,7 @@ __global__ void k_reset_scalars(DevScalars *sc, double dt_in, int n_real) {
     sc->n_ghost = 0;
     sc->max_count = 0;
     sc->n_fallback = 0;
+    sc->n_overflow = 0;
     sc->n_limited = 0ull;
     for (int a = 0; a < 3; ++a) { sc->xlo[a] = ~0ull; sc->xhi[a] = 0ull; }
 }

@@ -47,6 +47,7 @@ struct DevScalars {
     unsigned int error_bits;        // 1: capacity, 2: numeric
     unsigned int done;              // lp_run: t reached t_end
     int n_tiles;                    // search tiles of the last search
+    int n_overflow;                 // lists longer than the search kernel's LDS buffer
     unsigned long long xlo[3], xhi[3];  // bounding box of real particles (order-preserving keys)
     unsigned long long n_limited;
 };
@@ -109,7 +110,7 @@ void launch_scatter(const ScatterArgs &a, int n_real, const int *n_total_dev, in
 void launch_coarsen(uint32_t *tables, const DevGrid &g, int D, const int *n_total_dev, hipStream_t st);
 void launch_search(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real, const uint32_t *tables,
                    const DevGrid &g, const DevCfg &cfg, int *nbr, int ldn, int *count, DevScalars *sc,
-                   int group, hipStream_t st);
+                   int group, int *ovf_queue, hipStream_t st);
 void launch_search_tiles(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real,
                          const uint32_t *tables, const DevGrid &g, const DevCfg &cfg, double *hit_d2, int *hit_j,
                          int *nbr, int ldn, int *count, DevScalars *sc, const uint32_t *key, uint32_t *flags,

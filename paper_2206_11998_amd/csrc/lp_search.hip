@@ -12,26 +12,62 @@
 // reads it coalesced) holds cell-order indices; count[s] is the true count.
 #include "lp_internal.h"
 
+// Cells of level L that cover [x - r, x + r] per axis: first cell and count.
+template <int D>
+__device__ __forceinline__ void search_box(const DevGrid &g, const DevCfg &cfg, int L, const double xi[3], double ri,
+                                           int clo[3], int cn[3]) {
+    for (int a = 0; a < D; ++a) {
+        int n = g.nc[L][a];
+        double tl = (xi[a] - ri - g.lo[a]) * g.inv_s[L];
+        double th = (xi[a] + ri - g.lo[a]) * g.inv_s[L];
+        int lo = floor_clamped(tl - 1e-9), hi = floor_clamped(th + 1e-9);
+        if (cfg.periodic[a]) {
+            if (hi - lo + 1 >= n || hi < lo) { lo = 0; hi = n - 1; }
+        } else {
+            // particles outside the grid sit in its edge cells, so the
+            // clamped range still covers every candidate
+            lo = lo < 0 ? 0 : (lo > n - 1 ? n - 1 : lo);
+            hi = hi > n - 1 ? n - 1 : (hi < 0 ? 0 : hi);
+        }
+        clo[a] = lo;
+        cn[a] = hi - lo + 1;
+    }
+}
+
+// Morton code of the c-th cell of a search box (periodic axes wrapped).
+template <int D>
+__device__ __forceinline__ uint32_t cell_code(const DevGrid &g, const DevCfg &cfg, int L, const int clo[3],
+                                              const int cn[3], int c) {
+    int cc[3];
+    cc[0] = clo[0] + c % cn[0];
+    cc[1] = clo[1] + (c / cn[0]) % cn[1];
+    cc[2] = D == 3 ? clo[2] + c / (cn[0] * cn[1]) : 0;
+    for (int a = 0; a < D; ++a)
+        if (cfg.periodic[a]) {
+            int n = g.nc[L][a];
+            cc[a] = ((cc[a] % n) + n) % n;
+        }
+    return morton<D>(cc);
+}
+
 template <int D, int G>
 __global__ __launch_bounds__(LP_BLOCK) void k_search(Sorted srt, const int *n_total_dev, int n_real,
                                                      const uint32_t *tables, DevGrid g, DevCfg cfg, int *nbr, int ldn,
-                                                     int *count, DevScalars *sc) {
+                                                     int *count, DevScalars *sc, int lcap, int *ovf_queue) {
     constexpr int PPB = LP_BLOCK / G;
     extern __shared__ unsigned char smem[];
     const int max_nb = cfg.max_nb;
     double *ld2 = reinterpret_cast<double *>(smem);
-    int *lid = reinterpret_cast<int *>(ld2 + PPB * max_nb);
-    int *lj = lid + PPB * max_nb;
-    int *lcnt = lj + PPB * max_nb;
+    int *lj = reinterpret_cast<int *>(ld2 + PPB * lcap);
+    int *lcnt = lj + PPB * lcap;
 
     const int lane = threadIdx.x % G;
     const int grp = threadIdx.x / G;
-    const int s = blockIdx.x * PPB + grp;
+    const int s = xcd_remap(blockIdx.x, gridDim.x) * PPB + grp;
     const int n_total = *n_total_dev;
     const bool active = s < n_total && srt.id[s] < n_real;
-    double *gd2 = ld2 + grp * max_nb;
-    int *gid = lid + grp * max_nb;
-    int *gj = lj + grp * max_nb;
+    double *gd2 = ld2 + grp * lcap;
+    int *gj = lj + grp * lcap;
     if (lane == 0) lcnt[grp] = 0;
     __syncthreads();
 
@@ -42,34 +78,10 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search(Sorted srt, const int *n_to
         int L = level_for_radius(g, ri);
         const uint32_t *tab = tables + g.off[L];
         int clo[3] = {0, 0, 0}, cn[3] = {1, 1, 1};
-        for (int a = 0; a < D; ++a) {
-            int n = g.nc[L][a];
-            double tl = (xi[a] - ri - g.lo[a]) * g.inv_s[L];
-            double th = (xi[a] + ri - g.lo[a]) * g.inv_s[L];
-            int lo = floor_clamped(tl - 1e-9), hi = floor_clamped(th + 1e-9);
-            if (cfg.periodic[a]) {
-                if (hi - lo + 1 >= n || hi < lo) { lo = 0; hi = n - 1; }
-            } else {
-                // particles outside the grid sit in its edge cells, so the
-                // clamped range still covers every candidate
-                lo = lo < 0 ? 0 : (lo > n - 1 ? n - 1 : lo);
-                hi = hi > n - 1 ? n - 1 : (hi < 0 ? 0 : hi);
-            }
-            clo[a] = lo;
-            cn[a] = hi - lo + 1;
-        }
+        search_box<D>(g, cfg, L, xi, ri, clo, cn);
         const int ncells = cn[0] * cn[1] * (D == 3 ? cn[2] : 1);
         for (int c = lane; c < ncells; c += G) {
-            int cc[3];
-            cc[0] = clo[0] + c % cn[0];
-            cc[1] = clo[1] + (c / cn[0]) % cn[1];
-            cc[2] = D == 3 ? clo[2] + c / (cn[0] * cn[1]) : 0;
-            for (int a = 0; a < D; ++a)
-                if (cfg.periodic[a]) {
-                    int n = g.nc[L][a];
-                    cc[a] = ((cc[a] % n) + n) % n;
-                }
-            uint32_t code = morton<D>(cc);
+            uint32_t code = cell_code<D>(g, cfg, L, clo, cn, c);
             uint32_t b = tab[code], e = tab[code + 1];
             for (uint32_t j = b; j < e; ++j) {
                 if ((int)j == s) continue;
@@ -80,9 +92,8 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search(Sorted srt, const int *n_to
                 double d2 = dist2_exact<D>(dx);
                 if (d2 < r2) {
                     int slot = atomicAdd(&lcnt[grp], 1);
-                    if (slot < max_nb) {
+                    if (slot < lcap) {
                         gd2[slot] = d2;
-                        gid[slot] = srt.id[j];
                         gj[slot] = (int)j;
                     }
                 }
@@ -92,51 +103,116 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search(Sorted srt, const int *n_to
     __syncthreads();
     if (active) {
         int k = lcnt[grp];
-        int kk = k < max_nb ? k : max_nb;
         if (lane == 0) {
             count[s] = k;
             atomicMax(&sc->max_count, k);
             if (k > max_nb) atomicOr(&sc->error_bits, 1u);
+            // the list does not fit the LDS buffer: one wave redoes it (and
+            // for k > max_nb writes max_nb valid entries, so readers stay in bounds)
+            if (k > lcap) ovf_queue[atomicAdd(&sc->n_overflow, 1)] = s;
         }
-        for (int e = lane; e < kk; e += G) {
-            double de = gd2[e];
-            int ie = gid[e];
-            int rank = 0;
-            for (int f = 0; f < kk; ++f) {
-                double df = gd2[f];
-                int idf = gid[f];
-                rank += (df < de) || (df == de && idf < ie);
+        if (k <= lcap) {
+            for (int e = lane; e < k; e += G) {
+                double de = gd2[e];
+                int je = gj[e];
+                int rank = 0;
+                for (int f = 0; f < k; ++f) {
+                    double df = gd2[f];
+                    if (df < de) ++rank;
+                    else if (df == de && f != e && srt.id[gj[f]] < srt.id[je]) ++rank;  // exact tie: id order
+                }
+                nbr[ldn > 0 ? (int64_t)rank * ldn + s : (int64_t)s * (-ldn) + rank] = je;
             }
-            nbr[(int64_t)rank * ldn + s] = gj[e];
         }
     }
 }
 
-static size_t search_smem(int G, int max_nb) {
+// Lists longer than the LDS buffer of k_search: one wave per particle, a
+// buffer of max_nb entries.
+template <int D>
+__global__ __launch_bounds__(64) void k_search_overflow(Sorted srt, const uint32_t *tables, DevGrid g, DevCfg cfg,
+                                                         int *nbr, int ldn, DevScalars *sc, const int *ovf_queue) {
+    __shared__ double gd2[256];
+    __shared__ int gj[256];
+    __shared__ int lcnt;
+    const int lane = threadIdx.x;
+    const int nq = sc->n_overflow;
+    for (int w = blockIdx.x; w < nq; w += gridDim.x) {
+        const int s = ovf_queue[w];
+        if (lane == 0) lcnt = 0;
+        __syncthreads();
+        double xi[3] = {srt.x[0][s], srt.x[1][s], D == 3 ? srt.x[2][s] : 0.0};
+        double ri = srt.r[s];
+        double r2 = ri * ri;
+        int L = level_for_radius(g, ri);
+        const uint32_t *tab = tables + g.off[L];
+        int clo[3] = {0, 0, 0}, cn[3] = {1, 1, 1};
+        search_box<D>(g, cfg, L, xi, ri, clo, cn);
+        const int ncells = cn[0] * cn[1] * (D == 3 ? cn[2] : 1);
+        for (int c = lane; c < ncells; c += 64) {
+            uint32_t code = cell_code<D>(g, cfg, L, clo, cn, c);
+            uint32_t b = tab[code], e = tab[code + 1];
+            for (uint32_t j = b; j < e; ++j) {
+                if ((int)j == s) continue;
+                double dx[3];
+                dx[0] = min_image(cfg, 0, srt.x[0][j] - xi[0]);
+                dx[1] = min_image(cfg, 1, srt.x[1][j] - xi[1]);
+                dx[2] = D == 3 ? min_image(cfg, 2, srt.x[2][j] - xi[2]) : 0.0;
+                double d2 = dist2_exact<D>(dx);
+                if (d2 < r2) {
+                    int slot = atomicAdd(&lcnt, 1);
+                    if (slot < cfg.max_nb) {
+                        gd2[slot] = d2;
+                        gj[slot] = (int)j;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        int k = lcnt < cfg.max_nb ? lcnt : cfg.max_nb;
+        for (int e = lane; e < k; e += 64) {
+            double de = gd2[e];
+            int je = gj[e];
+            int rank = 0;
+            for (int f = 0; f < k; ++f) {
+                double df = gd2[f];
+                if (df < de) ++rank;
+                else if (df == de && f != e && srt.id[gj[f]] < srt.id[je]) ++rank;
+            }
+            nbr[ldn > 0 ? (int64_t)rank * ldn + s : (int64_t)s * (-ldn) + rank] = je;
+        }
+        __syncthreads();
+    }
+}
+
+static size_t search_smem(int G, int lcap) {
     int ppb = LP_BLOCK / G;
-    return (size_t)ppb * max_nb * (8 + 4 + 4) + (size_t)ppb * 4;
+    return (size_t)ppb * lcap * (8 + 4) + (size_t)ppb * 4;
 }
 
 template <int D, int G>
 static void launch_search_t(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real, const uint32_t *tables,
                             const DevGrid &g, const DevCfg &cfg, int *nbr, int ldn, int *count, DevScalars *sc,
-                            hipStream_t st) {
+                            int lcap, int *ovf_queue, hipStream_t st) {
     constexpr int PPB = LP_BLOCK / G;
     unsigned blocks = (unsigned)((n_total_cap + PPB - 1) / PPB);
     if (blocks < 1) blocks = 1;
-    size_t shm = search_smem(G, cfg.max_nb);
+    size_t shm = search_smem(G, lcap);
     hipLaunchKernelGGL((k_search<D, G>), dim3(blocks), dim3(LP_BLOCK), shm, st, s, n_total_dev, n_real, tables, g, cfg,
-                       nbr, ldn, count, sc);
+                       nbr, ldn, count, sc, lcap, ovf_queue);
+    unsigned ob = (unsigned)(n_total_cap < 1024 ? (n_total_cap > 0 ? n_total_cap : 1) : 1024);
+    hipLaunchKernelGGL(k_search_overflow<D>, dim3(ob), dim3(64), 0, st, s, tables, g, cfg, nbr, ldn, sc, ovf_queue);
 }
 
 void launch_search(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real, const uint32_t *tables,
                    const DevGrid &g, const DevCfg &cfg, int *nbr, int ldn, int *count, DevScalars *sc, int group,
-                   hipStream_t st) {
-    // LDS per block must stay within 64 KiB for the default launch
+                   int *ovf_queue, hipStream_t st) {
     int G = group;
     if (G != 4 && G != 8 && G != 16 && G != 32) G = 16;
-    while (search_smem(G, cfg.max_nb) > 65536 && G < 64) G *= 2;
-#define LS(DD, GG) launch_search_t<DD, GG>(s, n_total_dev, n_total_cap, n_real, tables, g, cfg, nbr, ldn, count, sc, st)
+    int lcap = cfg.max_nb < 128 ? cfg.max_nb : 128;
+    // LDS per block within 64 KiB
+    while (search_smem(G, lcap) > 65536 && G < 64) G *= 2;
+#define LS(DD, GG) launch_search_t<DD, GG>(s, n_total_dev, n_total_cap, n_real, tables, g, cfg, nbr, ldn, count, sc, lcap, ovf_queue, st)
     if (cfg.D == 3) {
         if (G == 4) LS(3, 4); else if (G == 8) LS(3, 8); else if (G == 16) LS(3, 16); else if (G == 32) LS(3, 32); else LS(3, 64);
     } else {

@@ -79,6 +79,15 @@ def test_neighbors_outside_box_and_anisotropic(lp, oracle_lib, mode):
     _nb_case(lp, oracle_lib, cfg, x, r, "mixed box", mode)
 
 
+@pytest.mark.parametrize("mode", SEARCH_MODES)
+def test_neighbors_long_lists(lp, oracle_lib, mode):
+    """Lists longer than the search kernel's LDS buffer (128) take the overflow path."""
+    cfg, st = W.uniform_box(3, 16, seed=8)
+    cfg["max_nb"] = 256
+    r = radii(cfg, st) * 1.75  # about 190 neighbours
+    _nb_case(lp, oracle_lib, cfg, st["x"], r, "long lists", mode)
+
+
 def test_neighbors_capacity(lp):
     cfg, st = W.uniform_box(2, 32)
     cfg["max_nb"] = 8
