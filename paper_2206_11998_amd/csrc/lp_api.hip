@@ -29,7 +29,7 @@ struct lp_ctx {
     std::string err;
     // workspace
     Buf h, r, gcnt, scan_tmp, ghosts, key, slot, tables, sorted, sortedf, sid, nbr, count, queue, partials, consout,
-        gfd_fields, hitd2, hitj, tflags, tlo, thi, prep_part, ovfq;
+        gfd_fields, hitd2, hitj, tflags, tlo, thi, prep_part, ovfq, der, lwst;
     int search_mode = 0;            // 0: lane group per particle walking its cells, 1: LDS-staged tiles
     int solve_block = 256;
     DevScalars *sc = nullptr;       // device scalars
@@ -242,7 +242,7 @@ extern "C" lp_status lp_destroy(lp_ctx *c) {
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     Buf *bufs[] = {&c->h, &c->r, &c->gcnt, &c->scan_tmp, &c->ghosts, &c->key, &c->slot, &c->tables, &c->sorted,
                    &c->sortedf, &c->sid, &c->nbr, &c->count, &c->queue, &c->partials, &c->consout, &c->gfd_fields,
-                   &c->hitd2, &c->hitj, &c->tflags, &c->tlo, &c->thi, &c->prep_part, &c->ovfq};
+                   &c->hitd2, &c->hitj, &c->tflags, &c->tlo, &c->thi, &c->prep_part, &c->ovfq, &c->der, &c->lwst};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->sc) (void)hipFree(c->sc);
@@ -354,6 +354,10 @@ static lp_status ensure_capacity(lp_ctx *c, int64_t n_real, int64_t n_total, boo
     ENSURE(c, c->count, sizeof(int) * nt);
     ENSURE(c, c->queue, sizeof(int) * nt);
     ENSURE(c, c->ovfq, sizeof(int) * nt);
+    if (state) {
+        ENSURE(c, c->der, sizeof(double) * (size_t)der_count(D) * nt);
+        ENSURE(c, c->lwst, (size_t)nt);
+    }
     if (c->search_mode == 1) {
         ENSURE(c, c->hitd2, sizeof(double) * (size_t)c->dc.max_nb * nt);
         ENSURE(c, c->hitj, sizeof(int) * (size_t)c->dc.max_nb * nt);
@@ -531,7 +535,8 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
     stage_mark(c, st, 2, false);
     stage_mark(c, st, 3, true);
     launch_solve(srt, soa, (const int *)c->nbr.p, ldn, (const int *)c->count.p, &c->sc->n_total, (int)n_total, n,
-                 c->dc, c->sc, (int *)c->queue.p, c->solve_block, st);
+                 c->dc, c->sc, (int *)c->queue.p, (double *)c->der.p, c->cap_total, (uint8_t *)c->lwst.p,
+                 c->solve_block, st);
     stage_mark(c, st, 3, false);
     stage_mark(c, st, 4, true);
     launch_solve_fallback(srt, soa, (const int *)c->nbr.p, ldn, (const int *)c->count.p, n, c->dc, c->sc,

@@ -117,9 +117,10 @@ void launch_search_tiles(const Sorted &s, const int *n_total_dev, int n_total_ca
                          uint32_t *scan_tmp, int *tile_lo, int *tile_hi, int *ntiles_dev, hipStream_t st);
 void launch_lists_out(const int *sorted_id, const int *nbr, int ldn, const int *count, int n, int max_nb,
                       int *count_out, int *idx_out, hipStream_t st);
+int der_count(int D);
 void launch_solve(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count, const int *n_total_dev,
-                  int n_total_cap, int n_real, const DevCfg &cfg, DevScalars *sc, int *queue, int block,
-                  hipStream_t st);
+                  int n_total_cap, int n_real, const DevCfg &cfg, DevScalars *sc, int *queue, double *der,
+                  int64_t ld, uint8_t *lwst, int block, hipStream_t st);
 void launch_solve_fallback(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count,
                            int n_real, const DevCfg &cfg, DevScalars *sc, const int *queue, int queue_cap,
                            hipStream_t st);

@@ -3,14 +3,17 @@
 // limiter, blended upwind / Lax-Wendroff update, EOS and particle mover
 // (Sec. 2.1; Sec. 2.2 steps 5-6).
 //
-// Fast path (k_solve): one thread per particle.  The second-order fit is solved
+// Fast path (k_lw_fit + k_finish): one thread per particle.  The second-order fit is solved
 // through the R factor of its QR decomposition obtained from the Cholesky
 // factor of the normal matrix (R^T R = A^T A) -- the rows of the scaled
 // stencil matrix stream through registers once, so the whole fit costs one
 // pass over the neighbour list, with no cross-lane traffic and no scratch
 // memory.  A condition estimate ||R||_F^2 ||R^-1||_F^2 of the normal matrix
 // routes every stencil for which this is not accurate to the FP64
-// pivoted-Householder path.
+// pivoted-Householder path.  The fit writes its derivatives to a SoA array and
+// a second kernel (k_finish) does the half-ball fits, the estimator and the
+// update; splitting keeps each kernel's register count low enough for two to
+// four waves per SIMD.
 //
 // Fallback (k_solve_fallback): one wave per particle, one stencil row per lane;
 // Householder QR with column pivoting (the paper's solver) with all column
@@ -207,6 +210,82 @@ __device__ __forceinline__ T halfball_cond(const T G[D * (D + 1) / 2]) {
         if (!(s3 > T(0))) return T(INFINITY);
         return sqrt(gpp / s3);
     }
+}
+
+
+// ---------------------------------------------------------------------------
+// Moments.  Every entry of the normal matrix A^T A of the second-order basis
+// (xi_a, xi_a^2 / 2, xi_a xi_b) is c_p c_q sum_j xi_j^(alpha_p + alpha_q), a
+// moment of degree 2..4 of the scaled offsets: 31 distinct moments in 3D
+// (12 in 2D) instead of 45 (15) matrix entries, so the fit loop keeps fewer
+// accumulators live.
+// ---------------------------------------------------------------------------
+template <int D> struct Mom;
+template <> struct Mom<3> {
+    static constexpr int N = 31;
+    static constexpr int E[N][3] = {
+        {2, 0, 0}, {0, 2, 0}, {0, 0, 2}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1},
+        {3, 0, 0}, {0, 3, 0}, {0, 0, 3}, {2, 1, 0}, {2, 0, 1}, {1, 2, 0}, {0, 2, 1}, {1, 0, 2}, {0, 1, 2}, {1, 1, 1},
+        {4, 0, 0}, {0, 4, 0}, {0, 0, 4}, {3, 1, 0}, {3, 0, 1}, {1, 3, 0}, {0, 3, 1}, {1, 0, 3}, {0, 1, 3},
+        {2, 2, 0}, {2, 0, 2}, {0, 2, 2}, {2, 1, 1}, {1, 2, 1}, {1, 1, 2}};
+};
+template <> struct Mom<2> {
+    static constexpr int N = 12;
+    static constexpr int E[N][3] = {{2, 0, 0}, {0, 2, 0}, {1, 1, 0}, {3, 0, 0}, {0, 3, 0}, {2, 1, 0},
+                                    {1, 2, 0}, {4, 0, 0}, {0, 4, 0}, {3, 1, 0}, {1, 3, 0}, {2, 2, 0}};
+};
+
+// exponents of basis function p (0..NU-1) in the column order of second_order_row
+template <int D>
+__host__ __device__ constexpr int basis_exp(int p, int a) {
+    return p < D ? (p == a ? 1 : 0)
+         : p < 2 * D ? (p - D == a ? 2 : 0)
+         : D == 2 ? 1
+         : (p == 2 * D ? (a != 2 ? 1 : 0) : p == 2 * D + 1 ? (a != 1 ? 1 : 0) : (a != 0 ? 1 : 0));
+}
+template <int D>
+__host__ __device__ constexpr double basis_coef(int p) { return (p >= D && p < 2 * D) ? 0.5 : 1.0; }
+template <int D>
+__host__ __device__ constexpr int mom_index(int e0, int e1, int e2) {
+    for (int m = 0; m < Mom<D>::N; ++m)
+        if (Mom<D>::E[m][0] == e0 && Mom<D>::E[m][1] == e1 && Mom<D>::E[m][2] == e2) return m;
+    return -1;
+}
+template <int D>
+__host__ __device__ constexpr int gram_mom(int p, int q) {
+    return mom_index<D>(basis_exp<D>(p, 0) + basis_exp<D>(q, 0), basis_exp<D>(p, 1) + basis_exp<D>(q, 1),
+                        D == 3 ? basis_exp<D>(p, 2) + basis_exp<D>(q, 2) : 0);
+}
+
+// add the moments of one scaled offset x
+template <int D, typename T>
+__device__ __forceinline__ void add_moments(const T x[3], T M[Mom<D>::N]) {
+    T px[5], py[5], pz[5];
+    px[0] = T(1); py[0] = T(1); pz[0] = T(1);
+#pragma unroll
+    for (int e = 1; e < 5; ++e) {
+        px[e] = px[e - 1] * x[0];
+        py[e] = py[e - 1] * x[1];
+        pz[e] = D == 3 ? pz[e - 1] * x[2] : T(0);
+    }
+#pragma unroll
+    for (int m = 0; m < Mom<D>::N; ++m) {
+        constexpr int dummy = 0;
+        (void)dummy;
+        const int e0 = Mom<D>::E[m][0], e1 = Mom<D>::E[m][1], e2 = Mom<D>::E[m][2];
+        T v = px[e0] * py[e1];
+        if (D == 3 && e2) v *= pz[e2];
+        M[m] += v;
+    }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void gram_from_moments(const T M[Mom<D>::N], T G[Dim<D>::NG]) {
+    constexpr int NU = Dim<D>::NU;
+#pragma unroll
+    for (int p = 0; p < NU; ++p)
+#pragma unroll
+        for (int q = p; q < NU; ++q) G[tri(p, q, NU)] = T(basis_coef<D>(p) * basis_coef<D>(q)) * M[gram_mom<D>(p, q)];
 }
 
 // ---------------------------------------------------------------------------
@@ -485,13 +564,62 @@ __device__ __forceinline__ void finish_particle(const Sorted &srt, const Soa &p,
     if (phi < 1.0) atomicAdd(&sc->n_limited, 1ull);
 }
 
+
+// ---------------------------------------------------------------------------
+// Second-order derivatives kept between the fit and the update kernels
+// (SoA, der[q * ld + s]): gradients of V, u_1..u_D, P (D each), the Hessians
+// of u_1..u_D (NS each) and the diagonal second derivatives of P (D).
+// ---------------------------------------------------------------------------
+template <int D> struct Der { static constexpr int N = (D + 2) * D + D * Dim<D>::NS + D; };
+
+template <int D>
+__device__ __forceinline__ void store_der(double *der, int64_t ld, int s, const double grad[Dim<D>::NF][3],
+                                          const double hess[Dim<D>::NF][Dim<D>::NS]) {
+    constexpr int NF = Dim<D>::NF, NS = Dim<D>::NS;
+    int q = 0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int a = 0; a < D; ++a) der[(q++) * ld + s] = grad[f][a];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int c = 0; c < NS; ++c) der[(q++) * ld + s] = hess[1 + k][c];
+#pragma unroll
+    for (int a = 0; a < D; ++a) der[(q++) * ld + s] = hess[D + 1][a];
+}
+
+template <int D>
+__device__ __forceinline__ void load_der(const double *der, int64_t ld, int s, double grad[Dim<D>::NF][3],
+                                         double hess[Dim<D>::NF][Dim<D>::NS]) {
+    constexpr int NF = Dim<D>::NF, NS = Dim<D>::NS;
+    int q = 0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) grad[f][a] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NS; ++c) hess[f][c] = 0.0;
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int a = 0; a < D; ++a) grad[f][a] = der[(q++) * ld + s];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int c = 0; c < NS; ++c) hess[1 + k][c] = der[(q++) * ld + s];
+#pragma unroll
+    for (int a = 0; a < D; ++a) hess[D + 1][a] = der[(q++) * ld + s];
+}
+
 // ---------------------------------------------------------------------------
 // Fast path: one thread per particle.
 // ---------------------------------------------------------------------------
 template <int D, typename T, bool REFINE>
-__global__ __launch_bounds__(LP_BLOCK) void k_solve(Sorted srt, Soa p, const int *nbr, int ldn, const int *count,
-                                                    const int *n_total_dev, int n_real, DevCfg cfg, DevScalars *sc,
-                                                    int *queue) {
+__global__ __launch_bounds__(LP_BLOCK, 2) void k_lw_fit(Sorted srt, const int *nbr, int ldn, const int *count,
+                                                     const int *n_total_dev, int n_real, DevCfg cfg, DevScalars *sc,
+                                                     int *queue, double *der, int64_t ld, uint8_t *lwst) {
     constexpr int NU = Dim<D>::NU, NF = Dim<D>::NF, NG = Dim<D>::NG, NS = Dim<D>::NS, FP = D + 1;
     const bool use_f = sizeof(T) == 4;
     int s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -520,10 +648,11 @@ __global__ __launch_bounds__(LP_BLOCK) void k_solve(Sorted srt, Soa p, const int
 #pragma unroll
         for (int f = 0; f < NF; ++f) fi[f] = (T)st[f];
     }
-    // normal equations of the scaled second-order system over the LW stencil
-    T G[NG], B[NF * NU];
+    // normal equations of the scaled second-order system over the LW stencil:
+    // moments of the offsets (the normal matrix) and A^T b
+    T M[Mom<D>::N], B[NF * NU];
 #pragma unroll
-    for (int q = 0; q < NG; ++q) G[q] = 0;
+    for (int q = 0; q < Mom<D>::N; ++q) M[q] = 0;
 #pragma unroll
     for (int q = 0; q < NF * NU; ++q) B[q] = 0;
     int m = 0;
@@ -531,6 +660,7 @@ __global__ __launch_bounds__(LP_BLOCK) void k_solve(Sorted srt, Soa p, const int
         T x[3];
 #pragma unroll
         for (int a = 0; a < D; ++a) x[a] = (T)(dx[a] * inv_r);
+        add_moments<D, T>(x, M);
         T row[NU];
         second_order_row<D, T>(x, row);
         T fj[NF];
@@ -546,10 +676,6 @@ __global__ __launch_bounds__(LP_BLOCK) void k_solve(Sorted srt, Soa p, const int
             fj[FP] = (T)srt.P[j];
         }
 #pragma unroll
-        for (int pp = 0; pp < NU; ++pp)
-#pragma unroll
-            for (int qq = pp; qq < NU; ++qq) G[tri(pp, qq, NU)] += row[pp] * row[qq];
-#pragma unroll
         for (int f = 0; f < NF; ++f) {
             T b = fj[f] - fi[f];
 #pragma unroll
@@ -557,26 +683,24 @@ __global__ __launch_bounds__(LP_BLOCK) void k_solve(Sorted srt, Soa p, const int
         }
         ++m;
     });
+    T G[NG];
+    gram_from_moments<D, T>(M, G);
     T inv[NU];
     bool good = m >= NU && cholesky<NU, T>(G, inv);
     if (good) good = cond_estimate<NU, T>(G, inv) <= (T)cfg.cond_fb;
     if (!good) {
         int slot = atomicAdd(&sc->n_fallback, 1);
         queue[slot] = s;
+        lwst[s] = 1;
         return;
     }
-    double Y[NF * NU];
-    {
-        T Bs[NF * NU];
-#pragma unroll
-        for (int q = 0; q < NF * NU; ++q) Bs[q] = B[q];
-        chol_solve<NU, NF, T, T>(G, inv, Bs);
-#pragma unroll
-        for (int q = 0; q < NF * NU; ++q) Y[q] = (double)Bs[q];
-    }
+    lwst[s] = 0;
+    // B <- (R^T R)^-1 B in place: the scaled coefficients of every field
+    chol_solve<NU, NF, T, T>(G, inv, B);
+    double grad[NF][3], hess[NF][NS];
     if (REFINE) {
-        // one refinement step: FP64 residual of the FP64 system, correction
-        // through the same factor
+        // one refinement step: the residual of the FP64 system at the FP32
+        // solution (promoted exactly), corrected through the same factor
         double Ar[NF * NU];
 #pragma unroll
         for (int q = 0; q < NF * NU; ++q) Ar[q] = 0.0;
@@ -595,40 +719,79 @@ __global__ __launch_bounds__(LP_BLOCK) void k_solve(Sorted srt, Soa p, const int
             for (int f = 0; f < NF; ++f) {
                 double res = fj[f] - st[f];
 #pragma unroll
-                for (int pp = 0; pp < NU; ++pp) res -= row[pp] * Y[f * NU + pp];
+                for (int pp = 0; pp < NU; ++pp) res -= row[pp] * (double)B[f * NU + pp];
 #pragma unroll
                 for (int pp = 0; pp < NU; ++pp) Ar[f * NU + pp] += row[pp] * res;
             }
         });
         chol_solve<NU, NF, T, double>(G, inv, Ar);
 #pragma unroll
-        for (int q = 0; q < NF * NU; ++q) Y[q] += Ar[q];
+        for (int f = 0; f < NF; ++f) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) grad[f][a] = a < D ? ((double)B[f * NU + a] + Ar[f * NU + a]) * inv_r : 0.0;
+#pragma unroll
+            for (int q = 0; q < NS; ++q)
+                hess[f][q] = ((double)B[f * NU + D + q] + Ar[f * NU + D + q]) * inv_r * inv_r;
+        }
+    } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) grad[f][a] = a < D ? (double)B[f * NU + a] * inv_r : 0.0;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) hess[f][q] = (double)B[f * NU + D + q] * inv_r * inv_r;
+        }
     }
+    store_der<D>(der, ld, s, grad, hess);
+    (void)i;
+    (void)dt;
+    (void)h;
+}
+
+// Half-ball fits, estimator, blended update and mover for every particle
+// whose second-order fit the fast path solved.
+template <int D, typename T>
+__global__ __launch_bounds__(LP_BLOCK) void k_finish(Sorted srt, Soa p, const int *nbr, int ldn, const int *count,
+                                                     const int *n_total_dev, int n_real, DevCfg cfg, DevScalars *sc,
+                                                     const double *der, int64_t ld, const uint8_t *lwst) {
+    constexpr int NF = Dim<D>::NF, NS = Dim<D>::NS, FP = D + 1;
+    int s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (s >= *n_total_dev) return;
+    int i = srt.id[s];
+    if (i >= n_real || lwst[s] != 0) return;
+    int k = count[s];
+    if (k > cfg.max_nb) k = cfg.max_nb;
+    double xi[3] = {srt.x[0][s], srt.x[1][s], D == 3 ? srt.x[2][s] : 0.0};
+    double st[NF];
+    st[0] = srt.V[s];
+#pragma unroll
+    for (int a = 0; a < D; ++a) st[1 + a] = srt.u[a][s];
+    st[FP] = srt.P[s];
+    const double h = srt.h[s];
+    const double r = cfg.kappa * h;
     double grad[NF][3], hess[NF][NS];
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) grad[f][a] = a < D ? Y[f * NU + a] * inv_r : 0.0;
-#pragma unroll
-        for (int q = 0; q < NS; ++q) hess[f][q] = Y[f * NU + D + q] * inv_r * inv_r;
-    }
-    finish_particle<D, T>(srt, p, cfg, sc, nbr, ldn, s, i, k, dt, xi, st, h, r, grad, hess, 0, 0);
+    load_der<D>(der, ld, s, grad, hess);
+    finish_particle<D, T>(srt, p, cfg, sc, nbr, ldn, s, i, k, sc->dt, xi, st, h, r, grad, hess, 0, 0);
 }
 
 template <int D, typename T, bool RF>
 static void launch_solve_t(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count,
                            const int *n_total_dev, int n_total_cap, int n_real, const DevCfg &cfg, DevScalars *sc,
-                           int *queue, int block, hipStream_t st) {
+                           int *queue, double *der, int64_t ld, uint8_t *lwst, int block, hipStream_t st) {
     unsigned blocks = (unsigned)((n_total_cap + block - 1) / block);
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((k_solve<D, T, RF>), dim3(blocks), dim3(block), 0, st, s, p, nbr, ldn, count, n_total_dev,
-                       n_real, cfg, sc, queue);
+    hipLaunchKernelGGL((k_lw_fit<D, T, RF>), dim3(blocks), dim3(block), 0, st, s, nbr, ldn, count, n_total_dev, n_real,
+                       cfg, sc, queue, der, ld, lwst);
+    hipLaunchKernelGGL((k_finish<D, T>), dim3(blocks), dim3(block), 0, st, s, p, nbr, ldn, count, n_total_dev, n_real,
+                       cfg, sc, der, ld, lwst);
 }
 
+int der_count(int D) { return D == 3 ? Der<3>::N : Der<2>::N; }
+
 void launch_solve(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count, const int *n_total_dev,
-                  int n_total_cap, int n_real, const DevCfg &cfg, DevScalars *sc, int *queue, int block,
-                  hipStream_t st) {
-#define LSV(DD, TT, RR) launch_solve_t<DD, TT, RR>(s, p, nbr, ldn, count, n_total_dev, n_total_cap, n_real, cfg, sc, queue, block, st)
+                  int n_total_cap, int n_real, const DevCfg &cfg, DevScalars *sc, int *queue, double *der,
+                  int64_t ld, uint8_t *lwst, int block, hipStream_t st) {
+#define LSV(DD, TT, RR) launch_solve_t<DD, TT, RR>(s, p, nbr, ldn, count, n_total_dev, n_total_cap, n_real, cfg, sc, queue, der, ld, lwst, block, st)
     bool mixed = cfg.precision == LP_MIXED;
     if (cfg.D == 3) {
         if (!mixed) LSV(3, double, false);
