@@ -26,16 +26,26 @@ PEAK_ALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FP64, 
 PEAK_HBM_GBS = 8000.0
 
 
-def flops_per_particle(k_lw, dim=3):
-    """Algorithmic flops of one particle update at LW stencil size k_lw:
-    second-order fit 20k + 2kn^2 - 2n^3/3 + R(4kn - 2n^2) + Rn^2 (n unknowns,
-    R right-hand sides), half-ball fits and the rest (rates, estimator, mover)."""
-    if dim == 3:
-        n, R, uw, rest = 9, 5, 2800.0, 300.0
-    else:
-        n, R, uw, rest = 5, 4, 1200.0, 300.0
+def fit_flops(k_lw, dim=3):
+    """Algorithmic flops of one particle's second-order least-squares fit over a
+    stencil of k_lw rows: row assembly 20k, Householder factorisation
+    2kn^2 - 2n^3/3 and R right-hand sides R(4kn - 2n^2) + Rn^2 (n unknowns)."""
+    n, R = (9, 5) if dim == 3 else (5, 4)
     k = np.asarray(k_lw, dtype=np.float64)
-    return 20 * k + 2 * k * n * n - 2.0 * n ** 3 / 3 + R * (4 * k * n - 2 * n * n) + R * n * n + uw + rest
+    return 20 * k + 2 * k * n * n - 2.0 * n ** 3 / 3 + R * (4 * k * n - 2 * n * n) + R * n * n
+
+
+def update_flops(dim=3):
+    """Half-ball fits (2D fits of 8 rows, D unknowns, 3 right-hand sides) plus
+    estimator, rates, blend and mover."""
+    return (2800.0 if dim == 3 else 1200.0) + 300.0
+
+
+def search_bytes(count):
+    """Algorithmic HBM bytes of the neighbour search: read position, radius and
+    id of every particle once (36 B), write its list and count (4k + 4 B)."""
+    k = np.asarray(count, dtype=np.float64)
+    return 40.0 + 4.0 * k
 
 
 def main():
@@ -44,7 +54,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=2_097_152)
-    ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
+    ap.add_argument("--precision", choices=["both", "all", "mixed", "fp64", "fp32"], default="both",
+                    help="mixed: FP32 fits + one FP64-residual refinement; fp32: mixed without the refinement; "
+                         "both: mixed then fp64; all: mixed, fp64, fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sample", type=int, default=0, help="particles in the CPU-reference sample (0: all)")
     ap.add_argument("--search-mode", type=int, default=None, help="override the neighbour-search mode (0/1)")
@@ -84,7 +96,7 @@ def main():
     sample = (np.arange(n) if args.sample <= 0 or args.sample >= n
               else np.sort(rng.choice(n, size=args.sample, replace=False)))
 
-    precisions = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
+    precisions = {"both": ["mixed", "fp64"], "all": ["mixed", "fp64", "fp32"]}.get(args.precision, [args.precision])
     results = {}
     first_step = {}
     def tuned(ctx):
@@ -97,7 +109,7 @@ def main():
         return ctx
 
     for prec in precisions:
-        ctx = tuned(lp.Context(cfg, precision=prec))
+        ctx = tuned(lp.Context(cfg, precision="fp64" if prec == "fp64" else "mixed", refine=prec != "fp32"))
         # one step from the initial state for the accuracy check
         dev = lp.state_to_device(st)
         ctx.step(dev)
@@ -128,15 +140,16 @@ def main():
         del dev
         ctx.close()
 
-    # LW stencil sizes for the algorithmic flop count (state at the start of the timed run)
+    # stencil sizes for the algorithmic work (state at the start of the timed run)
     ctx = lp.Context(cfg)
     d = lp.state_to_device(st)
     h = (st["m"] * st["V"]) ** (1.0 / 3.0)
     r = torch.from_numpy(cfg["kappa"] * h).cuda()
     count, _, _ = ctx.neighbors(d["x"], r)
-    cap = 54
-    k_lw = np.minimum(count.cpu().numpy(), cap)
-    flops_launch = float(flops_per_particle(k_lw).sum())
+    count = count.cpu().numpy()
+    k_lw = np.minimum(count, 54)
+    work = {"search": float(search_bytes(count).sum()), "fit": float(fit_flops(k_lw).sum()),
+            "update": float(update_flops() * n)}
     ctx.close()
     del d
 
@@ -169,13 +182,31 @@ def main():
     except Exception as exc:  # the reference is optional on hosts without gcc
         log("cpu reference unavailable:", repr(exc))
 
+    def kernel_rooflines(prof):
+        out = {}
+        for name, bound in (("search", "hbm"), ("fit", "alu"), ("update", "alu")):
+            ms, cnt = prof[name]
+            avg = ms / max(cnt, 1)
+            if bound == "hbm":
+                achieved = work[name] / (avg * 1e-3) / 1e9 if avg > 0 else None
+                peak, unit, per = PEAK_HBM_GBS, "GB/s", "algorithmic_bytes_per_launch"
+            else:
+                achieved = work[name] / (avg * 1e-3) / 1e12 if avg > 0 else None
+                peak, unit, per = PEAK_ALU_TFLOPS, "TFLOP/s", "algorithmic_flops_per_launch"
+            out[name] = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                         "frac": achieved / peak if achieved else None, "traffic": None, per: work[name],
+                         "avg_launch_ms": avg}
+        return out
+
     main_prec = precisions[0]
     res = results[main_prec]
     ms_step = 1e3 * res["elapsed"] / args.steps
     value = n * args.steps / res["elapsed"]
-    solve_ms, solve_cnt = res["prof"]["solve"]
-    solve_avg = solve_ms / max(solve_cnt, 1)
-    achieved = flops_launch / (solve_avg * 1e-3) / 1e12 if solve_avg > 0 else None
+    kr = kernel_rooflines(res["prof"])
+    dominant = max(kr, key=lambda k: kr[k]["avg_launch_ms"])
+    top = dict(kr[dominant])
+    top["kernel"] = {"search": "k_search (neighbour lists)", "fit": "k_lw_fit (second-order fits)",
+                     "update": "k_finish (half-ball fits, estimator, update, mover)"}[dominant]
     out = {
         "metric": METRIC,
         "value": value,
@@ -191,23 +222,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": "vacuum3d: %d equal-mass particles rejection-sampled from rho=exp(-r^2/0.05) "
                                "in the ball rho>=1/512, p=rho^1.4, kappa 2.2, CFL 0.2, free boundary" % n,
-                   "n_particles": n, "precision": main_prec},
-        "roofline": {"bound": "alu", "kernel": "k_solve (fused fit + update)", "achieved": achieved,
-                     "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_ALU_TFLOPS if achieved else None, "traffic": None,
-                     "algorithmic_flops_per_launch": flops_launch, "avg_launch_ms": solve_avg,
-                     "mean_lw_stencil": float(k_lw.mean())},
+                   "n_particles": n, "precision": main_prec, "mean_lw_stencil": float(k_lw.mean())},
+        "roofline": top,
+        "kernels": kr,
         "cpu_baseline": cpu,
         "stages_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in res["prof"].items()},
         "l1_vs_oracle": l1,
     }
     for prec in precisions[1:]:
         r2 = results[prec]
-        s2 = r2["prof"]["solve"]
-        avg2 = s2[0] / max(s2[1], 1)
         out[prec] = {"value": n * args.steps / r2["elapsed"], "ms_per_step": 1e3 * r2["elapsed"] / args.steps,
-                     "solve_avg_ms": avg2,
-                     "solve_tflops": flops_launch / (avg2 * 1e-3) / 1e12 if avg2 > 0 else None,
+                     "kernels": kernel_rooflines(r2["prof"]),
                      "stages_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in r2["prof"].items()}}
     print(json.dumps(out))
 

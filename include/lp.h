@@ -171,8 +171,9 @@ lp_status lp_set_time(struct lp_ctx *ctx, void *stream, double t);
  * and writes, per stage, the summed milliseconds ms[q] and the number of
  * timed launches count[q] (host arrays of LP_NSTAGES entries), then clears.
  * Stages: 0 radii/dt/ghosts, 1 cell ordering, 2 neighbour search,
- * 3 fused solver (fast path), 4 FP64 pivoted-QR fallback. */
-#define LP_NSTAGES 5
+ * 3 second-order fits (fast path), 4 half-ball fits + estimator + update +
+ * mover, 5 FP64 pivoted-QR fallback. */
+#define LP_NSTAGES 6
 
 /* Launch-shape parameters (results are identical for every setting; only the
  * speed changes).  Chosen by lp_autotune() or set explicitly: */

@@ -534,14 +534,20 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
     run_search(c, srt, n_total, n, st);
     stage_mark(c, st, 2, false);
     stage_mark(c, st, 3, true);
+    struct Between { lp_ctx *c; hipStream_t st; } bt{c, st};
+    auto between = [](void *a) {
+        Between *b = (Between *)a;
+        stage_mark(b->c, b->st, 3, false);
+        stage_mark(b->c, b->st, 4, true);
+    };
     launch_solve(srt, soa, (const int *)c->nbr.p, ldn, (const int *)c->count.p, &c->sc->n_total, (int)n_total, n,
                  c->dc, c->sc, (int *)c->queue.p, (double *)c->der.p, c->cap_total, (uint8_t *)c->lwst.p,
-                 c->solve_block, st);
-    stage_mark(c, st, 3, false);
-    stage_mark(c, st, 4, true);
+                 c->solve_block, +between, &bt, st);
+    stage_mark(c, st, 4, false);
+    stage_mark(c, st, 5, true);
     launch_solve_fallback(srt, soa, (const int *)c->nbr.p, ldn, (const int *)c->count.p, n, c->dc, c->sc,
                           (const int *)c->queue.p, n, st);
-    stage_mark(c, st, 4, false);
+    stage_mark(c, st, 5, false);
     launch_advance_time(c->sc, st);
     HIPCHK(c, hipGetLastError());
     return LP_OK;

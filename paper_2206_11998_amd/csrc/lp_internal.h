@@ -120,7 +120,8 @@ void launch_lists_out(const int *sorted_id, const int *nbr, int ldn, const int *
 int der_count(int D);
 void launch_solve(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count, const int *n_total_dev,
                   int n_total_cap, int n_real, const DevCfg &cfg, DevScalars *sc, int *queue, double *der,
-                  int64_t ld, uint8_t *lwst, int block, hipStream_t st);
+                  int64_t ld, uint8_t *lwst, int block, void (*between)(void *), void *between_arg,
+                  hipStream_t st);
 void launch_solve_fallback(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count,
                            int n_real, const DevCfg &cfg, DevScalars *sc, const int *queue, int queue_cap,
                            hipStream_t st);

@@ -777,11 +777,13 @@ __global__ __launch_bounds__(LP_BLOCK) void k_finish(Sorted srt, Soa p, const in
 template <int D, typename T, bool RF>
 static void launch_solve_t(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count,
                            const int *n_total_dev, int n_total_cap, int n_real, const DevCfg &cfg, DevScalars *sc,
-                           int *queue, double *der, int64_t ld, uint8_t *lwst, int block, hipStream_t st) {
+                           int *queue, double *der, int64_t ld, uint8_t *lwst, int block, void (*between)(void *),
+                           void *between_arg, hipStream_t st) {
     unsigned blocks = (unsigned)((n_total_cap + block - 1) / block);
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL((k_lw_fit<D, T, RF>), dim3(blocks), dim3(block), 0, st, s, nbr, ldn, count, n_total_dev, n_real,
                        cfg, sc, queue, der, ld, lwst);
+    if (between) between(between_arg);
     hipLaunchKernelGGL((k_finish<D, T>), dim3(blocks), dim3(block), 0, st, s, p, nbr, ldn, count, n_total_dev, n_real,
                        cfg, sc, der, ld, lwst);
 }
@@ -790,8 +792,9 @@ int der_count(int D) { return D == 3 ? Der<3>::N : Der<2>::N; }
 
 void launch_solve(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count, const int *n_total_dev,
                   int n_total_cap, int n_real, const DevCfg &cfg, DevScalars *sc, int *queue, double *der,
-                  int64_t ld, uint8_t *lwst, int block, hipStream_t st) {
-#define LSV(DD, TT, RR) launch_solve_t<DD, TT, RR>(s, p, nbr, ldn, count, n_total_dev, n_total_cap, n_real, cfg, sc, queue, der, ld, lwst, block, st)
+                  int64_t ld, uint8_t *lwst, int block, void (*between)(void *), void *between_arg,
+                  hipStream_t st) {
+#define LSV(DD, TT, RR) launch_solve_t<DD, TT, RR>(s, p, nbr, ldn, count, n_total_dev, n_total_cap, n_real, cfg, sc, queue, der, ld, lwst, block, between, between_arg, st)
     bool mixed = cfg.precision == LP_MIXED;
     if (cfg.D == 3) {
         if (!mixed) LSV(3, double, false);

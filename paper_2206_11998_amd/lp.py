@@ -23,7 +23,7 @@ EXPORTS = ["lp_config_default", "lp_create", "lp_destroy", "lp_neighbors", "lp_g
            "lp_conservation", "lp_check", "lp_get_info", "lp_set_time", "lp_profile", "lp_profile_read",
            "lp_set_tuning", "lp_get_tuning", "lp_status_str", "lp_last_error"]
 TUNE_SEARCH_MODE, TUNE_SEARCH_GROUP, TUNE_SOLVE_BLOCK = 0, 1, 2
-STAGES = ["prep", "cells", "search", "solve", "fallback"]
+STAGES = ["prep", "cells", "search", "fit", "update", "fallback"]
 
 
 class LpError(RuntimeError):
