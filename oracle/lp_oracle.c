@@ -20,7 +20,7 @@
  *   Sec. 2.1, LW derivation .......... Cauchy-Kowalevski second derivatives
  *                                       (multi-D form derived from the same
  *                                       commutation rule; 1D typo in the
- *                                       printed u-update fixed, see DESIGN)
+ *                                       printed u-update fixed to +gamma V u_x P_x)
  *   Sec. 2.1, GFD system + "QR with column pivoting"
  *   Sec. 2.1, blend, state estimator, limiter, particle mover
  *   Sec. 2.2, steps 1-6 of the time-step loop
