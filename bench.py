@@ -48,6 +48,38 @@ def search_bytes(count):
     return 40.0 + 4.0 * k
 
 
+KERNEL_PREFIX = {"search": "k_search<", "fit": "k_lw_fit<", "update": "k_finish<"}
+
+
+def source_hash():
+    """Hash of the kernel sources: HBM counters committed under profiles/ are
+    only reported while the kernels they were taken on are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_2206_11998_amd", "csrc")
+    for f in sorted(os.listdir(src)):
+        with open(os.path.join(src, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(kernel, precision):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) of a
+    kernel, from the rocprofv3 counter summary of the same workload and
+    precision in profiles/, or None when absent or taken on other sources."""
+    path = os.path.join(ROOT, "profiles", "vacuum3d_2M_%s_step_traffic.json" % precision)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != source_hash():
+        return None
+    for name, v in d["kernels"].items():
+        if name.startswith(KERNEL_PREFIX[kernel]):
+            return v["read_bytes"] + v["written_bytes"]
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +95,8 @@ def main():
     ap.add_argument("--search-group", type=int, default=None)
     ap.add_argument("--max-nb", type=int, default=None, help="override the neighbour-list capacity")
     ap.add_argument("--solve-block", type=int, default=None)
+    ap.add_argument("--solve-mode", type=int, default=None, help="0 direct, 1 work queue, 2 persistent work queue")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device copies of 1 GiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -100,6 +134,8 @@ def main():
     results = {}
     first_step = {}
     def tuned(ctx):
+        if args.solve_mode is not None:
+            ctx.set_tuning(lp.TUNE_SOLVE_MODE, args.solve_mode)
         if args.search_mode is not None:
             ctx.set_tuning(lp.TUNE_SEARCH_MODE, args.search_mode)
         if args.search_group is not None:
@@ -109,9 +145,16 @@ def main():
         return ctx
 
     for prec in precisions:
-        ctx = tuned(lp.Context(cfg, precision="fp64" if prec == "fp64" else "mixed", refine=prec != "fp32"))
-        # one step from the initial state for the accuracy check
+        ctx = lp.Context(cfg, precision="fp64" if prec == "fp64" else "mixed", refine=prec != "fp32")
         dev = lp.state_to_device(st)
+        tuning = None
+        if not args.no_autotune:
+            t_at = time.time()
+            tuning, at_ms = ctx.autotune(dev, reps=2)
+            log(prec, "autotune chose %s (%.3f ms/step) in %.1fs" % (tuning, at_ms, time.time() - t_at))
+        ctx = tuned(ctx)
+        tuning = {name: ctx.get_tuning(q) for q, name in enumerate(lp.TUNE_NAMES)}
+        # one step from the initial state for the accuracy check
         ctx.step(dev)
         if ctx.check() != lp.OK:
             raise RuntimeError(lp.lib().lp_last_error(ctx._h).decode())
@@ -136,7 +179,8 @@ def main():
         log(prec, "steps %d in %.3fs -> %.3f ms/step; stages %s; info %s" % (
             args.steps, elapsed, 1e3 * elapsed / args.steps,
             {k: "%.3f ms" % (v[0] / max(v[1], 1)) for k, v in prof.items()}, info))
-        results[prec] = {"elapsed": elapsed, "prof": prof, "status": status, "info": info, "dt0": dt0}
+        results[prec] = {"elapsed": elapsed, "prof": prof, "status": status, "info": info, "dt0": dt0,
+                         "tuning": tuning}
         del dev
         ctx.close()
 
@@ -182,7 +226,7 @@ def main():
     except Exception as exc:  # the reference is optional on hosts without gcc
         log("cpu reference unavailable:", repr(exc))
 
-    def kernel_rooflines(prof):
+    def kernel_rooflines(prof, precision):
         out = {}
         for name, bound in (("search", "hbm"), ("fit", "alu"), ("update", "alu")):
             ms, cnt = prof[name]
@@ -194,7 +238,8 @@ def main():
                 achieved = work[name] / (avg * 1e-3) / 1e12 if avg > 0 else None
                 peak, unit, per = PEAK_ALU_TFLOPS, "TFLOP/s", "algorithmic_flops_per_launch"
             out[name] = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                         "frac": achieved / peak if achieved else None, "traffic": None, per: work[name],
+                         "frac": achieved / peak if achieved else None,
+                         "traffic": committed_traffic(name, precision), per: work[name],
                          "avg_launch_ms": avg}
         return out
 
@@ -202,7 +247,7 @@ def main():
     res = results[main_prec]
     ms_step = 1e3 * res["elapsed"] / args.steps
     value = n * args.steps / res["elapsed"]
-    kr = kernel_rooflines(res["prof"])
+    kr = kernel_rooflines(res["prof"], main_prec)
     dominant = max(kr, key=lambda k: kr[k]["avg_launch_ms"])
     top = dict(kr[dominant])
     top["kernel"] = {"search": "k_search (neighbour lists)", "fit": "k_lw_fit (second-order fits)",
@@ -227,12 +272,13 @@ def main():
         "kernels": kr,
         "cpu_baseline": cpu,
         "stages_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in res["prof"].items()},
+        "tuning": res["tuning"],
         "l1_vs_oracle": l1,
     }
     for prec in precisions[1:]:
         r2 = results[prec]
         out[prec] = {"value": n * args.steps / r2["elapsed"], "ms_per_step": 1e3 * r2["elapsed"] / args.steps,
-                     "kernels": kernel_rooflines(r2["prof"]),
+                     "kernels": kernel_rooflines(r2["prof"], prec), "tuning": r2["tuning"],
                      "stages_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in r2["prof"].items()}}
     print(json.dumps(out))
 

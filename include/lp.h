@@ -147,8 +147,16 @@ lp_status lp_step(struct lp_ctx *ctx, void *stream, const lp_particles *p, doubl
 
 /* Advance p by nsteps CFL-limited steps or until the accumulated time reaches
  * t_end (t_end <= 0: no limit); the last step is shortened to end on t_end.
- * The steps are captured once into a HIP graph and replayed; dt and t stay on
- * the device. */
+ * The first step plans the cell grid and the workspace (with headroom for
+ * growth) and synchronises once; the following steps are one captured HIP
+ * graph replayed on `stream`, with dt and t kept on the device.  Every 8
+ * replays the call synchronises to stop at t_end and to re-plan (with a new
+ * capture) when the particles outgrow the grid or the ghost capacity; a
+ * replayed step that finds more mirror ghosts than the workspace holds is
+ * skipped whole and redone after re-planning.  Results are identical to
+ * nsteps calls of lp_step.  The graph is kept for the next call with the same
+ * particle arrays.  The caller must not free or move the arrays while the
+ * call runs. */
 lp_status lp_run(struct lp_ctx *ctx, void *stream, const lp_particles *p, int32_t nsteps, double t_end);
 
 /* Totals in FP64: out[0] = sum m, out[1..3] = sum m u, out[4] = sum m (e + |u|^2/2),
@@ -170,20 +178,37 @@ lp_status lp_set_time(struct lp_ctx *ctx, void *stream, double t);
  * earlier records), lp_profile(ctx, 0) stops.  lp_profile_read synchronises
  * and writes, per stage, the summed milliseconds ms[q] and the number of
  * timed launches count[q] (host arrays of LP_NSTAGES entries), then clears.
- * Stages: 0 radii/dt/ghosts, 1 cell ordering, 2 neighbour search,
- * 3 second-order fits (fast path), 4 half-ball fits + estimator + update +
- * mover, 5 FP64 pivoted-QR fallback. */
-#define LP_NSTAGES 6
+ * Stages: 0 radii/dt/ghosts, 1 cell ordering, 2 neighbour search (+ work
+ * queue), 3 second-order fits (fast path), 4 half-ball fits + estimator +
+ * update + mover, 5 FP64 pivoted-QR fallback, 6 whole step (also around each
+ * graph replay of lp_run, whose inner stages are not timed). */
+#define LP_NSTAGES 7
+#define LP_STAGE_STEP 6
 
 /* Launch-shape parameters (results are identical for every setting; only the
  * speed changes).  Chosen by lp_autotune() or set explicitly: */
 enum {
     LP_TUNE_SEARCH_MODE = 0,   /* 0: lane group per particle walking its cells, 1: LDS-staged tiles */
     LP_TUNE_SEARCH_GROUP = 1,  /* lanes per particle of mode 0: 4, 8, 16, 32 */
-    LP_TUNE_SOLVE_BLOCK = 2,   /* threads per block of the fused solver: 64, 128, 256 */
-    LP_TUNE_COUNT = 3
+    LP_TUNE_SOLVE_BLOCK = 2,   /* threads per block of the fit and update kernels: 64, 128, 256 */
+    LP_TUNE_SOLVE_MODE = 3,    /* 0: one thread per cell-order particle; 1: work queue regrouped by
+                                  neighbour count within tiles of cell-order particles; 2: persistent
+                                  launch over that queue */
+    LP_TUNE_QUEUE_TILE = 4,    /* tile of the work queue of modes 1 and 2: 256, 512, 1024 */
+    LP_TUNE_COUNT = 5
 };
 lp_status lp_set_tuning(struct lp_ctx *ctx, int32_t param, int32_t value);
+
+/* Autotuner: time full steps of a private copy of p (p itself is not
+ * modified) for every launch-shape setting in turn -- the solve mode, the
+ * queue tile, the fit/update block size, the search mode and group -- keep the
+ * fastest setting of each
+ * (coordinate descent, `reps` timed steps per candidate after one warm-up),
+ * and write the chosen values to best[LP_TUNE_COUNT] (host; may be NULL) and
+ * the per-step milliseconds of the best setting to *ms (host; may be NULL).
+ * Synchronises.  Allocates a copy of p's state for its duration. */
+lp_status lp_autotune(struct lp_ctx *ctx, void *stream, const lp_particles *p, int32_t reps, int32_t *best,
+                      double *ms);
 lp_status lp_get_tuning(const struct lp_ctx *ctx, int32_t param, int32_t *value);
 lp_status lp_profile(struct lp_ctx *ctx, int32_t enable);
 lp_status lp_profile_read(struct lp_ctx *ctx, void *stream, double *ms, int64_t *count);

@@ -9,6 +9,8 @@
 #include <string>
 #include <vector>
 
+#include <algorithm>
+
 #include "lp_internal.h"
 
 static double bits_to_double(unsigned long long b) {
@@ -29,7 +31,7 @@ struct lp_ctx {
     std::string err;
     // workspace
     Buf h, r, gcnt, scan_tmp, ghosts, key, slot, tables, sorted, sortedf, sid, nbr, count, queue, partials, consout,
-        gfd_fields, hitd2, hitj, tflags, tlo, thi, prep_part, ovfq, der, lwst;
+        gfd_fields, hitd2, hitj, tflags, tlo, thi, prep_part, ovfq, der, lwst, wq;
     int search_mode = 0;            // 0: lane group per particle walking its cells, 1: LDS-staged tiles
     int solve_block = 256;
     DevScalars *sc = nullptr;       // device scalars
@@ -51,8 +53,13 @@ struct lp_ctx {
     std::vector<Rec> recs;
     // lp_run graph
     hipGraphExec_t graph = nullptr;
+    hipStream_t cap_stream = nullptr;  // private stream to capture on (the caller's may be the null stream)
     lp_particles graph_p;
-    int64_t graph_n = -1;
+    uint64_t graph_gen = 0;         // workspace generation the graph was captured against
+    uint64_t gen = 1;               // bumped by every reallocation and grid change
+    double grid_margin = 0.0;       // bounding-box margin of planned grids (lp_run plans with headroom)
+    int solve_mode = 0;             // LP_TUNE_SOLVE_MODE
+    int queue_tile = 1024;          // LP_TUNE_QUEUE_TILE
 };
 
 static lp_status fail(lp_ctx *c, lp_status s, const char *fmt, ...) {
@@ -75,6 +82,7 @@ static lp_status fail(lp_ctx *c, lp_status s, const char *fmt, ...) {
 
 static lp_status ensure(lp_ctx *c, Buf &b, size_t bytes) {
     if (b.bytes >= bytes) return LP_OK;
+    ++c->gen;  // captured graphs hold the old address
     if (b.p) (void)hipFree(b.p);
     b.p = nullptr;
     b.bytes = 0;
@@ -102,8 +110,16 @@ static void stage_mark(lp_ctx *c, hipStream_t st, int stage, bool begin) {
     hipEvent_t e = next_event(c);
     if (!e) return;
     (void)hipEventRecord(e, st);
-    if (begin) c->recs.push_back({stage, e, nullptr});
-    else if (!c->recs.empty()) c->recs.back().b = e;
+    if (begin) {
+        c->recs.push_back({stage, e, nullptr});
+        return;
+    }
+    // stages nest (the whole step encloses its parts): close the latest open one
+    for (size_t q = c->recs.size(); q-- > 0;)
+        if (c->recs[q].stage == stage && !c->recs[q].b) {
+            c->recs[q].b = e;
+            return;
+        }
 }
 
 #define ENSURE(ctx, buf, bytes)                        \
@@ -239,10 +255,12 @@ extern "C" lp_status lp_destroy(lp_ctx *c) {
     if (!c) return LP_E_ARG;
     (void)hipDeviceSynchronize();
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     Buf *bufs[] = {&c->h, &c->r, &c->gcnt, &c->scan_tmp, &c->ghosts, &c->key, &c->slot, &c->tables, &c->sorted,
                    &c->sortedf, &c->sid, &c->nbr, &c->count, &c->queue, &c->partials, &c->consout, &c->gfd_fields,
-                   &c->hitd2, &c->hitj, &c->tflags, &c->tlo, &c->thi, &c->prep_part, &c->ovfq, &c->der, &c->lwst};
+                   &c->hitd2, &c->hitj, &c->tflags, &c->tlo, &c->thi, &c->prep_part, &c->ovfq, &c->der, &c->lwst,
+                   &c->wq};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->sc) (void)hipFree(c->sc);
@@ -263,8 +281,10 @@ static double key_to_double(unsigned long long k) {
 
 // Grid cube: with any periodic axis, the box-derived side S (periodic
 // extents are S / 2^j); otherwise the cube is fitted to the particles'
-// bounding box read back with the radii, so no level is wasted on empty space.
-static void choose_levels(lp_ctx *c, double rmin, double rmax) {
+// bounding box read back with the radii (widened by margin * extent on every
+// side), so no level is wasted on empty space.  Pure: writes only g and S.
+static void plan_grid(const lp_ctx *c, double rmin, double rmax, double margin, DevGrid &g, double &S_out,
+                      int levels[2]) {
     const int D = c->dc.D;
     const int Lmax = D == 3 ? 9 : 13;
     int jmin = 0;
@@ -284,9 +304,10 @@ static void choose_levels(lp_ctx *c, double rmin, double rmax) {
             if (hi - lo > ext) ext = hi - lo;
         }
         if (!(ext > 0.0)) ext = c->S;
-        S = ext * (1.0 + 1e-9) + 1e-300;
+        for (int a = 0; a < D; ++a) glo[a] -= margin * ext;
+        S = ext * (1.0 + 2.0 * margin) * (1.0 + 1e-9) + 1e-300;
     }
-    c->S_grid = S;
+    S_out = S;
     auto level_le = [&](double r) {
         int L = 0;
         while (L < Lmax && ldexp(S, -L) > r) ++L;
@@ -298,7 +319,6 @@ static void choose_levels(lp_ctx *c, double rmin, double rmax) {
     if (lo < jmin) lo = jmin;
     if (lo > hi) lo = hi;
     if (hi - lo > 6) lo = hi - 6;
-    DevGrid &g = c->grid;
     memset(&g, 0, sizeof g);
     g.L_lo = lo;
     g.L_hi = hi;
@@ -318,8 +338,41 @@ static void choose_levels(lp_ctx *c, double rmin, double rmax) {
         }
     }
     for (int a = 0; a < 3; ++a) g.lo[a] = a < D ? glo[a] : 0.0;
-    c->last_levels[0] = lo;
-    c->last_levels[1] = hi;
+    levels[0] = lo;
+    levels[1] = hi;
+}
+
+static void choose_levels(lp_ctx *c, double rmin, double rmax) {
+    DevGrid g;
+    double S;
+    int lv[2];
+    plan_grid(c, rmin, rmax, c->grid_margin, g, S, lv);
+    if (memcmp(&g, &c->grid, sizeof g) != 0) ++c->gen;
+    c->grid = g;
+    c->S_grid = S;
+    c->last_levels[0] = lv[0];
+    c->last_levels[1] = lv[1];
+}
+
+// A graph-replayed step keeps the grid it was captured with.  That grid stays
+// correct for any positions and radii (search boxes are clamped to the grid and
+// outlying particles sit in its edge cells), but it is re-planned once the
+// particles leave the cube or the radii need other levels.
+static bool grid_outdated(const lp_ctx *c) {
+    const DevScalars &h = *c->sc_host;
+    bool any_periodic = false;
+    for (int a = 0; a < c->dc.D; ++a) any_periodic |= c->dc.periodic[a] != 0;
+    if (!any_periodic)
+        for (int a = 0; a < c->dc.D; ++a) {
+            double lo = key_to_double(h.xlo[a]), hi = key_to_double(h.xhi[a]);
+            if (lo < c->grid.lo[a] || hi >= c->grid.lo[a] + c->S_grid) return true;
+        }
+    DevGrid g;
+    double S;
+    int lv[2];
+    plan_grid(c, bits_to_double(h.rmin), bits_to_double(h.rmax), c->grid_margin, g, S, lv);
+    // levels from the current cube side (the fitted side only grows between plans)
+    return lv[1] > c->grid.L_hi + 1 || lv[0] < c->grid.L_lo - 1;
 }
 
 static uint64_t table_words(const lp_ctx *c) {
@@ -357,6 +410,7 @@ static lp_status ensure_capacity(lp_ctx *c, int64_t n_real, int64_t n_total, boo
     if (state) {
         ENSURE(c, c->der, sizeof(double) * (size_t)der_count(D) * nt);
         ENSURE(c, c->lwst, (size_t)nt);
+        ENSURE(c, c->wq, sizeof(int) * nt);
     }
     if (c->search_mode == 1) {
         ENSURE(c, c->hitd2, sizeof(double) * (size_t)c->dc.max_nb * nt);
@@ -451,8 +505,10 @@ static Soa soa_of(const lp_particles *p) {
 }
 
 // One step.  sync_levels: read r_min / r_max / ghost count back to size the
-// grid (lp_step); otherwise the current grid and capacities are used as they
-// are (graph replays).
+// grid and the workspace (lp_step, and the planning steps of lp_run);
+// otherwise the current grid and capacities are used as they are (the step
+// captured for graph replay: no host synchronisation, no allocation, kernels
+// sized to the capacities and bounded by the device-side counts).
 static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, double dt_in, bool sync_levels,
                            int clip_t_end) {
     const int D = c->dc.D;
@@ -467,7 +523,7 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
         ENSURE(c, c->prep_part, sizeof(double) * prep_partial_words(n));
     }
     stage_mark(c, st, 0, true);
-    launch_reset_scalars(c->sc, dt_in, n, st);
+    launch_reset_scalars(c->sc, dt_in, n, sync_levels ? 1 : 0, st);
     launch_prep(soa, c->dc, c->sc, (double *)c->h.p, (double *)c->r.p, (double *)c->prep_part.p, st);
     launch_dt(c->dc, c->sc, clip_t_end, st);
     if (c->nwalls) {
@@ -485,16 +541,25 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
         }
         n_total = n + c->sc_host->n_ghost;
         choose_levels(c, bits_to_double(c->sc_host->rmin), bits_to_double(c->sc_host->rmax));
-        lp_status s = ensure_capacity(c, n, n_total, true, mixed);
+        int64_t want = n_total;
+        if (c->nwalls && c->grid_margin > 0.0) {
+            // planning for graph replays: room for the ghost count to grow
+            int64_t ng = c->sc_host->n_ghost;
+            want = n + ng + ng / 4 + 1024;
+        }
+        lp_status s = ensure_capacity(c, n, want, true, mixed);
         if (s != LP_OK) return s;
     } else {
         n_total = c->cap_total;
     }
+    // ghosts admitted: what both the ghost arrays and the cell-order arrays hold
+    const int64_t gcap = c->nwalls ? std::min<int64_t>(c->cap_ghost, c->cap_total - n) : 0;
+    launch_gate(c->sc, n, gcap, st);
     Ghosts gh = ghost_view(c);
     stage_mark(c, st, 1, true);
     if (c->nwalls)
         launch_ghost_write(soa, c->dc, c->sc, (const uint32_t *)c->gcnt.p, (const double *)c->h.p,
-                           (const double *)c->r.p, gh, st);
+                           (const double *)c->r.p, gh, c->cap_ghost, st);
     const double *gx[3] = {gh.x[0], gh.x[1], gh.x[2]};
     const double *x[3] = {p->x[0], p->x[1], D == 3 ? p->x[2] : p->x[1]};
     build_cells(c, st, x, gx, n, n_total);
@@ -532,17 +597,34 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
     int ldn = list_ldn(c);
     stage_mark(c, st, 2, true);
     run_search(c, srt, n_total, n, st);
+    if (c->solve_mode != 0)
+        launch_bin_tiles((const int *)c->count.p, srt.id, &c->sc->n_total, (int)n_total, n, c->dc.max_nb,
+                         c->queue_tile, (int *)c->wq.p, st);
     stage_mark(c, st, 2, false);
     stage_mark(c, st, 3, true);
     struct Between { lp_ctx *c; hipStream_t st; } bt{c, st};
-    auto between = [](void *a) {
-        Between *b = (Between *)a;
+    auto between = [](void *arg) {
+        Between *b = (Between *)arg;
         stage_mark(b->c, b->st, 3, false);
         stage_mark(b->c, b->st, 4, true);
     };
-    launch_solve(srt, soa, (const int *)c->nbr.p, ldn, (const int *)c->count.p, &c->sc->n_total, (int)n_total, n,
-                 c->dc, c->sc, (int *)c->queue.p, (double *)c->der.p, c->cap_total, (uint8_t *)c->lwst.p,
-                 c->solve_block, +between, &bt, st);
+    SolveArgs sv;
+    memset(&sv, 0, sizeof sv);
+    sv.srt = srt;
+    sv.p = soa;
+    sv.nbr = (const int *)c->nbr.p;
+    sv.ldn = ldn;
+    sv.count = (const int *)c->count.p;
+    sv.n_total_dev = &c->sc->n_total;
+    sv.n_real = n;
+    sv.cfg = c->dc;
+    sv.sc = c->sc;
+    sv.queue = (int *)c->queue.p;
+    sv.der = (double *)c->der.p;
+    sv.ld = c->cap_total;
+    sv.lwst = (uint8_t *)c->lwst.p;
+    sv.wq = c->solve_mode != 0 ? (const int *)c->wq.p : nullptr;
+    launch_solve(sv, (int)n_total, c->solve_block, c->solve_mode, +between, &bt, st);
     stage_mark(c, st, 4, false);
     stage_mark(c, st, 5, true);
     launch_solve_fallback(srt, soa, (const int *)c->nbr.p, ldn, (const int *)c->count.p, n, c->dc, c->sc,
@@ -558,8 +640,58 @@ extern "C" lp_status lp_step(lp_ctx *c, void *stream, const lp_particles *p, dou
     lp_status s = check_particles(c, p);
     if (s != LP_OK) return s;
     HIPCHK(c, hipSetDevice(c->device));
-    return step_impl(c, (hipStream_t)stream, p, dt, true, 0);
+    hipStream_t st = (hipStream_t)stream;
+    c->grid_margin = 0.0;
+    stage_mark(c, st, LP_STAGE_STEP, true);
+    s = step_impl(c, st, p, dt, true, 0);
+    stage_mark(c, st, LP_STAGE_STEP, false);
+    return s;
 }
+
+static lp_status read_scalars(lp_ctx *c, hipStream_t st) {
+    HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    return LP_OK;
+}
+
+// Capture one step of p with the current plan into c->graph (unless the
+// graph of the same particle arrays and workspace generation exists).
+static lp_status graph_prepare(lp_ctx *c, const lp_particles *p) {
+    if (c->graph && c->graph_gen == c->gen && memcmp(&c->graph_p, p, sizeof *p) == 0) return LP_OK;
+    if (c->graph) {
+        (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    const bool prof = c->profiling;
+    c->profiling = false;  // no event nodes in the graph
+    const uint64_t gen0 = c->gen;
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+    lp_status s = step_impl(c, c->cap_stream, p, 0.0, false, 1);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    c->profiling = prof;
+    if (s != LP_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return s;
+    }
+    if (e != hipSuccess || !g) return fail(c, LP_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    if (c->gen != gen0) {
+        (void)hipGraphDestroy(g);
+        return fail(c, LP_E_STATE, "workspace changed during graph capture");
+    }
+    e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->graph = nullptr;
+        return fail(c, LP_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    c->graph_gen = c->gen;
+    c->graph_p = *p;
+    return LP_OK;
+}
+
+#define LP_GRAPH_CHUNK 8
 
 extern "C" lp_status lp_run(lp_ctx *c, void *stream, const lp_particles *p, int32_t nsteps, double t_end) {
     if (!c) return LP_E_ARG;
@@ -569,16 +701,44 @@ extern "C" lp_status lp_run(lp_ctx *c, void *stream, const lp_particles *p, int3
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)stream;
     // t_end is kept on the device; each step shortens its dt to land on it
-    HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipStreamSynchronize(st));
+    if ((s = read_scalars(c, st)) != LP_OK) return s;
     c->sc_host->t_end = t_end;
     c->sc_host->done = 0u;
+    c->sc_host->halt = 0u;
     HIPCHK(c, hipMemcpyAsync(c->sc, c->sc_host, sizeof(DevScalars), hipMemcpyHostToDevice, st));
     c->run_done = false;
-    for (int k = 0; k < nsteps && !c->run_done; ++k) {
+    int64_t steps = 0;
+    while (steps < nsteps && !c->run_done) {
+        // planning step: sizes the grid (with headroom) and the workspace
+        c->grid_margin = 0.125;
+        stage_mark(c, st, LP_STAGE_STEP, true);
         s = step_impl(c, st, p, 0.0, true, 1);
+        stage_mark(c, st, LP_STAGE_STEP, false);
         if (s != LP_OK) return s;
+        if (c->run_done) break;
+        ++steps;
+        if (steps >= nsteps) break;
+        if ((s = graph_prepare(c, p)) != LP_OK) return s;
+        if ((s = read_scalars(c, st)) != LP_OK) return s;
+        // replays of the captured step, checked every LP_GRAPH_CHUNK steps
+        for (;;) {
+            const unsigned long long before = c->sc_host->steps;
+            int64_t chunk = nsteps - steps < LP_GRAPH_CHUNK ? nsteps - steps : LP_GRAPH_CHUNK;
+            for (int64_t q = 0; q < chunk; ++q) {
+                stage_mark(c, st, LP_STAGE_STEP, true);
+                HIPCHK(c, hipGraphLaunch(c->graph, st));
+                stage_mark(c, st, LP_STAGE_STEP, false);
+            }
+            if ((s = read_scalars(c, st)) != LP_OK) return s;
+            steps += (int64_t)(c->sc_host->steps - before);
+            if (c->sc_host->done || (t_end > 0.0 && c->sc_host->t >= t_end)) {
+                c->run_done = true;
+                break;
+            }
+            if (steps >= nsteps || c->sc_host->halt || grid_outdated(c)) break;
+        }
     }
+    c->grid_margin = 0.0;
     return LP_OK;
 }
 
@@ -590,7 +750,7 @@ extern "C" lp_status lp_neighbors(lp_ctx *c, void *stream, int64_t n, const doub
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)stream;
     const int D = c->dc.D;
-    launch_reset_scalars(c->sc, 0.0, (int)n, st);
+    launch_reset_scalars(c->sc, 0.0, (int)n, 1, st);
     {
         const double *xs[3] = {x, y, c->dc.D == 3 ? z : y};
         launch_rminmax(r, xs, c->dc.D, (int)n, c->sc, st);
@@ -635,7 +795,7 @@ extern "C" lp_status lp_gfd(lp_ctx *c, void *stream, int64_t n, const double *x,
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)stream;
     const int D = c->dc.D;
-    launch_reset_scalars(c->sc, 0.0, (int)n, st);
+    launch_reset_scalars(c->sc, 0.0, (int)n, 1, st);
     {
         const double *xs[3] = {x, y, c->dc.D == 3 ? z : y};
         launch_rminmax(r, xs, c->dc.D, (int)n, c->sc, st);
@@ -786,6 +946,14 @@ extern "C" lp_status lp_set_tuning(lp_ctx *c, int32_t param, int32_t value) {
         if (value != 64 && value != 128 && value != 256) return fail(c, LP_E_ARG, "solve block must be 64..256");
         c->solve_block = value;
         return LP_OK;
+    case LP_TUNE_SOLVE_MODE:
+        if (value < 0 || value > 2) return fail(c, LP_E_ARG, "solve mode must be 0, 1 or 2");
+        c->solve_mode = value;
+        return LP_OK;
+    case LP_TUNE_QUEUE_TILE:
+        if (value != 256 && value != 512 && value != 1024) return fail(c, LP_E_ARG, "queue tile must be 256, 512 or 1024");
+        c->queue_tile = value;
+        return LP_OK;
     default:
         return fail(c, LP_E_ARG, "unknown tuning parameter %d", param);
     }
@@ -797,6 +965,116 @@ extern "C" lp_status lp_get_tuning(const lp_ctx *c, int32_t param, int32_t *valu
     case LP_TUNE_SEARCH_MODE: *value = c->search_mode; return LP_OK;
     case LP_TUNE_SEARCH_GROUP: *value = c->search_group; return LP_OK;
     case LP_TUNE_SOLVE_BLOCK: *value = c->solve_block; return LP_OK;
+    case LP_TUNE_SOLVE_MODE: *value = c->solve_mode; return LP_OK;
+    case LP_TUNE_QUEUE_TILE: *value = c->queue_tile; return LP_OK;
     default: return LP_E_ARG;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: coordinate descent over the launch-shape parameters, each
+// candidate timed on full steps of a private copy of the particle state.
+// ---------------------------------------------------------------------------
+extern "C" lp_status lp_autotune(lp_ctx *c, void *stream, const lp_particles *p, int32_t reps, int32_t *best,
+                                 double *ms_out) {
+    if (!c) return LP_E_ARG;
+    lp_status s = check_particles(c, p);
+    if (s != LP_OK) return s;
+    if (reps < 1) reps = 3;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int D = c->dc.D;
+    const int64_t n = p->n;
+    const int narr = 2 * D + 2;
+    double *buf = nullptr;
+    if (hipMalloc(&buf, sizeof(double) * narr * n) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, LP_E_NOMEM, "autotune: no room for a copy of the state");
+    }
+    lp_particles q = *p;
+    const double *src[8];
+    double *dst[8];
+    int k = 0;
+    for (int a = 0; a < D; ++a) { q.x[a] = buf + (int64_t)k * n; src[k] = p->x[a]; dst[k++] = q.x[a]; }
+    for (int a = 0; a < D; ++a) { q.u[a] = buf + (int64_t)k * n; src[k] = p->u[a]; dst[k++] = q.u[a]; }
+    q.V = buf + (int64_t)k * n; src[k] = p->V; dst[k++] = q.V;
+    q.P = buf + (int64_t)k * n; src[k] = p->P; dst[k++] = q.P;
+    q.phi = c->dc.est_mode == LP_EST_INJECTED ? p->phi : nullptr;
+    q.flags = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool prof = c->profiling;
+    c->profiling = false;
+    double t0 = 0.0;
+    auto cleanup = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(buf);
+        c->profiling = prof;
+    };
+    auto run_candidate = [&](double &ms) -> lp_status {
+        for (int a = 0; a < narr; ++a)
+            HIPCHK(c, hipMemcpyAsync(dst[a], src[a], sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        lp_status r = step_impl(c, st, &q, 0.0, true, 0);  // warm-up (plans and allocates)
+        if (r != LP_OK) return r;
+        HIPCHK(c, hipEventRecord(e0, st));
+        for (int i = 0; i < reps; ++i) {
+            r = step_impl(c, st, &q, 0.0, true, 0);
+            if (r != LP_OK) return r;
+        }
+        HIPCHK(c, hipEventRecord(e1, st));
+        HIPCHK(c, hipEventSynchronize(e1));
+        float t = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&t, e0, e1));
+        ms = (double)t / reps;
+        return LP_OK;
+    };
+    auto body = [&]() -> lp_status {
+        HIPCHK(c, hipEventCreate(&e0));
+        HIPCHK(c, hipEventCreate(&e1));
+        lp_status r = read_scalars(c, st);
+        if (r != LP_OK) return r;
+        t0 = c->sc_host->t;
+        c->grid_margin = 0.0;
+        struct Param { int id; std::vector<int> values; };
+        std::vector<Param> params = {{LP_TUNE_SOLVE_MODE, {0, 1, 2}},
+                                     {LP_TUNE_QUEUE_TILE, {256, 512, 1024}},
+                                     {LP_TUNE_SOLVE_BLOCK, {64, 128, 256}},
+                                     {LP_TUNE_SEARCH_MODE, {0, 1}},
+                                     {LP_TUNE_SEARCH_GROUP, {4, 8, 16, 32}}};
+        double best_ms = 0.0;
+        r = run_candidate(best_ms);
+        if (r != LP_OK) return r;
+        for (const Param &pr : params) {
+            int32_t cur = 0;
+            (void)lp_get_tuning(c, pr.id, &cur);
+            int chosen = cur;
+            for (int v : pr.values) {
+                if (v == cur) continue;
+                if (pr.id == LP_TUNE_SEARCH_GROUP && c->search_mode != 0) continue;
+                if (pr.id == LP_TUNE_QUEUE_TILE && c->solve_mode == 0) continue;
+                r = lp_set_tuning(c, pr.id, v);
+                if (r != LP_OK) return r;
+                double ms = 0.0;
+                r = run_candidate(ms);
+                if (r != LP_OK) return r;
+                if (ms < best_ms) { best_ms = ms; chosen = v; }
+            }
+            r = lp_set_tuning(c, pr.id, chosen);
+            if (r != LP_OK) return r;
+        }
+        if (best)
+            for (int id = 0; id < LP_TUNE_COUNT; ++id) (void)lp_get_tuning(c, id, &best[id]);
+        if (ms_out) *ms_out = best_ms;
+        // the private steps advanced the context's clock: restore it
+        r = read_scalars(c, st);
+        if (r != LP_OK) return r;
+        c->sc_host->t = t0;
+        HIPCHK(c, hipMemcpyAsync(c->sc, c->sc_host, sizeof(DevScalars), hipMemcpyHostToDevice, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        return LP_OK;
+    };
+    s = body();
+    cleanup();
+    return s;
 }

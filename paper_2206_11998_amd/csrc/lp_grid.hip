@@ -19,7 +19,7 @@ static inline unsigned blocks_for(uint64_t n, int per = LP_BLOCK) {
 // ---------------------------------------------------------------------------
 // Scalars
 // ---------------------------------------------------------------------------
-__global__ void k_reset_scalars(DevScalars *sc, double dt_in, int n_real) {
+__global__ void k_reset_scalars(DevScalars *sc, double dt_in, int n_real, int clear_halt) {
     sc->n_total = n_real;
     sc->min_hc = 0x7ff0000000000000ull;  // +inf
     sc->rmax = 0ull;
@@ -30,11 +30,33 @@ __global__ void k_reset_scalars(DevScalars *sc, double dt_in, int n_real) {
     sc->n_fallback = 0;
     sc->n_overflow = 0;
     sc->n_limited = 0ull;
+    sc->done = 0u;  // recomputed by k_dt from t and t_end
+    if (clear_halt) sc->halt = 0u;
     for (int a = 0; a < 3; ++a) { sc->xlo[a] = ~0ull; sc->xhi[a] = 0ull; }
+    for (int q = 0; q < 8; ++q) { sc->head[0][q] = 0u; sc->head[1][q] = 0u; }
 }
 
-void launch_reset_scalars(DevScalars *sc, double dt_in, int n_real, hipStream_t st) {
-    hipLaunchKernelGGL(k_reset_scalars, dim3(1), dim3(1), 0, st, sc, dt_in, n_real);
+void launch_reset_scalars(DevScalars *sc, double dt_in, int n_real, int clear_halt, hipStream_t st) {
+    hipLaunchKernelGGL(k_reset_scalars, dim3(1), dim3(1), 0, st, sc, dt_in, n_real, clear_halt);
+    CHECK_LAUNCH();
+}
+
+// Admission of the particle work of a step.  n_total = real + ghost particles,
+// or 0 with dt = 0 when the step is skipped: t_end reached, or more ghosts
+// than the workspace was sized for (then halt stays raised until the host
+// re-plans the workspace; every later kernel of the step sees n_total = 0).
+__global__ void k_gate(DevScalars *sc, int n_real, long long cap_ghost) {
+    if (sc->n_ghost > cap_ghost) sc->halt = 1u;
+    if (sc->done || sc->halt) {
+        sc->n_total = 0;
+        sc->dt = 0.0;
+    } else {
+        sc->n_total = n_real + sc->n_ghost;
+    }
+}
+
+void launch_gate(DevScalars *sc, int n_real, int64_t cap_ghost, hipStream_t st) {
+    hipLaunchKernelGGL(k_gate, dim3(1), dim3(1), 0, st, sc, n_real, (long long)cap_ghost);
     CHECK_LAUNCH();
 }
 
@@ -140,10 +162,11 @@ size_t prep_partial_words(int64_t n) { return (size_t)((n + LP_BLOCK - 1) / LP_B
 // does not pass t_end (and set to zero once t_end is reached).
 __global__ void k_dt(DevCfg cfg, DevScalars *sc, int clip) {
     double dt = sc->dt_in > 0.0 ? sc->dt_in : cfg.cfl * bits_dbl(sc->min_hc);
+    sc->clipped = 0u;
     if (clip && sc->t_end > 0.0) {
         double rem = sc->t_end - sc->t;
         if (!(rem > 0.0)) { dt = 0.0; sc->done = 1u; }
-        else if (dt >= rem) dt = rem;
+        else if (dt >= rem) { dt = rem; sc->clipped = 1u; }
     }
     sc->dt = dt;
 }
@@ -170,7 +193,12 @@ void launch_rminmax(const double *r, const double *const x[3], int D, int n, Dev
 }
 
 // t += dt after a step
-__global__ void k_advance_time(DevScalars *sc) { sc->t += sc->dt; }
+__global__ void k_advance_time(DevScalars *sc) {
+    if (sc->n_total > 0) {
+        sc->t = sc->clipped ? sc->t_end : sc->t + sc->dt;  // a clipped step lands on t_end exactly
+        sc->steps += 1ull;
+    }
+}
 
 void launch_advance_time(DevScalars *sc, hipStream_t st) {
     hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(1), 0, st, sc);
@@ -210,10 +238,9 @@ void launch_ghost_count(const Soa &p, const DevCfg &cfg, DevScalars *sc, uint32_
 }
 
 __global__ void k_ghost_write(Soa p, DevCfg cfg, DevScalars *sc, const uint32_t *goff, const double *h,
-                              const double *r, Ghosts g) {
+                              const double *r, Ghosts g, long long cap_ghost) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) sc->n_total = p.n + sc->n_ghost;
-    if (i >= p.n) return;
+    if (i >= p.n || sc->n_total == 0) return;  // step skipped by k_gate
     double rmax = bits_dbl(sc->rmax);
     int which[6];
     int k = ghost_walls(cfg, p, i, rmax, which);
@@ -222,6 +249,7 @@ __global__ void k_ghost_write(Soa p, DevCfg cfg, DevScalars *sc, const uint32_t 
         int a = which[q] >> 1;
         double w = (which[q] & 1) ? cfg.hi[a] : cfg.lo[a];
         uint32_t gi = o + q;
+        if ((long long)gi >= cap_ghost) return;  // k_gate has already raised halt
         for (int b = 0; b < cfg.D; ++b) {
             double xb = p.x[b][i], ub = p.u[b][i];
             if (b == a) { xb = 2.0 * w - xb; ub = -ub; }
@@ -236,8 +264,9 @@ __global__ void k_ghost_write(Soa p, DevCfg cfg, DevScalars *sc, const uint32_t 
 }
 
 void launch_ghost_write(const Soa &p, const DevCfg &cfg, DevScalars *sc, const uint32_t *goff, const double *h,
-                        const double *r, Ghosts g, hipStream_t st) {
-    hipLaunchKernelGGL(k_ghost_write, dim3(blocks_for(p.n)), dim3(LP_BLOCK), 0, st, p, cfg, sc, goff, h, r, g);
+                        const double *r, Ghosts g, int64_t cap_ghost, hipStream_t st) {
+    hipLaunchKernelGGL(k_ghost_write, dim3(blocks_for(p.n)), dim3(LP_BLOCK), 0, st, p, cfg, sc, goff, h, r, g,
+                       (long long)cap_ghost);
     CHECK_LAUNCH();
 }
 

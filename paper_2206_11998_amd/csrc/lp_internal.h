@@ -9,6 +9,7 @@
 
 #define LP_MAX_LEVEL 16
 #define LP_BLOCK 256
+#define LP_QTILE 1024  // largest tile of the stencil-size work queue
 
 // ---------------------------------------------------------------------------
 // Configuration as seen by the kernels (passed by value).
@@ -46,10 +47,14 @@ struct DevScalars {
     int n_fallback;
     unsigned int error_bits;        // 1: capacity, 2: numeric
     unsigned int done;              // lp_run: t reached t_end
+    unsigned int clipped;           // this step's dt was shortened to end on t_end
+    unsigned int halt;              // a graph-replayed step found more ghosts than its workspace holds
     int n_tiles;                    // search tiles of the last search
     int n_overflow;                 // lists longer than the search kernel's LDS buffer
     unsigned long long xlo[3], xhi[3];  // bounding box of real particles (order-preserving keys)
     unsigned long long n_limited;
+    unsigned long long steps;       // steps executed (skipped steps do not count)
+    unsigned int head[2][8];        // chunk counters of the persistent fit / update launches, per XCD range
 };
 
 // Particle state in the caller's order (real particles only).
@@ -87,7 +92,8 @@ struct ScatterArgs {
 // ---------------------------------------------------------------------------
 // Host launchers (defined in the .hip files).
 // ---------------------------------------------------------------------------
-void launch_reset_scalars(DevScalars *sc, double dt_in, int n_real, hipStream_t st);
+void launch_reset_scalars(DevScalars *sc, double dt_in, int n_real, int clear_halt, hipStream_t st);
+void launch_gate(DevScalars *sc, int n_real, int64_t cap_ghost, hipStream_t st);
 void launch_rminmax(const double *r, const double *const x[3], int D, int n, DevScalars *sc, hipStream_t st);
 void launch_advance_time(DevScalars *sc, hipStream_t st);
 void launch_prep(const Soa &p, const DevCfg &cfg, DevScalars *sc, double *h, double *r, double *part,
@@ -96,7 +102,7 @@ size_t prep_partial_words(int64_t n);
 void launch_dt(const DevCfg &cfg, DevScalars *sc, int clip_t_end, hipStream_t st);
 void launch_ghost_count(const Soa &p, const DevCfg &cfg, DevScalars *sc, uint32_t *gcnt, hipStream_t st);
 void launch_ghost_write(const Soa &p, const DevCfg &cfg, DevScalars *sc, const uint32_t *goff,
-                        const double *h, const double *r, Ghosts g, hipStream_t st);
+                        const double *h, const double *r, Ghosts g, int64_t cap_ghost, hipStream_t st);
 void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
 void launch_keys(const double *const x[3], const double *const gx[3], int n_real, const int *n_total_dev,
                  int n_total_cap, const DevGrid &g, int D, uint32_t *key, uint32_t *slot, uint32_t *cnt,
@@ -118,10 +124,28 @@ void launch_search_tiles(const Sorted &s, const int *n_total_dev, int n_total_ca
 void launch_lists_out(const int *sorted_id, const int *nbr, int ldn, const int *count, int n, int max_nb,
                       int *count_out, int *idx_out, hipStream_t st);
 int der_count(int D);
-void launch_solve(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count, const int *n_total_dev,
-                  int n_total_cap, int n_real, const DevCfg &cfg, DevScalars *sc, int *queue, double *der,
-                  int64_t ld, uint8_t *lwst, int block, void (*between)(void *), void *between_arg,
-                  hipStream_t st);
+// Everything the fit and update kernels read or write.
+struct SolveArgs {
+    Sorted srt;
+    Soa p;
+    const int *nbr;
+    int ldn;
+    const int *count;
+    const int *n_total_dev;
+    int n_real;
+    DevCfg cfg;
+    DevScalars *sc;
+    int *queue;                     // FP64 fallback queue (written by the fit)
+    double *der;                    // derivatives between fit and update, der[q * ld + work slot]
+    int64_t ld;
+    uint8_t *lwst;                  // per particle: 0 fast path, 1 queued for the fallback
+    const int *wq;                  // work queue of launch_bin_tiles (NULL: direct indexing)
+};
+// mode: 0 direct, 1 work queue, 2 persistent launch over the work queue
+void launch_solve(const SolveArgs &a, int n_total_cap, int block, int mode, void (*between)(void *),
+                  void *between_arg, hipStream_t st);
+void launch_bin_tiles(const int *count, const int *sid, const int *n_total_dev, int n_total_cap, int n_real,
+                      int max_nb, int tile, int *wq, hipStream_t st);
 void launch_solve_fallback(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count,
                            int n_real, const DevCfg &cfg, DevScalars *sc, const int *queue, int queue_cap,
                            hipStream_t st);
@@ -217,6 +241,35 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     int q = nb / X, rem = nb % X;
     int xcd = b % X, idx = b / X;
     return xcd * q + (xcd < rem ? xcd : rem) + idx;
+}
+
+// Persistent work loop: the ceil(n / blockDim) chunks of blockDim items are
+// split into 8 contiguous ranges, one per XCD.  A block claims chunks of its
+// own XCD's range (blocks are dispatched round-robin over the XCDs) through
+// head[range], then helps with the other ranges; body(t) runs for every item
+// index t of every chunk claimed (t may exceed n - 1 in the last chunk).
+// Every block leaves once all 8 counters have passed their range's end.
+template <typename F>
+__device__ __forceinline__ void persistent_chunks(unsigned *head, int n, F &&body) {
+    __shared__ int sh_chunk;
+    const int B = blockDim.x;
+    const int nch = (n + B - 1) / B;
+    const int home = blockIdx.x % 8;
+    for (int x = 0; x < 8; ++x) {
+        const int rg = (home + x) % 8;
+        const int lo = (int)((int64_t)nch * rg / 8), hi = (int)((int64_t)nch * (rg + 1) / 8);
+        for (;;) {
+            if (threadIdx.x == 0) {
+                unsigned c = atomicAdd(&head[rg], 1u);
+                sh_chunk = c < (unsigned)(hi - lo) ? lo + (int)c : -1;
+            }
+            __syncthreads();
+            const int c = sh_chunk;
+            __syncthreads();
+            if (c < 0) break;
+            body(c * B + (int)threadIdx.x);
+        }
+    }
 }
 
 // Neighbour-list element c of cell-order particle s.  ldn > 0: column-major

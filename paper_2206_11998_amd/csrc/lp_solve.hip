@@ -567,7 +567,7 @@ __device__ __forceinline__ void finish_particle(const Sorted &srt, const Soa &p,
 
 // ---------------------------------------------------------------------------
 // Second-order derivatives kept between the fit and the update kernels
-// (SoA, der[q * ld + s]): gradients of V, u_1..u_D, P (D each), the Hessians
+// (SoA, der[q * ld + t], t the particle's work slot): gradients of V, u_1..u_D, P (D each), the Hessians
 // of u_1..u_D (NS each) and the diagonal second derivatives of P (D).
 // ---------------------------------------------------------------------------
 template <int D> struct Der { static constexpr int N = (D + 2) * D + D * Dim<D>::NS + D; };
@@ -616,33 +616,32 @@ __device__ __forceinline__ void load_der(const double *der, int64_t ld, int s, d
 // ---------------------------------------------------------------------------
 // Fast path: one thread per particle.
 // ---------------------------------------------------------------------------
+// s: cell-order particle; t: its work slot, which indexes der (the queue
+// order, so that a wave's derivative stores and loads stay coalesced).
 template <int D, typename T, bool REFINE>
-__global__ __launch_bounds__(LP_BLOCK, 2) void k_lw_fit(Sorted srt, const int *nbr, int ldn, const int *count,
-                                                     const int *n_total_dev, int n_real, DevCfg cfg, DevScalars *sc,
-                                                     int *queue, double *der, int64_t ld, uint8_t *lwst) {
+__device__ __forceinline__ void lw_fit_one(const SolveArgs &a, int s, int t) {
     constexpr int NU = Dim<D>::NU, NF = Dim<D>::NF, NG = Dim<D>::NG, NS = Dim<D>::NS, FP = D + 1;
     const bool use_f = sizeof(T) == 4;
-    int s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (s >= *n_total_dev) return;
+    const Sorted &srt = a.srt;
+    const DevCfg &cfg = a.cfg;
     int i = srt.id[s];
-    if (i >= n_real) return;
-    int k = count[s];
+    if (i >= a.n_real) return;
+    int k = a.count[s];
     if (k > cfg.max_nb) k = cfg.max_nb;
     double xi[3] = {srt.x[0][s], srt.x[1][s], D == 3 ? srt.x[2][s] : 0.0};
     double st[NF];
     st[0] = srt.V[s];
 #pragma unroll
-    for (int a = 0; a < D; ++a) st[1 + a] = srt.u[a][s];
+    for (int q = 0; q < D; ++q) st[1 + q] = srt.u[q][s];
     st[FP] = srt.P[s];
     const double h = srt.h[s];
     const double r = cfg.kappa * h;
     const double inv_r = 1.0 / r;
-    const double dt = sc->dt;
     T fi[NF];
     if (use_f) {
         fi[0] = (T)srt.Vf[s];
 #pragma unroll
-        for (int a = 0; a < D; ++a) fi[1 + a] = (T)srt.uf[a][s];
+        for (int q = 0; q < D; ++q) fi[1 + q] = (T)srt.uf[q][s];
         fi[FP] = (T)srt.Pf[s];
     } else {
 #pragma unroll
@@ -656,10 +655,10 @@ __global__ __launch_bounds__(LP_BLOCK, 2) void k_lw_fit(Sorted srt, const int *n
 #pragma unroll
     for (int q = 0; q < NF * NU; ++q) B[q] = 0;
     int m = 0;
-    for_lw_stencil<D>(srt, cfg, nbr, ldn, s, k, xi, [&](int j, const double dx[3]) {
+    for_lw_stencil<D>(srt, cfg, a.nbr, a.ldn, s, k, xi, [&](int j, const double dx[3]) {
         T x[3];
 #pragma unroll
-        for (int a = 0; a < D; ++a) x[a] = (T)(dx[a] * inv_r);
+        for (int q = 0; q < D; ++q) x[q] = (T)(dx[q] * inv_r);
         add_moments<D, T>(x, M);
         T row[NU];
         second_order_row<D, T>(x, row);
@@ -667,12 +666,12 @@ __global__ __launch_bounds__(LP_BLOCK, 2) void k_lw_fit(Sorted srt, const int *n
         if (use_f) {
             fj[0] = (T)srt.Vf[j];
 #pragma unroll
-            for (int a = 0; a < D; ++a) fj[1 + a] = (T)srt.uf[a][j];
+            for (int q = 0; q < D; ++q) fj[1 + q] = (T)srt.uf[q][j];
             fj[FP] = (T)srt.Pf[j];
         } else {
             fj[0] = (T)srt.V[j];
 #pragma unroll
-            for (int a = 0; a < D; ++a) fj[1 + a] = (T)srt.u[a][j];
+            for (int q = 0; q < D; ++q) fj[1 + q] = (T)srt.u[q][j];
             fj[FP] = (T)srt.P[j];
         }
 #pragma unroll
@@ -689,123 +688,260 @@ __global__ __launch_bounds__(LP_BLOCK, 2) void k_lw_fit(Sorted srt, const int *n
     bool good = m >= NU && cholesky<NU, T>(G, inv);
     if (good) good = cond_estimate<NU, T>(G, inv) <= (T)cfg.cond_fb;
     if (!good) {
-        int slot = atomicAdd(&sc->n_fallback, 1);
-        queue[slot] = s;
-        lwst[s] = 1;
+        int slot = atomicAdd(&a.sc->n_fallback, 1);
+        a.queue[slot] = s;
+        a.lwst[s] = 1;
         return;
     }
-    lwst[s] = 0;
+    a.lwst[s] = 0;
     // B <- (R^T R)^-1 B in place: the scaled coefficients of every field
     chol_solve<NU, NF, T, T>(G, inv, B);
     double grad[NF][3], hess[NF][NS];
     if (REFINE) {
-        // one refinement step: the residual of the FP64 system at the FP32
-        // solution (promoted exactly), corrected through the same factor
-        double Ar[NF * NU];
+        // one step of iterative refinement: the residual b - A y of the FP64
+        // system at the FP32 solution y (promoted exactly) is formed in FP64;
+        // its normal-equation image A^T r and the correction solve use the
+        // FP32 factor, as the correction only needs working precision
+        T Ar[NF * NU];
 #pragma unroll
-        for (int q = 0; q < NF * NU; ++q) Ar[q] = 0.0;
-        for_lw_stencil<D>(srt, cfg, nbr, ldn, s, k, xi, [&](int j, const double dx[3]) {
+        for (int q = 0; q < NF * NU; ++q) Ar[q] = 0;
+        for_lw_stencil<D>(srt, cfg, a.nbr, a.ldn, s, k, xi, [&](int j, const double dx[3]) {
             double x[3];
 #pragma unroll
-            for (int a = 0; a < D; ++a) x[a] = dx[a] * inv_r;
+            for (int q = 0; q < D; ++q) x[q] = dx[q] * inv_r;
             double row[NU];
             second_order_row<D, double>(x, row);
+            T rowf[NU];
+#pragma unroll
+            for (int pp = 0; pp < NU; ++pp) rowf[pp] = (T)row[pp];
             double fj[NF];
             fj[0] = srt.V[j];
 #pragma unroll
-            for (int a = 0; a < D; ++a) fj[1 + a] = srt.u[a][j];
+            for (int q = 0; q < D; ++q) fj[1 + q] = srt.u[q][j];
             fj[FP] = srt.P[j];
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
                 double res = fj[f] - st[f];
 #pragma unroll
                 for (int pp = 0; pp < NU; ++pp) res -= row[pp] * (double)B[f * NU + pp];
+                T rf = (T)res;
 #pragma unroll
-                for (int pp = 0; pp < NU; ++pp) Ar[f * NU + pp] += row[pp] * res;
+                for (int pp = 0; pp < NU; ++pp) Ar[f * NU + pp] += rowf[pp] * rf;
             }
         });
-        chol_solve<NU, NF, T, double>(G, inv, Ar);
+        chol_solve<NU, NF, T, T>(G, inv, Ar);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) grad[f][a] = a < D ? ((double)B[f * NU + a] + Ar[f * NU + a]) * inv_r : 0.0;
+            for (int q = 0; q < 3; ++q)
+                grad[f][q] = q < D ? ((double)B[f * NU + q] + (double)Ar[f * NU + q]) * inv_r : 0.0;
 #pragma unroll
             for (int q = 0; q < NS; ++q)
-                hess[f][q] = ((double)B[f * NU + D + q] + Ar[f * NU + D + q]) * inv_r * inv_r;
+                hess[f][q] = ((double)B[f * NU + D + q] + (double)Ar[f * NU + D + q]) * inv_r * inv_r;
         }
     } else {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) grad[f][a] = a < D ? (double)B[f * NU + a] * inv_r : 0.0;
+            for (int q = 0; q < 3; ++q) grad[f][q] = q < D ? (double)B[f * NU + q] * inv_r : 0.0;
 #pragma unroll
             for (int q = 0; q < NS; ++q) hess[f][q] = (double)B[f * NU + D + q] * inv_r * inv_r;
         }
     }
-    store_der<D>(der, ld, s, grad, hess);
-    (void)i;
-    (void)dt;
-    (void)h;
+    store_der<D>(a.der, a.ld, t, grad, hess);
 }
 
-// Half-ball fits, estimator, blended update and mover for every particle
-// whose second-order fit the fast path solved.
+// Half-ball fits, estimator, blended update and mover of one particle whose
+// second-order fit the fast path solved.
 template <int D, typename T>
-__global__ __launch_bounds__(LP_BLOCK) void k_finish(Sorted srt, Soa p, const int *nbr, int ldn, const int *count,
-                                                     const int *n_total_dev, int n_real, DevCfg cfg, DevScalars *sc,
-                                                     const double *der, int64_t ld, const uint8_t *lwst) {
+__device__ __forceinline__ void finish_one(const SolveArgs &a, int s, int t) {
     constexpr int NF = Dim<D>::NF, NS = Dim<D>::NS, FP = D + 1;
-    int s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (s >= *n_total_dev) return;
+    const Sorted &srt = a.srt;
+    const DevCfg &cfg = a.cfg;
     int i = srt.id[s];
-    if (i >= n_real || lwst[s] != 0) return;
-    int k = count[s];
+    if (i >= a.n_real || a.lwst[s] != 0) return;
+    int k = a.count[s];
     if (k > cfg.max_nb) k = cfg.max_nb;
     double xi[3] = {srt.x[0][s], srt.x[1][s], D == 3 ? srt.x[2][s] : 0.0};
     double st[NF];
     st[0] = srt.V[s];
 #pragma unroll
-    for (int a = 0; a < D; ++a) st[1 + a] = srt.u[a][s];
+    for (int q = 0; q < D; ++q) st[1 + q] = srt.u[q][s];
     st[FP] = srt.P[s];
     const double h = srt.h[s];
     const double r = cfg.kappa * h;
     double grad[NF][3], hess[NF][NS];
-    load_der<D>(der, ld, s, grad, hess);
-    finish_particle<D, T>(srt, p, cfg, sc, nbr, ldn, s, i, k, sc->dt, xi, st, h, r, grad, hess, 0, 0);
+    load_der<D>(a.der, a.ld, t, grad, hess);
+    finish_particle<D, T>(srt, a.p, cfg, a.sc, a.nbr, a.ldn, s, i, k, a.sc->dt, xi, st, h, r, grad, hess, 0, 0);
 }
 
-template <int D, typename T, bool RF>
-static void launch_solve_t(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count,
-                           const int *n_total_dev, int n_total_cap, int n_real, const DevCfg &cfg, DevScalars *sc,
-                           int *queue, double *der, int64_t ld, uint8_t *lwst, int block, void (*between)(void *),
+// Work distribution.  WQ_DIRECT: thread t of the grid serves cell-order
+// particle t.  WQ_QUEUE: it serves wq[t], the cell-order particles regrouped
+// tile by tile by stencil size, so the lanes of a wave loop over similar
+// neighbour counts.  WQ_PERSISTENT: a grid sized to the resident capacity of
+// the chip takes chunks of wq (blockDim entries each) from per-XCD ranges
+// until every range is drained.
+enum { WQ_DIRECT = 0, WQ_QUEUE = 1, WQ_PERSISTENT = 2 };
+
+template <int MODE, typename F>
+__device__ __forceinline__ void for_work(const SolveArgs &a, unsigned *head, F &&body) {
+    const int n = *a.n_total_dev;
+    if (MODE == WQ_PERSISTENT) {
+        persistent_chunks(head, n, [&](int t) {
+            if (t < n) body(a.wq[t], t);
+        });
+    } else {
+        int t = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+        if (t >= n) return;
+        body(MODE == WQ_QUEUE ? a.wq[t] : t, t);
+    }
+}
+
+template <int D, typename T, bool REFINE, int MODE>
+__global__ __launch_bounds__(LP_BLOCK, 2) void k_lw_fit(SolveArgs a) {
+    for_work<MODE>(a, a.sc->head[0], [&](int s, int t) { lw_fit_one<D, T, REFINE>(a, s, t); });
+}
+
+template <int D, typename T, int MODE>
+__global__ __launch_bounds__(LP_BLOCK) void k_finish(SolveArgs a) {
+    for_work<MODE>(a, a.sc->head[1], [&](int s, int t) { finish_one<D, T>(a, s, t); });
+}
+
+// Grid of a persistent launch: the blocks that can be resident at once.
+// Resident blocks per CU are queried once per (kernel, block size), so that a
+// launch under stream capture makes no runtime query.
+static unsigned persistent_grid(const void *kernel, int block, int n_total_cap) {
+    static int n_cu = 0;
+    struct Occ { const void *k; int block, per_cu; };
+    static Occ occ[32];
+    static int n_occ = 0;
+    if (n_cu == 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            n_cu = prop.multiProcessorCount;
+        if (n_cu <= 0) n_cu = 256;
+    }
+    int per_cu = 0;
+    for (int q = 0; q < n_occ; ++q)
+        if (occ[q].k == kernel && occ[q].block == block) per_cu = occ[q].per_cu;
+    if (per_cu <= 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu <= 0)
+            per_cu = 1;
+        (void)hipGetLastError();
+        if (n_occ < 32) occ[n_occ++] = {kernel, block, per_cu};
+    }
+    uint64_t g = (uint64_t)n_cu * per_cu;
+    uint64_t need = ((uint64_t)n_total_cap + block - 1) / block;
+    if (g > need) g = need;
+    return g < 1 ? 1u : (unsigned)g;
+}
+
+template <int D, typename T, bool RF, int MODE>
+static void launch_solve_t(const SolveArgs &a, int n_total_cap, int block, void (*between)(void *),
                            void *between_arg, hipStream_t st) {
     unsigned blocks = (unsigned)((n_total_cap + block - 1) / block);
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((k_lw_fit<D, T, RF>), dim3(blocks), dim3(block), 0, st, s, nbr, ldn, count, n_total_dev, n_real,
-                       cfg, sc, queue, der, ld, lwst);
+    unsigned gf = blocks, gu = blocks;
+    if (MODE == WQ_PERSISTENT) {
+        gf = persistent_grid((const void *)k_lw_fit<D, T, RF, MODE>, block, n_total_cap);
+        gu = persistent_grid((const void *)k_finish<D, T, MODE>, block, n_total_cap);
+    }
+    hipLaunchKernelGGL((k_lw_fit<D, T, RF, MODE>), dim3(gf), dim3(block), 0, st, a);
     if (between) between(between_arg);
-    hipLaunchKernelGGL((k_finish<D, T>), dim3(blocks), dim3(block), 0, st, s, p, nbr, ldn, count, n_total_dev, n_real,
-                       cfg, sc, der, ld, lwst);
+    hipLaunchKernelGGL((k_finish<D, T, MODE>), dim3(gu), dim3(block), 0, st, a);
 }
 
 int der_count(int D) { return D == 3 ? Der<3>::N : Der<2>::N; }
 
-void launch_solve(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count, const int *n_total_dev,
-                  int n_total_cap, int n_real, const DevCfg &cfg, DevScalars *sc, int *queue, double *der,
-                  int64_t ld, uint8_t *lwst, int block, void (*between)(void *), void *between_arg,
-                  hipStream_t st) {
-#define LSV(DD, TT, RR) launch_solve_t<DD, TT, RR>(s, p, nbr, ldn, count, n_total_dev, n_total_cap, n_real, cfg, sc, queue, der, ld, lwst, block, between, between_arg, st)
-    bool mixed = cfg.precision == LP_MIXED;
-    if (cfg.D == 3) {
-        if (!mixed) LSV(3, double, false);
-        else if (cfg.refine) LSV(3, float, true);
-        else LSV(3, float, false);
+template <int D, typename T, bool RF>
+static void launch_solve_m(const SolveArgs &a, int n_total_cap, int block, int mode, void (*between)(void *),
+                           void *between_arg, hipStream_t st) {
+    if (mode == WQ_PERSISTENT) launch_solve_t<D, T, RF, WQ_PERSISTENT>(a, n_total_cap, block, between, between_arg, st);
+    else if (mode == WQ_QUEUE) launch_solve_t<D, T, RF, WQ_QUEUE>(a, n_total_cap, block, between, between_arg, st);
+    else launch_solve_t<D, T, RF, WQ_DIRECT>(a, n_total_cap, block, between, between_arg, st);
+}
+
+void launch_solve(const SolveArgs &a, int n_total_cap, int block, int mode, void (*between)(void *),
+                  void *between_arg, hipStream_t st) {
+    if (a.wq == nullptr) mode = WQ_DIRECT;
+    const bool mixed = a.cfg.precision == LP_MIXED;
+    if (a.cfg.D == 3) {
+        if (!mixed) launch_solve_m<3, double, false>(a, n_total_cap, block, mode, between, between_arg, st);
+        else if (a.cfg.refine) launch_solve_m<3, float, true>(a, n_total_cap, block, mode, between, between_arg, st);
+        else launch_solve_m<3, float, false>(a, n_total_cap, block, mode, between, between_arg, st);
     } else {
-        if (!mixed) LSV(2, double, false);
-        else if (cfg.refine) LSV(2, float, true);
-        else LSV(2, float, false);
+        if (!mixed) launch_solve_m<2, double, false>(a, n_total_cap, block, mode, between, between_arg, st);
+        else if (a.cfg.refine) launch_solve_m<2, float, true>(a, n_total_cap, block, mode, between, between_arg, st);
+        else launch_solve_m<2, float, false>(a, n_total_cap, block, mode, between, between_arg, st);
     }
-#undef LSV
+    (void)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Work queue: within every tile of 256, 512 or LP_QTILE consecutive cell-order particles,
+// a counting sort by neighbour count (largest first; ghosts, which need no
+// solve, last).  Tiles stay in cell order, so the data a wave gathers stays
+// local; inside a tile the lanes of a wave get similar loop lengths.
+// ---------------------------------------------------------------------------
+#define LP_NBIN 258  // counts 0..256 plus the ghost bin
+__global__ __launch_bounds__(LP_QTILE) void k_bin_tiles(const int *count, const int *sid, const int *n_total_dev,
+                                                        int n_real, int max_nb, int *wq) {
+    __shared__ unsigned hist[LP_NBIN];
+    __shared__ unsigned offs[LP_NBIN];
+    const int n_total = *n_total_dev;
+    const int base = blockIdx.x * (int)blockDim.x;  // one tile per block
+    if (base >= n_total) return;
+    for (int b = threadIdx.x; b < LP_NBIN; b += blockDim.x) hist[b] = 0u;
+    __syncthreads();
+    const int s = base + threadIdx.x;
+    int bin = 0;
+    unsigned rank = 0u;
+    if (s < n_total) {
+        if (sid[s] >= n_real) {
+            bin = LP_NBIN - 1;
+        } else {
+            int k = count[s];
+            k = k < max_nb ? k : max_nb;
+            bin = max_nb - k;
+        }
+        rank = atomicAdd(&hist[bin], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        constexpr int PER = (LP_NBIN + 63) / 64;
+        const int lane = threadIdx.x;
+        unsigned loc[PER], sum = 0u;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            int b = lane * PER + q;
+            loc[q] = b < LP_NBIN ? hist[b] : 0u;
+            sum += loc[q];
+        }
+        unsigned incl = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            unsigned v = __shfl_up(incl, o);
+            if (lane >= o) incl += v;
+        }
+        unsigned run = incl - sum;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            int b = lane * PER + q;
+            if (b < LP_NBIN) offs[b] = run;
+            run += loc[q];
+        }
+    }
+    __syncthreads();
+    if (s < n_total) wq[base + (int)(offs[bin] + rank)] = s;
+}
+
+void launch_bin_tiles(const int *count, const int *sid, const int *n_total_dev, int n_total_cap, int n_real,
+                      int max_nb, int tile, int *wq, hipStream_t st) {
+    if (tile != 256 && tile != 512) tile = LP_QTILE;
+    unsigned blocks = (unsigned)((n_total_cap + tile - 1) / tile);
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_bin_tiles, dim3(blocks), dim3(tile), 0, st, count, sid, n_total_dev, n_real, max_nb, wq);
     (void)hipGetLastError();
 }
 

@@ -21,9 +21,11 @@ FLAG_LIMITED, FLAG_DEGENERATE, FLAG_VACUUM, FLAG_SUBSTITUTED, FLAG_FALLBACK, FLA
 
 EXPORTS = ["lp_config_default", "lp_create", "lp_destroy", "lp_neighbors", "lp_gfd", "lp_step", "lp_run",
            "lp_conservation", "lp_check", "lp_get_info", "lp_set_time", "lp_profile", "lp_profile_read",
-           "lp_set_tuning", "lp_get_tuning", "lp_status_str", "lp_last_error"]
-TUNE_SEARCH_MODE, TUNE_SEARCH_GROUP, TUNE_SOLVE_BLOCK = 0, 1, 2
-STAGES = ["prep", "cells", "search", "fit", "update", "fallback"]
+           "lp_set_tuning", "lp_get_tuning", "lp_autotune", "lp_status_str", "lp_last_error"]
+TUNE_SEARCH_MODE, TUNE_SEARCH_GROUP, TUNE_SOLVE_BLOCK, TUNE_SOLVE_MODE, TUNE_QUEUE_TILE = 0, 1, 2, 3, 4
+TUNE_COUNT = 5
+TUNE_NAMES = ["search_mode", "search_group", "solve_block", "solve_mode", "queue_tile"]
+STAGES = ["prep", "cells", "search", "fit", "update", "fallback", "step"]
 
 
 class LpError(RuntimeError):
@@ -99,6 +101,8 @@ def lib():
         L.lp_set_tuning.argtypes = [vp, i32, i32]
         L.lp_get_tuning.restype = i32
         L.lp_get_tuning.argtypes = [vp, i32, C.POINTER(i32)]
+        L.lp_autotune.restype = i32
+        L.lp_autotune.argtypes = [vp, vp, C.POINTER(Particles), i32, C.POINTER(i32), C.POINTER(C.c_double)]
         L.lp_status_str.restype = C.c_char_p
         L.lp_status_str.argtypes = [i32]
         L.lp_last_error.restype = C.c_char_p
@@ -287,3 +291,12 @@ class Context:
         v = C.c_int32(0)
         self._raise(lib().lp_get_tuning(self._h, int(param), C.byref(v)))
         return v.value
+
+    def autotune(self, s: dict, reps: int = 3, stream=None):
+        """Choose the launch shapes by timing steps of a private copy of s
+        (s is not modified).  Returns ({name: value}, ms per step)."""
+        p = self._particles(s)
+        best = (C.c_int32 * TUNE_COUNT)()
+        ms = C.c_double(0.0)
+        self._raise(lib().lp_autotune(self._h, _stream_ptr(stream), C.byref(p), int(reps), best, C.byref(ms)))
+        return {name: best[q] for q, name in enumerate(TUNE_NAMES)}, ms.value

@@ -1,0 +1,152 @@
+"""Batching on the GPU: the stencil-size work queue (plain and persistent
+launches), graph-replayed steps (lp_run) and the autotuner.
+
+None of these may change a result: every comparison here is bit for bit
+against the plain one-thread-per-particle, one-launch-per-step path, which the
+parity tests tie to the oracle."""
+import numpy as np
+import pytest
+
+from paper_2206_11998_amd import workloads as W
+from tests.gpu_util import say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2206_11998_amd import lp as _lp
+    _lp.lib()
+    return _lp
+
+
+CASES = {
+    "pulse2d": lambda: W.pulse2d(),
+    "sod slab": lambda: W.sod3d(n=64, ny=8, nz=8),
+    "vacuum 60k": lambda: W.vacuum3d(n_particles=60_000, seed=5),
+}
+
+
+def _same(a, b, tag):
+    for k in ("x", "V", "u", "P", "phi", "flags"):
+        assert np.array_equal(a[k], b[k]), (tag, k, np.nonzero(np.asarray(a[k] != b[k]).reshape(len(a[k]), -1).any(1))[0][:5])
+
+
+def _steps(lp, cfg, st, nsteps, precision="fp64", tuning=None):
+    ctx = lp.Context(cfg, precision=precision)
+    for p, v in (tuning or {}).items():
+        ctx.set_tuning(p, v)
+    dev = lp.state_to_device(st)
+    for _ in range(nsteps):
+        ctx.step(dev)
+    assert ctx.check() == lp.OK, lp.lib().lp_last_error(ctx._h)
+    out = lp.state_to_host(dev)
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_modes_identical(lp, case, precision):
+    cfg, st = CASES[case]()
+    ref = None
+    for mode, block, tile in ((0, 256, 1024), (1, 256, 1024), (1, 128, 256), (2, 256, 1024), (2, 64, 512)):
+        tag = "%s %s solve mode %d block %d tile %d" % (case, precision, mode, block, tile)
+        say("batching", tag)
+        got = _steps(lp, cfg, st, 3, precision,
+                     {lp.TUNE_SOLVE_MODE: mode, lp.TUNE_SOLVE_BLOCK: block, lp.TUNE_QUEUE_TILE: tile})
+        if ref is None:
+            ref = got
+        else:
+            _same(got, ref, tag)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_run_graph_matches_steps(lp, case):
+    cfg, st = CASES[case]()
+    # planning step + full replay chunks + a partial one (the edge of the
+    # coarse 60k-particle vacuum cloud outgrows max_nb = 256 after 8 steps, so
+    # that case stops at 5 + 2)
+    nsteps = 5 if case.startswith("vacuum") else 19
+    say("lp_run vs lp_step", case, nsteps)
+    ref = _steps(lp, cfg, st, nsteps)
+    for mode in (0, 2):
+        ctx = lp.Context(cfg)
+        ctx.set_tuning(lp.TUNE_SOLVE_MODE, mode)
+        ctx.set_tuning(lp.TUNE_QUEUE_TILE, 256)
+        dev = lp.state_to_device(st)
+        ctx.run(dev, nsteps)
+        assert ctx.check() == lp.OK
+        _same(lp.state_to_host(dev), ref, "%s lp_run solve mode %d" % (case, mode))
+        # a second call reuses the captured graph
+        ctx.run(dev, 2)
+        ref2 = _steps(lp, cfg, st, nsteps + 2)
+        _same(lp.state_to_host(dev), ref2, "%s second lp_run" % case)
+        ctx.close()
+
+
+def test_run_stops_on_t_end(lp):
+    cfg, st = CASES["sod slab"]()
+    ctx = lp.Context(cfg)
+    dev = lp.state_to_device(st)
+    ctx.step(dev)
+    dt0 = ctx.info()["dt"]
+    ctx.close()
+    t_end = 6.5 * dt0
+    say("lp_run t_end", t_end)
+    # reference: one planning step per call, each clipped on the device
+    ctx = lp.Context(cfg)
+    ref = lp.state_to_device(st)
+    n_ref = 0
+    while ctx.info()["t"] < t_end and n_ref < 100:
+        ctx.run(ref, 1, t_end)
+        n_ref += 1
+    ctx.close()
+    ctx = lp.Context(cfg)
+    dev = lp.state_to_device(st)
+    ctx.run(dev, 1000, t_end)
+    info = ctx.info()
+    assert info["t"] == t_end, (info["t"], t_end)
+    _same(lp.state_to_host(dev), lp.state_to_host(ref), "t_end")
+    assert 6 <= n_ref <= 9
+
+
+def test_autotune_leaves_state_and_results(lp):
+    cfg, st = CASES["sod slab"]()
+    ctx = lp.Context(cfg)
+    dev = lp.state_to_device(st)
+    before = lp.state_to_host(dev)
+    say("autotune")
+    best, ms = ctx.autotune(dev, reps=1)
+    say("autotune chose", best, "%.3f ms/step" % ms)
+    assert ms > 0
+    assert best["solve_mode"] in (0, 1, 2) and best["solve_block"] in (64, 128, 256)
+    assert best["search_mode"] in (0, 1) and best["search_group"] in (4, 8, 16, 32)
+    assert best["queue_tile"] in (256, 512, 1024)
+    assert ctx.info()["t"] == 0.0
+    after = lp.state_to_host(dev)
+    for k in ("x", "V", "u", "P"):
+        assert np.array_equal(after[k], before[k]), k
+    for q, name in enumerate(lp.TUNE_NAMES):
+        assert ctx.get_tuning(q) == best[name]
+    for _ in range(3):
+        ctx.step(dev)
+    _same(lp.state_to_host(dev), _steps(lp, cfg, st, 3), "after autotune")
+
+
+def test_step_stage_timing(lp):
+    cfg, st = CASES["pulse2d"]()
+    ctx = lp.Context(cfg)
+    dev = lp.state_to_device(st)
+    ctx.profile(True)
+    ctx.step(dev)
+    ctx.run(dev, 10)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    say("stages", prof)
+    assert prof["step"][1] == 11  # one eager step, one planning step, nine replays
+    assert prof["search"][1] == 2 and prof["fit"][1] == 2
+    assert all(v[0] >= 0 for v in prof.values())
