@@ -48,9 +48,6 @@ def search_bytes(count):
     return 40.0 + 4.0 * k
 
 
-KERNEL_PREFIX = {"search": "k_search<", "fit": "k_lw_fit<", "update": "k_finish<"}
-
-
 def source_hash():
     """Hash of the kernel sources: HBM counters committed under profiles/ are
     only reported while the kernels they were taken on are unchanged."""
@@ -64,20 +61,19 @@ def source_hash():
 
 
 def committed_traffic(kernel, precision):
-    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) of a
-    kernel, from the rocprofv3 counter summary of the same workload and
-    precision in profiles/, or None when absent or taken on other sources."""
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) of the
+    search / fit / update kernel, from the rocprofv3 counter summary of the
+    same workload and precision in profiles/; None when there is none or it
+    was taken on other kernel sources."""
     path = os.path.join(ROOT, "profiles", "vacuum3d_2M_%s_step_traffic.json" % precision)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("source_hash") != source_hash():
+    if d.get("source_hash") != source_hash() or kernel not in d.get("kernels", {}):
         return None
-    for name, v in d["kernels"].items():
-        if name.startswith(KERNEL_PREFIX[kernel]):
-            return v["read_bytes"] + v["written_bytes"]
-    return None
+    v = d["kernels"][kernel]
+    return v["read_bytes"] + v["written_bytes"]
 
 
 def main():

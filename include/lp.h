@@ -188,8 +188,9 @@ lp_status lp_set_time(struct lp_ctx *ctx, void *stream, double t);
 /* Launch-shape parameters (results are identical for every setting; only the
  * speed changes).  Chosen by lp_autotune() or set explicitly: */
 enum {
-    LP_TUNE_SEARCH_MODE = 0,   /* 0: lane group per particle walking its cells, 1: LDS-staged tiles */
-    LP_TUNE_SEARCH_GROUP = 1,  /* lanes per particle of mode 0: 4, 8, 16, 32 */
+    LP_TUNE_SEARCH_MODE = 0,   /* 0: lane group per particle walking its cells, 1: LDS-staged tiles,
+                                  2: lane group with pruned cells and candidates dealt evenly (default) */
+    LP_TUNE_SEARCH_GROUP = 1,  /* lanes per particle of modes 0 and 2: 4, 8 (default), 16, 32 */
     LP_TUNE_SOLVE_BLOCK = 2,   /* threads per block of the fit and update kernels: 64, 128, 256 */
     LP_TUNE_SOLVE_MODE = 3,    /* 0: one thread per cell-order particle; 1: work queue regrouped by
                                   neighbour count within tiles of cell-order particles; 2: persistent

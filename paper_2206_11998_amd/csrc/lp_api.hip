@@ -32,7 +32,7 @@ struct lp_ctx {
     // workspace
     Buf h, r, gcnt, scan_tmp, ghosts, key, slot, tables, sorted, sortedf, sid, nbr, count, queue, partials, consout,
         gfd_fields, hitd2, hitj, tflags, tlo, thi, prep_part, ovfq, der, lwst, wq;
-    int search_mode = 0;            // 0: lane group per particle walking its cells, 1: LDS-staged tiles
+    int search_mode = 2;            // 0: lane group walking its cells, 1: LDS-staged tiles, 2: balanced lane group
     int solve_block = 256;
     DevScalars *sc = nullptr;       // device scalars
     DevScalars *sc_host = nullptr;  // pinned copy
@@ -40,7 +40,7 @@ struct lp_ctx {
     double S = 1.0;                 // cube side from the box (periodic extents are S / 2^j)
     double S_grid = 1.0;            // cube side used by the last grid
     int jper[3] = {0, 0, 0};        // periodic extent = S / 2^jper
-    int search_group = 16;
+    int search_group = 8;
     int64_t cap_real = 0, cap_total = 0, cap_ghost = 0;
     bool run_done = false;
     DevGrid grid;
@@ -436,7 +436,8 @@ static void run_search(lp_ctx *c, const Sorted &srt, int64_t n_total, int n_real
                             (int *)c->tlo.p, (int *)c->thi.p, &c->sc->n_tiles, st);
     else
         launch_search(srt, &c->sc->n_total, (int)n_total, n_real, (const uint32_t *)c->tables.p, c->grid, c->dc,
-                      (int *)c->nbr.p, ldn, (int *)c->count.p, c->sc, c->search_group, (int *)c->ovfq.p, st);
+                      (int *)c->nbr.p, ldn, (int *)c->count.p, c->sc, c->search_group, (int *)c->ovfq.p,
+                      c->search_mode == 2, st);
 }
 
 static Sorted sorted_view(lp_ctx *c, bool state) {
@@ -935,7 +936,7 @@ extern "C" lp_status lp_set_tuning(lp_ctx *c, int32_t param, int32_t value) {
     if (!c) return LP_E_ARG;
     switch (param) {
     case LP_TUNE_SEARCH_MODE:
-        if (value != 0 && value != 1) return fail(c, LP_E_ARG, "search mode must be 0 or 1");
+        if (value < 0 || value > 2) return fail(c, LP_E_ARG, "search mode must be 0, 1 or 2");
         c->search_mode = value;
         return LP_OK;
     case LP_TUNE_SEARCH_GROUP:
@@ -1040,7 +1041,7 @@ extern "C" lp_status lp_autotune(lp_ctx *c, void *stream, const lp_particles *p,
         std::vector<Param> params = {{LP_TUNE_SOLVE_MODE, {0, 1, 2}},
                                      {LP_TUNE_QUEUE_TILE, {256, 512, 1024}},
                                      {LP_TUNE_SOLVE_BLOCK, {64, 128, 256}},
-                                     {LP_TUNE_SEARCH_MODE, {0, 1}},
+                                     {LP_TUNE_SEARCH_MODE, {0, 1, 2}},
                                      {LP_TUNE_SEARCH_GROUP, {4, 8, 16, 32}}};
         double best_ms = 0.0;
         r = run_candidate(best_ms);
@@ -1051,7 +1052,7 @@ extern "C" lp_status lp_autotune(lp_ctx *c, void *stream, const lp_particles *p,
             int chosen = cur;
             for (int v : pr.values) {
                 if (v == cur) continue;
-                if (pr.id == LP_TUNE_SEARCH_GROUP && c->search_mode != 0) continue;
+                if (pr.id == LP_TUNE_SEARCH_GROUP && c->search_mode == 1) continue;
                 if (pr.id == LP_TUNE_QUEUE_TILE && c->solve_mode == 0) continue;
                 r = lp_set_tuning(c, pr.id, v);
                 if (r != LP_OK) return r;

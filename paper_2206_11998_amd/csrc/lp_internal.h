@@ -116,7 +116,7 @@ void launch_scatter(const ScatterArgs &a, int n_real, const int *n_total_dev, in
 void launch_coarsen(uint32_t *tables, const DevGrid &g, int D, const int *n_total_dev, hipStream_t st);
 void launch_search(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real, const uint32_t *tables,
                    const DevGrid &g, const DevCfg &cfg, int *nbr, int ldn, int *count, DevScalars *sc,
-                   int group, int *ovf_queue, hipStream_t st);
+                   int group, int *ovf_queue, bool balanced, hipStream_t st);
 void launch_search_tiles(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real,
                          const uint32_t *tables, const DevGrid &g, const DevCfg &cfg, double *hit_d2, int *hit_j,
                          int *nbr, int ldn, int *count, DevScalars *sc, const uint32_t *key, uint32_t *flags,
@@ -170,13 +170,29 @@ __device__ __forceinline__ unsigned long long dbl_key(double v) {
 __device__ __forceinline__ double bits_dbl(unsigned long long b) { return __longlong_as_double((long long)b); }
 
 // Minimum-image displacement x_j - x_i along axis a.  Evaluated exactly as
-// written (IEEE binary64 add/sub only).
+// written (IEEE binary64 add/sub only); the fold is a select, not a branch, so
+// loads around it are not serialised by divergent control flow.
 __device__ __forceinline__ double min_image(const DevCfg &c, int a, double d) {
-    if (c.periodic[a]) {
-        if (d > c.half[a]) d = d - c.L[a];
-        else if (d < -c.half[a]) d = d + c.L[a];
-    }
-    return d;
+    const bool p = c.periodic[a] != 0;
+    const double down = d - c.L[a], up = d + c.L[a];
+    double r = d;
+    r = (p && d < -c.half[a]) ? up : r;
+    r = (p && d > c.half[a]) ? down : r;
+    return r;
+}
+
+// Displacements x_j - x_i (minimum image) of particle j of a SoA position set;
+// the coordinates of j are all loaded before any arithmetic, so the loads are
+// in flight together.
+// PER = false: the caller knows that no axis is periodic (plain differences).
+template <int D, bool PER = true>
+__device__ __forceinline__ void disp_to(const DevCfg &c, const double *const x[3], int j, const double xi[3],
+                                        double dx[3]) {
+    const double a0 = x[0][j], a1 = x[1][j];
+    const double a2 = D == 3 ? x[2][j] : 0.0;
+    dx[0] = PER ? min_image(c, 0, a0 - xi[0]) : a0 - xi[0];
+    dx[1] = PER ? min_image(c, 1, a1 - xi[1]) : a1 - xi[1];
+    dx[2] = D == 3 ? (PER ? min_image(c, 2, a2 - xi[2]) : a2 - xi[2]) : 0.0;
 }
 
 // Squared distance ((dx*dx) + (dy*dy)) + (dz*dz) with every product and sum

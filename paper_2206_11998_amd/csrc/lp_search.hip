@@ -86,9 +86,7 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search(Sorted srt, const int *n_to
             for (uint32_t j = b; j < e; ++j) {
                 if ((int)j == s) continue;
                 double dx[3];
-                dx[0] = min_image(cfg, 0, srt.x[0][j] - xi[0]);
-                dx[1] = min_image(cfg, 1, srt.x[1][j] - xi[1]);
-                dx[2] = D == 3 ? min_image(cfg, 2, srt.x[2][j] - xi[2]) : 0.0;
+                disp_to<D>(cfg, srt.x, j, xi, dx);
                 double d2 = dist2_exact<D>(dx);
                 if (d2 < r2) {
                     int slot = atomicAdd(&lcnt[grp], 1);
@@ -101,11 +99,15 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search(Sorted srt, const int *n_to
         }
     }
     __syncthreads();
+    {
+        int kmax = active ? lcnt[grp] : 0;
+        for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o));
+        if ((threadIdx.x & 63) == 0 && kmax > 0) atomicMax(&sc->max_count, kmax);
+    }
     if (active) {
         int k = lcnt[grp];
         if (lane == 0) {
             count[s] = k;
-            atomicMax(&sc->max_count, k);
             if (k > max_nb) atomicOr(&sc->error_bits, 1u);
             // the list does not fit the LDS buffer: one wave redoes it (and
             // for k > max_nb writes max_nb valid entries, so readers stay in bounds)
@@ -155,9 +157,7 @@ __global__ __launch_bounds__(64) void k_search_overflow(Sorted srt, const uint32
             for (uint32_t j = b; j < e; ++j) {
                 if ((int)j == s) continue;
                 double dx[3];
-                dx[0] = min_image(cfg, 0, srt.x[0][j] - xi[0]);
-                dx[1] = min_image(cfg, 1, srt.x[1][j] - xi[1]);
-                dx[2] = D == 3 ? min_image(cfg, 2, srt.x[2][j] - xi[2]) : 0.0;
+                disp_to<D>(cfg, srt.x, j, xi, dx);
                 double d2 = dist2_exact<D>(dx);
                 if (d2 < r2) {
                     int slot = atomicAdd(&lcnt, 1);
@@ -185,34 +185,327 @@ __global__ __launch_bounds__(64) void k_search_overflow(Sorted srt, const uint32
     }
 }
 
+// Balanced variant: the group prunes the cells of the search box whose box
+// lies provably outside the ball, prefix-sums the candidate counts of the rest
+// (G cells at a time) and deals the candidates out so that in every round each
+// lane tests exactly one -- consecutive lanes test consecutive particles of a
+// cell, so the position loads coalesce.  Hits are compacted with a ballot and
+// ranked by a counting sort on a monotone bucket of d2 followed by exact
+// (d2, original id) comparisons inside each bucket, so the list is the same
+// unique (d2, id) order as k_search's.
+#define SB_NB 32  // rank buckets per particle
+
+// c = q * n + rem for 0 <= c < 2^24 without an integer division
+__device__ __forceinline__ int div_small(int c, int n, float rcp, int &rem) {
+    int q = (int)((float)c * rcp);
+    int r = c - q * n;
+    if (r < 0) { --q; r += n; }
+    else if (r >= n) { ++q; r -= n; }
+    rem = r;
+    return q;
+}
+
+template <int D, int G, bool PER>
+__global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *n_total_dev, int n_real,
+                                                         const uint32_t *tables, DevGrid g, DevCfg cfg, int *nbr,
+                                                         int ldn, int *count, DevScalars *sc, int lcap,
+                                                         int *ovf_queue) {
+    constexpr int PPB = LP_BLOCK / G;
+    extern __shared__ unsigned char smem[];
+    const int max_nb = cfg.max_nb;
+    const int stride = lcap + 1;  // odd group stride: groups of a wave hit different LDS banks
+    double *ld2 = reinterpret_cast<double *>(smem);
+    int *lj = reinterpret_cast<int *>(ld2 + PPB * stride);
+    unsigned char *lperm = reinterpret_cast<unsigned char *>(lj + PPB * stride);
+    int *lbk = reinterpret_cast<int *>(lperm + PPB * ((stride + 3) & ~3));
+    // after ranking, the (d2) slots hold the ranked lists lout[rank * PPB + grp]
+    // and the bucket counters the list length of every group (0: written elsewhere)
+    int *lout = reinterpret_cast<int *>(smem);
+    int *lk = lbk;
+
+    const int lane = threadIdx.x % G;
+    const int grp = threadIdx.x / G;
+    const int gshift = (int)(threadIdx.x & 63) - lane;  // first wave lane of the group
+    const unsigned long long gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int s = xcd_remap(blockIdx.x, gridDim.x) * PPB + grp;
+    const int n_total = *n_total_dev;
+    const bool active = s < n_total && srt.id[s] < n_real;
+    double *gd2 = ld2 + grp * stride;
+    int *gj = lj + grp * stride;
+    unsigned char *gperm = lperm + grp * ((stride + 3) & ~3);
+    int *gbk = lbk + grp * SB_NB;
+    int k = 0;  // hits so far (the same in every lane of the group)
+    double r2 = 0.0;
+
+    for (int q = lane; q < SB_NB; q += G) gbk[q] = 0;
+    if (active) {
+        const double xi[3] = {srt.x[0][s], srt.x[1][s], D == 3 ? srt.x[2][s] : 0.0};
+        const double ri = srt.r[s];
+        r2 = ri * ri;
+        // a cell is skipped only when even its box widened by a rounding slack
+        // (and unbounded on the outer side of edge cells, which hold the
+        // particles clamped into the grid) is farther than r from x_i
+        const double r2_keep = r2 * (1.0 + 1e-12);
+        const int L = level_for_radius(g, ri);
+        const double cs = g.s[L];
+        const double slack = 1e-12 * g.s[0];
+        const uint32_t *tab = tables + g.off[L];
+        int clo[3] = {0, 0, 0}, cn[3] = {1, 1, 1};
+        search_box<D>(g, cfg, L, xi, ri, clo, cn);
+        const int ncells = cn[0] * cn[1] * (D == 3 ? cn[2] : 1);
+        const float rcp0 = 1.0f / (float)cn[0], rcp1 = 1.0f / (float)cn[1];
+        for (int c0 = 0; c0 < ncells; c0 += G) {
+            const int c = c0 + lane;
+            int b = 0, len = 0;
+            if (c < ncells) {
+                int cc[3], rem;
+                const int q0 = div_small(c, cn[0], rcp0, rem);
+                cc[0] = clo[0] + rem;
+                if (D == 3) {
+                    const int q1 = div_small(q0, cn[1], rcp1, rem);
+                    cc[1] = clo[1] + rem;
+                    cc[2] = clo[2] + q1;
+                } else {
+                    cc[1] = clo[1] + q0;
+                    cc[2] = 0;
+                }
+                double dd = 0.0;
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    if (PER && cfg.periodic[a]) continue;
+                    const int n_a = g.nc[L][a];
+                    const double lo_a = cc[a] <= 0 ? -INFINITY : g.lo[a] + cc[a] * cs - slack;
+                    const double hi_a = cc[a] >= n_a - 1 ? INFINITY : g.lo[a] + (cc[a] + 1) * cs + slack;
+                    const double t = xi[a] < lo_a ? lo_a - xi[a] : (xi[a] > hi_a ? xi[a] - hi_a : 0.0);
+                    dd += t * t;
+                }
+                if (!(dd > r2_keep)) {
+#pragma unroll
+                    for (int a = 0; a < D; ++a)
+                        if (PER && cfg.periodic[a]) {
+                            const int n_a = g.nc[L][a];
+                            cc[a] = cc[a] < 0 ? cc[a] + n_a : (cc[a] >= n_a ? cc[a] - n_a : cc[a]);
+                        }
+                    const uint32_t code = morton<D>(cc);
+                    b = (int)tab[code];
+                    len = (int)tab[code + 1] - b;
+                }
+            }
+            // inclusive prefix sum of the candidate counts over the group
+            int incl = len;
+#pragma unroll
+            for (int o = 1; o < G; o <<= 1) {
+                const int v = __shfl_up(incl, o, G);
+                if (lane >= o) incl += v;
+            }
+            const int excl = incl - len;
+            const int total = __shfl(incl, G - 1, G);
+            // two candidates per lane and round (t and t + G), so that two
+            // search chains and six position loads are in flight together
+            for (int t0 = 0; t0 < total; t0 += 2 * G) {
+                const int ta = t0 + lane, tb = ta + G;
+                // the cell of candidate t: the last lane q with excl_q <= t
+                int qa = 0, qb = 0;
+#pragma unroll
+                for (int step = G / 2; step > 0; step >>= 1) {
+                    const int va = __shfl(excl, qa + step, G);
+                    const int vb = __shfl(excl, qb + step, G);
+                    if (va <= ta) qa += step;
+                    if (vb <= tb) qb += step;
+                }
+                const int ja = __shfl(b, qa, G) + (ta - __shfl(excl, qa, G));
+                const int jb = __shfl(b, qb, G) + (tb - __shfl(excl, qb, G));
+                const bool oka = ta < total && ja != s, okb = tb < total && jb != s;
+                // slots past the end read the particle itself (a valid index)
+                double dxa[3], dxb[3];
+                disp_to<D, PER>(cfg, srt.x, oka ? ja : s, xi, dxa);
+                disp_to<D, PER>(cfg, srt.x, okb ? jb : s, xi, dxb);
+                const double d2a = dist2_exact<D>(dxa), d2b = dist2_exact<D>(dxb);
+                const bool hita = oka && d2a < r2, hitb = okb && d2b < r2;
+                const unsigned long long ma = (__ballot(hita) >> gshift) & gmask;
+                const unsigned long long mb = (__ballot(hitb) >> gshift) & gmask;
+                if (hita) {
+                    const int slot = k + __popcll(ma & below);
+                    if (slot < lcap) {
+                        gd2[slot] = d2a;
+                        gj[slot] = ja;
+                    }
+                }
+                k += __popcll(ma);
+                if (hitb) {
+                    const int slot = k + __popcll(mb & below);
+                    if (slot < lcap) {
+                        gd2[slot] = d2b;
+                        gj[slot] = jb;
+                    }
+                }
+                k += __popcll(mb);
+            }
+        }
+    }
+    __syncthreads();
+    // rank: bucket B(d2) = floor(SB_NB (d2/r2)^(3/2)) in FP32 is non-decreasing
+    // in d2 (every operation is monotone), so entries of lower buckets rank
+    // lower; inside a bucket the exact (d2, id) comparison decides.  The 3/2
+    // power spreads a uniform particle density evenly over the buckets.
+    const bool ranked = active && k <= lcap;
+    const float inv_r2 = ranked ? (float)(1.0 / r2) : 0.0f;
+    constexpr int EMAX = 128 / G;  // entries per lane (k <= lcap <= 128)
+    int bk[EMAX];                  // bucket of each of this lane's entries
+    int pos[EMAX];                 // its place inside the bucket
+    if (ranked) {
+#pragma unroll
+        for (int q = 0; q < EMAX; ++q) {
+            const int e = lane + q * G;
+            if (e < k) {
+                const float x = (float)gd2[e] * inv_r2;
+                int bb = (int)((float)SB_NB * (x * sqrtf(x)));
+                bb = bb < 0 ? 0 : (bb > SB_NB - 1 ? SB_NB - 1 : bb);
+                bk[q] = bb;
+                pos[q] = atomicAdd(&gbk[bb], 1);
+            }
+        }
+    }
+    __syncthreads();
+    if (ranked) {
+        // exclusive scan of the bucket counts, in place (lane q holds buckets q, q + G, ...)
+        constexpr int BPL = SB_NB / G > 0 ? SB_NB / G : 1;  // buckets per lane
+        int cnt[BPL];
+        int mine = 0;
+#pragma unroll
+        for (int q = 0; q < BPL; ++q) {
+            const int bb = lane * BPL + q;
+            cnt[q] = bb < SB_NB ? gbk[bb] : 0;
+            mine += cnt[q];
+        }
+        int incl = mine;
+#pragma unroll
+        for (int o = 1; o < G; o <<= 1) {
+            const int v = __shfl_up(incl, o, G);
+            if (lane >= o) incl += v;
+        }
+        int run = incl - mine;
+#pragma unroll
+        for (int q = 0; q < BPL; ++q) {
+            const int bb = lane * BPL + q;
+            if (bb < SB_NB) gbk[bb] = run;  // start of bucket bb
+            run += cnt[q];
+        }
+    }
+    __syncthreads();
+    if (ranked) {
+#pragma unroll
+        for (int q = 0; q < EMAX; ++q) {
+            const int e = lane + q * G;
+            if (e < k) gperm[gbk[bk[q]] + pos[q]] = (unsigned char)e;
+        }
+    }
+    __syncthreads();
+    {
+        // largest count of the wave: one atomic per wave (all lanes active here)
+        int kmax = k;
+        for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o));
+        if ((threadIdx.x & 63) == 0 && kmax > 0) atomicMax(&sc->max_count, kmax);
+    }
+    if (active) {
+        if (lane == 0) {
+            count[s] = k;
+            if (k > max_nb) atomicOr(&sc->error_bits, 1u);
+            // the list does not fit the LDS buffer: one wave redoes it (and
+            // for k > max_nb writes max_nb valid entries, so readers stay in bounds)
+            if (k > lcap) ovf_queue[atomicAdd(&sc->n_overflow, 1)] = s;
+        }
+    }
+    int rank[EMAX], jq[EMAX];
+    if (ranked) {
+#pragma unroll
+        for (int q = 0; q < EMAX; ++q) {
+            const int e = lane + q * G;
+            if (e < k) {
+                const double de = gd2[e];
+                const int je = gj[e];
+                const int bb = bk[q];
+                const int lo = gbk[bb];
+                const int hi = bb + 1 < SB_NB ? gbk[bb + 1] : k;
+                int rk = lo;
+                for (int f = lo; f < hi; ++f) {
+                    const int pf = gperm[f];
+                    const double df = gd2[pf];
+                    if (df < de) ++rk;
+                    else if (df == de && pf != e && srt.id[gj[pf]] < srt.id[je]) ++rk;  // exact tie: id order
+                }
+                rank[q] = rk;
+                jq[q] = je;
+            }
+        }
+    }
+    __syncthreads();  // every group is done with its slots and counters
+    if (lane == 0) lk[grp] = ranked ? k : 0;
+    if (ranked) {
+#pragma unroll
+        for (int q = 0; q < EMAX; ++q)
+            if (lane + q * G < k) lout[rank[q] * PPB + grp] = jq[q];
+    }
+    __syncthreads();
+    // write the block's lists: with column-major lists the PPB particles of
+    // the block are consecutive in every column, so a column is one segment
+    const int s0 = xcd_remap(blockIdx.x, gridDim.x) * PPB;
+    int kb = 0;
+    for (int q = 0; q < PPB; ++q) kb = max(kb, lk[q]);
+    for (int idx = threadIdx.x; idx < kb * PPB; idx += LP_BLOCK) {
+        const int c = idx / PPB, gq = idx % PPB;
+        if (c < lk[gq]) {
+            const int sq = s0 + gq;
+            nbr[ldn > 0 ? (int64_t)c * ldn + sq : (int64_t)sq * (-ldn) + c] = lout[c * PPB + gq];
+        }
+    }
+}
+
 static size_t search_smem(int G, int lcap) {
     int ppb = LP_BLOCK / G;
     return (size_t)ppb * lcap * (8 + 4) + (size_t)ppb * 4;
 }
 
+// LDS of k_search_bal: per group, lcap + 1 (d2, index) slots, a byte
+// permutation and SB_NB bucket counters (the ranked lists reuse the slots)
+static size_t search_bal_smem(int G, int lcap) {
+    size_t ppb = (size_t)(LP_BLOCK / G);
+    size_t stride = (size_t)lcap + 1;
+    return ppb * stride * 12 + ppb * ((stride + 3) & ~(size_t)3) + ppb * SB_NB * 4;
+}
+
 template <int D, int G>
 static void launch_search_t(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real, const uint32_t *tables,
                             const DevGrid &g, const DevCfg &cfg, int *nbr, int ldn, int *count, DevScalars *sc,
-                            int lcap, int *ovf_queue, hipStream_t st) {
+                            int lcap, int *ovf_queue, bool balanced, hipStream_t st) {
     constexpr int PPB = LP_BLOCK / G;
     unsigned blocks = (unsigned)((n_total_cap + PPB - 1) / PPB);
     if (blocks < 1) blocks = 1;
-    size_t shm = search_smem(G, lcap);
-    hipLaunchKernelGGL((k_search<D, G>), dim3(blocks), dim3(LP_BLOCK), shm, st, s, n_total_dev, n_real, tables, g, cfg,
-                       nbr, ldn, count, sc, lcap, ovf_queue);
+    size_t shm = balanced ? search_bal_smem(G, lcap) : search_smem(G, lcap);
+    const bool per = cfg.periodic[0] || cfg.periodic[1] || (D == 3 && cfg.periodic[2]);
+    if (balanced && per)
+        hipLaunchKernelGGL((k_search_bal<D, G, true>), dim3(blocks), dim3(LP_BLOCK), shm, st, s, n_total_dev, n_real,
+                           tables, g, cfg, nbr, ldn, count, sc, lcap, ovf_queue);
+    else if (balanced)
+        hipLaunchKernelGGL((k_search_bal<D, G, false>), dim3(blocks), dim3(LP_BLOCK), shm, st, s, n_total_dev, n_real,
+                           tables, g, cfg, nbr, ldn, count, sc, lcap, ovf_queue);
+    else
+        hipLaunchKernelGGL((k_search<D, G>), dim3(blocks), dim3(LP_BLOCK), shm, st, s, n_total_dev, n_real, tables, g,
+                           cfg, nbr, ldn, count, sc, lcap, ovf_queue);
     unsigned ob = (unsigned)(n_total_cap < 1024 ? (n_total_cap > 0 ? n_total_cap : 1) : 1024);
     hipLaunchKernelGGL(k_search_overflow<D>, dim3(ob), dim3(64), 0, st, s, tables, g, cfg, nbr, ldn, sc, ovf_queue);
 }
 
 void launch_search(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real, const uint32_t *tables,
                    const DevGrid &g, const DevCfg &cfg, int *nbr, int ldn, int *count, DevScalars *sc, int group,
-                   int *ovf_queue, hipStream_t st) {
+                   int *ovf_queue, bool balanced, hipStream_t st) {
     int G = group;
     if (G != 4 && G != 8 && G != 16 && G != 32) G = 16;
     int lcap = cfg.max_nb < 128 ? cfg.max_nb : 128;
     // LDS per block within 64 KiB
-    while (search_smem(G, lcap) > 65536 && G < 64) G *= 2;
-#define LS(DD, GG) launch_search_t<DD, GG>(s, n_total_dev, n_total_cap, n_real, tables, g, cfg, nbr, ldn, count, sc, lcap, ovf_queue, st)
+    while ((balanced ? search_bal_smem(G, lcap) : search_smem(G, lcap)) > 65536 && G < 64) G *= 2;
+#define LS(DD, GG) launch_search_t<DD, GG>(s, n_total_dev, n_total_cap, n_real, tables, g, cfg, nbr, ldn, count, sc, lcap, ovf_queue, balanced, st)
     if (cfg.D == 3) {
         if (G == 4) LS(3, 4); else if (G == 8) LS(3, 8); else if (G == 16) LS(3, 16); else if (G == 32) LS(3, 32); else LS(3, 64);
     } else {

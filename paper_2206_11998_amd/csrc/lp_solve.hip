@@ -48,9 +48,7 @@ __device__ __forceinline__ void second_order_row(const T xi[3], T row[Dim<D>::NU
 template <int D>
 __device__ __forceinline__ void displacement(const Sorted &srt, const DevCfg &cfg, int j, const double xi[3],
                                              double dx[3]) {
-    dx[0] = min_image(cfg, 0, srt.x[0][j] - xi[0]);
-    dx[1] = min_image(cfg, 1, srt.x[1][j] - xi[1]);
-    dx[2] = D == 3 ? min_image(cfg, 2, srt.x[2][j] - xi[2]) : 0.0;
+    disp_to<D>(cfg, srt.x, j, xi, dx);
 }
 
 template <int D>
@@ -370,7 +368,7 @@ __device__ __forceinline__ T limiter(T r) {
 // its second-order derivatives.  Writes the caller's arrays at index i.
 // ---------------------------------------------------------------------------
 template <int D, typename T>
-__device__ __forceinline__ void finish_particle(const Sorted &srt, const Soa &p, const DevCfg &cfg, DevScalars *sc,
+__device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p, const DevCfg &cfg, DevScalars *sc,
                                                 const int *nbr, int ldn, int s, int i, int k, double dt,
                                                 const double xi[3], const double st[Dim<D>::NF], double h, double r,
                                                 const double grad[Dim<D>::NF][3], const double hess[Dim<D>::NF][Dim<D>::NS],
@@ -561,7 +559,7 @@ __device__ __forceinline__ void finish_particle(const Sorted &srt, const Soa &p,
     }
     if (p.flags) p.flags[i] = flags;
     if (p.phi && cfg.est_mode != LP_EST_INJECTED) p.phi[i] = (float)phi;
-    if (phi < 1.0) atomicAdd(&sc->n_limited, 1ull);
+    return phi < 1.0;  // limited: counted by the caller
 }
 
 
@@ -754,12 +752,12 @@ __device__ __forceinline__ void lw_fit_one(const SolveArgs &a, int s, int t) {
 // Half-ball fits, estimator, blended update and mover of one particle whose
 // second-order fit the fast path solved.
 template <int D, typename T>
-__device__ __forceinline__ void finish_one(const SolveArgs &a, int s, int t) {
+__device__ __forceinline__ bool finish_one(const SolveArgs &a, int s, int t) {
     constexpr int NF = Dim<D>::NF, NS = Dim<D>::NS, FP = D + 1;
     const Sorted &srt = a.srt;
     const DevCfg &cfg = a.cfg;
     int i = srt.id[s];
-    if (i >= a.n_real || a.lwst[s] != 0) return;
+    if (i >= a.n_real || a.lwst[s] != 0) return false;
     int k = a.count[s];
     if (k > cfg.max_nb) k = cfg.max_nb;
     double xi[3] = {srt.x[0][s], srt.x[1][s], D == 3 ? srt.x[2][s] : 0.0};
@@ -772,7 +770,8 @@ __device__ __forceinline__ void finish_one(const SolveArgs &a, int s, int t) {
     const double r = cfg.kappa * h;
     double grad[NF][3], hess[NF][NS];
     load_der<D>(a.der, a.ld, t, grad, hess);
-    finish_particle<D, T>(srt, a.p, cfg, a.sc, a.nbr, a.ldn, s, i, k, a.sc->dt, xi, st, h, r, grad, hess, 0, 0);
+    return finish_particle<D, T>(srt, a.p, cfg, a.sc, a.nbr, a.ldn, s, i, k, a.sc->dt, xi, st, h, r, grad, hess, 0,
+                                 0);
 }
 
 // Work distribution.  WQ_DIRECT: thread t of the grid serves cell-order
@@ -792,8 +791,7 @@ __device__ __forceinline__ void for_work(const SolveArgs &a, unsigned *head, F &
         });
     } else {
         int t = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-        if (t >= n) return;
-        body(MODE == WQ_QUEUE ? a.wq[t] : t, t);
+        if (t < n) body(MODE == WQ_QUEUE ? a.wq[t] : t, t);  // no early exit: callers reduce over the wave
     }
 }
 
@@ -804,7 +802,11 @@ __global__ __launch_bounds__(LP_BLOCK, 2) void k_lw_fit(SolveArgs a) {
 
 template <int D, typename T, int MODE>
 __global__ __launch_bounds__(LP_BLOCK) void k_finish(SolveArgs a) {
-    for_work<MODE>(a, a.sc->head[1], [&](int s, int t) { finish_one<D, T>(a, s, t); });
+    int limited = 0;
+    for_work<MODE>(a, a.sc->head[1], [&](int s, int t) { limited += finish_one<D, T>(a, s, t) ? 1 : 0; });
+    // one atomic per wave (every lane of the wave is active here)
+    for (int o = 32; o > 0; o >>= 1) limited += __shfl_xor(limited, o);
+    if ((threadIdx.x & 63) == 0 && limited) atomicAdd(&a.sc->n_limited, (unsigned long long)limited);
 }
 
 // Grid of a persistent launch: the blocks that can be resident at once.
@@ -1131,9 +1133,10 @@ __global__ __launch_bounds__(64) void k_solve_fallback(Sorted srt, Soa p, const 
                                             return f == 0 ? srt.V[j] : (f == FP ? srt.P[j] : srt.u[f - 1][j]);
                                         },
                                         grad, hess, sel);
-        if ((threadIdx.x & 63) == 0)
+        if ((threadIdx.x & 63) == 0 &&
             finish_particle<D, double>(srt, p, cfg, sc, nbr, ldn, s, i, k, sc->dt, xi, st, h, r, grad, hess, status,
-                                       LP_FLAG_FALLBACK);
+                                       LP_FLAG_FALLBACK))
+            atomicAdd(&sc->n_limited, 1ull);
         __syncthreads();
     }
 }

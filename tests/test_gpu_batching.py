@@ -124,7 +124,7 @@ def test_autotune_leaves_state_and_results(lp):
     say("autotune chose", best, "%.3f ms/step" % ms)
     assert ms > 0
     assert best["solve_mode"] in (0, 1, 2) and best["solve_block"] in (64, 128, 256)
-    assert best["search_mode"] in (0, 1) and best["search_group"] in (4, 8, 16, 32)
+    assert best["search_mode"] in (0, 1, 2) and best["search_group"] in (4, 8, 16, 32)
     assert best["queue_tile"] in (256, 512, 1024)
     assert ctx.info()["t"] == 0.0
     after = lp.state_to_host(dev)

@@ -25,7 +25,7 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-SEARCH_MODES = [0, 1]
+SEARCH_MODES = [0, 1, 2]
 
 
 def _nb_case(lp, oracle_lib, cfg, x, r, tag, mode=1):
