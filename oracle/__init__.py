@@ -80,7 +80,11 @@ def lib():
         L.lpo_timestep.argtypes = [cp, C.c_int64, dp, dp, dp]
         L.lpo_step_subset.restype = C.c_int
         L.lpo_step_subset.argtypes = [cp, C.c_int64, dp, dp, dp, dp, dp, dp, dp, dp, dp, C.c_double,
-                                      C.c_int64, i64p, dp, dp, dp, dp, dp, dp, dp, dp, dp, u8p, dp, i64p]
+                                      C.c_int64, i64p, dp, dp, dp, dp, dp, dp, dp, dp, dp, u8p, dp, i64p, dp]
+        L.lpo_mlp_forward.restype = None
+        L.lpo_mlp_forward.argtypes = [dp, C.c_int64, dp, dp, dp]
+        L.lpo_mlp_loss_grad.restype = C.c_double
+        L.lpo_mlp_loss_grad.argtypes = [dp, C.c_int64, dp, dp, dp]
         L.lpo_step.restype = C.c_int
         L.lpo_step.argtypes = [cp, C.c_int64, dp, dp, dp, dp, dp, dp, dp, dp, dp, C.c_double, dp, u8p,
                                dp, i64p]
@@ -265,8 +269,10 @@ def step(cfg: dict, state: dict, dt: float = 0.0):
     return new, {"dt": dt_used.value, "phi": phi, "flags": flags, "n_ghost": ng.value, "status": st}
 
 
-def step_subset(cfg: dict, state: dict, sub: np.ndarray, dt: float = 0.0):
-    """One time step evaluated only for the particles in ``sub`` (global dt, ghosts, neighbours)."""
+def step_subset(cfg: dict, state: dict, sub: np.ndarray, dt: float = 0.0, features: bool = False):
+    """One time step evaluated only for the particles in ``sub`` (global dt, ghosts, neighbours).
+    With features=True the result also holds the 16 estimator-network inputs
+    of every particle of ``sub`` (key "feat", shape (len(sub), 16))."""
     c = make_cfg(cfg)
     d = c.dim
     X, U, V, P, m = _state_cols(state, d)
@@ -278,12 +284,16 @@ def step_subset(cfg: dict, state: dict, sub: np.ndarray, dt: float = 0.0):
     flags = np.zeros(ns, dtype=np.uint8)
     dt_used = C.c_double(0.0)
     ng = C.c_int64(0)
+    feat = np.zeros((ns, 16)) if features else None
     st = lib().lpo_step_subset(C.byref(c), n, _dp(X[0]), _dp(X[1]), _dp(X[2]), _dp(V), _dp(U[0]), _dp(U[1]),
                                _dp(U[2]), _dp(P), _dp(m), float(dt), ns,
                                sub.ctypes.data_as(C.POINTER(C.c_int64)), *[_dp(a) for a in o], _dp(phi),
-                               flags.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(dt_used), C.byref(ng))
+                               flags.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(dt_used), C.byref(ng),
+                               _dp(feat) if features else None)
     out = {"x": np.stack(o[0:d], axis=1), "V": o[3], "u": np.stack(o[4:4 + d], axis=1), "P": o[7],
            "phi": phi, "flags": flags}
+    if features:
+        out["feat"] = feat
     return out, {"dt": dt_used.value, "n_ghost": ng.value, "status": st}
 
 
@@ -312,3 +322,27 @@ def particle_derivs(cfg: dict, state: dict, i: int, nb: np.ndarray, h: float, s:
                               _dp(grad), _dp(hess), _dp(dl), _dp(dr), _ip(valid), C.byref(phi), C.byref(flags))
     return {"grad": grad.reshape(5, 3), "hess": hess.reshape(5, 6), "dl": dl.reshape(3, 3),
             "dr": dr.reshape(3, 3), "valid": valid.reshape(3, 2), "phi": phi.value, "flags": flags.value}
+
+
+MLP_NPARAM = 5313
+
+
+def mlp_forward(theta: np.ndarray, feat: np.ndarray):
+    """Estimator network on feat (n x 16): returns (z, y = sigmoid(z))."""
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    feat = np.ascontiguousarray(feat, dtype=np.float64)
+    n = feat.shape[0]
+    z = np.zeros(n)
+    y = np.zeros(n)
+    lib().lpo_mlp_forward(_dp(theta), n, _dp(feat), _dp(z), _dp(y))
+    return z, y
+
+
+def mlp_loss_grad(theta: np.ndarray, feat: np.ndarray, target: np.ndarray):
+    """Mean binary cross-entropy of the network output against target, and its gradient."""
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    feat = np.ascontiguousarray(feat, dtype=np.float64)
+    target = np.ascontiguousarray(target, dtype=np.float64)
+    grad = np.zeros(MLP_NPARAM)
+    loss = lib().lpo_mlp_loss_grad(_dp(theta), feat.shape[0], _dp(feat), _dp(target), _dp(grad))
+    return loss, grad

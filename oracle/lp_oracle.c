@@ -462,6 +462,7 @@ typedef struct {
     int lw_degenerate, vacuum_used, substituted, insufficient;
     double phi;
     double rate[ORC_MAXF];
+    double vmin, vmax, pmin, pmax; /* V and P over the particle and its half-ball members */
 } particle_result;
 
 /* Fit the LW (second-order) polynomial for all fields over the selected rows.
@@ -565,6 +566,8 @@ static void solve_particle(const lpo_cfg *c, int64_t i, const int32_t *list, int
     res->lw_degenerate = st != 0;
     res->insufficient = st == 2;
     /* upwind one-sided fits on half-balls */
+    res->vmin = res->vmax = fi[0];
+    res->pmin = res->pmax = fi[D + 1];
     int uwcap = c->uw_cap > 0 ? c->uw_cap : 8;
     int *self = (int *)malloc(sizeof(int) * (size_t)(uwcap > 0 ? uwcap : 1));
     int *selo = (int *)malloc(sizeof(int) * (size_t)(uwcap > 0 ? uwcap : 1));
@@ -580,6 +583,13 @@ static void solve_particle(const lpo_cfg *c, int64_t i, const int32_t *list, int
             double *d = side == 0 ? res->dl + a * 3 : res->dr + a * 3;
             int *valid = side == 0 ? &res->valid_l[a] : &res->valid_r[a];
             int ms = uw_select(k, dxs, a, sgn, uwcap, self);
+            for (int t = 0; t < ms; ++t) {
+                double vj = fj[self[t] * nf + 0], pj = fj[self[t] * nf + D + 1];
+                if (vj < res->vmin) res->vmin = vj;
+                if (vj > res->vmax) res->vmax = vj;
+                if (pj < res->pmin) res->pmin = pj;
+                if (pj > res->pmax) res->pmax = pj;
+            }
             int ok = 0;
             if (c->vacuum && ms < uwcap) {
                 /* free boundary (step 3): the half-ball is incomplete, so it is
@@ -621,6 +631,142 @@ static void solve_particle(const lpo_cfg *c, int64_t i, const int32_t *list, int
     res->phi = ph < 1.0 ? ph : 1.0;
     if (res->lw_degenerate || res->vacuum_used) res->phi = 0.0;
     free(dxs); free(fj); free(fj3); free(sel);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Inputs of the learned state estimator.  The paper's estimator looks only   */
+/* at the quotient of left and right one-sided derivatives; the network that  */
+/* may stand in for it sees that quotient per field and axis together with    */
+/* the local gradients it comes from.  All inputs are dimensionless.          */
+/* ------------------------------------------------------------------------- */
+
+/* Disagreement of the two one-sided slopes of a field along one axis: |log| of
+ * their quotient, capped at 8, and 8 when they differ in sign; 0 where the
+ * estimator ignores the pair (a side without a usable fit, or both slopes
+ * below the activity threshold). */
+static double slope_disagreement(const lpo_cfg *c, double sl, double sr, double s, double h, int valid)
+{
+    if (!valid) return 0.0;
+    double big = fabs(sl) > fabs(sr) ? fabs(sl) : fabs(sr);
+    if (!(big * h > c->est_eps * fabs(s))) return 0.0;
+    if (!(sl * sr > 0.0)) return 8.0;
+    double q = fabs(log(fabs(sr) / fabs(sl)));
+    return q < 8.0 ? q : 8.0;
+}
+
+/* feat[0..2]  h d_a(rho) / rho = -h d_a V / V
+ * feat[3..5]  h d_a P / P
+ * feat[6]     h div u / c,  c = sqrt(gamma P V)
+ * feat[7..9]  slope disagreement of V along each axis (that of rho is the same)
+ * feat[10..12] slope disagreement of P along each axis
+ * feat[13]    log(V_max / V_min) and feat[14] log(P_max / P_min) over the
+ *             particle and its half-ball members
+ * feat[15]    h |grad u|_F / c
+ * Axes beyond the dimension give 0. */
+static void particle_features(const lpo_cfg *c, const double *fi, const particle_result *res, double h,
+                              double *feat)
+{
+    int D = c->dim;
+    double V = fi[0], P = fi[D + 1];
+    double cs = sqrt(c->gamma * P * V);
+    double div = 0.0, gu2 = 0.0;
+    for (int q = 0; q < 16; ++q) feat[q] = 0.0;
+    for (int a = 0; a < D; ++a) {
+        feat[a] = -h * res->grad[0 * 3 + a] / V;
+        feat[3 + a] = h * res->grad[(D + 1) * 3 + a] / P;
+        div += res->grad[(1 + a) * 3 + a];
+        for (int b = 0; b < D; ++b) gu2 += res->grad[(1 + a) * 3 + b] * res->grad[(1 + a) * 3 + b];
+        int valid = res->valid_l[a] && res->valid_r[a];
+        feat[7 + a] = slope_disagreement(c, res->dl[a * 3 + 0], res->dr[a * 3 + 0], V, h, valid);
+        feat[10 + a] = slope_disagreement(c, res->dl[a * 3 + 2], res->dr[a * 3 + 2], P, h, valid);
+    }
+    feat[6] = h * div / cs;
+    feat[13] = log(res->vmax / res->vmin);
+    feat[14] = log(res->pmax / res->pmin);
+    feat[15] = h * sqrt(gu2) / cs;
+}
+
+/* ------------------------------------------------------------------------- */
+/* The estimator network: 16 -> 64 (ReLU) -> 64 (ReLU) -> 1, output           */
+/* y = 1 / (1 + exp(-z)).  Parameters packed as W1[64][16], b1[64],           */
+/* W2[64][64], b2[64], w3[64], b3.  Loss: mean binary cross-entropy of y      */
+/* against targets t in [0, 1].                                               */
+/* ------------------------------------------------------------------------- */
+
+#define MLP_IN 16
+#define MLP_H 64
+#define OFF_W1 0
+#define OFF_B1 (OFF_W1 + MLP_H * MLP_IN)
+#define OFF_W2 (OFF_B1 + MLP_H)
+#define OFF_B2 (OFF_W2 + MLP_H * MLP_H)
+#define OFF_W3 (OFF_B2 + MLP_H)
+#define OFF_B3 (OFF_W3 + MLP_H)
+
+static double mlp_one(const double *th, const double *x, double *a1, double *h1, double *a2, double *h2)
+{
+    for (int o = 0; o < MLP_H; ++o) {
+        double s = th[OFF_B1 + o];
+        for (int f = 0; f < MLP_IN; ++f) s += th[OFF_W1 + o * MLP_IN + f] * x[f];
+        a1[o] = s;
+        h1[o] = s > 0.0 ? s : 0.0;
+    }
+    for (int o = 0; o < MLP_H; ++o) {
+        double s = th[OFF_B2 + o];
+        for (int q = 0; q < MLP_H; ++q) s += th[OFF_W2 + o * MLP_H + q] * h1[q];
+        a2[o] = s;
+        h2[o] = s > 0.0 ? s : 0.0;
+    }
+    double z = th[OFF_B3];
+    for (int o = 0; o < MLP_H; ++o) z += th[OFF_W3 + o] * h2[o];
+    return z;
+}
+
+void lpo_mlp_forward(const double *theta, int64_t n, const double *feat, double *z, double *y)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double a1[MLP_H], h1[MLP_H], a2[MLP_H], h2[MLP_H];
+        double zi = mlp_one(theta, feat + i * MLP_IN, a1, h1, a2, h2);
+        if (z) z[i] = zi;
+        if (y) y[i] = 1.0 / (1.0 + exp(-zi));
+    }
+}
+
+/* Mean loss over n samples; grad (LPO_MLP_NPARAM entries) receives its
+ * gradient by back-propagation through the three layers. */
+double lpo_mlp_loss_grad(const double *theta, int64_t n, const double *feat, const double *target, double *grad)
+{
+    for (int q = 0; q < LPO_MLP_NPARAM; ++q) grad[q] = 0.0;
+    double loss = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double *x = feat + i * MLP_IN;
+        double a1[MLP_H], h1[MLP_H], a2[MLP_H], h2[MLP_H];
+        double z = mlp_one(theta, x, a1, h1, a2, h2);
+        double t = target[i];
+        /* -t log y - (1 - t) log(1 - y) = softplus(z) - t z */
+        double sp = (z > 0.0 ? z : 0.0) + log1p(exp(-fabs(z)));
+        loss += sp - t * z;
+        double dz = (1.0 / (1.0 + exp(-z)) - t) / (double)n;
+        grad[OFF_B3] += dz;
+        double d2[MLP_H], d1[MLP_H];
+        for (int o = 0; o < MLP_H; ++o) {
+            grad[OFF_W3 + o] += dz * h2[o];
+            d2[o] = a2[o] > 0.0 ? dz * theta[OFF_W3 + o] : 0.0;
+            grad[OFF_B2 + o] += d2[o];
+        }
+        for (int q = 0; q < MLP_H; ++q) {
+            double s = 0.0;
+            for (int o = 0; o < MLP_H; ++o) {
+                grad[OFF_W2 + o * MLP_H + q] += d2[o] * h1[q];
+                s += theta[OFF_W2 + o * MLP_H + q] * d2[o];
+            }
+            d1[q] = a1[q] > 0.0 ? s : 0.0;
+            grad[OFF_B1 + q] += d1[q];
+        }
+        for (int o = 0; o < MLP_H; ++o)
+            for (int f = 0; f < MLP_IN; ++f) grad[OFF_W1 + o * MLP_IN + f] += d1[o] * x[f];
+    }
+    return loss / (double)n;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -709,7 +855,7 @@ int lpo_step_subset(const lpo_cfg *c, int64_t n, const double *x, const double *
                     const double *P, const double *m, double dt_in, int64_t nsub, const int64_t *sub,
                     double *ox, double *oy, double *oz, double *oV, double *ou, double *ov,
                     double *ow, double *oP, double *ophi, uint8_t *oflags, double *dt_used,
-                    int64_t *n_ghost)
+                    int64_t *n_ghost, double *ofeat)
 {
     int D = c->dim;
     const double *X0[3] = {x, y, z ? z : x};
@@ -791,6 +937,7 @@ int lpo_step_subset(const lpo_cfg *c, int64_t n, const double *x, const double *
             oV[t] = ns[0]; ou[t] = ns[1]; ov[t] = ns[2]; if (D == 3 && ow) ow[t] = ns[3];
             oP[t] = ns[D + 1];
             if (ophi) ophi[t] = res.phi;
+            if (ofeat) particle_features(c, stv, &res, h[i], ofeat + (size_t)t * 16);
             uint8_t fl = 0;
             if (res.phi < 1.0) fl |= LPO_FLAG_LIMITED;
             if (res.lw_degenerate) fl |= LPO_FLAG_DEGENERATE;
@@ -818,7 +965,7 @@ int lpo_step(const lpo_cfg *c, int64_t n, double *x, double *y, double *z, doubl
     double *o[8];
     for (int q = 0; q < 8; ++q) o[q] = buf + (size_t)q * (size_t)n;
     int st = lpo_step_subset(c, n, x, y, z, V, u, v, w, P, m, dt_in, n, sub, o[0], o[1], o[2], o[3],
-                             o[4], o[5], o[6], o[7], phi, flags, dt_used, n_ghost);
+                             o[4], o[5], o[6], o[7], phi, flags, dt_used, n_ghost, NULL);
     if (st == LPO_OK || st == LPO_E_NUMERIC) {
         memcpy(x, o[0], sizeof(double) * (size_t)n);
         memcpy(y, o[1], sizeof(double) * (size_t)n);

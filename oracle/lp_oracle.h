@@ -55,12 +55,16 @@ int lpo_step_subset(const lpo_cfg *c, int64_t n, const double *x, const double *
                     const double *P, const double *m, double dt_in, int64_t nsub, const int64_t *sub,
                     double *ox, double *oy, double *oz, double *oV, double *ou, double *ov,
                     double *ow, double *oP, double *ophi, uint8_t *oflags, double *dt_used,
-                    int64_t *n_ghost);
+                    int64_t *n_ghost, double *ofeat /* nsub x 16 or NULL: estimator-network inputs */);
 int lpo_step(const lpo_cfg *c, int64_t n, double *x, double *y, double *z, double *V, double *u,
              double *v, double *w, double *P, const double *m, double dt_in, double *phi,
              uint8_t *flags, double *dt_used, int64_t *n_ghost);
 void lpo_conservation(const lpo_cfg *c, int64_t n, const double *V, const double *u, const double *v,
                       const double *w, const double *P, const double *m, double *out);
+#define LPO_MLP_NPARAM 5313
+void lpo_mlp_forward(const double *theta, int64_t n, const double *feat, double *z, double *y);
+double lpo_mlp_loss_grad(const double *theta, int64_t n, const double *feat, const double *target,
+                         double *grad);
 int lpo_particle_derivs(const lpo_cfg *c, int64_t n, const double *x, const double *y, const double *z,
                         const double *V, const double *u, const double *v, const double *w,
                         const double *P, int64_t i, const int32_t *list, int32_t k, double h, double s,
