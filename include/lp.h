@@ -45,7 +45,11 @@ enum {
 };
 
 enum { LP_FP64 = 0, LP_MIXED = 1 };                         /* lp_config.precision */
-enum { LP_EST_PLAIN = 0, LP_EST_INJECTED = 1, LP_EST_MLP = 2 }; /* lp_config.estimator */
+/* lp_config.estimator: PLAIN is the quotient estimator of Sec. 2.1; INJECTED
+ * reads phi from lp_particles.phi; MLP lets the estimator network of
+ * lp_mlp_* decide phi where it is trusted (see mlp_band), with PLAIN as the
+ * fallback and phi = 0 kept for degenerate and vacuum particles. */
+enum { LP_EST_PLAIN = 0, LP_EST_INJECTED = 1, LP_EST_MLP = 2 };
 
 /* Per-particle flag bits written to lp_particles.flags. */
 enum {
@@ -78,7 +82,10 @@ typedef struct lp_config {
     uint32_t periodic_mask; /* bit a: axis a periodic (minimum image, wrap on move) */
     uint32_t wall_lo_mask;  /* bit a: mirror wall at box_lo[a] */
     uint32_t wall_hi_mask;  /* bit a: mirror wall at box_hi[a] */
-    int32_t reserved[9];
+    float mlp_band;         /* LP_EST_MLP: the network's phi is used when |phi - 1/2| >= mlp_band ... */
+    float mlp_feat_max;     /* ... and every input lies within +-mlp_feat_max; otherwise the quotient
+                               estimator's phi (defaults 0.05 and 8) */
+    int32_t reserved[7];
 } lp_config;
 
 typedef struct lp_particles {
@@ -101,6 +108,8 @@ typedef struct lp_info {
     int64_t n_limited;      /* particles with phi < 1 in the last step */
     uint32_t error_bits;    /* bit 0: capacity overflow, bit 1: numeric */
     int32_t levels[2];      /* cell-grid levels used by the last search (coarsest, finest) */
+    int64_t n_mlp;          /* LP_EST_MLP: particles whose phi came from the network in the last step */
+    int64_t n_mlp_plain;    /* LP_EST_MLP: particles that fell back to the quotient estimator */
 } lp_info;
 
 /* Fill cfg with the defaults for the given dimension (gamma 1.4, cfl 0.5,
@@ -181,8 +190,9 @@ lp_status lp_set_time(struct lp_ctx *ctx, void *stream, double t);
  * Stages: 0 radii/dt/ghosts, 1 cell ordering, 2 neighbour search (+ work
  * queue), 3 second-order fits (fast path), 4 half-ball fits + estimator +
  * update + mover, 5 FP64 pivoted-QR fallback, 6 whole step (also around each
- * graph replay of lp_run, whose inner stages are not timed). */
-#define LP_NSTAGES 7
+ * graph replay of lp_run, whose inner stages are not timed), 7 estimator
+ * network with the update it decides (LP_EST_MLP). */
+#define LP_NSTAGES 8
 #define LP_STAGE_STEP 6
 
 /* Launch-shape parameters (results are identical for every setting; only the
@@ -213,6 +223,67 @@ lp_status lp_autotune(struct lp_ctx *ctx, void *stream, const lp_particles *p, i
 lp_status lp_get_tuning(const struct lp_ctx *ctx, int32_t param, int32_t *value);
 lp_status lp_profile(struct lp_ctx *ctx, int32_t enable);
 lp_status lp_profile_read(struct lp_ctx *ctx, void *stream, double *ms, int64_t *count);
+
+/* ---------------------------------------------------------------------------
+ * Estimator network (not part of the paper's method): 16 -> 64 -> 64 -> 1 with
+ * ReLU hidden layers and a sigmoid output, standing in for the state
+ * estimator of the blended update (Sec. 2.1).  Inputs per particle, all
+ * dimensionless: h d_a(rho)/rho (3), h d_a P/P (3), h div u / c, for V and P
+ * on every axis the disagreement of the one-sided slopes that the quotient
+ * estimator looks at (|log| of their quotient, at most 8; 8 for opposite signs;
+ * 0 where the estimator ignores the pair) (6), log(V_max/V_min) and
+ * log(P_max/P_min) over the half-ball members (2), h |grad u|_F / c.
+ * Parameters (FP32, LP_MLP_NPARAM in this order): W1[64][16], b1[64],
+ * W2[64][64], b2[64], w3[64], b3.  Inference and training run on BF16 matrix
+ * instructions with FP32 accumulation.
+ * ------------------------------------------------------------------------- */
+#define LP_MLP_NIN 16
+#define LP_MLP_NPARAM 5313
+
+typedef struct lp_train_cfg {
+    int32_t epochs;         /* passes over the samples */
+    int32_t batch;          /* samples per Adam step */
+    float lr, beta1, beta2, eps;   /* Adam */
+    uint64_t seed;          /* order of the batches in every epoch */
+    int32_t reserved[6];
+} lp_train_cfg;
+
+/* Defaults: 10 epochs, batch 4096, lr 2e-3, beta1 0.9, beta2 0.999, eps 1e-8, seed 1. */
+void lp_train_cfg_default(lp_train_cfg *cfg);
+
+/* Inputs and quotient-estimator phi of every particle of p at its current
+ * state (Sec. 2.2 steps 1-5 as in lp_step, nothing advanced): feat (device,
+ * n * 16 floats, particle i at feat[16 i]), phi (device, n floats), valid
+ * (device, n bytes: 0 where phi = 0 is forced, for degenerate or vacuum
+ * particles).  These are the training samples of the network.  The output
+ * buffers are the caller's; valid may be NULL. */
+lp_status lp_features(struct lp_ctx *ctx, void *stream, const lp_particles *p, float *feat, float *phi,
+                      uint8_t *valid);
+
+/* Network parameters: lp_mlp_init draws He-uniform weights (zero biases)
+ * from seed; lp_mlp_set / lp_mlp_get copy all LP_MLP_NPARAM FP32 values from /
+ * to a host array (count must be LP_MLP_NPARAM).  lp_step with LP_EST_MLP
+ * returns LP_E_STATE until parameters are set. */
+lp_status lp_mlp_init(struct lp_ctx *ctx, uint64_t seed);
+lp_status lp_mlp_set(struct lp_ctx *ctx, const float *params, int64_t count);
+lp_status lp_mlp_get(struct lp_ctx *ctx, float *params, int64_t count);
+
+/* Network output for n samples: feat (device, n * 16), z (device, n) the
+ * pre-sigmoid output and y (device, n) the sigmoid; z or y may be NULL. */
+lp_status lp_mlp_forward(struct lp_ctx *ctx, void *stream, int64_t n, const float *feat, float *z, float *y);
+
+/* Mean binary cross-entropy of the network output against target (device,
+ * n floats in [0, 1]) and its gradient with respect to the parameters
+ * (host, LP_MLP_NPARAM floats); *loss host.  Synchronises. */
+lp_status lp_mlp_grad(struct lp_ctx *ctx, void *stream, int64_t n, const float *feat, const float *target,
+                      float *grad, float *loss);
+
+/* Adam on the mean binary cross-entropy over n samples (device feat, target),
+ * from the current parameters; loss (host, cfg->epochs floats, may be NULL)
+ * receives each epoch's mean batch loss.  Samples should come shuffled: the
+ * batches are contiguous ranges, visited in a seeded order.  Synchronises. */
+lp_status lp_mlp_train(struct lp_ctx *ctx, void *stream, int64_t n, const float *feat, const float *target,
+                       const lp_train_cfg *cfg, float *loss);
 
 const char *lp_status_str(lp_status s);
 const char *lp_last_error(const struct lp_ctx *ctx);

@@ -12,7 +12,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblp.so")
-SOURCES = ["lp_grid.hip", "lp_search.hip", "lp_solve.hip", "lp_api.hip"]
+SOURCES = ["lp_grid.hip", "lp_search.hip", "lp_solve.hip", "lp_mlp.hip", "lp_api.hip"]
 ARCH = os.environ.get("LP_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",

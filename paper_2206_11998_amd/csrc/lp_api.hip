@@ -31,7 +31,9 @@ struct lp_ctx {
     std::string err;
     // workspace
     Buf h, r, gcnt, scan_tmp, ghosts, key, slot, tables, sorted, sortedf, sid, nbr, count, queue, partials, consout,
-        gfd_fields, hitd2, hitj, tflags, tlo, thi, prep_part, ovfq, der, lwst, wq;
+        gfd_fields, hitd2, hitj, tflags, tlo, thi, prep_part, ovfq, der, lwst, wq,
+        mfeat, mrates, mphi, mflag,                          // network-estimator staging
+        theta, adam_m, adam_v, mgrad, mpart, mlosspart, mscal; // network parameters and training
     int search_mode = 2;            // 0: lane group walking its cells, 1: LDS-staged tiles, 2: balanced lane group
     int solve_block = 256;
     DevScalars *sc = nullptr;       // device scalars
@@ -59,6 +61,8 @@ struct lp_ctx {
     uint64_t gen = 1;               // bumped by every reallocation and grid change
     double grid_margin = 0.0;       // bounding-box margin of planned grids (lp_run plans with headroom)
     int solve_mode = 0;             // LP_TUNE_SOLVE_MODE
+    bool mlp_ready = false;         // network parameters set
+    bool want_stage = false;        // keep network-estimator staging allocated (lp_features)
     int queue_tile = 1024;          // LP_TUNE_QUEUE_TILE
 };
 
@@ -144,6 +148,8 @@ extern "C" void lp_config_default(lp_config *cfg, int32_t dim) {
     cfg->cond_fallback = 1e6;
     for (int a = 0; a < 3; ++a) { cfg->box_lo[a] = 0.0; cfg->box_hi[a] = 1.0; }
     cfg->periodic_mask = dim == 2 ? 3u : 7u;
+    cfg->mlp_band = 0.05f;
+    cfg->mlp_feat_max = 8.0f;
 }
 
 extern "C" const char *lp_status_str(lp_status s) {
@@ -182,8 +188,10 @@ extern "C" lp_status lp_create(const lp_config *cfg, lp_ctx **out) {
     else if (k.lw_cap < 0 || k.lw_cap > 64) st = fail(c, LP_E_ARG, "lw_cap must be in 0..64");
     else if (k.uw_cap < 0 || k.uw_cap > 16) st = fail(c, LP_E_ARG, "uw_cap must be in 0..16");
     else if (k.precision != LP_FP64 && k.precision != LP_MIXED) st = fail(c, LP_E_ARG, "bad precision");
-    else if (k.estimator != LP_EST_PLAIN && k.estimator != LP_EST_INJECTED)
-        st = fail(c, LP_E_ARG, "estimator mode not available in this build");
+    else if (k.estimator != LP_EST_PLAIN && k.estimator != LP_EST_INJECTED && k.estimator != LP_EST_MLP)
+        st = fail(c, LP_E_ARG, "unknown estimator mode");
+    else if (!(k.mlp_band >= 0.0f && k.mlp_band <= 0.5f) || !(k.mlp_feat_max > 0.0f))
+        st = fail(c, LP_E_ARG, "mlp_band must be in [0, 1/2], mlp_feat_max positive");
     else if (!(k.gamma > 1.0) || !(k.kappa > 0.0) || !(k.cfl > 0.0)) st = fail(c, LP_E_ARG, "gamma, kappa, cfl");
     if (st == LP_OK) {
         double S = 0.0;
@@ -225,6 +233,8 @@ extern "C" lp_status lp_create(const lp_config *cfg, lp_ctx **out) {
     d.cond_max = k.cond_max;
     d.uw_cond_max = k.uw_cond_max;
     d.cond_fb = k.cond_fallback;
+    d.mlp_band = k.mlp_band;
+    d.mlp_feat_max = k.mlp_feat_max;
     for (int a = 0; a < 3; ++a) {
         d.lo[a] = k.box_lo[a];
         d.hi[a] = k.box_hi[a];
@@ -260,7 +270,8 @@ extern "C" lp_status lp_destroy(lp_ctx *c) {
     Buf *bufs[] = {&c->h, &c->r, &c->gcnt, &c->scan_tmp, &c->ghosts, &c->key, &c->slot, &c->tables, &c->sorted,
                    &c->sortedf, &c->sid, &c->nbr, &c->count, &c->queue, &c->partials, &c->consout, &c->gfd_fields,
                    &c->hitd2, &c->hitj, &c->tflags, &c->tlo, &c->thi, &c->prep_part, &c->ovfq, &c->der, &c->lwst,
-                   &c->wq};
+                   &c->wq, &c->mfeat, &c->mrates, &c->mphi, &c->mflag, &c->theta, &c->adam_m, &c->adam_v,
+                   &c->mgrad, &c->mpart, &c->mlosspart, &c->mscal};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->sc) (void)hipFree(c->sc);
@@ -411,6 +422,12 @@ static lp_status ensure_capacity(lp_ctx *c, int64_t n_real, int64_t n_total, boo
         ENSURE(c, c->der, sizeof(double) * (size_t)der_count(D) * nt);
         ENSURE(c, c->lwst, (size_t)nt);
         ENSURE(c, c->wq, sizeof(int) * nt);
+        if (c->dc.est_mode == LP_EST_MLP || c->want_stage) {
+            ENSURE(c, c->mfeat, sizeof(float) * LP_MLP_NIN * nt);
+            ENSURE(c, c->mrates, sizeof(double) * 2 * (D + 2) * nt);
+            ENSURE(c, c->mphi, sizeof(double) * nt);
+            ENSURE(c, c->mflag, (size_t)nt);
+        }
     }
     if (c->search_mode == 1) {
         ENSURE(c, c->hitd2, sizeof(double) * (size_t)c->dc.max_nb * nt);
@@ -485,12 +502,20 @@ static void build_cells(lp_ctx *c, hipStream_t st, const double *const x[3], con
     launch_scan_u32(finest, nfin, (uint32_t *)c->scan_tmp.p, nullptr, st);
 }
 
+// Output buffers of lp_features (caller order, device).
+struct lp_features_out {
+    float *feat, *phi;
+    uint8_t *valid;
+};
+
 static lp_status check_particles(lp_ctx *c, const lp_particles *p) {
     if (!p || p->n <= 0 || p->n > (1ll << 30)) return fail(c, LP_E_ARG, "particle count must be in 1..2^30");
     for (int a = 0; a < c->dc.D; ++a)
         if (!p->x[a] || !p->u[a]) return fail(c, LP_E_ARG, "null position/velocity array");
     if (!p->V || !p->P || !p->m) return fail(c, LP_E_ARG, "null V, P or m");
     if (c->dc.est_mode == LP_EST_INJECTED && !p->phi) return fail(c, LP_E_ARG, "injected estimator needs phi");
+    if (c->dc.est_mode == LP_EST_MLP && !c->mlp_ready)
+        return fail(c, LP_E_STATE, "estimator network has no parameters (lp_mlp_init / lp_mlp_set)");
     return LP_OK;
 }
 
@@ -511,7 +536,7 @@ static Soa soa_of(const lp_particles *p) {
 // captured for graph replay: no host synchronisation, no allocation, kernels
 // sized to the capacities and bounded by the device-side counts).
 static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, double dt_in, bool sync_levels,
-                           int clip_t_end) {
+                           int clip_t_end, const lp_features_out *harvest = nullptr) {
     const int D = c->dc.D;
     const int n = (int)p->n;
     const bool mixed = c->dc.precision == LP_MIXED;
@@ -625,12 +650,31 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
     sv.ld = c->cap_total;
     sv.lwst = (uint8_t *)c->lwst.p;
     sv.wq = c->solve_mode != 0 ? (const int *)c->wq.p : nullptr;
+    // the network estimator (or a harvest of its inputs) stages the update
+    const bool staged = harvest || c->dc.est_mode == LP_EST_MLP;
+    if (staged) {
+        sv.ms.feat = (float *)c->mfeat.p;
+        sv.ms.rates = (double *)c->mrates.p;
+        sv.ms.phi_plain = (double *)c->mphi.p;
+        sv.ms.mflag = (uint8_t *)c->mflag.p;
+        sv.ms.ld = c->cap_total;
+    }
     launch_solve(sv, (int)n_total, c->solve_block, c->solve_mode, +between, &bt, st);
     stage_mark(c, st, 4, false);
     stage_mark(c, st, 5, true);
     launch_solve_fallback(srt, soa, (const int *)c->nbr.p, ldn, (const int *)c->count.p, n, c->dc, c->sc,
-                          (const int *)c->queue.p, n, st);
+                          (const int *)c->queue.p, n, sv.ms, st);
     stage_mark(c, st, 5, false);
+    if (harvest) {
+        launch_features_out(srt, sv.ms, &c->sc->n_total, n_total, n, harvest->feat, harvest->phi, harvest->valid, st);
+        HIPCHK(c, hipGetLastError());
+        return LP_OK;  // nothing advanced
+    }
+    if (staged) {
+        stage_mark(c, st, 7, true);
+        launch_mlp_apply((const float *)c->theta.p, srt, soa, c->dc, c->sc, n_total, n, sv.ms, st);
+        stage_mark(c, st, 7, false);
+    }
     launch_advance_time(c->sc, st);
     HIPCHK(c, hipGetLastError());
     return LP_OK;
@@ -889,6 +933,8 @@ extern "C" lp_status lp_get_info(lp_ctx *c, void *stream, lp_info *out) {
     out->error_bits = c->sc_host->error_bits;
     out->levels[0] = c->last_levels[0];
     out->levels[1] = c->last_levels[1];
+    out->n_mlp = (int64_t)c->sc_host->n_mlp;
+    out->n_mlp_plain = (int64_t)c->sc_host->n_mlp_plain;
     return LP_OK;
 }
 
@@ -1078,4 +1124,177 @@ extern "C" lp_status lp_autotune(lp_ctx *c, void *stream, const lp_particles *p,
     s = body();
     cleanup();
     return s;
+}
+
+// ---------------------------------------------------------------------------
+// Estimator network
+// ---------------------------------------------------------------------------
+extern "C" void lp_train_cfg_default(lp_train_cfg *cfg) {
+    memset(cfg, 0, sizeof *cfg);
+    cfg->epochs = 10;
+    cfg->batch = 4096;
+    cfg->lr = 2e-3f;
+    cfg->beta1 = 0.9f;
+    cfg->beta2 = 0.999f;
+    cfg->eps = 1e-8f;
+    cfg->seed = 1;
+}
+
+extern "C" lp_status lp_features(lp_ctx *c, void *stream, const lp_particles *p, float *feat, float *phi,
+                                 uint8_t *valid) {
+    if (!c) return LP_E_ARG;
+    if (!p || p->n <= 0 || p->n > (1ll << 30) || !feat || !phi) return fail(c, LP_E_ARG, "lp_features: bad arguments");
+    for (int a = 0; a < c->dc.D; ++a)
+        if (!p->x[a] || !p->u[a]) return fail(c, LP_E_ARG, "null position/velocity array");
+    if (!p->V || !p->P || !p->m) return fail(c, LP_E_ARG, "null V, P or m");
+    HIPCHK(c, hipSetDevice(c->device));
+    c->want_stage = true;
+    c->grid_margin = 0.0;
+    lp_features_out out{feat, phi, valid};
+    lp_particles q = *p;
+    q.phi = nullptr;  // nothing is written to the particles
+    q.flags = nullptr;
+    return step_impl(c, (hipStream_t)stream, &q, 0.0, true, 0, &out);
+}
+
+// splitmix64: a counter-based generator for the initial weights
+static uint64_t splitmix64(uint64_t &x) {
+    uint64_t z = (x += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+static lp_status mlp_alloc(lp_ctx *c) {
+    ENSURE(c, c->theta, sizeof(float) * LP_MLP_NPARAM);
+    ENSURE(c, c->adam_m, sizeof(float) * LP_MLP_NPARAM);
+    ENSURE(c, c->adam_v, sizeof(float) * LP_MLP_NPARAM);
+    ENSURE(c, c->mgrad, sizeof(float) * LP_MLP_NPARAM);
+    return LP_OK;
+}
+
+extern "C" lp_status lp_mlp_set(lp_ctx *c, const float *params, int64_t count) {
+    if (!c) return LP_E_ARG;
+    if (!params || count != LP_MLP_NPARAM) return fail(c, LP_E_ARG, "lp_mlp_set: need %d parameters", LP_MLP_NPARAM);
+    HIPCHK(c, hipSetDevice(c->device));
+    lp_status s = mlp_alloc(c);
+    if (s != LP_OK) return s;
+    HIPCHK(c, hipMemcpy(c->theta.p, params, sizeof(float) * LP_MLP_NPARAM, hipMemcpyHostToDevice));
+    c->mlp_ready = true;
+    return LP_OK;
+}
+
+extern "C" lp_status lp_mlp_get(lp_ctx *c, float *params, int64_t count) {
+    if (!c) return LP_E_ARG;
+    if (!params || count != LP_MLP_NPARAM) return fail(c, LP_E_ARG, "lp_mlp_get: need %d parameters", LP_MLP_NPARAM);
+    if (!c->mlp_ready) return fail(c, LP_E_STATE, "estimator network has no parameters");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipDeviceSynchronize());
+    HIPCHK(c, hipMemcpy(params, c->theta.p, sizeof(float) * LP_MLP_NPARAM, hipMemcpyDeviceToHost));
+    return LP_OK;
+}
+
+extern "C" lp_status lp_mlp_init(lp_ctx *c, uint64_t seed) {
+    if (!c) return LP_E_ARG;
+    std::vector<float> th(LP_MLP_NPARAM, 0.0f);
+    uint64_t state = seed;
+    auto uniform = [&](double bound) {
+        double u = (double)(splitmix64(state) >> 11) * (1.0 / 9007199254740992.0);  // [0, 1)
+        return (float)((2.0 * u - 1.0) * bound);
+    };
+    const int nin = LP_MLP_NIN, nh = 64;
+    const int off_w1 = 0, off_w2 = nh * nin + nh, off_w3 = off_w2 + nh * nh + nh;
+    for (int q = 0; q < nh * nin; ++q) th[off_w1 + q] = uniform(sqrt(6.0 / nin));
+    for (int q = 0; q < nh * nh; ++q) th[off_w2 + q] = uniform(sqrt(6.0 / nh));
+    for (int q = 0; q < nh; ++q) th[off_w3 + q] = uniform(sqrt(6.0 / nh));
+    return lp_mlp_set(c, th.data(), LP_MLP_NPARAM);
+}
+
+extern "C" lp_status lp_mlp_forward(lp_ctx *c, void *stream, int64_t n, const float *feat, float *z, float *y) {
+    if (!c) return LP_E_ARG;
+    if (n < 0 || (n > 0 && !feat)) return fail(c, LP_E_ARG, "lp_mlp_forward: bad arguments");
+    if (!c->mlp_ready) return fail(c, LP_E_STATE, "estimator network has no parameters");
+    if (n == 0) return LP_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    launch_mlp_forward((const float *)c->theta.p, n, feat, z, y, (hipStream_t)stream);
+    HIPCHK(c, hipGetLastError());
+    return LP_OK;
+}
+
+static lp_status mlp_train_buffers(lp_ctx *c, int64_t batch, int epochs) {
+    lp_status s = mlp_alloc(c);
+    if (s != LP_OK) return s;
+    ENSURE(c, c->mpart, sizeof(float) * (size_t)mlp_grad_blocks(batch) * LP_MLP_NPARAM);
+    ENSURE(c, c->mlosspart, sizeof(float) * (size_t)mlp_grad_blocks(batch));
+    ENSURE(c, c->mscal, sizeof(float) * (size_t)(2 + (epochs > 0 ? epochs : 0)));
+    return LP_OK;
+}
+
+extern "C" lp_status lp_mlp_grad(lp_ctx *c, void *stream, int64_t n, const float *feat, const float *target,
+                                 float *grad, float *loss) {
+    if (!c) return LP_E_ARG;
+    if (n <= 0 || !feat || !target || !grad) return fail(c, LP_E_ARG, "lp_mlp_grad: bad arguments");
+    if (!c->mlp_ready) return fail(c, LP_E_STATE, "estimator network has no parameters");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    lp_status s = mlp_train_buffers(c, n, 0);
+    if (s != LP_OK) return s;
+    float *scal = (float *)c->mscal.p;
+    launch_mlp_grad((const float *)c->theta.p, 0, n, feat, target, (float *)c->mpart.p, (float *)c->mlosspart.p,
+                    (float *)c->mgrad.p, scal, st);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(grad, c->mgrad.p, sizeof(float) * LP_MLP_NPARAM, hipMemcpyDeviceToHost, st));
+    float l = 0.f;
+    HIPCHK(c, hipMemcpyAsync(&l, scal, sizeof(float), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (loss) *loss = l;
+    return LP_OK;
+}
+
+extern "C" lp_status lp_mlp_train(lp_ctx *c, void *stream, int64_t n, const float *feat, const float *target,
+                                  const lp_train_cfg *cfg, float *loss) {
+    if (!c) return LP_E_ARG;
+    if (n <= 0 || !feat || !target || !cfg) return fail(c, LP_E_ARG, "lp_mlp_train: bad arguments");
+    if (cfg->epochs < 0 || cfg->batch < 16 || !(cfg->lr > 0.f) || !(cfg->beta1 >= 0.f && cfg->beta1 < 1.f) ||
+        !(cfg->beta2 >= 0.f && cfg->beta2 < 1.f) || !(cfg->eps > 0.f))
+        return fail(c, LP_E_ARG, "lp_mlp_train: bad training configuration");
+    if (!c->mlp_ready) return fail(c, LP_E_STATE, "estimator network has no parameters");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t batch = cfg->batch < n ? cfg->batch : n;
+    lp_status s = mlp_train_buffers(c, batch, cfg->epochs);
+    if (s != LP_OK) return s;
+    float *scal = (float *)c->mscal.p;  // [0] batch loss, [1] unused, [2 + e] summed batch losses of epoch e
+    launch_fill_f32((float *)c->adam_m.p, LP_MLP_NPARAM, 0.f, st);
+    launch_fill_f32((float *)c->adam_v.p, LP_MLP_NPARAM, 0.f, st);
+    launch_fill_f32(scal, 2 + cfg->epochs, 0.f, st);
+    const int64_t nbatch = (n + batch - 1) / batch;
+    std::vector<int64_t> order((size_t)nbatch);
+    uint64_t rng = cfg->seed;
+    int t = 0;
+    for (int e = 0; e < cfg->epochs; ++e) {
+        for (int64_t b = 0; b < nbatch; ++b) order[(size_t)b] = b;
+        for (int64_t b = nbatch - 1; b > 0; --b) {  // Fisher-Yates
+            int64_t q = (int64_t)(splitmix64(rng) % (uint64_t)(b + 1));
+            std::swap(order[(size_t)b], order[(size_t)q]);
+        }
+        for (int64_t b = 0; b < nbatch; ++b) {
+            const int64_t b0 = order[(size_t)b] * batch;
+            const int64_t nb = n - b0 < batch ? n - b0 : batch;
+            launch_mlp_grad((const float *)c->theta.p, b0, nb, feat, target, (float *)c->mpart.p,
+                            (float *)c->mlosspart.p, (float *)c->mgrad.p, scal, st);
+            launch_mlp_adam((float *)c->theta.p, (float *)c->adam_m.p, (float *)c->adam_v.p,
+                            (const float *)c->mgrad.p, cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, ++t, scal,
+                            scal + 2 + e, st);
+        }
+    }
+    HIPCHK(c, hipGetLastError());
+    if (loss && cfg->epochs > 0) {
+        std::vector<float> acc((size_t)cfg->epochs);
+        HIPCHK(c, hipMemcpyAsync(acc.data(), scal + 2, sizeof(float) * cfg->epochs, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        for (int e = 0; e < cfg->epochs; ++e) loss[e] = acc[(size_t)e] / (float)nbatch;
+    }
+    HIPCHK(c, hipStreamSynchronize(st));
+    return LP_OK;
 }

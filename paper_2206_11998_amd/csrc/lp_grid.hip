@@ -30,6 +30,8 @@ __global__ void k_reset_scalars(DevScalars *sc, double dt_in, int n_real, int cl
     sc->n_fallback = 0;
     sc->n_overflow = 0;
     sc->n_limited = 0ull;
+    sc->n_mlp = 0ull;
+    sc->n_mlp_plain = 0ull;
     sc->done = 0u;  // recomputed by k_dt from t and t_end
     if (clear_halt) sc->halt = 0u;
     for (int a = 0; a < 3; ++a) { sc->xlo[a] = ~0ull; sc->xhi[a] = 0ull; }

@@ -21,6 +21,7 @@ struct DevCfg {
     double gamma, kappa, cfl, est_eps, cond_max, uw_cond_max, cond_fb;
     double lo[3], hi[3], L[3], half[3];
     int periodic[3], wall_lo[3], wall_hi[3];
+    float mlp_band, mlp_feat_max;   // network estimator: trusted away from 1/2 by mlp_band, inputs within +-max
 };
 
 // Hierarchy of uniform cell grids over the cube [lo, lo + S)^D.  Level L has
@@ -54,6 +55,8 @@ struct DevScalars {
     unsigned long long xlo[3], xhi[3];  // bounding box of real particles (order-preserving keys)
     unsigned long long n_limited;
     unsigned long long steps;       // steps executed (skipped steps do not count)
+    unsigned long long n_mlp;       // particles whose phi came from the network in the last step
+    unsigned long long n_mlp_plain; // particles for which the network was not trusted
     unsigned int head[2][8];        // chunk counters of the persistent fit / update launches, per XCD range
 };
 
@@ -124,6 +127,19 @@ void launch_search_tiles(const Sorted &s, const int *n_total_dev, int n_total_ca
 void launch_lists_out(const int *sorted_id, const int *nbr, int ldn, const int *count, int n, int max_nb,
                       int *count_out, int *idx_out, hipStream_t st);
 int der_count(int D);
+// Staging of the update when the network estimator decides phi: per
+// cell-order particle s its 16 inputs feat[16 s + q], the LW and upwind rates
+// rates[f * ld + s] and rates[(NF + f) * ld + s], the quotient estimator's
+// phi and the particle flags (LP_MLP_FORCE0: phi = 0 whatever the network says).
+#define LP_MLP_FORCE0 128
+struct MlpStage {
+    float *feat;
+    double *rates;
+    double *phi_plain;
+    uint8_t *mflag;
+    int64_t ld;
+};
+
 // Everything the fit and update kernels read or write.
 struct SolveArgs {
     Sorted srt;
@@ -140,6 +156,7 @@ struct SolveArgs {
     int64_t ld;
     uint8_t *lwst;                  // per particle: 0 fast path, 1 queued for the fallback
     const int *wq;                  // work queue of launch_bin_tiles (NULL: direct indexing)
+    MlpStage ms;                    // feat != NULL: stage for the network estimator instead of updating
 };
 // mode: 0 direct, 1 work queue, 2 persistent launch over the work queue
 void launch_solve(const SolveArgs &a, int n_total_cap, int block, int mode, void (*between)(void *),
@@ -148,7 +165,19 @@ void launch_bin_tiles(const int *count, const int *sid, const int *n_total_dev, 
                       int max_nb, int tile, int *wq, hipStream_t st);
 void launch_solve_fallback(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count,
                            int n_real, const DevCfg &cfg, DevScalars *sc, const int *queue, int queue_cap,
-                           hipStream_t st);
+                           const MlpStage &ms, hipStream_t st);
+// network estimator (lp_mlp.hip)
+void launch_mlp_forward(const float *th, int64_t n, const float *feat, float *z, float *y, hipStream_t st);
+void launch_mlp_apply(const float *th, const Sorted &s, const Soa &p, const DevCfg &cfg, DevScalars *sc,
+                      int64_t n_total_cap, int n_real, const MlpStage &ms, hipStream_t st);
+int mlp_grad_blocks(int64_t nb);
+void launch_mlp_grad(const float *th, int64_t b0, int64_t nb, const float *feat, const float *target, float *part,
+                     float *loss_part, float *grad, float *loss, hipStream_t st);
+void launch_mlp_adam(float *th, float *m, float *v, const float *grad, float lr, float b1, float b2, float eps,
+                     int t, const float *loss, float *loss_acc, hipStream_t st);
+void launch_features_out(const Sorted &s, const MlpStage &ms, const int *n_total_dev, int64_t n_total_cap,
+                         int n_real, float *feat, float *phi, uint8_t *valid, hipStream_t st);
+void launch_fill_f32(float *p, int n, float v, hipStream_t st);
 void launch_gfd(const Sorted &s, const double *const *fs, int nf, const int *nbr, int ldn, const int *count,
                 int n, const DevCfg &cfg, DevScalars *sc, int *queue, double *deriv, uint8_t *status,
                 hipStream_t st);

@@ -1,0 +1,499 @@
+// lp_mlp.hip -- the learned state estimator on gfx950: a 16 -> 64 -> 64 -> 1
+// network (ReLU hidden layers, sigmoid output) that may stand in for the
+// quotient estimator of the blended update (Sec. 2.1, state estimator), with
+// the quotient estimator kept as the fallback.  Not part of the paper's method.
+//
+// Both directions run on BF16 matrix cores (v_mfma_f32_16x16x16_bf16) with
+// FP32 accumulation; FP32 master weights.  One wave handles a tile of 16
+// samples.  Every layer is computed transposed, Y^T = W X^T, so that the
+// accumulator fragment of one layer (lane l: sample l % 16, units
+// 4 (l / 16) .. +3) is exactly the B-operand fragment of the next.
+//
+// Operand fragments of the 16x16x16 instruction, lane l, element v = 0..3:
+//   A[i][k]: i = l % 16, k = 4 (l / 16) + v
+//   B[k][j]: j = l % 16, k = 4 (l / 16) + v
+//   D[i][j]: j = l % 16, i = 4 (l / 16) + v
+#include "lp_internal.h"
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+#define MLP_IN 16
+#define MLP_H 64
+#define OFF_W1 0
+#define OFF_B1 (OFF_W1 + MLP_H * MLP_IN)
+#define OFF_W2 (OFF_B1 + MLP_H)
+#define OFF_B2 (OFF_W2 + MLP_H * MLP_H)
+#define OFF_W3 (OFF_B2 + MLP_H)
+#define OFF_B3 (OFF_W3 + MLP_H)
+static_assert(OFF_B3 + 1 == LP_MLP_NPARAM, "parameter layout");
+
+// FP32 -> BF16, round to nearest even (NaN stays NaN)
+__device__ __forceinline__ short f2bf(float f) {
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x4 zero4() {
+    f32x4 z = {0.f, 0.f, 0.f, 0.f};
+    return z;
+}
+
+// Weights of one wave, in fragment order.
+struct MlpRegs {
+    bf16x4 a1[4];       // W1 tiles (unit block ob): W1[16 ob + l%16][4 (l/16) + v]
+    bf16x4 a2[4][4];    // W2 tiles [ob][kb]: W2[16 ob + l%16][16 kb + 4 (l/16) + v]
+    float b1[4][4];     // b1[16 ob + 4 (l/16) + v]
+    float b2[4][4];
+    float w3[4][4];
+    float b3;
+};
+
+__device__ __forceinline__ void load_regs(const float *th, MlpRegs &R) {
+    const int l = threadIdx.x & 63, r = l & 15, c = 4 * (l >> 4);
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            R.a1[ob][v] = f2bf(th[OFF_W1 + (16 * ob + r) * MLP_IN + c + v]);
+            R.b1[ob][v] = th[OFF_B1 + 16 * ob + c + v];
+            R.b2[ob][v] = th[OFF_B2 + 16 * ob + c + v];
+            R.w3[ob][v] = th[OFF_W3 + 16 * ob + c + v];
+        }
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) R.a2[ob][kb][v] = f2bf(th[OFF_W2 + (16 * ob + r) * MLP_H + 16 * kb + c + v]);
+    }
+    R.b3 = th[OFF_B3];
+}
+
+// Input fragment: features 4 (l/16) .. +3 of sample l % 16 (zero when absent).
+__device__ __forceinline__ bf16x4 load_x(const float *feat, int64_t idx, bool ok) {
+    const int c = 4 * ((threadIdx.x & 63) >> 4);
+    bf16x4 x;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) x[v] = ok ? f2bf(feat[idx * MLP_IN + c + v]) : (short)0;
+    return x;
+}
+
+// Forward pass of the tile: pre-activations d1, d2 (FP32, bias added), the
+// BF16 hidden fragment h1 and the output z of sample l % 16 (in every lane).
+__device__ __forceinline__ float forward(const MlpRegs &R, bf16x4 x, f32x4 d1[4], bf16x4 h1[4], f32x4 d2[4]) {
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+        d1[ob] = mfma16(R.a1[ob], x, zero4());
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            d1[ob][v] += R.b1[ob][v];
+            h1[ob][v] = f2bf(d1[ob][v] > 0.f ? d1[ob][v] : 0.f);
+        }
+    }
+    float zp = 0.f;
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+        f32x4 acc = zero4();
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) acc = mfma16(R.a2[ob][kb], h1[kb], acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            acc[v] += R.b2[ob][v];
+            zp += R.w3[ob][v] * (acc[v] > 0.f ? acc[v] : 0.f);
+        }
+        d2[ob] = acc;
+    }
+    // the four lanes of a sample (l, l+16, l+32, l+48) hold a quarter each
+    zp += __shfl_xor(zp, 16);
+    zp += __shfl_xor(zp, 32);
+    return zp + R.b3;
+}
+
+__device__ __forceinline__ float sigmoidf(float z) { return 1.f / (1.f + __expf(-z)); }
+
+// ---------------------------------------------------------------------------
+// Network output z (and sigmoid) for n samples: one wave per tile of 16.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_mlp_forward(const float *th, int64_t n, const float *feat, float *z_out,
+                                                    float *y_out) {
+    MlpRegs R;
+    load_regs(th, R);
+    const int l = threadIdx.x & 63;
+    const int64_t ntile = (n + 15) / 16;
+    for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        const int64_t idx = tile * 16 + (l & 15);
+        const bool ok = idx < n;
+        f32x4 d1[4], d2[4];
+        bf16x4 h1[4];
+        const float z = forward(R, load_x(feat, idx, ok), d1, h1, d2);
+        if (ok && l < 16) {
+            if (z_out) z_out[idx] = z;
+            if (y_out) y_out[idx] = sigmoidf(z);
+        }
+    }
+}
+
+void launch_mlp_forward(const float *th, int64_t n, const float *feat, float *z, float *y, hipStream_t st) {
+    int64_t nt = (n + 15) / 16;
+    unsigned g = (unsigned)(nt < 4096 ? (nt > 0 ? nt : 1) : 4096);
+    hipLaunchKernelGGL(k_mlp_forward, dim3(g), dim3(64), 0, st, th, n, feat, z, y);
+    (void)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Estimator stage of a step with the network: phi from the network where it
+// is trusted, the quotient estimator's phi elsewhere, then the blended update
+// and the mover -- the same arithmetic as the update kernel.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(64) void k_mlp_apply(const float *th, Sorted srt, Soa p, DevCfg cfg, DevScalars *sc,
+                                                  int n_real, MlpStage ms) {
+    constexpr int NF = D + 2, FP = D + 1;
+    MlpRegs R;
+    load_regs(th, R);
+    const int l = threadIdx.x & 63;
+    const int n_total = sc->n_total;
+    const double dt = sc->dt;
+    const int64_t ntile = ((int64_t)n_total + 15) / 16;
+    unsigned long long used = 0, plain = 0, lim = 0;
+    for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        const int s = (int)(tile * 16 + (l & 15));
+        bool ok = s < n_total;
+        const int i = ok ? srt.id[s] : n_real;
+        ok = ok && i < n_real;
+        f32x4 d1[4], d2[4];
+        bf16x4 h1[4];
+        const float z = forward(R, load_x(ms.feat, s, ok), d1, h1, d2);
+        if (!(ok && l < 16)) continue;
+        const uint8_t mf = ms.mflag[s];
+        double phi;
+        if (mf & LP_MLP_FORCE0) {
+            phi = 0.0;
+        } else {
+            // trusted: every input within range and the output away from 1/2
+            bool in_range = true;
+#pragma unroll
+            for (int q = 0; q < MLP_IN; ++q) {
+                const float f = ms.feat[(int64_t)s * MLP_IN + q];
+                in_range = in_range && fabsf(f) <= cfg.mlp_feat_max;
+            }
+            const float y = sigmoidf(z);
+            if (in_range && fabsf(y - 0.5f) >= cfg.mlp_band) {
+                phi = (double)y;
+                ++used;
+            } else {
+                phi = ms.phi_plain[s];
+                ++plain;
+            }
+        }
+        double st[NF], ns[NF];
+        st[0] = srt.V[s];
+#pragma unroll
+        for (int a = 0; a < D; ++a) st[1 + a] = srt.u[a][s];
+        st[FP] = srt.P[s];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const double u_ = ms.rates[(int64_t)(NF + f) * ms.ld + s], l_ = ms.rates[(int64_t)f * ms.ld + s];
+            ns[f] = st[f] + dt * (u_ - phi * (u_ - l_));
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            double xn = srt.x[a][s] + 0.5 * dt * (st[1 + a] + ns[1 + a]);
+            if (cfg.periodic[a]) {
+                if (xn >= cfg.hi[a]) xn -= cfg.L[a];
+                else if (xn < cfg.lo[a]) xn += cfg.L[a];
+            }
+            p.x[a][i] = xn;
+            p.u[a][i] = ns[1 + a];
+        }
+        p.V[i] = ns[0];
+        p.P[i] = ns[FP];
+        uint8_t flags = mf & (uint8_t)~LP_MLP_FORCE0;
+        if (phi < 1.0) {
+            flags |= LP_FLAG_LIMITED;
+            ++lim;
+        }
+        if (!(ns[0] > 0.0) || !(ns[FP] > 0.0)) {
+            flags |= LP_FLAG_NUMERIC;
+            atomicOr(&sc->error_bits, 2u);
+        }
+        if (p.flags) p.flags[i] = flags;
+        if (p.phi) p.phi[i] = (float)phi;
+    }
+    // one atomic per wave and counter (every lane of the wave is active here)
+    for (int o = 32; o > 0; o >>= 1) {
+        used += __shfl_xor(used, o);
+        plain += __shfl_xor(plain, o);
+        lim += __shfl_xor(lim, o);
+    }
+    if (l == 0) {
+        if (used) atomicAdd(&sc->n_mlp, used);
+        if (plain) atomicAdd(&sc->n_mlp_plain, plain);
+        if (lim) atomicAdd(&sc->n_limited, lim);
+    }
+}
+
+void launch_mlp_apply(const float *th, const Sorted &s, const Soa &p, const DevCfg &cfg, DevScalars *sc,
+                      int64_t n_total_cap, int n_real, const MlpStage &ms, hipStream_t st) {
+    int64_t nt = (n_total_cap + 15) / 16;
+    unsigned g = (unsigned)(nt < 8192 ? (nt > 0 ? nt : 1) : 8192);
+    if (cfg.D == 3)
+        hipLaunchKernelGGL(k_mlp_apply<3>, dim3(g), dim3(64), 0, st, th, s, p, cfg, sc, n_real, ms);
+    else
+        hipLaunchKernelGGL(k_mlp_apply<2>, dim3(g), dim3(64), 0, st, th, s, p, cfg, sc, n_real, ms);
+    (void)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Training: forward and backward of the mean binary cross-entropy over a
+// batch.  Every block (one wave) accumulates its tiles' gradient in registers
+// and writes it, complete, to its row of part[]; k_mlp_reduce sums the rows in
+// a fixed order.  Weight gradients sum over samples, so their products take
+// the sample index as the contraction dimension: the fragments are turned
+// around through LDS.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_mlp_grad(const float *th, int64_t b0, int64_t nb, const float *feat,
+                                                 const float *target, float inv_batch, float *part,
+                                                 float *loss_part) {
+    __shared__ short sA[MLP_H * 16];   // [unit][sample], BF16
+    __shared__ short sB[MLP_H * 16];   // [unit][sample], BF16
+    __shared__ short sX[MLP_IN * 16];  // [feature][sample], BF16
+    MlpRegs R;
+    load_regs(th, R);
+    const int l = threadIdx.x & 63, r = l & 15, c = 4 * (l >> 4);
+    // W2 transposed tiles [ib][kb]: W2[16 kb + 4 (l/16) + v][16 ib + l%16]
+    bf16x4 a2t[4][4];
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) a2t[ib][kb][v] = f2bf(th[OFF_W2 + (16 * kb + c + v) * MLP_H + 16 * ib + r]);
+    f32x4 g1[4], g2[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        g1[q] = zero4();
+#pragma unroll
+        for (int w = 0; w < 4; ++w) g2[q][w] = zero4();
+    }
+    float gb1[4][4], gb2[4][4], gw3[4][4], gb3 = 0.f, loss = 0.f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) { gb1[q][v] = 0.f; gb2[q][v] = 0.f; gw3[q][v] = 0.f; }
+
+    const int64_t ntile = (nb + 15) / 16;
+    for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        const int64_t j = tile * 16 + r;  // sample of this lane, within the batch
+        const bool ok = j < nb;
+        const int64_t idx = b0 + j;
+        const bf16x4 x = load_x(feat, idx, ok);
+        f32x4 d1[4], d2[4];
+        bf16x4 h1[4];
+        const float z = forward(R, x, d1, h1, d2);
+        const float t = ok ? target[idx] : 0.f;
+        const float y = sigmoidf(z);
+        const float dz = ok ? (y - t) * inv_batch : 0.f;
+        if (ok && l < 16) {
+            loss += (z > 0.f ? z : 0.f) + log1pf(__expf(-fabsf(z))) - t * z;
+            gb3 += dz;
+        }
+        // output layer and second hidden layer
+        bf16x4 da2[4];
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float a2 = d2[ob][v];
+                gw3[ob][v] += dz * (a2 > 0.f ? a2 : 0.f);
+                const float g = a2 > 0.f ? dz * R.w3[ob][v] : 0.f;
+                gb2[ob][v] += g;
+                da2[ob][v] = f2bf(g);
+            }
+        // dW2 = dA2 H1^T over the tile's samples
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                sA[(16 * ob + c + v) * 16 + r] = da2[ob][v];
+                sB[(16 * ob + c + v) * 16 + r] = h1[ob][v];
+            }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sX[(c + v) * 16 + r] = x[v];
+        __syncthreads();
+        bf16x4 fa[4], fb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                fa[q][v] = sA[(16 * q + r) * 16 + c + v];
+                fb[q][v] = sB[(16 * q + r) * 16 + c + v];
+            }
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib) g2[ob][ib] = mfma16(fa[ob], fb[ib], g2[ob][ib]);
+        // dH1 = W2^T dA2, through the first hidden layer's ReLU
+        bf16x4 da1[4];
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) {
+            f32x4 acc = zero4();
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) acc = mfma16(a2t[ib][kb], da2[kb], acc);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float g = d1[ib][v] > 0.f ? acc[v] : 0.f;
+                gb1[ib][v] += g;
+                da1[ib][v] = f2bf(g);
+            }
+        }
+        __syncthreads();  // sA is reused
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sA[(16 * ob + c + v) * 16 + r] = da1[ob][v];
+        __syncthreads();
+        // dW1 = dA1 X over the tile's samples
+        bf16x4 fx;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) fx[v] = sX[r * 16 + c + v];
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+            bf16x4 f;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) f[v] = sA[(16 * ob + r) * 16 + c + v];
+            g1[ob] = mfma16(f, fx, g1[ob]);
+        }
+        __syncthreads();  // before the next tile overwrites sA, sB, sX
+    }
+    // this block's complete gradient, parameter layout order
+    float *out = part + (int64_t)blockIdx.x * LP_MLP_NPARAM;
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            out[OFF_W1 + (16 * ob + c + v) * MLP_IN + r] = g1[ob][v];
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib) out[OFF_W2 + (16 * ob + c + v) * MLP_H + 16 * ib + r] = g2[ob][ib][v];
+        }
+    // per-unit sums over the 16 lanes (samples) that share a unit set
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            float a = gb1[ob][v], b = gb2[ob][v], w = gw3[ob][v];
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) {
+                a += __shfl_xor(a, o);
+                b += __shfl_xor(b, o);
+                w += __shfl_xor(w, o);
+            }
+            if (r == 0) {
+                out[OFF_B1 + 16 * ob + c + v] = a;
+                out[OFF_B2 + 16 * ob + c + v] = b;
+                out[OFF_W3 + 16 * ob + c + v] = w;
+            }
+        }
+    for (int o = 1; o < 64; o <<= 1) {
+        gb3 += __shfl_xor(gb3, o);
+        loss += __shfl_xor(loss, o);
+    }
+    if (l == 0) {
+        out[OFF_B3] = gb3;
+        loss_part[blockIdx.x] = loss;
+    }
+}
+
+// grad[q] = sum of the blocks' rows in block order; *loss likewise (mean over the batch)
+__global__ void k_mlp_reduce(const float *part, const float *loss_part, int nblk, float inv_batch, float *grad,
+                             float *loss) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < LP_MLP_NPARAM) {
+        float s = 0.f;
+        for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * LP_MLP_NPARAM + q];
+        grad[q] = s;
+    }
+    if (q == 0 && loss) {
+        float s = 0.f;
+        for (int b = 0; b < nblk; ++b) s += loss_part[b];
+        *loss = s * inv_batch;
+    }
+}
+
+// Adam step t (1-based) on the FP32 master weights; the batch loss is added
+// to *loss_acc.
+__global__ void k_mlp_adam(float *th, float *m, float *v, const float *grad, float lr, float b1, float b2,
+                           float eps, int t, const float *loss, float *loss_acc) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < LP_MLP_NPARAM) {
+        const float g = grad[q];
+        const float mq = b1 * m[q] + (1.f - b1) * g;
+        const float vq = b2 * v[q] + (1.f - b2) * g * g;
+        m[q] = mq;
+        v[q] = vq;
+        const float mh = mq / (1.f - powf(b1, (float)t));
+        const float vh = vq / (1.f - powf(b2, (float)t));
+        th[q] -= lr * mh / (sqrtf(vh) + eps);
+    }
+    if (q == 0 && loss_acc) *loss_acc += *loss;
+}
+
+int mlp_grad_blocks(int64_t nb) {
+    int64_t nt = (nb + 15) / 16;
+    return (int)(nt < 1024 ? (nt > 0 ? nt : 1) : 1024);
+}
+
+void launch_mlp_grad(const float *th, int64_t b0, int64_t nb, const float *feat, const float *target, float *part,
+                     float *loss_part, float *grad, float *loss, hipStream_t st) {
+    const int blk = mlp_grad_blocks(nb);
+    const float inv = 1.f / (float)nb;
+    hipLaunchKernelGGL(k_mlp_grad, dim3(blk), dim3(64), 0, st, th, b0, nb, feat, target, inv, part, loss_part);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((LP_MLP_NPARAM + 255) / 256), dim3(256), 0, st, part, loss_part, blk, inv,
+                       grad, loss);
+    (void)hipGetLastError();
+}
+
+void launch_mlp_adam(float *th, float *m, float *v, const float *grad, float lr, float b1, float b2, float eps,
+                     int t, const float *loss, float *loss_acc, hipStream_t st) {
+    hipLaunchKernelGGL(k_mlp_adam, dim3((LP_MLP_NPARAM + 255) / 256), dim3(256), 0, st, th, m, v, grad, lr, b1, b2,
+                       eps, t, loss, loss_acc);
+    (void)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Staged inputs and quotient-estimator phi back to the caller's order.
+// ---------------------------------------------------------------------------
+__global__ void k_features_out(Sorted srt, MlpStage ms, const int *n_total_dev, int n_real, float *feat,
+                               float *phi, uint8_t *valid) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= *n_total_dev) return;
+    const int i = srt.id[s];
+    if (i >= n_real) return;
+#pragma unroll
+    for (int q = 0; q < MLP_IN; ++q) feat[(int64_t)i * MLP_IN + q] = ms.feat[(int64_t)s * MLP_IN + q];
+    phi[i] = (float)ms.phi_plain[s];
+    if (valid) valid[i] = (ms.mflag[s] & LP_MLP_FORCE0) ? 0 : 1;
+}
+
+void launch_features_out(const Sorted &s, const MlpStage &ms, const int *n_total_dev, int64_t n_total_cap,
+                         int n_real, float *feat, float *phi, uint8_t *valid, hipStream_t st) {
+    unsigned g = (unsigned)((n_total_cap + LP_BLOCK - 1) / LP_BLOCK);
+    hipLaunchKernelGGL(k_features_out, dim3(g > 0 ? g : 1), dim3(LP_BLOCK), 0, st, s, ms, n_total_dev, n_real, feat,
+                       phi, valid);
+    (void)hipGetLastError();
+}
+
+__global__ void k_fill_f32(float *p, int n, float v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+void launch_fill_f32(float *p, int n, float v, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_f32, dim3((n + 255) / 256 > 0 ? (n + 255) / 256 : 1), dim3(256), 0, st, p, n, v);
+    (void)hipGetLastError();
+}

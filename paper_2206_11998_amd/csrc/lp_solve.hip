@@ -367,14 +367,62 @@ __device__ __forceinline__ T limiter(T r) {
 // Half-ball fits, estimator, blended update and mover for one particle, given
 // its second-order derivatives.  Writes the caller's arrays at index i.
 // ---------------------------------------------------------------------------
+// Inputs of the network estimator (dimensionless; the definitions are the
+// oracle's): h d_a(rho)/rho, h d_a P/P, h div u / c, for V and P on every axis
+// the disagreement of the one-sided slopes (|log| of their quotient capped at
+// 8, 8 for opposite signs, 0 where the estimator ignores the pair), the log
+// range of V and P over the half-ball members, and h |grad u|_F / c.
+template <int D, typename T>
+__device__ __forceinline__ void estimator_features(const DevCfg &cfg, const double st[Dim<D>::NF],
+                                                   const double grad[Dim<D>::NF][3], const T dl[3][3],
+                                                   const T dr[3][3], const bool valid_l[3], const bool valid_r[3],
+                                                   double h, T vmin, T vmax, T pmin, T pmax, float f[16]) {
+    constexpr int FP = D + 1;
+    const double V = st[0], P = st[FP];
+    const double cs = sqrt(cfg.gamma * P * V);
+    double div = 0.0, gu2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) f[q] = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        f[a] = (float)(-h * grad[0][a] / V);
+        f[3 + a] = (float)(h * grad[FP][a] / P);
+        div += grad[1 + a][a];
+#pragma unroll
+        for (int b = 0; b < D; ++b) gu2 += grad[1 + a][b] * grad[1 + a][b];
+        const bool valid = valid_l[a] && valid_r[a];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const double sl = (double)dl[a][2 * q], sr = (double)dr[a][2 * q];
+            const double sv = q == 0 ? V : P;
+            const double big = fabs(sl) > fabs(sr) ? fabs(sl) : fabs(sr);
+            double g = 0.0;
+            if (valid && big * h > cfg.est_eps * fabs(sv)) {
+                if (!(sl * sr > 0.0)) g = 8.0;
+                else {
+                    g = fabs(log(fabs(sr) / fabs(sl)));
+                    g = g < 8.0 ? g : 8.0;
+                }
+            }
+            f[7 + 3 * q + a] = (float)g;
+        }
+    }
+    f[6] = (float)(h * div / cs);
+    f[13] = (float)log((double)vmax / (double)vmin);
+    f[14] = (float)log((double)pmax / (double)pmin);
+    f[15] = (float)(h * sqrt(gu2) / cs);
+}
+
 template <int D, typename T>
 __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p, const DevCfg &cfg, DevScalars *sc,
                                                 const int *nbr, int ldn, int s, int i, int k, double dt,
                                                 const double xi[3], const double st[Dim<D>::NF], double h, double r,
                                                 const double grad[Dim<D>::NF][3], const double hess[Dim<D>::NF][Dim<D>::NS],
-                                                int lw_status, uint8_t flags) {
+                                                int lw_status, uint8_t flags, const MlpStage *ms = nullptr) {
     constexpr int NF = Dim<D>::NF, FP = D + 1, NGD = D * (D + 1) / 2;
     const bool use_f = sizeof(T) == 4;
+    // V and P over the particle and its half-ball members (network inputs)
+    T vmin = (T)st[0], vmax = (T)st[0], pmin = (T)st[FP], pmax = (T)st[FP];
     const int ucap = cfg.uw_cap;
     const double inv_r = 1.0 / r;
     T dl[3][3], dr[3][3];
@@ -405,6 +453,10 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
             if (use_f) { fj[0] = (T)srt.Vf[j]; fj[1] = (T)srt.uf[a][j]; fj[2] = (T)srt.Pf[j]; }
             else { fj[0] = (T)srt.V[j]; fj[1] = (T)srt.u[a][j]; fj[2] = (T)srt.P[j]; }
             T bq[3] = {fj[0] - fi[0], fj[1] - fi[1], fj[2] - fi[2]};
+            vmin = fj[0] < vmin ? fj[0] : vmin;
+            vmax = fj[0] > vmax ? fj[0] : vmax;
+            pmin = fj[2] < pmin ? fj[2] : pmin;
+            pmax = fj[2] > pmax ? fj[2] : pmax;
             // both sides accumulate with 0/1 weights (no pointer selects, so the
             // accumulators stay in registers)
             T wr = right ? T(1) : T(0), wl = right ? T(0) : T(1);
@@ -530,6 +582,27 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
     }
     lw_rates<D, T>((T)cfg.gamma, (T)dt, stT, gT, hT, lw);
     uw_rates<D, T>((T)cfg.gamma, stT, dl, dr, uw);
+    if (ms) {
+        // network estimator: stage inputs, rates and the quotient estimator's
+        // phi; the network decides phi and applies the update afterwards
+        float fv[16];
+        estimator_features<D, T>(cfg, st, grad, dl, dr, valid_l, valid_r, h, vmin, vmax, pmin, pmax, fv);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) ms->feat[(int64_t)s * 16 + q] = fv[q];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            ms->rates[(int64_t)f * ms->ld + s] = (double)lw[f];
+            ms->rates[(int64_t)(NF + f) * ms->ld + s] = (double)uw[f];
+        }
+        ms->phi_plain[s] = phi;
+        uint8_t mf = flags;
+        if (lw_status != 0) mf |= LP_FLAG_DEGENERATE;
+        if (vac) mf |= LP_FLAG_VACUUM;
+        if (subst) mf |= LP_FLAG_SUBSTITUTED;
+        if (lw_status != 0 || vac) mf |= LP_MLP_FORCE0;
+        ms->mflag[s] = mf;
+        return false;
+    }
     double ns[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
@@ -771,7 +844,7 @@ __device__ __forceinline__ bool finish_one(const SolveArgs &a, int s, int t) {
     double grad[NF][3], hess[NF][NS];
     load_der<D>(a.der, a.ld, t, grad, hess);
     return finish_particle<D, T>(srt, a.p, cfg, a.sc, a.nbr, a.ldn, s, i, k, a.sc->dt, xi, st, h, r, grad, hess, 0,
-                                 0);
+                                 0, a.ms.feat ? &a.ms : nullptr);
 }
 
 // Work distribution.  WQ_DIRECT: thread t of the grid serves cell-order
@@ -1111,7 +1184,8 @@ __device__ __forceinline__ int lw_fit_wave(const Sorted &srt, const DevCfg &cfg,
 
 template <int D>
 __global__ __launch_bounds__(64) void k_solve_fallback(Sorted srt, Soa p, const int *nbr, int ldn, const int *count,
-                                                       int n_real, DevCfg cfg, DevScalars *sc, const int *queue) {
+                                                       int n_real, DevCfg cfg, DevScalars *sc, const int *queue,
+                                                       MlpStage ms) {
     constexpr int NF = Dim<D>::NF, NS = Dim<D>::NS, FP = D + 1;
     __shared__ int sel[64];
     const int nq = sc->n_fallback;
@@ -1135,21 +1209,22 @@ __global__ __launch_bounds__(64) void k_solve_fallback(Sorted srt, Soa p, const 
                                         grad, hess, sel);
         if ((threadIdx.x & 63) == 0 &&
             finish_particle<D, double>(srt, p, cfg, sc, nbr, ldn, s, i, k, sc->dt, xi, st, h, r, grad, hess, status,
-                                       LP_FLAG_FALLBACK))
+                                       LP_FLAG_FALLBACK, ms.feat ? &ms : nullptr))
             atomicAdd(&sc->n_limited, 1ull);
         __syncthreads();
     }
 }
 
 void launch_solve_fallback(const Sorted &s, const Soa &p, const int *nbr, int ldn, const int *count, int n_real,
-                           const DevCfg &cfg, DevScalars *sc, const int *queue, int queue_cap, hipStream_t st) {
+                           const DevCfg &cfg, DevScalars *sc, const int *queue, int queue_cap, const MlpStage &ms,
+                           hipStream_t st) {
     unsigned blocks = queue_cap < 2048 ? (unsigned)(queue_cap > 0 ? queue_cap : 1) : 2048u;
     if (cfg.D == 3)
         hipLaunchKernelGGL(k_solve_fallback<3>, dim3(blocks), dim3(64), 0, st, s, p, nbr, ldn, count, n_real, cfg, sc,
-                           queue);
+                           queue, ms);
     else
         hipLaunchKernelGGL(k_solve_fallback<2>, dim3(blocks), dim3(64), 0, st, s, p, nbr, ldn, count, n_real, cfg, sc,
-                           queue);
+                           queue, ms);
     (void)hipGetLastError();
 }
 

@@ -21,11 +21,15 @@ FLAG_LIMITED, FLAG_DEGENERATE, FLAG_VACUUM, FLAG_SUBSTITUTED, FLAG_FALLBACK, FLA
 
 EXPORTS = ["lp_config_default", "lp_create", "lp_destroy", "lp_neighbors", "lp_gfd", "lp_step", "lp_run",
            "lp_conservation", "lp_check", "lp_get_info", "lp_set_time", "lp_profile", "lp_profile_read",
-           "lp_set_tuning", "lp_get_tuning", "lp_autotune", "lp_status_str", "lp_last_error"]
+           "lp_set_tuning", "lp_get_tuning", "lp_autotune", "lp_train_cfg_default", "lp_features", "lp_mlp_init",
+           "lp_mlp_set", "lp_mlp_get", "lp_mlp_forward", "lp_mlp_grad", "lp_mlp_train", "lp_status_str",
+           "lp_last_error"]
+MLP_NPARAM = 5313
+MLP_NIN = 16
 TUNE_SEARCH_MODE, TUNE_SEARCH_GROUP, TUNE_SOLVE_BLOCK, TUNE_SOLVE_MODE, TUNE_QUEUE_TILE = 0, 1, 2, 3, 4
 TUNE_COUNT = 5
 TUNE_NAMES = ["search_mode", "search_group", "solve_block", "solve_mode", "queue_tile"]
-STAGES = ["prep", "cells", "search", "fit", "update", "fallback", "step"]
+STAGES = ["prep", "cells", "search", "fit", "update", "fallback", "step", "mlp"]
 
 
 class LpError(RuntimeError):
@@ -42,7 +46,14 @@ class Config(C.Structure):
         ("cond_max", C.c_double), ("uw_cond_max", C.c_double), ("cond_fallback", C.c_double),
         ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
         ("periodic_mask", C.c_uint32), ("wall_lo_mask", C.c_uint32), ("wall_hi_mask", C.c_uint32),
-        ("reserved", C.c_int32 * 9),
+        ("mlp_band", C.c_float), ("mlp_feat_max", C.c_float), ("reserved", C.c_int32 * 7),
+    ]
+
+
+class TrainCfg(C.Structure):
+    _fields_ = [
+        ("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+        ("eps", C.c_float), ("seed", C.c_uint64), ("reserved", C.c_int32 * 6),
     ]
 
 
@@ -57,6 +68,7 @@ class Info(C.Structure):
     _fields_ = [
         ("t", C.c_double), ("dt", C.c_double), ("n_ghost", C.c_int64), ("max_count", C.c_int32),
         ("n_fallback", C.c_int32), ("n_limited", C.c_int64), ("error_bits", C.c_uint32), ("levels", C.c_int32 * 2),
+        ("n_mlp", C.c_int64), ("n_mlp_plain", C.c_int64),
     ]
 
 
@@ -103,6 +115,23 @@ def lib():
         L.lp_get_tuning.argtypes = [vp, i32, C.POINTER(i32)]
         L.lp_autotune.restype = i32
         L.lp_autotune.argtypes = [vp, vp, C.POINTER(Particles), i32, C.POINTER(i32), C.POINTER(C.c_double)]
+        fp = C.POINTER(C.c_float)
+        L.lp_train_cfg_default.restype = None
+        L.lp_train_cfg_default.argtypes = [C.POINTER(TrainCfg)]
+        L.lp_features.restype = i32
+        L.lp_features.argtypes = [vp, vp, C.POINTER(Particles), vp, vp, vp]
+        L.lp_mlp_init.restype = i32
+        L.lp_mlp_init.argtypes = [vp, C.c_uint64]
+        L.lp_mlp_set.restype = i32
+        L.lp_mlp_set.argtypes = [vp, fp, i64]
+        L.lp_mlp_get.restype = i32
+        L.lp_mlp_get.argtypes = [vp, fp, i64]
+        L.lp_mlp_forward.restype = i32
+        L.lp_mlp_forward.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.lp_mlp_grad.restype = i32
+        L.lp_mlp_grad.argtypes = [vp, vp, i64, vp, vp, fp, fp]
+        L.lp_mlp_train.restype = i32
+        L.lp_mlp_train.argtypes = [vp, vp, i64, vp, vp, C.POINTER(TrainCfg), fp]
         L.lp_status_str.restype = C.c_char_p
         L.lp_status_str.argtypes = [i32]
         L.lp_last_error.restype = C.c_char_p
@@ -269,7 +298,7 @@ class Context:
         self._raise(lib().lp_get_info(self._h, _stream_ptr(stream), C.byref(inf)))
         return {"t": inf.t, "dt": inf.dt, "n_ghost": inf.n_ghost, "max_count": inf.max_count,
                 "n_fallback": inf.n_fallback, "n_limited": inf.n_limited, "error_bits": inf.error_bits,
-                "levels": (inf.levels[0], inf.levels[1])}
+                "levels": (inf.levels[0], inf.levels[1]), "n_mlp": inf.n_mlp, "n_mlp_plain": inf.n_mlp_plain}
 
     def set_time(self, t: float, stream=None):
         self._raise(lib().lp_set_time(self._h, _stream_ptr(stream), float(t)))
@@ -300,3 +329,78 @@ class Context:
         ms = C.c_double(0.0)
         self._raise(lib().lp_autotune(self._h, _stream_ptr(stream), C.byref(p), int(reps), best, C.byref(ms)))
         return {name: best[q] for q, name in enumerate(TUNE_NAMES)}, ms.value
+
+
+def train_cfg(**kw) -> TrainCfg:
+    """lp_train_cfg with the library defaults, overridden by keyword."""
+    t = TrainCfg()
+    lib().lp_train_cfg_default(C.byref(t))
+    for k, v in kw.items():
+        setattr(t, k, v)
+    return t
+
+
+def _ctx_features(self, s: dict, stream=None):
+    """Network inputs (n x 16 float32), quotient-estimator phi (n) and
+    validity (n, uint8) of every particle of s at its current state."""
+    import torch
+    p = self._particles(s)
+    n = s["V"].shape[0]
+    dev = s["V"].device
+    feat = torch.empty((n, MLP_NIN), dtype=torch.float32, device=dev)
+    phi = torch.empty(n, dtype=torch.float32, device=dev)
+    valid = torch.empty(n, dtype=torch.uint8, device=dev)
+    self._raise(lib().lp_features(self._h, _stream_ptr(stream), C.byref(p), _ptr(feat), _ptr(phi), _ptr(valid)))
+    return feat, phi, valid
+
+
+def _ctx_mlp_init(self, seed: int = 1):
+    self._raise(lib().lp_mlp_init(self._h, int(seed)))
+
+
+def _ctx_mlp_set(self, params):
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    self._raise(lib().lp_mlp_set(self._h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+
+
+def _ctx_mlp_get(self) -> np.ndarray:
+    a = np.zeros(MLP_NPARAM, dtype=np.float32)
+    self._raise(lib().lp_mlp_get(self._h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+    return a
+
+
+def _ctx_mlp_forward(self, feat, stream=None):
+    """(z, y) of the network on feat (device, n x 16 float32)."""
+    import torch
+    n = feat.shape[0]
+    z = torch.empty(n, dtype=torch.float32, device=feat.device)
+    y = torch.empty(n, dtype=torch.float32, device=feat.device)
+    self._raise(lib().lp_mlp_forward(self._h, _stream_ptr(stream), n, _ptr(feat), _ptr(z), _ptr(y)))
+    return z, y
+
+
+def _ctx_mlp_grad(self, feat, target, stream=None):
+    """(loss, gradient) of the mean cross-entropy (host values)."""
+    g = np.zeros(MLP_NPARAM, dtype=np.float32)
+    loss = C.c_float(0.0)
+    self._raise(lib().lp_mlp_grad(self._h, _stream_ptr(stream), feat.shape[0], _ptr(feat), _ptr(target),
+                                  g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss)))
+    return loss.value, g
+
+
+def _ctx_mlp_train(self, feat, target, stream=None, **kw):
+    """Train on (feat, target) (device tensors); returns the per-epoch mean loss."""
+    t = train_cfg(**kw)
+    loss = np.zeros(max(t.epochs, 1), dtype=np.float32)
+    self._raise(lib().lp_mlp_train(self._h, _stream_ptr(stream), feat.shape[0], _ptr(feat), _ptr(target),
+                                   C.byref(t), loss.ctypes.data_as(C.POINTER(C.c_float))))
+    return loss[:t.epochs]
+
+
+Context.features = _ctx_features
+Context.mlp_init = _ctx_mlp_init
+Context.mlp_set = _ctx_mlp_set
+Context.mlp_get = _ctx_mlp_get
+Context.mlp_forward = _ctx_mlp_forward
+Context.mlp_grad = _ctx_mlp_grad
+Context.mlp_train = _ctx_mlp_train

@@ -1,0 +1,268 @@
+"""The estimator network on the GPU (BF16 matrix instructions, FP32
+accumulation) against the FP64 oracle, the staged update path against the
+plain one, and what a trained network gains on the Sod tube."""
+import numpy as np
+import pytest
+
+from paper_2206_11998_amd import workloads as W
+from tests import riemann
+from tests.gpu_util import say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+NP = 5313
+OFF_W1, OFF_B1, OFF_W2, OFF_B2, OFF_W3, OFF_B3 = 0, 1024, 1088, 5184, 5248, 5312
+BLOCKS = {"W1": (OFF_W1, OFF_B1), "b1": (OFF_B1, OFF_W2), "W2": (OFF_W2, OFF_B2), "b2": (OFF_B2, OFF_W3),
+          "w3": (OFF_W3, OFF_B3), "b3": (OFF_B3, NP)}
+
+
+@pytest.fixture(scope="module")
+def lp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2206_11998_amd import lp as _lp
+    _lp.lib()
+    return _lp
+
+
+def bf16(a):
+    """Round float values to bfloat16 (nearest even), returned as float64."""
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _ctx(lp):
+    cfg, _ = W.pulse2d()
+    return lp.Context(cfg)
+
+
+def test_forward_exact_on_integer_network(lp, oracle_lib):
+    """Integer weights and inputs keep every product, sum and BF16 rounding
+    exact, so the matrix-core forward pass must equal the oracle bit for bit:
+    this pins the operand and accumulator layouts of all three layers."""
+    rng = np.random.default_rng(11)
+    th = rng.integers(-1, 2, NP).astype(np.float64)
+    th[OFF_B1:OFF_W2] = rng.integers(-2, 3, 64)
+    th[OFF_B3] = 1.0
+    n = 16 * 37 + 5  # ragged last tile
+    feat = rng.integers(-2, 3, (n, 16)).astype(np.float64)
+    ctx = _ctx(lp)
+    ctx.mlp_set(th.astype(np.float32))
+    z, _ = ctx.mlp_forward(torch.from_numpy(feat.astype(np.float32)).cuda())
+    zr, _ = oracle_lib.mlp_forward(th, feat)
+    say("integer network: max |z| %.0f" % np.abs(zr).max())
+    assert np.abs(zr).max() > 10  # the test exercises real sums
+    assert np.array_equal(z.cpu().numpy().astype(np.float64), zr)
+
+
+def test_forward_and_gradient_against_oracle(lp, oracle_lib):
+    rng = np.random.default_rng(12)
+    th = (rng.standard_normal(NP) * 0.2).astype(np.float32)
+    n = 8000 + 9
+    feat = rng.standard_normal((n, 16)).astype(np.float32)
+    # one target for all samples: the per-sample gradients add up coherently,
+    # so the rare ReLU masks that BF16 rounding of the hidden layer flips
+    # (the oracle keeps it exact) stay small against the sum
+    target = np.full(n, 0.05, dtype=np.float32)
+    ctx = _ctx(lp)
+    ctx.mlp_set(th)
+    fd = torch.from_numpy(feat).cuda()
+    td = torch.from_numpy(target).cuda()
+    z, y = ctx.mlp_forward(fd)
+    loss, g = ctx.mlp_grad(fd, td)
+    # the oracle on the same BF16-rounded weights and inputs, in FP64
+    thr = bf16(th)
+    for name in ("b1", "b2", "w3", "b3"):  # kept in FP32 on the device
+        a, b = BLOCKS[name]
+        thr[a:b] = th[a:b]
+    zr, yr = oracle_lib.mlp_forward(thr, bf16(feat))
+    lr, gr = oracle_lib.mlp_loss_grad(thr, bf16(feat), target.astype(np.float64))
+    ez = np.linalg.norm(z.cpu().numpy() - zr) / np.linalg.norm(zr)
+    say("forward rel. L2 %.2e, loss %.6f vs %.6f" % (ez, loss, lr))
+    assert ez <= 2e-2
+    assert np.allclose(y.cpu().numpy(), yr, atol=5e-3)
+    assert abs(loss - lr) <= 2e-3 * abs(lr)
+    for name, (a, b) in BLOCKS.items():
+        e = np.linalg.norm(g[a:b] - gr[a:b]) / max(np.linalg.norm(gr[a:b]), 1e-30)
+        say("gradient %s rel. L2 %.2e" % (name, e))
+        assert e <= 2e-2, name
+
+
+def test_features_against_oracle(lp, oracle_lib):
+    for tag, (cfg, st) in (("sod slab", W.sod3d(n=64, ny=8, nz=8)), ("pulse2d", W.pulse2d()),
+                           ("vacuum 40k", W.vacuum3d(n_particles=40_000, seed=7))):
+        say("features", tag)
+        ctx = lp.Context(cfg)
+        dev = lp.state_to_device(st)
+        feat, phi, valid = ctx.features(dev)
+        n = st["V"].shape[0]
+        ref, info = oracle_lib.step_subset(cfg, st, np.arange(n), features=True)
+        f = feat.cpu().numpy().astype(np.float64)
+        rf = ref["feat"].astype(np.float32).astype(np.float64)
+        close = np.all(np.abs(f - rf) <= 1e-5 * (1.0 + np.abs(rf)), axis=1)
+        say(tag, "particles with all features within 1e-5: %.5f" % close.mean(),
+            "mean |dphi| %.2e" % np.abs(phi.cpu().numpy() - ref["phi"]).mean())
+        assert close.mean() >= 0.999
+        assert np.abs(phi.cpu().numpy() - ref["phi"]).mean() <= 1e-4
+        assert np.array_equal(valid.cpu().numpy() == 0, (ref["flags"] & 6) != 0)
+        # nothing advanced: the state is untouched
+        back = lp.state_to_host(dev)
+        assert np.array_equal(back["V"], st["V"]) and np.array_equal(back["x"], st["x"])
+
+
+def _run(lp, cfg, st, nsteps, estimator="plain", phi=None, params=None):
+    ctx = lp.Context(cfg, estimator=estimator)
+    if params is not None:
+        ctx.mlp_set(params)
+    dev = lp.state_to_device(st)
+    if phi is not None:
+        dev["phi"].fill_(phi)
+    for _ in range(nsteps):
+        ctx.step(dev)
+        if phi is not None:
+            dev["phi"].fill_(phi)
+    assert ctx.check() == lp.OK
+    info = ctx.info()
+    out = lp.state_to_host(dev)
+    ctx.close()
+    return out, info
+
+
+def test_staged_update_matches_plain_paths(lp):
+    """A network saturated at phi = 1 gives the injected phi = 1 step; a network
+    that is never trusted (output 1/2) gives the quotient estimator's step."""
+    cfg, st = W.pulse2d()
+    sat = np.zeros(NP, dtype=np.float32)
+    sat[OFF_B3] = 30.0
+    a, ia = _run(lp, cfg, st, 4, "mlp", params=sat)
+    b, _ = _run(lp, cfg, st, 4, "injected", phi=1.0)
+    for k in ("x", "V", "u", "P"):
+        assert np.array_equal(a[k], b[k]), k
+    assert ia["n_mlp"] == st["V"].shape[0]
+    half = np.zeros(NP, dtype=np.float32)
+    c, ic = _run(lp, cfg, st, 4, "mlp", params=half)
+    d, _ = _run(lp, cfg, st, 4, "plain")
+    for k in ("x", "V", "u", "P", "phi", "flags"):
+        assert np.array_equal(c[k], d[k]), k
+    assert ic["n_mlp"] == 0 and ic["n_mlp_plain"] == st["V"].shape[0]
+
+
+def _sod_error(s, T=0.1):
+    x = s["x"][:, 0]
+    ex = riemann.sample(x, T, 0.5, 1.0, 0.0, 1.0, 0.125, 0.0, 0.1)
+    return np.mean(np.abs(1.0 / s["V"] - ex[:, 0])), np.mean(np.abs(s["P"] - ex[:, 2]))
+
+
+def _sod_run(lp, cfg, st, T, estimator="plain", phi=None, params=None, harvest=None):
+    ctx = lp.Context(cfg, estimator=estimator)
+    if params is not None:
+        ctx.mlp_set(params)
+    dev = lp.state_to_device(st)
+    hctx = lp.Context(cfg) if harvest is not None else None
+    while ctx.info()["t"] < T:
+        if harvest is not None:
+            f, p, v = hctx.features(dev)
+            keep = v.bool()
+            harvest.append((f[keep].clone(), p[keep].clone()))
+        if phi is not None:
+            dev["phi"].fill_(phi)
+        try:
+            ctx.run(dev, 1, T)  # one step, clipped to T
+        except lp.LpError:
+            break
+        if ctx.check() != lp.OK:
+            break
+    status = ctx.check()
+    ok = status == lp.OK and ctx.info()["t"] >= T
+    out = lp.state_to_host(dev)
+    info = ctx.info()
+    ctx.close()
+    return out, info, ok
+
+
+def _steps_harvest(lp, cfg, st, nsteps, harvest):
+    ctx = lp.Context(cfg)
+    dev = lp.state_to_device(st)
+    for _ in range(nsteps):
+        f, p, v = ctx.features(dev)
+        keep = v.bool()
+        harvest.append((f[keep].clone(), p[keep].clone()))
+        ctx.step(dev)
+    assert ctx.check() == lp.OK
+    ctx.close()
+
+
+def test_trained_network_on_sod(lp):
+    """Harvest (inputs, quotient-estimator phi) from Sod tubes, train the
+    network on the GPU, and run a Sod tube it has not seen with the network
+    as the estimator: it must decide most particles, track the quotient
+    estimator's error against the exact solution, and beat the scheme without
+    an estimator (phi = 1 everywhere)."""
+    T = 0.1
+    harvest = []
+    for seed in (21, 22):
+        cfg, st = W.sod3d(n=128, ny=8, nz=8, seed=seed)
+        assert _sod_run(lp, cfg, st, T, harvest=harvest)[2]
+    # smooth flow too, where the quotient estimator keeps phi = 1
+    wcfg, wst = W.smooth_wave(3, 20, seed=31, amp=3e-2)
+    _steps_harvest(lp, wcfg, wst, 12, harvest)
+    feat = torch.cat([h[0] for h in harvest])
+    phi = torch.cat([h[1] for h in harvest])
+    lim = phi < 1.0
+    gen = torch.Generator().manual_seed(5)
+    ia = torch.nonzero(lim).flatten().cpu()
+    ib = torch.nonzero(~lim).flatten().cpu()
+    m = min(len(ia), len(ib))
+    sel = torch.cat([ia[torch.randperm(len(ia), generator=gen)[:m]], ib[torch.randperm(len(ib), generator=gen)[:m]]])
+    sel = sel[torch.randperm(len(sel), generator=gen)].cuda()
+    fx = feat[sel].contiguous()
+    tx = phi[sel].contiguous()
+    say("training samples %d (limited %d of %d harvested)" % (len(sel), len(ia), len(phi)))
+    cfg, st = W.sod3d(n=128, ny=8, nz=8, seed=23)
+    ctx = lp.Context(cfg)
+    ctx.mlp_init(7)
+    losses = ctx.mlp_train(fx, tx, epochs=40, batch=2048, lr=3e-3)
+    say("loss by epoch", np.round(losses[[0, 4, 9, 19, 39]], 4))
+    assert losses[-1] < 0.8 * losses[0]
+    params = ctx.mlp_get()
+    _, y = ctx.mlp_forward(fx)
+    agree = (torch.abs(y - tx) < 0.1).float().mean().item()
+    say("training samples within 0.1 of the quotient estimator: %.3f" % agree)
+    assert agree > 0.8
+    # a tube the network has not seen
+    res = {}
+    for name, kw in (("plain", {}), ("mlp", {"estimator": "mlp", "params": params}),
+                     ("no estimator (phi=1)", {"estimator": "injected", "phi": 1.0}),
+                     ("upwind only (phi=0)", {"estimator": "injected", "phi": 0.0})):
+        out, info, ok = _sod_run(lp, cfg, st, T, **kw)
+        res[name] = (_sod_error(out) if ok else (np.inf, np.inf), info, ok)
+        say("%-22s reached t=%.3f %s  L1 rho %.5f  L1 p %.5f  network decided %d, fell back %d" % (
+            name, info["t"], "ok" if ok else "BROKE DOWN", res[name][0][0], res[name][0][1], info["n_mlp"],
+            info["n_mlp_plain"]))
+    e_plain, e_mlp = res["plain"][0], res["mlp"][0]
+    e_lw, e_uw = res["no estimator (phi=1)"][0], res["upwind only (phi=0)"][0]
+    info = res["mlp"][1]
+    n = st["V"].shape[0]
+    assert res["plain"][2] and res["mlp"][2]
+    assert info["n_mlp"] > 0.5 * n
+    # the gain over the scheme without an estimator: on the Sod tube that one
+    # breaks down (or ends farther from the exact solution); the network ends
+    # as close to it as the quotient estimator and pure upwind do
+    assert e_mlp[0] < e_lw[0] and e_mlp[1] < e_lw[1]
+    assert e_mlp[0] <= 1.01 * e_uw[0] and e_mlp[1] <= 1.01 * e_uw[1]
+    assert e_mlp[0] <= 1.15 * e_plain[0] and e_mlp[1] <= 1.15 * e_plain[1]
+    # on a smooth wave it has not seen, it keeps the second-order update where
+    # the quotient estimator does (pure upwind damps the wave)
+    wcfg, wst = W.smooth_wave(3, 20, seed=37, amp=3e-2)
+    waves = {}
+    for name, kw in (("plain", {}), ("mlp", {"estimator": "mlp", "params": params}),
+                     ("upwind only (phi=0)", {"estimator": "injected", "phi": 0.0})):
+        waves[name] = _run(lp, wcfg, wst, 12, **kw)
+    d_mlp = np.abs(waves["mlp"][0]["P"] - waves["plain"][0]["P"]).sum()
+    d_uw = np.abs(waves["upwind only (phi=0)"][0]["P"] - waves["plain"][0]["P"]).sum()
+    say("smooth wave: L1 distance of P to the quotient estimator's run: network %.3e, pure upwind %.3e; "
+        "network decided %d of %d" % (d_mlp, d_uw, waves["mlp"][1]["n_mlp"], wst["V"].shape[0]))
+    assert d_mlp < 0.25 * d_uw
