@@ -24,6 +24,8 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-updates/s at 2M particles, mixed vs FP64 step; L1 err vs oracle"
 PEAK_ALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FP64, and FP32 without packed math)
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0  # dense BF16 matrix-core peak
+MLP_FLOPS = 20 * 16 * 16 * 16 * 2 / 16.0  # 20 MFMA 16x16x16 per tile of 16 particles
 
 
 def fit_flops(k_lw, dim=3):
@@ -82,9 +84,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=2_097_152)
-    ap.add_argument("--precision", choices=["both", "all", "mixed", "fp64", "fp32"], default="both",
+    ap.add_argument("--precision", choices=["both", "all", "mixed", "fp64", "fp32", "mlp"], default="all",
                     help="mixed: FP32 fits + one FP64-residual refinement; fp32: mixed without the refinement; "
-                         "both: mixed then fp64; all: mixed, fp64, fp32")
+                         "mlp: mixed with the learned estimator (trained first, untimed); "
+                         "both: mixed then fp64; all: mixed, fp64, fp32, mlp")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sample", type=int, default=0, help="particles in the CPU-reference sample (0: all)")
     ap.add_argument("--search-mode", type=int, default=None, help="override the neighbour-search mode (0/1)")
@@ -126,7 +129,38 @@ def main():
     sample = (np.arange(n) if args.sample <= 0 or args.sample >= n
               else np.sort(rng.choice(n, size=args.sample, replace=False)))
 
-    precisions = {"both": ["mixed", "fp64"], "all": ["mixed", "fp64", "fp32"]}.get(args.precision, [args.precision])
+    precisions = {"both": ["mixed", "fp64"], "all": ["mixed", "fp64", "fp32", "mlp"]}.get(args.precision,
+                                                                                        [args.precision])
+    mlp_params = None
+    mlp_train = None
+    if "mlp" in precisions:
+        # the learned estimator's weights: trained on the GPU, before and
+        # outside the timed region, on (inputs, quotient-estimator phi) of this
+        # workload's particles, limited and unlimited ones in equal numbers
+        t_tr = time.time()
+        hctx = lp.Context(cfg)
+        hdev = lp.state_to_device(st)
+        feat, phi, valid = hctx.features(hdev)
+        keep = valid.bool()
+        feat, phi = feat[keep], phi[keep]
+        lim = torch.nonzero(phi < 1.0).flatten()
+        unl = torch.nonzero(phi >= 1.0).flatten()
+        g = torch.Generator(device="cuda").manual_seed(3)
+        m = min(len(lim), len(unl), 500_000)
+        sel = torch.cat([lim[torch.randperm(len(lim), generator=g, device="cuda")[:m]],
+                         unl[torch.randperm(len(unl), generator=g, device="cuda")[:m]]])
+        sel = sel[torch.randperm(len(sel), generator=g, device="cuda")]
+        fx, tx = feat[sel].contiguous(), (phi[sel] / 1.25).contiguous()  # the step uses min(1, 1.25 y)
+        hctx.mlp_init(7)
+        losses = hctx.mlp_train(fx, tx, epochs=8, batch=8192, lr=3e-3)
+        _, y = hctx.mlp_forward(fx)
+        agree = float((torch.abs(torch.clamp(1.25 * y, max=1.0) - 1.25 * tx) < 0.1).float().mean())
+        mlp_params = hctx.mlp_get()
+        mlp_train = {"samples": int(len(sel)), "epochs": 8, "final_loss": float(losses[-1]),
+                     "within_0.1_of_plain_phi": agree, "seconds": time.time() - t_tr}
+        log("learned estimator trained:", mlp_train)
+        hctx.close()
+        del hdev, feat, phi, fx, tx, y
     results = {}
     first_step = {}
     def tuned(ctx):
@@ -141,7 +175,10 @@ def main():
         return ctx
 
     for prec in precisions:
-        ctx = lp.Context(cfg, precision="fp64" if prec == "fp64" else "mixed", refine=prec != "fp32")
+        ctx = lp.Context(cfg, precision="fp64" if prec == "fp64" else "mixed", refine=prec != "fp32",
+                         estimator="mlp" if prec == "mlp" else "plain")
+        if prec == "mlp":
+            ctx.mlp_set(mlp_params)
         dev = lp.state_to_device(st)
         tuning = None
         if not args.no_autotune:
@@ -189,7 +226,7 @@ def main():
     count = count.cpu().numpy()
     k_lw = np.minimum(count, 54)
     work = {"search": float(search_bytes(count).sum()), "fit": float(fit_flops(k_lw).sum()),
-            "update": float(update_flops() * n)}
+            "update": float(update_flops() * n), "mlp": float(MLP_FLOPS * n)}
     ctx.close()
     del d
 
@@ -224,12 +261,17 @@ def main():
 
     def kernel_rooflines(prof, precision):
         out = {}
-        for name, bound in (("search", "hbm"), ("fit", "alu"), ("update", "alu")):
+        for name, bound in (("search", "hbm"), ("fit", "alu"), ("update", "alu"), ("mlp", "mfma")):
             ms, cnt = prof[name]
+            if cnt == 0:
+                continue
             avg = ms / max(cnt, 1)
             if bound == "hbm":
                 achieved = work[name] / (avg * 1e-3) / 1e9 if avg > 0 else None
                 peak, unit, per = PEAK_HBM_GBS, "GB/s", "algorithmic_bytes_per_launch"
+            elif bound == "mfma":
+                achieved = work[name] / (avg * 1e-3) / 1e12 if avg > 0 else None
+                peak, unit, per = PEAK_BF16_TFLOPS, "TFLOP/s", "algorithmic_flops_per_launch"
             else:
                 achieved = work[name] / (avg * 1e-3) / 1e12 if avg > 0 else None
                 peak, unit, per = PEAK_ALU_TFLOPS, "TFLOP/s", "algorithmic_flops_per_launch"
@@ -276,6 +318,9 @@ def main():
         out[prec] = {"value": n * args.steps / r2["elapsed"], "ms_per_step": 1e3 * r2["elapsed"] / args.steps,
                      "kernels": kernel_rooflines(r2["prof"], prec), "tuning": r2["tuning"],
                      "stages_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in r2["prof"].items()}}
+        if prec == "mlp":
+            out[prec]["learned_estimator"] = dict(mlp_train, n_network=r2["info"]["n_mlp"],
+                                                  n_fallback=r2["info"]["n_mlp_plain"])
     print(json.dumps(out))
 
 

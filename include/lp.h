@@ -235,7 +235,10 @@ lp_status lp_profile_read(struct lp_ctx *ctx, void *stream, double *ms, int64_t 
  * log(P_max/P_min) over the half-ball members (2), h |grad u|_F / c.
  * Parameters (FP32, LP_MLP_NPARAM in this order): W1[64][16], b1[64],
  * W2[64][64], b2[64], w3[64], b3.  Inference and training run on BF16 matrix
- * instructions with FP32 accumulation.
+ * instructions with FP32 accumulation.  As the estimator of a step the
+ * network gives phi = min(1, 1.25 y), y its sigmoid output -- the limiter's
+ * range -- so a network that imitates the quotient estimator is trained on
+ * targets phi / 1.25.
  * ------------------------------------------------------------------------- */
 #define LP_MLP_NIN 16
 #define LP_MLP_NPARAM 5313

@@ -146,9 +146,9 @@ void launch_mlp_forward(const float *th, int64_t n, const float *feat, float *z,
 }
 
 // ---------------------------------------------------------------------------
-// Estimator stage of a step with the network: phi from the network where it
-// is trusted, the quotient estimator's phi elsewhere, then the blended update
-// and the mover -- the same arithmetic as the update kernel.
+// Estimator stage of a step with the network: phi = min(1, 1.25 sigmoid(z))
+// where the network is trusted, the quotient estimator's phi elsewhere, then
+// the blended update and the mover -- the same arithmetic as the update kernel.
 // ---------------------------------------------------------------------------
 template <int D>
 __global__ __launch_bounds__(64) void k_mlp_apply(const float *th, Sorted srt, Soa p, DevCfg cfg, DevScalars *sc,
@@ -175,14 +175,15 @@ __global__ __launch_bounds__(64) void k_mlp_apply(const float *th, Sorted srt, S
         if (mf & LP_MLP_FORCE0) {
             phi = 0.0;
         } else {
-            // trusted: every input within range and the output away from 1/2
+            // trusted: every input within range and the estimate away from 1/2;
+            // the estimate is 1.25 sigmoid(z) capped at 1, the limiter's range
             bool in_range = true;
 #pragma unroll
             for (int q = 0; q < MLP_IN; ++q) {
                 const float f = ms.feat[(int64_t)s * MLP_IN + q];
                 in_range = in_range && fabsf(f) <= cfg.mlp_feat_max;
             }
-            const float y = sigmoidf(z);
+            const float y = fminf(1.25f * sigmoidf(z), 1.0f);
             if (in_range && fabsf(y - 0.5f) >= cfg.mlp_band) {
                 phi = (double)y;
                 ++used;
@@ -241,7 +242,7 @@ __global__ __launch_bounds__(64) void k_mlp_apply(const float *th, Sorted srt, S
 void launch_mlp_apply(const float *th, const Sorted &s, const Soa &p, const DevCfg &cfg, DevScalars *sc,
                       int64_t n_total_cap, int n_real, const MlpStage &ms, hipStream_t st) {
     int64_t nt = (n_total_cap + 15) / 16;
-    unsigned g = (unsigned)(nt < 8192 ? (nt > 0 ? nt : 1) : 8192);
+    unsigned g = (unsigned)(nt < 8192 ? (nt > 0 ? nt : 1) : 8192);  // each wave loads the weights once
     if (cfg.D == 3)
         hipLaunchKernelGGL(k_mlp_apply<3>, dim3(g), dim3(64), 0, st, th, s, p, cfg, sc, n_real, ms);
     else

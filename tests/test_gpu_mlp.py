@@ -143,6 +143,7 @@ def test_staged_update_matches_plain_paths(lp):
         assert np.array_equal(a[k], b[k]), k
     assert ia["n_mlp"] == st["V"].shape[0]
     half = np.zeros(NP, dtype=np.float32)
+    half[OFF_B3] = np.log(0.4 / 0.6)  # 1.25 sigmoid = 1/2: never trusted
     c, ic = _run(lp, cfg, st, 4, "mlp", params=half)
     d, _ = _run(lp, cfg, st, 4, "plain")
     for k in ("x", "V", "u", "P", "phi", "flags"):
@@ -219,17 +220,22 @@ def test_trained_network_on_sod(lp):
     sel = torch.cat([ia[torch.randperm(len(ia), generator=gen)[:m]], ib[torch.randperm(len(ib), generator=gen)[:m]]])
     sel = sel[torch.randperm(len(sel), generator=gen)].cuda()
     fx = feat[sel].contiguous()
-    tx = phi[sel].contiguous()
+    tx = (phi[sel] / 1.25).contiguous()  # the estimator uses min(1, 1.25 sigmoid)
     say("training samples %d (limited %d of %d harvested)" % (len(sel), len(ia), len(phi)))
     cfg, st = W.sod3d(n=128, ny=8, nz=8, seed=23)
     ctx = lp.Context(cfg)
     ctx.mlp_init(7)
+    loss0 = ctx.mlp_grad(fx, tx)[0]
     losses = ctx.mlp_train(fx, tx, epochs=40, batch=2048, lr=3e-3)
-    say("loss by epoch", np.round(losses[[0, 4, 9, 19, 39]], 4))
-    assert losses[-1] < 0.8 * losses[0]
+    # cross-entropy against soft targets cannot go below their entropy
+    t = tx.double().cpu().numpy()
+    tc = np.clip(t, 1e-12, 1 - 1e-12)
+    floor = float(np.mean(-(t * np.log(tc) + (1 - t) * np.log(1 - tc))))
+    say("loss: untrained %.4f, by epoch %s, floor %.4f" % (loss0, np.round(losses[[0, 4, 9, 19, 39]], 4), floor))
+    assert losses[-1] - floor < 0.2 * (loss0 - floor)
     params = ctx.mlp_get()
     _, y = ctx.mlp_forward(fx)
-    agree = (torch.abs(y - tx) < 0.1).float().mean().item()
+    agree = (torch.abs(torch.clamp(1.25 * y, max=1.0) - 1.25 * tx) < 0.1).float().mean().item()
     say("training samples within 0.1 of the quotient estimator: %.3f" % agree)
     assert agree > 0.8
     # a tube the network has not seen
