@@ -566,7 +566,10 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
             return LP_OK;
         }
         n_total = n + c->sc_host->n_ghost;
-        choose_levels(c, bits_to_double(c->sc_host->rmin), bits_to_double(c->sc_host->rmax));
+        // a planning step of lp_run keeps the grid a captured graph was made
+        // with while it still covers the particles and their radii
+        const bool keep = c->grid_margin > 0.0 && c->graph && c->graph_gen == c->gen && !grid_outdated(c);
+        if (!keep) choose_levels(c, bits_to_double(c->sc_host->rmin), bits_to_double(c->sc_host->rmax));
         int64_t want = n_total;
         if (c->nwalls && c->grid_margin > 0.0) {
             // planning for graph replays: room for the ghost count to grow

@@ -166,11 +166,33 @@ __global__ __launch_bounds__(64) void k_mlp_apply(const float *th, Sorted srt, S
         bool ok = s < n_total;
         const int i = ok ? srt.id[s] : n_real;
         ok = ok && i < n_real;
+        const bool mine = ok && l < 16;  // lanes 0..15 finish the tile's particles
+        // the update's operands are loaded before the network runs, so their
+        // latency overlaps the matrix instructions
+        double st[NF], lw[NF], uw[NF], xs[D];
+        double phi_plain = 0.0;
+        uint8_t mf = 0;
+        if (mine) {
+            st[0] = srt.V[s];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                st[1 + a] = srt.u[a][s];
+                xs[a] = srt.x[a][s];
+            }
+            st[FP] = srt.P[s];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                lw[f] = ms.rates[(int64_t)f * ms.ld + s];
+                uw[f] = ms.rates[(int64_t)(NF + f) * ms.ld + s];
+            }
+            phi_plain = ms.phi_plain[s];
+            mf = ms.mflag[s];
+        }
+        const bf16x4 x = load_x(ms.feat, s, ok);
         f32x4 d1[4], d2[4];
         bf16x4 h1[4];
-        const float z = forward(R, load_x(ms.feat, s, ok), d1, h1, d2);
-        if (!(ok && l < 16)) continue;
-        const uint8_t mf = ms.mflag[s];
+        const float z = forward(R, x, d1, h1, d2);
+        if (!mine) continue;
         double phi;
         if (mf & LP_MLP_FORCE0) {
             phi = 0.0;
@@ -188,23 +210,16 @@ __global__ __launch_bounds__(64) void k_mlp_apply(const float *th, Sorted srt, S
                 phi = (double)y;
                 ++used;
             } else {
-                phi = ms.phi_plain[s];
+                phi = phi_plain;
                 ++plain;
             }
         }
-        double st[NF], ns[NF];
-        st[0] = srt.V[s];
+        double ns[NF];
 #pragma unroll
-        for (int a = 0; a < D; ++a) st[1 + a] = srt.u[a][s];
-        st[FP] = srt.P[s];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            const double u_ = ms.rates[(int64_t)(NF + f) * ms.ld + s], l_ = ms.rates[(int64_t)f * ms.ld + s];
-            ns[f] = st[f] + dt * (u_ - phi * (u_ - l_));
-        }
+        for (int f = 0; f < NF; ++f) ns[f] = st[f] + dt * (uw[f] - phi * (uw[f] - lw[f]));
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            double xn = srt.x[a][s] + 0.5 * dt * (st[1 + a] + ns[1 + a]);
+            double xn = xs[a] + 0.5 * dt * (st[1 + a] + ns[1 + a]);
             if (cfg.periodic[a]) {
                 if (xn >= cfg.hi[a]) xn -= cfg.L[a];
                 else if (xn < cfg.lo[a]) xn += cfg.L[a];
