@@ -459,9 +459,11 @@ __global__ void k_mlp_adam(float *th, float *m, float *v, const float *grad, flo
     if (q == 0 && loss_acc) *loss_acc += *loss;
 }
 
+// Blocks of a gradient launch: every block covers several tiles, so that the
+// fixed-order reduction over the blocks' rows stays short.
 int mlp_grad_blocks(int64_t nb) {
     int64_t nt = (nb + 15) / 16;
-    return (int)(nt < 1024 ? (nt > 0 ? nt : 1) : 1024);
+    return (int)(nt < 128 ? (nt > 0 ? nt : 1) : 128);
 }
 
 void launch_mlp_grad(const float *th, int64_t b0, int64_t nb, const float *feat, const float *target, float *part,
