@@ -92,8 +92,12 @@ __device__ __forceinline__ void for_lw_stencil(const Sorted &srt, const DevCfg &
     }
     unsigned long long s03 = 0, s47 = 0;
     int takenR = 0;
+    // the next member's index is loaded one iteration ahead, so the gathers
+    // of a member wait for one memory round trip instead of two
+    int jn = k > 0 ? nb_at(nbr, ldn, s, 0) : 0;
     for (int t = 0; t < k; ++t) {
-        int j = nb_at(nbr, ldn, s, t);
+        const int j = jn;
+        if (t + 1 < k) jn = nb_at(nbr, ldn, s, t + 1);
         double dx[3];
         displacement<D>(srt, cfg, j, xi, dx);
         if (k > cap) {
@@ -440,8 +444,10 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
         for (int q = 0; q < D; ++q) { Sl[q] = 0; Sr[q] = 0; }
         int nl = 0, nr = 0;
         const T fi[3] = {(T)st[0], (T)st[1 + a], (T)st[FP]};
+        int jn = k > 0 ? nb_at(nbr, ldn, s, 0) : 0;  // next index loaded one iteration ahead
         for (int t = 0; t < k && (nl < ucap || nr < ucap); ++t) {
-            int j = nb_at(nbr, ldn, s, t);
+            const int j = jn;
+            if (t + 1 < k) jn = nb_at(nbr, ldn, s, t + 1);
             double dx[3];
             displacement<D>(srt, cfg, j, xi, dx);
             bool right = dx[a] > 0.0, left = dx[a] < 0.0;
