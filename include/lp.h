@@ -206,7 +206,11 @@ enum {
                                   neighbour count within tiles of cell-order particles; 2: persistent
                                   launch over that queue */
     LP_TUNE_QUEUE_TILE = 4,    /* tile of the work queue of modes 1 and 2: 256, 512, 1024 */
-    LP_TUNE_COUNT = 5
+    LP_TUNE_SEARCH_CAP = 5,    /* list slots per particle held in LDS by search mode 2 (longer lists
+                                  are redone by an overflow kernel): 0 (default) = chosen by each
+                                  planning step from the previous step's longest list, else a
+                                  multiple of 8 in 8..128 */
+    LP_TUNE_COUNT = 6
 };
 lp_status lp_set_tuning(struct lp_ctx *ctx, int32_t param, int32_t value);
 

@@ -43,6 +43,8 @@ struct lp_ctx {
     double S_grid = 1.0;            // cube side used by the last grid
     int jper[3] = {0, 0, 0};        // periodic extent = S / 2^jper
     int search_group = 8;
+    int search_cap = 0;             // LDS list slots per particle of the search: 0 = automatic
+    int search_lcap = 0;            // automatic choice for steps (0: the kernel's maximum)
     int64_t cap_real = 0, cap_total = 0, cap_ghost = 0;
     bool run_done = false;
     DevGrid grid;
@@ -444,7 +446,7 @@ static lp_status ensure_capacity(lp_ctx *c, int64_t n_real, int64_t n_total, boo
 // list stride convention of nb_at(): > 0 column-major, < 0 row-major
 static int list_ldn(const lp_ctx *c) { return c->search_mode == 1 ? -c->dc.max_nb : (int)c->cap_total; }
 
-static void run_search(lp_ctx *c, const Sorted &srt, int64_t n_total, int n_real, hipStream_t st) {
+static void run_search(lp_ctx *c, const Sorted &srt, int64_t n_total, int n_real, int lcap, hipStream_t st) {
     int ldn = (int)c->cap_total;
     if (c->search_mode == 1)
         launch_search_tiles(srt, &c->sc->n_total, (int)n_total, n_real, (const uint32_t *)c->tables.p, c->grid,
@@ -453,7 +455,7 @@ static void run_search(lp_ctx *c, const Sorted &srt, int64_t n_total, int n_real
                             (int *)c->tlo.p, (int *)c->thi.p, &c->sc->n_tiles, st);
     else
         launch_search(srt, &c->sc->n_total, (int)n_total, n_real, (const uint32_t *)c->tables.p, c->grid, c->dc,
-                      (int *)c->nbr.p, ldn, (int *)c->count.p, c->sc, c->search_group, (int *)c->ovfq.p,
+                      (int *)c->nbr.p, ldn, (int *)c->count.p, c->sc, c->search_group, lcap, (int *)c->ovfq.p,
                       c->search_mode == 2, st);
 }
 
@@ -578,6 +580,15 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
         }
         lp_status s = ensure_capacity(c, n, want, true, mixed);
         if (s != LP_OK) return s;
+        // search list slots in LDS: the last step's largest list, rounded up
+        // with room to grow (a longer list takes the overflow kernel)
+        const int prev = c->sc_host->prev_max_count;
+        int lcap = prev > 0 ? (prev + 8 + 15) / 16 * 16 : 0;
+        if (lcap > 128) lcap = 0;
+        if (lcap != c->search_lcap) {
+            c->search_lcap = lcap;
+            ++c->gen;  // a captured step holds the old buffer size
+        }
     } else {
         n_total = c->cap_total;
     }
@@ -625,7 +636,7 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
     stage_mark(c, st, 1, false);
     int ldn = list_ldn(c);
     stage_mark(c, st, 2, true);
-    run_search(c, srt, n_total, n, st);
+    run_search(c, srt, n_total, n, c->search_cap ? c->search_cap : c->search_lcap, st);
     if (c->solve_mode != 0)
         launch_bin_tiles((const int *)c->count.p, srt.id, &c->sc->n_total, (int)n_total, n, c->dc.max_nb,
                          c->queue_tile, (int *)c->wq.p, st);
@@ -822,7 +833,7 @@ extern "C" lp_status lp_neighbors(lp_ctx *c, void *stream, int64_t n, const doub
                    srt.id, st);
     launch_coarsen((uint32_t *)c->tables.p, c->grid, D, &c->sc->n_total, st);
     int ldn = list_ldn(c);
-    run_search(c, srt, n, (int)n, st);
+    run_search(c, srt, n, (int)n, c->search_cap, st);
     launch_lists_out(srt.id, (const int *)c->nbr.p, ldn, (const int *)c->count.p, (int)n, c->dc.max_nb, count, idx, st);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
@@ -875,7 +886,7 @@ extern "C" lp_status lp_gfd(lp_ctx *c, void *stream, int64_t n, const double *x,
                    srt.id, st);
     launch_coarsen((uint32_t *)c->tables.p, c->grid, D, &c->sc->n_total, st);
     int ldn = list_ldn(c);
-    run_search(c, srt, n, (int)n, st);
+    run_search(c, srt, n, (int)n, c->search_cap, st);
     launch_gfd(srt, fs, nf, (const int *)c->nbr.p, ldn, (const int *)c->count.p, (int)n, c->dc, c->sc,
                (int *)c->queue.p, deriv, status, st);
     launch_gfd_fallback(srt, fs, nf, (const int *)c->nbr.p, ldn, (const int *)c->count.p, (int)n, c->dc, c->sc,
@@ -983,30 +994,41 @@ extern "C" lp_status lp_profile_read(lp_ctx *c, void *stream, double *ms, int64_
 
 extern "C" lp_status lp_set_tuning(lp_ctx *c, int32_t param, int32_t value) {
     if (!c) return LP_E_ARG;
+    int *field = nullptr;
     switch (param) {
     case LP_TUNE_SEARCH_MODE:
         if (value < 0 || value > 2) return fail(c, LP_E_ARG, "search mode must be 0, 1 or 2");
-        c->search_mode = value;
-        return LP_OK;
+        field = &c->search_mode;
+        break;
     case LP_TUNE_SEARCH_GROUP:
         if (value != 4 && value != 8 && value != 16 && value != 32) return fail(c, LP_E_ARG, "group must be 4..32");
-        c->search_group = value;
-        return LP_OK;
+        field = &c->search_group;
+        break;
     case LP_TUNE_SOLVE_BLOCK:
         if (value != 64 && value != 128 && value != 256) return fail(c, LP_E_ARG, "solve block must be 64..256");
-        c->solve_block = value;
-        return LP_OK;
+        field = &c->solve_block;
+        break;
     case LP_TUNE_SOLVE_MODE:
         if (value < 0 || value > 2) return fail(c, LP_E_ARG, "solve mode must be 0, 1 or 2");
-        c->solve_mode = value;
-        return LP_OK;
+        field = &c->solve_mode;
+        break;
     case LP_TUNE_QUEUE_TILE:
         if (value != 256 && value != 512 && value != 1024) return fail(c, LP_E_ARG, "queue tile must be 256, 512 or 1024");
-        c->queue_tile = value;
-        return LP_OK;
+        field = &c->queue_tile;
+        break;
+    case LP_TUNE_SEARCH_CAP:
+        if (value != 0 && (value < 8 || value > 128 || value % 8 != 0))
+            return fail(c, LP_E_ARG, "search cap must be 0 or a multiple of 8 in 8..128");
+        field = &c->search_cap;
+        break;
     default:
         return fail(c, LP_E_ARG, "unknown tuning parameter %d", param);
     }
+    if (*field != value) {
+        *field = value;
+        ++c->gen;  // a captured step holds the old launch shapes
+    }
+    return LP_OK;
 }
 
 extern "C" lp_status lp_get_tuning(const lp_ctx *c, int32_t param, int32_t *value) {
@@ -1017,6 +1039,7 @@ extern "C" lp_status lp_get_tuning(const lp_ctx *c, int32_t param, int32_t *valu
     case LP_TUNE_SOLVE_BLOCK: *value = c->solve_block; return LP_OK;
     case LP_TUNE_SOLVE_MODE: *value = c->solve_mode; return LP_OK;
     case LP_TUNE_QUEUE_TILE: *value = c->queue_tile; return LP_OK;
+    case LP_TUNE_SEARCH_CAP: *value = c->search_cap; return LP_OK;
     default: return LP_E_ARG;
     }
 }

@@ -26,6 +26,7 @@ __global__ void k_reset_scalars(DevScalars *sc, double dt_in, int n_real, int cl
     sc->rmin = 0x7ff0000000000000ull;
     sc->dt_in = dt_in;
     sc->n_ghost = 0;
+    sc->prev_max_count = sc->max_count;
     sc->max_count = 0;
     sc->n_fallback = 0;
     sc->n_overflow = 0;

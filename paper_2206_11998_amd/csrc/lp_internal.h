@@ -45,6 +45,7 @@ struct DevScalars {
     int n_total;                    // real + ghost particles
     int n_ghost;
     int max_count;
+    int prev_max_count;             // max_count of the step before (kept by k_reset_scalars)
     int n_fallback;
     unsigned int error_bits;        // 1: capacity, 2: numeric
     unsigned int done;              // lp_run: t reached t_end
@@ -119,7 +120,7 @@ void launch_scatter(const ScatterArgs &a, int n_real, const int *n_total_dev, in
 void launch_coarsen(uint32_t *tables, const DevGrid &g, int D, const int *n_total_dev, hipStream_t st);
 void launch_search(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real, const uint32_t *tables,
                    const DevGrid &g, const DevCfg &cfg, int *nbr, int ldn, int *count, DevScalars *sc,
-                   int group, int *ovf_queue, bool balanced, hipStream_t st);
+                   int group, int lcap, int *ovf_queue, bool balanced, hipStream_t st);
 void launch_search_tiles(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real,
                          const uint32_t *tables, const DevGrid &g, const DevCfg &cfg, double *hit_d2, int *hit_j,
                          int *nbr, int ldn, int *count, DevScalars *sc, const uint32_t *key, uint32_t *flags,

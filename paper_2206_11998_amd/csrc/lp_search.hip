@@ -192,7 +192,9 @@ __global__ __launch_bounds__(64) void k_search_overflow(Sorted srt, const uint32
 // cell, so the position loads coalesce.  Hits are compacted with a ballot and
 // ranked by a counting sort on a monotone bucket of d2 followed by exact
 // (d2, original id) comparisons inside each bucket, so the list is the same
-// unique (d2, id) order as k_search's.
+// unique (d2, id) order as k_search's.  A hit is staged as the FP32 rounding
+// of its d2 (round to nearest is monotone, so a smaller key means a smaller
+// d2); only hits whose keys tie recompute their exact FP64 d2 for the order.
 #define SB_NB 32  // rank buckets per particle
 
 // c = q * n + rem for 0 <= c < 2^24 without an integer division
@@ -214,11 +216,11 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *
     extern __shared__ unsigned char smem[];
     const int max_nb = cfg.max_nb;
     const int stride = lcap + 1;  // odd group stride: groups of a wave hit different LDS banks
-    double *ld2 = reinterpret_cast<double *>(smem);
-    int *lj = reinterpret_cast<int *>(ld2 + PPB * stride);
+    float *lkey = reinterpret_cast<float *>(smem);
+    int *lj = reinterpret_cast<int *>(lkey + PPB * stride);
     unsigned char *lperm = reinterpret_cast<unsigned char *>(lj + PPB * stride);
     int *lbk = reinterpret_cast<int *>(lperm + PPB * ((stride + 3) & ~3));
-    // after ranking, the (d2) slots hold the ranked lists lout[rank * PPB + grp]
+    // after ranking, the key slots hold the ranked lists lout[rank * PPB + grp]
     // and the bucket counters the list length of every group (0: written elsewhere)
     int *lout = reinterpret_cast<int *>(smem);
     int *lk = lbk;
@@ -231,16 +233,19 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *
     const int s = xcd_remap(blockIdx.x, gridDim.x) * PPB + grp;
     const int n_total = *n_total_dev;
     const bool active = s < n_total && srt.id[s] < n_real;
-    double *gd2 = ld2 + grp * stride;
+    float *gkey = lkey + grp * stride;
     int *gj = lj + grp * stride;
     unsigned char *gperm = lperm + grp * ((stride + 3) & ~3);
     int *gbk = lbk + grp * SB_NB;
     int k = 0;  // hits so far (the same in every lane of the group)
     double r2 = 0.0;
+    double xi[3] = {0.0, 0.0, 0.0};
 
     for (int q = lane; q < SB_NB; q += G) gbk[q] = 0;
     if (active) {
-        const double xi[3] = {srt.x[0][s], srt.x[1][s], D == 3 ? srt.x[2][s] : 0.0};
+        xi[0] = srt.x[0][s];
+        xi[1] = srt.x[1][s];
+        if (D == 3) xi[2] = srt.x[2][s];
         const double ri = srt.r[s];
         r2 = ri * ri;
         // a cell is skipped only when even its box widened by a rounding slack
@@ -328,7 +333,7 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *
                 if (hita) {
                     const int slot = k + __popcll(ma & below);
                     if (slot < lcap) {
-                        gd2[slot] = d2a;
+                        gkey[slot] = (float)d2a;
                         gj[slot] = ja;
                     }
                 }
@@ -336,7 +341,7 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *
                 if (hitb) {
                     const int slot = k + __popcll(mb & below);
                     if (slot < lcap) {
-                        gd2[slot] = d2b;
+                        gkey[slot] = (float)d2b;
                         gj[slot] = jb;
                     }
                 }
@@ -359,7 +364,7 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *
         for (int q = 0; q < EMAX; ++q) {
             const int e = lane + q * G;
             if (e < k) {
-                const float x = (float)gd2[e] * inv_r2;
+                const float x = gkey[e] * inv_r2;
                 int bb = (int)((float)SB_NB * (x * sqrtf(x)));
                 bb = bb < 0 ? 0 : (bb > SB_NB - 1 ? SB_NB - 1 : bb);
                 bk[q] = bb;
@@ -423,17 +428,33 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *
         for (int q = 0; q < EMAX; ++q) {
             const int e = lane + q * G;
             if (e < k) {
-                const double de = gd2[e];
+                const float ke = gkey[e];
                 const int je = gj[e];
                 const int bb = bk[q];
                 const int lo = gbk[bb];
                 const int hi = bb + 1 < SB_NB ? gbk[bb + 1] : k;
                 int rk = lo;
+                bool have_de = false;
+                double de = 0.0;
                 for (int f = lo; f < hi; ++f) {
                     const int pf = gperm[f];
-                    const double df = gd2[pf];
-                    if (df < de) ++rk;
-                    else if (df == de && pf != e && srt.id[gj[pf]] < srt.id[je]) ++rk;  // exact tie: id order
+                    const float kf = gkey[pf];
+                    if (kf < ke) {
+                        ++rk;
+                    } else if (kf == ke && pf != e) {
+                        // equal keys: the exact d2, recomputed as the dealing
+                        // loop computed it, then the original id
+                        const int jf = gj[pf];
+                        double dx[3];
+                        if (!have_de) {
+                            disp_to<D, PER>(cfg, srt.x, je, xi, dx);
+                            de = dist2_exact<D>(dx);
+                            have_de = true;
+                        }
+                        disp_to<D, PER>(cfg, srt.x, jf, xi, dx);
+                        const double df = dist2_exact<D>(dx);
+                        if (df < de || (df == de && srt.id[jf] < srt.id[je])) ++rk;
+                    }
                 }
                 rank[q] = rk;
                 jq[q] = je;
@@ -467,12 +488,12 @@ static size_t search_smem(int G, int lcap) {
     return (size_t)ppb * lcap * (8 + 4) + (size_t)ppb * 4;
 }
 
-// LDS of k_search_bal: per group, lcap + 1 (d2, index) slots, a byte
-// permutation and SB_NB bucket counters (the ranked lists reuse the slots)
+// LDS of k_search_bal: per group, lcap + 1 (FP32 key, index) slots, a byte
+// permutation and SB_NB bucket counters (the ranked lists reuse the key slots)
 static size_t search_bal_smem(int G, int lcap) {
     size_t ppb = (size_t)(LP_BLOCK / G);
     size_t stride = (size_t)lcap + 1;
-    return ppb * stride * 12 + ppb * ((stride + 3) & ~(size_t)3) + ppb * SB_NB * 4;
+    return ppb * stride * 8 + ppb * ((stride + 3) & ~(size_t)3) + ppb * SB_NB * 4;
 }
 
 template <int D, int G>
@@ -499,10 +520,13 @@ static void launch_search_t(const Sorted &s, const int *n_total_dev, int n_total
 
 void launch_search(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real, const uint32_t *tables,
                    const DevGrid &g, const DevCfg &cfg, int *nbr, int ldn, int *count, DevScalars *sc, int group,
-                   int *ovf_queue, bool balanced, hipStream_t st) {
+                   int lcap_req, int *ovf_queue, bool balanced, hipStream_t st) {
     int G = group;
     if (G != 4 && G != 8 && G != 16 && G != 32) G = 16;
+    // slots per particle in LDS (longer lists take the overflow kernel); a
+    // smaller buffer lets more blocks share a CU
     int lcap = cfg.max_nb < 128 ? cfg.max_nb : 128;
+    if (lcap_req > 0 && lcap_req < lcap) lcap = lcap_req;
     // LDS per block within 64 KiB
     while ((balanced ? search_bal_smem(G, lcap) : search_smem(G, lcap)) > 65536 && G < 64) G *= 2;
 #define LS(DD, GG) launch_search_t<DD, GG>(s, n_total_dev, n_total_cap, n_real, tables, g, cfg, nbr, ldn, count, sc, lcap, ovf_queue, balanced, st)

@@ -26,9 +26,9 @@ EXPORTS = ["lp_config_default", "lp_create", "lp_destroy", "lp_neighbors", "lp_g
            "lp_last_error"]
 MLP_NPARAM = 5313
 MLP_NIN = 16
-TUNE_SEARCH_MODE, TUNE_SEARCH_GROUP, TUNE_SOLVE_BLOCK, TUNE_SOLVE_MODE, TUNE_QUEUE_TILE = 0, 1, 2, 3, 4
-TUNE_COUNT = 5
-TUNE_NAMES = ["search_mode", "search_group", "solve_block", "solve_mode", "queue_tile"]
+TUNE_SEARCH_MODE, TUNE_SEARCH_GROUP, TUNE_SOLVE_BLOCK, TUNE_SOLVE_MODE, TUNE_QUEUE_TILE, TUNE_SEARCH_CAP = range(6)
+TUNE_COUNT = 6
+TUNE_NAMES = ["search_mode", "search_group", "solve_block", "solve_mode", "queue_tile", "search_cap"]
 STAGES = ["prep", "cells", "search", "fit", "update", "fallback", "step", "mlp"]
 
 

@@ -65,6 +65,18 @@ def test_solve_modes_identical(lp, case, precision):
 
 
 @pytest.mark.parametrize("case", list(CASES))
+def test_search_cap_identical(lp, case):
+    """The search's LDS list slots: automatic (from the previous step's
+    longest list), the full 128, and caps small enough that most lists are
+    redone by the overflow kernel."""
+    cfg, st = CASES[case]()
+    ref = _steps(lp, cfg, st, 3, tuning={lp.TUNE_SEARCH_CAP: 128})
+    for cap in (0, 8, 40):
+        say("search cap", case, cap)
+        _same(_steps(lp, cfg, st, 3, tuning={lp.TUNE_SEARCH_CAP: cap}), ref, "%s search cap %d" % (case, cap))
+
+
+@pytest.mark.parametrize("case", list(CASES))
 def test_run_graph_matches_steps(lp, case):
     cfg, st = CASES[case]()
     # planning step + full replay chunks + a partial one (the edge of the

@@ -28,10 +28,11 @@ def _dev(a):
 SEARCH_MODES = [0, 1, 2]
 
 
-def _nb_case(lp, oracle_lib, cfg, x, r, tag, mode=1):
-    say("neighbors", tag, x.shape, "search mode", mode)
+def _nb_case(lp, oracle_lib, cfg, x, r, tag, mode=1, cap=0):
+    say("neighbors", tag, x.shape, "search mode", mode, "cap", cap)
     ctx = lp.Context(cfg)
     ctx.set_tuning(lp.TUNE_SEARCH_MODE, mode)
+    ctx.set_tuning(lp.TUNE_SEARCH_CAP, cap)
     count, idx, st = ctx.neighbors([_dev(x[:, a]) for a in range(cfg["dim"])], _dev(r))
     assert st == lp.OK
     count = count.cpu().numpy()
@@ -86,6 +87,14 @@ def test_neighbors_long_lists(lp, oracle_lib, mode):
     cfg["max_nb"] = 256
     r = radii(cfg, st) * 1.75  # about 190 neighbours
     _nb_case(lp, oracle_lib, cfg, st["x"], r, "long lists", mode)
+
+
+@pytest.mark.parametrize("cap", [8, 24])
+def test_neighbors_small_lds_cap(lp, oracle_lib, cap):
+    """With few LDS slots most lists are redone by the overflow kernel; on the
+    exact lattice every shell of equal distances is a tie of staged keys."""
+    cfg, st = W.uniform_box(3, 12, jitter=0.0)
+    _nb_case(lp, oracle_lib, cfg, st["x"], radii(cfg, st), "exact lattice", 2, cap)
 
 
 def test_neighbors_capacity(lp):
