@@ -216,13 +216,17 @@ __device__ __forceinline__ double min_image(const DevCfg &c, int a, double d) {
 // in flight together.
 // PER = false: the caller knows that no axis is periodic (plain differences).
 template <int D, bool PER = true>
+__device__ __forceinline__ void disp_of(const DevCfg &c, const double xj[3], const double xi[3], double dx[3]) {
+    dx[0] = PER ? min_image(c, 0, xj[0] - xi[0]) : xj[0] - xi[0];
+    dx[1] = PER ? min_image(c, 1, xj[1] - xi[1]) : xj[1] - xi[1];
+    dx[2] = D == 3 ? (PER ? min_image(c, 2, xj[2] - xi[2]) : xj[2] - xi[2]) : 0.0;
+}
+
+template <int D, bool PER = true>
 __device__ __forceinline__ void disp_to(const DevCfg &c, const double *const x[3], int j, const double xi[3],
                                         double dx[3]) {
-    const double a0 = x[0][j], a1 = x[1][j];
-    const double a2 = D == 3 ? x[2][j] : 0.0;
-    dx[0] = PER ? min_image(c, 0, a0 - xi[0]) : a0 - xi[0];
-    dx[1] = PER ? min_image(c, 1, a1 - xi[1]) : a1 - xi[1];
-    dx[2] = D == 3 ? (PER ? min_image(c, 2, a2 - xi[2]) : a2 - xi[2]) : 0.0;
+    const double xj[3] = {x[0][j], x[1][j], D == 3 ? x[2][j] : 0.0};
+    disp_of<D, PER>(c, xj, xi, dx);
 }
 
 // Squared distance ((dx*dx) + (dy*dy)) + (dz*dz) with every product and sum
@@ -327,7 +331,12 @@ __device__ __forceinline__ int nb_at(const int *nbr, int ldn, int s, int c) {
 // Level used by a particle of radius r: the coarsest level whose cells are not
 // larger than r (so the search box spans 2-5 cells per axis), clamped.
 __device__ __forceinline__ int level_for_radius(const DevGrid &g, double r) {
+    // s[L] = S 2^-L: halving is exact, so only the first level's side is read
     int L = g.L_lo;
-    while (L < g.L_hi && g.s[L] > r) ++L;
+    double sL = g.s[g.L_lo];
+    while (L < g.L_hi && sL > r) {
+        ++L;
+        sL *= 0.5;
+    }
     return L;
 }

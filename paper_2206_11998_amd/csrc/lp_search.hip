@@ -18,8 +18,10 @@ __device__ __forceinline__ void search_box(const DevGrid &g, const DevCfg &cfg, 
                                            int clo[3], int cn[3]) {
     for (int a = 0; a < D; ++a) {
         int n = g.nc[L][a];
-        double tl = (xi[a] - ri - g.lo[a]) * g.inv_s[L];
-        double th = (xi[a] + ri - g.lo[a]) * g.inv_s[L];
+        // inv_s[L] = 2^L / S, an exact power-of-two scaling of the first level's
+        const double inv = ldexp(g.inv_s[g.L_lo], L - g.L_lo);
+        double tl = (xi[a] - ri - g.lo[a]) * inv;
+        double th = (xi[a] + ri - g.lo[a]) * inv;
         int lo = floor_clamped(tl - 1e-9), hi = floor_clamped(th + 1e-9);
         if (cfg.periodic[a]) {
             if (hi - lo + 1 >= n || hi < lo) { lo = 0; hi = n - 1; }
@@ -197,13 +199,14 @@ __global__ __launch_bounds__(64) void k_search_overflow(Sorted srt, const uint32
 // d2); only hits whose keys tie recompute their exact FP64 d2 for the order.
 #define SB_NB 32  // rank buckets per particle
 
-// c = q * n + rem for 0 <= c < 2^24 without an integer division
+// c = q * n + rem for 0 <= c < 2^24 without an integer division (the FP32
+// quotient is off by at most one either way; corrected without branches)
 __device__ __forceinline__ int div_small(int c, int n, float rcp, int &rem) {
     int q = (int)((float)c * rcp);
     int r = c - q * n;
-    if (r < 0) { --q; r += n; }
-    else if (r >= n) { ++q; r -= n; }
-    rem = r;
+    const int lo = r < 0 ? 1 : 0, hi = r >= n ? 1 : 0;
+    q += hi - lo;
+    rem = r + (lo - hi) * n;
     return q;
 }
 
@@ -253,50 +256,66 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *
         // particles clamped into the grid) is farther than r from x_i
         const double r2_keep = r2 * (1.0 + 1e-12);
         const int L = level_for_radius(g, ri);
-        const double cs = g.s[L];
+        const double cs = ldexp(g.s[g.L_lo], g.L_lo - L);  // = s[L] exactly
         const double slack = 1e-12 * g.s[0];
         const uint32_t *tab = tables + g.off[L];
         int clo[3] = {0, 0, 0}, cn[3] = {1, 1, 1};
         search_box<D>(g, cfg, L, xi, ri, clo, cn);
         const int ncells = cn[0] * cn[1] * (D == 3 ? cn[2] : 1);
         const float rcp0 = 1.0f / (float)cn[0], rcp1 = 1.0f / (float)cn[1];
-        for (int c0 = 0; c0 < ncells; c0 += G) {
-            const int c = c0 + lane;
-            int b = 0, len = 0;
-            if (c < ncells) {
-                int cc[3], rem;
-                const int q0 = div_small(c, cn[0], rcp0, rem);
-                cc[0] = clo[0] + rem;
-                if (D == 3) {
-                    const int q1 = div_small(q0, cn[1], rcp1, rem);
-                    cc[1] = clo[1] + rem;
-                    cc[2] = clo[2] + q1;
-                } else {
-                    cc[1] = clo[1] + q0;
-                    cc[2] = 0;
-                }
-                double dd = 0.0;
+        // cells per axis at level L (indexed by a per-particle level, so read
+        // once here rather than in every batch)
+        int nL[3];
 #pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    if (PER && cfg.periodic[a]) continue;
-                    const int n_a = g.nc[L][a];
-                    const double lo_a = cc[a] <= 0 ? -INFINITY : g.lo[a] + cc[a] * cs - slack;
-                    const double hi_a = cc[a] >= n_a - 1 ? INFINITY : g.lo[a] + (cc[a] + 1) * cs + slack;
-                    const double t = xi[a] < lo_a ? lo_a - xi[a] : (xi[a] > hi_a ? xi[a] - hi_a : 0.0);
-                    dd += t * t;
-                }
-                if (!(dd > r2_keep)) {
-#pragma unroll
-                    for (int a = 0; a < D; ++a)
-                        if (PER && cfg.periodic[a]) {
-                            const int n_a = g.nc[L][a];
-                            cc[a] = cc[a] < 0 ? cc[a] + n_a : (cc[a] >= n_a ? cc[a] - n_a : cc[a]);
-                        }
-                    const uint32_t code = morton<D>(cc);
-                    b = (int)tab[code];
-                    len = (int)tab[code + 1] - b;
-                }
+        for (int a = 0; a < 3; ++a) nL[a] = g.nc[L][a];
+        // Morton code of cell c of the box; false for a cell past the end or
+        // provably outside the ball
+        auto cell_code = [&](int c, uint32_t &code) -> bool {
+            code = 0u;
+            if (c >= ncells) return false;
+            int cc[3], rem;
+            const int q0 = div_small(c, cn[0], rcp0, rem);
+            cc[0] = clo[0] + rem;
+            if (D == 3) {
+                const int q1 = div_small(q0, cn[1], rcp1, rem);
+                cc[1] = clo[1] + rem;
+                cc[2] = clo[2] + q1;
+            } else {
+                cc[1] = clo[1] + q0;
+                cc[2] = 0;
             }
+            double dd = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                if (PER && cfg.periodic[a]) continue;
+                const int n_a = nL[a];
+                const double lo_a = cc[a] <= 0 ? -INFINITY : g.lo[a] + cc[a] * cs - slack;
+                const double hi_a = cc[a] >= n_a - 1 ? INFINITY : g.lo[a] + (cc[a] + 1) * cs + slack;
+                // distance of x_i to [lo_a, hi_a] along a (at most one term is positive)
+                const double t = fmax(lo_a - xi[a], 0.0) + fmax(xi[a] - hi_a, 0.0);
+                dd += t * t;
+            }
+            if (dd > r2_keep) return false;
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+                if (PER && cfg.periodic[a]) {
+                    const int n_a = nL[a];
+                    cc[a] = cc[a] < 0 ? cc[a] + n_a : (cc[a] >= n_a ? cc[a] - n_a : cc[a]);
+                }
+            code = morton<D>(cc);
+            return true;
+        };
+        // the cell-table entries of the next batch are loaded (unconditionally:
+        // a skipped cell reads entry 0) while this batch's candidates are tested
+        uint32_t nb_code;
+        bool nb_ok = cell_code(lane, nb_code);
+        uint32_t nb_lo = tab[nb_code], nb_hi = tab[nb_code + 1];
+        for (int c0 = 0; c0 < ncells; c0 += G) {
+            const int b = (int)nb_lo;
+            const int len = nb_ok ? (int)(nb_hi - nb_lo) : 0;
+            nb_ok = cell_code(c0 + G + lane, nb_code);
+            nb_lo = tab[nb_code];
+            nb_hi = tab[nb_code + 1];
             // inclusive prefix sum of the candidate counts over the group
             int incl = len;
 #pragma unroll
@@ -306,9 +325,10 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *
             }
             const int excl = incl - len;
             const int total = __shfl(incl, G - 1, G);
-            // two candidates per lane and round (t and t + G), so that two
-            // search chains and six position loads are in flight together
-            for (int t0 = 0; t0 < total; t0 += 2 * G) {
+            // two candidates per lane and round (t and t + G).  The positions
+            // of the next round are loaded (unconditionally, so that the loads
+            // stay in flight) before this round's hits are compacted.
+            auto fetch = [&](int t0, int &ja, int &jb, bool &oka, bool &okb, double *pa, double *pb) {
                 const int ta = t0 + lane, tb = ta + G;
                 // the cell of candidate t: the last lane q with excl_q <= t
                 int qa = 0, qb = 0;
@@ -319,22 +339,38 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *
                     if (va <= ta) qa += step;
                     if (vb <= tb) qb += step;
                 }
-                const int ja = __shfl(b, qa, G) + (ta - __shfl(excl, qa, G));
-                const int jb = __shfl(b, qb, G) + (tb - __shfl(excl, qb, G));
-                const bool oka = ta < total && ja != s, okb = tb < total && jb != s;
+                ja = __shfl(b, qa, G) + (ta - __shfl(excl, qa, G));
+                jb = __shfl(b, qb, G) + (tb - __shfl(excl, qb, G));
+                oka = ta < total && ja != s;
+                okb = tb < total && jb != s;
                 // slots past the end read the particle itself (a valid index)
+                const int ia = oka ? ja : s, ib = okb ? jb : s;
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    pa[a] = srt.x[a][ia];
+                    pb[a] = srt.x[a][ib];
+                }
+            };
+            int ja, jb;
+            bool oka, okb;
+            double pa[3] = {0.0, 0.0, 0.0}, pb[3] = {0.0, 0.0, 0.0};
+            fetch(0, ja, jb, oka, okb, pa, pb);
+            for (int t0 = 0; t0 < total; t0 += 2 * G) {
+                const int ca = ja, cb = jb;
+                const bool ua = oka, ub = okb;
                 double dxa[3], dxb[3];
-                disp_to<D, PER>(cfg, srt.x, oka ? ja : s, xi, dxa);
-                disp_to<D, PER>(cfg, srt.x, okb ? jb : s, xi, dxb);
+                disp_of<D, PER>(cfg, pa, xi, dxa);
+                disp_of<D, PER>(cfg, pb, xi, dxb);
+                fetch(t0 + 2 * G, ja, jb, oka, okb, pa, pb);
                 const double d2a = dist2_exact<D>(dxa), d2b = dist2_exact<D>(dxb);
-                const bool hita = oka && d2a < r2, hitb = okb && d2b < r2;
+                const bool hita = ua && d2a < r2, hitb = ub && d2b < r2;
                 const unsigned long long ma = (__ballot(hita) >> gshift) & gmask;
                 const unsigned long long mb = (__ballot(hitb) >> gshift) & gmask;
                 if (hita) {
                     const int slot = k + __popcll(ma & below);
                     if (slot < lcap) {
                         gkey[slot] = (float)d2a;
-                        gj[slot] = ja;
+                        gj[slot] = ca;
                     }
                 }
                 k += __popcll(ma);
@@ -342,7 +378,7 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *
                     const int slot = k + __popcll(mb & below);
                     if (slot < lcap) {
                         gkey[slot] = (float)d2b;
-                        gj[slot] = jb;
+                        gj[slot] = cb;
                     }
                 }
                 k += __popcll(mb);
@@ -350,10 +386,10 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *
         }
     }
     __syncthreads();
-    // rank: bucket B(d2) = floor(SB_NB (d2/r2)^(3/2)) in FP32 is non-decreasing
-    // in d2 (every operation is monotone), so entries of lower buckets rank
-    // lower; inside a bucket the exact (d2, id) comparison decides.  The 3/2
-    // power spreads a uniform particle density evenly over the buckets.
+    // rank: bucket B(d2) = floor(SB_NB d2/r2) in FP32 is non-decreasing in d2
+    // (every operation is monotone), so entries of lower buckets rank lower;
+    // inside a bucket the exact (d2, id) comparison decides.  For a uniform
+    // particle density the outermost bucket holds 1.5x the mean share.
     const bool ranked = active && k <= lcap;
     const float inv_r2 = ranked ? (float)(1.0 / r2) : 0.0f;
     constexpr int EMAX = 128 / G;  // entries per lane (k <= lcap <= 128)
@@ -365,7 +401,7 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *
             const int e = lane + q * G;
             if (e < k) {
                 const float x = gkey[e] * inv_r2;
-                int bb = (int)((float)SB_NB * (x * sqrtf(x)));
+                int bb = (int)((float)SB_NB * x);
                 bb = bb < 0 ? 0 : (bb > SB_NB - 1 ? SB_NB - 1 : bb);
                 bk[q] = bb;
                 pos[q] = atomicAdd(&gbk[bb], 1);
