@@ -417,12 +417,89 @@ __device__ __forceinline__ void estimator_features(const DevCfg &cfg, const doub
     f[15] = (float)(h * sqrt(gu2) / cs);
 }
 
-template <int D, typename T>
+// ---------------------------------------------------------------------------
+// Second-order derivatives kept between the fit and the update kernels
+// (SoA, der[q * ld + t], t the particle's work slot): gradients of V, u_1..u_D, P (D each), the Hessians
+// of u_1..u_D (NS each) and the diagonal second derivatives of P (D).
+// ---------------------------------------------------------------------------
+template <int D> struct Der { static constexpr int N = (D + 2) * D + D * Dim<D>::NS + D; };
+
+template <int D>
+__device__ __forceinline__ void store_der(double *der, int64_t ld, int s, const double grad[Dim<D>::NF][3],
+                                          const double hess[Dim<D>::NF][Dim<D>::NS]) {
+    constexpr int NF = Dim<D>::NF, NS = Dim<D>::NS;
+    int q = 0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int a = 0; a < D; ++a) der[(q++) * ld + s] = grad[f][a];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int c = 0; c < NS; ++c) der[(q++) * ld + s] = hess[1 + k][c];
+#pragma unroll
+    for (int a = 0; a < D; ++a) der[(q++) * ld + s] = hess[D + 1][a];
+}
+
+template <int D>
+__device__ __forceinline__ void load_der(const double *der, int64_t ld, int s, double grad[Dim<D>::NF][3],
+                                         double hess[Dim<D>::NF][Dim<D>::NS]) {
+    constexpr int NF = Dim<D>::NF, NS = Dim<D>::NS;
+    int q = 0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) grad[f][a] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NS; ++c) hess[f][c] = 0.0;
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int a = 0; a < D; ++a) grad[f][a] = der[(q++) * ld + s];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int c = 0; c < NS; ++c) hess[1 + k][c] = der[(q++) * ld + s];
+#pragma unroll
+    for (int a = 0; a < D; ++a) hess[D + 1][a] = der[(q++) * ld + s];
+}
+
+// Where the update reads the particle's LW derivatives: registers (the
+// fallback's own fit) or the derivative array of the fast fit, read where
+// they are used, so that they hold no registers through the half-ball loops.
+template <int D> struct DerRegs {
+    const double (*grad)[3];
+    const double (*hess)[Dim<D>::NS];
+    __device__ __forceinline__ double g(int f, int a) const { return grad[f][a]; }
+    __device__ __forceinline__ void all(double gr[Dim<D>::NF][3], double he[Dim<D>::NF][Dim<D>::NS]) const {
+#pragma unroll
+        for (int f = 0; f < Dim<D>::NF; ++f) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) gr[f][a] = grad[f][a];
+#pragma unroll
+            for (int c = 0; c < Dim<D>::NS; ++c) he[f][c] = hess[f][c];
+        }
+    }
+};
+
+template <int D> struct DerMem {
+    const double *der;
+    int64_t ld;
+    int t;
+    // gradient entry (f, a) is entry f * D + a of the array's layout
+    __device__ __forceinline__ double g(int f, int a) const { return der[(int64_t)(f * D + a) * ld + t]; }
+    __device__ __forceinline__ void all(double gr[Dim<D>::NF][3], double he[Dim<D>::NF][Dim<D>::NS]) const {
+        load_der<D>(der, ld, t, gr, he);
+    }
+};
+
+template <int D, typename T, class DS>
 __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p, const DevCfg &cfg, DevScalars *sc,
                                                 const int *nbr, int ldn, int s, int i, int k, double dt,
                                                 const double xi[3], const double st[Dim<D>::NF], double h, double r,
-                                                const double grad[Dim<D>::NF][3], const double hess[Dim<D>::NF][Dim<D>::NS],
-                                                int lw_status, uint8_t flags, const MlpStage *ms = nullptr) {
+                                                const DS &ds, int lw_status, uint8_t flags,
+                                                const MlpStage *ms = nullptr) {
     constexpr int NF = Dim<D>::NF, FP = D + 1, NGD = D * (D + 1) / 2;
     const bool use_f = sizeof(T) == 4;
     // V and P over the particle and its half-ball members (network inputs)
@@ -542,9 +619,9 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
                 }
             }
             if (!ok) {
-                d[0] = (T)grad[0][a];
-                d[1] = (T)grad[1 + a][a];
-                d[2] = (T)grad[FP][a];
+                d[0] = (T)ds.g(0, a);
+                d[1] = (T)ds.g(1 + a, a);
+                d[2] = (T)ds.g(FP, a);
                 subst = true;
             }
 #pragma unroll
@@ -578,6 +655,8 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
     }
     // rates
     T stT[NF], gT[NF][3], hT[NF][Dim<D>::NS], lw[NF], uw[NF];
+    double grad[NF][3], hess[NF][Dim<D>::NS];
+    ds.all(grad, hess);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         stT[f] = (T)st[f];
@@ -641,54 +720,6 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
     return phi < 1.0;  // limited: counted by the caller
 }
 
-
-// ---------------------------------------------------------------------------
-// Second-order derivatives kept between the fit and the update kernels
-// (SoA, der[q * ld + t], t the particle's work slot): gradients of V, u_1..u_D, P (D each), the Hessians
-// of u_1..u_D (NS each) and the diagonal second derivatives of P (D).
-// ---------------------------------------------------------------------------
-template <int D> struct Der { static constexpr int N = (D + 2) * D + D * Dim<D>::NS + D; };
-
-template <int D>
-__device__ __forceinline__ void store_der(double *der, int64_t ld, int s, const double grad[Dim<D>::NF][3],
-                                          const double hess[Dim<D>::NF][Dim<D>::NS]) {
-    constexpr int NF = Dim<D>::NF, NS = Dim<D>::NS;
-    int q = 0;
-#pragma unroll
-    for (int f = 0; f < NF; ++f)
-#pragma unroll
-        for (int a = 0; a < D; ++a) der[(q++) * ld + s] = grad[f][a];
-#pragma unroll
-    for (int k = 0; k < D; ++k)
-#pragma unroll
-        for (int c = 0; c < NS; ++c) der[(q++) * ld + s] = hess[1 + k][c];
-#pragma unroll
-    for (int a = 0; a < D; ++a) der[(q++) * ld + s] = hess[D + 1][a];
-}
-
-template <int D>
-__device__ __forceinline__ void load_der(const double *der, int64_t ld, int s, double grad[Dim<D>::NF][3],
-                                         double hess[Dim<D>::NF][Dim<D>::NS]) {
-    constexpr int NF = Dim<D>::NF, NS = Dim<D>::NS;
-    int q = 0;
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) grad[f][a] = 0.0;
-#pragma unroll
-        for (int c = 0; c < NS; ++c) hess[f][c] = 0.0;
-    }
-#pragma unroll
-    for (int f = 0; f < NF; ++f)
-#pragma unroll
-        for (int a = 0; a < D; ++a) grad[f][a] = der[(q++) * ld + s];
-#pragma unroll
-    for (int k = 0; k < D; ++k)
-#pragma unroll
-        for (int c = 0; c < NS; ++c) hess[1 + k][c] = der[(q++) * ld + s];
-#pragma unroll
-    for (int a = 0; a < D; ++a) hess[D + 1][a] = der[(q++) * ld + s];
-}
 
 // ---------------------------------------------------------------------------
 // Fast path: one thread per particle.
@@ -847,10 +878,9 @@ __device__ __forceinline__ bool finish_one(const SolveArgs &a, int s, int t) {
     st[FP] = srt.P[s];
     const double h = srt.h[s];
     const double r = cfg.kappa * h;
-    double grad[NF][3], hess[NF][NS];
-    load_der<D>(a.der, a.ld, t, grad, hess);
-    return finish_particle<D, T>(srt, a.p, cfg, a.sc, a.nbr, a.ldn, s, i, k, a.sc->dt, xi, st, h, r, grad, hess, 0,
-                                 0, a.ms.feat ? &a.ms : nullptr);
+    const DerMem<D> ds{a.der, a.ld, t};
+    return finish_particle<D, T>(srt, a.p, cfg, a.sc, a.nbr, a.ldn, s, i, k, a.sc->dt, xi, st, h, r, ds, 0, 0,
+                                 a.ms.feat ? &a.ms : nullptr);
 }
 
 // Work distribution.  WQ_DIRECT: thread t of the grid serves cell-order
@@ -879,8 +909,10 @@ __global__ __launch_bounds__(LP_BLOCK, 2) void k_lw_fit(SolveArgs a) {
     for_work<MODE>(a, a.sc->head[0], [&](int s, int t) { lw_fit_one<D, T, REFINE>(a, s, t); });
 }
 
+// Three waves per SIMD: the FP64 update spills a few registers at that
+// bound, but the extra resident wave hides more of its gather latency.
 template <int D, typename T, int MODE>
-__global__ __launch_bounds__(LP_BLOCK) void k_finish(SolveArgs a) {
+__global__ __launch_bounds__(LP_BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void k_finish(SolveArgs a) {
     int limited = 0;
     for_work<MODE>(a, a.sc->head[1], [&](int s, int t) { limited += finish_one<D, T>(a, s, t) ? 1 : 0; });
     // one atomic per wave (every lane of the wave is active here)
@@ -1214,8 +1246,8 @@ __global__ __launch_bounds__(64) void k_solve_fallback(Sorted srt, Soa p, const 
                                         },
                                         grad, hess, sel);
         if ((threadIdx.x & 63) == 0 &&
-            finish_particle<D, double>(srt, p, cfg, sc, nbr, ldn, s, i, k, sc->dt, xi, st, h, r, grad, hess, status,
-                                       LP_FLAG_FALLBACK, ms.feat ? &ms : nullptr))
+            finish_particle<D, double>(srt, p, cfg, sc, nbr, ldn, s, i, k, sc->dt, xi, st, h, r,
+                                       DerRegs<D>{grad, hess}, status, LP_FLAG_FALLBACK, ms.feat ? &ms : nullptr))
             atomicAdd(&sc->n_limited, 1ull);
         __syncthreads();
     }
