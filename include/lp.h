@@ -68,7 +68,7 @@ typedef struct lp_config {
     int32_t max_nb;         /* neighbour-list capacity per particle, 1..256 */
     int32_t lw_cap;         /* Lax-Wendroff stencil size; 0 -> 54 (3D) / 32 (2D); at most 64 */
     int32_t uw_cap;         /* upwind half-ball size; 0 -> 8; at most 16 */
-    int32_t refine;         /* LP_MIXED: 1 = one FP64-residual refinement of the fit */
+    int32_t refine;         /* LP_MIXED: 1 = one FP64-residual refinement of the fit (see refine_cond) */
     int32_t vacuum;         /* free boundary: incomplete half-balls get vacuum ghosts */
     double gamma;           /* ideal-gas exponent */
     double cfl;             /* dt = cfl * min_i h_i / c_i */
@@ -85,7 +85,13 @@ typedef struct lp_config {
     float mlp_band;         /* LP_EST_MLP: the network's phi is used when |phi - 1/2| >= mlp_band ... */
     float mlp_feat_max;     /* ... and every input lies within +-mlp_feat_max; otherwise the quotient
                                estimator's phi (defaults 0.05 and 8) */
-    int32_t reserved[7];
+    float refine_cond;      /* LP_MIXED with refine: 0 (default) refines every fast-path fit; > 0 refines
+                               only the fits whose normal-matrix condition estimate ||R||_F^2 ||R^-1||_F^2
+                               exceeds it (an upper bound on cond(A)^2, so the FP32 solve's relative
+                               error is at most about refine_cond * 2^-24 elsewhere); the rest keep
+                               the FP32 solution.  A refined fit is computed by a separate launch over
+                               the queued particles, with the same arithmetic as refine_cond = 0 */
+    int32_t reserved[6];
 } lp_config;
 
 typedef struct lp_particles {
@@ -110,6 +116,7 @@ typedef struct lp_info {
     int32_t levels[2];      /* cell-grid levels used by the last search (coarsest, finest) */
     int64_t n_mlp;          /* LP_EST_MLP: particles whose phi came from the network in the last step */
     int64_t n_mlp_plain;    /* LP_EST_MLP: particles that fell back to the quotient estimator */
+    int64_t n_refined;      /* LP_MIXED with refine: fits refined in the last step */
 } lp_info;
 
 /* Fill cfg with the defaults for the given dimension (gamma 1.4, cfl 0.5,

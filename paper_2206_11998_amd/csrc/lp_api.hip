@@ -31,7 +31,7 @@ struct lp_ctx {
     std::string err;
     // workspace
     Buf h, r, gcnt, scan_tmp, ghosts, key, slot, tables, sorted, sortedf, sid, nbr, count, queue, partials, consout,
-        gfd_fields, hitd2, hitj, tflags, tlo, thi, prep_part, ovfq, der, lwst, wq,
+        gfd_fields, hitd2, hitj, tflags, tlo, thi, prep_part, ovfq, der, lwst, wq, rq, rkeep,
         mfeat, mrates, mphi, mflag,                          // network-estimator staging
         theta, adam_m, adam_v, mgrad, mpart, mlosspart, mscal; // network parameters and training
     int search_mode = 2;            // 0: lane group walking its cells, 1: LDS-staged tiles, 2: balanced lane group
@@ -194,6 +194,8 @@ extern "C" lp_status lp_create(const lp_config *cfg, lp_ctx **out) {
         st = fail(c, LP_E_ARG, "unknown estimator mode");
     else if (!(k.mlp_band >= 0.0f && k.mlp_band <= 0.5f) || !(k.mlp_feat_max > 0.0f))
         st = fail(c, LP_E_ARG, "mlp_band must be in [0, 1/2], mlp_feat_max positive");
+    else if (!(k.refine_cond >= 0.0f) || !(k.refine_cond < INFINITY))
+        st = fail(c, LP_E_ARG, "refine_cond must be finite and non-negative");
     else if (!(k.gamma > 1.0) || !(k.kappa > 0.0) || !(k.cfl > 0.0)) st = fail(c, LP_E_ARG, "gamma, kappa, cfl");
     if (st == LP_OK) {
         double S = 0.0;
@@ -228,6 +230,7 @@ extern "C" lp_status lp_create(const lp_config *cfg, lp_ctx **out) {
     d.est_mode = k.estimator;
     d.precision = k.precision;
     d.refine = k.refine;
+    d.refine_cond = k.refine_cond;
     d.gamma = k.gamma;
     d.kappa = k.kappa;
     d.cfl = k.cfl;
@@ -272,7 +275,7 @@ extern "C" lp_status lp_destroy(lp_ctx *c) {
     Buf *bufs[] = {&c->h, &c->r, &c->gcnt, &c->scan_tmp, &c->ghosts, &c->key, &c->slot, &c->tables, &c->sorted,
                    &c->sortedf, &c->sid, &c->nbr, &c->count, &c->queue, &c->partials, &c->consout, &c->gfd_fields,
                    &c->hitd2, &c->hitj, &c->tflags, &c->tlo, &c->thi, &c->prep_part, &c->ovfq, &c->der, &c->lwst,
-                   &c->wq, &c->mfeat, &c->mrates, &c->mphi, &c->mflag, &c->theta, &c->adam_m, &c->adam_v,
+                   &c->wq, &c->rq, &c->rkeep, &c->mfeat, &c->mrates, &c->mphi, &c->mflag, &c->theta, &c->adam_m, &c->adam_v,
                    &c->mgrad, &c->mpart, &c->mlosspart, &c->mscal};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
@@ -424,6 +427,10 @@ static lp_status ensure_capacity(lp_ctx *c, int64_t n_real, int64_t n_total, boo
         ENSURE(c, c->der, sizeof(double) * (size_t)der_count(D) * nt);
         ENSURE(c, c->lwst, (size_t)nt);
         ENSURE(c, c->wq, sizeof(int) * nt);
+        if (mixed && c->dc.refine && c->dc.refine_cond > 0.0f) {
+            ENSURE(c, c->rq, sizeof(int) * 2 * nt);
+            ENSURE(c, c->rkeep, sizeof(float) * (size_t)refine_keep_count(D) * nt);
+        }
         if (c->dc.est_mode == LP_EST_MLP || c->want_stage) {
             ENSURE(c, c->mfeat, sizeof(float) * LP_MLP_NIN * nt);
             ENSURE(c, c->mrates, sizeof(double) * 2 * (D + 2) * nt);
@@ -664,6 +671,8 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
     sv.ld = c->cap_total;
     sv.lwst = (uint8_t *)c->lwst.p;
     sv.wq = c->solve_mode != 0 ? (const int *)c->wq.p : nullptr;
+    sv.rq = (int *)c->rq.p;
+    sv.rkeep = (float *)c->rkeep.p;
     // the network estimator (or a harvest of its inputs) stages the update
     const bool staged = harvest || c->dc.est_mode == LP_EST_MLP;
     if (staged) {
@@ -949,6 +958,7 @@ extern "C" lp_status lp_get_info(lp_ctx *c, void *stream, lp_info *out) {
     out->levels[1] = c->last_levels[1];
     out->n_mlp = (int64_t)c->sc_host->n_mlp;
     out->n_mlp_plain = (int64_t)c->sc_host->n_mlp_plain;
+    out->n_refined = c->sc_host->n_refine;
     return LP_OK;
 }
 

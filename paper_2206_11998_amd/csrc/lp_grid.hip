@@ -29,6 +29,7 @@ __global__ void k_reset_scalars(DevScalars *sc, double dt_in, int n_real, int cl
     sc->prev_max_count = sc->max_count;
     sc->max_count = 0;
     sc->n_fallback = 0;
+    sc->n_refine = 0;
     sc->n_overflow = 0;
     sc->n_limited = 0ull;
     sc->n_mlp = 0ull;

@@ -18,6 +18,7 @@ struct DevCfg {
     int D, nu, nf;              // dimension, second-order unknowns, fields (V, u.., P)
     int lw_cap, uw_cap, max_nb;
     int vacuum, est_mode, precision, refine;
+    float refine_cond;              // > 0: refine only fits whose condition estimate exceeds it
     double gamma, kappa, cfl, est_eps, cond_max, uw_cond_max, cond_fb;
     double lo[3], hi[3], L[3], half[3];
     int periodic[3], wall_lo[3], wall_hi[3];
@@ -47,6 +48,7 @@ struct DevScalars {
     int max_count;
     int prev_max_count;             // max_count of the step before (kept by k_reset_scalars)
     int n_fallback;
+    int n_refine;                   // fits queued for the refinement launch
     unsigned int error_bits;        // 1: capacity, 2: numeric
     unsigned int done;              // lp_run: t reached t_end
     unsigned int clipped;           // this step's dt was shortened to end on t_end
@@ -128,6 +130,7 @@ void launch_search_tiles(const Sorted &s, const int *n_total_dev, int n_total_ca
 void launch_lists_out(const int *sorted_id, const int *nbr, int ldn, const int *count, int n, int max_nb,
                       int *count_out, int *idx_out, hipStream_t st);
 int der_count(int D);
+int refine_keep_count(int D);
 // Staging of the update when the network estimator decides phi: per
 // cell-order particle s its 16 inputs feat[16 s + q], the LW and upwind rates
 // rates[f * ld + s] and rates[(NF + f) * ld + s], the quotient estimator's
@@ -157,6 +160,8 @@ struct SolveArgs {
     int64_t ld;
     uint8_t *lwst;                  // per particle: 0 fast path, 1 queued for the fallback
     const int *wq;                  // work queue of launch_bin_tiles (NULL: direct indexing)
+    int *rq;                        // refinement queue: (cell-order particle, work slot) pairs
+    float *rkeep;                   // per refinement-queue slot: factor, 1/diag and FP32 coefficients
     MlpStage ms;                    // feat != NULL: stage for the network estimator instead of updating
 };
 // mode: 0 direct, 1 work queue, 2 persistent launch over the work queue

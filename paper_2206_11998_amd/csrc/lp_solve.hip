@@ -21,9 +21,18 @@
 // It applies the same rank-deficiency rule as the definition (|R11|/|Rnn|).
 #include "lp_internal.h"
 
+// Multiply-adds are fused only inside one source expression, never across
+// statements, so that every kernel instantiating the same fit code rounds it
+// the same way (the adaptive refinement relies on the FP32 fit of one kernel
+// reproducing the other's bit for bit).
+#pragma clang fp contract(on)
+
 template <int D> struct Dim;
 template <> struct Dim<3> { static constexpr int NU = 9, NF = 5, NS = 6, NG = 45; };
 template <> struct Dim<2> { static constexpr int NU = 5, NF = 4, NS = 3, NG = 15; };
+// what an FP32 fit queued for refinement keeps per queue slot: the factor R
+// (packed), 1/diag R and the FP32 coefficients
+template <int D> struct RefineKeep { static constexpr int N = Dim<D>::NG + Dim<D>::NU + Dim<D>::NF * Dim<D>::NU; };
 
 __host__ __device__ constexpr int tri(int p, int q, int n) { return p * n - p * (p - 1) / 2 + (q - p); }
 
@@ -724,6 +733,59 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
 // ---------------------------------------------------------------------------
 // Fast path: one thread per particle.
 // ---------------------------------------------------------------------------
+// One step of iterative refinement of an FP32 fit: the residual b - A y of
+// the FP64 system at the FP32 solution y (promoted exactly) is formed in
+// FP64; its normal-equation image A^T r and the correction solve use the FP32
+// factor (R, 1/diag R), as the correction only needs working precision.  The
+// refined coefficients are stored as the particle's derivatives.
+template <int D>
+__device__ __forceinline__ void lw_refine_tail(const SolveArgs &a, int s, int t, int k, const double xi[3],
+                                               const double st[Dim<D>::NF], double inv_r, const float G[Dim<D>::NG],
+                                               const float inv[Dim<D>::NU], const float B[Dim<D>::NF * Dim<D>::NU]) {
+    constexpr int NU = Dim<D>::NU, NF = Dim<D>::NF, NS = Dim<D>::NS, FP = D + 1;
+    using T = float;
+    const Sorted &srt = a.srt;
+    T Ar[NF * NU];
+#pragma unroll
+    for (int q = 0; q < NF * NU; ++q) Ar[q] = 0;
+    for_lw_stencil<D>(srt, a.cfg, a.nbr, a.ldn, s, k, xi, [&](int j, const double dx[3]) {
+        double x[3];
+#pragma unroll
+        for (int q = 0; q < D; ++q) x[q] = dx[q] * inv_r;
+        double row[NU];
+        second_order_row<D, double>(x, row);
+        T rowf[NU];
+#pragma unroll
+        for (int pp = 0; pp < NU; ++pp) rowf[pp] = (T)row[pp];
+        double fj[NF];
+        fj[0] = srt.V[j];
+#pragma unroll
+        for (int q = 0; q < D; ++q) fj[1 + q] = srt.u[q][j];
+        fj[FP] = srt.P[j];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            double res = fj[f] - st[f];
+#pragma unroll
+            for (int pp = 0; pp < NU; ++pp) res -= row[pp] * (double)B[f * NU + pp];
+            T rf = (T)res;
+#pragma unroll
+            for (int pp = 0; pp < NU; ++pp) Ar[f * NU + pp] += rowf[pp] * rf;
+        }
+    });
+    chol_solve<NU, NF, T, T>(G, inv, Ar);
+    double grad[NF][3], hess[NF][NS];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            grad[f][q] = q < D ? ((double)B[f * NU + q] + (double)Ar[f * NU + q]) * inv_r : 0.0;
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+            hess[f][q] = ((double)B[f * NU + D + q] + (double)Ar[f * NU + D + q]) * inv_r * inv_r;
+    }
+    store_der<D>(a.der, a.ld, t, grad, hess);
+}
+
 // s: cell-order particle; t: its work slot, which indexes der (the queue
 // order, so that a wave's derivative stores and loads stay coalesced).
 template <int D, typename T, bool REFINE>
@@ -794,7 +856,11 @@ __device__ __forceinline__ void lw_fit_one(const SolveArgs &a, int s, int t) {
     gram_from_moments<D, T>(M, G);
     T inv[NU];
     bool good = m >= NU && cholesky<NU, T>(G, inv);
-    if (good) good = cond_estimate<NU, T>(G, inv) <= (T)cfg.cond_fb;
+    T cond = 0;
+    if (good) {
+        cond = cond_estimate<NU, T>(G, inv);
+        good = cond <= (T)cfg.cond_fb;
+    }
     if (!good) {
         int slot = atomicAdd(&a.sc->n_fallback, 1);
         a.queue[slot] = s;
@@ -804,57 +870,31 @@ __device__ __forceinline__ void lw_fit_one(const SolveArgs &a, int s, int t) {
     a.lwst[s] = 0;
     // B <- (R^T R)^-1 B in place: the scaled coefficients of every field
     chol_solve<NU, NF, T, T>(G, inv, B);
+    if constexpr (REFINE) {
+        lw_refine_tail<D>(a, s, t, k, xi, st, inv_r, G, inv, B);
+        return;
+    }
+    if (use_f && a.rq && cfg.refine && cfg.refine_cond > 0.0f && cond > (T)cfg.refine_cond) {
+        // refined by k_lw_refine from the stored factor and FP32 solution
+        const int slot = atomicAdd(&a.sc->n_refine, 1);
+        a.rq[2 * slot] = s;
+        a.rq[2 * slot + 1] = t;
+        float *keep = a.rkeep + (int64_t)slot * RefineKeep<D>::N;
+#pragma unroll
+        for (int q = 0; q < NG; ++q) keep[q] = (float)G[q];
+#pragma unroll
+        for (int q = 0; q < NU; ++q) keep[NG + q] = (float)inv[q];
+#pragma unroll
+        for (int q = 0; q < NF * NU; ++q) keep[NG + NU + q] = (float)B[q];
+        return;
+    }
     double grad[NF][3], hess[NF][NS];
-    if (REFINE) {
-        // one step of iterative refinement: the residual b - A y of the FP64
-        // system at the FP32 solution y (promoted exactly) is formed in FP64;
-        // its normal-equation image A^T r and the correction solve use the
-        // FP32 factor, as the correction only needs working precision
-        T Ar[NF * NU];
 #pragma unroll
-        for (int q = 0; q < NF * NU; ++q) Ar[q] = 0;
-        for_lw_stencil<D>(srt, cfg, a.nbr, a.ldn, s, k, xi, [&](int j, const double dx[3]) {
-            double x[3];
+    for (int f = 0; f < NF; ++f) {
 #pragma unroll
-            for (int q = 0; q < D; ++q) x[q] = dx[q] * inv_r;
-            double row[NU];
-            second_order_row<D, double>(x, row);
-            T rowf[NU];
+        for (int q = 0; q < 3; ++q) grad[f][q] = q < D ? (double)B[f * NU + q] * inv_r : 0.0;
 #pragma unroll
-            for (int pp = 0; pp < NU; ++pp) rowf[pp] = (T)row[pp];
-            double fj[NF];
-            fj[0] = srt.V[j];
-#pragma unroll
-            for (int q = 0; q < D; ++q) fj[1 + q] = srt.u[q][j];
-            fj[FP] = srt.P[j];
-#pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                double res = fj[f] - st[f];
-#pragma unroll
-                for (int pp = 0; pp < NU; ++pp) res -= row[pp] * (double)B[f * NU + pp];
-                T rf = (T)res;
-#pragma unroll
-                for (int pp = 0; pp < NU; ++pp) Ar[f * NU + pp] += rowf[pp] * rf;
-            }
-        });
-        chol_solve<NU, NF, T, T>(G, inv, Ar);
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-#pragma unroll
-            for (int q = 0; q < 3; ++q)
-                grad[f][q] = q < D ? ((double)B[f * NU + q] + (double)Ar[f * NU + q]) * inv_r : 0.0;
-#pragma unroll
-            for (int q = 0; q < NS; ++q)
-                hess[f][q] = ((double)B[f * NU + D + q] + (double)Ar[f * NU + D + q]) * inv_r * inv_r;
-        }
-    } else {
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-#pragma unroll
-            for (int q = 0; q < 3; ++q) grad[f][q] = q < D ? (double)B[f * NU + q] * inv_r : 0.0;
-#pragma unroll
-            for (int q = 0; q < NS; ++q) hess[f][q] = (double)B[f * NU + D + q] * inv_r * inv_r;
-        }
+        for (int q = 0; q < NS; ++q) hess[f][q] = (double)B[f * NU + D + q] * inv_r * inv_r;
     }
     store_der<D>(a.der, a.ld, t, grad, hess);
 }
@@ -920,6 +960,38 @@ __global__ __launch_bounds__(LP_BLOCK) __attribute__((amdgpu_waves_per_eu(3))) v
     if ((threadIdx.x & 63) == 0 && limited) atomicAdd(&a.sc->n_limited, (unsigned long long)limited);
 }
 
+// The fits queued for refinement (condition estimate above refine_cond):
+// the refinement step from the factor and FP32 solution the fit stored, so
+// that each result is the always-refining launch's.  Grid-stride over the
+// device-side queue length.
+template <int D>
+__global__ __launch_bounds__(LP_BLOCK) void k_lw_refine(SolveArgs a) {
+    constexpr int NU = Dim<D>::NU, NF = Dim<D>::NF, NG = Dim<D>::NG, FP = D + 1;
+    const int n = a.sc->n_refine;
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < n; w += gridDim.x * blockDim.x) {
+        const int s = a.rq[2 * w], t = a.rq[2 * w + 1];
+        const Sorted &srt = a.srt;
+        int k = a.count[s];
+        if (k > a.cfg.max_nb) k = a.cfg.max_nb;
+        const double xi[3] = {srt.x[0][s], srt.x[1][s], D == 3 ? srt.x[2][s] : 0.0};
+        double st[NF];
+        st[0] = srt.V[s];
+#pragma unroll
+        for (int q = 0; q < D; ++q) st[1 + q] = srt.u[q][s];
+        st[FP] = srt.P[s];
+        const double inv_r = 1.0 / (a.cfg.kappa * srt.h[s]);
+        const float *keep = a.rkeep + (int64_t)w * RefineKeep<D>::N;
+        float G[NG], inv[NU], B[NF * NU];
+#pragma unroll
+        for (int q = 0; q < NG; ++q) G[q] = keep[q];
+#pragma unroll
+        for (int q = 0; q < NU; ++q) inv[q] = keep[NG + q];
+#pragma unroll
+        for (int q = 0; q < NF * NU; ++q) B[q] = keep[NG + NU + q];
+        lw_refine_tail<D>(a, s, t, k, xi, st, inv_r, G, inv, B);
+    }
+}
+
 // Grid of a persistent launch: the blocks that can be resident at once.
 // Resident blocks per CU are queried once per (kernel, block size), so that a
 // launch under stream capture makes no runtime query.
@@ -961,11 +1033,17 @@ static void launch_solve_t(const SolveArgs &a, int n_total_cap, int block, void 
         gu = persistent_grid((const void *)k_finish<D, T, MODE>, block, n_total_cap);
     }
     hipLaunchKernelGGL((k_lw_fit<D, T, RF, MODE>), dim3(gf), dim3(block), 0, st, a);
+    if (sizeof(T) == 4 && !RF && a.rq && a.cfg.refine && a.cfg.refine_cond > 0.0f) {
+        unsigned gr = (unsigned)((n_total_cap + LP_BLOCK - 1) / LP_BLOCK);
+        gr = gr < 1 ? 1 : (gr > 1024 ? 1024 : gr);
+        hipLaunchKernelGGL((k_lw_refine<D>), dim3(gr), dim3(LP_BLOCK), 0, st, a);
+    }
     if (between) between(between_arg);
     hipLaunchKernelGGL((k_finish<D, T, MODE>), dim3(gu), dim3(block), 0, st, a);
 }
 
 int der_count(int D) { return D == 3 ? Der<3>::N : Der<2>::N; }
+int refine_keep_count(int D) { return D == 3 ? RefineKeep<3>::N : RefineKeep<2>::N; }
 
 template <int D, typename T, bool RF>
 static void launch_solve_m(const SolveArgs &a, int n_total_cap, int block, int mode, void (*between)(void *),
@@ -979,13 +1057,15 @@ void launch_solve(const SolveArgs &a, int n_total_cap, int block, int mode, void
                   void *between_arg, hipStream_t st) {
     if (a.wq == nullptr) mode = WQ_DIRECT;
     const bool mixed = a.cfg.precision == LP_MIXED;
+    // refine_cond > 0: the FP32 fit queues the fits to refine for k_lw_refine
+    const bool refine_all = a.cfg.refine && !(a.cfg.refine_cond > 0.0f && a.rq);
     if (a.cfg.D == 3) {
         if (!mixed) launch_solve_m<3, double, false>(a, n_total_cap, block, mode, between, between_arg, st);
-        else if (a.cfg.refine) launch_solve_m<3, float, true>(a, n_total_cap, block, mode, between, between_arg, st);
+        else if (refine_all) launch_solve_m<3, float, true>(a, n_total_cap, block, mode, between, between_arg, st);
         else launch_solve_m<3, float, false>(a, n_total_cap, block, mode, between, between_arg, st);
     } else {
         if (!mixed) launch_solve_m<2, double, false>(a, n_total_cap, block, mode, between, between_arg, st);
-        else if (a.cfg.refine) launch_solve_m<2, float, true>(a, n_total_cap, block, mode, between, between_arg, st);
+        else if (refine_all) launch_solve_m<2, float, true>(a, n_total_cap, block, mode, between, between_arg, st);
         else launch_solve_m<2, float, false>(a, n_total_cap, block, mode, between, between_arg, st);
     }
     (void)hipGetLastError();

@@ -46,7 +46,8 @@ class Config(C.Structure):
         ("cond_max", C.c_double), ("uw_cond_max", C.c_double), ("cond_fallback", C.c_double),
         ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
         ("periodic_mask", C.c_uint32), ("wall_lo_mask", C.c_uint32), ("wall_hi_mask", C.c_uint32),
-        ("mlp_band", C.c_float), ("mlp_feat_max", C.c_float), ("reserved", C.c_int32 * 7),
+        ("mlp_band", C.c_float), ("mlp_feat_max", C.c_float), ("refine_cond", C.c_float),
+        ("reserved", C.c_int32 * 6),
     ]
 
 
@@ -68,7 +69,7 @@ class Info(C.Structure):
     _fields_ = [
         ("t", C.c_double), ("dt", C.c_double), ("n_ghost", C.c_int64), ("max_count", C.c_int32),
         ("n_fallback", C.c_int32), ("n_limited", C.c_int64), ("error_bits", C.c_uint32), ("levels", C.c_int32 * 2),
-        ("n_mlp", C.c_int64), ("n_mlp_plain", C.c_int64),
+        ("n_mlp", C.c_int64), ("n_mlp_plain", C.c_int64), ("n_refined", C.c_int64),
     ]
 
 
@@ -140,14 +141,18 @@ def lib():
     return _lib
 
 
-def make_config(cfg: dict, precision: str = "fp64", estimator: str = "plain", refine: bool = True) -> Config:
-    """lp_config from a workload config dict (see workloads.base_config)."""
+def make_config(cfg: dict, precision: str = "fp64", estimator: str = "plain", refine: bool = True,
+                refine_cond: float = 0.0) -> Config:
+    """lp_config from a workload config dict (see workloads.base_config).
+    refine_cond > 0 refines only the mixed fits whose condition estimate
+    exceeds it (0: every fit)."""
     c = Config()
     d = int(cfg["dim"])
     lib().lp_config_default(C.byref(c), d)
     c.precision = {"fp64": FP64, "mixed": MIXED}[precision]
     c.estimator = {"plain": EST_PLAIN, "injected": EST_INJECTED, "mlp": EST_MLP}[estimator]
     c.refine = int(bool(refine))
+    c.refine_cond = float(refine_cond)
     c.max_nb = int(cfg.get("max_nb", 128))
     c.lw_cap = int(cfg.get("lw_cap", 0))
     c.uw_cap = int(cfg.get("uw_cap", 0))
@@ -208,11 +213,11 @@ def state_to_host(st: dict) -> dict:
 class Context:
     """One liblp context (one per stream)."""
 
-    def __init__(self, cfg: dict, precision="fp64", estimator="plain", refine=True):
+    def __init__(self, cfg: dict, precision="fp64", estimator="plain", refine=True, refine_cond=0.0):
         self.cfg = cfg
         self.dim = int(cfg["dim"])
         self.max_nb = int(cfg.get("max_nb", 128))
-        self._c = make_config(cfg, precision, estimator, refine)
+        self._c = make_config(cfg, precision, estimator, refine, refine_cond)
         h = C.c_void_p()
         st = lib().lp_create(C.byref(self._c), C.byref(h))
         if st != OK:
@@ -298,7 +303,8 @@ class Context:
         self._raise(lib().lp_get_info(self._h, _stream_ptr(stream), C.byref(inf)))
         return {"t": inf.t, "dt": inf.dt, "n_ghost": inf.n_ghost, "max_count": inf.max_count,
                 "n_fallback": inf.n_fallback, "n_limited": inf.n_limited, "error_bits": inf.error_bits,
-                "levels": (inf.levels[0], inf.levels[1]), "n_mlp": inf.n_mlp, "n_mlp_plain": inf.n_mlp_plain}
+                "levels": (inf.levels[0], inf.levels[1]), "n_mlp": inf.n_mlp, "n_mlp_plain": inf.n_mlp_plain,
+                "n_refined": inf.n_refined}
 
     def set_time(self, t: float, stream=None):
         self._raise(lib().lp_set_time(self._h, _stream_ptr(stream), float(t)))

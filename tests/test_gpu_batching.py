@@ -76,6 +76,41 @@ def test_search_cap_identical(lp, case):
         _same(_steps(lp, cfg, st, 3, tuning={lp.TUNE_SEARCH_CAP: cap}), ref, "%s search cap %d" % (case, cap))
 
 
+def test_adaptive_refinement_selects_per_particle(lp):
+    """refine_cond > 0: a particle's update depends only on its own fit, so
+    after one step every particle equals, bit for bit, either the step that
+    refines every fit or the step that refines none, and the particles taking
+    the refined result are the ones counted as refined."""
+    cfg, st = CASES["vacuum 60k"]()
+    runs = {}
+    for tag, refine, cond in (("all", True, 0.0), ("none", False, 0.0), ("adaptive", True, 300.0)):
+        ctx = lp.Context(cfg, precision="mixed", refine=refine, refine_cond=cond)
+        dev = lp.state_to_device(st)
+        ctx.step(dev)
+        assert ctx.check() == lp.OK
+        runs[tag] = (lp.state_to_host(dev), ctx.info())
+        ctx.close()
+    n = st["V"].shape[0]
+
+    def same(a, b):
+        eq = np.ones(n, bool)
+        for k in ("x", "V", "u", "P", "phi", "flags"):
+            d = np.asarray(a[k] == b[k]).reshape(n, -1).all(1)
+            eq &= d
+        return eq
+    ad, inf = runs["adaptive"]
+    eq_all, eq_none = same(ad, runs["all"][0]), same(ad, runs["none"][0])
+    assert np.all(eq_all | eq_none), np.nonzero(~(eq_all | eq_none))[0][:5]
+    took_refined = int((eq_all & ~eq_none).sum())
+    say("adaptive refinement: %d fits refined, %d particles differ from the unrefined step"
+        % (inf["n_refined"], took_refined))
+    assert runs["all"][1]["n_refined"] == 0 and runs["none"][1]["n_refined"] == 0
+    assert 0.05 * n < inf["n_refined"] < 0.95 * n
+    # a refined fit leaves the state unchanged where phi = 0 (no LW part) or
+    # where its correction rounds away
+    assert 0.25 * inf["n_refined"] <= took_refined <= inf["n_refined"]
+
+
 @pytest.mark.parametrize("case", list(CASES))
 def test_run_graph_matches_steps(lp, case):
     cfg, st = CASES[case]()

@@ -132,9 +132,10 @@ def test_gfd_quadratic_and_oracle(lp, oracle_lib, dim):
             assert err <= 1e-10, (f, c, err)
 
 
-def _run_both(lp, oracle_lib, cfg, st, nsteps, precision, tol, tag, dt=None, mode=None):
-    say("step", tag, precision, st["V"].shape[0], "particles", nsteps, "steps", "search mode", mode)
-    ctx = lp.Context(cfg, precision=precision)
+def _run_both(lp, oracle_lib, cfg, st, nsteps, precision, tol, tag, dt=None, mode=None, refine_cond=0.0):
+    say("step", tag, precision, st["V"].shape[0], "particles", nsteps, "steps", "search mode", mode,
+        "refine_cond", refine_cond)
+    ctx = lp.Context(cfg, precision=precision, refine_cond=refine_cond)
     if mode is not None:
         ctx.set_tuning(lp.TUNE_SEARCH_MODE, mode)
     dev = lp.state_to_device(st)
@@ -178,6 +179,15 @@ def test_step_sod_slab_fp64(lp, oracle_lib):
 def test_step_sod_slab_mixed(lp, oracle_lib):
     cfg, st = W.sod3d(n=64, ny=8, nz=8)
     _run_both(lp, oracle_lib, cfg, st, 12, "mixed", 1e-4, "sod slab")
+
+
+@pytest.mark.parametrize("refine_cond", [300.0, 1e3])
+def test_step_vacuum_mixed_adaptive_refinement(lp, oracle_lib, refine_cond):
+    """Mixed step refining only the fits whose condition estimate exceeds
+    refine_cond (FP32 solution elsewhere)."""
+    cfg, st = W.vacuum3d(n_particles=120_000, seed=9)
+    got, ref, info, ctx = _run_both(lp, oracle_lib, cfg, st, 2, "mixed", 1e-4, "vacuum 120k", refine_cond=refine_cond)
+    say("refined fits in the last step:", ctx.info()["n_refined"])
 
 
 @pytest.mark.parametrize("mode", SEARCH_MODES)
