@@ -4,11 +4,13 @@ Workload: the 3D expansion into vacuum -- 2,097,152 equal-mass particles
 rejection-sampled from rho = exp(-|x|^2/0.05) (spacing varies 8x), kappa 2.2,
 CFL 0.2, free boundary -- one time step = neighbour search + GFD fits + blended
 update + mover for every particle.  Prints one JSON line: particle-updates/s of
-the mixed-precision step (FP32 fits with one FP64-residual refinement, FP64
-state), the FP64 step next to it, the relative L1 error of both against the
-CPU reference on a sample of particles, the roofline of the dominant kernel
-(timed with HIP events on the library's stream) and the CPU reference's own
-throughput on the host cores.
+the mixed-precision step (FP32 fits, one FP64-residual refinement step for the
+fits whose condition estimate exceeds --refine-cond, FP64 for ill-conditioned
+stencils and the state), the FP64 step, the mixed step refining every fit, the
+FP32 step without refinement and the learned-estimator step next to it, the
+relative L1 error of each against the CPU reference, the roofline of the
+dominant kernel (timed with HIP events on the library's stream) and the CPU
+reference's own throughput on the host cores.
 """
 import argparse
 import json
@@ -84,10 +86,16 @@ def main():
     ap.add_argument("--steps", type=int, default=20, help="timed steps (lp_run: graph-replayed steps)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=2_097_152)
-    ap.add_argument("--precision", choices=["both", "all", "mixed", "fp64", "fp32", "mlp"], default="all",
-                    help="mixed: FP32 fits + one FP64-residual refinement; fp32: mixed without the refinement; "
-                         "mlp: mixed with the learned estimator (trained first, untimed); "
-                         "both: mixed then fp64; all: mixed, fp64, fp32, mlp")
+    ap.add_argument("--precision", choices=["both", "all", "mixed", "mixed_all", "fp64", "fp32", "mlp"],
+                    default="all",
+                    help="mixed: FP32 fits, the FP64-residual refinement step where the condition estimate "
+                         "exceeds --refine-cond; mixed_all: the refinement step for every fit; fp32: no "
+                         "refinement; mlp: mixed with the learned estimator (trained first, untimed); "
+                         "both: mixed then fp64; all: mixed, fp64, mixed_all, fp32, mlp")
+    ap.add_argument("--refine-cond", type=float, default=1e3,
+                    help="condition-estimate threshold of the refinement step (mixed, mlp); the estimate "
+                         "bounds cond(A)^2, so unrefined fits carry a relative error of at most about "
+                         "refine_cond * 2^-24")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sample", type=int, default=0, help="particles in the CPU-reference sample (0: all)")
     ap.add_argument("--search-mode", type=int, default=None, help="override the neighbour-search mode (0/1)")
@@ -129,8 +137,8 @@ def main():
     sample = (np.arange(n) if args.sample <= 0 or args.sample >= n
               else np.sort(rng.choice(n, size=args.sample, replace=False)))
 
-    precisions = {"both": ["mixed", "fp64"], "all": ["mixed", "fp64", "fp32", "mlp"]}.get(args.precision,
-                                                                                        [args.precision])
+    precisions = {"both": ["mixed", "fp64"], "all": ["mixed", "fp64", "mixed_all", "fp32", "mlp"]}.get(
+        args.precision, [args.precision])
     mlp_params = None
     mlp_train = None
     if "mlp" in precisions:
@@ -176,6 +184,7 @@ def main():
 
     for prec in precisions:
         ctx = lp.Context(cfg, precision="fp64" if prec == "fp64" else "mixed", refine=prec != "fp32",
+                         refine_cond=args.refine_cond if prec in ("mixed", "mlp") else 0.0,
                          estimator="mlp" if prec == "mlp" else "plain")
         if prec == "mlp":
             ctx.mlp_set(mlp_params)
@@ -308,11 +317,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if main_prec == "mixed" else "f64",
+        "dtype": "f64" if main_prec == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "vacuum3d: %d equal-mass particles rejection-sampled from rho=exp(-r^2/0.05) "
                                "in the ball rho>=1/512, p=rho^1.4, kappa 2.2, CFL 0.2, free boundary" % n,
-                   "n_particles": n, "precision": main_prec, "mean_lw_stencil": float(k_lw.mean())},
+                   "n_particles": n, "precision": main_prec, "mean_lw_stencil": float(k_lw.mean()),
+                   "refine_cond": args.refine_cond if main_prec in ("mixed", "mlp") else None,
+                   "refined_fits_per_step": res["info"].get("n_refined")},
         "roofline": top,
         "kernels": kr,
         "cpu_baseline": cpu,
