@@ -30,7 +30,7 @@ struct lp_ctx {
     int device = 0;
     std::string err;
     // workspace
-    Buf h, r, gcnt, scan_tmp, ghosts, key, slot, tables, sorted, sortedf, sid, nbr, count, queue, partials, consout,
+    Buf h, r, gcnt, scan_tmp, ghosts, key, slot, tables, sorted, srec, sid, nbr, count, queue, partials, consout,
         gfd_fields, hitd2, hitj, tflags, tlo, thi, prep_part, ovfq, der, lwst, wq, rq, rkeep,
         mfeat, mrates, mphi, mflag,                          // network-estimator staging
         theta, adam_m, adam_v, mgrad, mpart, mlosspart, mscal; // network parameters and training
@@ -273,7 +273,7 @@ extern "C" lp_status lp_destroy(lp_ctx *c) {
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     Buf *bufs[] = {&c->h, &c->r, &c->gcnt, &c->scan_tmp, &c->ghosts, &c->key, &c->slot, &c->tables, &c->sorted,
-                   &c->sortedf, &c->sid, &c->nbr, &c->count, &c->queue, &c->partials, &c->consout, &c->gfd_fields,
+                   &c->srec, &c->sid, &c->nbr, &c->count, &c->queue, &c->partials, &c->consout, &c->gfd_fields,
                    &c->hitd2, &c->hitj, &c->tflags, &c->tlo, &c->thi, &c->prep_part, &c->ovfq, &c->der, &c->lwst,
                    &c->wq, &c->rq, &c->rkeep, &c->mfeat, &c->mrates, &c->mphi, &c->mflag, &c->theta, &c->adam_m, &c->adam_v,
                    &c->mgrad, &c->mpart, &c->mlosspart, &c->mscal};
@@ -417,7 +417,7 @@ static lp_status ensure_capacity(lp_ctx *c, int64_t n_real, int64_t n_total, boo
     ENSURE(c, c->slot, sizeof(uint32_t) * nt);
     ENSURE(c, c->tables, sizeof(uint32_t) * table_words(c));
     ENSURE(c, c->sorted, sizeof(double) * (state ? 10 : 4) * nt);
-    if (mixed) ENSURE(c, c->sortedf, sizeof(float) * 5 * nt);
+    if (state) ENSURE(c, c->srec, sizeof(double) * LP_REC * nt);
     ENSURE(c, c->sid, sizeof(int) * nt);
     ENSURE(c, c->nbr, sizeof(int) * (size_t)c->dc.max_nb * nt);
     ENSURE(c, c->count, sizeof(int) * nt);
@@ -476,10 +476,7 @@ static Sorted sorted_view(lp_ctx *c, bool state) {
     if (state) {
         s.V = b + 4 * n; s.u[0] = b + 5 * n; s.u[1] = b + 6 * n; s.u[2] = b + 7 * n; s.P = b + 8 * n; s.h = b + 9 * n;
     }
-    if (c->sortedf.p && c->sortedf.bytes >= sizeof(float) * 5 * n) {
-        float *f = (float *)c->sortedf.p;
-        s.Vf = f; s.uf[0] = f + n; s.uf[1] = f + 2 * n; s.uf[2] = f + 3 * n; s.Pf = f + 4 * n;
-    }
+    if (state && c->srec.p && c->srec.bytes >= sizeof(double) * LP_REC * n) s.rec = (double *)c->srec.p;
     s.id = (int *)c->sid.p;
     return s;
 }
@@ -620,25 +617,15 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
     sa.nd = 10;
     for (int q = 0; q < 10; ++q) { sa.src[q] = src[q]; sa.gsrc[q] = gsrc[q]; sa.dst[q] = dst[q]; }
     if (D == 2) { sa.src[2] = soa.x[0]; sa.src[7] = soa.u[0]; }
-    if (mixed) {
-        sa.nff = 4;  // V, u0, u1, P (u2 below in 3D)
-        sa.fsrc[0] = 4; sa.dstf[0] = srt.Vf;
-        sa.fsrc[1] = 5; sa.dstf[1] = srt.uf[0];
-        sa.fsrc[2] = 6; sa.dstf[2] = srt.uf[1];
-        sa.fsrc[3] = 8; sa.dstf[3] = srt.Pf;
+    // gather records: x_0..x_{D-1}, V, u_0..u_{D-1}, P (value indices above)
+    sa.rec = srt.rec;
+    {
+        const int r3[LP_REC] = {0, 1, 2, 4, 5, 6, 7, 8}, r2[LP_REC] = {0, 1, 4, 5, 6, 8, -1, -1};
+        for (int q = 0; q < LP_REC; ++q) sa.rec_src[q] = D == 3 ? r3[q] : r2[q];
     }
     const uint32_t *start = (const uint32_t *)c->tables.p + c->grid.off[c->grid.L_hi];
     launch_scatter(sa, n, &c->sc->n_total, (int)n_total, (const uint32_t *)c->key.p, (const uint32_t *)c->slot.p, start,
                    srt.id, st);
-    if (mixed && D == 3) {
-        ScatterArgs sb;
-        memset(&sb, 0, sizeof sb);
-        sb.nd = 1;
-        sb.src[0] = soa.u[2]; sb.gsrc[0] = gh.u[2]; sb.dst[0] = srt.u[2];
-        sb.nff = 1; sb.fsrc[0] = 0; sb.dstf[0] = srt.uf[2];
-        launch_scatter(sb, n, &c->sc->n_total, (int)n_total, (const uint32_t *)c->key.p, (const uint32_t *)c->slot.p,
-                       start, srt.id, st);
-    }
     launch_coarsen((uint32_t *)c->tables.p, c->grid, D, &c->sc->n_total, st);
     stage_mark(c, st, 1, false);
     int ldn = list_ldn(c);

@@ -455,7 +455,19 @@ __global__ void k_scatter(ScatterArgs a, int n_real, const int *n_total_dev, con
         vals[d] = v;
         a.dst[d][pos] = v;
     }
-    for (int f = 0; f < a.nff; ++f) a.dstf[f][pos] = (float)vals[a.fsrc[f]];
+    if (a.rec) {
+        // the particle's gather record: one 64-byte write
+        double e[LP_REC];
+#pragma unroll
+        for (int q = 0; q < LP_REC; ++q) {
+            e[q] = 0.0;
+            for (int d = 0; d < 12; ++d)
+                if (d == a.rec_src[q]) e[q] = vals[d];
+        }
+        double2 *r = reinterpret_cast<double2 *>(a.rec + (int64_t)LP_REC * pos);
+#pragma unroll
+        for (int q = 0; q < LP_REC / 2; ++q) r[q] = make_double2(e[2 * q], e[2 * q + 1]);
+    }
 }
 
 void launch_scatter(const ScatterArgs &a, int n_real, const int *n_total_dev, int n_total_cap, const uint32_t *key,

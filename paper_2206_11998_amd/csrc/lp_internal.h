@@ -80,9 +80,44 @@ struct Ghosts {
 // Sorted (cell-ordered) copies of real + ghost particles.
 struct Sorted {
     double *x[3], *V, *u[3], *P, *h, *r;
-    float *Vf, *uf[3], *Pf;
+    double *rec;                    // packed gather records (LP_REC doubles each), or NULL
     int *id;                        // original id (ghosts: n + g)
 };
+
+// Packed gather record of a cell-order particle, LP_REC doubles (64 B, one
+// half cache line): x_0 .. x_{D-1}, V, u_0 .. u_{D-1}, P (2D: two unused).
+// The fits gather a neighbour's position and fields from it in four 16-byte
+// loads of one line, instead of eight loads from eight arrays.
+#define LP_REC 8
+
+template <int D>
+__device__ __forceinline__ void rec_pos(const double *rec, int j, double p[3]) {
+    const double2 *r = reinterpret_cast<const double2 *>(rec + (int64_t)LP_REC * j);
+    const double2 a = r[0];
+    p[0] = a.x;
+    p[1] = a.y;
+    p[2] = D == 3 ? r[1].x : 0.0;
+}
+
+// V, u_0 .. u_{D-1}, P of cell-order particle j (from its record when there is one)
+template <int D>
+__device__ __forceinline__ void gather_fields(const Sorted &srt, int j, double f[D + 2]) {
+    if (srt.rec) {
+        const double2 *r = reinterpret_cast<const double2 *>(srt.rec + (int64_t)LP_REC * j);
+        if constexpr (D == 3) {
+            const double2 b = r[1], c = r[2], d = r[3];
+            f[0] = b.y; f[1] = c.x; f[2] = c.y; f[3] = d.x; f[4] = d.y;
+        } else {
+            const double2 b = r[1], c = r[2];
+            f[0] = b.x; f[1] = b.y; f[2] = c.x; f[3] = c.y;
+        }
+    } else {
+        f[0] = srt.V[j];
+#pragma unroll
+        for (int q = 0; q < D; ++q) f[1 + q] = srt.u[q][j];
+        f[D + 1] = srt.P[j];
+    }
+}
 
 // Generic gather of up to 12 double arrays into cell order.
 struct ScatterArgs {
@@ -90,9 +125,8 @@ struct ScatterArgs {
     const double *src[12];          // caller order (ids < n_real)
     const double *gsrc[12];         // ghosts (ids >= n_real); may be NULL
     double *dst[12];
-    int nff;
-    int fsrc[4];                    // which dst arrays get an FP32 copy
-    float *dstf[4];
+    double *rec;                    // packed gather records (LP_REC doubles), or NULL
+    int rec_src[LP_REC];            // value index of each record entry (-1: zero)
 };
 
 // ---------------------------------------------------------------------------

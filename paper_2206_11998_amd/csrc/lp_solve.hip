@@ -57,7 +57,13 @@ __device__ __forceinline__ void second_order_row(const T xi[3], T row[Dim<D>::NU
 template <int D>
 __device__ __forceinline__ void displacement(const Sorted &srt, const DevCfg &cfg, int j, const double xi[3],
                                              double dx[3]) {
-    disp_to<D>(cfg, srt.x, j, xi, dx);
+    if (srt.rec) {
+        double p[3];
+        rec_pos<D>(srt.rec, j, p);
+        disp_of<D>(cfg, p, xi, dx);
+    } else {
+        disp_to<D>(cfg, srt.x, j, xi, dx);
+    }
 }
 
 template <int D>
@@ -510,7 +516,6 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
                                                 const DS &ds, int lw_status, uint8_t flags,
                                                 const MlpStage *ms = nullptr) {
     constexpr int NF = Dim<D>::NF, FP = D + 1, NGD = D * (D + 1) / 2;
-    const bool use_f = sizeof(T) == 4;
     // V and P over the particle and its half-ball members (network inputs)
     T vmin = (T)st[0], vmax = (T)st[0], pmin = (T)st[FP], pmax = (T)st[FP];
     const int ucap = cfg.uw_cap;
@@ -541,9 +546,9 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
             T x[3];
 #pragma unroll
             for (int b = 0; b < D; ++b) x[b] = (T)(dx[b] * inv_r);
-            T fj[3];
-            if (use_f) { fj[0] = (T)srt.Vf[j]; fj[1] = (T)srt.uf[a][j]; fj[2] = (T)srt.Pf[j]; }
-            else { fj[0] = (T)srt.V[j]; fj[1] = (T)srt.u[a][j]; fj[2] = (T)srt.P[j]; }
+            double fr[NF];
+            gather_fields<D>(srt, j, fr);
+            const T fj[3] = {(T)fr[0], (T)fr[1 + a], (T)fr[FP]};
             T bq[3] = {fj[0] - fi[0], fj[1] - fi[1], fj[2] - fi[2]};
             vmin = fj[0] < vmin ? fj[0] : vmin;
             vmax = fj[0] > vmax ? fj[0] : vmax;
@@ -758,10 +763,7 @@ __device__ __forceinline__ void lw_refine_tail(const SolveArgs &a, int s, int t,
 #pragma unroll
         for (int pp = 0; pp < NU; ++pp) rowf[pp] = (T)row[pp];
         double fj[NF];
-        fj[0] = srt.V[j];
-#pragma unroll
-        for (int q = 0; q < D; ++q) fj[1 + q] = srt.u[q][j];
-        fj[FP] = srt.P[j];
+        gather_fields<D>(srt, j, fj);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             double res = fj[f] - st[f];
@@ -808,15 +810,8 @@ __device__ __forceinline__ void lw_fit_one(const SolveArgs &a, int s, int t) {
     const double r = cfg.kappa * h;
     const double inv_r = 1.0 / r;
     T fi[NF];
-    if (use_f) {
-        fi[0] = (T)srt.Vf[s];
 #pragma unroll
-        for (int q = 0; q < D; ++q) fi[1 + q] = (T)srt.uf[q][s];
-        fi[FP] = (T)srt.Pf[s];
-    } else {
-#pragma unroll
-        for (int f = 0; f < NF; ++f) fi[f] = (T)st[f];
-    }
+    for (int f = 0; f < NF; ++f) fi[f] = (T)st[f];
     // normal equations of the scaled second-order system over the LW stencil:
     // moments of the offsets (the normal matrix) and A^T b
     T M[Mom<D>::N], B[NF * NU];
@@ -832,18 +827,11 @@ __device__ __forceinline__ void lw_fit_one(const SolveArgs &a, int s, int t) {
         add_moments<D, T>(x, M);
         T row[NU];
         second_order_row<D, T>(x, row);
+        double fr[NF];
+        gather_fields<D>(srt, j, fr);
         T fj[NF];
-        if (use_f) {
-            fj[0] = (T)srt.Vf[j];
 #pragma unroll
-            for (int q = 0; q < D; ++q) fj[1 + q] = (T)srt.uf[q][j];
-            fj[FP] = (T)srt.Pf[j];
-        } else {
-            fj[0] = (T)srt.V[j];
-#pragma unroll
-            for (int q = 0; q < D; ++q) fj[1 + q] = (T)srt.u[q][j];
-            fj[FP] = (T)srt.P[j];
-        }
+        for (int f = 0; f < NF; ++f) fj[f] = (T)fr[f];
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             T b = fj[f] - fi[f];
