@@ -170,9 +170,12 @@ lp_status lp_step(struct lp_ctx *ctx, void *stream, const lp_particles *p, doubl
  * capture) when the particles outgrow the grid or the ghost capacity; a
  * replayed step that finds more mirror ghosts than the workspace holds is
  * skipped whole and redone after re-planning.  Results are identical to
- * nsteps calls of lp_step.  The graph is kept for the next call with the same
- * particle arrays.  The caller must not free or move the arrays while the
- * call runs. */
+ * nsteps calls of lp_step.  The run stops after the first step that reports
+ * a capacity or numeric error (steps replayed after it are skipped whole and
+ * change nothing); lp_check then reports the error, and an error still
+ * pending from earlier steps stops the run before its first step.  The graph
+ * is kept for the next call with the same particle arrays.  The caller must
+ * not free or move the arrays while the call runs. */
 lp_status lp_run(struct lp_ctx *ctx, void *stream, const lp_particles *p, int32_t nsteps, double t_end);
 
 /* Totals in FP64: out[0] = sum m, out[1..3] = sum m u, out[4] = sum m (e + |u|^2/2),

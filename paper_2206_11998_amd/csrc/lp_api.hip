@@ -598,7 +598,7 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
     }
     // ghosts admitted: what both the ghost arrays and the cell-order arrays hold
     const int64_t gcap = c->nwalls ? std::min<int64_t>(c->cap_ghost, c->cap_total - n) : 0;
-    launch_gate(c->sc, n, gcap, st);
+    launch_gate(c->sc, n, gcap, clip_t_end, st);  // lp_run's steps stop at a reported error
     Ghosts gh = ghost_view(c);
     stage_mark(c, st, 1, true);
     if (c->nwalls)
@@ -771,6 +771,8 @@ extern "C" lp_status lp_run(lp_ctx *c, void *stream, const lp_particles *p, int3
         stage_mark(c, st, LP_STAGE_STEP, false);
         if (s != LP_OK) return s;
         if (c->run_done) break;
+        if ((s = read_scalars(c, st)) != LP_OK) return s;
+        if (c->sc_host->error_bits) break;  // reported by lp_check; later steps would be skipped
         ++steps;
         if (steps >= nsteps) break;
         if ((s = graph_prepare(c, p)) != LP_OK) return s;
@@ -788,6 +790,10 @@ extern "C" lp_status lp_run(lp_ctx *c, void *stream, const lp_particles *p, int3
             steps += (int64_t)(c->sc_host->steps - before);
             if (c->sc_host->done || (t_end > 0.0 && c->sc_host->t >= t_end)) {
                 c->run_done = true;
+                break;
+            }
+            if (c->sc_host->error_bits) {
+                c->run_done = true;  // the steps after the failing one were skipped
                 break;
             }
             if (steps >= nsteps || c->sc_host->halt || grid_outdated(c)) break;

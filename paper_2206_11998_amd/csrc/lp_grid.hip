@@ -46,12 +46,13 @@ void launch_reset_scalars(DevScalars *sc, double dt_in, int n_real, int clear_ha
 }
 
 // Admission of the particle work of a step.  n_total = real + ghost particles,
-// or 0 with dt = 0 when the step is skipped: t_end reached, or more ghosts
-// than the workspace was sized for (then halt stays raised until the host
-// re-plans the workspace; every later kernel of the step sees n_total = 0).
-__global__ void k_gate(DevScalars *sc, int n_real, long long cap_ghost) {
+// or 0 with dt = 0 when the step is skipped: t_end reached, more ghosts than
+// the workspace was sized for (then halt stays raised until the host re-plans
+// the workspace; every later kernel of the step sees n_total = 0), or, with
+// stop_on_error, an error reported by an earlier step and not yet collected.
+__global__ void k_gate(DevScalars *sc, int n_real, long long cap_ghost, int stop_on_error) {
     if (sc->n_ghost > cap_ghost) sc->halt = 1u;
-    if (sc->done || sc->halt) {
+    if (sc->done || sc->halt || (stop_on_error && sc->error_bits)) {
         sc->n_total = 0;
         sc->dt = 0.0;
     } else {
@@ -59,8 +60,8 @@ __global__ void k_gate(DevScalars *sc, int n_real, long long cap_ghost) {
     }
 }
 
-void launch_gate(DevScalars *sc, int n_real, int64_t cap_ghost, hipStream_t st) {
-    hipLaunchKernelGGL(k_gate, dim3(1), dim3(1), 0, st, sc, n_real, (long long)cap_ghost);
+void launch_gate(DevScalars *sc, int n_real, int64_t cap_ghost, int stop_on_error, hipStream_t st) {
+    hipLaunchKernelGGL(k_gate, dim3(1), dim3(1), 0, st, sc, n_real, (long long)cap_ghost, stop_on_error);
     CHECK_LAUNCH();
 }
 

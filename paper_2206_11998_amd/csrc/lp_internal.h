@@ -133,7 +133,7 @@ struct ScatterArgs {
 // Host launchers (defined in the .hip files).
 // ---------------------------------------------------------------------------
 void launch_reset_scalars(DevScalars *sc, double dt_in, int n_real, int clear_halt, hipStream_t st);
-void launch_gate(DevScalars *sc, int n_real, int64_t cap_ghost, hipStream_t st);
+void launch_gate(DevScalars *sc, int n_real, int64_t cap_ghost, int stop_on_error, hipStream_t st);
 void launch_rminmax(const double *r, const double *const x[3], int D, int n, DevScalars *sc, hipStream_t st);
 void launch_advance_time(DevScalars *sc, hipStream_t st);
 void launch_prep(const Soa &p, const DevCfg &cfg, DevScalars *sc, double *h, double *r, double *part,

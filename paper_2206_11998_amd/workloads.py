@@ -19,6 +19,10 @@ Workloads (γ = 1.4 everywhere):
 * ``sedov3d``   -- 3D Sedov-type blast: jittered 2:1:1 lattice on
   [0,2]x[0,1]², ρ = 1, p = 1e-5, energy 1 deposited as internal energy in the
   27 lattice particles around the centre, periodic, κ = 2.1.
+* ``yee_vortex`` -- 2D Yee vortex (Sec. 3): an isentropic vortex of strength
+  β = 5 in the free stream (u, v, ρ, p) = (1, 0, 1, 1), on an almost hexagonal
+  lattice of the periodic square [-5, 5]², κ = 2.5; ``yee_exact`` is its
+  exact solution, the initial state convected with the free stream.
 * ``shear3d``   -- 3D shear layer: jittered n³ lattice of [0,1]³, periodic in
   x, z, mirror walls at y = 0, 1, u_x = 0.5 tanh((y-½)/0.025),
   u_y = 0.01 sin(2πx) exp(-((y-½)/0.05)²), ρ = 1.5 + 0.5 tanh((y-½)/0.025),
@@ -228,3 +232,48 @@ WORKLOADS = {
     "sedov3d": sedov3d,
     "shear3d": shear3d,
 }
+
+
+def yee_exact(x, t, beta=5.0, half=5.0, center=(0.0, 0.0)):
+    """Yee vortex at time t: the initial vortex convected by the free stream
+    (1, 0), its centre wrapped into the periodic square [-half, half]^2 and
+    offsets taken to the nearest image (the vortex is below e^-12 of its
+    amplitude at distance 5).  Returns (rho, u (N x 2), p).
+
+    T = 1 - (gamma-1) beta^2 / (8 gamma pi^2) exp(1 - r^2), rho = T^(1/(gamma-1)),
+    (u, v) = (1, 0) + beta/(2 pi) exp((1 - r^2)/2) (-(y - y0), x - x0), p = rho^gamma."""
+    L = 2.0 * half
+    xc = np.array([center[0] + t, center[1]])
+    xc = (xc + half) % L - half
+    d = x[:, :2] - xc
+    d -= L * np.round(d / L)
+    r2 = (d * d).sum(axis=1)
+    T = 1.0 - (GAMMA - 1.0) * beta ** 2 / (8.0 * GAMMA * math.pi ** 2) * np.exp(1.0 - r2)
+    rho = T ** (1.0 / (GAMMA - 1.0))
+    a = beta / (2.0 * math.pi) * np.exp(0.5 * (1.0 - r2))
+    u = np.stack([1.0 - a * d[:, 1], a * d[:, 0]], axis=1)
+    return rho, u, rho ** GAMMA
+
+
+def yee_vortex(dx, beta=5.0, half=5.0, jitter=0.0, seed=7):
+    """2D Yee vortex on an almost hexagonal lattice of the periodic square
+    [-half, half]^2: nx = L/dx columns, an even number of rows spaced as close
+    to dx sqrt(3)/2 as the box allows, alternate rows shifted by dx/2 (the
+    rows of a periodic square cannot be exactly sqrt(3)/2 apart); optional
+    uniform jitter of +-jitter*dx.  Masses m = rho dx dy."""
+    L = 2.0 * half
+    nx = max(2, int(round(L / dx)))
+    ddx = L / nx
+    ny = max(2, int(round(L / (ddx * math.sqrt(3.0) / 2.0))))
+    ny += ny % 2
+    ddy = L / ny
+    j, i = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    x = np.stack([-half + (i + 0.5 + 0.5 * (j % 2)) * ddx, -half + (j + 0.5) * ddy], axis=-1).reshape(-1, 2)
+    if jitter > 0.0:
+        rng = np.random.default_rng(seed)
+        x += rng.uniform(-jitter, jitter, size=x.shape) * np.array([ddx, ddy])
+    x = (x + half) % L - half
+    rho, u, p = yee_exact(x, 0.0, beta, half)
+    m = rho * ddx * ddy
+    cfg = base_config("yee2d", 2, 2.5, [-half, -half], [half, half], [True, True], beta=beta)
+    return cfg, _state(x, rho, u, p, m)

@@ -135,6 +135,32 @@ def test_run_graph_matches_steps(lp, case):
         ctx.close()
 
 
+def test_run_stops_at_first_error(lp):
+    """The coarse 60k-particle vacuum cloud outgrows max_nb = 256 after a few
+    steps: lp_run stops at the step that overflows, with the time and state
+    that lp_step reaches there, and lp_check reports the capacity error."""
+    cfg, st = CASES["vacuum 60k"]()
+    ctx = lp.Context(cfg)
+    dev = lp.state_to_device(st)
+    for k in range(1, 40):
+        ctx.step(dev)
+        if ctx.check() != lp.OK:
+            break
+    else:
+        pytest.skip("no capacity error within 40 steps")
+    t_fail = ctx.info()["t"]
+    ref = lp.state_to_host(dev)
+    ctx.close()
+    say("first failing step", k, "t", t_fail)
+    ctx = lp.Context(cfg)
+    dev = lp.state_to_device(st)
+    ctx.run(dev, k + 20)
+    assert ctx.check() == lp.E_CAPACITY
+    assert ctx.info()["t"] == t_fail
+    _same(lp.state_to_host(dev), ref, "lp_run stopped at the failing step")
+    ctx.close()
+
+
 def test_run_stops_on_t_end(lp):
     cfg, st = CASES["sod slab"]()
     ctx = lp.Context(cfg)
