@@ -41,7 +41,7 @@ class Cfg(C.Structure):
         ("est_eps", C.c_double), ("cond_max", C.c_double), ("uw_cond_max", C.c_double),
         ("lo", C.c_double * 3), ("hi", C.c_double * 3),
         ("periodic", C.c_int32 * 3), ("wall_lo", C.c_int32 * 3), ("wall_hi", C.c_int32 * 3),
-        ("vacuum", C.c_int32),
+        ("vacuum", C.c_int32), ("phi_fixed", C.c_double),
     ]
 
 
@@ -136,6 +136,8 @@ def make_cfg(cfg: dict) -> Cfg:
         c.wall_lo[a] = int(bool(wl[a])) if a < d else 0
         c.wall_hi[a] = int(bool(wh[a])) if a < d else 0
     c.vacuum = int(bool(cfg.get("vacuum", False)))
+    # blend with a fixed phi (1: pure Lax-Wendroff, 0: pure upwind); None: the estimator
+    c.phi_fixed = -1.0 if cfg.get("phi_fixed") is None else float(cfg["phi_fixed"])
     return c
 
 

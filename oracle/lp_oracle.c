@@ -630,6 +630,8 @@ static void solve_particle(const lpo_cfg *c, int64_t i, const int32_t *list, int
     double ph = lpo_limiter(r);
     res->phi = ph < 1.0 ? ph : 1.0;
     if (res->lw_degenerate || res->vacuum_used) res->phi = 0.0;
+    /* a fixed phi isolates one side of the blend (Sec. 2.1) */
+    if (c->phi_fixed >= 0.0) res->phi = c->phi_fixed;
     free(dxs); free(fj); free(fj3); free(sel);
 }
 

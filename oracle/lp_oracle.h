@@ -34,6 +34,8 @@ typedef struct {
     int32_t periodic[3];
     int32_t wall_lo[3], wall_hi[3];
     int32_t vacuum;       /* free boundary: vacuum ghosts complete half-balls */
+    double phi_fixed;     /* >= 0: every particle blends with this phi (1: pure Lax-Wendroff,
+                             0: pure upwind) instead of the estimator's; < 0: the estimator */
 } lpo_cfg;
 
 int lpo_num_threads(void);

@@ -1,0 +1,74 @@
+"""Yee vortex on the GPU (Sec. 3): FP64 parity with the oracle and the
+convergence of the Lax-Wendroff part of the update against the exact
+solution."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2206_11998_amd import workloads as W
+from tests.gpu_util import compare_states, say
+from tests.test_oracle_yee import yee_errors
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2206_11998_amd import lp as _lp
+    _lp.lib()
+    return _lp
+
+
+def _gpu_stepper(lp, phi_fixed):
+    """One-step function over host states, through the library (the injected
+    estimator holds phi fixed)."""
+    def step(cfg, st, d):
+        ctx = lp.Context(cfg, estimator="plain" if phi_fixed is None else "injected")
+        dev = lp.state_to_device(st)
+        if phi_fixed is not None:
+            dev["phi"].fill_(phi_fixed)
+        ctx.step(dev, d)
+        assert ctx.check() == lp.OK
+        out = lp.state_to_host(dev)
+        ctx.close()
+        return {k: out[k] for k in ("x", "u", "V", "P", "m")}
+    return step
+
+
+@pytest.mark.parametrize("phi_fixed", [None, 1.0])
+def test_yee_parity_with_oracle(lp, oracle_lib, phi_fixed):
+    """dx = 0.4 (750 particles): 20 steps of the blended step, and with phi
+    held at 1 the whole run to t = 8, step for step with the oracle."""
+    cfg, st = W.yee_vortex(0.4)
+    cfg = dict(cfg, phi_fixed=phi_fixed)
+    ctx = lp.Context(cfg, estimator="plain" if phi_fixed is None else "injected")
+    dev = lp.state_to_device(st)
+    ref, t, k = st, 0.0, 0
+    T = 8.0 if phi_fixed is not None else 1e9
+    while t < T - 1e-12 and k < (1000 if phi_fixed is not None else 20):
+        d = min(oracle_lib.timestep(cfg, ref), T - t)
+        if phi_fixed is not None:
+            dev["phi"].fill_(phi_fixed)
+        ctx.step(dev, d)
+        assert ctx.check() == lp.OK
+        ref, info = oracle_lib.step(cfg, ref, d)
+        assert info["status"] == 0
+        t += d
+        k += 1
+    say("Yee dx 0.4, phi %s: %d steps to t = %.3f" % (phi_fixed, k, t))
+    compare_states(lp.state_to_host(dev), ref, cfg, 1e-10, "yee phi=%s" % phi_fixed)
+
+
+def test_yee_lax_wendroff_second_order_on_gpu(lp):
+    step = _gpu_stepper(lp, 1.0)
+    from oracle import timestep
+    e4 = yee_errors(step, timestep, 0.4, phi_fixed=1.0)
+    e2 = yee_errors(step, timestep, 0.2, phi_fixed=1.0)
+    order_p, order_u = math.log2(e4[0] / e2[0]), math.log2(e4[2] / e2[2])
+    say("GPU Yee vortex, phi = 1: P L2 %.5f -> %.5f (order %.2f), u L2 %.5f -> %.5f (order %.2f)"
+        % (e4[0], e2[0], order_p, e4[2], e2[2], order_u))
+    assert order_p > 1.8 and order_u > 1.8

@@ -1,0 +1,71 @@
+"""The Yee vortex (Sec. 3): an isentropic vortex carried by the free stream
+(1, 0), an exact smooth solution of the Euler equations.
+
+- The exact solution is pinned by its radial momentum balance
+  dP/dr = rho v_theta^2 / r, which holds only with the exponent (1 - r^2)/2
+  in the velocity.
+- The Lax-Wendroff part of the blended update (phi held at 1) converges at
+  second order in pressure and velocity from dx = 0.4 to 0.2 at t = 8. The
+  paper's errors at the same resolutions are context, not a target; they are
+  printed."""
+import math
+
+import numpy as np
+
+from paper_2206_11998_amd import workloads as W
+
+# the paper's L2 errors at t = 8 (Tables 1-2), dx = 0.4 and 0.2
+PAPER_L2 = {"P": (0.02508, 0.00549), "u": (0.067, 0.01789)}
+
+
+def test_exact_solution_radial_balance():
+    beta, g = 5.0, W.GAMMA
+    r = np.linspace(0.2, 4.0, 60)
+    e = 1e-5
+    x = np.stack([np.concatenate([r, r + e, r - e]), np.zeros(3 * r.size)], axis=1)
+    rho, u, p = W.yee_exact(x, 0.0, beta)
+    n = r.size
+    dpdr = (p[n:2 * n] - p[2 * n:]) / (2 * e)
+    vt = u[:n, 1]  # on the positive x axis the swirl is along +y
+    assert np.allclose(vt, beta / (2 * math.pi) * np.exp(0.5 * (1 - r * r)) * r, rtol=1e-14)
+    assert np.allclose(dpdr, rho[:n] * vt * vt / r, rtol=1e-6)
+    # the free stream far away
+    far = W.yee_exact(np.array([[4.9, 4.9]]), 0.0, beta)
+    assert abs(far[0][0] - 1.0) < 1e-8 and abs(far[2][0] - 1.0) < 1e-8
+
+
+def test_generator_is_the_exact_solution_at_t0():
+    cfg, st = W.yee_vortex(0.4)
+    rho, u, p = W.yee_exact(st["x"], 0.0)
+    assert np.allclose(st["V"], 1.0 / rho, rtol=1e-15)
+    assert np.allclose(st["u"], u, rtol=0, atol=1e-15) and np.allclose(st["P"], p, rtol=1e-15)
+    assert cfg["periodic"] == [True, True]
+
+
+def yee_errors(step, timestep, dx, phi_fixed=None, T=8.0):
+    """Run the Yee vortex to T with the given one-step function; L2 (RMS) and
+    L-infinity errors of P and |u| against the exact solution."""
+    cfg, st = W.yee_vortex(dx)
+    cfg = dict(cfg, phi_fixed=phi_fixed)
+    t = 0.0
+    while t < T - 1e-12:
+        d = min(timestep(cfg, st), T - t)
+        st = step(cfg, st, d)
+        t += d
+    rho, u, p = W.yee_exact(st["x"], T)
+    ep = st["P"] - p
+    eu = np.sqrt(((st["u"] - u) ** 2).sum(axis=1))
+    return np.sqrt((ep ** 2).mean()), np.abs(ep).max(), np.sqrt((eu ** 2).mean()), eu.max()
+
+
+def test_lax_wendroff_part_converges_at_second_order(oracle_lib):
+    def step(cfg, st, d):
+        new, info = oracle_lib.step(cfg, st, d)
+        assert info["status"] == 0
+        return new
+    e4 = yee_errors(step, oracle_lib.timestep, 0.4, phi_fixed=1.0)
+    e2 = yee_errors(step, oracle_lib.timestep, 0.2, phi_fixed=1.0)
+    order_p, order_u = math.log2(e4[0] / e2[0]), math.log2(e4[2] / e2[2])
+    print("Yee vortex, phi = 1: P L2 %.5f -> %.5f (order %.2f), u L2 %.5f -> %.5f (order %.2f); "
+          "paper P %s, u %s" % (e4[0], e2[0], order_p, e4[2], e2[2], order_u, PAPER_L2["P"], PAPER_L2["u"]))
+    assert order_p > 1.8 and order_u > 1.8
