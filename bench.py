@@ -45,6 +45,14 @@ def update_flops(dim=3):
     return (2800.0 if dim == 3 else 1200.0) + 300.0
 
 
+def cells_bytes(n):
+    """Algorithmic HBM bytes of the prep and cell stages per particle: read
+    x, V, m (40 B), write h, r (16 B); Morton key and slot (8 B written, 8 B
+    read back); the cell-order scatter reads 10 FP64 values and writes them
+    with the 64-byte gather record (80 + 80 + 64 B)."""
+    return float(n) * (40 + 16 + 16 + 80 + 80 + 64)
+
+
 def search_bytes(count):
     """Algorithmic HBM bytes of the neighbour search: read position, radius and
     id of every particle once (36 B), write its list and count (4k + 4 B)."""
@@ -242,7 +250,7 @@ def main():
     count = count.cpu().numpy()
     k_lw = np.minimum(count, 54)
     work = {"search": float(search_bytes(count).sum()), "fit": float(fit_flops(k_lw).sum()),
-            "update": float(update_flops() * n), "mlp": float(MLP_FLOPS * n)}
+            "update": float(update_flops() * n), "mlp": float(MLP_FLOPS * n), "cells": cells_bytes(n)}
     ctx.close()
     del d
 
@@ -302,6 +310,20 @@ def main():
                          "avg_launch_ms": avg}
         return out
 
+    def step_roofline(prof, ms_step):
+        """The whole step against its roofline: each stage's algorithmic
+        minimum time (bytes / HBM peak or flops / ALU or MFMA peak), summed,
+        over the measured time per step."""
+        terms = {"prep+cells": work["cells"] / (PEAK_HBM_GBS * 1e9) * 1e3,
+                 "search": work["search"] / (PEAK_HBM_GBS * 1e9) * 1e3,
+                 "fit": work["fit"] / (PEAK_ALU_TFLOPS * 1e12) * 1e3,
+                 "update": work["update"] / (PEAK_ALU_TFLOPS * 1e12) * 1e3}
+        if prof.get("mlp", (0, 0))[1]:
+            terms["mlp"] = work["mlp"] / (PEAK_BF16_TFLOPS * 1e12) * 1e3
+        floor = sum(terms.values())
+        return {"floor_ms": floor, "measured_ms": ms_step, "frac": floor / ms_step,
+                "terms_ms": terms}
+
     main_prec = precisions[0]
     res = results[main_prec]
     ms_step = 1e3 * res["elapsed"] / args.steps
@@ -330,6 +352,7 @@ def main():
                    "refine_cond": args.refine_cond if main_prec in ("mixed", "mlp") else None,
                    "refined_fits_per_step": res["info"].get("n_refined")},
         "roofline": top,
+        "step_roofline": step_roofline(res["prof"], ms_step),
         "kernels": kr,
         "cpu_baseline": cpu,
         "stages_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in res["prof"].items()},
@@ -340,6 +363,8 @@ def main():
         r2 = results[prec]
         out[prec] = {"value": n * args.steps / r2["elapsed"], "ms_per_step": 1e3 * r2["elapsed"] / args.steps,
                      "kernels": kernel_rooflines(r2["prof"], prec), "tuning": r2["tuning"],
+                     "step_roofline": step_roofline(r2["prof"], 1e3 * r2["elapsed"] / args.steps),
+                     "refined_fits_per_step": r2["info"].get("n_refined"),
                      "stages_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in r2["prof"].items()}}
         if prec == "mlp":
             out[prec]["learned_estimator"] = dict(mlp_train, n_network=r2["info"]["n_mlp"],
