@@ -128,6 +128,81 @@ __device__ __forceinline__ void for_lw_stencil(const Sorted &srt, const DevCfg &
     }
 }
 
+// The same stencil walk over the gather records, two entries deep: while
+// entry t is processed, the record of entry t + 1 and the index of entry
+// t + 2 are in flight (every load is unconditional, with the index clamped
+// to the list, so that no load result passes through a branch).  body(j, dx,
+// f) gets the member's V, u_0..u_{D-1}, P.  Needs srt.rec.
+template <int D, typename F>
+__device__ __forceinline__ void for_lw_stencil_rec(const Sorted &srt, const DevCfg &cfg, const int *nbr, int ldn,
+                                                   int s, int k, const double xi[3], F &&body) {
+    const int cap = cfg.lw_cap;
+    int Rstar = 1 << 30, rem = 0;
+    if (k > cap) {
+        unsigned long long c03 = 0, c47 = 0;  // octant counts, 16 bits each
+        for (int t = 0; t < k; ++t) {
+            int j = nb_at(nbr, ldn, s, t);
+            double dx[3];
+            displacement<D>(srt, cfg, j, xi, dx);
+            int o = octant<D>(dx);
+            if (o < 4) c03 += 1ull << (16 * o); else c47 += 1ull << (16 * (o - 4));
+        }
+        int cnt[8];
+        for (int o = 0; o < 4; ++o) cnt[o] = (int)((c03 >> (16 * o)) & 0xffff);
+        for (int o = 0; o < 4; ++o) cnt[4 + o] = (int)((c47 >> (16 * o)) & 0xffff);
+        int R = 0, taken = 0;
+        for (;;) {
+            int next = 0;
+            for (int o = 0; o < 8; ++o) next += cnt[o] < R + 1 ? cnt[o] : R + 1;
+            if (next > cap) break;
+            taken = next;
+            ++R;
+        }
+        Rstar = R;
+        rem = cap - taken;
+    }
+    if (k <= 0) return;
+    unsigned long long s03 = 0, s47 = 0;
+    int takenR = 0;
+    auto rec_of = [&](int j, double2 r[4]) {
+        const double2 *p = reinterpret_cast<const double2 *>(srt.rec + (int64_t)LP_REC * j);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) r[q] = p[q];
+    };
+    int jc = nb_at(nbr, ldn, s, 0);                  // entry t
+    int jn = nb_at(nbr, ldn, s, k > 1 ? 1 : 0);      // entry t + 1
+    double2 rc[4];
+    rec_of(jc, rc);
+    for (int t = 0; t < k; ++t) {
+        const int j = jc;
+        double2 cur[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cur[q] = rc[q];
+        jc = jn;
+        rec_of(jc, rc);                                   // record of entry t + 1
+        jn = nb_at(nbr, ldn, s, t + 2 < k ? t + 2 : k - 1);  // index of entry t + 2
+        const double p[3] = {cur[0].x, cur[0].y, D == 3 ? cur[1].x : 0.0};
+        double dx[3];
+        disp_of<D>(cfg, p, xi, dx);
+        if (k > cap) {
+            int o = octant<D>(dx);
+            int rho;
+            if (o < 4) { rho = (int)((s03 >> (16 * o)) & 0xffff); s03 += 1ull << (16 * o); }
+            else { rho = (int)((s47 >> (16 * (o - 4))) & 0xffff); s47 += 1ull << (16 * (o - 4)); }
+            bool take = rho < Rstar || (rho == Rstar && takenR < rem);
+            if (rho == Rstar && take) ++takenR;
+            if (!take) continue;
+        }
+        double f[D + 2];
+        if constexpr (D == 3) {
+            f[0] = cur[1].y; f[1] = cur[2].x; f[2] = cur[2].y; f[3] = cur[3].x; f[4] = cur[3].y;
+        } else {
+            f[0] = cur[1].x; f[1] = cur[1].y; f[2] = cur[2].x; f[3] = cur[2].y;
+        }
+        body(j, dx, f);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Small dense algebra in registers
 // ---------------------------------------------------------------------------
@@ -820,15 +895,13 @@ __device__ __forceinline__ void lw_fit_one(const SolveArgs &a, int s, int t) {
 #pragma unroll
     for (int q = 0; q < NF * NU; ++q) B[q] = 0;
     int m = 0;
-    for_lw_stencil<D>(srt, cfg, a.nbr, a.ldn, s, k, xi, [&](int j, const double dx[3]) {
+    auto member = [&](const double dx[3], const double fr[NF]) {
         T x[3];
 #pragma unroll
         for (int q = 0; q < D; ++q) x[q] = (T)(dx[q] * inv_r);
         add_moments<D, T>(x, M);
         T row[NU];
         second_order_row<D, T>(x, row);
-        double fr[NF];
-        gather_fields<D>(srt, j, fr);
         T fj[NF];
 #pragma unroll
         for (int f = 0; f < NF; ++f) fj[f] = (T)fr[f];
@@ -839,7 +912,18 @@ __device__ __forceinline__ void lw_fit_one(const SolveArgs &a, int s, int t) {
             for (int pp = 0; pp < NU; ++pp) B[f * NU + pp] += row[pp] * b;
         }
         ++m;
-    });
+    };
+    if (use_f && srt.rec) {
+        // FP32 sums leave registers for one record in flight
+        for_lw_stencil_rec<D>(srt, cfg, a.nbr, a.ldn, s, k, xi,
+                              [&](int, const double dx[3], const double fr[NF]) { member(dx, fr); });
+    } else {
+        for_lw_stencil<D>(srt, cfg, a.nbr, a.ldn, s, k, xi, [&](int j, const double dx[3]) {
+            double fr[NF];
+            gather_fields<D>(srt, j, fr);
+            member(dx, fr);
+        });
+    }
     T G[NG];
     gram_from_moments<D, T>(M, G);
     T inv[NU];
