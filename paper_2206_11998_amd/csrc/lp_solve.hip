@@ -610,19 +610,12 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
         for (int q = 0; q < D; ++q) { Sl[q] = 0; Sr[q] = 0; }
         int nl = 0, nr = 0;
         const T fi[3] = {(T)st[0], (T)st[1 + a], (T)st[FP]};
-        int jn = k > 0 ? nb_at(nbr, ldn, s, 0) : 0;  // next index loaded one iteration ahead
-        for (int t = 0; t < k && (nl < ucap || nr < ucap); ++t) {
-            const int j = jn;
-            if (t + 1 < k) jn = nb_at(nbr, ldn, s, t + 1);
-            double dx[3];
-            displacement<D>(srt, cfg, j, xi, dx);
-            bool right = dx[a] > 0.0, left = dx[a] < 0.0;
-            if (!((right && nr < ucap) || (left && nl < ucap))) continue;
+        // a member of an open half-ball of axis a: accumulate it
+        auto visit = [&](const double dx[3], const double fr[NF]) {
+            const bool right = dx[a] > 0.0;
             T x[3];
 #pragma unroll
             for (int b = 0; b < D; ++b) x[b] = (T)(dx[b] * inv_r);
-            double fr[NF];
-            gather_fields<D>(srt, j, fr);
             const T fj[3] = {(T)fr[0], (T)fr[1 + a], (T)fr[FP]};
             T bq[3] = {fj[0] - fi[0], fj[1] - fi[1], fj[2] - fi[2]};
             vmin = fj[0] < vmin ? fj[0] : vmin;
@@ -653,6 +646,53 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
                 Sl[b] += wl * x[b];
             }
             if (right) ++nr; else ++nl;
+        };
+        if (sizeof(T) == 4 && srt.rec && k > 0) {
+            // FP32 sums leave registers for the walk two entries deep over the
+            // gather records: the next record and the index after it are in
+            // flight while an entry is examined (loads unconditional, index
+            // clamped to the list)
+            int jc = nb_at(nbr, ldn, s, 0), jn = nb_at(nbr, ldn, s, k > 1 ? 1 : 0);
+            double2 rc[4];
+            auto rec_of = [&](int j, double2 r[4]) {
+                const double2 *pr = reinterpret_cast<const double2 *>(srt.rec + (int64_t)LP_REC * j);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) r[q] = pr[q];
+            };
+            rec_of(jc, rc);
+            for (int t = 0; t < k && (nl < ucap || nr < ucap); ++t) {
+                double2 cur[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) cur[q] = rc[q];
+                jc = jn;
+                rec_of(jc, rc);
+                jn = nb_at(nbr, ldn, s, t + 2 < k ? t + 2 : k - 1);
+                const double pj[3] = {cur[0].x, cur[0].y, D == 3 ? cur[1].x : 0.0};
+                double dx[3];
+                disp_of<D>(cfg, pj, xi, dx);
+                const bool right = dx[a] > 0.0, left = dx[a] < 0.0;
+                if (!((right && nr < ucap) || (left && nl < ucap))) continue;
+                double fr[NF];
+                if constexpr (D == 3) {
+                    fr[0] = cur[1].y; fr[1] = cur[2].x; fr[2] = cur[2].y; fr[3] = cur[3].x; fr[4] = cur[3].y;
+                } else {
+                    fr[0] = cur[1].x; fr[1] = cur[1].y; fr[2] = cur[2].x; fr[3] = cur[2].y;
+                }
+                visit(dx, fr);
+            }
+        } else {
+            int jn = k > 0 ? nb_at(nbr, ldn, s, 0) : 0;  // next index loaded one iteration ahead
+            for (int t = 0; t < k && (nl < ucap || nr < ucap); ++t) {
+                const int j = jn;
+                if (t + 1 < k) jn = nb_at(nbr, ldn, s, t + 1);
+                double dx[3];
+                displacement<D>(srt, cfg, j, xi, dx);
+                const bool right = dx[a] > 0.0, left = dx[a] < 0.0;
+                if (!((right && nr < ucap) || (left && nl < ucap))) continue;
+                double fr[NF];
+                gather_fields<D>(srt, j, fr);
+                visit(dx, fr);
+            }
         }
         // per side: fit, vacuum ghosts, or LW substitute
 #pragma unroll
