@@ -647,11 +647,11 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
             }
             if (right) ++nr; else ++nl;
         };
-        if (sizeof(T) == 4 && srt.rec && k > 0) {
-            // FP32 sums leave registers for the walk two entries deep over the
-            // gather records: the next record and the index after it are in
-            // flight while an entry is examined (loads unconditional, index
-            // clamped to the list)
+        if (srt.rec && k > 0) {
+            // the walk two entries deep over the gather records: the next
+            // record and the index after it are in flight while an entry is
+            // examined (loads unconditional, index clamped to the list); the
+            // FP64 variant spills a few registers for it and is still faster
             int jc = nb_at(nbr, ldn, s, 0), jn = nb_at(nbr, ldn, s, k > 1 ? 1 : 0);
             double2 rc[4];
             auto rec_of = [&](int j, double2 r[4]) {
@@ -953,8 +953,8 @@ __device__ __forceinline__ void lw_fit_one(const SolveArgs &a, int s, int t) {
         }
         ++m;
     };
-    if (use_f && srt.rec) {
-        // FP32 sums leave registers for one record in flight
+    if (srt.rec) {
+        // one record in flight while a member is accumulated
         for_lw_stencil_rec<D>(srt, cfg, a.nbr, a.ldn, s, k, xi,
                               [&](int, const double dx[3], const double fr[NF]) { member(dx, fr); });
     } else {
