@@ -868,7 +868,7 @@ __device__ __forceinline__ void lw_refine_tail(const SolveArgs &a, int s, int t,
     T Ar[NF * NU];
 #pragma unroll
     for (int q = 0; q < NF * NU; ++q) Ar[q] = 0;
-    for_lw_stencil<D>(srt, a.cfg, a.nbr, a.ldn, s, k, xi, [&](int j, const double dx[3]) {
+    auto member = [&](const double dx[3], const double fj[NF]) {
         double x[3];
 #pragma unroll
         for (int q = 0; q < D; ++q) x[q] = dx[q] * inv_r;
@@ -877,8 +877,6 @@ __device__ __forceinline__ void lw_refine_tail(const SolveArgs &a, int s, int t,
         T rowf[NU];
 #pragma unroll
         for (int pp = 0; pp < NU; ++pp) rowf[pp] = (T)row[pp];
-        double fj[NF];
-        gather_fields<D>(srt, j, fj);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             double res = fj[f] - st[f];
@@ -888,7 +886,17 @@ __device__ __forceinline__ void lw_refine_tail(const SolveArgs &a, int s, int t,
 #pragma unroll
             for (int pp = 0; pp < NU; ++pp) Ar[f * NU + pp] += rowf[pp] * rf;
         }
-    });
+    };
+    if (srt.rec) {
+        for_lw_stencil_rec<D>(srt, a.cfg, a.nbr, a.ldn, s, k, xi,
+                              [&](int, const double dx[3], const double fj[NF]) { member(dx, fj); });
+    } else {
+        for_lw_stencil<D>(srt, a.cfg, a.nbr, a.ldn, s, k, xi, [&](int j, const double dx[3]) {
+            double fj[NF];
+            gather_fields<D>(srt, j, fj);
+            member(dx, fj);
+        });
+    }
     chol_solve<NU, NF, T, T>(G, inv, Ar);
     double grad[NF][3], hess[NF][NS];
 #pragma unroll
