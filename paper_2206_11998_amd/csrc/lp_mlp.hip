@@ -159,14 +159,15 @@ __global__ __launch_bounds__(64) void k_mlp_apply(const float *th, Sorted srt, S
     const int l = threadIdx.x & 63;
     const int n_total = sc->n_total;
     const double dt = sc->dt;
-    const int64_t ntile = ((int64_t)n_total + 15) / 16;
+    // groups of 64 particles: four 16-particle tiles through the network,
+    // then every lane finishes its own particle of the group
+    const int64_t ngroup = ((int64_t)n_total + 63) / 64;
     unsigned long long used = 0, plain = 0, lim = 0;
-    for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
-        const int s = (int)(tile * 16 + (l & 15));
+    for (int64_t grp = blockIdx.x; grp < ngroup; grp += gridDim.x) {
+        const int s = (int)(grp * 64 + l);
         bool ok = s < n_total;
         const int i = ok ? srt.id[s] : n_real;
-        ok = ok && i < n_real;
-        const bool mine = ok && l < 16;  // lanes 0..15 finish the tile's particles
+        const bool mine = ok && i < n_real;
         // the update's operands are loaded before the network runs, so their
         // latency overlaps the matrix instructions
         double st[NF], lw[NF], uw[NF], xs[D];
@@ -188,10 +189,20 @@ __global__ __launch_bounds__(64) void k_mlp_apply(const float *th, Sorted srt, S
             phi_plain = ms.phi_plain[s];
             mf = ms.mflag[s];
         }
-        const bf16x4 x = load_x(ms.feat, s, ok);
-        f32x4 d1[4], d2[4];
-        bf16x4 h1[4];
-        const float z = forward(R, x, d1, h1, d2);
+        // tile t covers particles 64 grp + 16 t .. + 15; after its pass, lane
+        // l of quarter t holds the output of particle 64 grp + l (a column of
+        // the products depends on its own sample only, so unstaged rows of
+        // ghosts affect nothing else)
+        float z = 0.f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int64_t sx = grp * 64 + 16 * t + (l & 15);
+            const bf16x4 x = load_x(ms.feat, sx, sx < n_total);
+            f32x4 d1[4], d2[4];
+            bf16x4 h1[4];
+            const float zt = forward(R, x, d1, h1, d2);
+            if ((l >> 4) == t) z = zt;
+        }
         if (!mine) continue;
         double phi;
         if (mf & LP_MLP_FORCE0) {
@@ -256,8 +267,8 @@ __global__ __launch_bounds__(64) void k_mlp_apply(const float *th, Sorted srt, S
 
 void launch_mlp_apply(const float *th, const Sorted &s, const Soa &p, const DevCfg &cfg, DevScalars *sc,
                       int64_t n_total_cap, int n_real, const MlpStage &ms, hipStream_t st) {
-    int64_t nt = (n_total_cap + 15) / 16;
-    unsigned g = (unsigned)(nt < 8192 ? (nt > 0 ? nt : 1) : 8192);  // each wave loads the weights once
+    int64_t ng = (n_total_cap + 63) / 64;
+    unsigned g = (unsigned)(ng < 8192 ? (ng > 0 ? ng : 1) : 8192);  // each wave loads the weights once
     if (cfg.D == 3)
         hipLaunchKernelGGL(k_mlp_apply<3>, dim3(g), dim3(64), 0, st, th, s, p, cfg, sc, n_real, ms);
     else
