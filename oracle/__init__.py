@@ -76,6 +76,8 @@ def lib():
         L.lpo_neighbors.argtypes = [cp, C.c_int64, dp, dp, dp, dp, C.c_int32, ip, ip]
         L.lpo_gfd.restype = C.c_int
         L.lpo_gfd.argtypes = [cp, C.c_int64, dp, dp, dp, dp, C.c_int32, C.POINTER(dp), dp, u8p]
+        L.lpo_gfd3.restype = C.c_int
+        L.lpo_gfd3.argtypes = [cp, C.c_int64, dp, dp, dp, dp, C.c_int32, C.POINTER(dp), dp, u8p]
         L.lpo_timestep.restype = C.c_double
         L.lpo_timestep.argtypes = [cp, C.c_int64, dp, dp, dp]
         L.lpo_step_subset.restype = C.c_int
@@ -229,6 +231,26 @@ def gfd(cfg: dict, x: np.ndarray, r: np.ndarray, fields):
     status = np.zeros(n, dtype=np.uint8)
     st = lib().lpo_gfd(C.byref(c), n, _dp(X[0]), _dp(X[1]), _dp(X[2]), _dp(r), len(fs), arr, _dp(deriv),
                        status.ctypes.data_as(C.POINTER(C.c_uint8)))
+    return deriv, status, st
+
+
+def gfd3(cfg: dict, x: np.ndarray, r: np.ndarray, fields):
+    """Third-order GFD derivatives: deriv[f, c, i] (c over the 19 / 9 columns:
+    x, y, z, xx, yy, zz, xy, xz, yz, xxx, yyy, zzz, xxy, xxz, xyy, yyz, xzz,
+    yzz, xyz in 3D; x, y, xx, yy, xy, xxx, yyy, xxy, xyy in 2D), status[i]
+    (0 cubic, 1 quadratic, 2 linear, 3 none)."""
+    c = make_cfg(cfg)
+    d = c.dim
+    n = x.shape[0]
+    nu = 19 if d == 3 else 9
+    X = _xyz(x, d)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    fs = [np.ascontiguousarray(f, dtype=np.float64) for f in fields]
+    arr = (C.POINTER(C.c_double) * len(fs))(*[_dp(f) for f in fs])
+    deriv = np.zeros((len(fs), nu, n))
+    status = np.zeros(n, dtype=np.uint8)
+    st = lib().lpo_gfd3(C.byref(c), n, _dp(X[0]), _dp(X[1]), _dp(X[2]), _dp(r), len(fs), arr, _dp(deriv),
+                        status.ctypes.data_as(C.POINTER(C.c_uint8)))
     return deriv, status, st
 
 

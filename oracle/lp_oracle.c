@@ -46,6 +46,7 @@ int lpo_num_threads(void)
 }
 
 #define ORC_MAXN 9      /* unknowns of the 3D second-order fit */
+#define ORC_MAXN3 19    /* unknowns of the 3D third-order fit */
 #define ORC_MAXF 5      /* fields V, u1..uD, P */
 
 /* ------------------------------------------------------------------------- */
@@ -53,6 +54,7 @@ int lpo_num_threads(void)
 /* ------------------------------------------------------------------------- */
 
 static int nfit2(int dim) { return dim == 3 ? 9 : 5; }           /* 2nd-order unknowns */
+static int nfit3(int dim) { return dim == 3 ? 19 : 9; }          /* 3rd-order unknowns */
 static int nsecond(int dim) { return dim == 3 ? 6 : 3; }         /* 2nd-derivative cols */
 
 /* Minimum-image displacement along one axis (Sec. 2.2: periodic domains are
@@ -104,8 +106,8 @@ double lpo_estimator_ratio(double sl, double sr)
 
 double lpo_lstsq_qrp(int k, int n, int nrhs, double *A, double *B, double *X)
 {
-    int perm[ORC_MAXN + 1];
-    double Y[(ORC_MAXN + 1) * ORC_MAXF];
+    int perm[ORC_MAXN3 + 1];
+    double Y[(ORC_MAXN3 + 1) * ORC_MAXF];
     for (int j = 0; j < n; ++j) perm[j] = j;
     int steps = k < n ? k : n;
     for (int p = 0; p < steps; ++p) {
@@ -374,6 +376,36 @@ static void second_order_row(int dim, const double *xi, double *row)
     for (int a = 0; a < dim; ++a) row[dim + a] = 0.5 * xi[a] * xi[a];
     if (dim == 2) row[4] = xi[0] * xi[1];
     else { row[6] = xi[0] * xi[1]; row[7] = xi[0] * xi[2]; row[8] = xi[1] * xi[2]; }
+}
+
+/* Third-order row: the second-order row followed by the cubic Taylor terms
+ * xi^alpha / alpha! (|alpha| = 3) in the order
+ *   3D: xxx, yyy, zzz, xxy, xxz, xyy, yyz, xzz, yzz, xyz
+ *   2D: xxx, yyy, xxy, xyy
+ * (xyy is d3f / dx dy dy with the term xi_x xi_y^2 / 2). */
+static void third_order_row(int dim, const double *xi, double *row)
+{
+    second_order_row(dim, xi, row);
+    int o = nfit2(dim);
+    double x = xi[0], y = xi[1];
+    if (dim == 2) {
+        row[o + 0] = x * x * x / 6.0;
+        row[o + 1] = y * y * y / 6.0;
+        row[o + 2] = 0.5 * x * x * y;
+        row[o + 3] = 0.5 * x * y * y;
+    } else {
+        double z = xi[2];
+        row[o + 0] = x * x * x / 6.0;
+        row[o + 1] = y * y * y / 6.0;
+        row[o + 2] = z * z * z / 6.0;
+        row[o + 3] = 0.5 * x * x * y;
+        row[o + 4] = 0.5 * x * x * z;
+        row[o + 5] = 0.5 * x * y * y;
+        row[o + 6] = 0.5 * y * y * z;
+        row[o + 7] = 0.5 * x * z * z;
+        row[o + 8] = 0.5 * y * z * z;
+        row[o + 9] = x * y * z;
+    }
 }
 
 /* Column index of the mixed second derivative d2/dx_a dx_b (a != b) */
@@ -815,6 +847,93 @@ int lpo_gfd(const lpo_cfg *c, int64_t n, const double *x, const double *y, const
                     deriv[((size_t)ff * nu + D + qq) * (size_t)n + i] = hess[ff * 6 + qq];
             }
             free(dxs); free(fj); free(fi); free(sel); free(grad); free(hess);
+        }
+    }
+    free(count); free(lists); free(q);
+    return st;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Third-order derivative operator: lp_gfd3's definition (Sec. 2.1: the GFD   */
+/* system is the Taylor expansion truncated at second order; the same         */
+/* construction one order further).                                           */
+/* ------------------------------------------------------------------------- */
+
+/* Fit over the selected rows; out[f * nu3 + col].  Returns 0 = cubic fit,
+ * 1 = cubic deficient (fewer rows than unknowns or |R11|/|Rnn| > cond_max)
+ * -> the second-order fit on the same rows, 2 = that one deficient too ->
+ * linear fit, 3 = nothing usable (all 0). */
+static int gfd3_fit(const lpo_cfg *c, int m, const int *sel, const double *dxs, double s, int nf,
+                    const double *fi, const double *fj, double *out)
+{
+    int D = c->dim, n = nfit3(D), n2 = nfit2(D);
+    memset(out, 0, sizeof(double) * (size_t)nf * (size_t)n);
+    if (m >= n) {
+        double *A = (double *)malloc(sizeof(double) * (size_t)m * ORC_MAXN3);
+        double *B = (double *)malloc(sizeof(double) * (size_t)m * ORC_MAXF);
+        double X[ORC_MAXN3 * ORC_MAXF];
+        for (int t = 0; t < m; ++t) {
+            double xi[3] = {0.0, 0.0, 0.0};
+            for (int a = 0; a < D; ++a) xi[a] = dxs[sel[t] * 3 + a] / s;
+            third_order_row(D, xi, A + (size_t)t * n);
+            for (int f = 0; f < nf; ++f) B[t * nf + f] = fj[sel[t] * nf + f] - fi[f];
+        }
+        double cond = lpo_lstsq_qrp(m, n, nf, A, B, X);
+        free(A); free(B);
+        if (cond <= c->cond_max) {
+            /* unscale: a column of degree p carries the derivative times s^p */
+            for (int f = 0; f < nf; ++f)
+                for (int q = 0; q < n; ++q) {
+                    double sp = q < D ? s : (q < n2 ? s * s : s * s * s);
+                    out[f * n + q] = X[q * nf + f] / sp;
+                }
+            return 0;
+        }
+    }
+    double grad[ORC_MAXF * 3], hess[ORC_MAXF * 6];
+    int st2 = lw_fit(c, m, sel, dxs, s, nf, fi, fj, grad, hess);
+    for (int f = 0; f < nf; ++f) {
+        for (int a = 0; a < D; ++a) out[f * n + a] = grad[f * 3 + a];
+        for (int q = 0; q < nsecond(D); ++q) out[f * n + D + q] = hess[f * 6 + q];
+    }
+    return 1 + st2;
+}
+
+int lpo_gfd3(const lpo_cfg *c, int64_t n, const double *x, const double *y, const double *z,
+             const double *r, int32_t nf, const double *const *f, double *deriv, uint8_t *status)
+{
+    int D = c->dim, nu = nfit3(D);
+    if (nf < 1 || nf > ORC_MAXF) return LPO_E_ARG;
+    const double *X[3] = {x, y, z ? z : x};
+    int cap = c->max_nb;
+    int32_t *count = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *lists = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1) * (size_t)cap);
+    int64_t *q = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!count || !lists || !q) { free(count); free(lists); free(q); return LPO_E_NOMEM; }
+    for (int64_t i = 0; i < n; ++i) q[i] = i;
+    int st = neighbor_lists(c, n, q, n, X, r, cap, count, lists);
+    if (st == LPO_OK) {
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t i = 0; i < n; ++i) {
+            int k = count[i];
+            double *dxs = (double *)malloc(sizeof(double) * 3 * (size_t)(k > 0 ? k : 1));
+            double *fj = (double *)malloc(sizeof(double) * (size_t)nf * (size_t)(k > 0 ? k : 1));
+            int *sel = (int *)malloc(sizeof(int) * (size_t)(k > 0 ? k : 1));
+            double fi[ORC_MAXF], out[ORC_MAXF * ORC_MAXN3];
+            for (int ff = 0; ff < nf; ++ff) fi[ff] = f[ff][i];
+            for (int t = 0; t < k; ++t) {
+                int64_t j = lists[(size_t)i * (size_t)cap + t];
+                double dx[3];
+                dist2(c, X, i, j, dx);
+                for (int a = 0; a < 3; ++a) dxs[t * 3 + a] = dx[a];
+                for (int ff = 0; ff < nf; ++ff) fj[t * nf + ff] = f[ff][j];
+            }
+            int lcap = c->lw_cap > 0 ? c->lw_cap : (D == 3 ? 54 : 32);
+            int m = lw_select(D, k, dxs, lcap, sel);
+            status[i] = (uint8_t)gfd3_fit(c, m, sel, dxs, r[i], nf, fi, fj, out);
+            for (int ff = 0; ff < nf; ++ff)
+                for (int qq = 0; qq < nu; ++qq) deriv[((size_t)ff * nu + qq) * (size_t)n + i] = out[ff * nu + qq];
+            free(dxs); free(fj); free(sel);
         }
     }
     free(count); free(lists); free(q);

@@ -51,6 +51,11 @@ int lpo_neighbors(const lpo_cfg *c, int64_t n, const double *x, const double *y,
                   const double *r, int32_t max_nb, int32_t *count, int32_t *idx);
 int lpo_gfd(const lpo_cfg *c, int64_t n, const double *x, const double *y, const double *z,
             const double *r, int32_t nf, const double *const *f, double *deriv, uint8_t *status);
+/* Third-order GFD derivatives: deriv[(f * nu + col) * n + i], nu = 19 (3D) or 9
+ * (2D), columns as lp_gfd's followed by the cubic ones; status 0 = cubic fit,
+ * 1 = quadratic, 2 = linear, 3 = none. */
+int lpo_gfd3(const lpo_cfg *c, int64_t n, const double *x, const double *y, const double *z,
+             const double *r, int32_t nf, const double *const *f, double *deriv, uint8_t *status);
 double lpo_timestep(const lpo_cfg *c, int64_t n, const double *V, const double *P, const double *m);
 int lpo_step_subset(const lpo_cfg *c, int64_t n, const double *x, const double *y, const double *z,
                     const double *V, const double *u, const double *v, const double *w,
