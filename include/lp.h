@@ -156,6 +156,24 @@ lp_status lp_gfd(struct lp_ctx *ctx, void *stream, int64_t n, const double *x, c
                  const double *z, const double *r, int32_t nf, const double *const *f, double *deriv,
                  uint8_t *status);
 
+/* Third-order GFD derivatives (Sec. 2.1, the Taylor system carried to the
+ * cubic terms): for each particle i, the least-squares fit over the same
+ * stencil as lp_gfd of
+ *   f_j - f_i = (second-order terms of lp_gfd)
+ *             + sum_{|alpha| = 3} d^alpha f dx^alpha / alpha!,
+ * solved by Householder QR with column pivoting on coordinates scaled by r[i].
+ * Arguments and layout as lp_gfd with nu = 19 (3D: x, y, z, xx, yy, zz, xy,
+ * xz, yz, xxx, yyy, zzz, xxy, xxz, xyy, yyz, xzz, yzz, xyz; xyy is
+ * d3f / dx dy dy) or 9 (2D: x, y, xx, yy, xy, xxx, yyy, xxy, xyy).
+ * status: 0 = third-order fit; 1 = the cubic system has fewer rows than
+ * unknowns or |R11|/|Rnn| above cond_max, and the values are lp_gfd's
+ * second-order fit of the same stencil (third derivatives 0); 2 = that fit is
+ * deficient too (linear fit); 3 = fewer than dim usable neighbours (all 0).
+ * Always FP64; one wave per particle. */
+lp_status lp_gfd3(struct lp_ctx *ctx, void *stream, int64_t n, const double *x, const double *y,
+                  const double *z, const double *r, int32_t nf, const double *const *f, double *deriv,
+                  uint8_t *status);
+
 /* One time step (Sec. 2.2, steps 1-6) of the particle set p, in place:
  * dt > 0 is used as given, dt <= 0 selects cfl * min_i h_i / c_i.
  * Synchronises once (to size the cell grid).  Mass is never modified. */

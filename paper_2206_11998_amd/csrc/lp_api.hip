@@ -845,14 +845,18 @@ extern "C" lp_status lp_neighbors(lp_ctx *c, void *stream, int64_t n, const doub
     return LP_OK;
 }
 
-extern "C" lp_status lp_gfd(lp_ctx *c, void *stream, int64_t n, const double *x, const double *y, const double *z,
-                            const double *r, int32_t nf, const double *const *f, double *deriv, uint8_t *status) {
+// lp_gfd (order 2) and lp_gfd3 (order 3): cells, search and the fit of the
+// given order over the caller's positions and fields
+static lp_status gfd_run(lp_ctx *c, void *stream, int64_t n, const double *x, const double *y, const double *z,
+                         const double *r, int32_t nf, const double *const *f, double *deriv, uint8_t *status,
+                         int order) {
+    const char *name = order == 3 ? "lp_gfd3" : "lp_gfd";
     if (!c) return LP_E_ARG;
     if (n <= 0 || n > (1ll << 30) || !x || !y || (c->dc.D == 3 && !z) || !r || !f || nf < 1 || nf > 5 || !deriv ||
         !status)
-        return fail(c, LP_E_ARG, "lp_gfd: bad arguments");
+        return fail(c, LP_E_ARG, "%s: bad arguments", name);
     for (int q = 0; q < nf; ++q)
-        if (!f[q]) return fail(c, LP_E_ARG, "lp_gfd: null field");
+        if (!f[q]) return fail(c, LP_E_ARG, "%s: null field", name);
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)stream;
     const int D = c->dc.D;
@@ -889,16 +893,31 @@ extern "C" lp_status lp_gfd(lp_ctx *c, void *stream, int64_t n, const double *x,
     launch_coarsen((uint32_t *)c->tables.p, c->grid, D, &c->sc->n_total, st);
     int ldn = list_ldn(c);
     run_search(c, srt, n, (int)n, c->search_cap, st);
-    launch_gfd(srt, fs, nf, (const int *)c->nbr.p, ldn, (const int *)c->count.p, (int)n, c->dc, c->sc,
-               (int *)c->queue.p, deriv, status, st);
-    launch_gfd_fallback(srt, fs, nf, (const int *)c->nbr.p, ldn, (const int *)c->count.p, (int)n, c->dc, c->sc,
-                        (const int *)c->queue.p, (int)n, deriv, status, st);
+    if (order == 3) {
+        launch_gfd3(srt, fs, nf, (const int *)c->nbr.p, ldn, (const int *)c->count.p, (int)n, c->dc, deriv, status,
+                    st);
+    } else {
+        launch_gfd(srt, fs, nf, (const int *)c->nbr.p, ldn, (const int *)c->count.p, (int)n, c->dc, c->sc,
+                   (int *)c->queue.p, deriv, status, st);
+        launch_gfd_fallback(srt, fs, nf, (const int *)c->nbr.p, ldn, (const int *)c->count.p, (int)n, c->dc, c->sc,
+                            (const int *)c->queue.p, (int)n, deriv, status, st);
+    }
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     if (c->sc_host->max_count > c->dc.max_nb) return fail(c, LP_E_CAPACITY, "neighbour count %d exceeds max_nb %d",
                                                           c->sc_host->max_count, c->dc.max_nb);
     return LP_OK;
+}
+
+extern "C" lp_status lp_gfd(lp_ctx *c, void *stream, int64_t n, const double *x, const double *y, const double *z,
+                            const double *r, int32_t nf, const double *const *f, double *deriv, uint8_t *status) {
+    return gfd_run(c, stream, n, x, y, z, r, nf, f, deriv, status, 2);
+}
+
+extern "C" lp_status lp_gfd3(lp_ctx *c, void *stream, int64_t n, const double *x, const double *y, const double *z,
+                             const double *r, int32_t nf, const double *const *f, double *deriv, uint8_t *status) {
+    return gfd_run(c, stream, n, x, y, z, r, nf, f, deriv, status, 3);
 }
 
 extern "C" lp_status lp_conservation(lp_ctx *c, void *stream, const lp_particles *p, double *out) {

@@ -224,6 +224,8 @@ void launch_gfd(const Sorted &s, const double *const *fs, int nf, const int *nbr
 void launch_gfd_fallback(const Sorted &s, const double *const *fs, int nf, const int *nbr, int ldn,
                          const int *count, int n, const DevCfg &cfg, DevScalars *sc, const int *queue,
                          int queue_cap, double *deriv, uint8_t *status, hipStream_t st);
+void launch_gfd3(const Sorted &s, const double *const *fs, int nf, const int *nbr, int ldn, const int *count,
+                 int n, const DevCfg &cfg, double *deriv, uint8_t *status, hipStream_t st);
 void launch_conservation(const Soa &p, const DevCfg &cfg, double *partials, int nblocks, double *out,
                          hipStream_t st);
 

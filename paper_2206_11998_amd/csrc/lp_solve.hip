@@ -1559,6 +1559,230 @@ __global__ __launch_bounds__(64) void k_gfd_fallback(Sorted srt, FieldPtrs fs, i
     }
 }
 
+// ---------------------------------------------------------------------------
+// Third-order derivative operator (lp_gfd3): the Taylor system of Sec. 2.1
+// carried to the cubic terms, one wave per particle (one stencil row per
+// lane), solved by pivoted Householder QR; a deficient cubic system takes the
+// second-order fit of the same stencil.
+// ---------------------------------------------------------------------------
+template <int D> struct Dim3 { static constexpr int NU = D == 3 ? 19 : 9; };
+
+// Second-order row followed by xi^alpha / alpha! for |alpha| = 3, in the order
+// 3D: xxx, yyy, zzz, xxy, xxz, xyy, yyz, xzz, yzz, xyz; 2D: xxx, yyy, xxy, xyy.
+template <int D>
+__device__ __forceinline__ void third_order_row(const double xi[3], double row[Dim3<D>::NU]) {
+    second_order_row<D, double>(xi, row);
+    constexpr int o = Dim<D>::NU;
+    const double x = xi[0], y = xi[1];
+    if constexpr (D == 2) {
+        row[o + 0] = x * x * x / 6.0;
+        row[o + 1] = y * y * y / 6.0;
+        row[o + 2] = 0.5 * x * x * y;
+        row[o + 3] = 0.5 * x * y * y;
+    } else {
+        const double z = xi[2];
+        row[o + 0] = x * x * x / 6.0;
+        row[o + 1] = y * y * y / 6.0;
+        row[o + 2] = z * z * z / 6.0;
+        row[o + 3] = 0.5 * x * x * y;
+        row[o + 4] = 0.5 * x * x * z;
+        row[o + 5] = 0.5 * x * y * y;
+        row[o + 6] = 0.5 * y * y * z;
+        row[o + 7] = 0.5 * x * z * z;
+        row[o + 8] = 0.5 * y * z * z;
+        row[o + 9] = x * y * z;
+    }
+}
+
+// degree of unknown q of the third-order fit
+template <int D>
+__device__ __forceinline__ int third_order_degree(int q) { return q < D ? 1 : (q < Dim<D>::NU ? 2 : 3); }
+
+// lane permutation of a double by DPP (both halves)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// sum over the 64 lanes (all active), the result in every lane: within each
+// 16-lane row by DPP (lanes ^ 1, ^ 2, then the 8- and 16-lane mirrors), then
+// across the rows
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x141>(v);
+    v += dpp_f64<0x140>(v);
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    return v;
+}
+
+// Pivoted Householder QR of the wave's rows a[N] (one row per lane; rows of
+// lanes beyond the stencil are zero) and least squares for the first nr of NR
+// right-hand sides b.  The pivot is the remaining column of largest norm over
+// the remaining rows.  Back substitution runs column by column, so on return
+// lane p < N holds in y[c] the solution for unknown col = perm[p] (col = -1
+// in lanes >= N).  Returns |R11| / |Rnn|.
+template <int N, int NR>
+__device__ __forceinline__ double wave_qrp_lanes(double a[N], double b[NR], int nr, double y[NR], int &col) {
+    const int l = threadIdx.x & 63;
+    int perm[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) perm[j] = j;
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+        int best = p;
+        double bn = -1.0;
+#pragma unroll
+        for (int j = p; j < N; ++j) {
+            const double c = wave_sum_dpp(l >= p ? a[j] * a[j] : 0.0);
+            if (c > bn) {
+                bn = c;
+                best = j;
+            }
+        }
+#pragma unroll
+        for (int j = p + 1; j < N; ++j)
+            if (j == best) {  // wave-uniform
+                const double t = a[p];
+                a[p] = a[j];
+                a[j] = t;
+                const int u = perm[p];
+                perm[p] = perm[j];
+                perm[j] = u;
+            }
+        const double x0 = __shfl(a[p], p);
+        const double sigma = wave_sum_dpp(l > p ? a[p] * a[p] : 0.0);
+        const double normx = sqrt(x0 * x0 + sigma);
+        if (normx == 0.0) continue;
+        const double alpha = x0 >= 0.0 ? -normx : normx;
+        const double v0 = x0 - alpha;
+        const double tau = -1.0 / (alpha * v0);
+        const double v = l == p ? v0 : (l > p ? a[p] : 0.0);
+#pragma unroll
+        for (int j = p + 1; j < N; ++j) {
+            const double w = wave_sum_dpp(v * a[j]) * tau;
+            a[j] -= w * v;
+        }
+#pragma unroll
+        for (int c = 0; c < NR; ++c)
+            if (c < nr) {
+                const double w = wave_sum_dpp(v * b[c]) * tau;
+                b[c] -= w * v;
+            }
+        a[p] = l == p ? alpha : (l > p ? 0.0 : a[p]);
+    }
+    const double r11 = fabs(__shfl(a[0], 0));
+    const double rnn = fabs(__shfl(a[N - 1], N - 1));
+#pragma unroll
+    for (int c = 0; c < NR; ++c) y[c] = 0.0;
+    // lane p holds row p of R (a[j], j >= p) and of Q^T b
+#pragma unroll
+    for (int p = N - 1; p >= 0; --p) {
+        const double d = a[p];
+#pragma unroll
+        for (int c = 0; c < NR; ++c)
+            if (c < nr) {
+                const double t = (l == p && d != 0.0) ? b[c] / d : 0.0;
+                const double yp = __shfl(t, p);
+                if (l == p) y[c] = yp;
+                if (l < p) b[c] -= a[p] * yp;
+            }
+    }
+    col = -1;
+#pragma unroll
+    for (int p = 0; p < N; ++p)
+        if (l == p) col = perm[p];
+    return rnn == 0.0 ? INFINITY : r11 / rnn;
+}
+
+// One wave per particle (blocks of one wave: the second-order fallback
+// synchronises the block), particles in a grid-stride loop.
+template <int D>
+__global__ __launch_bounds__(64) void k_gfd3(Sorted srt, FieldPtrs fs, int nf, const int *nbr, int ldn,
+                                             const int *count, int n, DevCfg cfg, double *deriv, uint8_t *status) {
+    constexpr int N3 = Dim3<D>::NU, NU = Dim<D>::NU, NS = Dim<D>::NS;
+    __shared__ int sel[64];
+    __shared__ int m_sh;
+    const int l = threadIdx.x & 63;
+    for (int s = blockIdx.x; s < n; s += gridDim.x) {
+        const int i = srt.id[s];
+        int k = count[s];
+        if (k > cfg.max_nb) k = cfg.max_nb;
+        const double xi[3] = {srt.x[0][s], srt.x[1][s], D == 3 ? srt.x[2][s] : 0.0};
+        const double r = srt.r[s];
+        double fi[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) fi[f] = f < nf ? fs.f[f][s] : 0.0;
+        if (l == 0) {
+            int m = 0;
+            for_lw_stencil<D>(srt, cfg, nbr, ldn, s, k, xi, [&](int j, const double dx[3]) { sel[m++] = j; });
+            m_sh = m;
+        }
+        __syncthreads();
+        const int m = m_sh;
+        double row[N3], b[5];
+#pragma unroll
+        for (int q = 0; q < N3; ++q) row[q] = 0.0;
+#pragma unroll
+        for (int f = 0; f < 5; ++f) b[f] = 0.0;
+        if (l < m) {
+            const int j = sel[l];
+            double dx[3];
+            displacement<D>(srt, cfg, j, xi, dx);
+            double x[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int a = 0; a < D; ++a) x[a] = dx[a] / r;
+            third_order_row<D>(x, row);
+#pragma unroll
+            for (int f = 0; f < 5; ++f)
+                if (f < nf) b[f] = fs.f[f][j] - fi[f];
+        }
+        __syncthreads();  // sel is rewritten by the fallback below
+        double y[5];
+        int col = -1;
+        double cond = INFINITY;
+        if (m >= N3) cond = wave_qrp_lanes<N3, 5>(row, b, nf, y, col);
+        if (m >= N3 && cond <= cfg.cond_max) {
+            if (col >= 0) {
+                const int deg = third_order_degree<D>(col);
+                const double sp = deg == 1 ? r : (deg == 2 ? r * r : r * r * r);
+                for (int f = 0; f < nf; ++f) deriv[((int64_t)f * N3 + col) * n + i] = y[f] / sp;
+            }
+            if (l == 0) status[i] = 0;
+        } else {
+            double grad[5][3], hess[5][NS];
+            const int st2 = lw_fit_wave<D, 5>(srt, cfg, nbr, ldn, s, k, xi, r, fi,
+                                              [&](int j, int f) { return f < nf ? fs.f[f][j] : 0.0; }, grad, hess,
+                                              sel);
+            if (l == 0) {
+                for (int f = 0; f < nf; ++f) {
+                    for (int a = 0; a < D; ++a) deriv[((int64_t)f * N3 + a) * n + i] = grad[f][a];
+                    for (int q = 0; q < NS; ++q) deriv[((int64_t)f * N3 + D + q) * n + i] = hess[f][q];
+                    for (int q = NU; q < N3; ++q) deriv[((int64_t)f * N3 + q) * n + i] = 0.0;
+                }
+                status[i] = (uint8_t)(1 + st2);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+void launch_gfd3(const Sorted &s, const double *const *fs, int nf, const int *nbr, int ldn, const int *count, int n,
+                 const DevCfg &cfg, double *deriv, uint8_t *status, hipStream_t st) {
+    FieldPtrs f{};
+    for (int q = 0; q < nf && q < 5; ++q) f.f[q] = fs[q];
+    unsigned blocks = (unsigned)(n < 65536 ? (n > 0 ? n : 1) : 65536);
+    if (cfg.D == 3)
+        hipLaunchKernelGGL(k_gfd3<3>, dim3(blocks), dim3(64), 0, st, s, f, nf, nbr, ldn, count, n, cfg, deriv, status);
+    else
+        hipLaunchKernelGGL(k_gfd3<2>, dim3(blocks), dim3(64), 0, st, s, f, nf, nbr, ldn, count, n, cfg, deriv, status);
+    (void)hipGetLastError();
+}
+
 void launch_gfd(const Sorted &s, const double *const *fs, int nf, const int *nbr, int ldn, const int *count, int n,
                 const DevCfg &cfg, DevScalars *sc, int *queue, double *deriv, uint8_t *status, hipStream_t st) {
     FieldPtrs f{};

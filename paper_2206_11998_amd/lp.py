@@ -19,7 +19,7 @@ FP64, MIXED = 0, 1
 EST_PLAIN, EST_INJECTED, EST_MLP = 0, 1, 2
 FLAG_LIMITED, FLAG_DEGENERATE, FLAG_VACUUM, FLAG_SUBSTITUTED, FLAG_FALLBACK, FLAG_NUMERIC = 1, 2, 4, 8, 16, 32
 
-EXPORTS = ["lp_config_default", "lp_create", "lp_destroy", "lp_neighbors", "lp_gfd", "lp_step", "lp_run",
+EXPORTS = ["lp_config_default", "lp_create", "lp_destroy", "lp_neighbors", "lp_gfd", "lp_gfd3", "lp_step", "lp_run",
            "lp_conservation", "lp_check", "lp_get_info", "lp_set_time", "lp_profile", "lp_profile_read",
            "lp_set_tuning", "lp_get_tuning", "lp_autotune", "lp_train_cfg_default", "lp_features", "lp_mlp_init",
            "lp_mlp_set", "lp_mlp_get", "lp_mlp_forward", "lp_mlp_grad", "lp_mlp_train", "lp_status_str",
@@ -94,6 +94,8 @@ def lib():
         L.lp_neighbors.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
         L.lp_gfd.restype = i32
         L.lp_gfd.argtypes = [vp, vp, i64, vp, vp, vp, vp, i32, C.POINTER(vp), vp, vp]
+        L.lp_gfd3.restype = i32
+        L.lp_gfd3.argtypes = [vp, vp, i64, vp, vp, vp, vp, i32, C.POINTER(vp), vp, vp]
         L.lp_step.restype = i32
         L.lp_step.argtypes = [vp, vp, C.POINTER(Particles), dbl]
         L.lp_run.restype = i32
@@ -278,6 +280,22 @@ class Context:
         z = x[2] if self.dim == 3 else None
         st = lib().lp_gfd(self._h, _stream_ptr(stream), n, _ptr(x[0]), _ptr(x[1]), _ptr(z), _ptr(r), nf, fp,
                           _ptr(deriv), _ptr(status))
+        self._raise(st)
+        return deriv, status
+
+    def gfd3(self, x, r, fields, stream=None):
+        """Third-order GFD derivatives: deriv[f, c, i] over the 19 (3D) / 9 (2D)
+        columns of lp_gfd3, status[i]."""
+        import torch
+        n = r.shape[0]
+        nu = 19 if self.dim == 3 else 9
+        nf = len(fields)
+        deriv = torch.zeros((nf, nu, n), dtype=torch.float64, device=r.device)
+        status = torch.zeros(n, dtype=torch.uint8, device=r.device)
+        fp = (C.c_void_p * nf)(*[f.data_ptr() for f in fields])
+        z = x[2] if self.dim == 3 else None
+        st = lib().lp_gfd3(self._h, _stream_ptr(stream), n, _ptr(x[0]), _ptr(x[1]), _ptr(z), _ptr(r), nf, fp,
+                           _ptr(deriv), _ptr(status))
         self._raise(st)
         return deriv, status
 

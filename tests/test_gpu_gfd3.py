@@ -1,0 +1,122 @@
+"""Third-order GFD derivatives (lp_gfd3) on the GPU.
+
+- Parity with the oracle's third-order fit on scattered 2D and 3D clouds:
+  statuses equal, every derivative column within 1e-10 relative L1.
+- Exactness on cubic fields at 262,144 particles: a property that holds at
+  any size, checked on every particle whose fit is cubic.
+- Deficient stencils: the values of lp_gfd on the same input, cubic columns
+  zero, status shifted by one."""
+import numpy as np
+import pytest
+
+from paper_2206_11998_amd import workloads as W
+from tests.gpu_util import radii, say
+from tests.test_oracle_gfd3 import _columns, _cubic, _cubic_eval
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2206_11998_amd import lp as _lp
+    _lp.lib()
+    return _lp
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _gpu(lp, cfg, x, r, fields):
+    dim = cfg["dim"]
+    ctx = lp.Context(cfg)
+    d, s = ctx.gfd3([_dev(x[:, a]) for a in range(dim)], _dev(r), [_dev(f) for f in fields])
+    torch.cuda.synchronize()
+    ctx.close()
+    return d.cpu().numpy(), s.cpu().numpy()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gfd3_matches_oracle(lp, oracle_lib, dim):
+    say("gfd3 parity", dim)
+    rng = np.random.default_rng(50 + dim)
+    cfg, st = W.uniform_box(dim, 40 if dim == 2 else 14, seed=3, periodic=False)
+    cfg = dict(cfg, box_lo=[-0.5] * dim, box_hi=[1.5] * dim)
+    x = st["x"]
+    r = radii(cfg, st)
+    fields = []
+    for _ in range(dim + 2):
+        g = rng.standard_normal(dim)
+        fields.append(1.0 + x @ g + np.sin(3.0 * x[:, 0] + 1.0) * np.cos(2.0 * x[:, 1]) + 0.3 * x[:, -1] ** 3)
+    got, gst = _gpu(lp, cfg, x, r, fields)
+    ref, rst, rs = oracle_lib.gfd3(cfg, x, r, fields)
+    assert rs == 0
+    assert np.array_equal(gst, rst), np.flatnonzero(gst != rst)[:10]
+    say("statuses", np.bincount(rst, minlength=4))
+    for f in range(len(fields)):
+        for c in range(ref.shape[1]):
+            den = np.abs(ref[f, c]).sum()
+            err = np.abs(got[f, c] - ref[f, c]).sum() / max(den, 1e-300)
+            assert err <= 1e-10, (f, c, err)
+
+
+def test_gfd3_cubic_exact_at_262k(lp):
+    """64^3 jittered lattice: the cubic fit reproduces a cubic field."""
+    say("gfd3 cubic exactness, 262144 particles")
+    rng = np.random.default_rng(7)
+    cfg, st = W.uniform_box(3, 64, seed=1, periodic=False)
+    x = st["x"]
+    r = radii(cfg, st)
+    n = len(x)
+    c0, g, H, T = _cubic(3, rng)
+    f, grad, hess = _cubic_eval(x, c0, g, H, T)
+    want = _columns(3, grad, hess, T, n)
+    got, status = _gpu(lp, cfg, x, r, [f])
+    ok = status == 0
+    say("statuses", np.bincount(status, minlength=4))
+    assert ok.mean() > 0.8
+    # A cubic coefficient carries r^3 (about 4e-5 here), so rounding of
+    # O(|f| cond eps) reaches it magnified by r^-3: tight for the symmetric
+    # stencils of particles whose ball lies in the box, looser for the
+    # one-sided ones at the faces.
+    inner = ok & np.all((x - r[:, None] > 0.0) & (x + r[:, None] < 1.0), axis=1)
+    scale = np.abs(want).max(axis=1)
+    err_in = np.abs(got[0][:, inner] - want[:, inner]).max(axis=1) / scale
+    err_all = np.abs(got[0][:, ok] - want[:, ok]).max(axis=1) / scale
+    say("max relative error: interior %.2e, all cubic fits %.2e" % (err_in.max(), err_all.max()))
+    assert np.all(err_in <= 1e-6), err_in
+    assert np.all(err_all <= 1e-4), err_all
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gfd3_deficient_falls_back_to_second_order(lp, oracle_lib, dim):
+    say("gfd3 fallback", dim)
+    rng = np.random.default_rng(60 + dim)
+    n = 14 if dim == 3 else 7
+    x = 0.5 + 0.08 * (rng.random((n, dim)) - 0.5)
+    r = np.full(n, 0.2)
+    cfg = W.base_config("sparse", dim, 2.2, [0.0] * dim, [1.0] * dim, [False] * dim)
+    fields = [1.0 + x @ rng.standard_normal(dim) + (x ** 2).sum(axis=1) for _ in range(2)]
+    got, gst = _gpu(lp, cfg, x, r, fields)
+    ctx = lp.Context(cfg)
+    d2, s2 = ctx.gfd([_dev(x[:, a]) for a in range(dim)], _dev(r), [_dev(f) for f in fields])
+    d2, s2 = d2.cpu().numpy(), s2.cpu().numpy()
+    ctx.close()
+    nu2 = d2.shape[1]
+    assert np.all(gst == 1 + s2)
+    assert np.all(got[:, nu2:] == 0.0)
+    ref, rst, _ = oracle_lib.gfd3(cfg, x, r, fields)
+    assert np.array_equal(gst, rst)
+    # the same least-squares problem, solved by QR here and by the normal
+    # equations in lp_gfd: equal to the parity bar, and both to the oracle
+    # (L1 error over n times the field's largest derivative: on these tiny,
+    # poorly conditioned clouds the exactly zero d_xy comes out as rounding
+    # noise amplified by 1/r^2 on both sides)
+    for f in range(len(fields)):
+        den = n * np.abs(ref[f]).max()
+        for c in range(nu2):
+            assert np.abs(got[f, c] - ref[f, c]).sum() / den <= 1e-10, (f, c)
+            assert np.abs(got[f, c] - d2[f, c]).sum() / den <= 1e-10, (f, c)
