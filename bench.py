@@ -39,6 +39,16 @@ def fit_flops(k_lw, dim=3):
     return 20 * k + 2 * k * n * n - 2.0 * n ** 3 / 3 + R * (4 * k * n - 2 * n * n) + R * n * n
 
 
+def gfd3_flops(k_lw, dim=3):
+    """Algorithmic flops of one particle's third-order least-squares fit
+    (lp_gfd3) over k_lw rows: row assembly 40k, Householder factorisation
+    2kn^2 - 2n^3/3 and R right-hand sides R(4kn - 2n^2) + Rn^2, n = 19 (3D) or
+    9 (2D) unknowns, R = 5 fields."""
+    n, R = (19, 5) if dim == 3 else (9, 4)
+    k = np.asarray(k_lw, dtype=np.float64)
+    return 40 * k + 2 * k * n * n - 2.0 * n ** 3 / 3 + R * (4 * k * n - 2 * n * n) + R * n * n
+
+
 def update_flops(dim=3):
     """Half-ball fits (2D fits of 8 rows, D unknowns, 3 right-hand sides) plus
     estimator, rates, blend and mover."""
@@ -88,6 +98,89 @@ def committed_traffic(kernel, precision):
     return v["read_bytes"] + v["written_bytes"]
 
 
+def gfd3_leg(lp, torch, cfg, st, log, no_cpu):
+    """lp_gfd3 (third-order derivatives of V, u, P) on the workload's particles:
+    the fit kernel timed by the library's stage events over 3 calls, its FP64
+    ALU roofline, and the oracle's third-order operator on the central
+    particles beside it (on that sample the GPU result is compared too)."""
+    n = st["V"].shape[0]
+    h = (st["m"] * st["V"]) ** (1.0 / 3.0)
+    r_np = cfg["kappa"] * h
+    fields_np = [st["V"], st["u"][:, 0], st["u"][:, 1], st["u"][:, 2], st["P"]]
+
+    def dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+    ctx = lp.Context(cfg)
+    x = [dev(st["x"][:, a]) for a in range(3)]
+    r = dev(r_np)
+    f = [dev(v) for v in fields_np]
+    ctx.gfd3(x, r, f)  # warm-up (workspace, tables)
+    torch.cuda.synchronize()
+    calls = 3
+    ctx.profile(True)
+    t1 = time.perf_counter()
+    for _ in range(calls):
+        deriv, status = ctx.gfd3(x, r, f)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t1) / calls
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    count, _, _ = ctx.neighbors(x, r)
+    k_lw = np.minimum(count.cpu().numpy(), 54)
+    flops = float(gfd3_flops(k_lw).sum())
+    fit_ms = prof["fit"][0] / max(prof["fit"][1], 1)
+    stat = np.bincount(status.cpu().numpy(), minlength=4)
+    achieved = flops / (fit_ms * 1e-3) / 1e12
+    res = {"particles": n, "fields": 5, "calls": calls, "ms_per_call": wall * 1e3,
+           "stages_ms_per_call": {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]},
+           "status_counts": {"cubic": int(stat[0]), "quadratic": int(stat[1]), "linear": int(stat[2]),
+                             "none": int(stat[3])},
+           "mean_stencil": float(k_lw.mean()),
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
+                        "frac": achieved / PEAK_ALU_TFLOPS, "traffic": None,
+                        "algorithmic_flops_per_launch": flops, "avg_launch_ms": fit_ms,
+                        "kernel": "k_gfd3 (third-order fits)"},
+           "cpu_baseline": None}
+    del deriv, status
+    log("gfd3: %.2f ms per call (fit kernel %.2f ms), %.3f TFLOP/s" % (wall * 1e3, fit_ms, achieved))
+    if not no_cpu:
+        try:
+            import oracle
+            # the particles of a central cube, about 200k of them, repeated
+            # until 3 s of CPU time have elapsed (at most 8 times)
+            xs = st["x"]
+            half = np.sort(np.abs(xs).max(axis=1))[min(200_000, n) - 1]
+            sel = np.flatnonzero(np.abs(xs).max(axis=1) <= half)
+            xs_s, r_s = xs[sel], r_np[sel]
+            f_s = [v[sel] for v in fields_np]
+            reps, cpu_total = 0, 0.0
+            while reps == 0 or (cpu_total < 3.0 and reps < 8):
+                t1 = time.perf_counter()
+                ref, rst, rs = oracle.gfd3(cfg, xs_s, r_s, f_s)
+                cpu_total += time.perf_counter() - t1
+                reps += 1
+            cpu_t = cpu_total / reps
+            got, gst = ctx.gfd3([dev(xs_s[:, a]) for a in range(3)], dev(r_s), [dev(v) for v in f_s])
+            got, gst = got.cpu().numpy(), gst.cpu().numpy()
+            worst = 0.0
+            for q in range(ref.shape[0]):
+                for c in range(ref.shape[1]):
+                    worst = max(worst, float(np.abs(got[q, c] - ref[q, c]).sum() / max(np.abs(ref[q, c]).sum(),
+                                                                                       1e-300)))
+            res["cpu_baseline"] = {"value": len(sel) / cpu_t, "unit": "particles/s", "cores": oracle.num_threads(),
+                                   "kind": "oracle",
+                                   "sample": "lp_gfd3 of the %d particles with |x|_inf <= %.4f (their neighbourhoods "
+                                             "limited to the sample), mean of %d calls" % (len(sel), half, reps)}
+            res["sample_parity"] = {"status_equal": bool(np.array_equal(gst, rst)),
+                                    "max_column_rel_l1": worst}
+            log("gfd3 oracle: %d particles in %.2fs; sample parity %s" % (len(sel), cpu_t, res["sample_parity"]))
+        except Exception as exc:
+            log("gfd3 oracle unavailable:", repr(exc))
+    ctx.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +205,8 @@ def main():
     ap.add_argument("--solve-block", type=int, default=None)
     ap.add_argument("--solve-mode", type=int, default=None, help="0 direct, 1 work queue, 2 persistent work queue")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--no-gfd3", action="store_true",
+                    help="skip the third-order derivative operator (lp_gfd3) on the same particles")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device copies of 1 GiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -359,6 +454,8 @@ def main():
         "tuning": res["tuning"],
         "l1_vs_oracle": l1,
     }
+    if not args.no_gfd3:
+        out["gfd3"] = gfd3_leg(lp, torch, cfg, st, log, args.no_cpu_baseline)
     for prec in precisions[1:]:
         r2 = results[prec]
         out[prec] = {"value": n * args.steps / r2["elapsed"], "ms_per_step": 1e3 * r2["elapsed"] / args.steps,

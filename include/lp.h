@@ -216,7 +216,8 @@ lp_status lp_set_time(struct lp_ctx *ctx, void *stream, double t);
  * and writes, per stage, the summed milliseconds ms[q] and the number of
  * timed launches count[q] (host arrays of LP_NSTAGES entries), then clears.
  * Stages: 0 radii/dt/ghosts, 1 cell ordering, 2 neighbour search (+ work
- * queue), 3 second-order fits (fast path), 4 half-ball fits + estimator +
+ * queue), 3 second-order fits (fast path; in lp_gfd and lp_gfd3 their fit
+ * kernels, fallback included), 4 half-ball fits + estimator +
  * update + mover, 5 FP64 pivoted-QR fallback, 6 whole step (also around each
  * graph replay of lp_run, whose inner stages are not timed), 7 estimator
  * network with the update it decides (LP_EST_MLP). */

@@ -873,6 +873,7 @@ static lp_status gfd_run(lp_ctx *c, void *stream, int64_t n, const double *x, co
     ENSURE(c, c->gfd_fields, sizeof(double) * nf * n);
     const double *xs[3] = {x, y, D == 3 ? z : y};
     const double *gx[3] = {nullptr, nullptr, nullptr};
+    stage_mark(c, st, 1, true);
     build_cells(c, st, xs, gx, (int)n, n);
     Sorted srt = sorted_view(c, false);
     ScatterArgs sa;
@@ -891,8 +892,12 @@ static lp_status gfd_run(lp_ctx *c, void *stream, int64_t n, const double *x, co
     launch_scatter(sa, (int)n, &c->sc->n_total, (int)n, (const uint32_t *)c->key.p, (const uint32_t *)c->slot.p, start,
                    srt.id, st);
     launch_coarsen((uint32_t *)c->tables.p, c->grid, D, &c->sc->n_total, st);
+    stage_mark(c, st, 1, false);
     int ldn = list_ldn(c);
+    stage_mark(c, st, 2, true);
     run_search(c, srt, n, (int)n, c->search_cap, st);
+    stage_mark(c, st, 2, false);
+    stage_mark(c, st, 3, true);
     if (order == 3) {
         launch_gfd3(srt, fs, nf, (const int *)c->nbr.p, ldn, (const int *)c->count.p, (int)n, c->dc, deriv, status,
                     st);
@@ -902,6 +907,7 @@ static lp_status gfd_run(lp_ctx *c, void *stream, int64_t n, const double *x, co
         launch_gfd_fallback(srt, fs, nf, (const int *)c->nbr.p, ldn, (const int *)c->count.p, (int)n, c->dc, c->sc,
                             (const int *)c->queue.p, (int)n, deriv, status, st);
     }
+    stage_mark(c, st, 3, false);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));

@@ -1598,26 +1598,44 @@ __device__ __forceinline__ void third_order_row(const double xi[3], double row[D
 template <int D>
 __device__ __forceinline__ int third_order_degree(int q) { return q < D ? 1 : (q < Dim<D>::NU ? 2 : 3); }
 
-// lane permutation of a double by DPP (both halves)
+// lane permutation of a double by DPP (both halves; every lane is written)
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// sum over the 64 lanes (all active), the result in every lane: within each
-// 16-lane row by DPP (lanes ^ 1, ^ 2, then the 8- and 16-lane mirrors), then
-// across the rows
+// DPP with a row mask: rows outside the mask receive 0
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_rows_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// the value of lane `lane` (all lanes active), as a wave-uniform value
+__device__ __forceinline__ double lane_f64(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the 64 lanes (all active) as a wave-uniform value, by DPP only:
+// within each 16-lane row (lanes ^ 1, ^ 2, then the 8- and 16-lane mirrors),
+// then row 1 += row 0 and row 3 += row 2 (broadcast of lane 15 of the row
+// before), then rows 2, 3 += lane 31; lane 63 holds (r3 + r2) + (r1 + r0).
 __device__ __forceinline__ double wave_sum_dpp(double v) {
     v += dpp_f64<0xB1>(v);
     v += dpp_f64<0x4E>(v);
     v += dpp_f64<0x141>(v);
     v += dpp_f64<0x140>(v);
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-    return v;
+    v += dpp_rows_f64<0x142, 0xA>(v);
+    v += dpp_rows_f64<0x143, 0xC>(v);
+    return lane_f64(v, 63);
 }
 
 // Pivoted Householder QR of the wave's rows a[N] (one row per lane; rows of
@@ -1654,7 +1672,7 @@ __device__ __forceinline__ double wave_qrp_lanes(double a[N], double b[NR], int 
                 perm[p] = perm[j];
                 perm[j] = u;
             }
-        const double x0 = __shfl(a[p], p);
+        const double x0 = lane_f64(a[p], p);
         const double sigma = wave_sum_dpp(l > p ? a[p] * a[p] : 0.0);
         const double normx = sqrt(x0 * x0 + sigma);
         if (normx == 0.0) continue;
@@ -1675,8 +1693,8 @@ __device__ __forceinline__ double wave_qrp_lanes(double a[N], double b[NR], int 
             }
         a[p] = l == p ? alpha : (l > p ? 0.0 : a[p]);
     }
-    const double r11 = fabs(__shfl(a[0], 0));
-    const double rnn = fabs(__shfl(a[N - 1], N - 1));
+    const double r11 = fabs(lane_f64(a[0], 0));
+    const double rnn = fabs(lane_f64(a[N - 1], N - 1));
 #pragma unroll
     for (int c = 0; c < NR; ++c) y[c] = 0.0;
     // lane p holds row p of R (a[j], j >= p) and of Q^T b
@@ -1687,7 +1705,7 @@ __device__ __forceinline__ double wave_qrp_lanes(double a[N], double b[NR], int 
         for (int c = 0; c < NR; ++c)
             if (c < nr) {
                 const double t = (l == p && d != 0.0) ? b[c] / d : 0.0;
-                const double yp = __shfl(t, p);
+                const double yp = lane_f64(t, p);
                 if (l == p) y[c] = yp;
                 if (l < p) b[c] -= a[p] * yp;
             }
@@ -1699,6 +1717,77 @@ __device__ __forceinline__ double wave_qrp_lanes(double a[N], double b[NR], int 
     return rnn == 0.0 ? INFINITY : r11 / rnn;
 }
 
+// The Lax-Wendroff stencil of for_lw_stencil, chosen by the whole wave: list
+// entries are taken 64 at a time, one per lane; per-octant ballots give the
+// octant counts and each entry's rank within its octant, and the members
+// taken are compacted into sel[] in list order.  Returns their number.  The
+// same members in the same order as for_lw_stencil.
+template <int D>
+__device__ __forceinline__ int wave_lw_select(const Sorted &srt, const DevCfg &cfg, const int *nbr, int ldn, int s,
+                                              int k, const double xi[3], int *sel) {
+    const int l = threadIdx.x & 63;
+    const unsigned long long below = (1ull << l) - 1ull;
+    const int cap = cfg.lw_cap;
+    auto entry = [&](int t, int &j, int &o) {
+        j = 0;
+        o = -1;
+        if (t < k) {
+            j = nb_at(nbr, ldn, s, t);
+            double dx[3];
+            displacement<D>(srt, cfg, j, xi, dx);
+            o = octant<D>(dx);
+        }
+    };
+    if (k <= cap) {
+        for (int t0 = 0; t0 < k; t0 += 64) {
+            if (t0 + l < k) sel[t0 + l] = nb_at(nbr, ldn, s, t0 + l);
+        }
+        return k;
+    }
+    // octant counts, then the round R* taken whole and rem of round R*
+    int cnt[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) cnt[q] = 0;
+    for (int t0 = 0; t0 < k; t0 += 64) {
+        int j, o;
+        entry(t0 + l, j, o);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) cnt[q] += __popcll(__ballot(o == q));
+    }
+    int R = 0, taken = 0;
+    for (;;) {
+        int next = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) next += cnt[q] < R + 1 ? cnt[q] : R + 1;
+        if (next > cap) break;
+        taken = next;
+        ++R;
+    }
+    const int rem = cap - taken;
+    int seen[8];  // entries of each octant in earlier chunks
+#pragma unroll
+    for (int q = 0; q < 8; ++q) seen[q] = 0;
+    int seenR = 0, m = 0;  // entries of round R in earlier chunks; members taken
+    for (int t0 = 0; t0 < k; t0 += 64) {
+        int j, o;
+        entry(t0 + l, j, o);
+        int rho = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const unsigned long long mq = __ballot(o == q);
+            if (o == q) rho = seen[q] + __popcll(mq & below);
+            seen[q] += __popcll(mq);
+        }
+        const unsigned long long onR = __ballot(o >= 0 && rho == R);
+        const bool take = o >= 0 && (rho < R || (rho == R && seenR + __popcll(onR & below) < rem));
+        seenR += __popcll(onR);
+        const unsigned long long mt = __ballot(take);
+        if (take) sel[m + __popcll(mt & below)] = j;
+        m += __popcll(mt);
+    }
+    return m;
+}
+
 // One wave per particle (blocks of one wave: the second-order fallback
 // synchronises the block), particles in a grid-stride loop.
 template <int D>
@@ -1706,7 +1795,6 @@ __global__ __launch_bounds__(64) void k_gfd3(Sorted srt, FieldPtrs fs, int nf, c
                                              const int *count, int n, DevCfg cfg, double *deriv, uint8_t *status) {
     constexpr int N3 = Dim3<D>::NU, NU = Dim<D>::NU, NS = Dim<D>::NS;
     __shared__ int sel[64];
-    __shared__ int m_sh;
     const int l = threadIdx.x & 63;
     for (int s = blockIdx.x; s < n; s += gridDim.x) {
         const int i = srt.id[s];
@@ -1717,13 +1805,8 @@ __global__ __launch_bounds__(64) void k_gfd3(Sorted srt, FieldPtrs fs, int nf, c
         double fi[5];
 #pragma unroll
         for (int f = 0; f < 5; ++f) fi[f] = f < nf ? fs.f[f][s] : 0.0;
-        if (l == 0) {
-            int m = 0;
-            for_lw_stencil<D>(srt, cfg, nbr, ldn, s, k, xi, [&](int j, const double dx[3]) { sel[m++] = j; });
-            m_sh = m;
-        }
+        const int m = wave_lw_select<D>(srt, cfg, nbr, ldn, s, k, xi, sel);
         __syncthreads();
-        const int m = m_sh;
         double row[N3], b[5];
 #pragma unroll
         for (int q = 0; q < N3; ++q) row[q] = 0.0;
