@@ -138,7 +138,7 @@ def gfd3_leg(lp, torch, cfg, st, log, no_cpu):
                              "none": int(stat[3])},
            "mean_stencil": float(k_lw.mean()),
            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
-                        "frac": achieved / PEAK_ALU_TFLOPS, "traffic": None,
+                        "frac": achieved / PEAK_ALU_TFLOPS, "traffic": committed_traffic("gfd3", "mixed"),
                         "algorithmic_flops_per_launch": flops, "avg_launch_ms": fit_ms,
                         "kernel": "k_gfd3 (third-order fits)"},
            "cpu_baseline": None}

@@ -74,20 +74,6 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// bounding box of the positions (wave-reduced, then one atomic per wave)
-__device__ __forceinline__ void bbox_reduce(double *const x[3], int D, int i, int n, DevScalars *sc) {
-    for (int a = 0; a < D; ++a) {
-        double lo = INFINITY, hi = -INFINITY;
-        if (i < n) { lo = x[a][i]; hi = lo; }
-        lo = wave_min(lo);
-        hi = wave_max(hi);
-        if ((threadIdx.x & 63) == 0 && lo <= hi) {
-            atomicMin(&sc->xlo[a], dbl_key(lo));
-            atomicMax(&sc->xhi[a], dbl_key(hi));
-        }
-    }
-}
-
 // Per-block minima of (h/c, r, -r, x_a, -x_a) written to part[block * 9 + q];
 // k_prep_final folds the block results (order-free min, so exact).
 #define PREP_Q 9
@@ -177,22 +163,54 @@ __global__ void k_dt(DevCfg cfg, DevScalars *sc, int clip) {
 }
 
 // min / max of given radii (for searches on caller-provided radii)
-__global__ void k_rminmax(const double *r, double *x0, double *x1, double *x2, int D, int n, DevScalars *sc) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double lo = INFINITY, hi = 0.0;
-    if (i < n) { lo = r[i]; hi = r[i]; }
-    lo = wave_min(lo);
-    hi = wave_max(hi);
-    if ((threadIdx.x & 63) == 0) {
-        if (lo < INFINITY) atomicMin(&sc->rmin, dbl_bits(lo));
-        if (hi > 0.0) atomicMax(&sc->rmax, dbl_bits(hi));
+// Range of the radii and bounding box of the positions: a grid-stride pass per
+// thread, then per wave and per block (LDS), then one atomic per block and
+// quantity (min and max are order-free, so the result is exact).
+__global__ __launch_bounds__(LP_BLOCK) void k_rminmax(const double *r, double *x0, double *x1, double *x2, int D,
+                                                      int n, DevScalars *sc) {
+    constexpr int NW = LP_BLOCK / 64;
+    __shared__ double red[8][NW];
+    const double *const xs[3] = {x0, x1, x2};
+    // v[0] = min r, v[1] = max r, v[2 + a] = min x_a, v[5 + a] = max x_a
+    double v[8] = {INFINITY, 0.0, INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double ri = r[i];
+        v[0] = fmin(v[0], ri);
+        v[1] = fmax(v[1], ri);
+        for (int a = 0; a < D; ++a) {
+            const double xa = xs[a][i];
+            v[2 + a] = fmin(v[2 + a], xa);
+            v[5 + a] = fmax(v[5 + a], xa);
+        }
     }
-    double *const xs[3] = {x0, x1, x2};
-    bbox_reduce(xs, D, i, n, sc);
+    const int w = threadIdx.x >> 6;
+    for (int q = 0; q < 8; ++q) {
+        const bool is_min = q == 0 || (q >= 2 && q < 5);
+        const double t = is_min ? wave_min(v[q]) : wave_max(v[q]);
+        if ((threadIdx.x & 63) == 0) red[q][w] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b[8];
+        for (int q = 0; q < 8; ++q) {
+            const bool is_min = q == 0 || (q >= 2 && q < 5);
+            b[q] = red[q][0];
+            for (int k = 1; k < NW; ++k) b[q] = is_min ? fmin(b[q], red[q][k]) : fmax(b[q], red[q][k]);
+        }
+        if (b[0] < INFINITY) atomicMin(&sc->rmin, dbl_bits(b[0]));
+        if (b[1] > 0.0) atomicMax(&sc->rmax, dbl_bits(b[1]));
+        for (int a = 0; a < D; ++a)
+            if (b[2 + a] <= b[5 + a]) {
+                atomicMin(&sc->xlo[a], dbl_key(b[2 + a]));
+                atomicMax(&sc->xhi[a], dbl_key(b[5 + a]));
+            }
+    }
 }
 
 void launch_rminmax(const double *r, const double *const x[3], int D, int n, DevScalars *sc, hipStream_t st) {
-    hipLaunchKernelGGL(k_rminmax, dim3(blocks_for(n)), dim3(LP_BLOCK), 0, st, r, (double *)x[0], (double *)x[1],
+    unsigned blocks = blocks_for(n);
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_rminmax, dim3(blocks), dim3(LP_BLOCK), 0, st, r, (double *)x[0], (double *)x[1],
                        (double *)x[2], D, n, sc);
     CHECK_LAUNCH();
 }
