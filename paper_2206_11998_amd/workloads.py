@@ -19,7 +19,7 @@ Workloads (γ = 1.4 everywhere):
 * ``sedov3d``   -- 3D Sedov-type blast: jittered 2:1:1 lattice on
   [0,2]x[0,1]², ρ = 1, p = 1e-5, energy 1 deposited as internal energy in the
   27 lattice particles around the centre, periodic, κ = 2.1.
-* ``yee_vortex`` -- 2D Yee vortex (Sec. 3): an isentropic vortex of strength
+* ``yee_vortex`` -- 2D Yee vortex (Sec. 2.3): an isentropic vortex of strength
   β = 5 in the free stream (u, v, ρ, p) = (1, 0, 1, 1), on an almost hexagonal
   lattice of the periodic square [-5, 5]², κ = 2.5; ``yee_exact`` is its
   exact solution, the initial state convected with the free stream.

@@ -1,4 +1,4 @@
-"""Yee vortex on the GPU (Sec. 3): FP64 parity with the oracle and the
+"""Yee vortex on the GPU (Sec. 2.3): FP64 parity with the oracle and the
 convergence of the Lax-Wendroff part of the update against the exact
 solution."""
 import math

@@ -1,4 +1,4 @@
-"""The Yee vortex (Sec. 3): an isentropic vortex carried by the free stream
+"""The Yee vortex (Sec. 2.3): an isentropic vortex carried by the free stream
 (1, 0), an exact smooth solution of the Euler equations.
 
 - The exact solution is pinned by its radial momentum balance
