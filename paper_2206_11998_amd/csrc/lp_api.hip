@@ -30,7 +30,7 @@ struct lp_ctx {
     int device = 0;
     std::string err;
     // workspace
-    Buf h, r, gcnt, scan_tmp, ghosts, key, slot, tables, sorted, srec, sid, nbr, count, queue, partials, consout,
+    Buf h, r, gcnt, scan_tmp, ghosts, key, slot, tables, sorted, srec, srecf, sid, nbr, count, queue, partials, consout,
         gfd_fields, hitd2, hitj, tflags, tlo, thi, prep_part, ovfq, der, lwst, wq, rq, rkeep,
         mfeat, mrates, mphi, mflag,                          // network-estimator staging
         theta, adam_m, adam_v, mgrad, mpart, mlosspart, mscal; // network parameters and training
@@ -273,7 +273,7 @@ extern "C" lp_status lp_destroy(lp_ctx *c) {
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     Buf *bufs[] = {&c->h, &c->r, &c->gcnt, &c->scan_tmp, &c->ghosts, &c->key, &c->slot, &c->tables, &c->sorted,
-                   &c->srec, &c->sid, &c->nbr, &c->count, &c->queue, &c->partials, &c->consout, &c->gfd_fields,
+                   &c->srec, &c->srecf, &c->sid, &c->nbr, &c->count, &c->queue, &c->partials, &c->consout, &c->gfd_fields,
                    &c->hitd2, &c->hitj, &c->tflags, &c->tlo, &c->thi, &c->prep_part, &c->ovfq, &c->der, &c->lwst,
                    &c->wq, &c->rq, &c->rkeep, &c->mfeat, &c->mrates, &c->mphi, &c->mflag, &c->theta, &c->adam_m, &c->adam_v,
                    &c->mgrad, &c->mpart, &c->mlosspart, &c->mscal};
@@ -418,6 +418,7 @@ static lp_status ensure_capacity(lp_ctx *c, int64_t n_real, int64_t n_total, boo
     ENSURE(c, c->tables, sizeof(uint32_t) * table_words(c));
     ENSURE(c, c->sorted, sizeof(double) * (state ? 10 : 4) * nt);
     if (state) ENSURE(c, c->srec, sizeof(double) * LP_REC * nt);
+    if (state && c->dc.precision == LP_MIXED) ENSURE(c, c->srecf, (size_t)LP_RECF_BYTES * nt);
     ENSURE(c, c->sid, sizeof(int) * nt);
     ENSURE(c, c->nbr, sizeof(int) * (size_t)c->dc.max_nb * nt);
     ENSURE(c, c->count, sizeof(int) * nt);
@@ -477,6 +478,8 @@ static Sorted sorted_view(lp_ctx *c, bool state) {
         s.V = b + 4 * n; s.u[0] = b + 5 * n; s.u[1] = b + 6 * n; s.u[2] = b + 7 * n; s.P = b + 8 * n; s.h = b + 9 * n;
     }
     if (state && c->srec.p && c->srec.bytes >= sizeof(double) * LP_REC * n) s.rec = (double *)c->srec.p;
+    if (state && c->dc.precision == LP_MIXED && c->srecf.p && c->srecf.bytes >= (size_t)LP_RECF_BYTES * n)
+        s.recf = (float *)c->srecf.p;
     s.id = (int *)c->sid.p;
     return s;
 }
@@ -619,6 +622,8 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
     if (D == 2) { sa.src[2] = soa.x[0]; sa.src[7] = soa.u[0]; }
     // gather records: x_0..x_{D-1}, V, u_0..u_{D-1}, P (value indices above)
     sa.rec = srt.rec;
+    sa.recf = srt.recf;
+    sa.dim = D;
     {
         const int r3[LP_REC] = {0, 1, 2, 4, 5, 6, 7, 8}, r2[LP_REC] = {0, 1, 4, 5, 6, 8, -1, -1};
         for (int q = 0; q < LP_REC; ++q) sa.rec_src[q] = D == 3 ? r3[q] : r2[q];

@@ -474,8 +474,7 @@ __global__ void k_scatter(ScatterArgs a, int n_real, const int *n_total_dev, con
         vals[d] = v;
         a.dst[d][pos] = v;
     }
-    if (a.rec) {
-        // the particle's gather record: one 64-byte write
+    if (a.rec || a.recf) {
         double e[LP_REC];
 #pragma unroll
         for (int q = 0; q < LP_REC; ++q) {
@@ -483,9 +482,27 @@ __global__ void k_scatter(ScatterArgs a, int n_real, const int *n_total_dev, con
             for (int d = 0; d < 12; ++d)
                 if (d == a.rec_src[q]) e[q] = vals[d];
         }
-        double2 *r = reinterpret_cast<double2 *>(a.rec + (int64_t)LP_REC * pos);
+        if (a.rec) {
+            // the particle's gather record: one 64-byte write
+            double2 *r = reinterpret_cast<double2 *>(a.rec + (int64_t)LP_REC * pos);
 #pragma unroll
-        for (int q = 0; q < LP_REC / 2; ++q) r[q] = make_double2(e[2 * q], e[2 * q + 1]);
+            for (int q = 0; q < LP_REC / 2; ++q) r[q] = make_double2(e[2 * q], e[2 * q + 1]);
+        }
+        if (a.recf) {
+            // the FP32-field record: positions, then the fields rounded to FP32
+            uint4 *r = reinterpret_cast<uint4 *>(reinterpret_cast<char *>(a.recf) + (int64_t)LP_RECF_BYTES * pos);
+            auto lo = [](double v) { return (unsigned)__double2loint(v); };
+            auto hi = [](double v) { return (unsigned)__double2hiint(v); };
+            auto fb = [](double v) { return __float_as_uint((float)v); };
+            r[0] = make_uint4(lo(e[0]), hi(e[0]), lo(e[1]), hi(e[1]));
+            if (a.dim == 3) {
+                r[1] = make_uint4(lo(e[2]), hi(e[2]), fb(e[3]), fb(e[4]));
+                r[2] = make_uint4(fb(e[5]), fb(e[6]), fb(e[7]), 0u);
+            } else {
+                r[1] = make_uint4(fb(e[2]), fb(e[3]), fb(e[4]), fb(e[5]));
+                r[2] = make_uint4(0u, 0u, 0u, 0u);
+            }
+        }
     }
 }
 

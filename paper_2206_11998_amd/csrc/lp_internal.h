@@ -81,6 +81,7 @@ struct Ghosts {
 struct Sorted {
     double *x[3], *V, *u[3], *P, *h, *r;
     double *rec;                    // packed gather records (LP_REC doubles each), or NULL
+    float *recf;                    // packed FP32-field gather records (LP_RECF_BYTES each), or NULL
     int *id;                        // original id (ghosts: n + g)
 };
 
@@ -89,6 +90,13 @@ struct Sorted {
 // The fits gather a neighbour's position and fields from it in four 16-byte
 // loads of one line, instead of eight loads from eight arrays.
 #define LP_REC 8
+
+// The FP32 kernels' record, 48 B (three 16-byte loads): the positions in FP64
+// (the stencil's octants and the displacements need them exactly), then V,
+// u_0 .. u_{D-1}, P rounded to FP32 (round to nearest, as those kernels round
+// the FP64 values themselves).  3D: x0 x1 | x2 V u0 | u1 u2 P -;
+// 2D: x0 x1 | V u0 u1 P.
+#define LP_RECF_BYTES 48
 
 template <int D>
 __device__ __forceinline__ void rec_pos(const double *rec, int j, double p[3]) {
@@ -126,7 +134,9 @@ struct ScatterArgs {
     const double *gsrc[12];         // ghosts (ids >= n_real); may be NULL
     double *dst[12];
     double *rec;                    // packed gather records (LP_REC doubles), or NULL
+    float *recf;                    // FP32-field gather records (LP_RECF_BYTES each), or NULL
     int rec_src[LP_REC];            // value index of each record entry (-1: zero)
+    int dim;                        // layout of the FP32-field record
 };
 
 // ---------------------------------------------------------------------------

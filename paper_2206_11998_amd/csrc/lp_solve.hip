@@ -128,12 +128,66 @@ __device__ __forceinline__ void for_lw_stencil(const Sorted &srt, const DevCfg &
     }
 }
 
+// Raw gather record of a neighbour as loaded: four 16-byte words of the FP64
+// record, or the three (2D: two) of the FP32-field record.
+template <bool F32REC> struct RecRaw;
+template <> struct RecRaw<false> { double2 q[4]; };
+template <> struct RecRaw<true> { uint4 q[3]; };
+
+template <int D, bool F32REC>
+__device__ __forceinline__ void load_rec(const Sorted &srt, int j, RecRaw<F32REC> &r) {
+    if constexpr (F32REC) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(srt.recf) +
+                                                         (int64_t)LP_RECF_BYTES * j);
+        r.q[0] = p[0];
+        r.q[1] = p[1];
+        if constexpr (D == 3) r.q[2] = p[2];
+    } else {
+        const double2 *p = reinterpret_cast<const double2 *>(srt.rec + (int64_t)LP_REC * j);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) r.q[q] = p[q];
+    }
+}
+
+// position p and fields V, u_0 .. u_{D-1}, P of a loaded record
+template <int D, bool F32REC>
+__device__ __forceinline__ void unpack_rec(const RecRaw<F32REC> &r, double p[3], double f[D + 2]) {
+    if constexpr (F32REC) {
+        p[0] = __hiloint2double((int)r.q[0].y, (int)r.q[0].x);
+        p[1] = __hiloint2double((int)r.q[0].w, (int)r.q[0].z);
+        if constexpr (D == 3) {
+            p[2] = __hiloint2double((int)r.q[1].y, (int)r.q[1].x);
+            f[0] = __uint_as_float(r.q[1].z);
+            f[1] = __uint_as_float(r.q[1].w);
+            f[2] = __uint_as_float(r.q[2].x);
+            f[3] = __uint_as_float(r.q[2].y);
+            f[4] = __uint_as_float(r.q[2].z);
+        } else {
+            p[2] = 0.0;
+            f[0] = __uint_as_float(r.q[1].x);
+            f[1] = __uint_as_float(r.q[1].y);
+            f[2] = __uint_as_float(r.q[1].z);
+            f[3] = __uint_as_float(r.q[1].w);
+        }
+    } else {
+        p[0] = r.q[0].x;
+        p[1] = r.q[0].y;
+        if constexpr (D == 3) {
+            p[2] = r.q[1].x;
+            f[0] = r.q[1].y; f[1] = r.q[2].x; f[2] = r.q[2].y; f[3] = r.q[3].x; f[4] = r.q[3].y;
+        } else {
+            p[2] = 0.0;
+            f[0] = r.q[1].x; f[1] = r.q[1].y; f[2] = r.q[2].x; f[3] = r.q[2].y;
+        }
+    }
+}
+
 // The same stencil walk over the gather records, two entries deep: while
 // entry t is processed, the record of entry t + 1 and the index of entry
 // t + 2 are in flight (every load is unconditional, with the index clamped
 // to the list, so that no load result passes through a branch).  body(j, dx,
 // f) gets the member's V, u_0..u_{D-1}, P.  Needs srt.rec.
-template <int D, typename F>
+template <int D, bool F32REC = false, typename F>
 __device__ __forceinline__ void for_lw_stencil_rec(const Sorted &srt, const DevCfg &cfg, const int *nbr, int ldn,
                                                    int s, int k, const double xi[3], F &&body) {
     const int cap = cfg.lw_cap;
@@ -164,24 +218,18 @@ __device__ __forceinline__ void for_lw_stencil_rec(const Sorted &srt, const DevC
     if (k <= 0) return;
     unsigned long long s03 = 0, s47 = 0;
     int takenR = 0;
-    auto rec_of = [&](int j, double2 r[4]) {
-        const double2 *p = reinterpret_cast<const double2 *>(srt.rec + (int64_t)LP_REC * j);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) r[q] = p[q];
-    };
     int jc = nb_at(nbr, ldn, s, 0);                  // entry t
     int jn = nb_at(nbr, ldn, s, k > 1 ? 1 : 0);      // entry t + 1
-    double2 rc[4];
-    rec_of(jc, rc);
+    RecRaw<F32REC> rc;
+    load_rec<D, F32REC>(srt, jc, rc);
     for (int t = 0; t < k; ++t) {
         const int j = jc;
-        double2 cur[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) cur[q] = rc[q];
+        const RecRaw<F32REC> cur = rc;
         jc = jn;
-        rec_of(jc, rc);                                   // record of entry t + 1
+        load_rec<D, F32REC>(srt, jc, rc);                 // record of entry t + 1
         jn = nb_at(nbr, ldn, s, t + 2 < k ? t + 2 : k - 1);  // index of entry t + 2
-        const double p[3] = {cur[0].x, cur[0].y, D == 3 ? cur[1].x : 0.0};
+        double p[3], f[D + 2];
+        unpack_rec<D, F32REC>(cur, p, f);
         double dx[3];
         disp_of<D>(cfg, p, xi, dx);
         if (k > cap) {
@@ -192,12 +240,6 @@ __device__ __forceinline__ void for_lw_stencil_rec(const Sorted &srt, const DevC
             bool take = rho < Rstar || (rho == Rstar && takenR < rem);
             if (rho == Rstar && take) ++takenR;
             if (!take) continue;
-        }
-        double f[D + 2];
-        if constexpr (D == 3) {
-            f[0] = cur[1].y; f[1] = cur[2].x; f[2] = cur[2].y; f[3] = cur[3].x; f[4] = cur[3].y;
-        } else {
-            f[0] = cur[1].x; f[1] = cur[1].y; f[2] = cur[2].x; f[3] = cur[2].y;
         }
         body(j, dx, f);
     }
@@ -647,39 +689,41 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
             }
             if (right) ++nr; else ++nl;
         };
-        if (srt.rec && k > 0) {
-            // the walk two entries deep over the gather records: the next
-            // record and the index after it are in flight while an entry is
-            // examined (loads unconditional, index clamped to the list); the
-            // FP64 variant spills a few registers for it and is still faster
+        // the walk two entries deep over the gather records: the next record
+        // and the index after it are in flight while an entry is examined
+        // (loads unconditional, index clamped to the list); the FP64 variant
+        // spills a few registers for it and is still faster.  The FP32 update
+        // rounds every field it reads to FP32 first, so it reads the
+        // FP32-field record.
+        auto walk = [&](auto f32rec) {
+            constexpr bool F32REC = decltype(f32rec)::value;
             int jc = nb_at(nbr, ldn, s, 0), jn = nb_at(nbr, ldn, s, k > 1 ? 1 : 0);
-            double2 rc[4];
-            auto rec_of = [&](int j, double2 r[4]) {
-                const double2 *pr = reinterpret_cast<const double2 *>(srt.rec + (int64_t)LP_REC * j);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) r[q] = pr[q];
-            };
-            rec_of(jc, rc);
+            RecRaw<F32REC> rc;
+            load_rec<D, F32REC>(srt, jc, rc);
             for (int t = 0; t < k && (nl < ucap || nr < ucap); ++t) {
-                double2 cur[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) cur[q] = rc[q];
+                const RecRaw<F32REC> cur = rc;
                 jc = jn;
-                rec_of(jc, rc);
+                load_rec<D, F32REC>(srt, jc, rc);
                 jn = nb_at(nbr, ldn, s, t + 2 < k ? t + 2 : k - 1);
-                const double pj[3] = {cur[0].x, cur[0].y, D == 3 ? cur[1].x : 0.0};
+                double pj[3], fr[NF];
+                unpack_rec<D, F32REC>(cur, pj, fr);
                 double dx[3];
                 disp_of<D>(cfg, pj, xi, dx);
                 const bool right = dx[a] > 0.0, left = dx[a] < 0.0;
                 if (!((right && nr < ucap) || (left && nl < ucap))) continue;
-                double fr[NF];
-                if constexpr (D == 3) {
-                    fr[0] = cur[1].y; fr[1] = cur[2].x; fr[2] = cur[2].y; fr[3] = cur[3].x; fr[4] = cur[3].y;
-                } else {
-                    fr[0] = cur[1].x; fr[1] = cur[1].y; fr[2] = cur[2].x; fr[3] = cur[2].y;
-                }
                 visit(dx, fr);
             }
+        };
+        bool walked = false;
+        if constexpr (std::is_same<T, float>::value) {
+            if (srt.recf && k > 0) {
+                walk(std::true_type{});
+                walked = true;
+            }
+        }
+        if (walked) {
+        } else if (srt.rec && k > 0) {
+            walk(std::false_type{});
         } else {
             int jn = k > 0 ? nb_at(nbr, ldn, s, 0) : 0;  // next index loaded one iteration ahead
             for (int t = 0; t < k && (nl < ucap || nr < ucap); ++t) {
@@ -961,7 +1005,14 @@ __device__ __forceinline__ void lw_fit_one(const SolveArgs &a, int s, int t) {
         }
         ++m;
     };
-    if (srt.rec) {
+    // the FP32 fit rounds every field it reads to FP32 first, so it reads the
+    // FP32-field record (three loads instead of four); its refinement walks
+    // the FP64 record
+    constexpr bool F32REC = std::is_same<T, float>::value;
+    if (F32REC && srt.recf) {
+        for_lw_stencil_rec<D, F32REC>(srt, cfg, a.nbr, a.ldn, s, k, xi,
+                                      [&](int, const double dx[3], const double fr[NF]) { member(dx, fr); });
+    } else if (srt.rec) {
         // one record in flight while a member is accumulated
         for_lw_stencil_rec<D>(srt, cfg, a.nbr, a.ldn, s, k, xi,
                               [&](int, const double dx[3], const double fr[NF]) { member(dx, fr); });
