@@ -151,7 +151,12 @@ lp_status lp_neighbors(struct lp_ctx *ctx, void *stream, int64_t n, const double
  * (3D: x, y, z, xx, yy, zz, xy, xz, yz) or 5 (2D: x, y, xx, yy, xy).
  * status: device, n bytes: 0 = second-order fit, 1 = rank deficient (linear
  * fit, second derivatives 0), 2 = fewer than dim usable neighbours (all 0).
- * Always solved in FP64. */
+ * x, y, z, r: device arrays of n doubles (z ignored in 2D); all arrays are
+ * the caller's and are only read (deriv, status only written).  Always solved
+ * in FP64.  Synchronises twice (to size the cell grid, and at the end).
+ * Returns LP_E_ARG for n outside 1..2^30, nf outside 1..5 or a null pointer,
+ * LP_E_CAPACITY when a neighbour count exceeds max_nb (the fits then use the
+ * first max_nb neighbours), LP_E_NOMEM when the workspace cannot grow. */
 lp_status lp_gfd(struct lp_ctx *ctx, void *stream, int64_t n, const double *x, const double *y,
                  const double *z, const double *r, int32_t nf, const double *const *f, double *deriv,
                  uint8_t *status);
@@ -169,7 +174,7 @@ lp_status lp_gfd(struct lp_ctx *ctx, void *stream, int64_t n, const double *x, c
  * unknowns or |R11|/|Rnn| above cond_max, and the values are lp_gfd's
  * second-order fit of the same stencil (third derivatives 0); 2 = that fit is
  * deficient too (linear fit); 3 = fewer than dim usable neighbours (all 0).
- * Always FP64; one wave per particle. */
+ * Always FP64; one wave per particle.  Synchronisation and errors as lp_gfd. */
 lp_status lp_gfd3(struct lp_ctx *ctx, void *stream, int64_t n, const double *x, const double *y,
                   const double *z, const double *r, int32_t nf, const double *const *f, double *deriv,
                   uint8_t *status);

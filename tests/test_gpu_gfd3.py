@@ -142,3 +142,23 @@ def test_gfd3_periodic_matches_oracle(lp, oracle_lib, dim):
             den = np.abs(ref[f, c]).sum()
             err = np.abs(got[f, c] - ref[f, c]).sum() / max(den, 1e-300)
             assert err <= 1e-10, (f, c, err)
+
+
+def test_gfd3_long_lists_match_oracle(lp, oracle_lib):
+    """kappa 3.2: well over 64 neighbours, so the wave picks the stencil from
+    the list in several chunks of 64 and cuts the octant rounds at lw_cap."""
+    say("gfd3 long lists")
+    cfg, st = W.uniform_box(3, 12, seed=11, periodic=True)
+    cfg = dict(cfg, kappa=3.2, max_nb=256)
+    x = st["x"]
+    r = radii(cfg, st)
+    fields = [np.sin(2.0 * np.pi * x[:, 0]) + np.cos(2.0 * np.pi * x[:, 1]) * np.sin(2.0 * np.pi * x[:, 2])]
+    count, _, st_nb = oracle_lib.neighbors(cfg, x, r, max_nb=256)
+    assert st_nb == 0 and count.min() > 64
+    got, gst = _gpu(lp, cfg, x, r, fields)
+    ref, rst, rs = oracle_lib.gfd3(cfg, x, r, fields)
+    assert rs == 0 and np.array_equal(gst, rst)
+    for c in range(ref.shape[1]):
+        den = np.abs(ref[0, c]).sum()
+        err = np.abs(got[0, c] - ref[0, c]).sum() / max(den, 1e-300)
+        assert err <= 1e-10, (c, err)
