@@ -893,6 +893,17 @@ static lp_status gfd_run(lp_ctx *c, void *stream, int64_t n, const double *x, co
         sa.dst[4 + q] = dq;
         fs[q] = dq;
     }
+    if (order == 2 && nf <= D + 2) {
+        // gather records for the fit: positions, then the caller's fields
+        ENSURE(c, c->srec, sizeof(double) * LP_REC * n);
+        srt.rec = (double *)c->srec.p;
+        sa.rec = srt.rec;
+        const int r3[LP_REC] = {0, 1, 2, 4, 5, 6, 7, 8}, r2[LP_REC] = {0, 1, 4, 5, 6, 7, -1, -1};
+        for (int q = 0; q < LP_REC; ++q) {
+            const int v = D == 3 ? r3[q] : r2[q];
+            sa.rec_src[q] = v < 4 + nf ? v : -1;
+        }
+    }
     const uint32_t *start = (const uint32_t *)c->tables.p + c->grid.off[c->grid.L_hi];
     launch_scatter(sa, (int)n, &c->sc->n_total, (int)n, (const uint32_t *)c->key.p, (const uint32_t *)c->slot.p, start,
                    srt.id, st);

@@ -1545,7 +1545,7 @@ __global__ __launch_bounds__(LP_BLOCK) void k_gfd(Sorted srt, FieldPtrs fs, int 
 #pragma unroll
     for (int q = 0; q < 5 * NU; ++q) B[q] = 0;
     int m = 0;
-    for_lw_stencil<D>(srt, cfg, nbr, ldn, s, k, xi, [&](int j, const double dx[3]) {
+    auto member = [&](const double dx[3], const double *fj) {
         double x[3];
 #pragma unroll
         for (int a = 0; a < D; ++a) x[a] = dx[a] * inv_r;
@@ -1558,12 +1558,25 @@ __global__ __launch_bounds__(LP_BLOCK) void k_gfd(Sorted srt, FieldPtrs fs, int 
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
             if (f >= nf) break;
-            double b = fs.f[f][j] - fi[f];
+            double b = fj[f] - fi[f];
 #pragma unroll
             for (int pp = 0; pp < NU; ++pp) B[f * NU + pp] += row[pp] * b;
         }
         ++m;
-    });
+    };
+    if (srt.rec) {
+        // the caller's fields in the gather records (nf <= D + 2), walked one
+        // entry ahead as in the step's fit
+        for_lw_stencil_rec<D>(srt, cfg, nbr, ldn, s, k, xi,
+                              [&](int, const double dx[3], const double fr[D + 2]) { member(dx, fr); });
+    } else {
+        for_lw_stencil<D>(srt, cfg, nbr, ldn, s, k, xi, [&](int j, const double dx[3]) {
+            double fj[5];
+#pragma unroll
+            for (int f = 0; f < 5; ++f) fj[f] = f < nf ? fs.f[f][j] : 0.0;
+            member(dx, fj);
+        });
+    }
     double inv[NU];
     bool good = m >= NU && cholesky<NU, double>(G, inv);
     if (good) good = cond_estimate<NU, double>(G, inv) <= cfg.cond_fb;
