@@ -45,6 +45,7 @@ struct lp_ctx {
     int search_group = 8;
     int search_cap = 0;             // LDS list slots per particle of the search: 0 = automatic
     int search_lcap = 0;            // automatic choice for steps (0: the kernel's maximum)
+    int gfd_lcap = 0;               // the same for lp_gfd / lp_gfd3, from the last such call's longest list
     int64_t cap_real = 0, cap_total = 0, cap_ghost = 0;
     bool run_done = false;
     DevGrid grid;
@@ -911,7 +912,9 @@ static lp_status gfd_run(lp_ctx *c, void *stream, int64_t n, const double *x, co
     stage_mark(c, st, 1, false);
     int ldn = list_ldn(c);
     stage_mark(c, st, 2, true);
-    run_search(c, srt, n, (int)n, c->search_cap, st);
+    // list slots in LDS sized from the last call's longest list (a longer
+    // list takes the overflow kernel, so the lists are the same either way)
+    run_search(c, srt, n, (int)n, c->search_cap ? c->search_cap : c->gfd_lcap, st);
     stage_mark(c, st, 2, false);
     stage_mark(c, st, 3, true);
     if (order == 3) {
@@ -927,6 +930,11 @@ static lp_status gfd_run(lp_ctx *c, void *stream, int64_t n, const double *x, co
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
+    {
+        const int mc = c->sc_host->max_count;
+        const int lc = mc > 0 ? (mc + 8 + 15) / 16 * 16 : 0;
+        c->gfd_lcap = lc <= 128 ? lc : 0;
+    }
     if (c->sc_host->max_count > c->dc.max_nb) return fail(c, LP_E_CAPACITY, "neighbour count %d exceeds max_nb %d",
                                                           c->sc_host->max_count, c->dc.max_nb);
     return LP_OK;

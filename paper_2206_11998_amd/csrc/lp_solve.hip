@@ -1587,7 +1587,9 @@ __global__ __launch_bounds__(LP_BLOCK) void k_gfd(Sorted srt, FieldPtrs fs, int 
     }
     chol_solve<NU, 5, double, double>(G, inv, B);
     const int nu = NU;
-    for (int f = 0; f < nf; ++f) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+        if (f >= nf) break;  // constant indices keep the arrays in registers
         for (int a = 0; a < D; ++a) deriv[((int64_t)f * nu + a) * n + i] = B[f * NU + a] * inv_r;
         for (int q = 0; q < NS; ++q) deriv[((int64_t)f * nu + D + q) * n + i] = B[f * NU + D + q] * inv_r * inv_r;
     }
@@ -1613,7 +1615,9 @@ __global__ __launch_bounds__(64) void k_gfd_fallback(Sorted srt, FieldPtrs fs, i
         int st = lw_fit_wave<D, 5>(srt, cfg, nbr, ldn, s, k, xi, srt.r[s], fi,
                                    [&](int j, int f) { return f < nf ? fs.f[f][j] : 0.0; }, grad, hess, sel);
         if ((threadIdx.x & 63) == 0) {
-            for (int f = 0; f < nf; ++f) {
+#pragma unroll
+            for (int f = 0; f < 5; ++f) {
+                if (f >= nf) break;  // constant indices keep the arrays in registers
                 for (int a = 0; a < D; ++a) deriv[((int64_t)f * NU + a) * n + i] = grad[f][a];
                 for (int q = 0; q < NS; ++q) deriv[((int64_t)f * NU + D + q) * n + i] = hess[f][q];
             }
@@ -1899,7 +1903,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             if (col >= 0) {
                 const int deg = third_order_degree<D>(col);
                 const double sp = deg == 1 ? r : (deg == 2 ? r * r : r * r * r);
-                for (int f = 0; f < nf; ++f) deriv[((int64_t)f * N3 + col) * n + i] = y[f] / sp;
+#pragma unroll
+                for (int f = 0; f < 5; ++f)
+                    if (f < nf) deriv[((int64_t)f * N3 + col) * n + i] = y[f] / sp;
             }
             if (l == 0) status[i] = 0;
         } else {
@@ -1908,7 +1914,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                                               [&](int j, int f) { return f < nf ? fs.f[f][j] : 0.0; }, grad, hess,
                                               sel);
             if (l == 0) {
-                for (int f = 0; f < nf; ++f) {
+#pragma unroll
+                for (int f = 0; f < 5; ++f) {
+                    if (f >= nf) break;  // constant indices keep the arrays in registers
                     for (int a = 0; a < D; ++a) deriv[((int64_t)f * N3 + a) * n + i] = grad[f][a];
                     for (int q = 0; q < NS; ++q) deriv[((int64_t)f * N3 + D + q) * n + i] = hess[f][q];
                     for (int q = NU; q < N3; ++q) deriv[((int64_t)f * N3 + q) * n + i] = 0.0;
