@@ -78,6 +78,12 @@ def lib():
         L.lpo_gfd.argtypes = [cp, C.c_int64, dp, dp, dp, dp, C.c_int32, C.POINTER(dp), dp, u8p]
         L.lpo_gfd3.restype = C.c_int
         L.lpo_gfd3.argtypes = [cp, C.c_int64, dp, dp, dp, dp, C.c_int32, C.POINTER(dp), dp, u8p]
+        L.lpo_outflow.restype = C.c_int
+        L.lpo_outflow.argtypes = [cp, C.c_int64, C.POINTER(dp), C.c_int, C.POINTER(dp), C.c_uint32, C.c_uint32,
+                                  C.POINTER(C.c_int64)]
+        L.lpo_reservoir_inflow.restype = C.c_int
+        L.lpo_reservoir_inflow.argtypes = [cp, C.c_int64, C.POINTER(dp), dp, C.c_int, C.c_int, C.c_double,
+                                           C.c_double, C.c_double, dp]
         L.lpo_timestep.restype = C.c_double
         L.lpo_timestep.argtypes = [cp, C.c_int64, dp, dp, dp]
         L.lpo_step_subset.restype = C.c_int
@@ -252,6 +258,39 @@ def gfd3(cfg: dict, x: np.ndarray, r: np.ndarray, fields):
     st = lib().lpo_gfd3(C.byref(c), n, _dp(X[0]), _dp(X[1]), _dp(X[2]), _dp(r), len(fs), arr, _dp(deriv),
                         status.ctypes.data_as(C.POINTER(C.c_uint8)))
     return deriv, status, st
+
+
+def outflow(cfg: dict, state: dict, lo_mask: int, hi_mask: int) -> dict:
+    """Delete the particles past the outflow faces; returns the kept state
+    (every per-particle array, order kept)."""
+    c = make_cfg(cfg)
+    d = c.dim
+    n = state["V"].shape[0]
+    cols = [np.ascontiguousarray(state["x"][:, a], dtype=np.float64).copy() for a in range(d)]
+    cols += [np.ascontiguousarray(state["u"][:, a], dtype=np.float64).copy() for a in range(d)]
+    cols += [np.ascontiguousarray(state[k], dtype=np.float64).copy() for k in ("V", "P", "m")]
+    arr = (C.POINTER(C.c_double) * len(cols))(*[_dp(a) for a in cols])
+    xs = (C.POINTER(C.c_double) * d)(*[_dp(cols[a]) for a in range(d)])
+    kept = C.c_int64(0)
+    st = lib().lpo_outflow(C.byref(c), n, arr, len(cols), xs, lo_mask, hi_mask, C.byref(kept))
+    assert st == 0
+    k = kept.value
+    return {"x": np.stack([cols[a][:k] for a in range(d)], axis=1),
+            "u": np.stack([cols[d + a][:k] for a in range(d)], axis=1),
+            "V": cols[2 * d][:k], "P": cols[2 * d + 1][:k], "m": cols[2 * d + 2][:k]}
+
+
+def reservoir_inflow(cfg: dict, state: dict, axis: int, side: int, width: float, p_res: float, rho_res: float):
+    """(P_in, rho_in, u_in, particles averaged) of the reservoir inflow condition."""
+    c = make_cfg(cfg)
+    d = c.dim
+    n = state["V"].shape[0]
+    cols = [np.ascontiguousarray(state["x"][:, a], dtype=np.float64) for a in range(d)]
+    xs = (C.POINTER(C.c_double) * d)(*[_dp(a) for a in cols])
+    P = np.ascontiguousarray(state["P"], dtype=np.float64)
+    out = np.zeros(4)
+    st = lib().lpo_reservoir_inflow(C.byref(c), n, xs, _dp(P), axis, side, width, p_res, rho_res, _dp(out))
+    return out, st
 
 
 def timestep(cfg: dict, state: dict) -> float:

@@ -941,6 +941,74 @@ int lpo_gfd3(const lpo_cfg *c, int64_t n, const double *x, const double *y, cons
 }
 
 /* ------------------------------------------------------------------------- */
+/* Open boundaries (Sec. 2.2, step 1: outflow by deleting particles, inflow   */
+/* by generating them; Sec. 3.2: the state of particles entering from a       */
+/* reservoir).                                                                */
+/* ------------------------------------------------------------------------- */
+
+/* Delete, in place, every particle past an outflow face: x_a < lo_a for a
+ * bit a of lo_mask, x_a >= hi_a for a bit a of hi_mask.  The others keep their
+ * order.  arrays[0..narr-1] are the per-particle FP64 arrays to compact. */
+int lpo_outflow(const lpo_cfg *c, int64_t n, double *const *arrays, int narr, const double *const *x,
+                uint32_t lo_mask, uint32_t hi_mask, int64_t *n_kept)
+{
+    int D = c->dim;
+    int64_t k = 0;
+    char *keep = (char *)malloc((size_t)(n > 0 ? n : 1));
+    if (!keep) return LPO_E_NOMEM;
+    for (int64_t i = 0; i < n; ++i) {
+        int gone = 0;
+        for (int a = 0; a < D; ++a) {
+            if (((lo_mask >> a) & 1u) && x[a][i] < c->lo[a]) gone = 1;
+            if (((hi_mask >> a) & 1u) && x[a][i] >= c->hi[a]) gone = 1;
+        }
+        keep[i] = (char)!gone;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        if (!keep[i]) continue;
+        for (int q = 0; q < narr; ++q) arrays[q][k] = arrays[q][i];
+        ++k;
+    }
+    free(keep);
+    *n_kept = k;
+    return LPO_OK;
+}
+
+/* State of the particles entering through the face of axis `axis` (side 0:
+ * box_lo, 1: box_hi) from a reservoir at rest with pressure p_res and
+ * density rho_res:
+ *   P_in   = mean pressure of the particles with distance 0 <= d < width
+ *            from the face inside the box (p_res when there are none);
+ *   rho_in from equal entropy, P_res / rho_res^gamma = P_in / rho_in^gamma;
+ *   u_in   from equal enthalpy with the reservoir at rest,
+ *            u_in^2 / 2 + c_in^2 / (gamma - 1) = c_res^2 / (gamma - 1),
+ *            c^2 = gamma P / rho (0 when the right side is negative).
+ * out[0] = P_in, out[1] = rho_in, out[2] = u_in, out[3] = particles averaged. */
+int lpo_reservoir_inflow(const lpo_cfg *c, int64_t n, const double *const *x, const double *P, int axis, int side,
+                         double width, double p_res, double rho_res, double *out)
+{
+    if (axis < 0 || axis >= c->dim || side < 0 || side > 1 || !(width > 0.0) || !(p_res > 0.0) ||
+        !(rho_res > 0.0))
+        return LPO_E_ARG;
+    double sum = 0.0;
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        double d = side == 0 ? x[axis][i] - c->lo[axis] : c->hi[axis] - x[axis][i];
+        if (d >= 0.0 && d < width) { sum += P[i]; ++cnt; }
+    }
+    double g = c->gamma;
+    double p_in = cnt > 0 ? sum / (double)cnt : p_res;
+    double rho_in = rho_res * pow(p_in / p_res, 1.0 / g);
+    double c2_res = g * p_res / rho_res, c2_in = g * p_in / rho_in;
+    double u2 = 2.0 * (c2_res - c2_in) / (g - 1.0);
+    out[0] = p_in;
+    out[1] = rho_in;
+    out[2] = u2 > 0.0 ? sqrt(u2) : 0.0;
+    out[3] = (double)cnt;
+    return LPO_OK;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Time step (Sec. 2.2, steps 1-6).                                           */
 /* ------------------------------------------------------------------------- */
 

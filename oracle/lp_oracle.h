@@ -56,6 +56,12 @@ int lpo_gfd(const lpo_cfg *c, int64_t n, const double *x, const double *y, const
  * 1 = quadratic, 2 = linear, 3 = none. */
 int lpo_gfd3(const lpo_cfg *c, int64_t n, const double *x, const double *y, const double *z,
              const double *r, int32_t nf, const double *const *f, double *deriv, uint8_t *status);
+/* Open boundaries: outflow deletion (in place, order kept) and the state of
+ * particles entering from a reservoir at rest (out: P_in, rho_in, u_in, count). */
+int lpo_outflow(const lpo_cfg *c, int64_t n, double *const *arrays, int narr, const double *const *x,
+                uint32_t lo_mask, uint32_t hi_mask, int64_t *n_kept);
+int lpo_reservoir_inflow(const lpo_cfg *c, int64_t n, const double *const *x, const double *P, int axis, int side,
+                         double width, double p_res, double rho_res, double *out);
 double lpo_timestep(const lpo_cfg *c, int64_t n, const double *V, const double *P, const double *m);
 int lpo_step_subset(const lpo_cfg *c, int64_t n, const double *x, const double *y, const double *z,
                     const double *V, const double *u, const double *v, const double *w,
