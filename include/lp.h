@@ -205,6 +205,33 @@ lp_status lp_run(struct lp_ctx *ctx, void *stream, const lp_particles *p, int32_
  * e = P V / (gamma - 1).  out is a host array of 5 doubles.  Synchronises. */
 lp_status lp_conservation(struct lp_ctx *ctx, void *stream, const lp_particles *p, double *out);
 
+/* Open boundary, outflow (Sec. 2.2, step 1: outflow boundaries delete
+ * particles): remove, in place, every particle with x_a < box_lo[a] for a bit
+ * a of lo_mask or x_a >= box_hi[a] for a bit a of hi_mask; the others keep
+ * their order.  Every array of p is compacted: x, u, V, P, m (the caller's
+ * mass array, constant for the step, is written here) and phi, flags when not
+ * NULL.  *n_kept (host) receives the new count; entries past it are left as
+ * they were.  Synchronises once.  Call between steps, with a p->n of the new
+ * count afterwards. */
+lp_status lp_outflow(struct lp_ctx *ctx, void *stream, const lp_particles *p, uint32_t lo_mask, uint32_t hi_mask,
+                     int64_t *n_kept);
+
+/* Reservoir inflow state (Sec. 3.2): the state of particles entering through
+ * the face of axis `axis` (side 0: box_lo, 1: box_hi) from a reservoir at rest
+ * with pressure p_res and density rho_res.
+ *   P_in:   mean pressure of the particles at distance 0 <= d < width inside
+ *           the face (p_res when there are none);
+ *   rho_in: equal entropy, p_res / rho_res^gamma = P_in / rho_in^gamma;
+ *   u_in:   equal enthalpy with the reservoir at rest,
+ *           u_in^2 / 2 + c_in^2 / (gamma - 1) = c_res^2 / (gamma - 1), c^2 = gamma P / rho
+ *           (0 when the layer's pressure is at or above the reservoir's).
+ * out (host, 4 doubles): P_in, rho_in, u_in (speed into the domain, normal to
+ * the face), particles averaged.  LP_E_ARG for a bad face, width <= 0 or a
+ * non-positive reservoir state.  Synchronises once.  Placing the particles
+ * that enter (and their mass) is the caller's. */
+lp_status lp_reservoir_inflow(struct lp_ctx *ctx, void *stream, const lp_particles *p, int32_t axis, int32_t side,
+                              double width, double p_res, double rho_res, double *out);
+
 /* Synchronise and report kernel-side errors of all work since the last
  * check (LP_E_CAPACITY / LP_E_NUMERIC), then clear them. */
 lp_status lp_check(struct lp_ctx *ctx, void *stream);

@@ -965,6 +965,72 @@ extern "C" lp_status lp_conservation(lp_ctx *c, void *stream, const lp_particles
     return LP_OK;
 }
 
+extern "C" lp_status lp_outflow(lp_ctx *c, void *stream, const lp_particles *p, uint32_t lo_mask,
+                                uint32_t hi_mask, int64_t *n_kept) {
+    if (!c || !n_kept) return LP_E_ARG;
+    lp_status s = check_particles(c, p);
+    if (s != LP_OK) return s;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = p->n;
+    const int D = c->dc.D;
+    ENSURE(c, c->gcnt, sizeof(uint32_t) * (n + 1));
+    ENSURE(c, c->scan_tmp, sizeof(uint32_t) * scan_tmp_words((uint64_t)n));
+    ENSURE(c, c->gfd_fields, sizeof(double) * n);
+    uint32_t *pos = (uint32_t *)c->gcnt.p;
+    launch_out_keep(soa_of(p), c->dc, lo_mask, hi_mask, pos, st);
+    launch_scan_u32(pos, (uint64_t)n, (uint32_t *)c->scan_tmp.p, nullptr, st);
+    uint32_t kept = 0;
+    HIPCHK(c, hipMemcpyAsync(&kept, pos + n, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if ((int64_t)kept < n) {
+        // each array through the temporary, then back into the caller's array
+        double *tmp = (double *)c->gfd_fields.p;
+        double *arrs[9];
+        int na = 0;
+        for (int a = 0; a < D; ++a) arrs[na++] = p->x[a];
+        for (int a = 0; a < D; ++a) arrs[na++] = p->u[a];
+        arrs[na++] = p->V;
+        arrs[na++] = p->P;
+        arrs[na++] = const_cast<double *>(p->m);  // the caller's array: constant for the step, compacted here
+        for (int q = 0; q < na; ++q) {
+            launch_out_gather<double>(arrs[q], tmp, pos, (int)n, st);
+            HIPCHK(c, hipMemcpyAsync(arrs[q], tmp, sizeof(double) * kept, hipMemcpyDeviceToDevice, st));
+        }
+        if (p->phi) {
+            launch_out_gather<float>(p->phi, (float *)tmp, pos, (int)n, st);
+            HIPCHK(c, hipMemcpyAsync(p->phi, tmp, sizeof(float) * kept, hipMemcpyDeviceToDevice, st));
+        }
+        if (p->flags) {
+            launch_out_gather<uint8_t>(p->flags, (uint8_t *)tmp, pos, (int)n, st);
+            HIPCHK(c, hipMemcpyAsync(p->flags, tmp, kept, hipMemcpyDeviceToDevice, st));
+        }
+        HIPCHK(c, hipGetLastError());
+    }
+    *n_kept = kept;
+    return LP_OK;
+}
+
+extern "C" lp_status lp_reservoir_inflow(lp_ctx *c, void *stream, const lp_particles *p, int32_t axis, int32_t side,
+                                         double width, double p_res, double rho_res, double *out) {
+    if (!c || !out) return LP_E_ARG;
+    lp_status s = check_particles(c, p);
+    if (s != LP_OK) return s;
+    if (axis < 0 || axis >= c->dc.D || side < 0 || side > 1 || !(width > 0.0) || !(p_res > 0.0) || !(rho_res > 0.0))
+        return fail(c, LP_E_ARG, "lp_reservoir_inflow: bad face, width or reservoir state");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int nblocks = 256;
+    ENSURE(c, c->partials, sizeof(double) * 2 * nblocks);
+    ENSURE(c, c->consout, sizeof(double) * 5);
+    const double face = side == 0 ? c->dc.lo[axis] : c->dc.hi[axis];
+    launch_reservoir(p->x[axis], p->P, (int)p->n, side, face, width, p_res, rho_res, c->dc.gamma,
+                     (double *)c->partials.p, nblocks, (double *)c->consout.p, st);
+    HIPCHK(c, hipMemcpyAsync(out, c->consout.p, sizeof(double) * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    return LP_OK;
+}
+
 extern "C" lp_status lp_check(lp_ctx *c, void *stream) {
     if (!c) return LP_E_ARG;
     HIPCHK(c, hipSetDevice(c->device));

@@ -596,3 +596,108 @@ void launch_conservation(const Soa &p, const DevCfg &cfg, double *partials, int 
     hipLaunchKernelGGL(k_cons_final, dim3(1), dim3(64), 0, st, partials, nblocks, out);
     CHECK_LAUNCH();
 }
+
+// ---------------------------------------------------------------------------
+// Open boundaries (Sec. 2.2, step 1: outflow by deleting particles; Sec. 3.2:
+// the state of particles entering from a reservoir).
+// ---------------------------------------------------------------------------
+// keep[i] = 1 for a particle inside every outflow face (x_a >= lo_a for a bit a
+// of lo_mask, x_a < hi_a for a bit a of hi_mask), else 0
+__global__ void k_out_keep(Soa p, DevCfg cfg, uint32_t lo_mask, uint32_t hi_mask, uint32_t *keep) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n) return;
+    bool gone = false;
+    for (int a = 0; a < cfg.D; ++a) {
+        const double xa = p.x[a][i];
+        if (((lo_mask >> a) & 1u) && xa < cfg.lo[a]) gone = true;
+        if (((hi_mask >> a) & 1u) && xa >= cfg.hi[a]) gone = true;
+    }
+    keep[i] = gone ? 0u : 1u;
+}
+
+// after the exclusive scan of keep (pos[n] = particles kept): the kept
+// particles of src, in order, to dst
+template <typename T>
+__global__ void k_out_gather(const T *src, T *dst, const uint32_t *pos, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t q = pos[i];
+    if (pos[i + 1] > q) dst[q] = src[i];
+}
+
+void launch_out_keep(const Soa &p, const DevCfg &cfg, uint32_t lo_mask, uint32_t hi_mask, uint32_t *keep,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_out_keep, dim3(blocks_for(p.n)), dim3(LP_BLOCK), 0, st, p, cfg, lo_mask, hi_mask, keep);
+    CHECK_LAUNCH();
+}
+
+template <typename T>
+void launch_out_gather(const T *src, T *dst, const uint32_t *pos, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_out_gather<T>, dim3(blocks_for(n)), dim3(LP_BLOCK), 0, st, src, dst, pos, n);
+    CHECK_LAUNCH();
+}
+template void launch_out_gather<double>(const double *, double *, const uint32_t *, int, hipStream_t);
+template void launch_out_gather<float>(const float *, float *, const uint32_t *, int, hipStream_t);
+template void launch_out_gather<uint8_t>(const uint8_t *, uint8_t *, const uint32_t *, int, hipStream_t);
+
+// Inlet layer of the face (side 0: lo, 1: hi): per block the sum of P and the
+// count of the particles at distance 0 <= d < width inside the face, in a
+// fixed order (grid-stride per thread, then the wave, then the block's waves)
+__global__ __launch_bounds__(LP_BLOCK) void k_res_partial(const double *xa, const double *P, int n, int side,
+                                                         double face, double width, double *part) {
+    __shared__ double red[2][LP_BLOCK / 64];
+    double sum = 0.0, cnt = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double d = side == 0 ? xa[i] - face : face - xa[i];
+        if (d >= 0.0 && d < width) {
+            sum += P[i];
+            cnt += 1.0;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        sum += __shfl_xor(sum, o);
+        cnt += __shfl_xor(cnt, o);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = sum;
+        red[1][w] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int k = 0; k < LP_BLOCK / 64; ++k) {
+            a += red[0][k];
+            b += red[1][k];
+        }
+        part[2 * blockIdx.x] = a;
+        part[2 * blockIdx.x + 1] = b;
+    }
+}
+
+// the reservoir inflow state from the block sums: the layer's mean pressure
+// (the reservoir's with an empty layer), the density of equal entropy and
+// the speed of equal enthalpy with the reservoir at rest
+__global__ void k_res_final(const double *part, int nblocks, double p_res, double rho_res, double gamma,
+                            double *out) {
+    double sum = 0.0, cnt = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+        sum += part[2 * b];
+        cnt += part[2 * b + 1];
+    }
+    const double p_in = cnt > 0.0 ? sum / cnt : p_res;
+    const double rho_in = rho_res * pow(p_in / p_res, 1.0 / gamma);
+    const double c2_res = gamma * p_res / rho_res, c2_in = gamma * p_in / rho_in;
+    const double u2 = 2.0 * (c2_res - c2_in) / (gamma - 1.0);
+    out[0] = p_in;
+    out[1] = rho_in;
+    out[2] = u2 > 0.0 ? sqrt(u2) : 0.0;
+    out[3] = cnt;
+}
+
+void launch_reservoir(const double *xa, const double *P, int n, int side, double face, double width, double p_res,
+                      double rho_res, double gamma, double *part, int nblocks, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_res_partial, dim3(nblocks), dim3(LP_BLOCK), 0, st, xa, P, n, side, face, width, part);
+    hipLaunchKernelGGL(k_res_final, dim3(1), dim3(1), 0, st, part, nblocks, p_res, rho_res, gamma, out);
+    CHECK_LAUNCH();
+}

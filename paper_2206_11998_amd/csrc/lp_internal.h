@@ -236,6 +236,12 @@ void launch_gfd_fallback(const Sorted &s, const double *const *fs, int nf, const
                          int queue_cap, double *deriv, uint8_t *status, hipStream_t st);
 void launch_gfd3(const Sorted &s, const double *const *fs, int nf, const int *nbr, int ldn, const int *count,
                  int n, const DevCfg &cfg, double *deriv, uint8_t *status, hipStream_t st);
+void launch_out_keep(const Soa &p, const DevCfg &cfg, uint32_t lo_mask, uint32_t hi_mask, uint32_t *keep,
+                     hipStream_t st);
+template <typename T>
+void launch_out_gather(const T *src, T *dst, const uint32_t *pos, int n, hipStream_t st);
+void launch_reservoir(const double *xa, const double *P, int n, int side, double face, double width, double p_res,
+                      double rho_res, double gamma, double *part, int nblocks, double *out, hipStream_t st);
 void launch_conservation(const Soa &p, const DevCfg &cfg, double *partials, int nblocks, double *out,
                          hipStream_t st);
 

@@ -19,7 +19,8 @@ FP64, MIXED = 0, 1
 EST_PLAIN, EST_INJECTED, EST_MLP = 0, 1, 2
 FLAG_LIMITED, FLAG_DEGENERATE, FLAG_VACUUM, FLAG_SUBSTITUTED, FLAG_FALLBACK, FLAG_NUMERIC = 1, 2, 4, 8, 16, 32
 
-EXPORTS = ["lp_config_default", "lp_create", "lp_destroy", "lp_neighbors", "lp_gfd", "lp_gfd3", "lp_step", "lp_run",
+EXPORTS = ["lp_config_default", "lp_create", "lp_destroy", "lp_neighbors", "lp_gfd", "lp_gfd3", "lp_outflow",
+           "lp_reservoir_inflow", "lp_step", "lp_run",
            "lp_conservation", "lp_check", "lp_get_info", "lp_set_time", "lp_profile", "lp_profile_read",
            "lp_set_tuning", "lp_get_tuning", "lp_autotune", "lp_train_cfg_default", "lp_features", "lp_mlp_init",
            "lp_mlp_set", "lp_mlp_get", "lp_mlp_forward", "lp_mlp_grad", "lp_mlp_train", "lp_status_str",
@@ -94,6 +95,11 @@ def lib():
         L.lp_neighbors.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
         L.lp_gfd.restype = i32
         L.lp_gfd.argtypes = [vp, vp, i64, vp, vp, vp, vp, i32, C.POINTER(vp), vp, vp]
+        L.lp_outflow.restype = i32
+        L.lp_outflow.argtypes = [vp, vp, C.c_void_p, C.c_uint32, C.c_uint32, C.POINTER(C.c_int64)]
+        L.lp_reservoir_inflow.restype = i32
+        L.lp_reservoir_inflow.argtypes = [vp, vp, C.c_void_p, i32, i32, C.c_double, C.c_double, C.c_double,
+                                          C.POINTER(C.c_double)]
         L.lp_gfd3.restype = i32
         L.lp_gfd3.argtypes = [vp, vp, i64, vp, vp, vp, vp, i32, C.POINTER(vp), vp, vp]
         L.lp_step.restype = i32
@@ -298,6 +304,24 @@ class Context:
                            _ptr(deriv), _ptr(status))
         self._raise(st)
         return deriv, status
+
+    def outflow(self, s: dict, lo_mask: int, hi_mask: int, stream=None) -> int:
+        """Delete the particles past the outflow faces, in place; returns the
+        number kept (the first that many entries of every array)."""
+        p = self._particles(s)
+        kept = C.c_int64(0)
+        self._raise(lib().lp_outflow(self._h, _stream_ptr(stream), C.byref(p), int(lo_mask), int(hi_mask),
+                                     C.byref(kept)))
+        return kept.value
+
+    def reservoir_inflow(self, s: dict, axis: int, side: int, width: float, p_res: float, rho_res: float,
+                         stream=None):
+        """(P_in, rho_in, u_in, particles averaged) of the reservoir inflow condition."""
+        p = self._particles(s)
+        out = (C.c_double * 4)()
+        self._raise(lib().lp_reservoir_inflow(self._h, _stream_ptr(stream), C.byref(p), int(axis), int(side),
+                                              float(width), float(p_res), float(rho_res), out))
+        return np.array(out[:])
 
     def step(self, s: dict, dt: float = 0.0, stream=None):
         p = self._particles(s)
