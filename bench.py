@@ -181,6 +181,64 @@ def gfd3_leg(lp, torch, cfg, st, log, no_cpu):
     return res
 
 
+def openbc_leg(lp, torch, cfg, st, log, no_cpu):
+    """lp_outflow on the workload's particles with the x-high face moved to 0
+    (an outflow face through the middle of the cloud; about half the
+    particles leave), and lp_reservoir_inflow at that face.  The
+    compaction's algorithmic HBM bytes: every per-particle array read once
+    (x, u, V, P, m: 72 B; phi, flags: 5 B) and the kept part written once."""
+    n = st["V"].shape[0]
+    ocfg = dict(cfg, box_hi=[0.0] + list(cfg["box_hi"][1:]))
+    ctx = lp.Context(ocfg)
+    src = lp.state_to_device(st)
+    dev = {k: ([t.clone() for t in v] if isinstance(v, list) else v.clone()) for k, v in src.items()}
+    ctx.outflow(dev, 0, 1)  # warm-up (workspace)
+    times, kept = [], 0
+    for _ in range(5):
+        for k, v in src.items():
+            if isinstance(v, list):
+                for a, t in enumerate(v):
+                    dev[k][a].copy_(t)
+            else:
+                dev[k].copy_(v)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        kept = ctx.outflow(dev, 0, 1)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
+    per = 72.0 + 5.0
+    alg = per * n + per * kept
+    achieved = alg / (ms * 1e-3) / 1e9
+    res = {"particles": n, "kept": int(kept), "outflow_ms": ms,
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": achieved / PEAK_HBM_GBS, "traffic": None, "algorithmic_bytes_per_call": alg,
+                        "note": "one call: keep flags, scan, one gather and one copy back per array, one sync"}}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    inflow = ctx.reservoir_inflow(src, 0, 1, 0.02, 2.0, 1.5)  # the layer -0.02 < x <= 0 of the moved face
+    e1.record()
+    torch.cuda.synchronize()
+    res["reservoir_inflow"] = {"ms": e0.elapsed_time(e1), "p_in": float(inflow[0]), "rho_in": float(inflow[1]),
+                               "u_in": float(inflow[2]), "averaged": int(inflow[3])}
+    log("outflow: %d of %d kept in %.3f ms (%.0f GB/s algorithmic)" % (kept, n, ms, achieved))
+    if not no_cpu:
+        try:
+            import oracle
+            t1 = time.perf_counter()
+            ref = oracle.outflow(ocfg, st, 0, 1)
+            cpu_t = time.perf_counter() - t1
+            res["cpu_baseline"] = {"value": n / cpu_t, "unit": "particles/s", "cores": 1, "kind": "oracle",
+                                   "sample": "lp_outflow of all %d particles, one call (single-threaded loop)" % n}
+            res["parity"] = {"kept_equal": len(ref["V"]) == kept}
+        except Exception as exc:
+            log("open-boundary oracle unavailable:", repr(exc))
+    ctx.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -205,6 +263,8 @@ def main():
     ap.add_argument("--solve-block", type=int, default=None)
     ap.add_argument("--solve-mode", type=int, default=None, help="0 direct, 1 work queue, 2 persistent work queue")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--no-openbc", action="store_true",
+                    help="skip the open-boundary calls (lp_outflow, lp_reservoir_inflow) on the same particles")
     ap.add_argument("--no-gfd3", action="store_true",
                     help="skip the third-order derivative operator (lp_gfd3) on the same particles")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -456,6 +516,8 @@ def main():
     }
     if not args.no_gfd3:
         out["gfd3"] = gfd3_leg(lp, torch, cfg, st, log, args.no_cpu_baseline)
+    if not args.no_openbc:
+        out["open_boundary"] = openbc_leg(lp, torch, cfg, st, log, args.no_cpu_baseline)
     for prec in precisions[1:]:
         r2 = results[prec]
         out[prec] = {"value": n * args.steps / r2["elapsed"], "ms_per_step": 1e3 * r2["elapsed"] / args.steps,
