@@ -81,6 +81,10 @@ def lib():
         L.lpo_outflow.restype = C.c_int
         L.lpo_outflow.argtypes = [cp, C.c_int64, C.POINTER(dp), C.c_int, C.POINTER(dp), C.c_uint32, C.c_uint32,
                                   C.POINTER(C.c_int64)]
+        L.lpo_inflow_layer.restype = C.c_int
+        L.lpo_inflow_layer.argtypes = [cp, C.c_int64, C.c_int64, C.POINTER(dp), C.POINTER(dp), dp, dp, dp, C.c_int,
+                                       C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                                       C.POINTER(C.c_int64)]
         L.lpo_reservoir_inflow.restype = C.c_int
         L.lpo_reservoir_inflow.argtypes = [cp, C.c_int64, C.POINTER(dp), dp, C.c_int, C.c_int, C.c_double,
                                            C.c_double, C.c_double, dp]
@@ -291,6 +295,25 @@ def reservoir_inflow(cfg: dict, state: dict, axis: int, side: int, width: float,
     out = np.zeros(4)
     st = lib().lpo_reservoir_inflow(C.byref(c), n, xs, _dp(P), axis, side, width, p_res, rho_res, _dp(out))
     return out, st
+
+
+def inflow_layer(cfg: dict, n: int, cap: int, axis: int, side: int, spacing: float, depth: float, rho: float,
+                 p_in: float, u_n: float):
+    """The particles of the inflow layer (x, u, V, P, m of entries n .. n_new - 1)
+    and the status."""
+    c = make_cfg(cfg)
+    d = c.dim
+    xs = [np.zeros(cap) for _ in range(d)]
+    us = [np.zeros(cap) for _ in range(d)]
+    V, P, m = np.zeros(cap), np.zeros(cap), np.zeros(cap)
+    xp = (C.POINTER(C.c_double) * d)(*[_dp(a) for a in xs])
+    up = (C.POINTER(C.c_double) * d)(*[_dp(a) for a in us])
+    nn = C.c_int64(0)
+    st = lib().lpo_inflow_layer(C.byref(c), n, cap, xp, up, _dp(V), _dp(P), _dp(m), axis, side, spacing, depth, rho,
+                                p_in, u_n, C.byref(nn))
+    k = nn.value
+    return {"x": np.stack([a[n:k] for a in xs], axis=1), "u": np.stack([a[n:k] for a in us], axis=1),
+            "V": V[n:k], "P": P[n:k], "m": m[n:k]}, k, st
 
 
 def timestep(cfg: dict, state: dict) -> float:

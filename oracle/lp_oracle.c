@@ -1008,6 +1008,50 @@ int lpo_reservoir_inflow(const lpo_cfg *c, int64_t n, const double *const *x, co
     return LPO_OK;
 }
 
+/* Inflow layer (Sec. 2.2, step 1: inflow boundaries generate particles):
+ * particles on the square lattice of the given spacing over the face of axis
+ * `axis` (side 0: lo, 1: hi), at distance `depth` inside it.  The other axes
+ * b take box_lo[b] + (k + 1/2) spacing, k = 0 .. floor(extent_b / spacing + 1e-9) - 1
+ * (a cell short of a whole one by rounding alone still counts),
+ * the first other axis fastest.  State: V = 1/rho, pressure P, velocity u_n
+ * along the inward normal, mass rho spacing^dim.  Writes entries n .. n +
+ * count - 1 of the arrays (x[D], u[D], V, P, m) when n + count <= cap. */
+int lpo_inflow_layer(const lpo_cfg *c, int64_t n, int64_t cap, double *const *x, double *const *u, double *V,
+                     double *P, double *m, int axis, int side, double spacing, double depth, double rho,
+                     double p_in, double u_n, int64_t *n_new)
+{
+    int D = c->dim;
+    if (axis < 0 || axis >= D || side < 0 || side > 1 || !(spacing > 0.0) || !(depth >= 0.0) || !(rho > 0.0))
+        return LPO_E_ARG;
+    int other[2] = {0, 0}, no = 0;
+    for (int b = 0; b < D; ++b)
+        if (b != axis) other[no++] = b;
+    int64_t cnt[2] = {1, 1};
+    for (int q = 0; q < no; ++q) cnt[q] = (int64_t)floor((c->hi[other[q]] - c->lo[other[q]]) / spacing + 1e-9);
+    int64_t count = cnt[0] * cnt[1];
+    if (n + count > cap) return LPO_E_CAPACITY;
+    double mass = rho;
+    for (int a = 0; a < D; ++a) mass = mass * spacing;
+    double xa = side == 0 ? c->lo[axis] + depth : c->hi[axis] - depth;
+    double un = side == 0 ? u_n : -u_n;
+    for (int64_t q = 0; q < count; ++q) {
+        int64_t k[2] = {q % cnt[0], q / cnt[0]};
+        int64_t i = n + q;
+        for (int a = 0; a < D; ++a) u[a][i] = 0.0;
+        x[axis][i] = xa;
+        u[axis][i] = un;
+        for (int t = 0; t < no; ++t) {
+            double off = ((double)k[t] + 0.5) * spacing;
+            x[other[t]][i] = c->lo[other[t]] + off;
+        }
+        V[i] = 1.0 / rho;
+        P[i] = p_in;
+        m[i] = mass;
+    }
+    *n_new = n + count;
+    return LPO_OK;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Time step (Sec. 2.2, steps 1-6).                                           */
 /* ------------------------------------------------------------------------- */

@@ -62,6 +62,9 @@ int lpo_outflow(const lpo_cfg *c, int64_t n, double *const *arrays, int narr, co
                 uint32_t lo_mask, uint32_t hi_mask, int64_t *n_kept);
 int lpo_reservoir_inflow(const lpo_cfg *c, int64_t n, const double *const *x, const double *P, int axis, int side,
                          double width, double p_res, double rho_res, double *out);
+int lpo_inflow_layer(const lpo_cfg *c, int64_t n, int64_t cap, double *const *x, double *const *u, double *V,
+                     double *P, double *m, int axis, int side, double spacing, double depth, double rho,
+                     double p_in, double u_n, int64_t *n_new);
 double lpo_timestep(const lpo_cfg *c, int64_t n, const double *V, const double *P, const double *m);
 int lpo_step_subset(const lpo_cfg *c, int64_t n, const double *x, const double *y, const double *z,
                     const double *V, const double *u, const double *v, const double *w,

@@ -74,3 +74,54 @@ def test_reservoir_inflow_empty_layer_and_overpressure(oracle_lib):
     assert out[0] == 3.0 and out[2] == 0.0
     _, rs = oracle_lib.reservoir_inflow(cfg, st, 2, 0, 0.05, 2.0, 1.5)  # no z axis in 2D
     assert rs != 0
+
+
+@pytest.mark.parametrize("dim,axis,side", [(2, 0, 0), (2, 1, 1), (3, 0, 1), (3, 2, 0)])
+def test_inflow_layer_lattice(oracle_lib, dim, axis, side):
+    """Sec. 2.2, step 1 (inflow boundaries generate particles): one layer on a
+    square lattice over the face.  Pinned by the lattice's geometry: the count
+    is the number of whole cells per extent, neighbours are one spacing apart,
+    the layer is centred in its cells, sits at the given depth inside the face,
+    moves into the domain, and carries the mass of its slab of thickness one
+    spacing at the given density."""
+    cfg = W.base_config("open", dim, 2.1, [-0.5, 0.0, 0.25][:dim], [0.5, 0.7, 1.0][:dim], [False] * dim)
+    h, depth, rho, p_in, u_n = 0.05, 0.01, 1.3, 0.8, 0.4
+    lay, n_new, rs = oracle_lib.inflow_layer(cfg, 7, 7 + 5000, axis, side, h, depth, rho, p_in, u_n)
+    assert rs == 0
+    oth = [b for b in range(dim) if b != axis]
+    ext = [cfg["box_hi"][b] - cfg["box_lo"][b] for b in oth]
+    cnt = [int(np.floor(e / h + 1e-9)) for e in ext]          # 20, 14, 15 whole cells
+    assert n_new - 7 == int(np.prod(cnt)) == len(lay["V"])
+    x = lay["x"]
+    face = cfg["box_lo"][axis] if side == 0 else cfg["box_hi"][axis]
+    assert np.allclose(np.abs(x[:, axis] - face), depth, rtol=0, atol=1e-15)
+    for t, b in enumerate(oth):
+        k = np.rint((x[:, b] - cfg["box_lo"][b]) / h - 0.5)
+        assert np.allclose(x[:, b], cfg["box_lo"][b] + (k + 0.5) * h, rtol=0, atol=1e-14)
+        assert k.min() == 0 and k.max() == cnt[t] - 1
+        assert len(np.unique(k)) == cnt[t]
+        assert np.isclose(x[:, b].mean(), cfg["box_lo"][b] + cnt[t] * h / 2, rtol=0, atol=1e-13)
+    # the first other axis runs fastest: consecutive particles one spacing apart
+    assert np.allclose(np.diff(x[:cnt[0], oth[0]]), h, rtol=0, atol=1e-14)
+    if dim == 3:
+        assert np.all(x[:cnt[0], oth[1]] == x[0, oth[1]])
+    inward = 1.0 if side == 0 else -1.0
+    assert np.all(lay["u"][:, axis] * inward == u_n)
+    assert np.all(np.delete(lay["u"], axis, axis=1) == 0.0)
+    assert np.all(lay["P"] == p_in) and np.allclose(1.0 / lay["V"], rho, rtol=1e-15)
+    area = np.prod(cnt) * h ** (dim - 1)
+    assert np.isclose(lay["m"].sum(), rho * area * h, rtol=1e-12)
+
+
+def test_inflow_layer_capacity_and_degenerate(oracle_lib):
+    cfg = W.base_config("open", 2, 2.1, [0.0, 0.0], [1.0, 1.0], [False, False])
+    _, n_new, rs = oracle_lib.inflow_layer(cfg, 10, 10 + 9, 0, 0, 0.1, 0.0, 1.0, 1.0, 0.5)
+    assert rs == 2                           # 10 lattice points do not fit in 9
+    lay, n_new, rs = oracle_lib.inflow_layer(cfg, 10, 20, 0, 0, 0.1, 0.0, 1.0, 1.0, 0.5)
+    assert rs == 0 and n_new == 20
+    lay, n_new, rs = oracle_lib.inflow_layer(cfg, 3, 10, 1, 1, 1.5, 0.0, 1.0, 1.0, 0.5)
+    assert rs == 0 and n_new == 3 and len(lay["V"]) == 0   # spacing wider than the face: no particle
+    _, _, rs = oracle_lib.inflow_layer(cfg, 0, 10, 2, 0, 0.1, 0.0, 1.0, 1.0, 0.5)
+    assert rs == 1                           # no z axis in 2D
+    _, _, rs = oracle_lib.inflow_layer(cfg, 0, 10, 0, 0, 0.0, 0.0, 1.0, 1.0, 0.5)
+    assert rs == 1
