@@ -184,7 +184,8 @@ def gfd3_leg(lp, torch, cfg, st, log, no_cpu):
 def openbc_leg(lp, torch, cfg, st, log, no_cpu):
     """lp_outflow on the workload's particles with the x-high face moved to 0
     (an outflow face through the middle of the cloud; about half the
-    particles leave), and lp_reservoir_inflow at that face.  The
+    particles leave), lp_reservoir_inflow at that face, and lp_inflow_layer
+    of a 256 x 256 layer with that state after the kept particles.  The
     compaction's algorithmic HBM bytes: every per-particle array read once
     (x, u, V, P, m: 72 B; phi, flags: 5 B) and the kept part written once."""
     n = st["V"].shape[0]
@@ -223,7 +224,25 @@ def openbc_leg(lp, torch, cfg, st, log, no_cpu):
     torch.cuda.synchronize()
     res["reservoir_inflow"] = {"ms": e0.elapsed_time(e1), "p_in": float(inflow[0]), "rho_in": float(inflow[1]),
                                "u_in": float(inflow[2]), "averaged": int(inflow[3])}
-    log("outflow: %d of %d kept in %.3f ms (%.0f GB/s algorithmic)" % (kept, n, ms, achieved))
+    # one 256 x 256 lattice layer with that state, appended after the kept particles (77 B written each)
+    cap = int(kept) + 256 * 256
+    h = (cfg["box_hi"][1] - cfg["box_lo"][1]) / 256
+    args = (0, 0, h, 0.5 * h, float(inflow[1]), float(inflow[0]), float(inflow[2]))
+    ctx.inflow_layer(dev, kept, *args)  # warm-up
+    lt = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        n_new = ctx.inflow_layer({k: ([t[:cap] for t in v] if isinstance(v, list) else v[:cap])
+                                  for k, v in dev.items()}, kept, *args)
+        e1.record()
+        torch.cuda.synchronize()
+        lt.append(e0.elapsed_time(e1))
+    lms = float(np.median(lt))
+    res["inflow_layer"] = {"particles": int(n_new - kept), "ms": lms,
+                           "achieved_gbs": 77.0 * (n_new - kept) / (lms * 1e-3) / 1e9}
+    log("outflow: %d of %d kept in %.3f ms (%.0f GB/s algorithmic); inflow layer of %d in %.3f ms"
+        % (kept, n, ms, achieved, n_new - kept, lms))
     if not no_cpu:
         try:
             import oracle

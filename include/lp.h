@@ -232,6 +232,26 @@ lp_status lp_outflow(struct lp_ctx *ctx, void *stream, const lp_particles *p, ui
 lp_status lp_reservoir_inflow(struct lp_ctx *ctx, void *stream, const lp_particles *p, int32_t axis, int32_t side,
                               double width, double p_res, double rho_res, double *out);
 
+/* Inflow layer (Sec. 2.2, step 1: inflow boundaries generate particles):
+ * append one layer of particles on the square lattice of the given spacing,
+ * in the plane at distance `depth` inside the face of axis `axis` (side 0:
+ * box_lo, 1: box_hi).  Each other axis b holds box_lo[b] + (k + 1/2) spacing,
+ * k = 0 .. floor((box_hi[b] - box_lo[b]) / spacing + 1e-9) - 1 (a cell short
+ * of a whole one by rounding alone still counts), the first other axis running
+ * fastest.  The new particles take V = 1 / rho, pressure p_in,
+ * velocity u_n along the inward normal (0 in the other components) and mass
+ * rho spacing^dim; phi = 1 and flags = 0 when those arrays are given.  A
+ * reservoir face takes the state lp_reservoir_inflow returns.
+ * p->n is the current count; every array of p (device) must hold cap entries,
+ * and entries p->n .. *n_new - 1 are written (the mass array too).  *n_new
+ * (host) receives the new count.  LP_E_ARG for a bad face, spacing <= 0,
+ * depth < 0, rho <= 0, p_in <= 0, or cap < p->n; LP_E_CAPACITY (nothing
+ * written) when the layer does not fit in cap.  Asynchronous on `stream`.
+ * Call between steps, with a p->n of the new count afterwards. */
+lp_status lp_inflow_layer(struct lp_ctx *ctx, void *stream, const lp_particles *p, int64_t cap, int32_t axis,
+                          int32_t side, double spacing, double depth, double rho, double p_in, double u_n,
+                          int64_t *n_new);
+
 /* Synchronise and report kernel-side errors of all work since the last
  * check (LP_E_CAPACITY / LP_E_NUMERIC), then clear them. */
 lp_status lp_check(struct lp_ctx *ctx, void *stream);

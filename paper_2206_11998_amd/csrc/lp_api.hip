@@ -1031,6 +1031,43 @@ extern "C" lp_status lp_reservoir_inflow(lp_ctx *c, void *stream, const lp_parti
     return LP_OK;
 }
 
+extern "C" lp_status lp_inflow_layer(lp_ctx *c, void *stream, const lp_particles *p, int64_t cap, int32_t axis,
+                                     int32_t side, double spacing, double depth, double rho, double p_in, double u_n,
+                                     int64_t *n_new) {
+    if (!c || !p || !n_new) return LP_E_ARG;
+    const int D = c->dc.D;
+    if (axis < 0 || axis >= D || side < 0 || side > 1 || !(spacing > 0.0) || !(depth >= 0.0) || !(rho > 0.0) ||
+        !(p_in > 0.0) || !isfinite(u_n))
+        return fail(c, LP_E_ARG, "lp_inflow_layer: bad face, spacing, depth or state");
+    if (p->n < 0 || cap < p->n || cap > ((int64_t)1 << 30)) return fail(c, LP_E_ARG, "lp_inflow_layer: bad n or cap");
+    for (int a = 0; a < D; ++a)
+        if (!p->x[a] || !p->u[a]) return fail(c, LP_E_ARG, "lp_inflow_layer: null array");
+    if (!p->V || !p->P || !p->m) return fail(c, LP_E_ARG, "lp_inflow_layer: null array");
+    int oth[2] = {0, 0}, no = 0;
+    for (int b = 0; b < D; ++b)
+        if (b != axis) oth[no++] = b;
+    int64_t cnt[2] = {1, 1};
+    for (int t = 0; t < no; ++t) {
+        const double k = floor((c->dc.hi[oth[t]] - c->dc.lo[oth[t]]) / spacing + 1e-9);
+        if (!(k <= (double)((int64_t)1 << 30))) return fail(c, LP_E_ARG, "lp_inflow_layer: spacing too small");
+        cnt[t] = (int64_t)k;
+    }
+    const int64_t count = cnt[0] * cnt[1];
+    if (p->n + count > cap)
+        return fail(c, LP_E_CAPACITY, "lp_inflow_layer: %lld particles after the layer, capacity %lld",
+                    (long long)(p->n + count), (long long)cap);
+    *n_new = p->n + count;
+    if (count == 0) return LP_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    double mass = rho;
+    for (int a = 0; a < D; ++a) mass = mass * spacing;
+    const double xa = side == 0 ? c->dc.lo[axis] + depth : c->dc.hi[axis] - depth;
+    launch_inflow_layer(soa_of(p), c->dc, p->n, count, cnt[0], axis, oth[0], oth[1], spacing, xa,
+                        side == 0 ? u_n : -u_n, 1.0 / rho, p_in, mass, (hipStream_t)stream);
+    HIPCHK(c, hipGetLastError());
+    return LP_OK;
+}
+
 extern "C" lp_status lp_check(lp_ctx *c, void *stream) {
     if (!c) return LP_E_ARG;
     HIPCHK(c, hipSetDevice(c->device));

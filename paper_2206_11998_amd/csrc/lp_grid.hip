@@ -640,6 +640,41 @@ template void launch_out_gather<double>(const double *, double *, const uint32_t
 template void launch_out_gather<float>(const float *, float *, const uint32_t *, int, hipStream_t);
 template void launch_out_gather<uint8_t>(const uint8_t *, uint8_t *, const uint32_t *, int, hipStream_t);
 
+// Inflow layer: particle n + q sits at lattice point q (the first other axis
+// fastest) of the face plane at depth `depth` inside the face.  Each position
+// is one rounded product and one rounded sum: contraction into a fused
+// multiply-add is off here, as it would change the last bit.
+__global__ void k_inflow_layer(Soa p, DevCfg cfg, int64_t n0, int64_t count, int64_t cnt0, int axis, int o0, int o1,
+                               double spacing, double xa, double un, double V, double P, double mass) {
+#pragma clang fp contract(off)
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    const int64_t i = n0 + q;
+    const int64_t k[2] = {q % cnt0, q / cnt0};
+    const int oth[2] = {o0, o1};
+    for (int a = 0; a < cfg.D; ++a) p.u[a][i] = 0.0;
+    p.x[axis][i] = xa;
+    p.u[axis][i] = un;
+    for (int t = 0; t < cfg.D - 1; ++t) {
+        const double off = ((double)k[t] + 0.5) * spacing;
+        p.x[oth[t]][i] = cfg.lo[oth[t]] + off;
+    }
+    p.V[i] = V;
+    p.P[i] = P;
+    const_cast<double *>(p.m)[i] = mass;
+    if (p.phi) p.phi[i] = 1.0f;
+    if (p.flags) p.flags[i] = 0;
+}
+
+void launch_inflow_layer(const Soa &p, const DevCfg &cfg, int64_t n0, int64_t count, int64_t cnt0, int axis, int o0,
+                         int o1, double spacing, double xa, double un, double V, double P, double mass,
+                         hipStream_t st) {
+    const int64_t nb = (count + LP_BLOCK - 1) / LP_BLOCK;
+    hipLaunchKernelGGL(k_inflow_layer, dim3((unsigned)nb), dim3(LP_BLOCK), 0, st, p, cfg, n0, count, cnt0, axis, o0,
+                       o1, spacing, xa, un, V, P, mass);
+    CHECK_LAUNCH();
+}
+
 // Inlet layer of the face (side 0: lo, 1: hi): per block the sum of P and the
 // count of the particles at distance 0 <= d < width inside the face, in a
 // fixed order (grid-stride per thread, then the wave, then the block's waves)

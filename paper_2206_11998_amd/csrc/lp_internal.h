@@ -240,6 +240,9 @@ void launch_out_keep(const Soa &p, const DevCfg &cfg, uint32_t lo_mask, uint32_t
                      hipStream_t st);
 template <typename T>
 void launch_out_gather(const T *src, T *dst, const uint32_t *pos, int n, hipStream_t st);
+void launch_inflow_layer(const Soa &p, const DevCfg &cfg, int64_t n0, int64_t count, int64_t cnt0, int axis, int o0,
+                         int o1, double spacing, double xa, double un, double V, double P, double mass,
+                         hipStream_t st);
 void launch_reservoir(const double *xa, const double *P, int n, int side, double face, double width, double p_res,
                       double rho_res, double gamma, double *part, int nblocks, double *out, hipStream_t st);
 void launch_conservation(const Soa &p, const DevCfg &cfg, double *partials, int nblocks, double *out,

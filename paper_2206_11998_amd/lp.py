@@ -20,7 +20,7 @@ EST_PLAIN, EST_INJECTED, EST_MLP = 0, 1, 2
 FLAG_LIMITED, FLAG_DEGENERATE, FLAG_VACUUM, FLAG_SUBSTITUTED, FLAG_FALLBACK, FLAG_NUMERIC = 1, 2, 4, 8, 16, 32
 
 EXPORTS = ["lp_config_default", "lp_create", "lp_destroy", "lp_neighbors", "lp_gfd", "lp_gfd3", "lp_outflow",
-           "lp_reservoir_inflow", "lp_step", "lp_run",
+           "lp_reservoir_inflow", "lp_inflow_layer", "lp_step", "lp_run",
            "lp_conservation", "lp_check", "lp_get_info", "lp_set_time", "lp_profile", "lp_profile_read",
            "lp_set_tuning", "lp_get_tuning", "lp_autotune", "lp_train_cfg_default", "lp_features", "lp_mlp_init",
            "lp_mlp_set", "lp_mlp_get", "lp_mlp_forward", "lp_mlp_grad", "lp_mlp_train", "lp_status_str",
@@ -100,6 +100,9 @@ def lib():
         L.lp_reservoir_inflow.restype = i32
         L.lp_reservoir_inflow.argtypes = [vp, vp, C.c_void_p, i32, i32, C.c_double, C.c_double, C.c_double,
                                           C.POINTER(C.c_double)]
+        L.lp_inflow_layer.restype = i32
+        L.lp_inflow_layer.argtypes = [vp, vp, C.c_void_p, i64, i32, i32, C.c_double, C.c_double, C.c_double,
+                                      C.c_double, C.c_double, C.POINTER(C.c_int64)]
         L.lp_gfd3.restype = i32
         L.lp_gfd3.argtypes = [vp, vp, i64, vp, vp, vp, vp, i32, C.POINTER(vp), vp, vp]
         L.lp_step.restype = i32
@@ -322,6 +325,19 @@ class Context:
         self._raise(lib().lp_reservoir_inflow(self._h, _stream_ptr(stream), C.byref(p), int(axis), int(side),
                                               float(width), float(p_res), float(rho_res), out))
         return np.array(out[:])
+
+    def inflow_layer(self, s: dict, n: int, axis: int, side: int, spacing: float, depth: float, rho: float,
+                     p_in: float, u_n: float, stream=None) -> int:
+        """Append one lattice layer of inflow particles after the first n
+        entries of s (whose arrays are the capacity); returns the new count."""
+        p = self._particles(s)
+        cap = p.n
+        p.n = int(n)
+        n_new = C.c_int64(0)
+        self._raise(lib().lp_inflow_layer(self._h, _stream_ptr(stream), C.byref(p), cap, int(axis), int(side),
+                                          float(spacing), float(depth), float(rho), float(p_in), float(u_n),
+                                          C.byref(n_new)))
+        return n_new.value
 
     def step(self, s: dict, dt: float = 0.0, stream=None):
         p = self._particles(s)

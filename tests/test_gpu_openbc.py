@@ -83,3 +83,86 @@ def test_outflow_2m_vacuum_cloud(lp):
     assert np.array_equal(idx, np.flatnonzero(keep))
     assert np.array_equal(dev["V"][:kept].cpu().numpy(), st["V"][keep])
     ctx.close()
+
+
+def _capacity_state(st, cap, dim):
+    """Device arrays of `cap` entries holding the particles of st first, the
+    rest filled with a marker value."""
+    n = len(st["V"])
+    full = {"x": np.full((cap, dim), 7.0), "u": np.full((cap, dim), 7.0), "V": np.full(cap, 7.0),
+            "P": np.full(cap, 7.0), "m": np.full(cap, 7.0)}
+    for k in full:
+        full[k][:n] = st[k]
+    return full
+
+
+@pytest.mark.parametrize("dim,axis,side", [(2, 0, 0), (2, 1, 1), (3, 0, 1), (3, 2, 0), (3, 1, 0)])
+def test_inflow_layer_matches_oracle(lp, oracle_lib, dim, axis, side):
+    say("inflow layer", dim, axis, side)
+    cfg, st = _cloud(dim, 1000, seed=60 + dim + axis)
+    cfg = dict(cfg, box_lo=[-0.5, 0.0, 0.25][:dim], box_hi=[0.5, 0.7, 1.0][:dim])
+    h, depth, rho, p_in, u_n = 0.013, 0.002, 1.3, 0.8, 0.4
+    n, cap = 1000, 1000 + 6000
+    ref, n_ref, rs = oracle_lib.inflow_layer(cfg, n, cap, axis, side, h, depth, rho, p_in, u_n)
+    assert rs == 0 and n_ref > n
+    ctx = lp.Context(cfg)
+    dev = lp.state_to_device(_capacity_state(st, cap, dim))
+    dev["phi"].fill_(5.0)
+    dev["flags"].fill_(9)
+    n_new = ctx.inflow_layer(dev, n, axis, side, h, depth, rho, p_in, u_n)
+    torch.cuda.synchronize()
+    assert n_new == n_ref
+    got = lp.state_to_host(dev)
+    for key in ("x", "u", "V", "P", "m"):
+        assert np.array_equal(got[key][n:n_new], ref[key]), key
+        assert np.array_equal(got[key][:n], st[key]), key          # existing particles untouched
+        assert np.all(got[key][n_new:] == 7.0), key                 # nothing past the layer
+    assert np.all(got["phi"][n:n_new] == 1.0) and np.all(got["phi"][:n] == 5.0)
+    assert np.all(got["flags"][n:n_new] == 0) and np.all(got["flags"][n_new:] == 9)
+    ctx.close()
+
+
+def test_inflow_layer_errors_leave_arrays(lp, oracle_lib):
+    say("inflow layer errors")
+    cfg, st = _cloud(2, 100, seed=3)
+    ctx = lp.Context(cfg)
+    dev = lp.state_to_device(_capacity_state(st, 105, 2))
+    with pytest.raises(lp.LpError) as e:
+        ctx.inflow_layer(dev, 100, 0, 0, 0.1, 0.0, 1.0, 1.0, 0.5)     # 10 new particles, room for 5
+    assert e.value.status == 2
+    with pytest.raises(lp.LpError) as e:
+        ctx.inflow_layer(dev, 100, 2, 0, 0.1, 0.0, 1.0, 1.0, 0.5)     # no z axis in 2D
+    assert e.value.status == 1
+    assert ctx.inflow_layer(dev, 100, 1, 1, 1.5, 0.0, 1.0, 1.0, 0.5) == 100   # spacing wider than the face
+    torch.cuda.synchronize()
+    assert np.all(dev["V"][100:].cpu().numpy() == 7.0)
+    ctx.close()
+
+
+def test_inflow_layer_after_outflow_2m(lp, oracle_lib):
+    """At the 2M vacuum cloud's size: delete past an outflow face, then append
+    a 256 x 256 inflow layer carrying the reservoir state computed at the
+    outflow face, checked against the oracle bit for bit."""
+    say("outflow + inflow layer 2M")
+    cfg, st = W.vacuum3d()
+    n = len(st["V"])
+    cfg = dict(cfg, box_hi=[0.0] + list(cfg["box_hi"][1:]))
+    ctx = lp.Context(cfg)
+    cap = n + 300000
+    dev = lp.state_to_device(_capacity_state(st, cap, 3))
+    head = {k: ([t[:n] for t in v] if isinstance(v, list) else v[:n]) for k, v in dev.items()}
+    kept = ctx.outflow(head, 0, 1)
+    p_in, rho_in, u_in, cnt = ctx.reservoir_inflow(_head(dev, kept), 0, 1, 0.02, 2.0, 1.5)
+    assert cnt > 0 and u_in > 0.0
+    ext = cfg["box_hi"][1] - cfg["box_lo"][1]
+    h = ext / 256
+    n_new = ctx.inflow_layer(dev, kept, 0, 0, h, 0.5 * h, rho_in, p_in, u_in)
+    ref, n_ref, rs = oracle_lib.inflow_layer(cfg, kept, cap, 0, 0, h, 0.5 * h, rho_in, p_in, u_in)
+    assert rs == 0 and n_new == n_ref
+    torch.cuda.synchronize()
+    for key in ("V", "P", "m"):
+        assert np.array_equal(dev[key][kept:n_new].cpu().numpy(), ref[key]), key
+    for a in range(3):
+        assert np.array_equal(dev["x"][a][kept:n_new].cpu().numpy(), ref["x"][:, a])
+        assert np.array_equal(dev["u"][a][kept:n_new].cpu().numpy(), ref["u"][:, a])
+    ctx.close()
