@@ -216,7 +216,7 @@ def openbc_leg(lp, torch, cfg, st, log, no_cpu):
     res = {"particles": n, "kept": int(kept), "outflow_ms": ms,
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                         "frac": achieved / PEAK_HBM_GBS, "traffic": None, "algorithmic_bytes_per_call": alg,
-                        "note": "one call: keep flags, scan, one gather and one copy back per array, one sync"}}
+                        "note": "one call: keep flags, scan, one sync, one gather and one copy back over all arrays"}}
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     inflow = ctx.reservoir_inflow(src, 0, 1, 0.02, 2.0, 1.5)  # the layer -0.02 < x <= 0 of the moved face

@@ -976,7 +976,7 @@ extern "C" lp_status lp_outflow(lp_ctx *c, void *stream, const lp_particles *p, 
     const int D = c->dc.D;
     ENSURE(c, c->gcnt, sizeof(uint32_t) * (n + 1));
     ENSURE(c, c->scan_tmp, sizeof(uint32_t) * scan_tmp_words((uint64_t)n));
-    ENSURE(c, c->gfd_fields, sizeof(double) * n);
+    ENSURE(c, c->gfd_fields, out_stage_bytes(D, n));
     uint32_t *pos = (uint32_t *)c->gcnt.p;
     launch_out_keep(soa_of(p), c->dc, lo_mask, hi_mask, pos, st);
     launch_scan_u32(pos, (uint64_t)n, (uint32_t *)c->scan_tmp.p, nullptr, st);
@@ -984,27 +984,9 @@ extern "C" lp_status lp_outflow(lp_ctx *c, void *stream, const lp_particles *p, 
     HIPCHK(c, hipMemcpyAsync(&kept, pos + n, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     if ((int64_t)kept < n) {
-        // each array through the temporary, then back into the caller's array
-        double *tmp = (double *)c->gfd_fields.p;
-        double *arrs[9];
-        int na = 0;
-        for (int a = 0; a < D; ++a) arrs[na++] = p->x[a];
-        for (int a = 0; a < D; ++a) arrs[na++] = p->u[a];
-        arrs[na++] = p->V;
-        arrs[na++] = p->P;
-        arrs[na++] = const_cast<double *>(p->m);  // the caller's array: constant for the step, compacted here
-        for (int q = 0; q < na; ++q) {
-            launch_out_gather<double>(arrs[q], tmp, pos, (int)n, st);
-            HIPCHK(c, hipMemcpyAsync(arrs[q], tmp, sizeof(double) * kept, hipMemcpyDeviceToDevice, st));
-        }
-        if (p->phi) {
-            launch_out_gather<float>(p->phi, (float *)tmp, pos, (int)n, st);
-            HIPCHK(c, hipMemcpyAsync(p->phi, tmp, sizeof(float) * kept, hipMemcpyDeviceToDevice, st));
-        }
-        if (p->flags) {
-            launch_out_gather<uint8_t>(p->flags, (uint8_t *)tmp, pos, (int)n, st);
-            HIPCHK(c, hipMemcpyAsync(p->flags, tmp, kept, hipMemcpyDeviceToDevice, st));
-        }
+        // every array through the staging area, then back into the caller's arrays (the mass array
+        // too: constant for the step, compacted here)
+        launch_out_compact(soa_of(p), D, pos, kept, (double *)c->gfd_fields.p, st);
         HIPCHK(c, hipGetLastError());
     }
     *n_kept = kept;

@@ -615,14 +615,39 @@ __global__ void k_out_keep(Soa p, DevCfg cfg, uint32_t lo_mask, uint32_t hi_mask
     keep[i] = gone ? 0u : 1u;
 }
 
-// after the exclusive scan of keep (pos[n] = particles kept): the kept
-// particles of src, in order, to dst
-template <typename T>
-__global__ void k_out_gather(const T *src, T *dst, const uint32_t *pos, int n) {
+// Outflow compaction through a staging area: slot k (n entries) holds array k
+// of x[0..D-1], u[0..D-1], V, P, m, then n floats of phi and n bytes of flags.
+// After the exclusive scan of keep (pos[n] = particles kept), every kept
+// particle's entries go, in order, to the staging area ...
+__global__ void k_out_gather_all(Soa p, int D, const uint32_t *pos, double *tmp) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= p.n) return;
     const uint32_t q = pos[i];
-    if (pos[i + 1] > q) dst[q] = src[i];
+    if (pos[i + 1] == q) return;
+    const size_t n = (size_t)p.n;
+    double *t = tmp + q;
+    for (int a = 0; a < D; ++a) t[a * n] = p.x[a][i];
+    for (int a = 0; a < D; ++a) t[(D + a) * n] = p.u[a][i];
+    t[2 * D * n] = p.V[i];
+    t[(2 * D + 1) * n] = p.P[i];
+    t[(2 * D + 2) * n] = p.m[i];
+    if (p.phi) reinterpret_cast<float *>(tmp + (2 * D + 3) * n)[q] = p.phi[i];
+    if (p.flags) reinterpret_cast<uint8_t *>(tmp + (2 * D + 3) * n + (n + 1) / 2)[q] = p.flags[i];
+}
+
+// ... and back to the front of the caller's arrays
+__global__ void k_out_copy_back(Soa p, int D, uint32_t kept, const double *tmp) {
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= kept) return;
+    const size_t n = (size_t)p.n;
+    const double *t = tmp + q;
+    for (int a = 0; a < D; ++a) p.x[a][q] = t[a * n];
+    for (int a = 0; a < D; ++a) p.u[a][q] = t[(D + a) * n];
+    p.V[q] = t[2 * D * n];
+    p.P[q] = t[(2 * D + 1) * n];
+    const_cast<double *>(p.m)[q] = t[(2 * D + 2) * n];
+    if (p.phi) p.phi[q] = reinterpret_cast<const float *>(tmp + (2 * D + 3) * n)[q];
+    if (p.flags) p.flags[q] = reinterpret_cast<const uint8_t *>(tmp + (2 * D + 3) * n + (n + 1) / 2)[q];
 }
 
 void launch_out_keep(const Soa &p, const DevCfg &cfg, uint32_t lo_mask, uint32_t hi_mask, uint32_t *keep,
@@ -631,14 +656,17 @@ void launch_out_keep(const Soa &p, const DevCfg &cfg, uint32_t lo_mask, uint32_t
     CHECK_LAUNCH();
 }
 
-template <typename T>
-void launch_out_gather(const T *src, T *dst, const uint32_t *pos, int n, hipStream_t st) {
-    hipLaunchKernelGGL(k_out_gather<T>, dim3(blocks_for(n)), dim3(LP_BLOCK), 0, st, src, dst, pos, n);
+size_t out_stage_bytes(int D, int64_t n) {
+    return sizeof(double) * ((size_t)(2 * D + 3) * n + (n + 1) / 2) + (size_t)n;
+}
+
+void launch_out_compact(const Soa &p, int D, const uint32_t *pos, uint32_t kept, double *tmp, hipStream_t st) {
+    hipLaunchKernelGGL(k_out_gather_all, dim3(blocks_for(p.n)), dim3(LP_BLOCK), 0, st, p, D, pos, tmp);
+    if (kept > 0)
+        hipLaunchKernelGGL(k_out_copy_back, dim3(blocks_for((int)kept)), dim3(LP_BLOCK), 0, st, p, D, kept,
+                           (const double *)tmp);
     CHECK_LAUNCH();
 }
-template void launch_out_gather<double>(const double *, double *, const uint32_t *, int, hipStream_t);
-template void launch_out_gather<float>(const float *, float *, const uint32_t *, int, hipStream_t);
-template void launch_out_gather<uint8_t>(const uint8_t *, uint8_t *, const uint32_t *, int, hipStream_t);
 
 // Inflow layer: particle n + q sits at lattice point q (the first other axis
 // fastest) of the face plane at depth `depth` inside the face.  Each position

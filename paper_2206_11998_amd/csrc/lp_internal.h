@@ -238,8 +238,9 @@ void launch_gfd3(const Sorted &s, const double *const *fs, int nf, const int *nb
                  int n, const DevCfg &cfg, double *deriv, uint8_t *status, hipStream_t st);
 void launch_out_keep(const Soa &p, const DevCfg &cfg, uint32_t lo_mask, uint32_t hi_mask, uint32_t *keep,
                      hipStream_t st);
-template <typename T>
-void launch_out_gather(const T *src, T *dst, const uint32_t *pos, int n, hipStream_t st);
+// bytes of the outflow staging area for n particles in D dimensions
+size_t out_stage_bytes(int D, int64_t n);
+void launch_out_compact(const Soa &p, int D, const uint32_t *pos, uint32_t kept, double *tmp, hipStream_t st);
 void launch_inflow_layer(const Soa &p, const DevCfg &cfg, int64_t n0, int64_t count, int64_t cnt0, int axis, int o0,
                          int o1, double spacing, double xa, double un, double V, double P, double mass,
                          hipStream_t st);
