@@ -166,3 +166,44 @@ def test_inflow_layer_after_outflow_2m(lp, oracle_lib):
         assert np.array_equal(dev["x"][a][kept:n_new].cpu().numpy(), ref["x"][:, a])
         assert np.array_equal(dev["u"][a][kept:n_new].cpu().numpy(), ref["u"][:, a])
     ctx.close()
+
+
+def test_run_across_outflow_and_inflow_layer(lp, oracle_lib):
+    """Open-boundary calls between graph-replayed runs.  A jittered 2D pulse
+    between mirror walls at x = -h and x = 0.9 (y periodic) is cut at the
+    outflow face, run two steps with lp_run, given one inflow layer at the low
+    face carrying a reservoir state, then run two more steps on the new count.
+    That second run needs a new capture. FP64 against the oracle stepping the
+    same particles, within 1e-10 relative L1."""
+    from tests.gpu_util import compare_states
+    say("lp_run across outflow and an inflow layer")
+    cfg, st = W.pulse2d(n=48)
+    h = 1.0 / 48
+    cfg = dict(cfg, box_lo=[-h, 0.0], box_hi=[0.9, 1.0], periodic=[False, True], wall_lo=[True, False],
+               wall_hi=[True, False])
+    ctx = lp.Context(cfg, precision="fp64")
+    dev = lp.state_to_device(st)
+    kept = ctx.outflow(dev, 0, 1)
+    ref = oracle_lib.outflow(cfg, st, 0, 1)
+    assert kept == len(ref["V"]) < len(st["V"])
+    ctx.run(_head(dev, kept), 2)
+    assert ctx.check() == lp.OK
+    for _ in range(2):
+        ref, info = oracle_lib.step(cfg, ref)
+        assert info["status"] == 0
+    compare_states(lp.state_to_host(_head(dev, kept)), ref, cfg, 1e-10, "before the layer")
+    res, rs = oracle_lib.reservoir_inflow(cfg, ref, 0, 0, 2 * h, 1.1, 1.05)
+    got = ctx.reservoir_inflow(_head(dev, kept), 0, 0, 2 * h, 1.1, 1.05)
+    assert rs == 0 and got[3] == res[3] and np.allclose(got[:3], res[:3], rtol=1e-10, atol=0.0)
+    p_in, rho_in, u_in = (float(v) for v in res[:3])
+    n_new = ctx.inflow_layer(dev, kept, 0, 0, h, 0.5 * h, rho_in, p_in, u_in)
+    lay, n_ref, rs = oracle_lib.inflow_layer(cfg, kept, len(st["V"]), 0, 0, h, 0.5 * h, rho_in, p_in, u_in)
+    assert rs == 0 and n_new == n_ref == kept + 48
+    ref = {k: np.concatenate([ref[k], lay[k]]) for k in ("x", "u", "V", "P", "m")}
+    ctx.run(_head(dev, n_new), 2)
+    assert ctx.check() == lp.OK
+    for _ in range(2):
+        ref, info = oracle_lib.step(cfg, ref)
+        assert info["status"] == 0
+    compare_states(lp.state_to_host(_head(dev, n_new)), ref, cfg, 1e-10, "after the layer")
+    ctx.close()
