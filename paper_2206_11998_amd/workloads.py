@@ -277,3 +277,37 @@ def yee_vortex(dx, beta=5.0, half=5.0, jitter=0.0, seed=7):
     m = rho * ddx * ddy
     cfg = base_config("yee2d", 2, 2.5, [-half, -half], [half, half], [True, True], beta=beta)
     return cfg, _state(x, rho, u, p, m)
+
+
+def yee_vortex3d(dx, beta=5.0, half=5.0, z_div=8, kappa=2.2, jitter=0.0, seed=7):
+    """The Yee vortex extruded along z (the 3D variant of Sec. 2.3): the 2D
+    lattice of yee_vortex repeated in nz layers over the periodic z extent
+    L / z_div (L = 2 half; a periodic extent must be the largest one over a
+    power of two), nz = round(L / z_div / dx) layers at (k + 1/2) dz.  The
+    state does not depend on z and the z velocity is 0; masses m = rho dx dy dz.
+    Particles are stored layer by layer.  With jitter > 0 every particle
+    moves by up to +-jitter of the spacing per axis, independently in each
+    layer, and takes the exact state at its new position: no two neighbours
+    are then at exactly equal distance."""
+    _, st2 = yee_vortex(dx, beta, half)
+    L = 2.0 * half
+    lz = L / z_div
+    nz = max(2, int(round(lz / dx)))
+    dz = lz / nz
+    n2 = st2["V"].shape[0]
+    z = np.repeat((np.arange(nz) + 0.5) * dz, n2)
+    st = {"x": np.concatenate([np.tile(st2["x"], (nz, 1)), z[:, None]], axis=1),
+          "u": np.concatenate([np.tile(st2["u"], (nz, 1)), np.zeros((nz * n2, 1))], axis=1),
+          "V": np.tile(st2["V"], nz), "P": np.tile(st2["P"], nz), "m": np.tile(st2["m"], nz) * dz}
+    if jitter > 0.0:
+        rng = np.random.default_rng(seed)
+        area = st2["m"][0] * st2["V"][0]          # dx dy of the 2D lattice
+        hx = L / max(2, int(round(L / dx)))
+        x = st["x"] + rng.uniform(-jitter, jitter, size=st["x"].shape) * np.array([hx, area / hx, dz])
+        x[:, :2] = (x[:, :2] + half) % L - half
+        x[:, 2] %= lz
+        rho, u, p = yee_exact(x, 0.0, beta, half)
+        st = {"x": x, "u": np.concatenate([u, np.zeros((x.shape[0], 1))], axis=1), "V": 1.0 / rho, "P": p,
+              "m": rho * area * dz}
+    cfg = base_config("yee3d", 3, kappa, [-half, -half, 0.0], [half, half, lz], [True, True, True], beta=beta)
+    return cfg, {k: np.ascontiguousarray(v) for k, v in st.items()}

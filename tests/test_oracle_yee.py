@@ -69,3 +69,33 @@ def test_lax_wendroff_part_converges_at_second_order(oracle_lib):
     print("Yee vortex, phi = 1: P L2 %.5f -> %.5f (order %.2f), u L2 %.5f -> %.5f (order %.2f); "
           "paper P %s, u %s" % (e4[0], e2[0], order_p, e4[2], e2[2], order_u, PAPER_L2["P"], PAPER_L2["u"]))
     assert order_p > 1.8 and order_u > 1.8
+
+
+def test_yee3d_generator_and_lw_z_invariance(oracle_lib):
+    """The extruded vortex (the 3D variant of Sec. 2.3): each layer is the 2D
+    lattice with the exact initial state, the layers carry the mass of their
+    slabs, and the Lax-Wendroff part (phi held at 1) keeps every layer equal
+    and the z velocity zero to rounding over 10 steps."""
+    cfg2, st2 = W.yee_vortex(0.4)
+    cfg, st = W.yee_vortex3d(0.4)
+    n2 = len(st2["V"])
+    nz = len(st["V"]) // n2
+    lz = cfg["box_hi"][2] - cfg["box_lo"][2]
+    assert nz * n2 == len(st["V"]) and nz == 3 and np.isclose(lz, 1.25)
+    for q in range(nz):
+        sl = slice(q * n2, (q + 1) * n2)
+        assert np.array_equal(st["x"][sl, :2], st2["x"]) and np.allclose(st["x"][sl, 2], (q + 0.5) * lz / nz)
+        rho, u, p = W.yee_exact(st["x"][sl], 0.0)
+        assert np.allclose(1.0 / st["V"][sl], rho, rtol=1e-14) and np.allclose(st["P"][sl], p, rtol=1e-14)
+        assert np.allclose(st["u"][sl, :2], u, rtol=0, atol=1e-15) and np.all(st["u"][sl, 2] == 0.0)
+    assert np.isclose(st["m"].sum(), lz * st2["m"].sum(), rtol=1e-13)
+    cfgi = dict(cfg, phi_fixed=1.0)
+    ref = st
+    for _ in range(10):
+        ref, info = oracle_lib.step(cfgi, ref)
+        assert info["status"] == 0
+    assert np.abs(ref["u"][:, 2]).max() < 1e-13
+    for q in range(1, nz):
+        for k in ("V", "P"):
+            assert np.abs(ref[k][q * n2:(q + 1) * n2] - ref[k][:n2]).max() < 1e-13, (q, k)
+        assert np.abs(ref["u"][q * n2:(q + 1) * n2, :2] - ref["u"][:n2, :2]).max() < 1e-13
