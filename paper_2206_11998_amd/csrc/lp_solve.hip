@@ -1857,11 +1857,11 @@ __device__ __forceinline__ int wave_lw_select(const Sorted &srt, const DevCfg &c
 }
 
 // One wave per particle (blocks of one wave: the second-order fallback
-// synchronises the block), particles in a grid-stride loop.  Three waves per
-// SIMD (a few spilled registers) run the 2M-particle call in 65 ms against
-// 82 ms at the two that 193 registers allow.
+// synchronises the block), particles in a grid-stride loop.  Four waves per
+// SIMD (128 registers, the rest spilled) beat three (a 2M-particle fit in 58
+// against 60 ms), and three beat the two that 193 registers allow by a fifth.
 template <int D>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_gfd3(Sorted srt, FieldPtrs fs, int nf, const int *nbr, int ldn,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_gfd3(Sorted srt, FieldPtrs fs, int nf, const int *nbr, int ldn,
                                              const int *count, int n, DevCfg cfg, double *deriv, uint8_t *status) {
     constexpr int N3 = Dim3<D>::NU, NU = Dim<D>::NU, NS = Dim<D>::NS;
     __shared__ int sel[64];
