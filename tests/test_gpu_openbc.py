@@ -207,3 +207,31 @@ def test_run_across_outflow_and_inflow_layer(lp, oracle_lib):
         assert info["status"] == 0
     compare_states(lp.state_to_host(_head(dev, n_new)), ref, cfg, 1e-10, "after the layer")
     ctx.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_outflow_and_inflow_layer_without_phi_and_flags(lp, oracle_lib, dim):
+    """phi and flags are optional: both calls leave them out and still match
+    the oracle bit for bit."""
+    say("open boundaries without phi/flags", dim)
+    cfg, st = _cloud(dim, 2000, seed=90 + dim)
+    ref = oracle_lib.outflow(cfg, st, 1, 2)
+    ctx = lp.Context(cfg)
+    dev = lp.state_to_device(st)
+    del dev["phi"], dev["flags"]
+    kept = ctx.outflow(dev, 1, 2)
+    assert kept == len(ref["V"])
+    got = lp.state_to_host(dict(_head(dev, kept), phi=torch.zeros(1), flags=torch.zeros(1)))
+    for key in ("x", "u", "V", "P", "m"):
+        assert np.array_equal(got[key], ref[key]), key
+    lay, n_ref, rs = oracle_lib.inflow_layer(cfg, kept, len(st["V"]), 0, 1, 0.05, 0.01, 1.2, 0.9, 0.3)
+    assert rs == 0
+    n_new = ctx.inflow_layer(dev, kept, 0, 1, 0.05, 0.01, 1.2, 0.9, 0.3)
+    assert n_new == n_ref
+    torch.cuda.synchronize()
+    for key in ("V", "P", "m"):
+        assert np.array_equal(dev[key][kept:n_new].cpu().numpy(), lay[key]), key
+    for a in range(dim):
+        assert np.array_equal(dev["x"][a][kept:n_new].cpu().numpy(), lay["x"][:, a])
+        assert np.array_equal(dev["u"][a][kept:n_new].cpu().numpy(), lay["u"][:, a])
+    ctx.close()
