@@ -41,7 +41,7 @@ class Cfg(C.Structure):
         ("est_eps", C.c_double), ("cond_max", C.c_double), ("uw_cond_max", C.c_double),
         ("lo", C.c_double * 3), ("hi", C.c_double * 3),
         ("periodic", C.c_int32 * 3), ("wall_lo", C.c_int32 * 3), ("wall_hi", C.c_int32 * 3),
-        ("vacuum", C.c_int32), ("phi_fixed", C.c_double),
+        ("vacuum", C.c_int32), ("phi_fixed", C.c_double), ("limiter_cap", C.c_double),
     ]
 
 
@@ -150,6 +150,8 @@ def make_cfg(cfg: dict) -> Cfg:
     c.vacuum = int(bool(cfg.get("vacuum", False)))
     # blend with a fixed phi (1: pure Lax-Wendroff, 0: pure upwind); None: the estimator
     c.phi_fixed = -1.0 if cfg.get("phi_fixed") is None else float(cfg["phi_fixed"])
+    # cap on the limiter's value (1: phi never exceeds pure Lax-Wendroff); 0: as printed (up to 1.25)
+    c.limiter_cap = float(cfg.get("limiter_cap", 1.0))
     return c
 
 

@@ -543,26 +543,45 @@ static int lw_fit(const lpo_cfg *c, int k, const int *sel, const double *dxs, do
     return status;
 }
 
-/* Linear one-sided fit of (V, u_a, P) on a half-ball; rows sel[] with the a-th
- * coordinate mirrored when mirror != 0 and fixed right-hand sides when rhs
- * is non-NULL (vacuum ghosts).  Returns 1 if valid and writes d[3]. */
+/* Linear one-sided fit of (V, u_a, P) on a half-ball's rows sel[].  Returns
+ * 1 if valid and writes d[3]. */
 static int uw_fit(const lpo_cfg *c, int m, const int *sel, const double *dxs, double s, int a,
-                  int mirror, const double *fi3, const double *fj3 /* k x 3 */,
-                  const double *fixed_rhs, double *d)
+                  const double *fi3, const double *fj3 /* k x 3 */, double *d)
 {
     int D = c->dim;
     if (m < D) return 0;
     double A[64 * 3], B[64 * 3], X[9];
     for (int t = 0; t < m; ++t) {
-        for (int b = 0; b < D; ++b) {
-            double v = dxs[sel[t] * 3 + b] / s;
-            if (mirror && b == a) v = -v;
-            A[t * D + b] = v;
-        }
-        for (int q = 0; q < 3; ++q)
-            B[t * 3 + q] = fixed_rhs ? fixed_rhs[q] : fj3[sel[t] * 3 + q] - fi3[q];
+        for (int b = 0; b < D; ++b) A[t * D + b] = dxs[sel[t] * 3 + b] / s;
+        for (int q = 0; q < 3; ++q) B[t * 3 + q] = fj3[sel[t] * 3 + q] - fi3[q];
     }
     double cond = lpo_lstsq_qrp(m, D, 3, A, B, X);
+    if (!(cond <= c->uw_cond_max)) return 0;
+    for (int q = 0; q < 3; ++q) d[q] = X[a * 3 + q] / s;
+    return 1;
+}
+
+/* Half-ball completed by vacuum ghosts: the m real members of the half-ball
+ * and the mirror images, through the particle along axis a, of the mo members
+ * of the opposite half-ball, which carry P = 0 and the particle's own V and u
+ * (right-hand sides 0, 0, -P_i).  Returns 1 if valid and writes d[3]. */
+static int uw_fit_completed(const lpo_cfg *c, int m, const int *sel, int mo, const int *selo, const double *dxs,
+                            double s, int a, const double *fi3, const double *fj3, double Pi, double *d)
+{
+    int D = c->dim, rows = m + mo;
+    if (rows < D) return 0;
+    double A[128 * 3], B[128 * 3], X[9];
+    for (int t = 0; t < rows; ++t) {
+        int own = t < m;
+        int j = own ? sel[t] : selo[t - m];
+        for (int b = 0; b < D; ++b) {
+            double v = dxs[j * 3 + b] / s;
+            if (!own && b == a) v = -v;
+            A[t * D + b] = v;
+        }
+        for (int q = 0; q < 3; ++q) B[t * 3 + q] = own ? fj3[j * 3 + q] - fi3[q] : (q == 2 ? -Pi : 0.0);
+    }
+    double cond = lpo_lstsq_qrp(rows, D, 3, A, B, X);
     if (!(cond <= c->uw_cond_max)) return 0;
     for (int q = 0; q < 3; ++q) d[q] = X[a * 3 + q] / s;
     return 1;
@@ -624,14 +643,18 @@ static void solve_particle(const lpo_cfg *c, int64_t i, const int32_t *list, int
             }
             int ok = 0;
             if (c->vacuum && ms < uwcap) {
-                /* free boundary (step 3): the half-ball is incomplete, so it is
-                 * completed with ghosts mirrored from the opposite half-ball that
-                 * carry P = 0 and the particle's own V and u */
+                /* free boundary (step 3): the direction holds fewer members
+                 * than its list needs, so ghost particles complete it: the
+                 * mirror images of the opposite half-ball's members, with
+                 * P = 0 (vacuum) and the particle's own V and u, join the
+                 * half-ball's real members in the fit */
                 int mo = uw_select(k, dxs, a, -sgn, uwcap, selo);
-                double rhs[3] = {0.0, 0.0, -fi[D + 1]};
-                if (uw_fit(c, mo, selo, dxs, s, a, 1, fi3, fj3, rhs, d)) { res->vacuum_used = 1; ok = 1; }
+                if (uw_fit_completed(c, ms, self, mo, selo, dxs, s, a, fi3, fj3, fi[D + 1], d)) {
+                    res->vacuum_used = 1;
+                    ok = 1;
+                }
             } else {
-                ok = uw_fit(c, ms, self, dxs, s, a, 0, fi3, fj3, NULL, d);
+                ok = uw_fit(c, ms, self, dxs, s, a, fi3, fj3, d);
                 *valid = ok;
             }
             if (!ok) {
@@ -657,10 +680,11 @@ static void solve_particle(const lpo_cfg *c, int64_t i, const int32_t *list, int
             }
         }
     }
-    /* The estimator selects the points where the limiter falls below one; all
-     * other points advance with the pure Lax-Wendroff rate (phi = 1). */
+    /* phi = limiter(r); with a cap (the default 1) the points the estimator
+     * does not select advance with the pure Lax-Wendroff rate, without one the
+     * printed limiter reaches 1.25 at r = 1 */
     double ph = lpo_limiter(r);
-    res->phi = ph < 1.0 ? ph : 1.0;
+    res->phi = (c->limiter_cap > 0.0 && ph > c->limiter_cap) ? c->limiter_cap : ph;
     if (res->lw_degenerate || res->vacuum_used) res->phi = 0.0;
     /* a fixed phi isolates one side of the blend (Sec. 2.1) */
     if (c->phi_fixed >= 0.0) res->phi = c->phi_fixed;

@@ -36,6 +36,8 @@ typedef struct {
     int32_t vacuum;       /* free boundary: vacuum ghosts complete half-balls */
     double phi_fixed;     /* >= 0: every particle blends with this phi (1: pure Lax-Wendroff,
                              0: pure upwind) instead of the estimator's; < 0: the estimator */
+    double limiter_cap;   /* > 0: phi = min(phi, limiter_cap); <= 0: the limiter as printed, whose
+                             largest value is 1.25 at r = 1 */
 } lpo_cfg;
 
 int lpo_num_threads(void);

@@ -1,5 +1,6 @@
 """Pins of the full oracle time step (Sec. 2.1 and Sec. 2.2 steps 1-6)."""
 import json
+import math
 import os
 
 import numpy as np
@@ -130,3 +131,39 @@ def test_sod_converges_to_exact_solution(oracle_lib):
     assert e128[0] < 0.02
     x = e128[2]["x"][:, 0]
     assert x.min() > 0.0 and x.max() < 1.0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_momentum_and_energy_sums_closed_form(oracle_lib, dim):
+    """H11 sums on states whose totals are known in closed form:
+    - velocities of equal magnitude v in directions spread evenly over the
+      circle (2D) or in antipodal pairs (3D), equal masses: momentum 0 and
+      energy M (P V / (gamma - 1) + v^2 / 2) with P V the same for everyone;
+    - a constant velocity u0: momentum M u0."""
+    rng = np.random.default_rng(3)
+    n = 720
+    g = 1.4
+    m = np.full(n, 0.25)
+    V = rng.uniform(0.5, 2.0, n)
+    pv = 0.8
+    P = pv / V
+    v = 1.5
+    if dim == 2:
+        th = 2 * np.pi * np.arange(n) / n
+        u = v * np.stack([np.cos(th), np.sin(th)], 1)
+    else:
+        d = rng.standard_normal((n // 2, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        u = v * np.concatenate([d, -d])
+    st = {"x": rng.uniform(0, 1, (n, dim)), "u": np.ascontiguousarray(u), "V": V, "P": P, "m": m}
+    cfg = W.base_config("sums", dim, 2.5, [0] * dim, [1] * dim, [True] * dim)
+    out = oracle_lib.conservation(cfg, st)
+    M = 0.25 * n
+    assert out[0] == M
+    assert np.all(np.abs(out[1:1 + dim]) < 1e-12 * M * v)
+    assert math.isclose(out[4], M * (pv / (g - 1) + 0.5 * v * v), rel_tol=1e-13)
+    u0 = np.array([0.7, -0.3, 0.2])[:dim]
+    st["u"] = np.ascontiguousarray(np.tile(u0, (n, 1)))
+    out = oracle_lib.conservation(cfg, st)
+    assert np.allclose(out[1:1 + dim], M * u0, rtol=1e-13, atol=0)
+    assert math.isclose(out[4], M * (pv / (g - 1) + 0.5 * (u0 ** 2).sum()), rel_tol=1e-13)
