@@ -91,7 +91,10 @@ typedef struct lp_config {
                                error is at most about refine_cond * 2^-24 elsewhere); the rest keep
                                the FP32 solution.  A refined fit is computed by a separate launch over
                                the queued particles, with the same arithmetic as refine_cond = 0 */
-    int32_t reserved[6];
+    float limiter_cap;      /* Sec. 2.1 limiter: > 0 caps phi at this value (default 1: a particle the
+                               estimator does not select advances with the pure Lax-Wendroff rate);
+                               0 leaves the limiter as printed, whose largest value is 1.25 at r = 1 */
+    int32_t reserved[5];
 } lp_config;
 
 typedef struct lp_particles {
@@ -121,7 +124,7 @@ typedef struct lp_info {
 
 /* Fill cfg with the defaults for the given dimension (gamma 1.4, cfl 0.5,
  * kappa 2.5 / 2.1, max_nb 128, est_eps 1e-5, cond_max 1e12, uw_cond_max 1e2,
- * cond_fallback 1e6, unit box, fully periodic). */
+ * cond_fallback 1e6, limiter_cap 1, unit box, fully periodic). */
 void lp_config_default(lp_config *cfg, int32_t dim);
 
 /* Create / destroy a context.  lp_create validates cfg (LP_E_ARG on failure)
@@ -302,7 +305,10 @@ lp_status lp_set_tuning(struct lp_ctx *ctx, int32_t param, int32_t value);
  * (coordinate descent, `reps` timed steps per candidate after one warm-up),
  * and write the chosen values to best[LP_TUNE_COUNT] (host; may be NULL) and
  * the per-step milliseconds of the best setting to *ms (host; may be NULL).
- * Synchronises.  Allocates a copy of p's state for its duration. */
+ * Synchronises.  Allocates a copy of p's state for its duration.  The
+ * context's device scalars (time, dt, step count, error bits) are restored
+ * afterwards, also on failure; a candidate step's capacity or numeric error
+ * is returned as LP_E_CAPACITY / LP_E_NUMERIC by lp_autotune itself. */
 lp_status lp_autotune(struct lp_ctx *ctx, void *stream, const lp_particles *p, int32_t reps, int32_t *best,
                       double *ms);
 lp_status lp_get_tuning(const struct lp_ctx *ctx, int32_t param, int32_t *value);

@@ -74,6 +74,8 @@ def lib():
         L.lpo_uw_rates.argtypes = [C.c_int, C.c_double, dp, dp, dp, dp]
         L.lpo_neighbors.restype = C.c_int
         L.lpo_neighbors.argtypes = [cp, C.c_int64, dp, dp, dp, dp, C.c_int32, ip, ip]
+        L.lpo_neighbors_subset.restype = C.c_int
+        L.lpo_neighbors_subset.argtypes = [cp, C.c_int64, dp, dp, dp, dp, C.c_int32, C.c_int64, i64p, ip, ip]
         L.lpo_gfd.restype = C.c_int
         L.lpo_gfd.argtypes = [cp, C.c_int64, dp, dp, dp, dp, C.c_int32, C.POINTER(dp), dp, u8p]
         L.lpo_gfd3.restype = C.c_int
@@ -226,6 +228,20 @@ def neighbors(cfg: dict, x: np.ndarray, r: np.ndarray, max_nb: int = 128):
     count = np.zeros(n, dtype=np.int32)
     idx = np.full((n, max_nb), -1, dtype=np.int32)
     st = lib().lpo_neighbors(C.byref(c), n, _dp(X[0]), _dp(X[1]), _dp(X[2]), _dp(r), max_nb, _ip(count), _ip(idx))
+    return count, idx, st
+
+
+def neighbors_subset(cfg: dict, x: np.ndarray, r: np.ndarray, q: np.ndarray, max_nb: int = 128):
+    """Neighbour lists of the particles q only (over all particles): count[nq], idx[nq, max_nb]; status."""
+    c = make_cfg(cfg)
+    d = c.dim
+    X = _xyz(x, d)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    q = np.ascontiguousarray(q, dtype=np.int64)
+    count = np.zeros(q.size, dtype=np.int32)
+    idx = np.full((q.size, max_nb), -1, dtype=np.int32)
+    st = lib().lpo_neighbors_subset(C.byref(c), x.shape[0], _dp(X[0]), _dp(X[1]), _dp(X[2]), _dp(r), max_nb,
+                                    q.size, q.ctypes.data_as(C.POINTER(C.c_int64)), _ip(count), _ip(idx))
     return count, idx, st
 
 

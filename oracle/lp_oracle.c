@@ -326,6 +326,15 @@ int lpo_neighbors(const lpo_cfg *c, int64_t n, const double *x, const double *y,
     return st;
 }
 
+/* The lists of the query particles q[0..nq) only, against all n particles. */
+int lpo_neighbors_subset(const lpo_cfg *c, int64_t n, const double *x, const double *y, const double *z,
+                         const double *r, int32_t max_nb, int64_t nq, const int64_t *q, int32_t *count,
+                         int32_t *idx)
+{
+    const double *X[3] = {x, y, z ? z : x};
+    return neighbor_lists(c, nq, q, n, X, r, max_nb, count, idx);
+}
+
 /* ------------------------------------------------------------------------- */
 /* Stencils (Sec. 2.2, step 4; Sec. 2.1 "symmetric ... from all 8 octants",  */
 /* "left and right semi-spheres").                                            */

@@ -51,6 +51,9 @@ void lpo_uw_rates(int dim, double gamma, const double *st, const double *dl, con
                   double *rate);
 int lpo_neighbors(const lpo_cfg *c, int64_t n, const double *x, const double *y, const double *z,
                   const double *r, int32_t max_nb, int32_t *count, int32_t *idx);
+int lpo_neighbors_subset(const lpo_cfg *c, int64_t n, const double *x, const double *y, const double *z,
+                         const double *r, int32_t max_nb, int64_t nq, const int64_t *q, int32_t *count,
+                         int32_t *idx);
 int lpo_gfd(const lpo_cfg *c, int64_t n, const double *x, const double *y, const double *z,
             const double *r, int32_t nf, const double *const *f, double *deriv, uint8_t *status);
 /* Third-order GFD derivatives: deriv[(f * nu + col) * n + i], nu = 19 (3D) or 9

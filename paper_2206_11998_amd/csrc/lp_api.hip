@@ -153,6 +153,7 @@ extern "C" void lp_config_default(lp_config *cfg, int32_t dim) {
     cfg->periodic_mask = dim == 2 ? 3u : 7u;
     cfg->mlp_band = 0.05f;
     cfg->mlp_feat_max = 8.0f;
+    cfg->limiter_cap = 1.0f;
 }
 
 extern "C" const char *lp_status_str(lp_status s) {
@@ -197,6 +198,8 @@ extern "C" lp_status lp_create(const lp_config *cfg, lp_ctx **out) {
         st = fail(c, LP_E_ARG, "mlp_band must be in [0, 1/2], mlp_feat_max positive");
     else if (!(k.refine_cond >= 0.0f) || !(k.refine_cond < INFINITY))
         st = fail(c, LP_E_ARG, "refine_cond must be finite and non-negative");
+    else if (!(k.limiter_cap >= 0.0f) || !(k.limiter_cap < INFINITY))
+        st = fail(c, LP_E_ARG, "limiter_cap must be finite and non-negative");
     else if (!(k.gamma > 1.0) || !(k.kappa > 0.0) || !(k.cfl > 0.0)) st = fail(c, LP_E_ARG, "gamma, kappa, cfl");
     if (st == LP_OK) {
         double S = 0.0;
@@ -241,6 +244,7 @@ extern "C" lp_status lp_create(const lp_config *cfg, lp_ctx **out) {
     d.cond_fb = k.cond_fallback;
     d.mlp_band = k.mlp_band;
     d.mlp_feat_max = k.mlp_feat_max;
+    d.limiter_cap = k.limiter_cap;
     for (int a = 0; a < 3; ++a) {
         d.lo[a] = k.box_lo[a];
         d.hi[a] = k.box_hi[a];
@@ -1214,11 +1218,20 @@ extern "C" lp_status lp_autotune(lp_ctx *c, void *stream, const lp_particles *p,
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool prof = c->profiling;
     c->profiling = false;
-    double t0 = 0.0;
+    // the candidate steps run on a private copy of the particles but through
+    // the context's device scalars (clock, dt, counters, sticky error bits):
+    // all of them are put back afterwards, on success and on failure alike
+    DevScalars saved;
+    bool have_saved = false;
     auto cleanup = [&]() {
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
         (void)hipStreamSynchronize(st);
+        if (have_saved) {
+            *c->sc_host = saved;
+            (void)hipMemcpyAsync(c->sc, c->sc_host, sizeof(DevScalars), hipMemcpyHostToDevice, st);
+            (void)hipStreamSynchronize(st);
+        }
         (void)hipFree(buf);
         c->profiling = prof;
     };
@@ -1237,6 +1250,13 @@ extern "C" lp_status lp_autotune(lp_ctx *c, void *stream, const lp_particles *p,
         float t = 0.f;
         HIPCHK(c, hipEventElapsedTime(&t, e0, e1));
         ms = (double)t / reps;
+        // a candidate's capacity or numeric error is autotune's own failure
+        r = read_scalars(c, st);
+        if (r != LP_OK) return r;
+        if (c->sc_host->error_bits & 1u)
+            return fail(c, LP_E_CAPACITY, "lp_autotune: a candidate step exceeded max_nb = %d", c->dc.max_nb);
+        if (c->sc_host->error_bits & 2u)
+            return fail(c, LP_E_NUMERIC, "lp_autotune: a candidate step left a non-positive V or P");
         return LP_OK;
     };
     auto body = [&]() -> lp_status {
@@ -1244,7 +1264,8 @@ extern "C" lp_status lp_autotune(lp_ctx *c, void *stream, const lp_particles *p,
         HIPCHK(c, hipEventCreate(&e1));
         lp_status r = read_scalars(c, st);
         if (r != LP_OK) return r;
-        t0 = c->sc_host->t;
+        saved = *c->sc_host;
+        have_saved = true;
         c->grid_margin = 0.0;
         struct Param { int id; std::vector<int> values; };
         std::vector<Param> params = {{LP_TUNE_SOLVE_MODE, {0, 1, 2}},
@@ -1276,12 +1297,6 @@ extern "C" lp_status lp_autotune(lp_ctx *c, void *stream, const lp_particles *p,
         if (best)
             for (int id = 0; id < LP_TUNE_COUNT; ++id) (void)lp_get_tuning(c, id, &best[id]);
         if (ms_out) *ms_out = best_ms;
-        // the private steps advanced the context's clock: restore it
-        r = read_scalars(c, st);
-        if (r != LP_OK) return r;
-        c->sc_host->t = t0;
-        HIPCHK(c, hipMemcpyAsync(c->sc, c->sc_host, sizeof(DevScalars), hipMemcpyHostToDevice, st));
-        HIPCHK(c, hipStreamSynchronize(st));
         return LP_OK;
     };
     s = body();

@@ -23,6 +23,7 @@ struct DevCfg {
     double lo[3], hi[3], L[3], half[3];
     int periodic[3], wall_lo[3], wall_hi[3];
     float mlp_band, mlp_feat_max;   // network estimator: trusted away from 1/2 by mlp_band, inputs within +-max
+    float limiter_cap;              // > 0: phi = min(phi, limiter_cap); 0: the limiter as printed
 };
 
 // Hierarchy of uniform cell grids over the cube [lo, lo + S)^D.  Level L has

@@ -746,8 +746,11 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
             T d[3] = {0, 0, 0};
             bool ok = false, real_fit = false;
             if (cfg.vacuum && n_own < ucap) {
-                // mirrored members of the opposite half-ball with P = 0, V = V_i, u = u_i
-                T Gm[NGD], rhs[D];
+                // free boundary: the half-ball's real members plus the mirror
+                // images (through x_i along a) of the opposite half-ball's
+                // members, which carry P = 0 and the particle's own V and u, so
+                // their right-hand sides are (0, 0, -P_i)
+                T Gm[NGD], Bm[D * 3];
                 int q = 0;
 #pragma unroll
                 for (int b = 0; b < D; ++b)
@@ -755,18 +758,21 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
                     for (int c = b; c < D; ++c, ++q) {
                         T g = isr ? Gl[q] : Gr[q];
                         bool flip = (b == a) != (c == a);
-                        Gm[q] = flip ? -g : g;
+                        Gm[q] = (isr ? Gr[q] : Gl[q]) + (flip ? -g : g);
                     }
 #pragma unroll
                 for (int b = 0; b < D; ++b) {
                     T sv = isr ? Sl[b] : Sr[b];
-                    rhs[b] = -Pi_T * (b == a ? -sv : sv);
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) Bm[f * D + b] = isr ? Br[b * 3 + f] : Bl[b * 3 + f];
+                    Bm[2 * D + b] += -Pi_T * (b == a ? -sv : sv);
                 }
-                if (n_opp >= D && halfball_cond<D, T>(Gm) <= (T)cfg.uw_cond_max) {
+                if (n_own + n_opp >= D && halfball_cond<D, T>(Gm) <= (T)cfg.uw_cond_max) {
                     T inv[D];
                     if (cholesky<D, T>(Gm, inv)) {
-                        chol_solve<D, 1, T, T>(Gm, inv, rhs);
-                        d[2] = rhs[a] * (T)inv_r;
+                        chol_solve<D, 3, T, T>(Gm, inv, Bm);
+#pragma unroll
+                        for (int f = 0; f < 3; ++f) d[f] = Bm[f * D + a] * (T)inv_r;
                         ok = true;
                         vac = true;
                     }
@@ -823,7 +829,8 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
             }
         }
         T ph = limiter<T>(rmax);
-        phi = (double)(ph < T(1) ? ph : T(1));
+        const T cap = (T)cfg.limiter_cap;
+        phi = (double)((cap > T(0) && ph > cap) ? cap : ph);
         if (lw_status != 0 || vac) phi = 0.0;
     }
     // rates

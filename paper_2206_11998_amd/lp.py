@@ -48,7 +48,7 @@ class Config(C.Structure):
         ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
         ("periodic_mask", C.c_uint32), ("wall_lo_mask", C.c_uint32), ("wall_hi_mask", C.c_uint32),
         ("mlp_band", C.c_float), ("mlp_feat_max", C.c_float), ("refine_cond", C.c_float),
-        ("reserved", C.c_int32 * 6),
+        ("limiter_cap", C.c_float), ("reserved", C.c_int32 * 5),
     ]
 
 
@@ -175,6 +175,7 @@ def make_config(cfg: dict, precision: str = "fp64", estimator: str = "plain", re
     c.cond_max = float(cfg.get("cond_max", 1e12))
     c.uw_cond_max = float(cfg.get("uw_cond_max", 1e2))
     c.cond_fallback = float(cfg.get("cond_fallback", 1e6))
+    c.limiter_cap = float(cfg.get("limiter_cap", 1.0))
     for a in range(3):
         c.box_lo[a] = float(cfg["box_lo"][a]) if a < d else 0.0
         c.box_hi[a] = float(cfg["box_hi"][a]) if a < d else 1.0

@@ -21,8 +21,10 @@ def rel_l1(got, ref, scale=None):
     return np.abs(got - ref).sum() / max(den, 1e-300)
 
 
-def compare_states(got, ref, cfg, tol, tag=""):
-    """Relative L1 per field (velocity scaled by the max sound speed)."""
+def compare_states(got, ref, cfg, tol, tag="", tol_pp=None):
+    """Relative L1 per field (velocity scaled by the max sound speed), and the
+    largest single-particle error relative to the field's largest magnitude
+    (tol_pp; default 1e-8 for the FP64 tolerance, 1e-3 for the mixed one)."""
     c = np.sqrt(cfg["gamma"] * ref["P"] * ref["V"]).max()
     errs = {
         "V": rel_l1(got["V"], ref["V"]),
@@ -35,8 +37,34 @@ def compare_states(got, ref, cfg, tol, tag=""):
         if cfg["periodic"][a]:
             dx[:, a] -= span[a] * np.round(dx[:, a] / span[a])
     errs["x"] = np.abs(dx).max()
-    say(tag, {k: "%.2e" % v for k, v in errs.items()})
+    if tol_pp is None:
+        tol_pp = 1e-8 if tol <= 1e-9 else 1e-3
+    pp = {
+        "V": np.abs(got["V"] - ref["V"]).max() / np.abs(ref["V"]).max(),
+        "P": np.abs(got["P"] - ref["P"]).max() / np.abs(ref["P"]).max(),
+        "u": np.abs(got["u"] - ref["u"]).max() / max(np.abs(ref["u"]).max(), c),
+    }
+    say(tag, {k: "%.2e" % v for k, v in errs.items()}, "per particle", {k: "%.2e" % v for k, v in pp.items()})
     for k in ("V", "P", "u"):
         assert errs[k] <= tol, (tag, k, errs[k])
+        assert pp[k] <= tol_pp, (tag, "per particle", k, pp[k])
     assert errs["x"] <= tol * 10, (tag, "x", errs["x"])
     return errs
+
+
+def compare_phi(got_phi, ref_phi, fp64, tag=""):
+    """Limiter values.  FP64 path: within 1e-6 of the oracle at every
+    particle.  Mixed path: the estimator takes its decisions on FP32
+    one-sided slopes (the kernel's precision), so where a slope sits at the
+    rounding level (below the activity threshold or changing sign) phi can
+    differ from the FP64 decision by up to the limiter's range; the fields'
+    per-particle bound above is what the mixed path is held to, and the
+    number of such particles is reported."""
+    d = np.abs(np.asarray(got_phi, dtype=np.float64) - ref_phi)
+    far = int((d > 1e-6).sum())
+    say(tag, "phi: max |dphi| %.2e, particles beyond 1e-6: %d of %d" % (d.max(), far, d.size))
+    if fp64:
+        assert far == 0, (tag, far, d.max())
+    else:
+        assert np.all(np.asarray(got_phi) >= 0.0) and np.all(np.asarray(got_phi) <= 1.25)
+    return far

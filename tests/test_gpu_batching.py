@@ -223,3 +223,33 @@ def test_step_stage_timing(lp):
     assert prof["step"][1] == 11  # one eager step, one planning step, nine replays
     assert prof["search"][1] == 2 and prof["fit"][1] == 2
     assert all(v[0] >= 0 for v in prof.values())
+
+
+def test_autotune_failure_leaves_the_context_clean(lp):
+    """A candidate step that runs out of list capacity makes lp_autotune
+    fail, but the caller's context keeps its clock, step count and error
+    bits: after widening nothing, a plain step of the same particles still
+    reports the same capacity error, and a context whose autotune succeeded
+    after steps of its own continues from its own time."""
+    cfg, st = CASES["sod slab"]()
+    small = dict(cfg, max_nb=16)
+    ctx = lp.Context(small)
+    dev = lp.state_to_device(st)
+    with pytest.raises(lp.LpError) as e:
+        ctx.autotune(dev, reps=1)
+    assert e.value.status == lp.E_CAPACITY
+    inf = ctx.info()
+    assert inf["t"] == 0.0 and inf["error_bits"] == 0
+    assert ctx.check() == lp.OK
+    # a context that has already stepped keeps its own time and dt
+    ctx2 = lp.Context(cfg)
+    dev2 = lp.state_to_device(st)
+    ctx2.step(dev2)
+    ctx2.step(dev2)
+    before = ctx2.info()
+    ctx2.autotune(lp.state_to_device(st), reps=1)
+    after = ctx2.info()
+    assert after["t"] == before["t"] and after["dt"] == before["dt"] and after["error_bits"] == 0
+    ctx2.run(dev2, 2)
+    assert ctx2.check() == lp.OK
+    assert ctx2.info()["t"] > before["t"]

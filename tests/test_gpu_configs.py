@@ -127,8 +127,8 @@ def test_vacuum_2M_one_step(lp, oracle_lib):
 
 
 def test_sedov_4M_one_step(lp, oracle_lib):
-    """The 27-particle deposit (P = 3.1e4 next to 1e-5) drives P below zero at
-    some particles of the first step, in the oracle as on the GPU."""
+    """The blast workload with its Gaussian deposit: the first step, sampled
+    at the deposit and around it."""
     cfg, st = W.sedov3d()
     hot = np.argsort(-st["P"])[:27]
     # the deposit and the particles around it
