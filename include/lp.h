@@ -145,6 +145,24 @@ lp_status lp_destroy(struct lp_ctx *ctx);
 lp_status lp_neighbors(struct lp_ctx *ctx, void *stream, int64_t n, const double *x, const double *y,
                        const double *z, const double *r, int32_t *count, int32_t *idx);
 
+/* lp_neighbors for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same lists, bit for bit, computed in a static scratch block of
+ * LP_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs on
+ * until the process ends.  No hipMalloc, hipFree or allocating library call
+ * is made; the context's own workspace is left untouched.  The block must
+ * hold the call's whole workspace (about 4 * max_nb + 100 bytes per particle
+ * plus the cell tables: some 100,000 particles at max_nb 128); a larger call
+ * returns LP_E_NOMEM with nothing written to count or idx (LP_E_CAPACITY
+ * keeps lp_neighbors' meaning: a list longer than max_nb).  The context's
+ * device must be current (LP_E_STATE otherwise).  Every call on a device
+ * uses that device's one block: calls that overlap in time on one device
+ * (other streams, other threads, other contexts) race and must be
+ * serialised by the caller.  Synchronises like lp_neighbors. */
+#define LP_NOALLOC_SCRATCH_BYTES (64u << 20)
+lp_status lp_neighbors_noalloc(struct lp_ctx *ctx, void *stream, int64_t n, const double *x, const double *y,
+                               const double *z, const double *r, int32_t *count, int32_t *idx);
+
 /* Second-order GFD derivatives (Sec. 2.1): for each particle i, the
  * least-squares fit over its Lax-Wendroff stencil (neighbours within r[i],
  * octant round-robin order, first lw_cap) of

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include <algorithm>
+#include <mutex>
 
 #include "lp_internal.h"
 
@@ -67,7 +68,22 @@ struct lp_ctx {
     bool mlp_ready = false;         // network parameters set
     bool want_stage = false;        // keep network-estimator staging allocated (lp_features)
     int queue_tile = 1024;          // LP_TUNE_QUEUE_TILE
+    // while set, ensure() carves buffers out of this device block instead of
+    // allocating (lp_neighbors_noalloc)
+    char *arena = nullptr;
+    size_t arena_bytes = 0, arena_used = 0;
 };
+
+// every workspace buffer of a context, for swapping the whole set out and back
+static Buf lp_ctx::*const kBufs[] = {
+    &lp_ctx::h, &lp_ctx::r, &lp_ctx::gcnt, &lp_ctx::scan_tmp, &lp_ctx::ghosts, &lp_ctx::key, &lp_ctx::slot,
+    &lp_ctx::tables, &lp_ctx::sorted, &lp_ctx::srec, &lp_ctx::srecf, &lp_ctx::sid, &lp_ctx::nbr, &lp_ctx::count,
+    &lp_ctx::queue, &lp_ctx::partials, &lp_ctx::consout, &lp_ctx::gfd_fields, &lp_ctx::hitd2, &lp_ctx::hitj,
+    &lp_ctx::tflags, &lp_ctx::tlo, &lp_ctx::thi, &lp_ctx::prep_part, &lp_ctx::ovfq, &lp_ctx::der, &lp_ctx::lwst,
+    &lp_ctx::wq, &lp_ctx::rq, &lp_ctx::rkeep, &lp_ctx::mfeat, &lp_ctx::mrates, &lp_ctx::mphi, &lp_ctx::mflag,
+    &lp_ctx::theta, &lp_ctx::adam_m, &lp_ctx::adam_v, &lp_ctx::mgrad, &lp_ctx::mpart, &lp_ctx::mlosspart,
+    &lp_ctx::mscal};
+constexpr int kNumBufs = (int)(sizeof kBufs / sizeof kBufs[0]);
 
 static lp_status fail(lp_ctx *c, lp_status s, const char *fmt, ...) {
     if (c) {
@@ -90,6 +106,15 @@ static lp_status fail(lp_ctx *c, lp_status s, const char *fmt, ...) {
 static lp_status ensure(lp_ctx *c, Buf &b, size_t bytes) {
     if (b.bytes >= bytes) return LP_OK;
     ++c->gen;  // captured graphs hold the old address
+    if (c->arena) {
+        size_t off = (c->arena_used + 255) & ~(size_t)255;
+        if (off > c->arena_bytes || bytes > c->arena_bytes - off)
+            return fail(c, LP_E_NOMEM, "the workspace needs more than the %zu-byte scratch block", c->arena_bytes);
+        b.p = c->arena + off;
+        b.bytes = bytes;
+        c->arena_used = off + bytes;
+        return LP_OK;
+    }
     if (b.p) (void)hipFree(b.p);
     b.p = nullptr;
     b.bytes = 0;
@@ -134,6 +159,36 @@ static void stage_mark(lp_ctx *c, hipStream_t st, int stage, bool begin) {
         lp_status s_ = ensure(ctx, buf, bytes);        \
         if (s_ != LP_OK) return s_;                    \
     } while (0)
+
+// Scratch block of lp_neighbors_noalloc: one per device, held until the
+// process ends.  In host code `scratch` names a host-side stand-in; the
+// device address comes from hipGetSymbolAddress, once per device, in
+// lp_create, and only that address is ever passed on.
+#define LP_SCRATCH_MAX_DEVICES 64
+static __device__ __align__(256) unsigned char scratch[LP_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[LP_SCRATCH_MAX_DEVICES];
+static hipError_t g_scratch_err[LP_SCRATCH_MAX_DEVICES];
+
+static void scratch_setup(int device) {
+    if (device < 0 || device >= LP_SCRATCH_MAX_DEVICES) return;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return;
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess && p) g_scratch_ptr[device] = p;
+    else {
+        g_scratch_err[device] = e == hipSuccess ? hipErrorInvalidSymbol : e;
+        (void)hipGetLastError();
+    }
+}
+
+static void *scratch_ptr(int device, hipError_t *err) {
+    if (device < 0 || device >= LP_SCRATCH_MAX_DEVICES) { *err = hipErrorInvalidDevice; return nullptr; }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    *err = g_scratch_err[device];
+    return g_scratch_ptr[device];
+}
 
 extern "C" void lp_config_default(lp_config *cfg, int32_t dim) {
     memset(cfg, 0, sizeof *cfg);
@@ -256,6 +311,7 @@ extern "C" lp_status lp_create(const lp_config *cfg, lp_ctx **out) {
         c->nwalls += d.wall_lo[a] + d.wall_hi[a];
     }
     (void)hipGetDevice(&c->device);
+    scratch_setup(c->device);
     if (hipMalloc((void **)&c->sc, sizeof(DevScalars)) != hipSuccess ||
         hipHostMalloc((void **)&c->sc_host, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
@@ -853,6 +909,51 @@ extern "C" lp_status lp_neighbors(lp_ctx *c, void *stream, int64_t n, const doub
     if (c->sc_host->max_count > c->dc.max_nb) return fail(c, LP_E_CAPACITY, "neighbour count %d exceeds max_nb %d",
                                                           c->sc_host->max_count, c->dc.max_nb);
     return LP_OK;
+}
+
+extern "C" lp_status lp_neighbors_noalloc(lp_ctx *c, void *stream, int64_t n, const double *x, const double *y,
+                                          const double *z, const double *r, int32_t *count, int32_t *idx) {
+    if (!c) return LP_E_ARG;
+    if (n <= 0 || n > (1ll << 30) || !x || !y || (c->dc.D == 3 && !z) || !r || !count || !idx)
+        return fail(c, LP_E_ARG, "lp_neighbors_noalloc: bad arguments");
+    int dev = -1;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev != c->device)
+        return fail(c, LP_E_STATE, "lp_neighbors_noalloc: device %d is current, the context's is %d", dev, c->device);
+    hipError_t serr = hipSuccess;
+    void *block = scratch_ptr(c->device, &serr);
+    if (!block)
+        return fail(c, LP_E_DEVICE, "lp_neighbors_noalloc: no scratch block on device %d (%s)", c->device,
+                    hipGetErrorString(serr));
+    // swap every workspace buffer out, run lp_neighbors on buffers carved
+    // from the scratch block, then put the context's own buffers back
+    Buf saved[kNumBufs];
+    for (int q = 0; q < kNumBufs; ++q) {
+        saved[q] = c->*kBufs[q];
+        c->*kBufs[q] = Buf{};
+    }
+    const int64_t cr = c->cap_real, ct = c->cap_total, cg = c->cap_ghost;
+    const DevGrid grid = c->grid;
+    const double S_grid = c->S_grid;
+    const bool prof = c->profiling;
+    c->cap_real = c->cap_total = c->cap_ghost = 0;
+    c->profiling = false;
+    c->arena = (char *)block;
+    c->arena_bytes = LP_NOALLOC_SCRATCH_BYTES;
+    c->arena_used = 0;
+    lp_status s = lp_neighbors(c, stream, n, x, y, z, r, count, idx);
+    if (s != LP_OK) (void)hipStreamSynchronize((hipStream_t)stream);
+    c->arena = nullptr;
+    c->arena_bytes = c->arena_used = 0;
+    for (int q = 0; q < kNumBufs; ++q) c->*kBufs[q] = saved[q];
+    c->cap_real = cr;
+    c->cap_total = ct;
+    c->cap_ghost = cg;
+    c->grid = grid;
+    c->S_grid = S_grid;
+    c->profiling = prof;
+    ++c->gen;
+    return s;
 }
 
 // lp_gfd (order 2) and lp_gfd3 (order 3): cells, search and the fit of the

@@ -19,7 +19,7 @@ FP64, MIXED = 0, 1
 EST_PLAIN, EST_INJECTED, EST_MLP = 0, 1, 2
 FLAG_LIMITED, FLAG_DEGENERATE, FLAG_VACUUM, FLAG_SUBSTITUTED, FLAG_FALLBACK, FLAG_NUMERIC = 1, 2, 4, 8, 16, 32
 
-EXPORTS = ["lp_config_default", "lp_create", "lp_destroy", "lp_neighbors", "lp_gfd", "lp_gfd3", "lp_outflow",
+EXPORTS = ["lp_config_default", "lp_create", "lp_destroy", "lp_neighbors", "lp_neighbors_noalloc", "lp_gfd", "lp_gfd3", "lp_outflow",
            "lp_reservoir_inflow", "lp_inflow_layer", "lp_step", "lp_run",
            "lp_conservation", "lp_check", "lp_get_info", "lp_set_time", "lp_profile", "lp_profile_read",
            "lp_set_tuning", "lp_get_tuning", "lp_autotune", "lp_train_cfg_default", "lp_features", "lp_mlp_init",
@@ -93,6 +93,8 @@ def lib():
         L.lp_destroy.argtypes = [vp]
         L.lp_neighbors.restype = i32
         L.lp_neighbors.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
+        L.lp_neighbors_noalloc.restype = i32
+        L.lp_neighbors_noalloc.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
         L.lp_gfd.restype = i32
         L.lp_gfd.argtypes = [vp, vp, i64, vp, vp, vp, vp, i32, C.POINTER(vp), vp, vp]
         L.lp_outflow.restype = i32
@@ -277,6 +279,14 @@ class Context:
         if st not in (OK, E_CAPACITY):
             self._raise(st)
         return count, idx, st
+
+    def neighbors_noalloc(self, x, r, count, idx, stream=None):
+        """lp_neighbors_noalloc into the caller's count[n] / idx[n, max_nb]
+        (int32 CUDA tensors); returns the status."""
+        n = r.shape[0]
+        z = x[2] if self.dim == 3 else None
+        return lib().lp_neighbors_noalloc(self._h, _stream_ptr(stream), n, _ptr(x[0]), _ptr(x[1]), _ptr(z), _ptr(r),
+                                          _ptr(count), _ptr(idx))
 
     def gfd(self, x, r, fields, stream=None):
         """Second-order GFD derivatives: deriv[f, c, i], status[i]."""
