@@ -120,6 +120,8 @@ typedef struct lp_info {
     int64_t n_mlp;          /* LP_EST_MLP: particles whose phi came from the network in the last step */
     int64_t n_mlp_plain;    /* LP_EST_MLP: particles that fell back to the quotient estimator */
     int64_t n_refined;      /* LP_MIXED with refine: fits refined in the last step */
+    int64_t n_list_builds;  /* full neighbour searches of the steps so far (LP_TUNE_LIST_SKIN: the
+                               steps in between reuse their candidate lists) */
 } lp_info;
 
 /* Fill cfg with the defaults for the given dimension (gamma 1.4, cfl 0.5,
@@ -312,13 +314,22 @@ enum {
                                   are redone by an overflow kernel): 0 (default) = chosen by each
                                   planning step from the previous step's longest list, else a
                                   multiple of 8 in 8..128 */
-    LP_TUNE_COUNT = 6
+    LP_TUNE_LIST_SKIN = 6,     /* neighbour-list reuse across time steps, in per mille of r: 0 = a full
+                                  search every step; s > 0 (default 150) = a full search within
+                                  (1 + s/1000) r only when the last one may miss a neighbour (checked on
+                                  the device each step from the displacements since that search and
+                                  the growth of r), and in between the exact test d2 < r_i^2 and the
+                                  (d2, id) ranking over those candidates.  Used by lp_step / lp_run
+                                  without mirror walls and with search mode 2; the lists are the full
+                                  search's bit for bit.  Candidate lists must fit max_nb. */
+    LP_TUNE_COUNT = 7
 };
 lp_status lp_set_tuning(struct lp_ctx *ctx, int32_t param, int32_t value);
 
 /* Autotuner: time full steps of a private copy of p (p itself is not
- * modified) for every launch-shape setting in turn -- the solve mode, the
- * queue tile, the fit/update block size, the search mode and group -- keep the
+ * modified) for every launch-shape setting in turn -- the list skin, the
+ * solve mode, the queue tile, the fit/update block size, the search mode and
+ * group -- keep the
  * fastest setting of each
  * (coordinate descent, `reps` timed steps per candidate after one warm-up),
  * and write the chosen values to best[LP_TUNE_COUNT] (host; may be NULL) and

@@ -34,7 +34,8 @@ struct lp_ctx {
     Buf h, r, gcnt, scan_tmp, ghosts, key, slot, tables, sorted, srec, srecf, sid, nbr, count, queue, partials, consout,
         gfd_fields, hitd2, hitj, tflags, tlo, thi, prep_part, ovfq, der, lwst, wq, rq, rkeep,
         mfeat, mrates, mphi, mflag,                          // network-estimator staging
-        theta, adam_m, adam_v, mgrad, mpart, mlosspart, mscal; // network parameters and training
+        theta, adam_m, adam_v, mgrad, mpart, mlosspart, mscal, // network parameters and training
+        cand, ccount, xb, Rb, fovfq;                         // neighbour-list reuse
     int search_mode = 2;            // 0: lane group walking its cells, 1: LDS-staged tiles, 2: balanced lane group
     int solve_block = 256;
     DevScalars *sc = nullptr;       // device scalars
@@ -68,6 +69,12 @@ struct lp_ctx {
     bool mlp_ready = false;         // network parameters set
     bool want_stage = false;        // keep network-estimator staging allocated (lp_features)
     int queue_tile = 1024;          // LP_TUNE_QUEUE_TILE
+    // neighbour-list reuse (LP_TUNE_LIST_SKIN): candidate radius (1 + skin/1000) r
+    int list_skin = 150;
+    uint64_t reuse_gen = 0;         // workspace generation the device candidate set belongs to
+    lp_particles reuse_p;           // particle arrays it was built for
+    int reuse_skin = -1;            // skin it was built with
+    int search_lcap_cand = 0;       // LDS list slots of the rebuild search (from the longest candidate list)
     // while set, ensure() carves buffers out of this device block instead of
     // allocating (lp_neighbors_noalloc)
     char *arena = nullptr;
@@ -82,7 +89,7 @@ static Buf lp_ctx::*const kBufs[] = {
     &lp_ctx::tflags, &lp_ctx::tlo, &lp_ctx::thi, &lp_ctx::prep_part, &lp_ctx::ovfq, &lp_ctx::der, &lp_ctx::lwst,
     &lp_ctx::wq, &lp_ctx::rq, &lp_ctx::rkeep, &lp_ctx::mfeat, &lp_ctx::mrates, &lp_ctx::mphi, &lp_ctx::mflag,
     &lp_ctx::theta, &lp_ctx::adam_m, &lp_ctx::adam_v, &lp_ctx::mgrad, &lp_ctx::mpart, &lp_ctx::mlosspart,
-    &lp_ctx::mscal};
+    &lp_ctx::mscal, &lp_ctx::cand, &lp_ctx::ccount, &lp_ctx::xb, &lp_ctx::Rb, &lp_ctx::fovfq};
 constexpr int kNumBufs = (int)(sizeof kBufs / sizeof kBufs[0]);
 
 static lp_status fail(lp_ctx *c, lp_status s, const char *fmt, ...) {
@@ -333,13 +340,8 @@ extern "C" lp_status lp_destroy(lp_ctx *c) {
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-    Buf *bufs[] = {&c->h, &c->r, &c->gcnt, &c->scan_tmp, &c->ghosts, &c->key, &c->slot, &c->tables, &c->sorted,
-                   &c->srec, &c->srecf, &c->sid, &c->nbr, &c->count, &c->queue, &c->partials, &c->consout, &c->gfd_fields,
-                   &c->hitd2, &c->hitj, &c->tflags, &c->tlo, &c->thi, &c->prep_part, &c->ovfq, &c->der, &c->lwst,
-                   &c->wq, &c->rq, &c->rkeep, &c->mfeat, &c->mrates, &c->mphi, &c->mflag, &c->theta, &c->adam_m, &c->adam_v,
-                   &c->mgrad, &c->mpart, &c->mlosspart, &c->mscal};
-    for (Buf *b : bufs)
-        if (b->p) (void)hipFree(b->p);
+    for (int q = 0; q < kNumBufs; ++q)
+        if ((c->*kBufs[q]).p) (void)hipFree((c->*kBufs[q]).p);
     if (c->sc) (void)hipFree(c->sc);
     if (c->sc_host) (void)hipHostFree(c->sc_host);
     delete c;
@@ -461,6 +463,11 @@ static uint64_t table_words(const lp_ctx *c) {
 
 // Allocate everything that depends on the particle counts and the grid.
 // Arrays in cell order use the capacity cap_total as their stride.
+// Neighbour lists reused between steps: a time step, no mirror walls (the
+// ghost set would change with the positions), the balanced search, skin > 0.
+static bool reuse_on(const lp_ctx *c) { return c->list_skin > 0 && c->nwalls == 0 && c->search_mode == 2; }
+static double reuse_scale(const lp_ctx *c) { return 1.0 + c->list_skin / 1000.0; }
+
 static lp_status ensure_capacity(lp_ctx *c, int64_t n_real, int64_t n_total, bool state, bool mixed) {
     const int D = c->dc.D;
     if (n_total > c->cap_total) c->cap_total = n_total;
@@ -485,6 +492,13 @@ static lp_status ensure_capacity(lp_ctx *c, int64_t n_real, int64_t n_total, boo
     ENSURE(c, c->count, sizeof(int) * nt);
     ENSURE(c, c->queue, sizeof(int) * nt);
     ENSURE(c, c->ovfq, sizeof(int) * nt);
+    if (state && reuse_on(c)) {
+        ENSURE(c, c->cand, sizeof(int) * (size_t)c->dc.max_nb * nt);
+        ENSURE(c, c->ccount, sizeof(int) * nt);
+        ENSURE(c, c->xb, sizeof(double) * 3 * nr);
+        ENSURE(c, c->Rb, sizeof(double) * nr);
+        ENSURE(c, c->fovfq, sizeof(int) * nt);
+    }
     if (state) {
         ENSURE(c, c->der, sizeof(double) * (size_t)der_count(D) * nt);
         ENSURE(c, c->lwst, (size_t)nt);
@@ -558,18 +572,19 @@ static Ghosts ghost_view(lp_ctx *c) {
 }
 
 // Cell-order layout of n_total particles: keys, counting sort, level tables.
+// gate (may be NULL): the cells are rebuilt only where *gate != 0 on the device
 static void build_cells(lp_ctx *c, hipStream_t st, const double *const x[3], const double *const gx[3], int n_real,
-                        int64_t n_total) {
+                        int64_t n_total, const unsigned *gate = nullptr) {
     const int D = c->dc.D;
     const DevGrid &g = c->grid;
     uint32_t *tabs = (uint32_t *)c->tables.p;
     uint32_t *finest = tabs + g.off[g.L_hi];
     uint64_t nfin = 1ull << (D * g.L_hi);
-    launch_fill_u32(finest, nfin + 1, 0u, st);
+    launch_fill_u32(finest, nfin + 1, 0u, st, gate);
     int *n_total_dev = &c->sc->n_total;
     launch_keys(x, gx, n_real, n_total_dev, (int)n_total, g, D, (uint32_t *)c->key.p, (uint32_t *)c->slot.p, finest,
-                st);
-    launch_scan_u32(finest, nfin, (uint32_t *)c->scan_tmp.p, nullptr, st);
+                st, gate);
+    launch_scan_u32(finest, nfin, (uint32_t *)c->scan_tmp.p, nullptr, st, gate);
 }
 
 // Output buffers of lp_features (caller order, device).
@@ -657,12 +672,38 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
             c->search_lcap = lcap;
             ++c->gen;  // a captured step holds the old buffer size
         }
+        // the same for the rebuild search of reused lists (its lists are the candidates)
+        const int prevc = c->sc_host->max_cand;
+        int lcc = prevc > 0 ? (prevc + 8 + 15) / 16 * 16 : 0;
+        if (lcc > 128) lcc = 0;
+        if (lcc != c->search_lcap_cand) {
+            c->search_lcap_cand = lcc;
+            ++c->gen;
+        }
     } else {
         n_total = c->cap_total;
     }
     // ghosts admitted: what both the ghost arrays and the cell-order arrays hold
     const int64_t gcap = c->nwalls ? std::min<int64_t>(c->cap_ghost, c->cap_total - n) : 0;
     launch_gate(c->sc, n, gcap, clip_t_end, st);  // lp_run's steps stop at a reported error
+    // neighbour-list reuse: the device decides per step whether the
+    // candidate lists of the last rebuild still cover every neighbour; a
+    // rebuild is forced when the workspace, the grid, the particle arrays or
+    // the skin changed since they were built (host state, so only eager and
+    // planning steps can force one: a captured step is replayed on the same)
+    const bool reuse = reuse_on(c);
+    const unsigned *gate = nullptr;
+    if (reuse) {
+        const bool same = c->reuse_gen == c->gen && c->reuse_skin == c->list_skin &&
+                          memcmp(&c->reuse_p, p, sizeof *p) == 0;
+        double *xb[3] = {(double *)c->xb.p, (double *)c->xb.p + c->cap_real, (double *)c->xb.p + 2 * c->cap_real};
+        launch_reuse(soa, c->dc, (const double *)c->r.p, xb, (double *)c->Rb.p, n, reuse_scale(c), same ? 0 : 1,
+                     c->sc, st);
+        c->reuse_gen = c->gen;
+        c->reuse_skin = c->list_skin;
+        c->reuse_p = *p;
+        gate = &c->sc->rebuild;
+    }
     Ghosts gh = ghost_view(c);
     stage_mark(c, st, 1, true);
     if (c->nwalls)
@@ -670,7 +711,7 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
                            (const double *)c->r.p, gh, c->cap_ghost, st);
     const double *gx[3] = {gh.x[0], gh.x[1], gh.x[2]};
     const double *x[3] = {p->x[0], p->x[1], D == 3 ? p->x[2] : p->x[1]};
-    build_cells(c, st, x, gx, n, n_total);
+    build_cells(c, st, x, gx, n, n_total, gate);
     Sorted srt = sorted_view(c, true);
     ScatterArgs sa;
     memset(&sa, 0, sizeof sa);
@@ -692,11 +733,23 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
     const uint32_t *start = (const uint32_t *)c->tables.p + c->grid.off[c->grid.L_hi];
     launch_scatter(sa, n, &c->sc->n_total, (int)n_total, (const uint32_t *)c->key.p, (const uint32_t *)c->slot.p, start,
                    srt.id, st);
-    launch_coarsen((uint32_t *)c->tables.p, c->grid, D, &c->sc->n_total, st);
+    launch_coarsen((uint32_t *)c->tables.p, c->grid, D, &c->sc->n_total, st, gate);
     stage_mark(c, st, 1, false);
     int ldn = list_ldn(c);
     stage_mark(c, st, 2, true);
-    run_search(c, srt, n_total, n, c->search_cap ? c->search_cap : c->search_lcap, st);
+    if (reuse) {
+        // rebuild steps: the candidates within (1 + skin) r; every step: the exact lists from them
+        launch_search(srt, &c->sc->n_total, (int)n_total, n, (const uint32_t *)c->tables.p, c->grid, c->dc,
+                      (int *)c->cand.p, ldn, (int *)c->ccount.p, c->sc, c->search_group,
+                      c->search_cap ? c->search_cap : c->search_lcap_cand, (int *)c->ovfq.p, true, st,
+                      reuse_scale(c), gate, &c->sc->max_cand);
+        launch_filter(srt, &c->sc->n_total, (int)n_total, n, c->dc, (const int *)c->cand.p, ldn,
+                      (const int *)c->ccount.p, (int *)c->nbr.p, ldn, (int *)c->count.p,
+                      (const uint32_t *)c->tables.p, c->grid, c->sc, c->search_group,
+                      c->search_cap ? c->search_cap : c->search_lcap, (int *)c->fovfq.p, st);
+    } else {
+        run_search(c, srt, n_total, n, c->search_cap ? c->search_cap : c->search_lcap, st);
+    }
     if (c->solve_mode != 0)
         launch_bin_tiles((const int *)c->count.p, srt.id, &c->sc->n_total, (int)n_total, n, c->dc.max_nb,
                          c->queue_tile, (int *)c->wq.p, st);
@@ -877,6 +930,7 @@ extern "C" lp_status lp_neighbors(lp_ctx *c, void *stream, int64_t n, const doub
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)stream;
     const int D = c->dc.D;
+    ++c->gen;  // the cell arrays are rebuilt here: a step's reused lists and captured graph are outdated
     launch_reset_scalars(c->sc, 0.0, (int)n, 1, st);
     {
         const double *xs[3] = {x, y, c->dc.D == 3 ? z : y};
@@ -971,6 +1025,7 @@ static lp_status gfd_run(lp_ctx *c, void *stream, int64_t n, const double *x, co
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)stream;
     const int D = c->dc.D;
+    ++c->gen;  // the cell arrays are rebuilt here: a step's reused lists and captured graph are outdated
     launch_reset_scalars(c->sc, 0.0, (int)n, 1, st);
     {
         const double *xs[3] = {x, y, c->dc.D == 3 ? z : y};
@@ -1191,6 +1246,7 @@ extern "C" lp_status lp_get_info(lp_ctx *c, void *stream, lp_info *out) {
     out->n_mlp = (int64_t)c->sc_host->n_mlp;
     out->n_mlp_plain = (int64_t)c->sc_host->n_mlp_plain;
     out->n_refined = c->sc_host->n_refine;
+    out->n_list_builds = (int64_t)c->sc_host->n_builds;
     return LP_OK;
 }
 
@@ -1263,6 +1319,10 @@ extern "C" lp_status lp_set_tuning(lp_ctx *c, int32_t param, int32_t value) {
             return fail(c, LP_E_ARG, "search cap must be 0 or a multiple of 8 in 8..128");
         field = &c->search_cap;
         break;
+    case LP_TUNE_LIST_SKIN:
+        if (value < 0 || value > 1000) return fail(c, LP_E_ARG, "list skin must be in 0..1000 (per mille of r)");
+        field = &c->list_skin;
+        break;
     default:
         return fail(c, LP_E_ARG, "unknown tuning parameter %d", param);
     }
@@ -1280,6 +1340,7 @@ extern "C" lp_status lp_get_tuning(const lp_ctx *c, int32_t param, int32_t *valu
     case LP_TUNE_SEARCH_GROUP: *value = c->search_group; return LP_OK;
     case LP_TUNE_SOLVE_BLOCK: *value = c->solve_block; return LP_OK;
     case LP_TUNE_SOLVE_MODE: *value = c->solve_mode; return LP_OK;
+    case LP_TUNE_LIST_SKIN: *value = c->list_skin; return LP_OK;
     case LP_TUNE_QUEUE_TILE: *value = c->queue_tile; return LP_OK;
     case LP_TUNE_SEARCH_CAP: *value = c->search_cap; return LP_OK;
     default: return LP_E_ARG;
@@ -1369,7 +1430,8 @@ extern "C" lp_status lp_autotune(lp_ctx *c, void *stream, const lp_particles *p,
         have_saved = true;
         c->grid_margin = 0.0;
         struct Param { int id; std::vector<int> values; };
-        std::vector<Param> params = {{LP_TUNE_SOLVE_MODE, {0, 1, 2}},
+        std::vector<Param> params = {{LP_TUNE_LIST_SKIN, {0, 100, 150, 250}},
+                                     {LP_TUNE_SOLVE_MODE, {0, 1, 2}},
                                      {LP_TUNE_QUEUE_TILE, {256, 512, 1024}},
                                      {LP_TUNE_SOLVE_BLOCK, {64, 128, 256}},
                                      {LP_TUNE_SEARCH_MODE, {0, 1, 2}},

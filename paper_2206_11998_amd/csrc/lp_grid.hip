@@ -31,6 +31,7 @@ __global__ void k_reset_scalars(DevScalars *sc, double dt_in, int n_real, int cl
     sc->n_fallback = 0;
     sc->n_refine = 0;
     sc->n_overflow = 0;
+    sc->n_fovf = 0;
     sc->n_limited = 0ull;
     sc->n_mlp = 0ull;
     sc->n_mlp_plain = 0ull;
@@ -296,17 +297,18 @@ void launch_ghost_write(const Soa &p, const DevCfg &cfg, DevScalars *sc, const u
 // ---------------------------------------------------------------------------
 // Fill (used instead of memset so the sequence stays graph-safe).
 // ---------------------------------------------------------------------------
-__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
+__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v, const unsigned *gate) {
+    if (gate && *gate == 0u) return;
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (; i < n; i += stride) p[i] = v;
 }
 
-void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) {
+void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st, const unsigned *gate) {
     uint64_t b = (n + LP_BLOCK - 1) / LP_BLOCK;
     if (b > 65536) b = 65536;
     if (b < 1) b = 1;
-    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)b), dim3(LP_BLOCK), 0, st, p, n, v);
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)b), dim3(LP_BLOCK), 0, st, p, n, v, gate);
     CHECK_LAUNCH();
 }
 
@@ -316,7 +318,8 @@ void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) {
 template <int D>
 __global__ void k_keys(const double *x0, const double *x1, const double *x2, const double *g0, const double *g1,
                        const double *g2, int n_real, const int *n_total_dev, DevGrid g, uint32_t *key,
-                       uint32_t *slot, uint32_t *cnt) {
+                       uint32_t *slot, uint32_t *cnt, const unsigned *gate) {
+    if (gate && *gate == 0u) return;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int n_total = *n_total_dev;
     if (i >= n_total) return;
@@ -332,14 +335,14 @@ __global__ void k_keys(const double *x0, const double *x1, const double *x2, con
 
 void launch_keys(const double *const x[3], const double *const gx[3], int n_real, const int *n_total_dev,
                  int n_total_cap, const DevGrid &g, int D, uint32_t *key, uint32_t *slot, uint32_t *cnt,
-                 hipStream_t st) {
+                 hipStream_t st, const unsigned *gate) {
     dim3 grid(blocks_for(n_total_cap));
     if (D == 3)
         hipLaunchKernelGGL(k_keys<3>, grid, dim3(LP_BLOCK), 0, st, x[0], x[1], x[2], gx[0], gx[1], gx[2], n_real,
-                           n_total_dev, g, key, slot, cnt);
+                           n_total_dev, g, key, slot, cnt, gate);
     else
         hipLaunchKernelGGL(k_keys<2>, grid, dim3(LP_BLOCK), 0, st, x[0], x[1], x[1], gx[0], gx[1], gx[1], n_real,
-                           n_total_dev, g, key, slot, cnt);
+                           n_total_dev, g, key, slot, cnt, gate);
     CHECK_LAUNCH();
 }
 
@@ -376,7 +379,8 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
     return off + inc - v;
 }
 
-__global__ void k_scan_tiles(const uint32_t *data, uint64_t n, uint32_t *sums) {
+__global__ void k_scan_tiles(const uint32_t *data, uint64_t n, uint32_t *sums, const unsigned *gate) {
+    if (gate && *gate == 0u) return;
     uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
     uint32_t s = 0;
     for (int k = 0; k < SCAN_ITEMS; ++k) {
@@ -397,7 +401,8 @@ __global__ void k_scan_tiles(const uint32_t *data, uint64_t n, uint32_t *sums) {
 
 // one block of 1024 threads: exclusive scan of the tile sums in place, total to
 // sums[nt]; each thread scans a contiguous chunk sequentially.
-__global__ __launch_bounds__(1024) void k_scan_sums(uint32_t *sums, uint64_t nt) {
+__global__ __launch_bounds__(1024) void k_scan_sums(uint32_t *sums, uint64_t nt, const unsigned *gate) {
+    if (gate && *gate == 0u) return;
     __shared__ uint32_t ws[16];
     uint64_t chunk = (nt + 1023) / 1024;
     uint64_t b = (uint64_t)threadIdx.x * chunk, e = b + chunk;
@@ -422,7 +427,9 @@ __global__ __launch_bounds__(1024) void k_scan_sums(uint32_t *sums, uint64_t nt)
     if (threadIdx.x == 0) sums[nt] = tot;
 }
 
-__global__ void k_scan_apply(uint32_t *data, uint64_t n, const uint32_t *sums, int *total_dev) {
+__global__ void k_scan_apply(uint32_t *data, uint64_t n, const uint32_t *sums, int *total_dev,
+                             const unsigned *gate) {
+    if (gate && *gate == 0u) return;
     uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
     // each thread owns SCAN_ITEMS consecutive items
     uint64_t first = base + (uint64_t)threadIdx.x * SCAN_ITEMS;
@@ -449,12 +456,13 @@ __global__ void k_scan_apply(uint32_t *data, uint64_t n, const uint32_t *sums, i
 
 uint64_t scan_tmp_words(uint64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 2; }
 
-void launch_scan_u32(uint32_t *data, uint64_t n, uint32_t *tmp, int *total_dev, hipStream_t st) {
+void launch_scan_u32(uint32_t *data, uint64_t n, uint32_t *tmp, int *total_dev, hipStream_t st,
+                     const unsigned *gate) {
     uint64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nt < 1) nt = 1;
-    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(LP_BLOCK), 0, st, data, n, tmp);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, tmp, nt);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nt), dim3(LP_BLOCK), 0, st, data, n, tmp, total_dev);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(LP_BLOCK), 0, st, data, n, tmp, gate);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, tmp, nt, gate);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nt), dim3(LP_BLOCK), 0, st, data, n, tmp, total_dev, gate);
     CHECK_LAUNCH();
 }
 
@@ -517,18 +525,103 @@ void launch_scatter(const ScatterArgs &a, int n_real, const int *n_total_dev, in
 // Coarser cell tables: the first particle of a cell is the first particle of
 // its first child.
 // ---------------------------------------------------------------------------
-__global__ void k_coarsen(uint32_t *dst, const uint32_t *src, uint64_t ncell, int D, const int *n_total_dev) {
+__global__ void k_coarsen(uint32_t *dst, const uint32_t *src, uint64_t ncell, int D, const int *n_total_dev,
+                          const unsigned *gate) {
+    if (gate && *gate == 0u) return;
     uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c < ncell) dst[c] = src[c << D];
     else if (c == ncell) dst[c] = (uint32_t)*n_total_dev;
 }
 
-void launch_coarsen(uint32_t *tables, const DevGrid &g, int D, const int *n_total_dev, hipStream_t st) {
+void launch_coarsen(uint32_t *tables, const DevGrid &g, int D, const int *n_total_dev, hipStream_t st,
+                    const unsigned *gate) {
     for (int L = g.L_hi - 1; L >= g.L_lo; --L) {
         uint64_t ncell = 1ull << (D * L);
         hipLaunchKernelGGL(k_coarsen, dim3(blocks_for(ncell + 1)), dim3(LP_BLOCK), 0, st, tables + g.off[L],
-                           tables + g.off[L + 1], ncell, D, n_total_dev);
+                           tables + g.off[L + 1], ncell, D, n_total_dev, gate);
     }
+    CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------------------
+// Neighbour-list reuse.  A rebuild step finds, for every particle, the
+// candidates within R_i = rscale r_i; later steps filter them exactly.  That
+// filter misses no neighbour while |x_j - x_i| < r_i now implies
+// |x_j - x_i| < R_i at the rebuild, which the triangle inequality guarantees
+// when r_i + d_i + d_j < R_i for all i, j (d: displacement since the rebuild):
+// max_i (r_i + d_i - R_i) + max_j d_j < 0, checked with a margin of 1e-9 of
+// the smallest radius against rounding.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(LP_BLOCK) void k_reuse_check(Soa p, DevCfg cfg, const double *r, const double *xb0,
+                                                          const double *xb1, const double *xb2, const double *Rb,
+                                                          DevScalars *sc) {
+    if (!sc->have_cand || sc->n_total == 0) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double a = -INFINITY, d = 0.0;
+    if (i < p.n) {
+        const double *xb[3] = {xb0, xb1, xb2};
+        double d2 = 0.0;
+        for (int q = 0; q < cfg.D; ++q) {
+            const double e = min_image(cfg, q, p.x[q][i] - xb[q][i]);
+            d2 += e * e;
+        }
+        d = sqrt(d2);
+        a = r[i] + d - Rb[i];
+        if (!(a == a) || !(d == d)) { a = INFINITY; d = INFINITY; }  // NaN positions: rebuild
+    }
+    a = wave_max(a);
+    d = wave_max(d);
+    __shared__ double wa[LP_BLOCK / 64], wd[LP_BLOCK / 64];
+    if ((threadIdx.x & 63) == 0) { wa[threadIdx.x >> 6] = a; wd[threadIdx.x >> 6] = d; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < LP_BLOCK / 64; ++q) { a = fmax(a, wa[q]); d = fmax(d, wd[q]); }
+        atomicMax(&sc->reuse_a, dbl_key(a));
+        atomicMax(&sc->reuse_d, dbl_bits(d));
+    }
+}
+
+__global__ void k_reuse_decide(DevScalars *sc, int force) {
+    unsigned rb = 0u;
+    if (sc->n_total > 0) {
+        if (force || !sc->have_cand || sc->cand_short) rb = 1u;
+        else {
+            const unsigned long long ka = sc->reuse_a;
+            const double a = (ka >> 63) ? bits_dbl(ka & 0x7fffffffffffffffull) : bits_dbl(~ka);
+            const double d = bits_dbl(sc->reuse_d);
+            const double rmin = bits_dbl(sc->rmin);
+            rb = (a + d < -1e-9 * rmin) ? 0u : 1u;
+        }
+    }
+    sc->rebuild = rb;
+    if (rb) {
+        sc->have_cand = 1u;
+        sc->n_builds += 1ull;
+        sc->max_cand = 0;
+        sc->cand_short = 0u;
+    }
+    sc->reuse_a = 0ull;
+    sc->reuse_d = 0ull;
+}
+
+__global__ void k_reuse_commit(Soa p, DevCfg cfg, const double *r, double *xb0, double *xb1, double *xb2, double *Rb,
+                               double rscale, const DevScalars *sc) {
+    if (!sc->rebuild) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n) return;
+    xb0[i] = p.x[0][i];
+    xb1[i] = p.x[1][i];
+    if (cfg.D == 3) xb2[i] = p.x[2][i];
+    Rb[i] = r[i] * rscale;
+}
+
+void launch_reuse(const Soa &p, const DevCfg &cfg, const double *r, double *const xb[3], double *Rb, int n,
+                  double rscale, int force, DevScalars *sc, hipStream_t st) {
+    dim3 grid(blocks_for((uint64_t)n));
+    double *x2 = cfg.D == 3 ? xb[2] : xb[0];
+    hipLaunchKernelGGL(k_reuse_check, grid, dim3(LP_BLOCK), 0, st, p, cfg, r, xb[0], xb[1], x2, Rb, sc);
+    hipLaunchKernelGGL(k_reuse_decide, dim3(1), dim3(1), 0, st, sc, force);
+    hipLaunchKernelGGL(k_reuse_commit, grid, dim3(LP_BLOCK), 0, st, p, cfg, r, xb[0], xb[1], x2, Rb, rscale, sc);
     CHECK_LAUNCH();
 }
 

@@ -62,6 +62,15 @@ struct DevScalars {
     unsigned long long n_mlp;       // particles whose phi came from the network in the last step
     unsigned long long n_mlp_plain; // particles for which the network was not trusted
     unsigned int head[2][8];        // chunk counters of the persistent fit / update launches, per XCD range
+    // neighbour-list reuse (candidate lists built within an enlarged radius)
+    unsigned int rebuild;           // this step rebuilds the cells and the candidate lists
+    unsigned int have_cand;         // a candidate set exists (the last rebuild's)
+    int max_cand;                   // longest candidate list of the last rebuild
+    int n_fovf;                     // candidate filters whose hits overflow the LDS buffer
+    unsigned long long reuse_a;     // max_i (r_i + d_i - R_i) as an order-preserving key (d_i: displacement)
+    unsigned long long reuse_d;     // bits of max_i d_i
+    unsigned long long n_builds;    // rebuilds so far
+    unsigned int cand_short;        // the last rebuild found more candidates than max_nb for some particle
 };
 
 // Particle state in the caller's order (real particles only).
@@ -154,20 +163,39 @@ void launch_dt(const DevCfg &cfg, DevScalars *sc, int clip_t_end, hipStream_t st
 void launch_ghost_count(const Soa &p, const DevCfg &cfg, DevScalars *sc, uint32_t *gcnt, hipStream_t st);
 void launch_ghost_write(const Soa &p, const DevCfg &cfg, DevScalars *sc, const uint32_t *goff,
                         const double *h, const double *r, Ghosts g, int64_t cap_ghost, hipStream_t st);
-void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
+// gate (may be NULL): the kernels do nothing unless *gate != 0 (read on the device)
+void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st, const unsigned *gate = nullptr);
 void launch_keys(const double *const x[3], const double *const gx[3], int n_real, const int *n_total_dev,
                  int n_total_cap, const DevGrid &g, int D, uint32_t *key, uint32_t *slot, uint32_t *cnt,
-                 hipStream_t st);
+                 hipStream_t st, const unsigned *gate = nullptr);
 // exclusive scan of n u32 values in place; out[n] receives the total; tmp needs scan_tmp_words(n)
 uint64_t scan_tmp_words(uint64_t n);
-void launch_scan_u32(uint32_t *data, uint64_t n, uint32_t *tmp, int *total_dev, hipStream_t st);
+void launch_scan_u32(uint32_t *data, uint64_t n, uint32_t *tmp, int *total_dev, hipStream_t st,
+                     const unsigned *gate = nullptr);
 void launch_scatter(const ScatterArgs &a, int n_real, const int *n_total_dev, int n_total_cap,
                     const uint32_t *key, const uint32_t *slot, const uint32_t *start, int *sorted_id,
                     hipStream_t st);
-void launch_coarsen(uint32_t *tables, const DevGrid &g, int D, const int *n_total_dev, hipStream_t st);
+void launch_coarsen(uint32_t *tables, const DevGrid &g, int D, const int *n_total_dev, hipStream_t st,
+                    const unsigned *gate = nullptr);
+// rscale: the search radius is r * rscale (1: the neighbour lists themselves);
+// max_out receives the longest list (NULL: sc->max_count)
 void launch_search(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real, const uint32_t *tables,
                    const DevGrid &g, const DevCfg &cfg, int *nbr, int ldn, int *count, DevScalars *sc,
-                   int group, int lcap, int *ovf_queue, bool balanced, hipStream_t st);
+                   int group, int lcap, int *ovf_queue, bool balanced, hipStream_t st, double rscale = 1.0,
+                   const unsigned *gate = nullptr, int *max_out = nullptr);
+// neighbour lists from reused candidate lists cand[c * ldc + s], c < ccount[s]:
+// the exact test d2 < r_s^2 on the current positions, (d2, id) order
+// (ccount[s] < 0: no candidates were kept; the cells -- laid out by this
+// step's rebuild -- are searched exactly instead)
+void launch_filter(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real, const DevCfg &cfg,
+                   const int *cand, int ldc, const int *ccount, int *nbr, int ldn, int *count,
+                   const uint32_t *tables, const DevGrid &g, DevScalars *sc, int group, int lcap, int *ovf_queue,
+                   hipStream_t st);
+// reuse decision: displacement since the last rebuild and radius growth
+// against the enlarged radius; force != 0 rebuilds; a rebuild step copies
+// the positions and r * rscale of every particle
+void launch_reuse(const Soa &p, const DevCfg &cfg, const double *r, double *const xb[3], double *Rb, int n,
+                  double rscale, int force, DevScalars *sc, hipStream_t st);
 void launch_search_tiles(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real,
                          const uint32_t *tables, const DevGrid &g, const DevCfg &cfg, double *hit_d2, int *hit_j,
                          int *nbr, int ldn, int *count, DevScalars *sc, const uint32_t *key, uint32_t *flags,

@@ -55,7 +55,9 @@ __device__ __forceinline__ uint32_t cell_code(const DevGrid &g, const DevCfg &cf
 template <int D, int G>
 __global__ __launch_bounds__(LP_BLOCK) void k_search(Sorted srt, const int *n_total_dev, int n_real,
                                                      const uint32_t *tables, DevGrid g, DevCfg cfg, int *nbr, int ldn,
-                                                     int *count, DevScalars *sc, int lcap, int *ovf_queue) {
+                                                     int *count, DevScalars *sc, int lcap, int *ovf_queue,
+                                                     double rscale, const unsigned *gate, int *max_out) {
+    if (gate && *gate == 0u) return;
     constexpr int PPB = LP_BLOCK / G;
     extern __shared__ unsigned char smem[];
     const int max_nb = cfg.max_nb;
@@ -75,7 +77,7 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search(Sorted srt, const int *n_to
 
     if (active) {
         double xi[3] = {srt.x[0][s], srt.x[1][s], D == 3 ? srt.x[2][s] : 0.0};
-        double ri = srt.r[s];
+        double ri = srt.r[s] * rscale;
         double r2 = ri * ri;
         int L = level_for_radius(g, ri);
         const uint32_t *tab = tables + g.off[L];
@@ -104,7 +106,7 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search(Sorted srt, const int *n_to
     {
         int kmax = active ? lcnt[grp] : 0;
         for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o));
-        if ((threadIdx.x & 63) == 0 && kmax > 0) atomicMax(&sc->max_count, kmax);
+        if ((threadIdx.x & 63) == 0 && kmax > 0) atomicMax(max_out, kmax);
     }
     if (active) {
         int k = lcnt[grp];
@@ -135,7 +137,9 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search(Sorted srt, const int *n_to
 // buffer of max_nb entries.
 template <int D>
 __global__ __launch_bounds__(64) void k_search_overflow(Sorted srt, const uint32_t *tables, DevGrid g, DevCfg cfg,
-                                                         int *nbr, int ldn, DevScalars *sc, const int *ovf_queue) {
+                                                         int *nbr, int ldn, DevScalars *sc, const int *ovf_queue,
+                                                         double rscale, const unsigned *gate) {
+    if (gate && *gate == 0u) return;
     __shared__ double gd2[256];
     __shared__ int gj[256];
     __shared__ int lcnt;
@@ -146,7 +150,7 @@ __global__ __launch_bounds__(64) void k_search_overflow(Sorted srt, const uint32
         if (lane == 0) lcnt = 0;
         __syncthreads();
         double xi[3] = {srt.x[0][s], srt.x[1][s], D == 3 ? srt.x[2][s] : 0.0};
-        double ri = srt.r[s];
+        double ri = srt.r[s] * rscale;
         double r2 = ri * ri;
         int L = level_for_radius(g, ri);
         const uint32_t *tab = tables + g.off[L];
@@ -210,14 +214,204 @@ __device__ __forceinline__ int div_small(int c, int n, float rcp, int &rem) {
     return q;
 }
 
+// LDS layout shared by k_search_bal and k_filter_bal (per group of G lanes):
+// lcap + 1 FP32 keys and indices, a byte permutation, SB_NB bucket counters.
+struct BalLds {
+    float *gkey;
+    int *gj;
+    unsigned char *gperm;
+    int *gbk;
+    int *lout, *lk;  // after ranking: the block's ranked lists and their lengths
+};
+
+template <int G>
+__device__ __forceinline__ BalLds bal_lds(unsigned char *smem, int lcap, int grp) {
+    constexpr int PPB = LP_BLOCK / G;
+    const int stride = lcap + 1;  // odd group stride: groups of a wave hit different LDS banks
+    float *lkey = reinterpret_cast<float *>(smem);
+    int *lj = reinterpret_cast<int *>(lkey + PPB * stride);
+    unsigned char *lperm = reinterpret_cast<unsigned char *>(lj + PPB * stride);
+    int *lbk = reinterpret_cast<int *>(lperm + PPB * ((stride + 3) & ~3));
+    BalLds l;
+    l.gkey = lkey + grp * stride;
+    l.gj = lj + grp * stride;
+    l.gperm = lperm + grp * ((stride + 3) & ~3);
+    l.gbk = lbk + grp * SB_NB;
+    l.lout = reinterpret_cast<int *>(smem);
+    l.lk = lbk;
+    return l;
+}
+
+// The k hits staged in a group's slots (FP32 key of d2, cell-order index) are
+// ranked by (d2, original id) and the block's lists written out: nbr, count,
+// the capacity bit, the overflow queue (k > lcap) and the wave's largest
+// count into *max_out.  Called by every thread of the block.
+template <int D, int G, bool PER>
+__device__ __forceinline__ void bal_rank_write(const BalLds &l, int k, bool active, int s, double r2,
+                                               const double xi[3], const Sorted &srt, const DevCfg &cfg, int *nbr,
+                                               int ldn, int *count, DevScalars *sc, int lcap, int *ovf_queue,
+                                               int *ovf_count, int *max_out, bool cand_mode = false) {
+    constexpr int PPB = LP_BLOCK / G;
+    const int lane = threadIdx.x % G;
+    const int grp = threadIdx.x / G;
+    const int max_nb = cfg.max_nb;
+    float *gkey = l.gkey;
+    int *gj = l.gj;
+    unsigned char *gperm = l.gperm;
+    int *gbk = l.gbk;
+    int *lout = l.lout;
+    int *lk = l.lk;
+    __syncthreads();
+    // rank: bucket B(d2) = floor(SB_NB d2/r2) in FP32 is non-decreasing in d2
+    // (every operation is monotone), so entries of lower buckets rank lower;
+    // inside a bucket the exact (d2, id) comparison decides.  For a uniform
+    // particle density the outermost bucket holds 1.5x the mean share.
+    const bool ranked = active && k <= lcap;
+    const float inv_r2 = ranked ? (float)(1.0 / r2) : 0.0f;
+    constexpr int EMAX = 128 / G;  // entries per lane (k <= lcap <= 128)
+    int bk[EMAX];                  // bucket of each of this lane's entries
+    int pos[EMAX];                 // its place inside the bucket
+    if (ranked) {
+#pragma unroll
+        for (int q = 0; q < EMAX; ++q) {
+            const int e = lane + q * G;
+            if (e < k) {
+                const float x = gkey[e] * inv_r2;
+                int bb = (int)((float)SB_NB * x);
+                bb = bb < 0 ? 0 : (bb > SB_NB - 1 ? SB_NB - 1 : bb);
+                bk[q] = bb;
+                pos[q] = atomicAdd(&gbk[bb], 1);
+            }
+        }
+    }
+    __syncthreads();
+    if (ranked) {
+        // exclusive scan of the bucket counts, in place (lane q holds buckets q, q + G, ...)
+        constexpr int BPL = SB_NB / G > 0 ? SB_NB / G : 1;  // buckets per lane
+        int cnt[BPL];
+        int mine = 0;
+#pragma unroll
+        for (int q = 0; q < BPL; ++q) {
+            const int bb = lane * BPL + q;
+            cnt[q] = bb < SB_NB ? gbk[bb] : 0;
+            mine += cnt[q];
+        }
+        int incl = mine;
+#pragma unroll
+        for (int o = 1; o < G; o <<= 1) {
+            const int v = __shfl_up(incl, o, G);
+            if (lane >= o) incl += v;
+        }
+        int run = incl - mine;
+#pragma unroll
+        for (int q = 0; q < BPL; ++q) {
+            const int bb = lane * BPL + q;
+            if (bb < SB_NB) gbk[bb] = run;  // start of bucket bb
+            run += cnt[q];
+        }
+    }
+    __syncthreads();
+    if (ranked) {
+#pragma unroll
+        for (int q = 0; q < EMAX; ++q) {
+            const int e = lane + q * G;
+            if (e < k) gperm[gbk[bk[q]] + pos[q]] = (unsigned char)e;
+        }
+    }
+    __syncthreads();
+    {
+        // largest count of the wave: one atomic per wave (all lanes active here)
+        int kmax = k;
+        for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o));
+        if ((threadIdx.x & 63) == 0 && kmax > 0) atomicMax(max_out, kmax);
+    }
+    if (active) {
+        if (lane == 0) {
+            if (cand_mode && k > max_nb) {
+                // more candidates than a list holds: none are kept (count -1);
+                // this step's filter searches the particle's cells exactly,
+                // and the next step rebuilds again
+                count[s] = -1;
+                atomicOr(&sc->cand_short, 1u);
+            } else {
+                count[s] = k;
+                if (k > max_nb) atomicOr(&sc->error_bits, 1u);
+                // the list does not fit the LDS buffer: one wave redoes it (and
+                // for k > max_nb writes max_nb valid entries, so readers stay in bounds)
+                if (k > lcap) ovf_queue[atomicAdd(ovf_count, 1)] = s;
+            }
+        }
+    }
+    int rank[EMAX], jq[EMAX];
+    if (ranked) {
+#pragma unroll
+        for (int q = 0; q < EMAX; ++q) {
+            const int e = lane + q * G;
+            if (e < k) {
+                const float ke = gkey[e];
+                const int je = gj[e];
+                const int bb = bk[q];
+                const int lo = gbk[bb];
+                const int hi = bb + 1 < SB_NB ? gbk[bb + 1] : k;
+                int rk = lo;
+                bool have_de = false;
+                double de = 0.0;
+                for (int f = lo; f < hi; ++f) {
+                    const int pf = gperm[f];
+                    const float kf = gkey[pf];
+                    if (kf < ke) {
+                        ++rk;
+                    } else if (kf == ke && pf != e) {
+                        // equal keys: the exact d2, recomputed as the dealing
+                        // loop computed it, then the original id
+                        const int jf = gj[pf];
+                        double dx[3];
+                        if (!have_de) {
+                            disp_to<D, PER>(cfg, srt.x, je, xi, dx);
+                            de = dist2_exact<D>(dx);
+                            have_de = true;
+                        }
+                        disp_to<D, PER>(cfg, srt.x, jf, xi, dx);
+                        const double df = dist2_exact<D>(dx);
+                        if (df < de || (df == de && srt.id[jf] < srt.id[je])) ++rk;
+                    }
+                }
+                rank[q] = rk;
+                jq[q] = je;
+            }
+        }
+    }
+    __syncthreads();  // every group is done with its slots and counters
+    if (lane == 0) lk[grp] = ranked ? k : 0;
+    if (ranked) {
+#pragma unroll
+        for (int q = 0; q < EMAX; ++q)
+            if (lane + q * G < k) lout[rank[q] * PPB + grp] = jq[q];
+    }
+    __syncthreads();
+    // write the block's lists: with column-major lists the PPB particles of
+    // the block are consecutive in every column, so a column is one segment
+    const int s0 = xcd_remap(blockIdx.x, gridDim.x) * PPB;
+    int kb = 0;
+    for (int q = 0; q < PPB; ++q) kb = max(kb, lk[q]);
+    for (int idx = threadIdx.x; idx < kb * PPB; idx += LP_BLOCK) {
+        const int c = idx / PPB, gq = idx % PPB;
+        if (c < lk[gq]) {
+            const int sq = s0 + gq;
+            nbr[ldn > 0 ? (int64_t)c * ldn + sq : (int64_t)sq * (-ldn) + c] = lout[c * PPB + gq];
+        }
+    }
+}
+
 template <int D, int G, bool PER>
 __global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *n_total_dev, int n_real,
                                                          const uint32_t *tables, DevGrid g, DevCfg cfg, int *nbr,
                                                          int ldn, int *count, DevScalars *sc, int lcap,
-                                                         int *ovf_queue) {
+                                                         int *ovf_queue, double rscale, const unsigned *gate,
+                                                         int *max_out) {
+    if (gate && *gate == 0u) return;
     constexpr int PPB = LP_BLOCK / G;
     extern __shared__ unsigned char smem[];
-    const int max_nb = cfg.max_nb;
     const int stride = lcap + 1;  // odd group stride: groups of a wave hit different LDS banks
     float *lkey = reinterpret_cast<float *>(smem);
     int *lj = reinterpret_cast<int *>(lkey + PPB * stride);
@@ -249,7 +443,7 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *
         xi[0] = srt.x[0][s];
         xi[1] = srt.x[1][s];
         if (D == 3) xi[2] = srt.x[2][s];
-        const double ri = srt.r[s];
+        const double ri = srt.r[s] * rscale;
         r2 = ri * ri;
         // a cell is skipped only when even its box widened by a rounding slack
         // (and unbounded on the outer side of edge cells, which hold the
@@ -385,137 +579,179 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *
             }
         }
     }
-    __syncthreads();
-    // rank: bucket B(d2) = floor(SB_NB d2/r2) in FP32 is non-decreasing in d2
-    // (every operation is monotone), so entries of lower buckets rank lower;
-    // inside a bucket the exact (d2, id) comparison decides.  For a uniform
-    // particle density the outermost bucket holds 1.5x the mean share.
-    const bool ranked = active && k <= lcap;
-    const float inv_r2 = ranked ? (float)(1.0 / r2) : 0.0f;
-    constexpr int EMAX = 128 / G;  // entries per lane (k <= lcap <= 128)
-    int bk[EMAX];                  // bucket of each of this lane's entries
-    int pos[EMAX];                 // its place inside the bucket
-    if (ranked) {
-#pragma unroll
-        for (int q = 0; q < EMAX; ++q) {
-            const int e = lane + q * G;
-            if (e < k) {
-                const float x = gkey[e] * inv_r2;
-                int bb = (int)((float)SB_NB * x);
-                bb = bb < 0 ? 0 : (bb > SB_NB - 1 ? SB_NB - 1 : bb);
-                bk[q] = bb;
-                pos[q] = atomicAdd(&gbk[bb], 1);
-            }
-        }
-    }
-    __syncthreads();
-    if (ranked) {
-        // exclusive scan of the bucket counts, in place (lane q holds buckets q, q + G, ...)
-        constexpr int BPL = SB_NB / G > 0 ? SB_NB / G : 1;  // buckets per lane
-        int cnt[BPL];
-        int mine = 0;
-#pragma unroll
-        for (int q = 0; q < BPL; ++q) {
-            const int bb = lane * BPL + q;
-            cnt[q] = bb < SB_NB ? gbk[bb] : 0;
-            mine += cnt[q];
-        }
-        int incl = mine;
-#pragma unroll
-        for (int o = 1; o < G; o <<= 1) {
-            const int v = __shfl_up(incl, o, G);
-            if (lane >= o) incl += v;
-        }
-        int run = incl - mine;
-#pragma unroll
-        for (int q = 0; q < BPL; ++q) {
-            const int bb = lane * BPL + q;
-            if (bb < SB_NB) gbk[bb] = run;  // start of bucket bb
-            run += cnt[q];
-        }
-    }
-    __syncthreads();
-    if (ranked) {
-#pragma unroll
-        for (int q = 0; q < EMAX; ++q) {
-            const int e = lane + q * G;
-            if (e < k) gperm[gbk[bk[q]] + pos[q]] = (unsigned char)e;
-        }
-    }
-    __syncthreads();
-    {
-        // largest count of the wave: one atomic per wave (all lanes active here)
-        int kmax = k;
-        for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o));
-        if ((threadIdx.x & 63) == 0 && kmax > 0) atomicMax(&sc->max_count, kmax);
-    }
+    BalLds l;
+    l.gkey = gkey; l.gj = gj; l.gperm = gperm; l.gbk = gbk; l.lout = lout; l.lk = lk;
+    bal_rank_write<D, G, PER>(l, k, active, s, r2, xi, srt, cfg, nbr, ldn, count, sc, lcap, ovf_queue,
+                              &sc->n_overflow, max_out, rscale != 1.0);
+}
+
+
+// ---------------------------------------------------------------------------
+// Lists from reused candidates.  Candidate c of cell-order particle s is
+// cand[c * ldc + s] (c < ccount[s]), a particle found within the enlarged
+// radius by the last rebuild; the cell order has not changed since.  Each is
+// tested against the current positions and radius with the search's own
+// exact d2 < r^2, and the hits are ranked as the search ranks them, so the
+// lists are the search's bit for bit whenever the candidates cover every
+// neighbour (which the reuse check guarantees).  The G lanes of a group take
+// two candidates each per round; the next round's indices and positions are
+// loaded before this round's hits are compacted.
+// ---------------------------------------------------------------------------
+template <int D, int G, bool PER>
+__global__ __launch_bounds__(LP_BLOCK) void k_filter_bal(Sorted srt, const int *n_total_dev, int n_real, DevCfg cfg,
+                                                         const int *cand, int ldc, const int *ccount, int *nbr,
+                                                         int ldn, int *count, DevScalars *sc, int lcap,
+                                                         int *ovf_queue) {
+    constexpr int PPB = LP_BLOCK / G;
+    extern __shared__ unsigned char smem[];
+    const int lane = threadIdx.x % G;
+    const int grp = threadIdx.x / G;
+    const int gshift = (int)(threadIdx.x & 63) - lane;
+    const unsigned long long gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int s = xcd_remap(blockIdx.x, gridDim.x) * PPB + grp;
+    const int n_total = *n_total_dev;
+    const bool active = s < n_total && srt.id[s] < n_real;
+    BalLds l = bal_lds<G>(smem, lcap, grp);
+    int k = 0;
+    double r2 = 0.0;
+    double xi[3] = {0.0, 0.0, 0.0};
+    for (int q = lane; q < SB_NB; q += G) l.gbk[q] = 0;
     if (active) {
-        if (lane == 0) {
-            count[s] = k;
-            if (k > max_nb) atomicOr(&sc->error_bits, 1u);
-            // the list does not fit the LDS buffer: one wave redoes it (and
-            // for k > max_nb writes max_nb valid entries, so readers stay in bounds)
-            if (k > lcap) ovf_queue[atomicAdd(&sc->n_overflow, 1)] = s;
+        xi[0] = srt.x[0][s];
+        xi[1] = srt.x[1][s];
+        if (D == 3) xi[2] = srt.x[2][s];
+        const double ri = srt.r[s];
+        r2 = ri * ri;
+        int kc = ccount[s];
+        if (kc < 0) {
+            // no candidates kept (more than max_nb of them at this step's
+            // rebuild): the overflow kernel searches the fresh cells exactly
+            if (lane == 0) ovf_queue[atomicAdd(&sc->n_fovf, 1)] = s;
+            kc = 0;
+        }
+        kc = kc < cfg.max_nb ? kc : cfg.max_nb;
+        // indices of rounds t0 / t0 + 2G are in ja/jb and na/nb; slots past
+        // the end read the particle itself (a valid index, never a hit)
+        auto index_at = [&](int t) -> int { return t < kc ? cand[(int64_t)t * ldc + s] : s; };
+        int ja = index_at(lane), jb = index_at(lane + G);
+        int na = index_at(lane + 2 * G), nb = index_at(lane + 3 * G);
+        double pa[3] = {0.0, 0.0, 0.0}, pb[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            pa[a] = srt.x[a][ja];
+            pb[a] = srt.x[a][jb];
+        }
+        for (int t0 = 0; t0 < kc; t0 += 2 * G) {
+            const int ca = ja, cb = jb;
+            const bool ua = t0 + lane < kc, ub = t0 + lane + G < kc;
+            double dxa[3], dxb[3];
+            disp_of<D, PER>(cfg, pa, xi, dxa);
+            disp_of<D, PER>(cfg, pb, xi, dxb);
+            ja = na;
+            jb = nb;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                pa[a] = srt.x[a][ja];
+                pb[a] = srt.x[a][jb];
+            }
+            na = index_at(t0 + 4 * G + lane);
+            nb = index_at(t0 + 5 * G + lane);
+            const double d2a = dist2_exact<D>(dxa), d2b = dist2_exact<D>(dxb);
+            const bool hita = ua && d2a < r2, hitb = ub && d2b < r2;
+            const unsigned long long ma = (__ballot(hita) >> gshift) & gmask;
+            const unsigned long long mb = (__ballot(hitb) >> gshift) & gmask;
+            if (hita) {
+                const int slot = k + __popcll(ma & below);
+                if (slot < lcap) {
+                    l.gkey[slot] = (float)d2a;
+                    l.gj[slot] = ca;
+                }
+            }
+            k += __popcll(ma);
+            if (hitb) {
+                const int slot = k + __popcll(mb & below);
+                if (slot < lcap) {
+                    l.gkey[slot] = (float)d2b;
+                    l.gj[slot] = cb;
+                }
+            }
+            k += __popcll(mb);
         }
     }
-    int rank[EMAX], jq[EMAX];
-    if (ranked) {
-#pragma unroll
-        for (int q = 0; q < EMAX; ++q) {
-            const int e = lane + q * G;
-            if (e < k) {
-                const float ke = gkey[e];
-                const int je = gj[e];
-                const int bb = bk[q];
-                const int lo = gbk[bb];
-                const int hi = bb + 1 < SB_NB ? gbk[bb + 1] : k;
-                int rk = lo;
-                bool have_de = false;
-                double de = 0.0;
-                for (int f = lo; f < hi; ++f) {
-                    const int pf = gperm[f];
-                    const float kf = gkey[pf];
-                    if (kf < ke) {
-                        ++rk;
-                    } else if (kf == ke && pf != e) {
-                        // equal keys: the exact d2, recomputed as the dealing
-                        // loop computed it, then the original id
-                        const int jf = gj[pf];
-                        double dx[3];
-                        if (!have_de) {
-                            disp_to<D, PER>(cfg, srt.x, je, xi, dx);
-                            de = dist2_exact<D>(dx);
-                            have_de = true;
-                        }
-                        disp_to<D, PER>(cfg, srt.x, jf, xi, dx);
-                        const double df = dist2_exact<D>(dx);
-                        if (df < de || (df == de && srt.id[jf] < srt.id[je])) ++rk;
-                    }
+    bal_rank_write<D, G, PER>(l, k, active, s, r2, xi, srt, cfg, nbr, ldn, count, sc, lcap, ovf_queue,
+                              &sc->n_fovf, &sc->max_count);
+}
+
+// Filtered lists longer than the LDS buffer of k_filter_bal: one wave per
+// particle, a buffer of max_nb entries, exact (d2, id) ranking.
+template <int D>
+__global__ __launch_bounds__(64) void k_filter_overflow(Sorted srt, DevCfg cfg, const int *cand, int ldc,
+                                                         const int *ccount, int *nbr, int ldn, int *count,
+                                                         const uint32_t *tables, DevGrid g, DevScalars *sc,
+                                                         const int *ovf_queue) {
+    __shared__ double gd2[256];
+    __shared__ int gj[256];
+    __shared__ int lcnt;
+    const int lane = threadIdx.x;
+    const int nq = sc->n_fovf;
+    for (int w = blockIdx.x; w < nq; w += gridDim.x) {
+        const int s = ovf_queue[w];
+        if (lane == 0) lcnt = 0;
+        __syncthreads();
+        const double xi[3] = {srt.x[0][s], srt.x[1][s], D == 3 ? srt.x[2][s] : 0.0};
+        const double ri = srt.r[s];
+        const double r2 = ri * ri;
+        int kc = ccount[s];
+        auto hit = [&](int j) {
+            double dx[3];
+            disp_to<D>(cfg, srt.x, j, xi, dx);
+            const double d2 = dist2_exact<D>(dx);
+            if (d2 < r2) {
+                const int slot = atomicAdd(&lcnt, 1);
+                if (slot < cfg.max_nb) {
+                    gd2[slot] = d2;
+                    gj[slot] = j;
                 }
-                rank[q] = rk;
-                jq[q] = je;
+            }
+        };
+        if (kc >= 0) {
+            kc = kc < cfg.max_nb ? kc : cfg.max_nb;
+            for (int t = lane; t < kc; t += 64) hit(cand[(int64_t)t * ldc + s]);
+        } else {
+            // no candidates kept: the exact search over the cells, which this
+            // step's rebuild has just laid out for the current positions
+            const int L = level_for_radius(g, ri);
+            const uint32_t *tab = tables + g.off[L];
+            int clo[3] = {0, 0, 0}, cn[3] = {1, 1, 1};
+            search_box<D>(g, cfg, L, xi, ri, clo, cn);
+            const int ncells = cn[0] * cn[1] * (D == 3 ? cn[2] : 1);
+            for (int c = lane; c < ncells; c += 64) {
+                const uint32_t code = cell_code<D>(g, cfg, L, clo, cn, c);
+                const uint32_t b = tab[code], e = tab[code + 1];
+                for (uint32_t j = b; j < e; ++j)
+                    if ((int)j != s) hit((int)j);
             }
         }
-    }
-    __syncthreads();  // every group is done with its slots and counters
-    if (lane == 0) lk[grp] = ranked ? k : 0;
-    if (ranked) {
-#pragma unroll
-        for (int q = 0; q < EMAX; ++q)
-            if (lane + q * G < k) lout[rank[q] * PPB + grp] = jq[q];
-    }
-    __syncthreads();
-    // write the block's lists: with column-major lists the PPB particles of
-    // the block are consecutive in every column, so a column is one segment
-    const int s0 = xcd_remap(blockIdx.x, gridDim.x) * PPB;
-    int kb = 0;
-    for (int q = 0; q < PPB; ++q) kb = max(kb, lk[q]);
-    for (int idx = threadIdx.x; idx < kb * PPB; idx += LP_BLOCK) {
-        const int c = idx / PPB, gq = idx % PPB;
-        if (c < lk[gq]) {
-            const int sq = s0 + gq;
-            nbr[ldn > 0 ? (int64_t)c * ldn + sq : (int64_t)sq * (-ldn) + c] = lout[c * PPB + gq];
+        __syncthreads();
+        if (ccount[s] < 0 && lane == 0) {
+            count[s] = lcnt;
+            if (lcnt > cfg.max_nb) atomicOr(&sc->error_bits, 1u);
+            atomicMax(&sc->max_count, lcnt);
         }
+        const int k = lcnt < cfg.max_nb ? lcnt : cfg.max_nb;
+        for (int e = lane; e < k; e += 64) {
+            const double de = gd2[e];
+            const int je = gj[e];
+            int rank = 0;
+            for (int f = 0; f < k; ++f) {
+                const double df = gd2[f];
+                if (df < de) ++rank;
+                else if (df == de && f != e && srt.id[gj[f]] < srt.id[je]) ++rank;
+            }
+            nbr[ldn > 0 ? (int64_t)rank * ldn + s : (int64_t)s * (-ldn) + rank] = je;
+        }
+        __syncthreads();
     }
 }
 
@@ -535,7 +771,8 @@ static size_t search_bal_smem(int G, int lcap) {
 template <int D, int G>
 static void launch_search_t(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real, const uint32_t *tables,
                             const DevGrid &g, const DevCfg &cfg, int *nbr, int ldn, int *count, DevScalars *sc,
-                            int lcap, int *ovf_queue, bool balanced, hipStream_t st) {
+                            int lcap, int *ovf_queue, bool balanced, hipStream_t st, double rscale,
+                            const unsigned *gate, int *max_out) {
     constexpr int PPB = LP_BLOCK / G;
     unsigned blocks = (unsigned)((n_total_cap + PPB - 1) / PPB);
     if (blocks < 1) blocks = 1;
@@ -543,20 +780,65 @@ static void launch_search_t(const Sorted &s, const int *n_total_dev, int n_total
     const bool per = cfg.periodic[0] || cfg.periodic[1] || (D == 3 && cfg.periodic[2]);
     if (balanced && per)
         hipLaunchKernelGGL((k_search_bal<D, G, true>), dim3(blocks), dim3(LP_BLOCK), shm, st, s, n_total_dev, n_real,
-                           tables, g, cfg, nbr, ldn, count, sc, lcap, ovf_queue);
+                           tables, g, cfg, nbr, ldn, count, sc, lcap, ovf_queue, rscale, gate, max_out);
     else if (balanced)
         hipLaunchKernelGGL((k_search_bal<D, G, false>), dim3(blocks), dim3(LP_BLOCK), shm, st, s, n_total_dev, n_real,
-                           tables, g, cfg, nbr, ldn, count, sc, lcap, ovf_queue);
+                           tables, g, cfg, nbr, ldn, count, sc, lcap, ovf_queue, rscale, gate, max_out);
     else
         hipLaunchKernelGGL((k_search<D, G>), dim3(blocks), dim3(LP_BLOCK), shm, st, s, n_total_dev, n_real, tables, g,
-                           cfg, nbr, ldn, count, sc, lcap, ovf_queue);
+                           cfg, nbr, ldn, count, sc, lcap, ovf_queue, rscale, gate, max_out);
     unsigned ob = (unsigned)(n_total_cap < 1024 ? (n_total_cap > 0 ? n_total_cap : 1) : 1024);
-    hipLaunchKernelGGL(k_search_overflow<D>, dim3(ob), dim3(64), 0, st, s, tables, g, cfg, nbr, ldn, sc, ovf_queue);
+    hipLaunchKernelGGL(k_search_overflow<D>, dim3(ob), dim3(64), 0, st, s, tables, g, cfg, nbr, ldn, sc, ovf_queue,
+                       rscale, gate);
+}
+
+template <int D, int G>
+static void launch_filter_t(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real, const DevCfg &cfg,
+                            const int *cand, int ldc, const int *ccount, int *nbr, int ldn, int *count,
+                            const uint32_t *tables, const DevGrid &g, DevScalars *sc, int lcap, int *ovf_queue,
+                            hipStream_t st) {
+    constexpr int PPB = LP_BLOCK / G;
+    unsigned blocks = (unsigned)((n_total_cap + PPB - 1) / PPB);
+    if (blocks < 1) blocks = 1;
+    size_t shm = search_bal_smem(G, lcap);
+    const bool per = cfg.periodic[0] || cfg.periodic[1] || (D == 3 && cfg.periodic[2]);
+    // the filter's overflow queue and counter (n_fovf) are its own: the
+    // rebuild search of the same step uses n_overflow
+    if (per)
+        hipLaunchKernelGGL((k_filter_bal<D, G, true>), dim3(blocks), dim3(LP_BLOCK), shm, st, s, n_total_dev, n_real,
+                           cfg, cand, ldc, ccount, nbr, ldn, count, sc, lcap, ovf_queue);
+    else
+        hipLaunchKernelGGL((k_filter_bal<D, G, false>), dim3(blocks), dim3(LP_BLOCK), shm, st, s, n_total_dev, n_real,
+                           cfg, cand, ldc, ccount, nbr, ldn, count, sc, lcap, ovf_queue);
+    unsigned ob = (unsigned)(n_total_cap < 1024 ? (n_total_cap > 0 ? n_total_cap : 1) : 1024);
+    hipLaunchKernelGGL(k_filter_overflow<D>, dim3(ob), dim3(64), 0, st, s, cfg, cand, ldc, ccount, nbr, ldn, count,
+                       tables, g, sc, ovf_queue);
+}
+
+void launch_filter(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real, const DevCfg &cfg,
+                   const int *cand, int ldc, const int *ccount, int *nbr, int ldn, int *count,
+                   const uint32_t *tables, const DevGrid &g, DevScalars *sc, int group, int lcap_req,
+                   int *ovf_queue, hipStream_t st) {
+    int G = group;
+    if (G != 4 && G != 8 && G != 16 && G != 32) G = 16;
+    int lcap = cfg.max_nb < 128 ? cfg.max_nb : 128;
+    if (lcap_req > 0 && lcap_req < lcap) lcap = lcap_req;
+    while (search_bal_smem(G, lcap) > 65536 && G < 64) G *= 2;
+#define LF(DD, GG) launch_filter_t<DD, GG>(s, n_total_dev, n_total_cap, n_real, cfg, cand, ldc, ccount, nbr, ldn, count, tables, g, sc, lcap, ovf_queue, st)
+    if (cfg.D == 3) {
+        if (G == 4) LF(3, 4); else if (G == 8) LF(3, 8); else if (G == 16) LF(3, 16); else if (G == 32) LF(3, 32); else LF(3, 64);
+    } else {
+        if (G == 4) LF(2, 4); else if (G == 8) LF(2, 8); else if (G == 16) LF(2, 16); else if (G == 32) LF(2, 32); else LF(2, 64);
+    }
+#undef LF
+    (void)hipGetLastError();
 }
 
 void launch_search(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real, const uint32_t *tables,
                    const DevGrid &g, const DevCfg &cfg, int *nbr, int ldn, int *count, DevScalars *sc, int group,
-                   int lcap_req, int *ovf_queue, bool balanced, hipStream_t st) {
+                   int lcap_req, int *ovf_queue, bool balanced, hipStream_t st, double rscale, const unsigned *gate,
+                   int *max_out) {
+    if (!max_out) max_out = &sc->max_count;
     int G = group;
     if (G != 4 && G != 8 && G != 16 && G != 32) G = 16;
     // slots per particle in LDS (longer lists take the overflow kernel); a
@@ -565,7 +847,7 @@ void launch_search(const Sorted &s, const int *n_total_dev, int n_total_cap, int
     if (lcap_req > 0 && lcap_req < lcap) lcap = lcap_req;
     // LDS per block within 64 KiB
     while ((balanced ? search_bal_smem(G, lcap) : search_smem(G, lcap)) > 65536 && G < 64) G *= 2;
-#define LS(DD, GG) launch_search_t<DD, GG>(s, n_total_dev, n_total_cap, n_real, tables, g, cfg, nbr, ldn, count, sc, lcap, ovf_queue, balanced, st)
+#define LS(DD, GG) launch_search_t<DD, GG>(s, n_total_dev, n_total_cap, n_real, tables, g, cfg, nbr, ldn, count, sc, lcap, ovf_queue, balanced, st, rscale, gate, max_out)
     if (cfg.D == 3) {
         if (G == 4) LS(3, 4); else if (G == 8) LS(3, 8); else if (G == 16) LS(3, 16); else if (G == 32) LS(3, 32); else LS(3, 64);
     } else {

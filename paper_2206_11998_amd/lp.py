@@ -27,9 +27,10 @@ EXPORTS = ["lp_config_default", "lp_create", "lp_destroy", "lp_neighbors", "lp_n
            "lp_last_error"]
 MLP_NPARAM = 5313
 MLP_NIN = 16
-TUNE_SEARCH_MODE, TUNE_SEARCH_GROUP, TUNE_SOLVE_BLOCK, TUNE_SOLVE_MODE, TUNE_QUEUE_TILE, TUNE_SEARCH_CAP = range(6)
-TUNE_COUNT = 6
-TUNE_NAMES = ["search_mode", "search_group", "solve_block", "solve_mode", "queue_tile", "search_cap"]
+(TUNE_SEARCH_MODE, TUNE_SEARCH_GROUP, TUNE_SOLVE_BLOCK, TUNE_SOLVE_MODE, TUNE_QUEUE_TILE, TUNE_SEARCH_CAP,
+ TUNE_LIST_SKIN) = range(7)
+TUNE_COUNT = 7
+TUNE_NAMES = ["search_mode", "search_group", "solve_block", "solve_mode", "queue_tile", "search_cap", "list_skin"]
 STAGES = ["prep", "cells", "search", "fit", "update", "fallback", "step", "mlp"]
 
 
@@ -70,7 +71,7 @@ class Info(C.Structure):
     _fields_ = [
         ("t", C.c_double), ("dt", C.c_double), ("n_ghost", C.c_int64), ("max_count", C.c_int32),
         ("n_fallback", C.c_int32), ("n_limited", C.c_int64), ("error_bits", C.c_uint32), ("levels", C.c_int32 * 2),
-        ("n_mlp", C.c_int64), ("n_mlp_plain", C.c_int64), ("n_refined", C.c_int64),
+        ("n_mlp", C.c_int64), ("n_mlp_plain", C.c_int64), ("n_refined", C.c_int64), ("n_list_builds", C.c_int64),
     ]
 
 
@@ -373,7 +374,7 @@ class Context:
         return {"t": inf.t, "dt": inf.dt, "n_ghost": inf.n_ghost, "max_count": inf.max_count,
                 "n_fallback": inf.n_fallback, "n_limited": inf.n_limited, "error_bits": inf.error_bits,
                 "levels": (inf.levels[0], inf.levels[1]), "n_mlp": inf.n_mlp, "n_mlp_plain": inf.n_mlp_plain,
-                "n_refined": inf.n_refined}
+                "n_refined": inf.n_refined, "n_list_builds": inf.n_list_builds}
 
     def set_time(self, t: float, stream=None):
         self._raise(lib().lp_set_time(self._h, _stream_ptr(stream), float(t)))

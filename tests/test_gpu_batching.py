@@ -253,3 +253,67 @@ def test_autotune_failure_leaves_the_context_clean(lp):
     ctx2.run(dev2, 2)
     assert ctx2.check() == lp.OK
     assert ctx2.info()["t"] > before["t"]
+
+
+def _run(lp, cfg, st, nsteps, precision="fp64", tuning=None, split=None):
+    """lp_run over nsteps (in pieces of `split` steps if given); state and info."""
+    ctx = lp.Context(cfg, precision=precision)
+    for p, v in (tuning or {}).items():
+        ctx.set_tuning(p, v)
+    dev = lp.state_to_device(st)
+    done = 0
+    while done < nsteps:
+        k = min(split or nsteps, nsteps - done)
+        ctx.run(dev, k)
+        done += k
+    assert ctx.check() == lp.OK, lp.lib().lp_last_error(ctx._h)
+    out, inf = lp.state_to_host(dev), ctx.info()
+    ctx.close()
+    return out, inf
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_list_reuse_identical(lp, case, precision):
+    """Neighbour lists reused across steps (candidates within (1 + skin) r,
+    filtered exactly every step) give the full search's results bit for bit,
+    in graph-replayed runs and in eager steps; without mirror walls the
+    candidate lists are rebuilt on fewer steps than there are steps."""
+    cfg, st = CASES[case]()
+    nsteps = 7  # the coarse vacuum cloud's lists outgrow 256 entries after 8 steps
+    ref, rinf = _run(lp, cfg, st, nsteps, precision, {lp.TUNE_LIST_SKIN: 0})
+    assert rinf["n_list_builds"] == 0
+    for skin in (50, 150, 400):
+        tag = "%s %s skin %d" % (case, precision, skin)
+        got, inf = _run(lp, cfg, st, nsteps, precision, {lp.TUNE_LIST_SKIN: skin})
+        say("list reuse", tag, "full searches:", inf["n_list_builds"], "of", nsteps, "steps")
+        _same(got, ref, tag)
+        if case == "sod slab":
+            assert inf["n_list_builds"] == 0  # mirror walls: a full search every step
+        elif skin <= 150:
+            assert 1 <= inf["n_list_builds"] < nsteps
+        else:
+            # the coarse cloud's candidate lists within 1.4 r outgrow max_nb:
+            # every step rebuilds, and the particles concerned are searched exactly
+            assert 1 <= inf["n_list_builds"] <= nsteps
+    got = _steps(lp, cfg, st, 4, precision, {lp.TUNE_LIST_SKIN: 150})
+    _same(got, _steps(lp, cfg, st, 4, precision, {lp.TUNE_LIST_SKIN: 0}), "%s %s eager" % (case, precision))
+
+
+def test_list_reuse_after_other_calls(lp):
+    """A neighbour search, a derivative call and a run on other particles
+    between steps of one context rebuild the candidate lists first."""
+    cfg, st = CASES["vacuum 60k"]()
+    ref, _ = _run(lp, cfg, st, 7, tuning={lp.TUNE_LIST_SKIN: 0})
+    ctx = lp.Context(cfg)
+    dev = lp.state_to_device(st)
+    ctx.run(dev, 2)
+    other = lp.state_to_device(W.vacuum3d(n_particles=30_000, seed=8)[1])
+    ctx.run(other, 2)
+    ctx.run(dev, 2)
+    h = (dev["m"] * dev["V"]) ** (1.0 / 3.0) * cfg["kappa"]
+    ctx.neighbors(dev["x"], h)
+    ctx.gfd(dev["x"], h, [dev["V"], dev["P"]])
+    ctx.run(dev, 3)
+    assert ctx.check() == lp.OK
+    _same(lp.state_to_host(dev), ref, "after other calls")
