@@ -280,6 +280,8 @@ def main():
     ap.add_argument("--search-group", type=int, default=None)
     ap.add_argument("--max-nb", type=int, default=None, help="override the neighbour-list capacity")
     ap.add_argument("--solve-block", type=int, default=None)
+    ap.add_argument("--list-skin", type=int, default=None,
+                    help="neighbour-list reuse skin in per mille of r (0: a full search every step)")
     ap.add_argument("--solve-mode", type=int, default=None, help="0 direct, 1 work queue, 2 persistent work queue")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-openbc", action="store_true",
@@ -362,6 +364,8 @@ def main():
             ctx.set_tuning(lp.TUNE_SEARCH_GROUP, args.search_group)
         if args.solve_block is not None:
             ctx.set_tuning(lp.TUNE_SOLVE_BLOCK, args.solve_block)
+        if args.list_skin is not None:
+            ctx.set_tuning(lp.TUNE_LIST_SKIN, args.list_skin)
         return ctx
 
     for prec in precisions:

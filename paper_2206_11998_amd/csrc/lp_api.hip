@@ -69,12 +69,14 @@ struct lp_ctx {
     bool mlp_ready = false;         // network parameters set
     bool want_stage = false;        // keep network-estimator staging allocated (lp_features)
     int queue_tile = 1024;          // LP_TUNE_QUEUE_TILE
-    // neighbour-list reuse (LP_TUNE_LIST_SKIN): candidate radius (1 + skin/1000) r
-    int list_skin = 150;
+    // neighbour-list reuse (LP_TUNE_LIST_SKIN): candidate radius (1 + skin/1000) r; off by
+    // default (on the 2M vacuum cloud the exact filter costs as much as the search it saves)
+    int list_skin = 0;
     uint64_t reuse_gen = 0;         // workspace generation the device candidate set belongs to
     lp_particles reuse_p;           // particle arrays it was built for
     int reuse_skin = -1;            // skin it was built with
     int search_lcap_cand = 0;       // LDS list slots of the rebuild search (from the longest candidate list)
+    bool grid_set = false;          // a grid has been planned
     // while set, ensure() carves buffers out of this device block instead of
     // allocating (lp_neighbors_noalloc)
     char *arena = nullptr;
@@ -431,6 +433,7 @@ static void choose_levels(lp_ctx *c, double rmin, double rmax) {
     c->S_grid = S;
     c->last_levels[0] = lv[0];
     c->last_levels[1] = lv[1];
+    c->grid_set = true;
 }
 
 // A graph-replayed step keeps the grid it was captured with.  That grid stays
@@ -493,7 +496,7 @@ static lp_status ensure_capacity(lp_ctx *c, int64_t n_real, int64_t n_total, boo
     ENSURE(c, c->queue, sizeof(int) * nt);
     ENSURE(c, c->ovfq, sizeof(int) * nt);
     if (state && reuse_on(c)) {
-        ENSURE(c, c->cand, sizeof(int) * (size_t)c->dc.max_nb * nt);
+        ENSURE(c, c->cand, sizeof(int) * (size_t)c->dc.max_nb * (size_t)((nt + 7) / 8 * 8));  // interleaved by 8
         ENSURE(c, c->ccount, sizeof(int) * nt);
         ENSURE(c, c->xb, sizeof(double) * 3 * nr);
         ENSURE(c, c->Rb, sizeof(double) * nr);
@@ -653,7 +656,8 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
         n_total = n + c->sc_host->n_ghost;
         // a planning step of lp_run keeps the grid a captured graph was made
         // with while it still covers the particles and their radii
-        const bool keep = c->grid_margin > 0.0 && c->graph && c->graph_gen == c->gen && !grid_outdated(c);
+        const bool keep = c->grid_set && c->grid_margin > 0.0 &&
+                          ((c->graph && c->graph_gen == c->gen) || reuse_on(c)) && !grid_outdated(c);
         if (!keep) choose_levels(c, bits_to_double(c->sc_host->rmin), bits_to_double(c->sc_host->rmax));
         int64_t want = n_total;
         if (c->nwalls && c->grid_margin > 0.0) {
@@ -739,11 +743,12 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
     stage_mark(c, st, 2, true);
     if (reuse) {
         // rebuild steps: the candidates within (1 + skin) r; every step: the exact lists from them
+        // (candidate lists interleaved by eight particles: list stride 0)
         launch_search(srt, &c->sc->n_total, (int)n_total, n, (const uint32_t *)c->tables.p, c->grid, c->dc,
-                      (int *)c->cand.p, ldn, (int *)c->ccount.p, c->sc, c->search_group,
+                      (int *)c->cand.p, 0, (int *)c->ccount.p, c->sc, c->search_group,
                       c->search_cap ? c->search_cap : c->search_lcap_cand, (int *)c->ovfq.p, true, st,
                       reuse_scale(c), gate, &c->sc->max_cand);
-        launch_filter(srt, &c->sc->n_total, (int)n_total, n, c->dc, (const int *)c->cand.p, ldn,
+        launch_filter(srt, &c->sc->n_total, (int)n_total, n, c->dc, (const int *)c->cand.p, 0,
                       (const int *)c->ccount.p, (int *)c->nbr.p, ldn, (int *)c->count.p,
                       (const uint32_t *)c->tables.p, c->grid, c->sc, c->search_group,
                       c->search_cap ? c->search_cap : c->search_lcap, (int *)c->fovfq.p, st);
@@ -815,7 +820,9 @@ extern "C" lp_status lp_step(lp_ctx *c, void *stream, const lp_particles *p, dou
     if (s != LP_OK) return s;
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)stream;
-    c->grid_margin = 0.0;
+    // with reused lists, eager steps also plan the grid with headroom and
+    // keep it while it serves (a new grid means new cells and candidates)
+    c->grid_margin = reuse_on(c) ? 0.125 : 0.0;
     stage_mark(c, st, LP_STAGE_STEP, true);
     s = step_impl(c, st, p, dt, true, 0);
     stage_mark(c, st, LP_STAGE_STEP, false);
@@ -1398,6 +1405,8 @@ extern "C" lp_status lp_autotune(lp_ctx *c, void *stream, const lp_particles *p,
         c->profiling = prof;
     };
     auto run_candidate = [&](double &ms) -> lp_status {
+        // the grid policy of lp_step (headroom, kept while it serves, when lists are reused)
+        c->grid_margin = reuse_on(c) ? 0.125 : 0.0;
         for (int a = 0; a < narr; ++a)
             HIPCHK(c, hipMemcpyAsync(dst[a], src[a], sizeof(double) * n, hipMemcpyDeviceToDevice, st));
         lp_status r = step_impl(c, st, &q, 0.0, true, 0);  // warm-up (plans and allocates)

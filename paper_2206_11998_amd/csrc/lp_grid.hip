@@ -556,18 +556,19 @@ __global__ __launch_bounds__(LP_BLOCK) void k_reuse_check(Soa p, DevCfg cfg, con
                                                           const double *xb1, const double *xb2, const double *Rb,
                                                           DevScalars *sc) {
     if (!sc->have_cand || sc->n_total == 0) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double a = -INFINITY, d = 0.0;
-    if (i < p.n) {
-        const double *xb[3] = {xb0, xb1, xb2};
+    const double *xb[3] = {xb0, xb1, xb2};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < p.n; i += gridDim.x * blockDim.x) {
         double d2 = 0.0;
         for (int q = 0; q < cfg.D; ++q) {
             const double e = min_image(cfg, q, p.x[q][i] - xb[q][i]);
             d2 += e * e;
         }
-        d = sqrt(d2);
-        a = r[i] + d - Rb[i];
-        if (!(a == a) || !(d == d)) { a = INFINITY; d = INFINITY; }  // NaN positions: rebuild
+        const double di = sqrt(d2);
+        const double ai = r[i] + di - Rb[i];
+        if (!(ai == ai) || !(di == di)) { a = INFINITY; d = INFINITY; }  // NaN positions: rebuild
+        a = fmax(a, ai);
+        d = fmax(d, di);
     }
     a = wave_max(a);
     d = wave_max(d);
@@ -618,8 +619,9 @@ __global__ void k_reuse_commit(Soa p, DevCfg cfg, const double *r, double *xb0, 
 void launch_reuse(const Soa &p, const DevCfg &cfg, const double *r, double *const xb[3], double *Rb, int n,
                   double rscale, int force, DevScalars *sc, hipStream_t st) {
     dim3 grid(blocks_for((uint64_t)n));
+    unsigned cb = blocks_for((uint64_t)n, 4 * LP_BLOCK);  // four particles per thread, one atomic pair per block
     double *x2 = cfg.D == 3 ? xb[2] : xb[0];
-    hipLaunchKernelGGL(k_reuse_check, grid, dim3(LP_BLOCK), 0, st, p, cfg, r, xb[0], xb[1], x2, Rb, sc);
+    hipLaunchKernelGGL(k_reuse_check, dim3(cb), dim3(LP_BLOCK), 0, st, p, cfg, r, xb[0], xb[1], x2, Rb, sc);
     hipLaunchKernelGGL(k_reuse_decide, dim3(1), dim3(1), 0, st, sc, force);
     hipLaunchKernelGGL(k_reuse_commit, grid, dim3(LP_BLOCK), 0, st, p, cfg, r, xb[0], xb[1], x2, Rb, rscale, sc);
     CHECK_LAUNCH();

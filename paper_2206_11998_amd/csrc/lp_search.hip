@@ -12,6 +12,17 @@
 // reads it coalesced) holds cell-order indices; count[s] is the true count.
 #include "lp_internal.h"
 
+// Entry c of the list of cell-order particle s: ldn > 0 column-major
+// (c * ldn + s), ldn < 0 row-major (s * (-ldn) + c), ldn == 0 interleaved by
+// eight particles, (s / 8) * 8 max_nb + 8 c + s % 8, the layout of the
+// candidate lists: the eight lane groups of a wave reading entries c0 .. c0 + 7
+// of their particles read 64 consecutive entries.
+__device__ __forceinline__ int64_t list_at(int ldn, int s, int c, int max_nb) {
+    if (ldn > 0) return (int64_t)c * ldn + s;
+    if (ldn < 0) return (int64_t)s * (-ldn) + c;
+    return (int64_t)(s >> 3) * (8 * max_nb) + 8 * c + (s & 7);
+}
+
 // Cells of level L that cover [x - r, x + r] per axis: first cell and count.
 template <int D>
 __device__ __forceinline__ void search_box(const DevGrid &g, const DevCfg &cfg, int L, const double xi[3], double ri,
@@ -127,7 +138,7 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search(Sorted srt, const int *n_to
                     if (df < de) ++rank;
                     else if (df == de && f != e && srt.id[gj[f]] < srt.id[je]) ++rank;  // exact tie: id order
                 }
-                nbr[ldn > 0 ? (int64_t)rank * ldn + s : (int64_t)s * (-ldn) + rank] = je;
+                nbr[list_at(ldn, s, rank, cfg.max_nb)] = je;
             }
         }
     }
@@ -185,7 +196,7 @@ __global__ __launch_bounds__(64) void k_search_overflow(Sorted srt, const uint32
                 if (df < de) ++rank;
                 else if (df == de && f != e && srt.id[gj[f]] < srt.id[je]) ++rank;
             }
-            nbr[ldn > 0 ? (int64_t)rank * ldn + s : (int64_t)s * (-ldn) + rank] = je;
+            nbr[list_at(ldn, s, rank, cfg.max_nb)] = je;
         }
         __syncthreads();
     }
@@ -398,7 +409,7 @@ __device__ __forceinline__ void bal_rank_write(const BalLds &l, int k, bool acti
         const int c = idx / PPB, gq = idx % PPB;
         if (c < lk[gq]) {
             const int sq = s0 + gq;
-            nbr[ldn > 0 ? (int64_t)c * ldn + sq : (int64_t)sq * (-ldn) + c] = lout[c * PPB + gq];
+            nbr[list_at(ldn, sq, c, max_nb)] = lout[c * PPB + gq];
         }
     }
 }
@@ -633,7 +644,7 @@ __global__ __launch_bounds__(LP_BLOCK) void k_filter_bal(Sorted srt, const int *
         kc = kc < cfg.max_nb ? kc : cfg.max_nb;
         // indices of rounds t0 / t0 + 2G are in ja/jb and na/nb; slots past
         // the end read the particle itself (a valid index, never a hit)
-        auto index_at = [&](int t) -> int { return t < kc ? cand[(int64_t)t * ldc + s] : s; };
+        auto index_at = [&](int t) -> int { return t < kc ? cand[list_at(ldc, s, t, cfg.max_nb)] : s; };
         int ja = index_at(lane), jb = index_at(lane + G);
         int na = index_at(lane + 2 * G), nb = index_at(lane + 3 * G);
         double pa[3] = {0.0, 0.0, 0.0}, pb[3] = {0.0, 0.0, 0.0};
@@ -717,7 +728,7 @@ __global__ __launch_bounds__(64) void k_filter_overflow(Sorted srt, DevCfg cfg, 
         };
         if (kc >= 0) {
             kc = kc < cfg.max_nb ? kc : cfg.max_nb;
-            for (int t = lane; t < kc; t += 64) hit(cand[(int64_t)t * ldc + s]);
+            for (int t = lane; t < kc; t += 64) hit(cand[list_at(ldc, s, t, cfg.max_nb)]);
         } else {
             // no candidates kept: the exact search over the cells, which this
             // step's rebuild has just laid out for the current positions
@@ -749,7 +760,7 @@ __global__ __launch_bounds__(64) void k_filter_overflow(Sorted srt, DevCfg cfg, 
                 if (df < de) ++rank;
                 else if (df == de && f != e && srt.id[gj[f]] < srt.id[je]) ++rank;
             }
-            nbr[ldn > 0 ? (int64_t)rank * ldn + s : (int64_t)s * (-ldn) + rank] = je;
+            nbr[list_at(ldn, s, rank, cfg.max_nb)] = je;
         }
         __syncthreads();
     }
