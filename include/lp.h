@@ -147,6 +147,32 @@ lp_status lp_destroy(struct lp_ctx *ctx);
 lp_status lp_neighbors(struct lp_ctx *ctx, void *stream, int64_t n, const double *x, const double *y,
                        const double *z, const double *r, int32_t *count, int32_t *idx);
 
+/* Caller-owned workspace (the store/solver split of Sec. 2.2: the particle
+ * store and the solver's scratch are separate objects).
+ *
+ * lp_workspace_bytes: the device bytes a time step (lp_step or lp_run) of the
+ * particles p needs when every buffer comes from one caller block: the
+ * radii, ghosts, cell tables of the grid planned for p (with lp_run's
+ * headroom), cell-order copies, neighbour lists, derivatives and, per the
+ * context's configuration, refinement, network and list-reuse buffers.
+ * Runs the planning part of a step (radii, ghost count, grid; synchronises)
+ * and writes the total, with 256 bytes of alignment slack, to *bytes (host).
+ * The particles are only read.
+ *
+ * lp_set_workspace: every later buffer of the context is carved, 256-byte
+ * aligned, from the caller's device block dev[0 .. bytes) instead of being
+ * allocated; the context's own buffers are freed (the network's parameters
+ * and optimiser moments move into the block).  dev stays the caller's (never
+ * freed by the library) and must outlive the context or a later call; dev =
+ * NULL returns to library-allocated buffers.  A step whose buffers no longer
+ * fit -- more particles or ghosts, a finer grid, a buffer that grows (it is
+ * carved again after the others) -- returns LP_E_CAPACITY before launching
+ * anything; calling lp_set_workspace again (with the same or a larger
+ * block) starts carving afresh.  Synchronises the stream.  LP_E_ARG for a
+ * block that is not 256-byte aligned or smaller than 256 bytes. */
+lp_status lp_workspace_bytes(struct lp_ctx *ctx, void *stream, const lp_particles *p, int64_t *bytes);
+lp_status lp_set_workspace(struct lp_ctx *ctx, void *stream, void *dev, int64_t bytes);
+
 /* lp_neighbors for callers that cannot allocate device memory (code under
  * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
  * same lists, bit for bit, computed in a static scratch block of

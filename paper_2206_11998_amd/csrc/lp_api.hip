@@ -23,6 +23,7 @@ static double bits_to_double(unsigned long long b) {
 struct Buf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool owned = false;  // allocated by the library (else carved from a caller's or the scratch block)
 };
 
 struct lp_ctx {
@@ -78,9 +79,15 @@ struct lp_ctx {
     int search_lcap_cand = 0;       // LDS list slots of the rebuild search (from the longest candidate list)
     bool grid_set = false;          // a grid has been planned
     // while set, ensure() carves buffers out of this device block instead of
-    // allocating (lp_neighbors_noalloc)
+    // allocating: the caller's workspace (lp_set_workspace) or the scratch
+    // block of lp_neighbors_noalloc; running out returns arena_status
     char *arena = nullptr;
     size_t arena_bytes = 0, arena_used = 0;
+    lp_status arena_status = LP_E_NOMEM;
+    bool caller_ws = false;         // arena is the caller's workspace
+    // while set, ensure() only adds up the bytes it would carve (lp_workspace_bytes)
+    bool measure = false;
+    size_t measure_bytes = 0;
 };
 
 // every workspace buffer of a context, for swapping the whole set out and back
@@ -112,27 +119,39 @@ static lp_status fail(lp_ctx *c, lp_status s, const char *fmt, ...) {
         if (e_ != hipSuccess) return fail(ctx, LP_E_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 static lp_status ensure(lp_ctx *c, Buf &b, size_t bytes) {
+    if (c->measure) {
+        c->measure_bytes += align256(bytes);
+        return LP_OK;
+    }
     if (b.bytes >= bytes) return LP_OK;
     ++c->gen;  // captured graphs hold the old address
     if (c->arena) {
-        size_t off = (c->arena_used + 255) & ~(size_t)255;
+        // a buffer that grows is carved anew after the others (its old region stays unused)
+        size_t off = align256(c->arena_used);
         if (off > c->arena_bytes || bytes > c->arena_bytes - off)
-            return fail(c, LP_E_NOMEM, "the workspace needs more than the %zu-byte scratch block", c->arena_bytes);
+            return fail(c, c->arena_status, "the workspace needs more than the %zu-byte %s", c->arena_bytes,
+                        c->caller_ws ? "caller workspace" : "scratch block");
+        if (b.p && b.owned) (void)hipFree(b.p);
         b.p = c->arena + off;
         b.bytes = bytes;
+        b.owned = false;
         c->arena_used = off + bytes;
         return LP_OK;
     }
-    if (b.p) (void)hipFree(b.p);
+    if (b.p && b.owned) (void)hipFree(b.p);
     b.p = nullptr;
     b.bytes = 0;
+    b.owned = false;
     size_t want = bytes + bytes / 8 + 256;
     if (hipMalloc(&b.p, want) != hipSuccess) {
         (void)hipGetLastError();
         return fail(c, LP_E_NOMEM, "device allocation of %zu bytes failed", want);
     }
     b.bytes = want;
+    b.owned = true;
     return LP_OK;
 }
 
@@ -343,7 +362,7 @@ extern "C" lp_status lp_destroy(lp_ctx *c) {
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     for (int q = 0; q < kNumBufs; ++q)
-        if ((c->*kBufs[q]).p) (void)hipFree((c->*kBufs[q]).p);
+        if ((c->*kBufs[q]).p && (c->*kBufs[q]).owned) (void)hipFree((c->*kBufs[q]).p);
     if (c->sc) (void)hipFree(c->sc);
     if (c->sc_host) (void)hipHostFree(c->sc_host);
     delete c;
@@ -997,15 +1016,24 @@ extern "C" lp_status lp_neighbors_noalloc(lp_ctx *c, void *stream, int64_t n, co
     const DevGrid grid = c->grid;
     const double S_grid = c->S_grid;
     const bool prof = c->profiling;
+    char *const arena0 = c->arena;
+    const size_t arena_bytes0 = c->arena_bytes, arena_used0 = c->arena_used;
+    const lp_status arena_status0 = c->arena_status;
+    const bool caller_ws0 = c->caller_ws;
     c->cap_real = c->cap_total = c->cap_ghost = 0;
     c->profiling = false;
     c->arena = (char *)block;
     c->arena_bytes = LP_NOALLOC_SCRATCH_BYTES;
     c->arena_used = 0;
+    c->arena_status = LP_E_NOMEM;
+    c->caller_ws = false;
     lp_status s = lp_neighbors(c, stream, n, x, y, z, r, count, idx);
     if (s != LP_OK) (void)hipStreamSynchronize((hipStream_t)stream);
-    c->arena = nullptr;
-    c->arena_bytes = c->arena_used = 0;
+    c->arena = arena0;
+    c->arena_bytes = arena_bytes0;
+    c->arena_used = arena_used0;
+    c->arena_status = arena_status0;
+    c->caller_ws = caller_ws0;
     for (int q = 0; q < kNumBufs; ++q) c->*kBufs[q] = saved[q];
     c->cap_real = cr;
     c->cap_total = ct;
@@ -1520,6 +1548,99 @@ static lp_status mlp_alloc(lp_ctx *c) {
     ENSURE(c, c->adam_m, sizeof(float) * LP_MLP_NPARAM);
     ENSURE(c, c->adam_v, sizeof(float) * LP_MLP_NPARAM);
     ENSURE(c, c->mgrad, sizeof(float) * LP_MLP_NPARAM);
+    return LP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Caller-owned workspace
+// ---------------------------------------------------------------------------
+extern "C" lp_status lp_workspace_bytes(lp_ctx *c, void *stream, const lp_particles *p, int64_t *bytes) {
+    if (!c || !bytes) return LP_E_ARG;
+    lp_status s = check_particles(c, p);
+    if (s != LP_OK) return s;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int n = (int)p->n;
+    const bool mixed = c->dc.precision == LP_MIXED;
+    // the planning part of a step: radii, time-step bound, ghost count, grid
+    ENSURE(c, c->h, sizeof(double) * n);
+    ENSURE(c, c->r, sizeof(double) * n);
+    ENSURE(c, c->gcnt, sizeof(uint32_t) * (n + 1));
+    ENSURE(c, c->scan_tmp, sizeof(uint32_t) * scan_tmp_words(n));
+    ENSURE(c, c->prep_part, sizeof(double) * prep_partial_words(n));
+    Soa soa = soa_of(p);
+    launch_reset_scalars(c->sc, 0.0, n, 1, st);
+    launch_prep(soa, c->dc, c->sc, (double *)c->h.p, (double *)c->r.p, (double *)c->prep_part.p, st);
+    if (c->nwalls) {
+        launch_ghost_count(soa, c->dc, c->sc, (uint32_t *)c->gcnt.p, st);
+        launch_scan_u32((uint32_t *)c->gcnt.p, n, (uint32_t *)c->scan_tmp.p, &c->sc->n_ghost, st);
+    }
+    HIPCHK(c, hipGetLastError());
+    if ((s = read_scalars(c, st)) != LP_OK) return s;
+    const double margin0 = c->grid_margin;
+    c->grid_margin = 0.125;  // lp_run's headroom
+    choose_levels(c, bits_to_double(c->sc_host->rmin), bits_to_double(c->sc_host->rmax));
+    c->grid_margin = margin0;
+    const int64_t ng = c->sc_host->n_ghost;
+    const int64_t want = c->nwalls ? n + ng + ng / 4 + 1024 : n;
+    // every buffer a step (eager or replayed) of these particles carves, from an empty workspace
+    const int64_t cr = c->cap_real, ct = c->cap_total, cg = c->cap_ghost;
+    c->cap_real = c->cap_total = c->cap_ghost = 0;
+    c->measure = true;
+    c->measure_bytes = 0;
+    (void)ensure(c, c->h, sizeof(double) * n);
+    (void)ensure(c, c->r, sizeof(double) * n);
+    (void)ensure(c, c->gcnt, sizeof(uint32_t) * (n + 1));
+    (void)ensure(c, c->scan_tmp, sizeof(uint32_t) * scan_tmp_words(n));
+    (void)ensure(c, c->prep_part, sizeof(double) * prep_partial_words(n));
+    (void)ensure_capacity(c, n, want, true, mixed);
+    if (c->mlp_ready || c->dc.est_mode == LP_EST_MLP) (void)mlp_alloc(c);
+    c->measure = false;
+    c->cap_real = cr;
+    c->cap_total = ct;
+    c->cap_ghost = cg;
+    *bytes = (int64_t)c->measure_bytes + 256;
+    return LP_OK;
+}
+
+extern "C" lp_status lp_set_workspace(lp_ctx *c, void *stream, void *dev, int64_t bytes) {
+    if (!c) return LP_E_ARG;
+    if (dev && (bytes < 256 || ((uintptr_t)dev & 255u) != 0))
+        return fail(c, LP_E_ARG, "lp_set_workspace: the block must be 256-byte aligned and at least 256 bytes");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+    // the network's parameters and optimiser moments outlive the move
+    std::vector<float> keep;
+    const bool have = c->mlp_ready && c->theta.p && c->adam_m.p && c->adam_v.p;
+    if (have) {
+        keep.resize(3 * (size_t)LP_MLP_NPARAM);
+        HIPCHK(c, hipMemcpy(keep.data(), c->theta.p, sizeof(float) * LP_MLP_NPARAM, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(keep.data() + LP_MLP_NPARAM, c->adam_m.p, sizeof(float) * LP_MLP_NPARAM,
+                            hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(keep.data() + 2 * LP_MLP_NPARAM, c->adam_v.p, sizeof(float) * LP_MLP_NPARAM,
+                            hipMemcpyDeviceToHost));
+    }
+    for (int q = 0; q < kNumBufs; ++q) {
+        Buf &b = c->*kBufs[q];
+        if (b.p && b.owned) (void)hipFree(b.p);
+        b = Buf{};
+    }
+    c->cap_real = c->cap_total = c->cap_ghost = 0;
+    c->arena = (char *)dev;
+    c->arena_bytes = dev ? (size_t)bytes : 0;
+    c->arena_used = 0;
+    c->arena_status = LP_E_CAPACITY;
+    c->caller_ws = dev != nullptr;
+    ++c->gen;
+    if (have) {
+        lp_status s = mlp_alloc(c);
+        if (s != LP_OK) return s;
+        HIPCHK(c, hipMemcpy(c->theta.p, keep.data(), sizeof(float) * LP_MLP_NPARAM, hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->adam_m.p, keep.data() + LP_MLP_NPARAM, sizeof(float) * LP_MLP_NPARAM,
+                            hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->adam_v.p, keep.data() + 2 * LP_MLP_NPARAM, sizeof(float) * LP_MLP_NPARAM,
+                            hipMemcpyHostToDevice));
+    }
     return LP_OK;
 }
 

@@ -19,7 +19,8 @@ FP64, MIXED = 0, 1
 EST_PLAIN, EST_INJECTED, EST_MLP = 0, 1, 2
 FLAG_LIMITED, FLAG_DEGENERATE, FLAG_VACUUM, FLAG_SUBSTITUTED, FLAG_FALLBACK, FLAG_NUMERIC = 1, 2, 4, 8, 16, 32
 
-EXPORTS = ["lp_config_default", "lp_create", "lp_destroy", "lp_neighbors", "lp_neighbors_noalloc", "lp_gfd", "lp_gfd3", "lp_outflow",
+EXPORTS = ["lp_config_default", "lp_create", "lp_destroy", "lp_workspace_bytes", "lp_set_workspace", "lp_neighbors",
+           "lp_neighbors_noalloc", "lp_gfd", "lp_gfd3", "lp_outflow",
            "lp_reservoir_inflow", "lp_inflow_layer", "lp_step", "lp_run",
            "lp_conservation", "lp_check", "lp_get_info", "lp_set_time", "lp_profile", "lp_profile_read",
            "lp_set_tuning", "lp_get_tuning", "lp_autotune", "lp_train_cfg_default", "lp_features", "lp_mlp_init",
@@ -94,6 +95,10 @@ def lib():
         L.lp_destroy.argtypes = [vp]
         L.lp_neighbors.restype = i32
         L.lp_neighbors.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
+        L.lp_workspace_bytes.restype = i32
+        L.lp_workspace_bytes.argtypes = [vp, vp, C.POINTER(Particles), C.POINTER(C.c_int64)]
+        L.lp_set_workspace.restype = i32
+        L.lp_set_workspace.argtypes = [vp, vp, vp, i64]
         L.lp_neighbors_noalloc.restype = i32
         L.lp_neighbors_noalloc.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
         L.lp_gfd.restype = i32
@@ -280,6 +285,23 @@ class Context:
         if st not in (OK, E_CAPACITY):
             self._raise(st)
         return count, idx, st
+
+    def workspace_bytes(self, s: dict, stream=None) -> int:
+        """lp_workspace_bytes: device bytes a step of these particles needs in a caller block."""
+        p = self._particles(s)
+        b = C.c_int64(0)
+        self._raise(lib().lp_workspace_bytes(self._h, _stream_ptr(stream), C.byref(p), C.byref(b)))
+        return b.value
+
+    def set_workspace(self, buf, stream=None):
+        """lp_set_workspace over a CUDA uint8 tensor (kept alive here); None: library-allocated buffers."""
+        if buf is None:
+            self._ws = None
+            self._raise(lib().lp_set_workspace(self._h, _stream_ptr(stream), None, 0))
+            return
+        self._ws = buf
+        self._raise(lib().lp_set_workspace(self._h, _stream_ptr(stream), C.c_void_p(buf.data_ptr()),
+                                           int(buf.numel() * buf.element_size())))
 
     def neighbors_noalloc(self, x, r, count, idx, stream=None):
         """lp_neighbors_noalloc into the caller's count[n] / idx[n, max_nb]
