@@ -70,6 +70,18 @@ def search_bytes(count):
     return 40.0 + 4.0 * k
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def source_hash():
     """Hash of the kernel sources: HBM counters committed under profiles/ are
     only reported while the kernels they were taken on are unchanged."""
@@ -450,7 +462,21 @@ def main():
             len(sample), cpu_time, reps, threads, rinfo["status"]))
         cpu = {"value": len(sample) / cpu_time, "unit": "particle-updates/s", "cores": threads, "kind": "oracle",
                "sample": "one step of %d particles of the %d-particle workload (global dt and bucket grid over "
-                         "all particles included), timed %d times, mean" % (len(sample), n, reps)}
+                         "all particles included), timed %d times, mean" % (len(sample), n, reps),
+               "cpu_model": cpu_model(), "host_threads": os.cpu_count()}
+        # the same oracle on one thread, on the 100,000 particles nearest the centre (one step)
+        try:
+            sub = np.argsort((st["x"] ** 2).sum(axis=1))[:100_000]
+            oracle.set_num_threads(1)
+            t1 = time.perf_counter()
+            oracle.step_subset(cfg, st, np.sort(sub))
+            t1 = time.perf_counter() - t1
+            cpu["single_thread"] = {"value": len(sub) / t1, "unit": "particle-updates/s", "cores": 1,
+                                    "sample": "one step of the 100,000 particles nearest the centre (the densest, "
+                                              "longest lists) of the same workload"}
+            log("cpu reference, one thread: %d particles in %.2fs" % (len(sub), t1))
+        finally:
+            oracle.set_num_threads(threads)
         cvmax = np.sqrt(cfg["gamma"] * st["P"] * st["V"]).max()
         for prec, got in first_step.items():
             e = {}

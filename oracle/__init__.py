@@ -60,6 +60,8 @@ def lib():
         cp = C.POINTER(Cfg)
         L.lpo_num_threads.restype = C.c_int
         L.lpo_num_threads.argtypes = []
+        L.lpo_set_num_threads.restype = None
+        L.lpo_set_num_threads.argtypes = [C.c_int]
         L.lpo_limiter.restype = C.c_double
         L.lpo_limiter.argtypes = [C.c_double]
         L.lpo_estimator_ratio.restype = C.c_double
@@ -161,6 +163,11 @@ def _xyz(x, d):
     x = np.ascontiguousarray(x, dtype=np.float64)
     cols = [np.ascontiguousarray(x[:, a]) for a in range(d)]
     return cols + [None] * (3 - d)
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of later oracle calls (its results do not depend on the count)."""
+    lib().lpo_set_num_threads(int(n))
 
 
 def num_threads() -> int:

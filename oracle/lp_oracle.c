@@ -45,6 +45,15 @@ int lpo_num_threads(void)
 #endif
 }
 
+void lpo_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 #define ORC_MAXN 9      /* unknowns of the 3D second-order fit */
 #define ORC_MAXN3 19    /* unknowns of the 3D third-order fit */
 #define ORC_MAXF 5      /* fields V, u1..uD, P */

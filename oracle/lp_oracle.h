@@ -41,6 +41,7 @@ typedef struct {
 } lpo_cfg;
 
 int lpo_num_threads(void);
+void lpo_set_num_threads(int n);   /* OpenMP threads of later calls (results do not depend on it) */
 double lpo_limiter(double r);
 double lpo_estimator_ratio(double sl, double sr);
 double lpo_lstsq_qrp(int k, int n, int nrhs, double *A, double *B, double *X);
