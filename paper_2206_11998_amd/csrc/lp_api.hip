@@ -70,9 +70,8 @@ struct lp_ctx {
     bool mlp_ready = false;         // network parameters set
     bool want_stage = false;        // keep network-estimator staging allocated (lp_features)
     int queue_tile = 1024;          // LP_TUNE_QUEUE_TILE
-    // neighbour-list reuse (LP_TUNE_LIST_SKIN): candidate radius (1 + skin/1000) r; off by
-    // default (on the 2M vacuum cloud the exact filter costs as much as the search it saves)
-    int list_skin = 0;
+    // neighbour-list reuse (LP_TUNE_LIST_SKIN): candidate radius (1 + skin/1000) r
+    int list_skin = 150;
     uint64_t reuse_gen = 0;         // workspace generation the device candidate set belongs to
     lp_particles reuse_p;           // particle arrays it was built for
     int reuse_skin = -1;            // skin it was built with

@@ -117,7 +117,10 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search(Sorted srt, const int *n_to
     {
         int kmax = active ? lcnt[grp] : 0;
         for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o));
-        if ((threadIdx.x & 63) == 0 && kmax > 0) atomicMax(max_out, kmax);
+        // the atomic only when it can raise the maximum: same-address atomics
+        // serialise in L2, and one per wave costs milliseconds at 2M particles
+        if ((threadIdx.x & 63) == 0 && kmax > __hip_atomic_load(max_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(max_out, kmax);
     }
     if (active) {
         int k = lcnt[grp];
@@ -334,7 +337,10 @@ __device__ __forceinline__ void bal_rank_write(const BalLds &l, int k, bool acti
         // largest count of the wave: one atomic per wave (all lanes active here)
         int kmax = k;
         for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o));
-        if ((threadIdx.x & 63) == 0 && kmax > 0) atomicMax(max_out, kmax);
+        // the atomic only when it can raise the maximum: same-address atomics
+        // serialise in L2, and one per wave costs milliseconds at 2M particles
+        if ((threadIdx.x & 63) == 0 && kmax > __hip_atomic_load(max_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(max_out, kmax);
     }
     if (active) {
         if (lane == 0) {

@@ -1133,9 +1133,17 @@ template <int D, typename T, int MODE>
 __global__ __launch_bounds__(LP_BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void k_finish(SolveArgs a) {
     int limited = 0;
     for_work<MODE>(a, a.sc->head[1], [&](int s, int t) { limited += finish_one<D, T>(a, s, t) ? 1 : 0; });
-    // one atomic per wave (every lane of the wave is active here)
+    // wave sums (every lane of the wave is active here), then one atomic per block
     for (int o = 32; o > 0; o >>= 1) limited += __shfl_xor(limited, o);
-    if ((threadIdx.x & 63) == 0 && limited) atomicAdd(&a.sc->n_limited, (unsigned long long)limited);
+    // (same-address atomics serialise in L2)
+    __shared__ int wl[LP_BLOCK / 64];
+    if ((threadIdx.x & 63) == 0) wl[threadIdx.x >> 6] = limited;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) tot += wl[q];
+        if (tot) atomicAdd(&a.sc->n_limited, (unsigned long long)tot);
+    }
 }
 
 // The fits queued for refinement (condition estimate above refine_cond):
