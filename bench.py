@@ -390,7 +390,7 @@ def main():
         tuning = None
         if not args.no_autotune:
             t_at = time.time()
-            tuning, at_ms = ctx.autotune(dev, reps=2)
+            tuning, at_ms = ctx.autotune(dev, reps=6)
             log(prec, "autotune chose %s (%.3f ms/step) in %.1fs" % (tuning, at_ms, time.time() - t_at))
         ctx = tuned(ctx)
         tuning = {name: ctx.get_tuning(q) for q, name in enumerate(lp.TUNE_NAMES)}

@@ -353,9 +353,9 @@ enum {
 lp_status lp_set_tuning(struct lp_ctx *ctx, int32_t param, int32_t value);
 
 /* Autotuner: time full steps of a private copy of p (p itself is not
- * modified) for every launch-shape setting in turn -- the list skin, the
- * solve mode, the queue tile, the fit/update block size, the search mode and
- * group -- keep the
+ * modified) for every launch-shape setting in turn -- the solve mode, the
+ * queue tile, the fit/update block size, the search mode and group (not the
+ * list skin: a few steps cannot show how often a run rebuilds) -- keep the
  * fastest setting of each
  * (coordinate descent, `reps` timed steps per candidate after one warm-up),
  * and write the chosen values to best[LP_TUNE_COUNT] (host; may be NULL) and

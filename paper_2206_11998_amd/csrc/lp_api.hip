@@ -768,7 +768,7 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
                       reuse_scale(c), gate, &c->sc->max_cand);
         launch_filter(srt, &c->sc->n_total, (int)n_total, n, c->dc, (const int *)c->cand.p, 0,
                       (const int *)c->ccount.p, (int *)c->nbr.p, ldn, (int *)c->count.p,
-                      (const uint32_t *)c->tables.p, c->grid, c->sc, c->search_group,
+                      (const uint32_t *)c->tables.p, c->grid, c->sc, 8 /* lanes per particle: measured best */,
                       c->search_cap ? c->search_cap : c->search_lcap, (int *)c->fovfq.p, st);
     } else {
         run_search(c, srt, n_total, n, c->search_cap ? c->search_cap : c->search_lcap, st);
@@ -1466,8 +1466,8 @@ extern "C" lp_status lp_autotune(lp_ctx *c, void *stream, const lp_particles *p,
         have_saved = true;
         c->grid_margin = 0.0;
         struct Param { int id; std::vector<int> values; };
-        std::vector<Param> params = {{LP_TUNE_LIST_SKIN, {0, 100, 150, 250}},
-                                     {LP_TUNE_SOLVE_MODE, {0, 1, 2}},
+        // (not the list skin: a few steps from one state cannot see how often a run rebuilds)
+        std::vector<Param> params = {{LP_TUNE_SOLVE_MODE, {0, 1, 2}},
                                      {LP_TUNE_QUEUE_TILE, {256, 512, 1024}},
                                      {LP_TUNE_SOLVE_BLOCK, {64, 128, 256}},
                                      {LP_TUNE_SEARCH_MODE, {0, 1, 2}},
