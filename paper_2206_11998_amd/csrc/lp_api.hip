@@ -75,7 +75,6 @@ struct lp_ctx {
     uint64_t reuse_gen = 0;         // workspace generation the device candidate set belongs to
     lp_particles reuse_p;           // particle arrays it was built for
     int reuse_skin = -1;            // skin it was built with
-    int search_lcap_cand = 0;       // LDS list slots of the rebuild search (from the longest candidate list)
     bool grid_set = false;          // a grid has been planned
     // while set, ensure() carves buffers out of this device block instead of
     // allocating: the caller's workspace (lp_set_workspace) or the scratch
@@ -694,14 +693,6 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
             c->search_lcap = lcap;
             ++c->gen;  // a captured step holds the old buffer size
         }
-        // the same for the rebuild search of reused lists (its lists are the candidates)
-        const int prevc = c->sc_host->max_cand;
-        int lcc = prevc > 0 ? (prevc + 8 + 15) / 16 * 16 : 0;
-        if (lcc > 128) lcc = 0;
-        if (lcc != c->search_lcap_cand) {
-            c->search_lcap_cand = lcc;
-            ++c->gen;
-        }
     } else {
         n_total = c->cap_total;
     }
@@ -762,10 +753,9 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
     if (reuse) {
         // rebuild steps: the candidates within (1 + skin) r; every step: the exact lists from them
         // (candidate lists interleaved by eight particles: list stride 0)
-        launch_search(srt, &c->sc->n_total, (int)n_total, n, (const uint32_t *)c->tables.p, c->grid, c->dc,
-                      (int *)c->cand.p, 0, (int *)c->ccount.p, c->sc, c->search_group,
-                      c->search_cap ? c->search_cap : c->search_lcap_cand, (int *)c->ovfq.p, true, st,
-                      reuse_scale(c), gate, &c->sc->max_cand);
+        launch_search_cand(srt, &c->sc->n_total, (int)n_total, n, (const uint32_t *)c->tables.p, c->grid, c->dc,
+                           (int *)c->cand.p, (int *)c->ccount.p, c->sc, c->search_group, reuse_scale(c), gate,
+                           &c->sc->max_cand, st);
         launch_filter(srt, &c->sc->n_total, (int)n_total, n, c->dc, (const int *)c->cand.p, 0,
                       (const int *)c->ccount.p, (int *)c->nbr.p, ldn, (int *)c->count.p,
                       (const uint32_t *)c->tables.p, c->grid, c->sc, 8 /* lanes per particle: measured best */,

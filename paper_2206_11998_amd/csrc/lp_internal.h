@@ -183,6 +183,11 @@ void launch_search(const Sorted &s, const int *n_total_dev, int n_total_cap, int
                    const DevGrid &g, const DevCfg &cfg, int *nbr, int ldn, int *count, DevScalars *sc,
                    int group, int lcap, int *ovf_queue, bool balanced, hipStream_t st, double rscale = 1.0,
                    const unsigned *gate = nullptr, int *max_out = nullptr);
+// candidate lists of a rebuild (interleaved layout, unranked): every particle
+// within r_s * rscale; runs where *gate is set; max_out: the longest
+void launch_search_cand(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real, const uint32_t *tables,
+                        const DevGrid &g, const DevCfg &cfg, int *cand, int *ccount, DevScalars *sc, int group,
+                        double rscale, const unsigned *gate, int *max_out, hipStream_t st);
 // neighbour lists from reused candidate lists cand[c * ldc + s], c < ccount[s]:
 // the exact test d2 < r_s^2 on the current positions, (d2, id) order
 // (ccount[s] < 0: no candidates were kept; the cells -- laid out by this

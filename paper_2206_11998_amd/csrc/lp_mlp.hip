@@ -151,19 +151,20 @@ void launch_mlp_forward(const float *th, int64_t n, const float *feat, float *z,
 // the blended update and the mover -- the same arithmetic as the update kernel.
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ __launch_bounds__(64) void k_mlp_apply(const float *th, Sorted srt, Soa p, DevCfg cfg, DevScalars *sc,
+__global__ __launch_bounds__(256) void k_mlp_apply(const float *th, Sorted srt, Soa p, DevCfg cfg, DevScalars *sc,
                                                   int n_real, MlpStage ms) {
     constexpr int NF = D + 2, FP = D + 1;
     MlpRegs R;
     load_regs(th, R);
     const int l = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
     const int n_total = sc->n_total;
     const double dt = sc->dt;
-    // groups of 64 particles: four 16-particle tiles through the network,
-    // then every lane finishes its own particle of the group
+    // groups of 64 particles, one wave each: four 16-particle tiles through
+    // the network, then every lane finishes its own particle of the group
     const int64_t ngroup = ((int64_t)n_total + 63) / 64;
     unsigned long long used = 0, plain = 0, lim = 0;
-    for (int64_t grp = blockIdx.x; grp < ngroup; grp += gridDim.x) {
+    for (int64_t grp = (int64_t)blockIdx.x * 4 + wv; grp < ngroup; grp += (int64_t)gridDim.x * 4) {
         const int s = (int)(grp * 64 + l);
         bool ok = s < n_total;
         const int i = ok ? srt.id[s] : n_real;
@@ -252,27 +253,37 @@ __global__ __launch_bounds__(64) void k_mlp_apply(const float *th, Sorted srt, S
         if (p.flags) p.flags[i] = flags;
         if (p.phi) p.phi[i] = (float)phi;
     }
-    // one atomic per wave and counter (every lane of the wave is active here)
+    // one atomic per block and counter: the counters are single addresses,
+    // whose atomics serialise in the cache (every lane is active here)
     for (int o = 32; o > 0; o >>= 1) {
         used += __shfl_xor(used, o);
         plain += __shfl_xor(plain, o);
         lim += __shfl_xor(lim, o);
     }
+    __shared__ unsigned long long part[4][3];
     if (l == 0) {
-        if (used) atomicAdd(&sc->n_mlp, used);
-        if (plain) atomicAdd(&sc->n_mlp_plain, plain);
-        if (lim) atomicAdd(&sc->n_limited, lim);
+        part[wv][0] = used;
+        part[wv][1] = plain;
+        part[wv][2] = lim;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const unsigned long long v = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] +
+                                     part[3][threadIdx.x];
+        unsigned long long *dst = threadIdx.x == 0 ? &sc->n_mlp : threadIdx.x == 1 ? &sc->n_mlp_plain : &sc->n_limited;
+        if (v) atomicAdd(dst, v);
     }
 }
 
 void launch_mlp_apply(const float *th, const Sorted &s, const Soa &p, const DevCfg &cfg, DevScalars *sc,
                       int64_t n_total_cap, int n_real, const MlpStage &ms, hipStream_t st) {
-    int64_t ng = (n_total_cap + 63) / 64;
-    unsigned g = (unsigned)(ng < 8192 ? (ng > 0 ? ng : 1) : 8192);  // each wave loads the weights once
+    // four waves per block, at most 8192 waves: each wave loads the weights once
+    int64_t nb = ((n_total_cap + 63) / 64 + 3) / 4;
+    unsigned g = (unsigned)(nb < 2048 ? (nb > 0 ? nb : 1) : 2048);
     if (cfg.D == 3)
-        hipLaunchKernelGGL(k_mlp_apply<3>, dim3(g), dim3(64), 0, st, th, s, p, cfg, sc, n_real, ms);
+        hipLaunchKernelGGL(k_mlp_apply<3>, dim3(g), dim3(256), 0, st, th, s, p, cfg, sc, n_real, ms);
     else
-        hipLaunchKernelGGL(k_mlp_apply<2>, dim3(g), dim3(64), 0, st, th, s, p, cfg, sc, n_real, ms);
+        hipLaunchKernelGGL(k_mlp_apply<2>, dim3(g), dim3(256), 0, st, th, s, p, cfg, sc, n_real, ms);
     (void)hipGetLastError();
 }
 

@@ -264,7 +264,7 @@ template <int D, int G, bool PER>
 __device__ __forceinline__ void bal_rank_write(const BalLds &l, int k, bool active, int s, double r2,
                                                const double xi[3], const Sorted &srt, const DevCfg &cfg, int *nbr,
                                                int ldn, int *count, DevScalars *sc, int lcap, int *ovf_queue,
-                                               int *ovf_count, int *max_out, bool cand_mode = false) {
+                                               int *ovf_count, int *max_out) {
     constexpr int PPB = LP_BLOCK / G;
     const int lane = threadIdx.x % G;
     const int grp = threadIdx.x / G;
@@ -344,19 +344,11 @@ __device__ __forceinline__ void bal_rank_write(const BalLds &l, int k, bool acti
     }
     if (active) {
         if (lane == 0) {
-            if (cand_mode && k > max_nb) {
-                // more candidates than a list holds: none are kept (count -1);
-                // this step's filter searches the particle's cells exactly,
-                // and the next step rebuilds again
-                count[s] = -1;
-                atomicOr(&sc->cand_short, 1u);
-            } else {
-                count[s] = k;
-                if (k > max_nb) atomicOr(&sc->error_bits, 1u);
-                // the list does not fit the LDS buffer: one wave redoes it (and
-                // for k > max_nb writes max_nb valid entries, so readers stay in bounds)
-                if (k > lcap) ovf_queue[atomicAdd(ovf_count, 1)] = s;
-            }
+            count[s] = k;
+            if (k > max_nb) atomicOr(&sc->error_bits, 1u);
+            // the list does not fit the LDS buffer: one wave redoes it (and
+            // for k > max_nb writes max_nb valid entries, so readers stay in bounds)
+            if (k > lcap) ovf_queue[atomicAdd(ovf_count, 1)] = s;
         }
     }
     int rank[EMAX], jq[EMAX];
@@ -420,6 +412,134 @@ __device__ __forceinline__ void bal_rank_write(const BalLds &l, int k, bool acti
     }
 }
 
+// The cells of particle s's search box at the level of radius ri, and in
+// them every candidate j != s: the G lanes of a group deal the box's cells,
+// then the candidates of G cells at a time, two per lane and round (t and
+// t + G).  round(ua, d2a, ja, ub, d2b, jb) gets each lane's pair with the
+// exact d2 (u: a real candidate); the lanes of a group call it together.
+// The next round's positions are loaded (unconditionally, so that the loads
+// stay in flight) before round() runs.
+template <int D, int G, bool PER, typename F>
+__device__ __forceinline__ void for_cell_candidates(const Sorted &srt, const uint32_t *tables, const DevGrid &g,
+                                                    const DevCfg &cfg, int s, const double xi[3], double ri,
+                                                    double r2, F &&round) {
+    const int lane = threadIdx.x % G;
+    // a cell is skipped only when even its box widened by a rounding slack
+    // (and unbounded on the outer side of edge cells, which hold the
+    // particles clamped into the grid) is farther than r from x_i
+    const double r2_keep = r2 * (1.0 + 1e-12);
+    const int L = level_for_radius(g, ri);
+    const double cs = ldexp(g.s[g.L_lo], g.L_lo - L);  // = s[L] exactly
+    const double slack = 1e-12 * g.s[0];
+    const uint32_t *tab = tables + g.off[L];
+    int clo[3] = {0, 0, 0}, cn[3] = {1, 1, 1};
+    search_box<D>(g, cfg, L, xi, ri, clo, cn);
+    const int ncells = cn[0] * cn[1] * (D == 3 ? cn[2] : 1);
+    const float rcp0 = 1.0f / (float)cn[0], rcp1 = 1.0f / (float)cn[1];
+    // cells per axis at level L (indexed by a per-particle level, so read
+    // once here rather than in every batch)
+    int nL[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) nL[a] = g.nc[L][a];
+    // Morton code of cell c of the box; false for a cell past the end or
+    // provably outside the ball
+    auto cell_code = [&](int c, uint32_t &code) -> bool {
+        code = 0u;
+        if (c >= ncells) return false;
+        int cc[3], rem;
+        const int q0 = div_small(c, cn[0], rcp0, rem);
+        cc[0] = clo[0] + rem;
+        if (D == 3) {
+            const int q1 = div_small(q0, cn[1], rcp1, rem);
+            cc[1] = clo[1] + rem;
+            cc[2] = clo[2] + q1;
+        } else {
+            cc[1] = clo[1] + q0;
+            cc[2] = 0;
+        }
+        double dd = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            if (PER && cfg.periodic[a]) continue;
+            const int n_a = nL[a];
+            const double lo_a = cc[a] <= 0 ? -INFINITY : g.lo[a] + cc[a] * cs - slack;
+            const double hi_a = cc[a] >= n_a - 1 ? INFINITY : g.lo[a] + (cc[a] + 1) * cs + slack;
+            // distance of x_i to [lo_a, hi_a] along a (at most one term is positive)
+            const double t = fmax(lo_a - xi[a], 0.0) + fmax(xi[a] - hi_a, 0.0);
+            dd += t * t;
+        }
+        if (dd > r2_keep) return false;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+            if (PER && cfg.periodic[a]) {
+                const int n_a = nL[a];
+                cc[a] = cc[a] < 0 ? cc[a] + n_a : (cc[a] >= n_a ? cc[a] - n_a : cc[a]);
+            }
+        code = morton<D>(cc);
+        return true;
+    };
+    // the cell-table entries of the next batch are loaded (unconditionally:
+    // a skipped cell reads entry 0) while this batch's candidates are tested
+    uint32_t nb_code;
+    bool nb_ok = cell_code(lane, nb_code);
+    uint32_t nb_lo = tab[nb_code], nb_hi = tab[nb_code + 1];
+    for (int c0 = 0; c0 < ncells; c0 += G) {
+        const int b = (int)nb_lo;
+        const int len = nb_ok ? (int)(nb_hi - nb_lo) : 0;
+        nb_ok = cell_code(c0 + G + lane, nb_code);
+        nb_lo = tab[nb_code];
+        nb_hi = tab[nb_code + 1];
+        // inclusive prefix sum of the candidate counts over the group
+        int incl = len;
+#pragma unroll
+        for (int o = 1; o < G; o <<= 1) {
+            const int v = __shfl_up(incl, o, G);
+            if (lane >= o) incl += v;
+        }
+        const int excl = incl - len;
+        const int total = __shfl(incl, G - 1, G);
+        // two candidates per lane and round (t and t + G).  The positions
+        // of the next round are loaded (unconditionally, so that the loads
+        // stay in flight) before this round's hits are compacted.
+        auto fetch = [&](int t0, int &ja, int &jb, bool &oka, bool &okb, double *pa, double *pb) {
+            const int ta = t0 + lane, tb = ta + G;
+            // the cell of candidate t: the last lane q with excl_q <= t
+            int qa = 0, qb = 0;
+#pragma unroll
+            for (int step = G / 2; step > 0; step >>= 1) {
+                const int va = __shfl(excl, qa + step, G);
+                const int vb = __shfl(excl, qb + step, G);
+                if (va <= ta) qa += step;
+                if (vb <= tb) qb += step;
+            }
+            ja = __shfl(b, qa, G) + (ta - __shfl(excl, qa, G));
+            jb = __shfl(b, qb, G) + (tb - __shfl(excl, qb, G));
+            oka = ta < total && ja != s;
+            okb = tb < total && jb != s;
+            // slots past the end read the particle itself (a valid index)
+            const int ia = oka ? ja : s, ib = okb ? jb : s;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                pa[a] = srt.x[a][ia];
+                pb[a] = srt.x[a][ib];
+            }
+        };
+        int ja, jb;
+        bool oka, okb;
+        double pa[3] = {0.0, 0.0, 0.0}, pb[3] = {0.0, 0.0, 0.0};
+        fetch(0, ja, jb, oka, okb, pa, pb);
+        for (int t0 = 0; t0 < total; t0 += 2 * G) {
+            const int ca = ja, cb = jb;
+            const bool ua = oka, ub = okb;
+            double dxa[3], dxb[3];
+            disp_of<D, PER>(cfg, pa, xi, dxa);
+            disp_of<D, PER>(cfg, pb, xi, dxb);
+            fetch(t0 + 2 * G, ja, jb, oka, okb, pa, pb);
+            round(ua, dist2_exact<D>(dxa), ca, ub, dist2_exact<D>(dxb), cb);
+        }
+    }
+}
+
 template <int D, int G, bool PER>
 __global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *n_total_dev, int n_real,
                                                          const uint32_t *tables, DevGrid g, DevCfg cfg, int *nbr,
@@ -462,118 +582,8 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *
         if (D == 3) xi[2] = srt.x[2][s];
         const double ri = srt.r[s] * rscale;
         r2 = ri * ri;
-        // a cell is skipped only when even its box widened by a rounding slack
-        // (and unbounded on the outer side of edge cells, which hold the
-        // particles clamped into the grid) is farther than r from x_i
-        const double r2_keep = r2 * (1.0 + 1e-12);
-        const int L = level_for_radius(g, ri);
-        const double cs = ldexp(g.s[g.L_lo], g.L_lo - L);  // = s[L] exactly
-        const double slack = 1e-12 * g.s[0];
-        const uint32_t *tab = tables + g.off[L];
-        int clo[3] = {0, 0, 0}, cn[3] = {1, 1, 1};
-        search_box<D>(g, cfg, L, xi, ri, clo, cn);
-        const int ncells = cn[0] * cn[1] * (D == 3 ? cn[2] : 1);
-        const float rcp0 = 1.0f / (float)cn[0], rcp1 = 1.0f / (float)cn[1];
-        // cells per axis at level L (indexed by a per-particle level, so read
-        // once here rather than in every batch)
-        int nL[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) nL[a] = g.nc[L][a];
-        // Morton code of cell c of the box; false for a cell past the end or
-        // provably outside the ball
-        auto cell_code = [&](int c, uint32_t &code) -> bool {
-            code = 0u;
-            if (c >= ncells) return false;
-            int cc[3], rem;
-            const int q0 = div_small(c, cn[0], rcp0, rem);
-            cc[0] = clo[0] + rem;
-            if (D == 3) {
-                const int q1 = div_small(q0, cn[1], rcp1, rem);
-                cc[1] = clo[1] + rem;
-                cc[2] = clo[2] + q1;
-            } else {
-                cc[1] = clo[1] + q0;
-                cc[2] = 0;
-            }
-            double dd = 0.0;
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                if (PER && cfg.periodic[a]) continue;
-                const int n_a = nL[a];
-                const double lo_a = cc[a] <= 0 ? -INFINITY : g.lo[a] + cc[a] * cs - slack;
-                const double hi_a = cc[a] >= n_a - 1 ? INFINITY : g.lo[a] + (cc[a] + 1) * cs + slack;
-                // distance of x_i to [lo_a, hi_a] along a (at most one term is positive)
-                const double t = fmax(lo_a - xi[a], 0.0) + fmax(xi[a] - hi_a, 0.0);
-                dd += t * t;
-            }
-            if (dd > r2_keep) return false;
-#pragma unroll
-            for (int a = 0; a < D; ++a)
-                if (PER && cfg.periodic[a]) {
-                    const int n_a = nL[a];
-                    cc[a] = cc[a] < 0 ? cc[a] + n_a : (cc[a] >= n_a ? cc[a] - n_a : cc[a]);
-                }
-            code = morton<D>(cc);
-            return true;
-        };
-        // the cell-table entries of the next batch are loaded (unconditionally:
-        // a skipped cell reads entry 0) while this batch's candidates are tested
-        uint32_t nb_code;
-        bool nb_ok = cell_code(lane, nb_code);
-        uint32_t nb_lo = tab[nb_code], nb_hi = tab[nb_code + 1];
-        for (int c0 = 0; c0 < ncells; c0 += G) {
-            const int b = (int)nb_lo;
-            const int len = nb_ok ? (int)(nb_hi - nb_lo) : 0;
-            nb_ok = cell_code(c0 + G + lane, nb_code);
-            nb_lo = tab[nb_code];
-            nb_hi = tab[nb_code + 1];
-            // inclusive prefix sum of the candidate counts over the group
-            int incl = len;
-#pragma unroll
-            for (int o = 1; o < G; o <<= 1) {
-                const int v = __shfl_up(incl, o, G);
-                if (lane >= o) incl += v;
-            }
-            const int excl = incl - len;
-            const int total = __shfl(incl, G - 1, G);
-            // two candidates per lane and round (t and t + G).  The positions
-            // of the next round are loaded (unconditionally, so that the loads
-            // stay in flight) before this round's hits are compacted.
-            auto fetch = [&](int t0, int &ja, int &jb, bool &oka, bool &okb, double *pa, double *pb) {
-                const int ta = t0 + lane, tb = ta + G;
-                // the cell of candidate t: the last lane q with excl_q <= t
-                int qa = 0, qb = 0;
-#pragma unroll
-                for (int step = G / 2; step > 0; step >>= 1) {
-                    const int va = __shfl(excl, qa + step, G);
-                    const int vb = __shfl(excl, qb + step, G);
-                    if (va <= ta) qa += step;
-                    if (vb <= tb) qb += step;
-                }
-                ja = __shfl(b, qa, G) + (ta - __shfl(excl, qa, G));
-                jb = __shfl(b, qb, G) + (tb - __shfl(excl, qb, G));
-                oka = ta < total && ja != s;
-                okb = tb < total && jb != s;
-                // slots past the end read the particle itself (a valid index)
-                const int ia = oka ? ja : s, ib = okb ? jb : s;
-#pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    pa[a] = srt.x[a][ia];
-                    pb[a] = srt.x[a][ib];
-                }
-            };
-            int ja, jb;
-            bool oka, okb;
-            double pa[3] = {0.0, 0.0, 0.0}, pb[3] = {0.0, 0.0, 0.0};
-            fetch(0, ja, jb, oka, okb, pa, pb);
-            for (int t0 = 0; t0 < total; t0 += 2 * G) {
-                const int ca = ja, cb = jb;
-                const bool ua = oka, ub = okb;
-                double dxa[3], dxb[3];
-                disp_of<D, PER>(cfg, pa, xi, dxa);
-                disp_of<D, PER>(cfg, pb, xi, dxb);
-                fetch(t0 + 2 * G, ja, jb, oka, okb, pa, pb);
-                const double d2a = dist2_exact<D>(dxa), d2b = dist2_exact<D>(dxb);
+        for_cell_candidates<D, G, PER>(
+            srt, tables, g, cfg, s, xi, ri, r2, [&](bool ua, double d2a, int ca, bool ub, double d2b, int cb) {
                 const bool hita = ua && d2a < r2, hitb = ub && d2b < r2;
                 const unsigned long long ma = (__ballot(hita) >> gshift) & gmask;
                 const unsigned long long mb = (__ballot(hitb) >> gshift) & gmask;
@@ -593,15 +603,74 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *
                     }
                 }
                 k += __popcll(mb);
-            }
-        }
+            });
     }
     BalLds l;
     l.gkey = gkey; l.gj = gj; l.gperm = gperm; l.gbk = gbk; l.lout = lout; l.lk = lk;
     bal_rank_write<D, G, PER>(l, k, active, s, r2, xi, srt, cfg, nbr, ldn, count, sc, lcap, ovf_queue,
-                              &sc->n_overflow, max_out, rscale != 1.0);
+                              &sc->n_overflow, max_out);
 }
 
+
+// Candidate lists of a rebuild: every particle within the enlarged radius
+// rscale r_s, in the order found.  The filter ranks what it keeps, so the
+// candidates need no ranking and are written straight to their slots
+// (interleaved layout, ccount[s] of them); a particle with more than max_nb
+// gets ccount -1 and raises cand_short, which has this step's filter search
+// its cells exactly and the next step rebuild again.  *max_out: the longest
+// candidate list.  Runs only where *gate is set.
+template <int D, int G, bool PER>
+__global__ __launch_bounds__(LP_BLOCK) void k_search_cand(Sorted srt, const int *n_total_dev, int n_real,
+                                                          const uint32_t *tables, DevGrid g, DevCfg cfg, int *cand,
+                                                          int *ccount, DevScalars *sc, double rscale,
+                                                          const unsigned *gate, int *max_out) {
+    if (gate && *gate == 0u) return;
+    constexpr int PPB = LP_BLOCK / G;
+    const int lane = threadIdx.x % G;
+    const int gshift = (int)(threadIdx.x & 63) - lane;
+    const unsigned long long gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int s = xcd_remap(blockIdx.x, gridDim.x) * PPB + (int)threadIdx.x / G;
+    const int n_total = *n_total_dev;
+    const bool active = s < n_total && srt.id[s] < n_real;
+    const int max_nb = cfg.max_nb;
+    int k = 0;
+    if (active) {
+        const double xi[3] = {srt.x[0][s], srt.x[1][s], D == 3 ? srt.x[2][s] : 0.0};
+        const double ri = srt.r[s] * rscale;
+        const double r2 = ri * ri;
+        for_cell_candidates<D, G, PER>(
+            srt, tables, g, cfg, s, xi, ri, r2, [&](bool ua, double d2a, int ca, bool ub, double d2b, int cb) {
+                const bool hita = ua && d2a < r2, hitb = ub && d2b < r2;
+                const unsigned long long ma = (__ballot(hita) >> gshift) & gmask;
+                const unsigned long long mb = (__ballot(hitb) >> gshift) & gmask;
+                if (hita) {
+                    const int slot = k + __popcll(ma & below);
+                    if (slot < max_nb) cand[list_at(0, s, slot, max_nb)] = ca;
+                }
+                k += __popcll(ma);
+                if (hitb) {
+                    const int slot = k + __popcll(mb & below);
+                    if (slot < max_nb) cand[list_at(0, s, slot, max_nb)] = cb;
+                }
+                k += __popcll(mb);
+            });
+    }
+    // longest list of the wave: an atomic only where it raises the maximum
+    // (same-address atomics serialise in L2)
+    int kmax = k;
+    for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o));
+    if ((threadIdx.x & 63) == 0 && kmax > __hip_atomic_load(max_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(max_out, kmax);
+    if (active && lane == 0) {
+        if (k > max_nb) {
+            ccount[s] = -1;
+            atomicOr(&sc->cand_short, 1u);
+        } else {
+            ccount[s] = k;
+        }
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Lists from reused candidates.  Candidate c of cell-order particle s is
@@ -807,6 +876,37 @@ static void launch_search_t(const Sorted &s, const int *n_total_dev, int n_total
     unsigned ob = (unsigned)(n_total_cap < 1024 ? (n_total_cap > 0 ? n_total_cap : 1) : 1024);
     hipLaunchKernelGGL(k_search_overflow<D>, dim3(ob), dim3(64), 0, st, s, tables, g, cfg, nbr, ldn, sc, ovf_queue,
                        rscale, gate);
+}
+
+template <int D, int G>
+static void launch_search_cand_t(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real,
+                                 const uint32_t *tables, const DevGrid &g, const DevCfg &cfg, int *cand, int *ccount,
+                                 DevScalars *sc, double rscale, const unsigned *gate, int *max_out, hipStream_t st) {
+    constexpr int PPB = LP_BLOCK / G;
+    unsigned blocks = (unsigned)((n_total_cap + PPB - 1) / PPB);
+    if (blocks < 1) blocks = 1;
+    const bool per = cfg.periodic[0] || cfg.periodic[1] || (D == 3 && cfg.periodic[2]);
+    if (per)
+        hipLaunchKernelGGL((k_search_cand<D, G, true>), dim3(blocks), dim3(LP_BLOCK), 0, st, s, n_total_dev, n_real,
+                           tables, g, cfg, cand, ccount, sc, rscale, gate, max_out);
+    else
+        hipLaunchKernelGGL((k_search_cand<D, G, false>), dim3(blocks), dim3(LP_BLOCK), 0, st, s, n_total_dev, n_real,
+                           tables, g, cfg, cand, ccount, sc, rscale, gate, max_out);
+}
+
+void launch_search_cand(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real, const uint32_t *tables,
+                        const DevGrid &g, const DevCfg &cfg, int *cand, int *ccount, DevScalars *sc, int group,
+                        double rscale, const unsigned *gate, int *max_out, hipStream_t st) {
+    int G = group;
+    if (G != 4 && G != 8 && G != 16 && G != 32) G = 16;
+#define LC(DD, GG) launch_search_cand_t<DD, GG>(s, n_total_dev, n_total_cap, n_real, tables, g, cfg, cand, ccount, sc, rscale, gate, max_out, st)
+    if (cfg.D == 3) {
+        if (G == 4) LC(3, 4); else if (G == 8) LC(3, 8); else if (G == 16) LC(3, 16); else LC(3, 32);
+    } else {
+        if (G == 4) LC(2, 4); else if (G == 8) LC(2, 8); else if (G == 16) LC(2, 16); else LC(2, 32);
+    }
+#undef LC
+    (void)hipGetLastError();
 }
 
 template <int D, int G>

@@ -74,6 +74,54 @@ __device__ __forceinline__ int octant(const double dx[3]) {
     return o;
 }
 
+// Position of cell-order particle j: from its gather record when there is one.
+template <int D>
+__device__ __forceinline__ void position_of(const Sorted &srt, int j, double p[3]) {
+    if (srt.rec) {
+        rec_pos<D>(srt.rec, j, p);
+    } else {
+        p[0] = srt.x[0][j];
+        p[1] = srt.x[1][j];
+        p[2] = D == 3 ? srt.x[2][j] : 0.0;
+    }
+}
+
+// A list longer than the cap keeps its members of octant rank below Rstar
+// and the first rem members (in list order) of rank Rstar: from the octant
+// counts of the whole list, Rstar is the largest number of rounds (one
+// member per non-empty octant each) that fit under the cap.  The count walk
+// keeps the next position and the index after it in flight (k >= 2 here).
+template <int D>
+__device__ __forceinline__ void lw_round_limit(const Sorted &srt, const DevCfg &cfg, const int *nbr, int ldn, int s,
+                                               int k, const double xi[3], int cap, int &Rstar, int &rem) {
+    unsigned long long c03 = 0, c47 = 0;  // octant counts, 16 bits each
+    double pn[3];
+    position_of<D>(srt, nb_at(nbr, ldn, s, 0), pn);
+    int jn = nb_at(nbr, ldn, s, 1);
+    for (int t = 0; t < k; ++t) {
+        const double pc[3] = {pn[0], pn[1], pn[2]};
+        position_of<D>(srt, jn, pn);
+        jn = nb_at(nbr, ldn, s, t + 2 < k ? t + 2 : k - 1);
+        double dx[3];
+        disp_of<D>(cfg, pc, xi, dx);
+        const int o = octant<D>(dx);
+        if (o < 4) c03 += 1ull << (16 * o); else c47 += 1ull << (16 * (o - 4));
+    }
+    int cnt[8];
+    for (int o = 0; o < 4; ++o) cnt[o] = (int)((c03 >> (16 * o)) & 0xffff);
+    for (int o = 0; o < 4; ++o) cnt[4 + o] = (int)((c47 >> (16 * o)) & 0xffff);
+    int R = 0, taken = 0;
+    for (;;) {
+        int next = 0;
+        for (int o = 0; o < 8; ++o) next += cnt[o] < R + 1 ? cnt[o] : R + 1;
+        if (next > cap) break;
+        taken = next;
+        ++R;
+    }
+    Rstar = R;
+    rem = cap - taken;
+}
+
 // Visit the Lax-Wendroff stencil: all neighbours when they fit under the cap,
 // otherwise the first `cap` in the order (rank within own octant, list
 // position), i.e. the top of the list holds members of every octant.
@@ -82,29 +130,7 @@ __device__ __forceinline__ void for_lw_stencil(const Sorted &srt, const DevCfg &
                                                int k, const double xi[3], F &&body) {
     const int cap = cfg.lw_cap;
     int Rstar = 1 << 30, rem = 0;
-    if (k > cap) {
-        unsigned long long c03 = 0, c47 = 0;  // octant counts, 16 bits each
-        for (int t = 0; t < k; ++t) {
-            int j = nb_at(nbr, ldn, s, t);
-            double dx[3];
-            displacement<D>(srt, cfg, j, xi, dx);
-            int o = octant<D>(dx);
-            if (o < 4) c03 += 1ull << (16 * o); else c47 += 1ull << (16 * (o - 4));
-        }
-        int cnt[8];
-        for (int o = 0; o < 4; ++o) cnt[o] = (int)((c03 >> (16 * o)) & 0xffff);
-        for (int o = 0; o < 4; ++o) cnt[4 + o] = (int)((c47 >> (16 * o)) & 0xffff);
-        int R = 0, taken = 0;
-        for (;;) {
-            int next = 0;
-            for (int o = 0; o < 8; ++o) next += cnt[o] < R + 1 ? cnt[o] : R + 1;
-            if (next > cap) break;
-            taken = next;
-            ++R;
-        }
-        Rstar = R;
-        rem = cap - taken;
-    }
+    if (k > cap) lw_round_limit<D>(srt, cfg, nbr, ldn, s, k, xi, cap, Rstar, rem);
     unsigned long long s03 = 0, s47 = 0;
     int takenR = 0;
     // the next member's index is loaded one iteration ahead, so the gathers
@@ -192,29 +218,7 @@ __device__ __forceinline__ void for_lw_stencil_rec(const Sorted &srt, const DevC
                                                    int s, int k, const double xi[3], F &&body) {
     const int cap = cfg.lw_cap;
     int Rstar = 1 << 30, rem = 0;
-    if (k > cap) {
-        unsigned long long c03 = 0, c47 = 0;  // octant counts, 16 bits each
-        for (int t = 0; t < k; ++t) {
-            int j = nb_at(nbr, ldn, s, t);
-            double dx[3];
-            displacement<D>(srt, cfg, j, xi, dx);
-            int o = octant<D>(dx);
-            if (o < 4) c03 += 1ull << (16 * o); else c47 += 1ull << (16 * (o - 4));
-        }
-        int cnt[8];
-        for (int o = 0; o < 4; ++o) cnt[o] = (int)((c03 >> (16 * o)) & 0xffff);
-        for (int o = 0; o < 4; ++o) cnt[4 + o] = (int)((c47 >> (16 * o)) & 0xffff);
-        int R = 0, taken = 0;
-        for (;;) {
-            int next = 0;
-            for (int o = 0; o < 8; ++o) next += cnt[o] < R + 1 ? cnt[o] : R + 1;
-            if (next > cap) break;
-            taken = next;
-            ++R;
-        }
-        Rstar = R;
-        rem = cap - taken;
-    }
+    if (k > cap) lw_round_limit<D>(srt, cfg, nbr, ldn, s, k, xi, cap, Rstar, rem);
     if (k <= 0) return;
     unsigned long long s03 = 0, s47 = 0;
     int takenR = 0;
