@@ -492,25 +492,37 @@ def main():
     except Exception as exc:  # the reference is optional on hosts without gcc
         log("cpu reference unavailable:", repr(exc))
 
+    def fused(precision):
+        """FP32 fits refined where ill-conditioned (or not at all) run with the
+        update in one kernel (k_fit_finish); FP64 and always-refined fits
+        keep the fit and update kernels apart."""
+        return precision == "fp32" or (precision in ("mixed", "mlp") and args.refine_cond > 0)
+
     def kernel_rooflines(prof, precision):
         out = {}
         for name, bound in (("search", "hbm"), ("fit", "alu"), ("update", "alu"), ("mlp", "mfma")):
             ms, cnt = prof[name]
-            if cnt == 0:
+            if cnt == 0 or (name == "update" and fused(precision)):
                 continue
             avg = ms / max(cnt, 1)
+            if name == "fit" and fused(precision):
+                # the fit stage holds the fused kernel (and the refinement of
+                # the queued fits, which updates those particles)
+                name, wk = "fit+update", work["fit"] + work["update"]
+            else:
+                wk = work[name]
             if bound == "hbm":
-                achieved = work[name] / (avg * 1e-3) / 1e9 if avg > 0 else None
+                achieved = wk / (avg * 1e-3) / 1e9 if avg > 0 else None
                 peak, unit, per = PEAK_HBM_GBS, "GB/s", "algorithmic_bytes_per_launch"
             elif bound == "mfma":
-                achieved = work[name] / (avg * 1e-3) / 1e12 if avg > 0 else None
+                achieved = wk / (avg * 1e-3) / 1e12 if avg > 0 else None
                 peak, unit, per = PEAK_BF16_TFLOPS, "TFLOP/s", "algorithmic_flops_per_launch"
             else:
-                achieved = work[name] / (avg * 1e-3) / 1e12 if avg > 0 else None
+                achieved = wk / (avg * 1e-3) / 1e12 if avg > 0 else None
                 peak, unit, per = PEAK_ALU_TFLOPS, "TFLOP/s", "algorithmic_flops_per_launch"
             out[name] = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                          "frac": achieved / peak if achieved else None,
-                         "traffic": committed_traffic(name, precision), per: work[name],
+                         "traffic": committed_traffic(name, precision), per: wk,
                          "avg_launch_ms": avg}
         return out
 
@@ -536,7 +548,9 @@ def main():
     dominant = max(kr, key=lambda k: kr[k]["avg_launch_ms"])
     top = dict(kr[dominant])
     top["kernel"] = {"search": "k_search (neighbour lists)", "fit": "k_lw_fit (second-order fits)",
-                     "update": "k_finish (half-ball fits, estimator, update, mover)"}[dominant]
+                     "update": "k_finish (half-ball fits, estimator, update, mover)",
+                     "fit+update": "k_fit_finish (second-order fit, half-ball fits, estimator, update, mover)",
+                     "mlp": "k_mlp_apply (network estimator, update, mover)"}[dominant]
     out = {
         "metric": METRIC,
         "value": value,

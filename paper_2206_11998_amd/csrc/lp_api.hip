@@ -36,7 +36,7 @@ struct lp_ctx {
         gfd_fields, hitd2, hitj, tflags, tlo, thi, prep_part, ovfq, der, lwst, wq, rq, rkeep,
         mfeat, mrates, mphi, mflag,                          // network-estimator staging
         theta, adam_m, adam_v, mgrad, mpart, mlosspart, mscal, // network parameters and training
-        cand, ccount, xb, Rb, fovfq;                         // neighbour-list reuse
+        cand, ccount, xb, Rb, fovfq, octc;                   // neighbour-list reuse
     int search_mode = 2;            // 0: lane group walking its cells, 1: LDS-staged tiles, 2: balanced lane group
     int solve_block = 256;
     DevScalars *sc = nullptr;       // device scalars
@@ -96,7 +96,7 @@ static Buf lp_ctx::*const kBufs[] = {
     &lp_ctx::tflags, &lp_ctx::tlo, &lp_ctx::thi, &lp_ctx::prep_part, &lp_ctx::ovfq, &lp_ctx::der, &lp_ctx::lwst,
     &lp_ctx::wq, &lp_ctx::rq, &lp_ctx::rkeep, &lp_ctx::mfeat, &lp_ctx::mrates, &lp_ctx::mphi, &lp_ctx::mflag,
     &lp_ctx::theta, &lp_ctx::adam_m, &lp_ctx::adam_v, &lp_ctx::mgrad, &lp_ctx::mpart, &lp_ctx::mlosspart,
-    &lp_ctx::mscal, &lp_ctx::cand, &lp_ctx::ccount, &lp_ctx::xb, &lp_ctx::Rb, &lp_ctx::fovfq};
+    &lp_ctx::mscal, &lp_ctx::cand, &lp_ctx::ccount, &lp_ctx::xb, &lp_ctx::Rb, &lp_ctx::fovfq, &lp_ctx::octc};
 constexpr int kNumBufs = (int)(sizeof kBufs / sizeof kBufs[0]);
 
 static lp_status fail(lp_ctx *c, lp_status s, const char *fmt, ...) {
@@ -518,9 +518,13 @@ static lp_status ensure_capacity(lp_ctx *c, int64_t n_real, int64_t n_total, boo
         ENSURE(c, c->xb, sizeof(double) * 3 * nr);
         ENSURE(c, c->Rb, sizeof(double) * nr);
         ENSURE(c, c->fovfq, sizeof(int) * nt);
+        ENSURE(c, c->octc, sizeof(unsigned long long) * nt);
     }
     if (state) {
-        ENSURE(c, c->der, sizeof(double) * (size_t)der_count(D) * nt);
+        // the derivative array between the fit and the update kernels: FP64
+        // fits and always-refined FP32 fits (the fused kernel keeps them in registers)
+        if (!mixed || (c->dc.refine && !(c->dc.refine_cond > 0.0f)))
+            ENSURE(c, c->der, sizeof(double) * (size_t)der_count(D) * nt);
         ENSURE(c, c->lwst, (size_t)nt);
         ENSURE(c, c->wq, sizeof(int) * nt);
         if (mixed && c->dc.refine && c->dc.refine_cond > 0.0f) {
@@ -759,7 +763,8 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
         launch_filter(srt, &c->sc->n_total, (int)n_total, n, c->dc, (const int *)c->cand.p, 0,
                       (const int *)c->ccount.p, (int *)c->nbr.p, ldn, (int *)c->count.p,
                       (const uint32_t *)c->tables.p, c->grid, c->sc, 8 /* lanes per particle: measured best */,
-                      c->search_cap ? c->search_cap : c->search_lcap, (int *)c->fovfq.p, st);
+                      c->search_cap ? c->search_cap : c->search_lcap, (int *)c->fovfq.p,
+                      (unsigned long long *)c->octc.p, st);
     } else {
         run_search(c, srt, n_total, n, c->search_cap ? c->search_cap : c->search_lcap, st);
     }
@@ -786,6 +791,7 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
     sv.cfg = c->dc;
     sv.sc = c->sc;
     sv.queue = (int *)c->queue.p;
+    sv.octc = reuse ? (const unsigned long long *)c->octc.p : nullptr;
     sv.der = (double *)c->der.p;
     sv.ld = c->cap_total;
     sv.lwst = (uint8_t *)c->lwst.p;

@@ -108,6 +108,15 @@ struct Sorted {
 // 2D: x0 x1 | V u0 u1 P.
 #define LP_RECF_BYTES 48
 
+// octant of an offset: bit a set where dx[a] >= 0
+template <int D>
+__device__ __forceinline__ int octant(const double dx[3]) {
+    int o = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) o |= (dx[a] >= 0.0 ? 1 : 0) << a;
+    return o;
+}
+
 template <int D>
 __device__ __forceinline__ void rec_pos(const double *rec, int j, double p[3]) {
     const double2 *r = reinterpret_cast<const double2 *>(rec + (int64_t)LP_REC * j);
@@ -191,11 +200,13 @@ void launch_search_cand(const Sorted &s, const int *n_total_dev, int n_total_cap
 // neighbour lists from reused candidate lists cand[c * ldc + s], c < ccount[s]:
 // the exact test d2 < r_s^2 on the current positions, (d2, id) order
 // (ccount[s] < 0: no candidates were kept; the cells -- laid out by this
-// step's rebuild -- are searched exactly instead)
+// step's rebuild -- are searched exactly instead).  octc[s]: for lists longer
+// than lw_cap, the members per octant of the offset (8 bits each; ~0 where
+// not counted)
 void launch_filter(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real, const DevCfg &cfg,
                    const int *cand, int ldc, const int *ccount, int *nbr, int ldn, int *count,
                    const uint32_t *tables, const DevGrid &g, DevScalars *sc, int group, int lcap, int *ovf_queue,
-                   hipStream_t st);
+                   unsigned long long *octc, hipStream_t st);
 // reuse decision: displacement since the last rebuild and radius growth
 // against the enlarged radius; force != 0 rebuilds; a rebuild step copies
 // the positions and r * rscale of every particle
@@ -241,6 +252,8 @@ struct SolveArgs {
     int *rq;                        // refinement queue: (cell-order particle, work slot) pairs
     float *rkeep;                   // per refinement-queue slot: factor, 1/diag and FP32 coefficients
     MlpStage ms;                    // feat != NULL: stage for the network estimator instead of updating
+    const unsigned long long *octc; // per particle with a list longer than lw_cap: its octant counts
+                                    // (8 bits each, written by the list filter; ~0: not counted), or NULL
 };
 // mode: 0 direct, 1 work queue, 2 persistent launch over the work queue
 void launch_solve(const SolveArgs &a, int n_total_cap, int block, int mode, void (*between)(void *),

@@ -687,7 +687,7 @@ template <int D, int G, bool PER>
 __global__ __launch_bounds__(LP_BLOCK) void k_filter_bal(Sorted srt, const int *n_total_dev, int n_real, DevCfg cfg,
                                                          const int *cand, int ldc, const int *ccount, int *nbr,
                                                          int ldn, int *count, DevScalars *sc, int lcap,
-                                                         int *ovf_queue) {
+                                                         int *ovf_queue, unsigned long long *octc) {
     constexpr int PPB = LP_BLOCK / G;
     extern __shared__ unsigned char smem[];
     const int lane = threadIdx.x % G;
@@ -710,12 +710,16 @@ __global__ __launch_bounds__(LP_BLOCK) void k_filter_bal(Sorted srt, const int *
         const double ri = srt.r[s];
         r2 = ri * ri;
         int kc = ccount[s];
-        if (kc < 0) {
+        const bool have_cand = kc >= 0;
+        if (!have_cand) {
             // no candidates kept (more than max_nb of them at this step's
             // rebuild): the overflow kernel searches the fresh cells exactly
             if (lane == 0) ovf_queue[atomicAdd(&sc->n_fovf, 1)] = s;
             kc = 0;
         }
+        // members per octant of the offset, 8 bits each (a lane takes at
+        // most max_nb / G <= 32 of them), for the fit's stencil selection
+        unsigned long long oc = 0ull;
         kc = kc < cfg.max_nb ? kc : cfg.max_nb;
         // indices of rounds t0 / t0 + 2G are in ja/jb and na/nb; slots past
         // the end read the particle itself (a valid index, never a hit)
@@ -753,6 +757,7 @@ __global__ __launch_bounds__(LP_BLOCK) void k_filter_bal(Sorted srt, const int *
                     l.gkey[slot] = (float)d2a;
                     l.gj[slot] = ca;
                 }
+                oc += 1ull << (8 * octant<D>(dxa));
             }
             k += __popcll(ma);
             if (hitb) {
@@ -761,9 +766,15 @@ __global__ __launch_bounds__(LP_BLOCK) void k_filter_bal(Sorted srt, const int *
                     l.gkey[slot] = (float)d2b;
                     l.gj[slot] = cb;
                 }
+                oc += 1ull << (8 * octant<D>(dxb));
             }
             k += __popcll(mb);
         }
+        // group sum (every lane of the group is here); no field can carry
+        // while k <= 255.  Not counted: lists the overflow kernel searches.
+#pragma unroll
+        for (int o = 1; o < G; o <<= 1) oc += __shfl_xor(oc, o, G);
+        if (lane == 0) octc[s] = (have_cand && k <= 255) ? oc : ~0ull;
     }
     bal_rank_write<D, G, PER>(l, k, active, s, r2, xi, srt, cfg, nbr, ldn, count, sc, lcap, ovf_queue,
                               &sc->n_fovf, &sc->max_count);
@@ -913,7 +924,7 @@ template <int D, int G>
 static void launch_filter_t(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real, const DevCfg &cfg,
                             const int *cand, int ldc, const int *ccount, int *nbr, int ldn, int *count,
                             const uint32_t *tables, const DevGrid &g, DevScalars *sc, int lcap, int *ovf_queue,
-                            hipStream_t st) {
+                            unsigned long long *octc, hipStream_t st) {
     constexpr int PPB = LP_BLOCK / G;
     unsigned blocks = (unsigned)((n_total_cap + PPB - 1) / PPB);
     if (blocks < 1) blocks = 1;
@@ -923,10 +934,10 @@ static void launch_filter_t(const Sorted &s, const int *n_total_dev, int n_total
     // rebuild search of the same step uses n_overflow
     if (per)
         hipLaunchKernelGGL((k_filter_bal<D, G, true>), dim3(blocks), dim3(LP_BLOCK), shm, st, s, n_total_dev, n_real,
-                           cfg, cand, ldc, ccount, nbr, ldn, count, sc, lcap, ovf_queue);
+                           cfg, cand, ldc, ccount, nbr, ldn, count, sc, lcap, ovf_queue, octc);
     else
         hipLaunchKernelGGL((k_filter_bal<D, G, false>), dim3(blocks), dim3(LP_BLOCK), shm, st, s, n_total_dev, n_real,
-                           cfg, cand, ldc, ccount, nbr, ldn, count, sc, lcap, ovf_queue);
+                           cfg, cand, ldc, ccount, nbr, ldn, count, sc, lcap, ovf_queue, octc);
     unsigned ob = (unsigned)(n_total_cap < 1024 ? (n_total_cap > 0 ? n_total_cap : 1) : 1024);
     hipLaunchKernelGGL(k_filter_overflow<D>, dim3(ob), dim3(64), 0, st, s, cfg, cand, ldc, ccount, nbr, ldn, count,
                        tables, g, sc, ovf_queue);
@@ -935,13 +946,13 @@ static void launch_filter_t(const Sorted &s, const int *n_total_dev, int n_total
 void launch_filter(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real, const DevCfg &cfg,
                    const int *cand, int ldc, const int *ccount, int *nbr, int ldn, int *count,
                    const uint32_t *tables, const DevGrid &g, DevScalars *sc, int group, int lcap_req,
-                   int *ovf_queue, hipStream_t st) {
+                   int *ovf_queue, unsigned long long *octc, hipStream_t st) {
     int G = group;
     if (G != 4 && G != 8 && G != 16 && G != 32) G = 16;
     int lcap = cfg.max_nb < 128 ? cfg.max_nb : 128;
     if (lcap_req > 0 && lcap_req < lcap) lcap = lcap_req;
     while (search_bal_smem(G, lcap) > 65536 && G < 64) G *= 2;
-#define LF(DD, GG) launch_filter_t<DD, GG>(s, n_total_dev, n_total_cap, n_real, cfg, cand, ldc, ccount, nbr, ldn, count, tables, g, sc, lcap, ovf_queue, st)
+#define LF(DD, GG) launch_filter_t<DD, GG>(s, n_total_dev, n_total_cap, n_real, cfg, cand, ldc, ccount, nbr, ldn, count, tables, g, sc, lcap, ovf_queue, octc, st)
     if (cfg.D == 3) {
         if (G == 4) LF(3, 4); else if (G == 8) LF(3, 8); else if (G == 16) LF(3, 16); else if (G == 32) LF(3, 32); else LF(3, 64);
     } else {

@@ -66,14 +66,6 @@ __device__ __forceinline__ void displacement(const Sorted &srt, const DevCfg &cf
     }
 }
 
-template <int D>
-__device__ __forceinline__ int octant(const double dx[3]) {
-    int o = 0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) o |= (dx[a] >= 0.0 ? 1 : 0) << a;
-    return o;
-}
-
 // Position of cell-order particle j: from its gather record when there is one.
 template <int D>
 __device__ __forceinline__ void position_of(const Sorted &srt, int j, double p[3]) {
@@ -89,27 +81,35 @@ __device__ __forceinline__ void position_of(const Sorted &srt, int j, double p[3
 // A list longer than the cap keeps its members of octant rank below Rstar
 // and the first rem members (in list order) of rank Rstar: from the octant
 // counts of the whole list, Rstar is the largest number of rounds (one
-// member per non-empty octant each) that fit under the cap.  The count walk
-// keeps the next position and the index after it in flight (k >= 2 here).
+// member per non-empty octant each) that fit under the cap.  The counts come
+// from octc (8 bits per octant, as the list filter recorded them) unless it
+// is NULL or ~0; otherwise a walk counts them, keeping the next position and
+// the index after it in flight (k >= 2 here).
 template <int D>
 __device__ __forceinline__ void lw_round_limit(const Sorted &srt, const DevCfg &cfg, const int *nbr, int ldn, int s,
-                                               int k, const double xi[3], int cap, int &Rstar, int &rem) {
-    unsigned long long c03 = 0, c47 = 0;  // octant counts, 16 bits each
-    double pn[3];
-    position_of<D>(srt, nb_at(nbr, ldn, s, 0), pn);
-    int jn = nb_at(nbr, ldn, s, 1);
-    for (int t = 0; t < k; ++t) {
-        const double pc[3] = {pn[0], pn[1], pn[2]};
-        position_of<D>(srt, jn, pn);
-        jn = nb_at(nbr, ldn, s, t + 2 < k ? t + 2 : k - 1);
-        double dx[3];
-        disp_of<D>(cfg, pc, xi, dx);
-        const int o = octant<D>(dx);
-        if (o < 4) c03 += 1ull << (16 * o); else c47 += 1ull << (16 * (o - 4));
-    }
+                                               int k, const double xi[3], int cap, const unsigned long long *octc,
+                                               int &Rstar, int &rem) {
     int cnt[8];
-    for (int o = 0; o < 4; ++o) cnt[o] = (int)((c03 >> (16 * o)) & 0xffff);
-    for (int o = 0; o < 4; ++o) cnt[4 + o] = (int)((c47 >> (16 * o)) & 0xffff);
+    const unsigned long long known = octc ? octc[s] : ~0ull;
+    if (known != ~0ull) {
+        for (int o = 0; o < 8; ++o) cnt[o] = (int)((known >> (8 * o)) & 0xff);
+    } else {
+        unsigned long long c03 = 0, c47 = 0;  // octant counts, 16 bits each
+        double pn[3];
+        position_of<D>(srt, nb_at(nbr, ldn, s, 0), pn);
+        int jn = nb_at(nbr, ldn, s, 1);
+        for (int t = 0; t < k; ++t) {
+            const double pc[3] = {pn[0], pn[1], pn[2]};
+            position_of<D>(srt, jn, pn);
+            jn = nb_at(nbr, ldn, s, t + 2 < k ? t + 2 : k - 1);
+            double dx[3];
+            disp_of<D>(cfg, pc, xi, dx);
+            const int o = octant<D>(dx);
+            if (o < 4) c03 += 1ull << (16 * o); else c47 += 1ull << (16 * (o - 4));
+        }
+        for (int o = 0; o < 4; ++o) cnt[o] = (int)((c03 >> (16 * o)) & 0xffff);
+        for (int o = 0; o < 4; ++o) cnt[4 + o] = (int)((c47 >> (16 * o)) & 0xffff);
+    }
     int R = 0, taken = 0;
     for (;;) {
         int next = 0;
@@ -127,10 +127,11 @@ __device__ __forceinline__ void lw_round_limit(const Sorted &srt, const DevCfg &
 // position), i.e. the top of the list holds members of every octant.
 template <int D, typename F>
 __device__ __forceinline__ void for_lw_stencil(const Sorted &srt, const DevCfg &cfg, const int *nbr, int ldn, int s,
-                                               int k, const double xi[3], F &&body) {
+                                               int k, const double xi[3], F &&body,
+                                               const unsigned long long *octc = nullptr) {
     const int cap = cfg.lw_cap;
     int Rstar = 1 << 30, rem = 0;
-    if (k > cap) lw_round_limit<D>(srt, cfg, nbr, ldn, s, k, xi, cap, Rstar, rem);
+    if (k > cap) lw_round_limit<D>(srt, cfg, nbr, ldn, s, k, xi, cap, octc, Rstar, rem);
     unsigned long long s03 = 0, s47 = 0;
     int takenR = 0;
     // the next member's index is loaded one iteration ahead, so the gathers
@@ -215,10 +216,11 @@ __device__ __forceinline__ void unpack_rec(const RecRaw<F32REC> &r, double p[3],
 // f) gets the member's V, u_0..u_{D-1}, P.  Needs srt.rec.
 template <int D, bool F32REC = false, typename F>
 __device__ __forceinline__ void for_lw_stencil_rec(const Sorted &srt, const DevCfg &cfg, const int *nbr, int ldn,
-                                                   int s, int k, const double xi[3], F &&body) {
+                                                   int s, int k, const double xi[3], F &&body,
+                                                   const unsigned long long *octc = nullptr) {
     const int cap = cfg.lw_cap;
     int Rstar = 1 << 30, rem = 0;
-    if (k > cap) lw_round_limit<D>(srt, cfg, nbr, ldn, s, k, xi, cap, Rstar, rem);
+    if (k > cap) lw_round_limit<D>(srt, cfg, nbr, ldn, s, k, xi, cap, octc, Rstar, rem);
     if (k <= 0) return;
     unsigned long long s03 = 0, s47 = 0;
     int takenR = 0;
@@ -630,6 +632,24 @@ template <int D> struct DerMem {
     }
 };
 
+// The FP32 fit's scaled coefficients B[f * NU + column] and 1/r, held in
+// registers by the fused kernel: derivatives formed as the derivative array
+// would hold them.
+template <int D> struct DerCoef {
+    const float *B;
+    double inv_r;
+    __device__ __forceinline__ double g(int f, int a) const { return (double)B[f * Dim<D>::NU + a] * inv_r; }
+    __device__ __forceinline__ void all(double gr[Dim<D>::NF][3], double he[Dim<D>::NF][Dim<D>::NS]) const {
+#pragma unroll
+        for (int f = 0; f < Dim<D>::NF; ++f) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) gr[f][a] = a < D ? (double)B[f * Dim<D>::NU + a] * inv_r : 0.0;
+#pragma unroll
+            for (int c = 0; c < Dim<D>::NS; ++c) he[f][c] = (double)B[f * Dim<D>::NU + D + c] * inv_r * inv_r;
+        }
+    }
+};
+
 template <int D, typename T, class DS>
 __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p, const DevCfg &cfg, DevScalars *sc,
                                                 const int *nbr, int ldn, int s, int i, int k, double dt,
@@ -912,9 +932,10 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
 // the FP64 system at the FP32 solution y (promoted exactly) is formed in
 // FP64; its normal-equation image A^T r and the correction solve use the FP32
 // factor (R, 1/diag R), as the correction only needs working precision.  The
-// refined coefficients are stored as the particle's derivatives.
-template <int D>
-__device__ __forceinline__ void lw_refine_tail(const SolveArgs &a, int s, int t, int k, const double xi[3],
+// refined coefficients are stored as the particle's derivatives, or (FINISH)
+// go straight on to the particle's update; the result: limited.
+template <int D, bool FINISH>
+__device__ __forceinline__ bool lw_refine_tail(const SolveArgs &a, int s, int t, int k, const double xi[3],
                                                const double st[Dim<D>::NF], double inv_r, const float G[Dim<D>::NG],
                                                const float inv[Dim<D>::NU], const float B[Dim<D>::NF * Dim<D>::NU]) {
     constexpr int NU = Dim<D>::NU, NF = Dim<D>::NF, NS = Dim<D>::NS, FP = D + 1;
@@ -943,14 +964,18 @@ __device__ __forceinline__ void lw_refine_tail(const SolveArgs &a, int s, int t,
         }
     };
     if (srt.rec) {
-        for_lw_stencil_rec<D>(srt, a.cfg, a.nbr, a.ldn, s, k, xi,
-                              [&](int, const double dx[3], const double fj[NF]) { member(dx, fj); });
+        for_lw_stencil_rec<D>(
+            srt, a.cfg, a.nbr, a.ldn, s, k, xi, [&](int, const double dx[3], const double fj[NF]) { member(dx, fj); },
+            a.octc);
     } else {
-        for_lw_stencil<D>(srt, a.cfg, a.nbr, a.ldn, s, k, xi, [&](int j, const double dx[3]) {
-            double fj[NF];
-            gather_fields<D>(srt, j, fj);
-            member(dx, fj);
-        });
+        for_lw_stencil<D>(
+            srt, a.cfg, a.nbr, a.ldn, s, k, xi,
+            [&](int j, const double dx[3]) {
+                double fj[NF];
+                gather_fields<D>(srt, j, fj);
+                member(dx, fj);
+            },
+            a.octc);
     }
     chol_solve<NU, NF, T, T>(G, inv, Ar);
     double grad[NF][3], hess[NF][NS];
@@ -963,19 +988,33 @@ __device__ __forceinline__ void lw_refine_tail(const SolveArgs &a, int s, int t,
         for (int q = 0; q < NS; ++q)
             hess[f][q] = ((double)B[f * NU + D + q] + (double)Ar[f * NU + D + q]) * inv_r * inv_r;
     }
-    store_der<D>(a.der, a.ld, t, grad, hess);
+    if constexpr (FINISH) {
+        const double h = srt.h[s];
+        const DerRegs<D> ds{grad, hess};
+        return finish_particle<D, float>(srt, a.p, a.cfg, a.sc, a.nbr, a.ldn, s, srt.id[s], k, a.sc->dt, xi, st, h,
+                                         a.cfg.kappa * h, ds, 0, 0, a.ms.feat ? &a.ms : nullptr);
+    } else {
+        store_der<D>(a.der, a.ld, t, grad, hess);
+        return false;
+    }
 }
 
 // s: cell-order particle; t: its work slot, which indexes der (the queue
 // order, so that a wave's derivative stores and loads stay coalesced).
-template <int D, typename T, bool REFINE>
-__device__ __forceinline__ void lw_fit_one(const SolveArgs &a, int s, int t) {
+// REGS: the fused kernel's form -- the FP32 coefficients and 1/r are
+// returned in bout / inv_r_out instead of being stored as derivatives, and the
+// result says whether the caller goes on to the update (false: not a real
+// particle, queued for the FP64 fallback, or queued for refinement, whose
+// kernel finishes the particle)
+template <int D, typename T, bool REFINE, bool REGS = false>
+__device__ __forceinline__ bool lw_fit_one(const SolveArgs &a, int s, int t, float *bout = nullptr,
+                                           double *inv_r_out = nullptr) {
     constexpr int NU = Dim<D>::NU, NF = Dim<D>::NF, NG = Dim<D>::NG, NS = Dim<D>::NS, FP = D + 1;
     const bool use_f = sizeof(T) == 4;
     const Sorted &srt = a.srt;
     const DevCfg &cfg = a.cfg;
     int i = srt.id[s];
-    if (i >= a.n_real) return;
+    if (i >= a.n_real) return false;
     int k = a.count[s];
     if (k > cfg.max_nb) k = cfg.max_nb;
     double xi[3] = {srt.x[0][s], srt.x[1][s], D == 3 ? srt.x[2][s] : 0.0};
@@ -1021,18 +1060,23 @@ __device__ __forceinline__ void lw_fit_one(const SolveArgs &a, int s, int t) {
     // the FP64 record
     constexpr bool F32REC = std::is_same<T, float>::value;
     if (F32REC && srt.recf) {
-        for_lw_stencil_rec<D, F32REC>(srt, cfg, a.nbr, a.ldn, s, k, xi,
-                                      [&](int, const double dx[3], const double fr[NF]) { member(dx, fr); });
+        for_lw_stencil_rec<D, F32REC>(
+            srt, cfg, a.nbr, a.ldn, s, k, xi, [&](int, const double dx[3], const double fr[NF]) { member(dx, fr); },
+            a.octc);
     } else if (srt.rec) {
         // one record in flight while a member is accumulated
-        for_lw_stencil_rec<D>(srt, cfg, a.nbr, a.ldn, s, k, xi,
-                              [&](int, const double dx[3], const double fr[NF]) { member(dx, fr); });
+        for_lw_stencil_rec<D>(
+            srt, cfg, a.nbr, a.ldn, s, k, xi, [&](int, const double dx[3], const double fr[NF]) { member(dx, fr); },
+            a.octc);
     } else {
-        for_lw_stencil<D>(srt, cfg, a.nbr, a.ldn, s, k, xi, [&](int j, const double dx[3]) {
-            double fr[NF];
-            gather_fields<D>(srt, j, fr);
-            member(dx, fr);
-        });
+        for_lw_stencil<D>(
+            srt, cfg, a.nbr, a.ldn, s, k, xi,
+            [&](int j, const double dx[3]) {
+                double fr[NF];
+                gather_fields<D>(srt, j, fr);
+                member(dx, fr);
+            },
+            a.octc);
     }
     T G[NG];
     gram_from_moments<D, T>(M, G);
@@ -1047,14 +1091,14 @@ __device__ __forceinline__ void lw_fit_one(const SolveArgs &a, int s, int t) {
         int slot = atomicAdd(&a.sc->n_fallback, 1);
         a.queue[slot] = s;
         a.lwst[s] = 1;
-        return;
+        return false;
     }
     a.lwst[s] = 0;
     // B <- (R^T R)^-1 B in place: the scaled coefficients of every field
     chol_solve<NU, NF, T, T>(G, inv, B);
     if constexpr (REFINE) {
-        lw_refine_tail<D>(a, s, t, k, xi, st, inv_r, G, inv, B);
-        return;
+        lw_refine_tail<D, false>(a, s, t, k, xi, st, inv_r, G, inv, B);
+        return false;
     }
     if (use_f && a.rq && cfg.refine && cfg.refine_cond > 0.0f && cond > (T)cfg.refine_cond) {
         // refined by k_lw_refine from the stored factor and FP32 solution
@@ -1068,17 +1112,25 @@ __device__ __forceinline__ void lw_fit_one(const SolveArgs &a, int s, int t) {
         for (int q = 0; q < NU; ++q) keep[NG + q] = (float)inv[q];
 #pragma unroll
         for (int q = 0; q < NF * NU; ++q) keep[NG + NU + q] = (float)B[q];
-        return;
+        return false;
     }
-    double grad[NF][3], hess[NF][NS];
+    if constexpr (REGS) {
+        static_assert(std::is_same<T, float>::value, "the fused kernel runs the FP32 fit");
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
+        for (int q = 0; q < NF * NU; ++q) bout[q] = B[q];
+        *inv_r_out = inv_r;
+    } else {
+        double grad[NF][3], hess[NF][NS];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) grad[f][q] = q < D ? (double)B[f * NU + q] * inv_r : 0.0;
+        for (int f = 0; f < NF; ++f) {
 #pragma unroll
-        for (int q = 0; q < NS; ++q) hess[f][q] = (double)B[f * NU + D + q] * inv_r * inv_r;
+            for (int q = 0; q < 3; ++q) grad[f][q] = q < D ? (double)B[f * NU + q] * inv_r : 0.0;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) hess[f][q] = (double)B[f * NU + D + q] * inv_r * inv_r;
+        }
+        store_der<D>(a.der, a.ld, t, grad, hess);
     }
-    store_der<D>(a.der, a.ld, t, grad, hess);
+    return true;
 }
 
 // Half-ball fits, estimator, blended update and mover of one particle whose
@@ -1126,6 +1178,20 @@ __device__ __forceinline__ void for_work(const SolveArgs &a, unsigned *head, F &
     }
 }
 
+// count of limited particles: wave sums (every lane of the wave is here),
+// then one atomic per block (same-address atomics serialise in L2)
+__device__ __forceinline__ void block_add_limited(DevScalars *sc, int limited) {
+    for (int o = 32; o > 0; o >>= 1) limited += __shfl_xor(limited, o);
+    __shared__ int wl[LP_BLOCK / 64];
+    if ((threadIdx.x & 63) == 0) wl[threadIdx.x >> 6] = limited;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) tot += wl[q];
+        if (tot) atomicAdd(&sc->n_limited, (unsigned long long)tot);
+    }
+}
+
 template <int D, typename T, bool REFINE, int MODE>
 __global__ __launch_bounds__(LP_BLOCK, 2) void k_lw_fit(SolveArgs a) {
     for_work<MODE>(a, a.sc->head[0], [&](int s, int t) { lw_fit_one<D, T, REFINE>(a, s, t); });
@@ -1137,27 +1203,51 @@ template <int D, typename T, int MODE>
 __global__ __launch_bounds__(LP_BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void k_finish(SolveArgs a) {
     int limited = 0;
     for_work<MODE>(a, a.sc->head[1], [&](int s, int t) { limited += finish_one<D, T>(a, s, t) ? 1 : 0; });
-    // wave sums (every lane of the wave is active here), then one atomic per block
-    for (int o = 32; o > 0; o >>= 1) limited += __shfl_xor(limited, o);
-    // (same-address atomics serialise in L2)
-    __shared__ int wl[LP_BLOCK / 64];
-    if ((threadIdx.x & 63) == 0) wl[threadIdx.x >> 6] = limited;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int tot = 0;
-        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) tot += wl[q];
-        if (tot) atomicAdd(&a.sc->n_limited, (unsigned long long)tot);
-    }
+    block_add_limited(a.sc, limited);
+}
+
+// The FP32 fit and the update of a particle in one kernel: the fit's
+// coefficients stay in registers (no derivative array); particles queued for
+// refinement are updated by the refinement kernel, those queued for the FP64
+// fallback by the fallback kernel.  At most three waves per SIMD keeps the
+// fit's and the update's registers within 168 without spilling.
+template <int D, int MODE>
+__global__ __launch_bounds__(LP_BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void k_fit_finish(SolveArgs a) {
+    constexpr int NF = Dim<D>::NF, NU = Dim<D>::NU, FP = D + 1;
+    int limited = 0;
+    for_work<MODE>(a, a.sc->head[0], [&](int s, int t) {
+        float B[NF * NU];
+        double inv_r;
+        if (!lw_fit_one<D, float, false, true>(a, s, t, B, &inv_r)) return;
+        const Sorted &srt = a.srt;
+        int k = a.count[s];
+        if (k > a.cfg.max_nb) k = a.cfg.max_nb;
+        const double xi[3] = {srt.x[0][s], srt.x[1][s], D == 3 ? srt.x[2][s] : 0.0};
+        double st[NF];
+        st[0] = srt.V[s];
+#pragma unroll
+        for (int q = 0; q < D; ++q) st[1 + q] = srt.u[q][s];
+        st[FP] = srt.P[s];
+        const double h = srt.h[s];
+        const DerCoef<D> ds{B, inv_r};
+        limited += finish_particle<D, float>(srt, a.p, a.cfg, a.sc, a.nbr, a.ldn, s, srt.id[s], k, a.sc->dt, xi,
+                                             st, h, a.cfg.kappa * h, ds, 0, 0, a.ms.feat ? &a.ms : nullptr)
+                       ? 1
+                       : 0;
+    });
+    block_add_limited(a.sc, limited);
 }
 
 // The fits queued for refinement (condition estimate above refine_cond):
 // the refinement step from the factor and FP32 solution the fit stored, so
-// that each result is the always-refining launch's.  Grid-stride over the
+// that each result is the always-refining launch's; after the fused kernel
+// (FINISH) each refined particle is updated here.  Grid-stride over the
 // device-side queue length.
-template <int D>
+template <int D, bool FINISH>
 __global__ __launch_bounds__(LP_BLOCK) void k_lw_refine(SolveArgs a) {
     constexpr int NU = Dim<D>::NU, NF = Dim<D>::NF, NG = Dim<D>::NG, FP = D + 1;
     const int n = a.sc->n_refine;
+    int limited = 0;
     for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < n; w += gridDim.x * blockDim.x) {
         const int s = a.rq[2 * w], t = a.rq[2 * w + 1];
         const Sorted &srt = a.srt;
@@ -1178,8 +1268,9 @@ __global__ __launch_bounds__(LP_BLOCK) void k_lw_refine(SolveArgs a) {
         for (int q = 0; q < NU; ++q) inv[q] = keep[NG + q];
 #pragma unroll
         for (int q = 0; q < NF * NU; ++q) B[q] = keep[NG + NU + q];
-        lw_refine_tail<D>(a, s, t, k, xi, st, inv_r, G, inv, B);
+        limited += lw_refine_tail<D, FINISH>(a, s, t, k, xi, st, inv_r, G, inv, B) ? 1 : 0;
     }
+    if (FINISH) block_add_limited(a.sc, limited);
 }
 
 // Grid of a persistent launch: the blocks that can be resident at once.
@@ -1217,17 +1308,26 @@ static void launch_solve_t(const SolveArgs &a, int n_total_cap, int block, void 
                            void *between_arg, hipStream_t st) {
     unsigned blocks = (unsigned)((n_total_cap + block - 1) / block);
     if (blocks < 1) blocks = 1;
+    const bool refine_queue = sizeof(T) == 4 && !RF && a.rq && a.cfg.refine && a.cfg.refine_cond > 0.0f;
+    // refinement: one wave per block, so that the few queued fits spread over the CUs
+    unsigned gr = (unsigned)((n_total_cap + 63) / 64);
+    gr = gr < 1 ? 1 : (gr > 4096 ? 4096 : gr);
+    if constexpr (std::is_same<T, float>::value && !RF) {
+        // FP32 fits refined where ill-conditioned (or not at all): fused
+        unsigned gff = blocks;
+        if (MODE == WQ_PERSISTENT) gff = persistent_grid((const void *)k_fit_finish<D, MODE>, block, n_total_cap);
+        hipLaunchKernelGGL((k_fit_finish<D, MODE>), dim3(gff), dim3(block), 0, st, a);
+        if (refine_queue) hipLaunchKernelGGL((k_lw_refine<D, true>), dim3(gr), dim3(64), 0, st, a);
+        if (between) between(between_arg);
+        return;
+    }
     unsigned gf = blocks, gu = blocks;
     if (MODE == WQ_PERSISTENT) {
         gf = persistent_grid((const void *)k_lw_fit<D, T, RF, MODE>, block, n_total_cap);
         gu = persistent_grid((const void *)k_finish<D, T, MODE>, block, n_total_cap);
     }
     hipLaunchKernelGGL((k_lw_fit<D, T, RF, MODE>), dim3(gf), dim3(block), 0, st, a);
-    if (sizeof(T) == 4 && !RF && a.rq && a.cfg.refine && a.cfg.refine_cond > 0.0f) {
-        unsigned gr = (unsigned)((n_total_cap + LP_BLOCK - 1) / LP_BLOCK);
-        gr = gr < 1 ? 1 : (gr > 1024 ? 1024 : gr);
-        hipLaunchKernelGGL((k_lw_refine<D>), dim3(gr), dim3(LP_BLOCK), 0, st, a);
-    }
+    if (refine_queue) hipLaunchKernelGGL((k_lw_refine<D, false>), dim3(gr), dim3(64), 0, st, a);
     if (between) between(between_arg);
     hipLaunchKernelGGL((k_finish<D, T, MODE>), dim3(gu), dim3(block), 0, st, a);
 }
