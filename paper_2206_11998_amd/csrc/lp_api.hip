@@ -1108,8 +1108,8 @@ static lp_status gfd_run(lp_ctx *c, void *stream, int64_t n, const double *x, co
     stage_mark(c, st, 2, false);
     stage_mark(c, st, 3, true);
     if (order == 3) {
-        launch_gfd3(srt, fs, nf, (const int *)c->nbr.p, ldn, (const int *)c->count.p, (int)n, c->dc, deriv, status,
-                    st);
+        launch_gfd3(srt, fs, nf, (const int *)c->nbr.p, ldn, (const int *)c->count.p, (int)n, c->dc, c->sc,
+                    (int *)c->queue.p, deriv, status, st);
     } else {
         launch_gfd(srt, fs, nf, (const int *)c->nbr.p, ldn, (const int *)c->count.p, (int)n, c->dc, c->sc,
                    (int *)c->queue.p, deriv, status, st);

@@ -282,7 +282,8 @@ void launch_gfd_fallback(const Sorted &s, const double *const *fs, int nf, const
                          const int *count, int n, const DevCfg &cfg, DevScalars *sc, const int *queue,
                          int queue_cap, double *deriv, uint8_t *status, hipStream_t st);
 void launch_gfd3(const Sorted &s, const double *const *fs, int nf, const int *nbr, int ldn, const int *count,
-                 int n, const DevCfg &cfg, double *deriv, uint8_t *status, hipStream_t st);
+                 int n, const DevCfg &cfg, DevScalars *sc, int *queue, double *deriv, uint8_t *status,
+                 hipStream_t st);
 void launch_out_keep(const Soa &p, const DevCfg &cfg, uint32_t lo_mask, uint32_t hi_mask, uint32_t *keep,
                      hipStream_t st);
 // bytes of the outflow staging area for n particles in D dimensions

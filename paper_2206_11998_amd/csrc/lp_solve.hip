@@ -1794,127 +1794,49 @@ __device__ __forceinline__ double dpp_f64(double v) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// DPP with a row mask: rows outside the mask receive 0
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_rows_f64(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, false);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
-// the value of lane `lane` (all lanes active), as a wave-uniform value
-__device__ __forceinline__ double lane_f64(double v, int lane) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)b, lane);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
-// Sum over the 64 lanes (all active) as a wave-uniform value, by DPP only:
-// within each 16-lane row (lanes ^ 1, ^ 2, then the 8- and 16-lane mirrors),
-// then row 1 += row 0 and row 3 += row 2 (broadcast of lane 15 of the row
-// before), then rows 2, 3 += lane 31; lane 63 holds (r3 + r2) + (r1 + r0).
-__device__ __forceinline__ double wave_sum_dpp(double v) {
+// Sum over the 16 lanes of a DPP row, in every lane of the row (lanes ^ 1,
+// ^ 2, then the 8- and 16-lane mirrors; each step adds two equal operands in
+// either order, so every lane ends with the same bits).  All lanes active.
+__device__ __forceinline__ double row_sum16(double v) {
     v += dpp_f64<0xB1>(v);
     v += dpp_f64<0x4E>(v);
     v += dpp_f64<0x141>(v);
     v += dpp_f64<0x140>(v);
-    v += dpp_rows_f64<0x142, 0xA>(v);
-    v += dpp_rows_f64<0x143, 0xC>(v);
-    return lane_f64(v, 63);
+    return v;
 }
 
-// Pivoted Householder QR of the wave's rows a[N] (one row per lane; rows of
-// lanes beyond the stencil are zero) and least squares for the first nr of NR
-// right-hand sides b.  The pivot is the remaining column of largest norm over
-// the remaining rows.  Back substitution runs column by column, so on return
-// lane p < N holds in y[c] the solution for unknown col = perm[p] (col = -1
-// in lanes >= N).  Returns |R11| / |Rnn|.
-template <int N, int NR>
-__device__ __forceinline__ double wave_qrp_lanes(double a[N], double b[NR], int nr, double y[NR], int &col) {
-    const int l = threadIdx.x & 63;
-    int perm[N];
+// row_sum16 of K values at once, stage by stage, so that no DPP read waits
+// on the add just before it
+template <int K>
+__device__ __forceinline__ void row_sum16_k(double v[K]) {
 #pragma unroll
-    for (int j = 0; j < N; ++j) perm[j] = j;
+    for (int q = 0; q < K; ++q) v[q] += dpp_f64<0xB1>(v[q]);
 #pragma unroll
-    for (int p = 0; p < N; ++p) {
-        int best = p;
-        double bn = -1.0;
+    for (int q = 0; q < K; ++q) v[q] += dpp_f64<0x4E>(v[q]);
 #pragma unroll
-        for (int j = p; j < N; ++j) {
-            const double c = wave_sum_dpp(l >= p ? a[j] * a[j] : 0.0);
-            if (c > bn) {
-                bn = c;
-                best = j;
-            }
-        }
+    for (int q = 0; q < K; ++q) v[q] += dpp_f64<0x141>(v[q]);
 #pragma unroll
-        for (int j = p + 1; j < N; ++j)
-            if (j == best) {  // wave-uniform
-                const double t = a[p];
-                a[p] = a[j];
-                a[j] = t;
-                const int u = perm[p];
-                perm[p] = perm[j];
-                perm[j] = u;
-            }
-        const double x0 = lane_f64(a[p], p);
-        const double sigma = wave_sum_dpp(l > p ? a[p] * a[p] : 0.0);
-        const double normx = sqrt(x0 * x0 + sigma);
-        if (normx == 0.0) continue;
-        const double alpha = x0 >= 0.0 ? -normx : normx;
-        const double v0 = x0 - alpha;
-        const double tau = -1.0 / (alpha * v0);
-        const double v = l == p ? v0 : (l > p ? a[p] : 0.0);
-#pragma unroll
-        for (int j = p + 1; j < N; ++j) {
-            const double w = wave_sum_dpp(v * a[j]) * tau;
-            a[j] -= w * v;
-        }
-#pragma unroll
-        for (int c = 0; c < NR; ++c)
-            if (c < nr) {
-                const double w = wave_sum_dpp(v * b[c]) * tau;
-                b[c] -= w * v;
-            }
-        a[p] = l == p ? alpha : (l > p ? 0.0 : a[p]);
-    }
-    const double r11 = fabs(lane_f64(a[0], 0));
-    const double rnn = fabs(lane_f64(a[N - 1], N - 1));
-#pragma unroll
-    for (int c = 0; c < NR; ++c) y[c] = 0.0;
-    // lane p holds row p of R (a[j], j >= p) and of Q^T b
-#pragma unroll
-    for (int p = N - 1; p >= 0; --p) {
-        const double d = a[p];
-#pragma unroll
-        for (int c = 0; c < NR; ++c)
-            if (c < nr) {
-                const double t = (l == p && d != 0.0) ? b[c] / d : 0.0;
-                const double yp = lane_f64(t, p);
-                if (l == p) y[c] = yp;
-                if (l < p) b[c] -= a[p] * yp;
-            }
-    }
-    col = -1;
-#pragma unroll
-    for (int p = 0; p < N; ++p)
-        if (l == p) col = perm[p];
-    return rnn == 0.0 ? INFINITY : r11 / rnn;
+    for (int q = 0; q < K; ++q) v[q] += dpp_f64<0x140>(v[q]);
 }
 
-// The Lax-Wendroff stencil of for_lw_stencil, chosen by the whole wave: list
-// entries are taken 64 at a time, one per lane; per-octant ballots give the
-// octant counts and each entry's rank within its octant, and the members
-// taken are compacted into sel[] in list order.  Returns their number.  The
-// same members in the same order as for_lw_stencil.
+// value of lane src (0..15) of the caller's 16-lane row
+__device__ __forceinline__ double row_bcast16(double v, int src) {
+    return __shfl(v, src, 16);
+}
+
+// The Lax-Wendroff stencil of for_lw_stencil, chosen by a 16-lane group (one
+// particle): list entries are taken 16 at a time, one per lane; per-octant
+// ballots of the group give the octant counts and each entry's rank within
+// its octant, and the members taken are compacted into sel[] in list order.
+// Returns their number (at most lw_cap <= 64).  The same members in the same
+// order as for_lw_stencil.
 template <int D>
-__device__ __forceinline__ int wave_lw_select(const Sorted &srt, const DevCfg &cfg, const int *nbr, int ldn, int s,
-                                              int k, const double xi[3], int *sel) {
-    const int l = threadIdx.x & 63;
-    const unsigned long long below = (1ull << l) - 1ull;
+__device__ __forceinline__ int group_lw_select(const Sorted &srt, const DevCfg &cfg, const int *nbr, int ldn, int s,
+                                               int k, const double xi[3], int *sel) {
+    const int gl = threadIdx.x & 15, gshift = threadIdx.x & 48;
+    const unsigned below = (1u << gl) - 1u;
     const int cap = cfg.lw_cap;
+    auto gballot = [&](bool pr) -> unsigned { return (unsigned)((__ballot(pr) >> gshift) & 0xFFFFull); };
     auto entry = [&](int t, int &j, int &o) {
         j = 0;
         o = -1;
@@ -1926,20 +1848,19 @@ __device__ __forceinline__ int wave_lw_select(const Sorted &srt, const DevCfg &c
         }
     };
     if (k <= cap) {
-        for (int t0 = 0; t0 < k; t0 += 64) {
-            if (t0 + l < k) sel[t0 + l] = nb_at(nbr, ldn, s, t0 + l);
-        }
+        for (int t0 = 0; t0 < k; t0 += 16)
+            if (t0 + gl < k) sel[t0 + gl] = nb_at(nbr, ldn, s, t0 + gl);
         return k;
     }
     // octant counts, then the round R* taken whole and rem of round R*
     int cnt[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) cnt[q] = 0;
-    for (int t0 = 0; t0 < k; t0 += 64) {
+    for (int t0 = 0; t0 < k; t0 += 16) {
         int j, o;
-        entry(t0 + l, j, o);
+        entry(t0 + gl, j, o);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) cnt[q] += __popcll(__ballot(o == q));
+        for (int q = 0; q < 8; ++q) cnt[q] += __popc(gballot(o == q));
     }
     int R = 0, taken = 0;
     for (;;) {
@@ -1955,37 +1876,245 @@ __device__ __forceinline__ int wave_lw_select(const Sorted &srt, const DevCfg &c
 #pragma unroll
     for (int q = 0; q < 8; ++q) seen[q] = 0;
     int seenR = 0, m = 0;  // entries of round R in earlier chunks; members taken
-    for (int t0 = 0; t0 < k; t0 += 64) {
+    for (int t0 = 0; t0 < k; t0 += 16) {
         int j, o;
-        entry(t0 + l, j, o);
+        entry(t0 + gl, j, o);
         int rho = 0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const unsigned long long mq = __ballot(o == q);
-            if (o == q) rho = seen[q] + __popcll(mq & below);
-            seen[q] += __popcll(mq);
+            const unsigned mq = gballot(o == q);
+            if (o == q) rho = seen[q] + __popc(mq & below);
+            seen[q] += __popc(mq);
         }
-        const unsigned long long onR = __ballot(o >= 0 && rho == R);
-        const bool take = o >= 0 && (rho < R || (rho == R && seenR + __popcll(onR & below) < rem));
-        seenR += __popcll(onR);
-        const unsigned long long mt = __ballot(take);
-        if (take) sel[m + __popcll(mt & below)] = j;
-        m += __popcll(mt);
+        const unsigned onR = gballot(o >= 0 && rho == R);
+        const bool take = o >= 0 && (rho < R || (rho == R && seenR + __popc(onR & below) < rem));
+        seenR += __popc(onR);
+        const unsigned mt = gballot(take);
+        if (take) sel[m + __popc(mt & below)] = j;
+        m += __popc(mt);
     }
     return m;
 }
 
-// One wave per particle (blocks of one wave: the second-order fallback
-// synchronises the block), particles in a grid-stride loop.  Four waves per
-// SIMD (128 registers, the rest spilled) beat three (a 2M-particle fit in 58
-// against 60 ms), and three beat the two that 193 registers allow by a fifth.
+// Pivoted Householder QR of a 16-lane group's rows.  Row q of the system
+// (q < 16 ROWS; rows past the stencil are zero) is a[q / 16][.] of lane q % 16.
+// The pivot is the remaining column of largest norm over the remaining rows.
+// Each dot product adds the lane's rows, then the 16 lanes (DPP row sums,
+// every lane of the wave takes part).  On return a holds R above the
+// diagonal and the reflectors below it (the reflector's head v0 on the
+// diagonal); the group's LDS arrays hold the column order perm, R's diagonal
+// alpha and the reflector scales tau (written by lane 0).  Returns
+// |R11| / |Rnn|.
+template <int N, int ROWS>
+__device__ __forceinline__ double group_qrp(double a[ROWS][N], int *perm, double *alpha_out, double *tau_out) {
+    const int gl = threadIdx.x & 15;
+    if (gl == 0)
+        for (int j = 0; j < N; ++j) perm[j] = j;
+    double r11 = 0.0, rnn = 0.0;
+#pragma clang loop unroll(full)
+    for (int p = 0; p < N; ++p) {
+        int best = p;
+        double bn = -1.0;
+        // norms of the remaining columns over rows >= p, three at a time
+#pragma clang loop unroll(full)
+        for (int j0 = p; j0 < N; j0 += 3) {
+            double part[3];
+#pragma clang loop unroll(full)
+            for (int e = 0; e < 3; ++e) {
+                const int j = j0 + e < N ? j0 + e : N - 1;
+                part[e] = 0.0;
+#pragma clang loop unroll(full)
+                for (int c = 0; c < ROWS; ++c)
+                    if (16 * c + 15 >= p)  // else every row of slot c is above p
+                        part[e] += (16 * c >= p || gl + 16 * c >= p) ? a[c][j] * a[c][j] : 0.0;
+            }
+            row_sum16_k<3>(part);
+#pragma clang loop unroll(full)
+            for (int e = 0; e < 3; ++e)
+                if (j0 + e < N && part[e] > bn) {
+                    bn = part[e];
+                    best = j0 + e;
+                }
+        }
+        // best is the same in the 16 lanes of a group (groups differ); the
+        // swap is written as selects, so that every column keeps a register
+#pragma clang loop unroll(full)
+        for (int j = p + 1; j < N; ++j) {
+            const bool sw = j == best;
+#pragma clang loop unroll(full)
+            for (int c = 0; c < ROWS; ++c) {
+                const double t = a[c][p], u = a[c][j];
+                a[c][p] = sw ? u : t;
+                a[c][j] = sw ? t : u;
+            }
+        }
+        const double x0 = row_bcast16(a[p / 16][p], p % 16);
+        double sg = 0.0;
+#pragma clang loop unroll(full)
+        for (int c = 0; c < ROWS; ++c) sg += gl + 16 * c > p ? a[c][p] * a[c][p] : 0.0;
+        const double sigma = row_sum16(sg);
+        const double normx = sqrt(x0 * x0 + sigma);
+        // a zero column (normx = 0) leaves the rows as they are: tau = 0
+        const double alpha = x0 >= 0.0 ? -normx : normx;
+        const double v0 = x0 - alpha;
+        const double tau = normx != 0.0 ? -1.0 / (alpha * v0) : 0.0;
+        double v[ROWS];
+#pragma clang loop unroll(full)
+        for (int c = 0; c < ROWS; ++c) {
+            const int q = gl + 16 * c;
+            v[c] = q == p ? v0 : (q > p ? a[c][p] : 0.0);
+            a[c][p] = q == p ? v0 : a[c][p];
+        }
+        // the reflector applied to the remaining columns, three at a time
+#pragma clang loop unroll(full)
+        for (int j0 = p + 1; j0 < N; j0 += 3) {
+            double d[3];
+#pragma clang loop unroll(full)
+            for (int e = 0; e < 3; ++e) {
+                const int j = j0 + e < N ? j0 + e : N - 1;
+                d[e] = 0.0;
+#pragma clang loop unroll(full)
+                for (int c = 0; c < ROWS; ++c) d[e] += v[c] * a[c][j];
+            }
+            row_sum16_k<3>(d);
+#pragma clang loop unroll(full)
+            for (int e = 0; e < 3; ++e)
+                if (j0 + e < N) {
+                    const double w = d[e] * tau;
+#pragma clang loop unroll(full)
+                    for (int c = 0; c < ROWS; ++c) a[c][j0 + e] -= w * v[c];
+                }
+        }
+        if (gl == 0) {
+            if (best != p) {
+                const int u = perm[p];
+                perm[p] = perm[best];
+                perm[best] = u;
+            }
+            alpha_out[p] = alpha;
+            tau_out[p] = tau;
+        }
+        if (p == 0) r11 = fabs(alpha);
+        if (p == N - 1) rnn = fabs(alpha);
+    }
+    return rnn == 0.0 ? INFINITY : r11 / rnn;
+}
+
+// Least squares for one right-hand side from group_qrp's factors: the
+// reflectors applied to b (row q in b[q / 16] of lane q % 16), then back
+// substitution; on return row p of b holds the solution for unknown perm[p].
+template <int N, int ROWS>
+__device__ __forceinline__ void group_qr_solve(const double a[ROWS][N], const double *alpha, const double *tau,
+                                               double b[ROWS]) {
+    const int gl = threadIdx.x & 15;
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+        double d = 0.0;
+#pragma unroll
+        for (int c = 0; c < ROWS; ++c) d += gl + 16 * c >= p ? a[c][p] * b[c] : 0.0;
+        const double w = row_sum16(d) * tau[p];
+#pragma unroll
+        for (int c = 0; c < ROWS; ++c) b[c] -= gl + 16 * c >= p ? w * a[c][p] : 0.0;
+    }
+    // row p of R: alpha[p] on the diagonal, a[p / 16][j > p] of lane p % 16
+#pragma unroll
+    for (int p = N - 1; p >= 0; --p) {
+        const double dg = alpha[p];
+        const double t = (gl == p % 16 && dg != 0.0) ? b[p / 16] / dg : 0.0;
+        const double yp = row_bcast16(t, p % 16);
+        if (gl == p % 16) b[p / 16] = yp;
+#pragma unroll
+        for (int c = 0; c < ROWS; ++c)
+            if (gl + 16 * c < p) b[c] -= a[c][p] * yp;
+    }
+}
+
+// Four particles per wave, one 16-lane group (a DPP row) each, up to four
+// stencil rows per lane.  A deficient cubic system (fewer members than
+// unknowns, or |R11| / |Rnn| above cond_max) is queued for k_gfd3_fallback.
+// The right-hand sides are gathered after the factorisation, one field at a
+// time, so that only the factors stay in registers (two waves per SIMD).
 template <int D>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_gfd3(Sorted srt, FieldPtrs fs, int nf, const int *nbr, int ldn,
-                                             const int *count, int n, DevCfg cfg, double *deriv, uint8_t *status) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_gfd3(Sorted srt, FieldPtrs fs, int nf, const int *nbr, int ldn,
+                                             const int *count, int n, DevCfg cfg, DevScalars *sc, int *queue,
+                                             double *deriv, uint8_t *status) {
+    constexpr int N3 = Dim3<D>::NU, ROWS = 4;
+    __shared__ int sel_all[4][64];
+    __shared__ int perm_all[4][32];
+    __shared__ double alpha_all[4][32], tau_all[4][32];
+    const int gl = threadIdx.x & 15, grp = (threadIdx.x >> 4) & 3;
+    int *sel = sel_all[grp];
+    int *perm = perm_all[grp];
+    const int s = xcd_remap(blockIdx.x, gridDim.x) * 4 + grp;
+    const bool real = s < n;
+    const int i = real ? srt.id[s] : 0;
+    int k = real ? count[s] : 0;
+    if (k > cfg.max_nb) k = cfg.max_nb;
+    const double xi[3] = {real ? srt.x[0][s] : 0.0, real ? srt.x[1][s] : 0.0,
+                          D == 3 && real ? srt.x[2][s] : 0.0};
+    const double r = real ? srt.r[s] : 1.0;
+    const int m = real ? group_lw_select<D>(srt, cfg, nbr, ldn, s, k, xi, sel) : 0;
+    __syncthreads();  // sel written by the group's lanes
+    double a[ROWS][N3];
+    int jr[ROWS];  // the member in each of the lane's rows (rows past the stencil: the particle itself)
+#pragma unroll
+    for (int c = 0; c < ROWS; ++c) {
+        const int q = gl + 16 * c;
+        const bool in = q < m;
+        jr[c] = in ? sel[q] : (real ? s : 0);
+        double dx[3];
+        displacement<D>(srt, cfg, jr[c], xi, dx);
+        double x[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < D; ++e) x[e] = in ? dx[e] / r : 0.0;
+        double row[N3];
+        third_order_row<D>(x, row);
+#pragma unroll
+        for (int u = 0; u < N3; ++u) a[c][u] = row[u];
+    }
+    const double cond = group_qrp<N3, ROWS>(a, perm, alpha_all[grp], tau_all[grp]);
+    __syncthreads();  // perm, alpha and tau written by lane 0 of each group
+    const bool cubic = real && m >= N3 && cond <= cfg.cond_max;
+    for (int f = 0; f < nf; ++f) {
+        // rows past the stencil read the particle's own value: difference 0
+        const double fi = real ? fs.f[f][s] : 0.0;
+        double b[ROWS];
+#pragma unroll
+        for (int c = 0; c < ROWS; ++c) b[c] = real ? fs.f[f][jr[c]] - fi : 0.0;
+        group_qr_solve<N3, ROWS>(a, alpha_all[grp], tau_all[grp], b);
+        if (cubic) {
+#pragma unroll
+            for (int c = 0; c < ROWS; ++c) {
+                const int q = gl + 16 * c;
+                if (q < N3) {
+                    const int col = perm[q];
+                    const int deg = third_order_degree<D>(col);
+                    const double sp = deg == 1 ? r : (deg == 2 ? r * r : r * r * r);
+                    deriv[((int64_t)f * N3 + col) * n + i] = b[c] / sp;
+                }
+            }
+        }
+    }
+    if (!real) return;
+    if (cubic) {
+        if (gl == 0) status[i] = 0;
+    } else if (gl == 0) {
+        queue[atomicAdd(&sc->n_fallback, 1)] = s;
+    }
+}
+
+// The deficient cubic systems: the second-order fit of the same stencil (one
+// wave per queued particle), cubic columns zero, status 1 + its status.
+template <int D>
+__global__ __launch_bounds__(64) void k_gfd3_fallback(Sorted srt, FieldPtrs fs, int nf, const int *nbr, int ldn,
+                                                      const int *count, int n, DevCfg cfg, const DevScalars *sc,
+                                                      const int *queue, double *deriv, uint8_t *status) {
     constexpr int N3 = Dim3<D>::NU, NU = Dim<D>::NU, NS = Dim<D>::NS;
     __shared__ int sel[64];
     const int l = threadIdx.x & 63;
-    for (int s = blockIdx.x; s < n; s += gridDim.x) {
+    const int nq = sc->n_fallback;
+    for (int w = blockIdx.x; w < nq; w += gridDim.x) {
+        const int s = queue[w];
         const int i = srt.id[s];
         int k = count[s];
         if (k > cfg.max_nb) k = cfg.max_nb;
@@ -1994,68 +2123,40 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         double fi[5];
 #pragma unroll
         for (int f = 0; f < 5; ++f) fi[f] = f < nf ? fs.f[f][s] : 0.0;
-        const int m = wave_lw_select<D>(srt, cfg, nbr, ldn, s, k, xi, sel);
-        __syncthreads();
-        double row[N3], b[5];
+        double grad[5][3], hess[5][NS];
+        const int st2 = lw_fit_wave<D, 5>(srt, cfg, nbr, ldn, s, k, xi, r, fi,
+                                          [&](int j, int f) { return f < nf ? fs.f[f][j] : 0.0; }, grad, hess, sel);
+        if (l == 0) {
 #pragma unroll
-        for (int q = 0; q < N3; ++q) row[q] = 0.0;
-#pragma unroll
-        for (int f = 0; f < 5; ++f) b[f] = 0.0;
-        if (l < m) {
-            const int j = sel[l];
-            double dx[3];
-            displacement<D>(srt, cfg, j, xi, dx);
-            double x[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-            for (int a = 0; a < D; ++a) x[a] = dx[a] / r;
-            third_order_row<D>(x, row);
-#pragma unroll
-            for (int f = 0; f < 5; ++f)
-                if (f < nf) b[f] = fs.f[f][j] - fi[f];
-        }
-        __syncthreads();  // sel is rewritten by the fallback below
-        double y[5];
-        int col = -1;
-        double cond = INFINITY;
-        if (m >= N3) cond = wave_qrp_lanes<N3, 5>(row, b, nf, y, col);
-        if (m >= N3 && cond <= cfg.cond_max) {
-            if (col >= 0) {
-                const int deg = third_order_degree<D>(col);
-                const double sp = deg == 1 ? r : (deg == 2 ? r * r : r * r * r);
-#pragma unroll
-                for (int f = 0; f < 5; ++f)
-                    if (f < nf) deriv[((int64_t)f * N3 + col) * n + i] = y[f] / sp;
+            for (int f = 0; f < 5; ++f) {
+                if (f >= nf) break;  // constant indices keep the arrays in registers
+                for (int a = 0; a < D; ++a) deriv[((int64_t)f * N3 + a) * n + i] = grad[f][a];
+                for (int q = 0; q < NS; ++q) deriv[((int64_t)f * N3 + D + q) * n + i] = hess[f][q];
+                for (int q = NU; q < N3; ++q) deriv[((int64_t)f * N3 + q) * n + i] = 0.0;
             }
-            if (l == 0) status[i] = 0;
-        } else {
-            double grad[5][3], hess[5][NS];
-            const int st2 = lw_fit_wave<D, 5>(srt, cfg, nbr, ldn, s, k, xi, r, fi,
-                                              [&](int j, int f) { return f < nf ? fs.f[f][j] : 0.0; }, grad, hess,
-                                              sel);
-            if (l == 0) {
-#pragma unroll
-                for (int f = 0; f < 5; ++f) {
-                    if (f >= nf) break;  // constant indices keep the arrays in registers
-                    for (int a = 0; a < D; ++a) deriv[((int64_t)f * N3 + a) * n + i] = grad[f][a];
-                    for (int q = 0; q < NS; ++q) deriv[((int64_t)f * N3 + D + q) * n + i] = hess[f][q];
-                    for (int q = NU; q < N3; ++q) deriv[((int64_t)f * N3 + q) * n + i] = 0.0;
-                }
-                status[i] = (uint8_t)(1 + st2);
-            }
+            status[i] = (uint8_t)(1 + st2);
         }
         __syncthreads();
     }
 }
 
 void launch_gfd3(const Sorted &s, const double *const *fs, int nf, const int *nbr, int ldn, const int *count, int n,
-                 const DevCfg &cfg, double *deriv, uint8_t *status, hipStream_t st) {
+                 const DevCfg &cfg, DevScalars *sc, int *queue, double *deriv, uint8_t *status, hipStream_t st) {
     FieldPtrs f{};
     for (int q = 0; q < nf && q < 5; ++q) f.f[q] = fs[q];
-    unsigned blocks = (unsigned)(n < 65536 ? (n > 0 ? n : 1) : 65536);
-    if (cfg.D == 3)
-        hipLaunchKernelGGL(k_gfd3<3>, dim3(blocks), dim3(64), 0, st, s, f, nf, nbr, ldn, count, n, cfg, deriv, status);
-    else
-        hipLaunchKernelGGL(k_gfd3<2>, dim3(blocks), dim3(64), 0, st, s, f, nf, nbr, ldn, count, n, cfg, deriv, status);
+    const unsigned blocks = (unsigned)((n + 3) / 4 > 0 ? (n + 3) / 4 : 1);
+    const unsigned fb = (unsigned)(n < 4096 ? (n > 0 ? n : 1) : 4096);
+    if (cfg.D == 3) {
+        hipLaunchKernelGGL(k_gfd3<3>, dim3(blocks), dim3(64), 0, st, s, f, nf, nbr, ldn, count, n, cfg, sc, queue,
+                           deriv, status);
+        hipLaunchKernelGGL(k_gfd3_fallback<3>, dim3(fb), dim3(64), 0, st, s, f, nf, nbr, ldn, count, n, cfg, sc,
+                           queue, deriv, status);
+    } else {
+        hipLaunchKernelGGL(k_gfd3<2>, dim3(blocks), dim3(64), 0, st, s, f, nf, nbr, ldn, count, n, cfg, sc, queue,
+                           deriv, status);
+        hipLaunchKernelGGL(k_gfd3_fallback<2>, dim3(fb), dim3(64), 0, st, s, f, nf, nbr, ldn, count, n, cfg, sc,
+                           queue, deriv, status);
+    }
     (void)hipGetLastError();
 }
 
