@@ -294,6 +294,8 @@ def main():
     ap.add_argument("--solve-block", type=int, default=None)
     ap.add_argument("--list-skin", type=int, default=None,
                     help="neighbour-list reuse skin in per mille of r (0: a full search every step)")
+    ap.add_argument("--search-cap", type=int, default=None,
+                    help="list slots per particle in LDS for the search and filter kernels (0: from the last step)")
     ap.add_argument("--solve-mode", type=int, default=None, help="0 direct, 1 work queue, 2 persistent work queue")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-openbc", action="store_true",
@@ -378,6 +380,8 @@ def main():
             ctx.set_tuning(lp.TUNE_SOLVE_BLOCK, args.solve_block)
         if args.list_skin is not None:
             ctx.set_tuning(lp.TUNE_LIST_SKIN, args.list_skin)
+        if args.search_cap is not None:
+            ctx.set_tuning(lp.TUNE_SEARCH_CAP, args.search_cap)
         return ctx
 
     for prec in precisions:

@@ -229,14 +229,23 @@ __device__ __forceinline__ int div_small(int c, int n, float rcp, int &rem) {
 }
 
 // LDS layout shared by k_search_bal and k_filter_bal (per group of G lanes):
-// lcap + 1 FP32 keys and indices, a byte permutation, SB_NB bucket counters.
+// lcap + 1 FP32 keys and indices, a byte permutation, SB_NB 16-bit bucket
+// counters (two to a word: the counting adds 1 << 16 for an odd bucket, and
+// no count exceeds the 256 entries of a list).
 struct BalLds {
     float *gkey;
     int *gj;
     unsigned char *gperm;
-    int *gbk;
+    unsigned short *gbk;
     int *lout, *lk;  // after ranking: the block's ranked lists and their lengths
 };
+
+// bucket bb's counter += 1, returning its old value
+__device__ __forceinline__ int bucket_add(unsigned short *gbk, int bb) {
+    const unsigned sh = 16u * (unsigned)(bb & 1);
+    const unsigned old = atomicAdd(reinterpret_cast<unsigned *>(gbk) + (bb >> 1), 1u << sh);
+    return (int)((old >> sh) & 0xffffu);
+}
 
 template <int G>
 __device__ __forceinline__ BalLds bal_lds(unsigned char *smem, int lcap, int grp) {
@@ -245,15 +254,21 @@ __device__ __forceinline__ BalLds bal_lds(unsigned char *smem, int lcap, int grp
     float *lkey = reinterpret_cast<float *>(smem);
     int *lj = reinterpret_cast<int *>(lkey + PPB * stride);
     unsigned char *lperm = reinterpret_cast<unsigned char *>(lj + PPB * stride);
-    int *lbk = reinterpret_cast<int *>(lperm + PPB * ((stride + 3) & ~3));
+    unsigned short *lbk = reinterpret_cast<unsigned short *>(lperm + PPB * ((stride + 3) & ~3));
     BalLds l;
     l.gkey = lkey + grp * stride;
     l.gj = lj + grp * stride;
     l.gperm = lperm + grp * ((stride + 3) & ~3);
     l.gbk = lbk + grp * SB_NB;
     l.lout = reinterpret_cast<int *>(smem);
-    l.lk = lbk;
+    l.lk = reinterpret_cast<int *>(lbk);
     return l;
+}
+
+// zero a group's bucket counters (every lane of the group)
+template <int G>
+__device__ __forceinline__ void bucket_clear(unsigned short *gbk, int lane) {
+    for (int q = lane; q < SB_NB / 2; q += G) reinterpret_cast<unsigned *>(gbk)[q] = 0u;
 }
 
 // The k hits staged in a group's slots (FP32 key of d2, cell-order index) are
@@ -272,7 +287,7 @@ __device__ __forceinline__ void bal_rank_write(const BalLds &l, int k, bool acti
     float *gkey = l.gkey;
     int *gj = l.gj;
     unsigned char *gperm = l.gperm;
-    int *gbk = l.gbk;
+    unsigned short *gbk = l.gbk;
     int *lout = l.lout;
     int *lk = l.lk;
     __syncthreads();
@@ -294,7 +309,7 @@ __device__ __forceinline__ void bal_rank_write(const BalLds &l, int k, bool acti
                 int bb = (int)((float)SB_NB * x);
                 bb = bb < 0 ? 0 : (bb > SB_NB - 1 ? SB_NB - 1 : bb);
                 bk[q] = bb;
-                pos[q] = atomicAdd(&gbk[bb], 1);
+                pos[q] = bucket_add(gbk, bb);
             }
         }
     }
@@ -320,7 +335,7 @@ __device__ __forceinline__ void bal_rank_write(const BalLds &l, int k, bool acti
 #pragma unroll
         for (int q = 0; q < BPL; ++q) {
             const int bb = lane * BPL + q;
-            if (bb < SB_NB) gbk[bb] = run;  // start of bucket bb
+            if (bb < SB_NB) gbk[bb] = (unsigned short)run;  // start of bucket bb
             run += cnt[q];
         }
     }
@@ -549,16 +564,6 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *
     if (gate && *gate == 0u) return;
     constexpr int PPB = LP_BLOCK / G;
     extern __shared__ unsigned char smem[];
-    const int stride = lcap + 1;  // odd group stride: groups of a wave hit different LDS banks
-    float *lkey = reinterpret_cast<float *>(smem);
-    int *lj = reinterpret_cast<int *>(lkey + PPB * stride);
-    unsigned char *lperm = reinterpret_cast<unsigned char *>(lj + PPB * stride);
-    int *lbk = reinterpret_cast<int *>(lperm + PPB * ((stride + 3) & ~3));
-    // after ranking, the key slots hold the ranked lists lout[rank * PPB + grp]
-    // and the bucket counters the list length of every group (0: written elsewhere)
-    int *lout = reinterpret_cast<int *>(smem);
-    int *lk = lbk;
-
     const int lane = threadIdx.x % G;
     const int grp = threadIdx.x / G;
     const int gshift = (int)(threadIdx.x & 63) - lane;  // first wave lane of the group
@@ -567,15 +572,16 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *
     const int s = xcd_remap(blockIdx.x, gridDim.x) * PPB + grp;
     const int n_total = *n_total_dev;
     const bool active = s < n_total && srt.id[s] < n_real;
-    float *gkey = lkey + grp * stride;
-    int *gj = lj + grp * stride;
-    unsigned char *gperm = lperm + grp * ((stride + 3) & ~3);
-    int *gbk = lbk + grp * SB_NB;
+    // after ranking, the key slots hold the ranked lists lout[rank * PPB + grp]
+    // and the bucket counters the list length of every group (0: written elsewhere)
+    BalLds l = bal_lds<G>(smem, lcap, grp);
+    float *gkey = l.gkey;
+    int *gj = l.gj;
     int k = 0;  // hits so far (the same in every lane of the group)
     double r2 = 0.0;
     double xi[3] = {0.0, 0.0, 0.0};
 
-    for (int q = lane; q < SB_NB; q += G) gbk[q] = 0;
+    bucket_clear<G>(l.gbk, lane);
     if (active) {
         xi[0] = srt.x[0][s];
         xi[1] = srt.x[1][s];
@@ -605,8 +611,6 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *
                 k += __popcll(mb);
             });
     }
-    BalLds l;
-    l.gkey = gkey; l.gj = gj; l.gperm = gperm; l.gbk = gbk; l.lout = lout; l.lk = lk;
     bal_rank_write<D, G, PER>(l, k, active, s, r2, xi, srt, cfg, nbr, ldn, count, sc, lcap, ovf_queue,
                               &sc->n_overflow, max_out);
 }
@@ -702,7 +706,7 @@ __global__ __launch_bounds__(LP_BLOCK) void k_filter_bal(Sorted srt, const int *
     int k = 0;
     double r2 = 0.0;
     double xi[3] = {0.0, 0.0, 0.0};
-    for (int q = lane; q < SB_NB; q += G) l.gbk[q] = 0;
+    bucket_clear<G>(l.gbk, lane);
     if (active) {
         xi[0] = srt.x[0][s];
         xi[1] = srt.x[1][s];
@@ -862,7 +866,7 @@ static size_t search_smem(int G, int lcap) {
 static size_t search_bal_smem(int G, int lcap) {
     size_t ppb = (size_t)(LP_BLOCK / G);
     size_t stride = (size_t)lcap + 1;
-    return ppb * stride * 8 + ppb * ((stride + 3) & ~(size_t)3) + ppb * SB_NB * 4;
+    return ppb * stride * 8 + ppb * ((stride + 3) & ~(size_t)3) + ppb * SB_NB * 2;
 }
 
 template <int D, int G>
