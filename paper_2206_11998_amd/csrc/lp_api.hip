@@ -814,7 +814,10 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
         sv.ms.phi_plain = (double *)c->mphi.p;
         sv.ms.mflag = (uint8_t *)c->mflag.p;
         sv.ms.ld = c->cap_total;
+        // a step (not a harvest) with the network: the fused kernel applies it where it can
+        if (!harvest) sv.ms.theta = (const float *)c->theta.p;
     }
+    const bool net_fused = solve_fuses_network(sv, c->solve_mode);
     launch_solve(sv, (int)n_total, c->solve_block, c->solve_mode, +between, &bt, st);
     stage_mark(c, st, 4, false);
     stage_mark(c, st, 5, true);
@@ -828,7 +831,8 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
     }
     if (staged) {
         stage_mark(c, st, 7, true);
-        launch_mlp_apply((const float *)c->theta.p, srt, soa, c->dc, c->sc, n_total, n, sv.ms, st);
+        launch_mlp_apply((const float *)c->theta.p, srt, soa, c->dc, c->sc, n_total, n, sv.ms, net_fused ? 1 : 0,
+                         (const int *)c->queue.p, (const int *)c->rq.p, st);
         stage_mark(c, st, 7, false);
     }
     launch_advance_time(c->sc, st);

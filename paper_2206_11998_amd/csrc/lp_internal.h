@@ -231,6 +231,7 @@ struct MlpStage {
     double *phi_plain;
     uint8_t *mflag;
     int64_t ld;
+    const float *theta;  // non-NULL: the network's parameters, applied by the fused kernel itself
 };
 
 // Everything the fit and update kernels read or write.
@@ -255,6 +256,10 @@ struct SolveArgs {
     const unsigned long long *octc; // per particle with a list longer than lw_cap: its octant counts
                                     // (8 bits each, written by the list filter; ~0: not counted), or NULL
 };
+// whether launch_solve with these arguments and mode runs the network itself
+// (the fused kernel, with ms.theta set): then only the particles staged by the
+// refinement and the FP64 fallback are left for launch_mlp_apply
+bool solve_fuses_network(const SolveArgs &a, int mode);
 // mode: 0 direct, 1 work queue, 2 persistent launch over the work queue
 void launch_solve(const SolveArgs &a, int n_total_cap, int block, int mode, void (*between)(void *),
                   void *between_arg, hipStream_t st);
@@ -266,7 +271,8 @@ void launch_solve_fallback(const Sorted &s, const Soa &p, const int *nbr, int ld
 // network estimator (lp_mlp.hip)
 void launch_mlp_forward(const float *th, int64_t n, const float *feat, float *z, float *y, hipStream_t st);
 void launch_mlp_apply(const float *th, const Sorted &s, const Soa &p, const DevCfg &cfg, DevScalars *sc,
-                      int64_t n_total_cap, int n_real, const MlpStage &ms, hipStream_t st);
+                      int64_t n_total_cap, int n_real, const MlpStage &ms, int queued, const int *fq, const int *rq,
+                      hipStream_t st);
 int mlp_grad_blocks(int64_t nb);
 void launch_mlp_grad(const float *th, int64_t b0, int64_t nb, const float *feat, const float *target, float *part,
                      float *loss_part, float *grad, float *loss, hipStream_t st);

@@ -1,120 +1,8 @@
-// lp_mlp.hip -- the learned state estimator on gfx950: a 16 -> 64 -> 64 -> 1
-// network (ReLU hidden layers, sigmoid output) that may stand in for the
-// quotient estimator of the blended update (Sec. 2.1, state estimator), with
-// the quotient estimator kept as the fallback.  Not part of the paper's method.
-//
-// Both directions run on BF16 matrix cores (v_mfma_f32_16x16x16_bf16) with
-// FP32 accumulation; FP32 master weights.  One wave handles a tile of 16
-// samples.  Every layer is computed transposed, Y^T = W X^T, so that the
-// accumulator fragment of one layer (lane l: sample l % 16, units
-// 4 (l / 16) .. +3) is exactly the B-operand fragment of the next.
-//
-// Operand fragments of the 16x16x16 instruction, lane l, element v = 0..3:
-//   A[i][k]: i = l % 16, k = 4 (l / 16) + v
-//   B[k][j]: j = l % 16, k = 4 (l / 16) + v
-//   D[i][j]: j = l % 16, i = 4 (l / 16) + v
-#include "lp_internal.h"
-
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-#define MLP_IN 16
-#define MLP_H 64
-#define OFF_W1 0
-#define OFF_B1 (OFF_W1 + MLP_H * MLP_IN)
-#define OFF_W2 (OFF_B1 + MLP_H)
-#define OFF_B2 (OFF_W2 + MLP_H * MLP_H)
-#define OFF_W3 (OFF_B2 + MLP_H)
-#define OFF_B3 (OFF_W3 + MLP_H)
-static_assert(OFF_B3 + 1 == LP_MLP_NPARAM, "parameter layout");
-
-// FP32 -> BF16, round to nearest even (NaN stays NaN)
-__device__ __forceinline__ short f2bf(float f) {
-    unsigned u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
-}
-
-__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-}
-
-__device__ __forceinline__ f32x4 zero4() {
-    f32x4 z = {0.f, 0.f, 0.f, 0.f};
-    return z;
-}
-
-// Weights of one wave, in fragment order.
-struct MlpRegs {
-    bf16x4 a1[4];       // W1 tiles (unit block ob): W1[16 ob + l%16][4 (l/16) + v]
-    bf16x4 a2[4][4];    // W2 tiles [ob][kb]: W2[16 ob + l%16][16 kb + 4 (l/16) + v]
-    float b1[4][4];     // b1[16 ob + 4 (l/16) + v]
-    float b2[4][4];
-    float w3[4][4];
-    float b3;
-};
-
-__device__ __forceinline__ void load_regs(const float *th, MlpRegs &R) {
-    const int l = threadIdx.x & 63, r = l & 15, c = 4 * (l >> 4);
-#pragma unroll
-    for (int ob = 0; ob < 4; ++ob) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            R.a1[ob][v] = f2bf(th[OFF_W1 + (16 * ob + r) * MLP_IN + c + v]);
-            R.b1[ob][v] = th[OFF_B1 + 16 * ob + c + v];
-            R.b2[ob][v] = th[OFF_B2 + 16 * ob + c + v];
-            R.w3[ob][v] = th[OFF_W3 + 16 * ob + c + v];
-        }
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) R.a2[ob][kb][v] = f2bf(th[OFF_W2 + (16 * ob + r) * MLP_H + 16 * kb + c + v]);
-    }
-    R.b3 = th[OFF_B3];
-}
-
-// Input fragment: features 4 (l/16) .. +3 of sample l % 16 (zero when absent).
-__device__ __forceinline__ bf16x4 load_x(const float *feat, int64_t idx, bool ok) {
-    const int c = 4 * ((threadIdx.x & 63) >> 4);
-    bf16x4 x;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) x[v] = ok ? f2bf(feat[idx * MLP_IN + c + v]) : (short)0;
-    return x;
-}
-
-// Forward pass of the tile: pre-activations d1, d2 (FP32, bias added), the
-// BF16 hidden fragment h1 and the output z of sample l % 16 (in every lane).
-__device__ __forceinline__ float forward(const MlpRegs &R, bf16x4 x, f32x4 d1[4], bf16x4 h1[4], f32x4 d2[4]) {
-#pragma unroll
-    for (int ob = 0; ob < 4; ++ob) {
-        d1[ob] = mfma16(R.a1[ob], x, zero4());
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            d1[ob][v] += R.b1[ob][v];
-            h1[ob][v] = f2bf(d1[ob][v] > 0.f ? d1[ob][v] : 0.f);
-        }
-    }
-    float zp = 0.f;
-#pragma unroll
-    for (int ob = 0; ob < 4; ++ob) {
-        f32x4 acc = zero4();
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) acc = mfma16(R.a2[ob][kb], h1[kb], acc);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            acc[v] += R.b2[ob][v];
-            zp += R.w3[ob][v] * (acc[v] > 0.f ? acc[v] : 0.f);
-        }
-        d2[ob] = acc;
-    }
-    // the four lanes of a sample (l, l+16, l+32, l+48) hold a quarter each
-    zp += __shfl_xor(zp, 16);
-    zp += __shfl_xor(zp, 32);
-    return zp + R.b3;
-}
-
-__device__ __forceinline__ float sigmoidf(float z) { return 1.f / (1.f + __expf(-z)); }
+// lp_mlp.hip -- the learned state estimator's kernels on gfx950: inference
+// over a batch, the estimator stage of a step whose update was staged, and
+// training (forward and backward of the mean binary cross-entropy, Adam).
+// The network and its fragment layouts are in lp_mlp.h.
+#include "lp_mlp.h"
 
 // ---------------------------------------------------------------------------
 // Network output z (and sigmoid) for n samples: one wave per tile of 16.
@@ -130,7 +18,7 @@ __global__ __launch_bounds__(64) void k_mlp_forward(const float *th, int64_t n, 
         const bool ok = idx < n;
         f32x4 d1[4], d2[4];
         bf16x4 h1[4];
-        const float z = forward(R, load_x(feat, idx, ok), d1, h1, d2);
+        const float z = forward(RegWeights{R}, load_x(feat, idx, ok), d1, h1, d2);
         if (ok && l < 16) {
             if (z_out) z_out[idx] = z;
             if (y_out) y_out[idx] = sigmoidf(z);
@@ -149,24 +37,35 @@ void launch_mlp_forward(const float *th, int64_t n, const float *feat, float *z,
 // Estimator stage of a step with the network: phi = min(1, 1.25 sigmoid(z))
 // where the network is trusted, the quotient estimator's phi elsewhere, then
 // the blended update and the mover -- the same arithmetic as the update kernel.
+// Items: every cell-order particle (queued == 0), or (queued != 0) only the
+// particles staged by the FP64 fallback (its queue) and by the refinement
+// (its queue, pairs), when the fused kernel applied the network to the rest.
 // ---------------------------------------------------------------------------
 template <int D>
 __global__ __launch_bounds__(256) void k_mlp_apply(const float *th, Sorted srt, Soa p, DevCfg cfg, DevScalars *sc,
-                                                  int n_real, MlpStage ms) {
+                                                  int n_real, MlpStage ms, int queued, const int *fq, const int *rq) {
     constexpr int NF = D + 2, FP = D + 1;
     MlpRegs R;
     load_regs(th, R);
     const int l = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
+    const int n_fb = queued ? sc->n_fallback : 0;
+    const int n_items = queued ? n_fb + sc->n_refine : sc->n_total;
     const int n_total = sc->n_total;
     const double dt = sc->dt;
-    // groups of 64 particles, one wave each: four 16-particle tiles through
-    // the network, then every lane finishes its own particle of the group
-    const int64_t ngroup = ((int64_t)n_total + 63) / 64;
+    // the cell-order particle of item w (-1: none)
+    auto item = [&](int64_t w) -> int {
+        if (w >= n_items) return -1;
+        if (!queued) return (int)w;
+        return w < n_fb ? fq[w] : rq[2 * (w - n_fb)];
+    };
+    // groups of 64 items, one wave each: four 16-item tiles through the
+    // network, then every lane finishes its own item of the group
+    const int64_t ngroup = ((int64_t)n_items + 63) / 64;
     unsigned long long used = 0, plain = 0, lim = 0;
     for (int64_t grp = (int64_t)blockIdx.x * 4 + wv; grp < ngroup; grp += (int64_t)gridDim.x * 4) {
-        const int s = (int)(grp * 64 + l);
-        bool ok = s < n_total;
+        const int s = item(grp * 64 + l);
+        const bool ok = s >= 0 && s < n_total;
         const int i = ok ? srt.id[s] : n_real;
         const bool mine = ok && i < n_real;
         // the update's operands are loaded before the network runs, so their
@@ -190,100 +89,41 @@ __global__ __launch_bounds__(256) void k_mlp_apply(const float *th, Sorted srt, 
             phi_plain = ms.phi_plain[s];
             mf = ms.mflag[s];
         }
-        // tile t covers particles 64 grp + 16 t .. + 15; after its pass, lane
-        // l of quarter t holds the output of particle 64 grp + l (a column of
-        // the products depends on its own sample only, so unstaged rows of
-        // ghosts affect nothing else)
+        // tile t covers items 64 grp + 16 t .. + 15; after its pass, lane l
+        // of quarter t holds the output of item 64 grp + l (a column of the
+        // products depends on its own sample only, so unstaged rows of ghosts
+        // affect nothing else)
         float z = 0.f;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const int64_t sx = grp * 64 + 16 * t + (l & 15);
-            const bf16x4 x = load_x(ms.feat, sx, sx < n_total);
+            const int st_ = item(grp * 64 + 16 * t + (l & 15));
+            const bf16x4 x = load_x(ms.feat, st_ >= 0 ? st_ : 0, st_ >= 0 && st_ < n_total);
             f32x4 d1[4], d2[4];
             bf16x4 h1[4];
-            const float zt = forward(R, x, d1, h1, d2);
+            const float zt = forward(RegWeights{R}, x, d1, h1, d2);
             if ((l >> 4) == t) z = zt;
         }
         if (!mine) continue;
-        double phi;
-        if (mf & LP_MLP_FORCE0) {
-            phi = 0.0;
-        } else {
-            // trusted: every input within range and the estimate away from 1/2;
-            // the estimate is 1.25 sigmoid(z) capped at 1, the limiter's range
-            bool in_range = true;
+        bool in_range = true;
 #pragma unroll
-            for (int q = 0; q < MLP_IN; ++q) {
-                const float f = ms.feat[(int64_t)s * MLP_IN + q];
-                in_range = in_range && fabsf(f) <= cfg.mlp_feat_max;
-            }
-            const float y = fminf(1.25f * sigmoidf(z), 1.0f);
-            if (in_range && fabsf(y - 0.5f) >= cfg.mlp_band) {
-                phi = (double)y;
-                ++used;
-            } else {
-                phi = phi_plain;
-                ++plain;
-            }
-        }
-        double ns[NF];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) ns[f] = st[f] + dt * (uw[f] - phi * (uw[f] - lw[f]));
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            double xn = xs[a] + 0.5 * dt * (st[1 + a] + ns[1 + a]);
-            if (cfg.periodic[a]) {
-                if (xn >= cfg.hi[a]) xn -= cfg.L[a];
-                else if (xn < cfg.lo[a]) xn += cfg.L[a];
-            }
-            p.x[a][i] = xn;
-            p.u[a][i] = ns[1 + a];
-        }
-        p.V[i] = ns[0];
-        p.P[i] = ns[FP];
-        uint8_t flags = mf & (uint8_t)~LP_MLP_FORCE0;
-        if (phi < 1.0) {
-            flags |= LP_FLAG_LIMITED;
-            ++lim;
-        }
-        if (!(ns[0] > 0.0) || !(ns[FP] > 0.0)) {
-            flags |= LP_FLAG_NUMERIC;
-            atomicOr(&sc->error_bits, 2u);
-        }
-        if (p.flags) p.flags[i] = flags;
-        if (p.phi) p.phi[i] = (float)phi;
+        for (int q = 0; q < MLP_IN; ++q) in_range = in_range && fabsf(ms.feat[(int64_t)s * MLP_IN + q]) <= cfg.mlp_feat_max;
+        mlp_blend_update<D>(cfg, p, sc, i, dt, z, in_range, st, lw, uw, xs, phi_plain, mf, used, plain, lim);
     }
-    // one atomic per block and counter: the counters are single addresses,
-    // whose atomics serialise in the cache (every lane is active here)
-    for (int o = 32; o > 0; o >>= 1) {
-        used += __shfl_xor(used, o);
-        plain += __shfl_xor(plain, o);
-        lim += __shfl_xor(lim, o);
-    }
-    __shared__ unsigned long long part[4][3];
-    if (l == 0) {
-        part[wv][0] = used;
-        part[wv][1] = plain;
-        part[wv][2] = lim;
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-        const unsigned long long v = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] +
-                                     part[3][threadIdx.x];
-        unsigned long long *dst = threadIdx.x == 0 ? &sc->n_mlp : threadIdx.x == 1 ? &sc->n_mlp_plain : &sc->n_limited;
-        if (v) atomicAdd(dst, v);
-    }
+    mlp_block_counts(sc, used, plain, lim);
 }
 
 void launch_mlp_apply(const float *th, const Sorted &s, const Soa &p, const DevCfg &cfg, DevScalars *sc,
-                      int64_t n_total_cap, int n_real, const MlpStage &ms, hipStream_t st) {
-    // four waves per block, at most 8192 waves: each wave loads the weights once
+                      int64_t n_total_cap, int n_real, const MlpStage &ms, int queued, const int *fq, const int *rq,
+                      hipStream_t st) {
+    // four waves per block, at most 8192 waves: each wave loads the weights
+    // once (the queued particles are few: at most 256 blocks)
     int64_t nb = ((n_total_cap + 63) / 64 + 3) / 4;
-    unsigned g = (unsigned)(nb < 2048 ? (nb > 0 ? nb : 1) : 2048);
+    const int64_t cap = queued ? 256 : 2048;
+    unsigned g = (unsigned)(nb < cap ? (nb > 0 ? nb : 1) : cap);
     if (cfg.D == 3)
-        hipLaunchKernelGGL(k_mlp_apply<3>, dim3(g), dim3(256), 0, st, th, s, p, cfg, sc, n_real, ms);
+        hipLaunchKernelGGL(k_mlp_apply<3>, dim3(g), dim3(256), 0, st, th, s, p, cfg, sc, n_real, ms, queued, fq, rq);
     else
-        hipLaunchKernelGGL(k_mlp_apply<2>, dim3(g), dim3(256), 0, st, th, s, p, cfg, sc, n_real, ms);
+        hipLaunchKernelGGL(k_mlp_apply<2>, dim3(g), dim3(256), 0, st, th, s, p, cfg, sc, n_real, ms, queued, fq, rq);
     (void)hipGetLastError();
 }
 
@@ -333,7 +173,7 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const float *th, int64_t b0, in
         const bf16x4 x = load_x(feat, idx, ok);
         f32x4 d1[4], d2[4];
         bf16x4 h1[4];
-        const float z = forward(R, x, d1, h1, d2);
+        const float z = forward(RegWeights{R}, x, d1, h1, d2);
         const float t = ok ? target[idx] : 0.f;
         const float y = sigmoidf(z);
         const float dz = ok ? (y - t) * inv_batch : 0.f;

@@ -19,7 +19,7 @@
 // Householder QR with column pivoting (the paper's solver) with all column
 // norms and reflector products formed by wave-wide butterfly reductions.
 // It applies the same rank-deficiency rule as the definition (|R11|/|Rnn|).
-#include "lp_internal.h"
+#include "lp_mlp.h"
 
 // Multiply-adds are fused only inside one source expression, never across
 // statements, so that every kernel instantiating the same fit code rounds it
@@ -650,12 +650,24 @@ template <int D> struct DerCoef {
     }
 };
 
+// What the update of a particle hands to the network in the fused kernel:
+// the inputs go to the lane's row of the block's feature array in LDS, the
+// rates and the quotient estimator's phi stay in registers.
+template <int D> struct NetLane {
+    float *feat;
+    float lw[D + 2], uw[D + 2];
+    double phi_plain;
+    uint8_t mf;
+    bool in_range;  // every input within +-mlp_feat_max
+    bool have;
+};
+
 template <int D, typename T, class DS>
 __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p, const DevCfg &cfg, DevScalars *sc,
                                                 const int *nbr, int ldn, int s, int i, int k, double dt,
                                                 const double xi[3], const double st[Dim<D>::NF], double h, double r,
                                                 const DS &ds, int lw_status, uint8_t flags,
-                                                const MlpStage *ms = nullptr) {
+                                                const MlpStage *ms = nullptr, NetLane<D> *nl = nullptr) {
     constexpr int NF = Dim<D>::NF, FP = D + 1, NGD = D * (D + 1) / 2;
     // V and P over the particle and its half-ball members (network inputs)
     T vmin = (T)st[0], vmax = (T)st[0], pmin = (T)st[FP], pmax = (T)st[FP];
@@ -876,6 +888,29 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
         // phi; the network decides phi and applies the update afterwards
         float fv[16];
         estimator_features<D, T>(cfg, st, grad, dl, dr, valid_l, valid_r, h, vmin, vmax, pmin, pmax, fv);
+        uint8_t mf = flags;
+        if (lw_status != 0) mf |= LP_FLAG_DEGENERATE;
+        if (vac) mf |= LP_FLAG_VACUUM;
+        if (subst) mf |= LP_FLAG_SUBSTITUTED;
+        if (lw_status != 0 || vac) mf |= LP_MLP_FORCE0;
+        if (nl) {
+            bool in_range = true;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                nl->feat[q] = fv[q];
+                in_range = in_range && fabsf(fv[q]) <= cfg.mlp_feat_max;
+            }
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                nl->lw[f] = (float)lw[f];
+                nl->uw[f] = (float)uw[f];
+            }
+            nl->phi_plain = phi;
+            nl->mf = mf;
+            nl->in_range = in_range;
+            nl->have = true;
+            return false;
+        }
 #pragma unroll
         for (int q = 0; q < 16; ++q) ms->feat[(int64_t)s * 16 + q] = fv[q];
 #pragma unroll
@@ -884,11 +919,6 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
             ms->rates[(int64_t)(NF + f) * ms->ld + s] = (double)uw[f];
         }
         ms->phi_plain[s] = phi;
-        uint8_t mf = flags;
-        if (lw_status != 0) mf |= LP_FLAG_DEGENERATE;
-        if (vac) mf |= LP_FLAG_VACUUM;
-        if (subst) mf |= LP_FLAG_SUBSTITUTED;
-        if (lw_status != 0 || vac) mf |= LP_MLP_FORCE0;
         ms->mflag[s] = mf;
         return false;
     }
@@ -1210,10 +1240,30 @@ __global__ __launch_bounds__(LP_BLOCK) __attribute__((amdgpu_waves_per_eu(3))) v
 // coefficients stay in registers (no derivative array); particles queued for
 // refinement are updated by the refinement kernel, those queued for the FP64
 // fallback by the fallback kernel.  At most three waves per SIMD keeps the
-// fit's and the update's registers within 168 without spilling.
-template <int D, int MODE>
+// fit's and the update's registers within 168 without spilling.  NET: the
+// estimator network decides phi -- the block stages the network's BF16
+// weights in LDS, every lane leaves its particle's inputs in the block's
+// feature array, and each wave runs its 64 particles through the network in
+// four tiles before the blended update.
+template <bool NET> struct FusedShared {};
+template <> struct FusedShared<true> {
+    MlpShared w;
+    float feat[LP_BLOCK][MLP_IN + 1];  // padded rows: the tile loads spread over the banks
+};
+
+template <int D, int MODE, bool NET>
 __global__ __launch_bounds__(LP_BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void k_fit_finish(SolveArgs a) {
     constexpr int NF = Dim<D>::NF, NU = Dim<D>::NU, FP = D + 1;
+    __shared__ FusedShared<NET> sh;
+    NetLane<D> nl;
+    nl.have = false;
+    int own_i = 0;
+    double own_st[NF], own_x[D];
+    if constexpr (NET) {
+        mlp_shared_load(a.ms.theta, sh.w);
+        nl.feat = sh.feat[threadIdx.x];
+        __syncthreads();
+    }
     int limited = 0;
     for_work<MODE>(a, a.sc->head[0], [&](int s, int t) {
         float B[NF * NU];
@@ -1231,11 +1281,51 @@ __global__ __launch_bounds__(LP_BLOCK) __attribute__((amdgpu_waves_per_eu(3))) v
         const double h = srt.h[s];
         const DerCoef<D> ds{B, inv_r};
         limited += finish_particle<D, float>(srt, a.p, a.cfg, a.sc, a.nbr, a.ldn, s, srt.id[s], k, a.sc->dt, xi,
-                                             st, h, a.cfg.kappa * h, ds, 0, 0, a.ms.feat ? &a.ms : nullptr)
+                                             st, h, a.cfg.kappa * h, ds, 0, 0, a.ms.feat ? &a.ms : nullptr,
+                                             NET ? &nl : nullptr)
                        ? 1
                        : 0;
+        if (NET && nl.have) {
+            own_i = srt.id[s];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) own_st[f] = st[f];
+#pragma unroll
+            for (int q = 0; q < D; ++q) own_x[q] = xi[q];
+        }
     });
-    block_add_limited(a.sc, limited);
+    if constexpr (NET) {
+        if (!nl.have)
+#pragma unroll
+            for (int q = 0; q < MLP_IN; ++q) nl.feat[q] = 0.f;
+        __syncthreads();
+        const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const float *wfeat = sh.feat[64 * wv];
+        // tile t: the wave's lanes 16 t .. 16 t + 15; after it, lane l of
+        // quarter t holds the output of lane l's particle
+        float z = 0.f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const bf16x4 x = load_x(wfeat, 16 * t + (l & 15), true, MLP_IN + 1);
+            f32x4 d1[4], d2[4];
+            bf16x4 h1[4];
+            const float zt = forward(SharedWeights{sh.w}, x, d1, h1, d2);
+            if ((l >> 4) == t) z = zt;
+        }
+        unsigned long long used = 0, plain = 0, lim = 0;
+        if (nl.have) {
+            double lwd[NF], uwd[NF];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                lwd[f] = (double)nl.lw[f];
+                uwd[f] = (double)nl.uw[f];
+            }
+            mlp_blend_update<D>(a.cfg, a.p, a.sc, own_i, a.sc->dt, z, nl.in_range, own_st, lwd, uwd, own_x,
+                                nl.phi_plain, nl.mf, used, plain, lim);
+        }
+        mlp_block_counts(a.sc, used, plain, lim);
+    } else {
+        block_add_limited(a.sc, limited);
+    }
 }
 
 // The fits queued for refinement (condition estimate above refine_cond):
@@ -1314,9 +1404,15 @@ static void launch_solve_t(const SolveArgs &a, int n_total_cap, int block, void 
     gr = gr < 1 ? 1 : (gr > 4096 ? 4096 : gr);
     if constexpr (std::is_same<T, float>::value && !RF) {
         // FP32 fits refined where ill-conditioned (or not at all): fused
-        unsigned gff = blocks;
-        if (MODE == WQ_PERSISTENT) gff = persistent_grid((const void *)k_fit_finish<D, MODE>, block, n_total_cap);
-        hipLaunchKernelGGL((k_fit_finish<D, MODE>), dim3(gff), dim3(block), 0, st, a);
+        if constexpr (MODE != WQ_PERSISTENT) {
+            if (a.ms.feat && a.ms.theta)
+                hipLaunchKernelGGL((k_fit_finish<D, MODE, true>), dim3(blocks), dim3(block), 0, st, a);
+            else
+                hipLaunchKernelGGL((k_fit_finish<D, MODE, false>), dim3(blocks), dim3(block), 0, st, a);
+        } else {
+            const unsigned gff = persistent_grid((const void *)k_fit_finish<D, MODE, false>, block, n_total_cap);
+            hipLaunchKernelGGL((k_fit_finish<D, MODE, false>), dim3(gff), dim3(block), 0, st, a);
+        }
         if (refine_queue) hipLaunchKernelGGL((k_lw_refine<D, true>), dim3(gr), dim3(64), 0, st, a);
         if (between) between(between_arg);
         return;
@@ -1341,6 +1437,12 @@ static void launch_solve_m(const SolveArgs &a, int n_total_cap, int block, int m
     if (mode == WQ_PERSISTENT) launch_solve_t<D, T, RF, WQ_PERSISTENT>(a, n_total_cap, block, between, between_arg, st);
     else if (mode == WQ_QUEUE) launch_solve_t<D, T, RF, WQ_QUEUE>(a, n_total_cap, block, between, between_arg, st);
     else launch_solve_t<D, T, RF, WQ_DIRECT>(a, n_total_cap, block, between, between_arg, st);
+}
+
+bool solve_fuses_network(const SolveArgs &a, int mode) {
+    if (a.wq == nullptr) mode = WQ_DIRECT;
+    const bool refine_all = a.cfg.refine && !(a.cfg.refine_cond > 0.0f && a.rq);
+    return a.ms.feat && a.ms.theta && a.cfg.precision == LP_MIXED && !refine_all && mode != WQ_PERSISTENT;
 }
 
 void launch_solve(const SolveArgs &a, int n_total_cap, int block, int mode, void (*between)(void *),
