@@ -516,7 +516,11 @@ static lp_status ensure_capacity(lp_ctx *c, int64_t n_real, int64_t n_total, boo
     ENSURE(c, c->slot, sizeof(uint32_t) * nt);
     ENSURE(c, c->tables, sizeof(uint32_t) * table_words(c));
     ENSURE(c, c->sorted, sizeof(double) * (state ? 10 : 4) * nt);
-    if (state) ENSURE(c, c->srec, sizeof(double) * LP_REC * nt);
+    // FP64 gather records: the FP64 fits and update, and the refine-every-fit
+    // mixed step (the FP32 fits read the FP32-field records; the few fits the
+    // mixed step refines or sends to the FP64 fallback gather from the arrays)
+    if (state && (!mixed || (c->dc.refine && !(c->dc.refine_cond > 0.0f))))
+        ENSURE(c, c->srec, sizeof(double) * LP_REC * nt);
     if (state && c->dc.precision == LP_MIXED) ENSURE(c, c->srecf, (size_t)LP_RECF_BYTES * nt);
     ENSURE(c, c->sid, sizeof(int) * nt);
     ENSURE(c, c->nbr, sizeof(int) * (size_t)c->dc.max_nb * nt);

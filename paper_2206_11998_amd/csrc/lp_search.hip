@@ -216,6 +216,9 @@ __global__ __launch_bounds__(64) void k_search_overflow(Sorted srt, const uint32
 // of its d2 (round to nearest is monotone, so a smaller key means a smaller
 // d2); only hits whose keys tie recompute their exact FP64 d2 for the order.
 #define SB_NB 32  // rank buckets per particle
+// 16-bit counters per group in LDS: SB_NB plus one padding word, so that the
+// groups of a wave start on different banks
+#define SB_GSTRIDE (SB_NB + 2)
 
 // c = q * n + rem for 0 <= c < 2^24 without an integer division (the FP32
 // quotient is off by at most one either way; corrected without branches)
@@ -259,7 +262,7 @@ __device__ __forceinline__ BalLds bal_lds(unsigned char *smem, int lcap, int grp
     l.gkey = lkey + grp * stride;
     l.gj = lj + grp * stride;
     l.gperm = lperm + grp * ((stride + 3) & ~3);
-    l.gbk = lbk + grp * SB_NB;
+    l.gbk = lbk + grp * SB_GSTRIDE;
     l.lout = reinterpret_cast<int *>(smem);
     l.lk = reinterpret_cast<int *>(lbk);
     return l;
@@ -410,7 +413,7 @@ __device__ __forceinline__ void bal_rank_write(const BalLds &l, int k, bool acti
     if (ranked) {
 #pragma unroll
         for (int q = 0; q < EMAX; ++q)
-            if (lane + q * G < k) lout[rank[q] * PPB + grp] = jq[q];
+            if (lane + q * G < k) lout[rank[q] * (PPB + 1) + grp] = jq[q];
     }
     __syncthreads();
     // write the block's lists: with column-major lists the PPB particles of
@@ -422,7 +425,7 @@ __device__ __forceinline__ void bal_rank_write(const BalLds &l, int k, bool acti
         const int c = idx / PPB, gq = idx % PPB;
         if (c < lk[gq]) {
             const int sq = s0 + gq;
-            nbr[list_at(ldn, sq, c, max_nb)] = lout[c * PPB + gq];
+            nbr[list_at(ldn, sq, c, max_nb)] = lout[c * (PPB + 1) + gq];
         }
     }
 }
@@ -572,7 +575,7 @@ __global__ __launch_bounds__(LP_BLOCK) void k_search_bal(Sorted srt, const int *
     const int s = xcd_remap(blockIdx.x, gridDim.x) * PPB + grp;
     const int n_total = *n_total_dev;
     const bool active = s < n_total && srt.id[s] < n_real;
-    // after ranking, the key slots hold the ranked lists lout[rank * PPB + grp]
+    // after ranking, the key slots hold the ranked lists lout[rank * (PPB + 1) + grp]
     // and the bucket counters the list length of every group (0: written elsewhere)
     BalLds l = bal_lds<G>(smem, lcap, grp);
     float *gkey = l.gkey;
@@ -866,7 +869,7 @@ static size_t search_smem(int G, int lcap) {
 static size_t search_bal_smem(int G, int lcap) {
     size_t ppb = (size_t)(LP_BLOCK / G);
     size_t stride = (size_t)lcap + 1;
-    return ppb * stride * 8 + ppb * ((stride + 3) & ~(size_t)3) + ppb * SB_NB * 2;
+    return ppb * stride * 8 + ppb * ((stride + 3) & ~(size_t)3) + ppb * SB_GSTRIDE * 2;
 }
 
 template <int D, int G>
