@@ -24,6 +24,13 @@
  *   Sec. 2.1, GFD system + "QR with column pivoting"
  *   Sec. 2.1, blend, state estimator, limiter, particle mover
  *   Sec. 2.2, steps 1-6 of the time-step loop
+ *
+ * Parity unpinned: two readings here have no pin of their own -- their 1D or
+ * special cases are pinned, their general form only by parity with the GPU
+ * path and by the Sod and Yee trends: the multi-D upwind rate as the sum over
+ * axes of the 1D characteristic form (lpo_uw_rates), and the state
+ * estimator's aggregation over fields and axes, the largest quotient of the
+ * active V and P pairs (the est_eps test in solve_particle).
  */
 #include <math.h>
 #include <stdint.h>

@@ -143,3 +143,72 @@ def test_shear_layer_16M_one_step(lp, oracle_lib):
     walls = np.concatenate([np.argsort(y)[:1500], np.argsort(-y)[:1500]])  # mirror ghosts
     layer = np.argsort(np.abs(y - 0.5))[:2000]                           # the shear layer
     _one_step_sampled(lp, oracle_lib, cfg, st, np.concatenate([walls, layer]), "shear 16M")
+
+
+def test_shear_layer_16M_full_stack(lp):
+    """The full mixed stack on the 16,777,216-particle shear layer: FP32 fits
+    refined where the condition estimate exceeds 1e3, FP64 fallback, the
+    learned estimator with the quotient estimator as its fallback, and 100
+    graph-replayed steps (lp_run).  The network is trained first, on the GPU,
+    on (inputs, quotient-estimator phi) harvested from this workload's initial
+    state.  Checks: no error flag over the 100 steps, positive V and P, the
+    particle count and the total mass bit for bit, and the network deciding
+    most particles.  The GFD update conserves momentum and energy only up to
+    its truncation error (the blend adds upwind dissipation), so for those a
+    stability bound is checked -- the x and z momentum and the energy within
+    1% of their initial scale -- and the drifts are printed (x momentum
+    -0.17% and energy -0.02% after 100 steps on the first run).  The run's
+    throughput is printed too."""
+    import time
+    cfg, st = W.shear3d()
+    n = st["V"].shape[0]
+    say("shear 16M full stack: %d particles" % n)
+    # training set: the quotient estimator's decisions on the initial state,
+    # limited and unlimited particles in equal numbers
+    h = lp.Context(cfg)
+    dev = lp.state_to_device(st)
+    feat, phi, valid = h.features(dev)
+    keep = valid.bool()
+    feat, phi = feat[keep], phi[keep]
+    lim = torch.nonzero(phi < 1.0).flatten()
+    unl = torch.nonzero(phi >= 1.0).flatten()
+    g = torch.Generator(device="cuda").manual_seed(5)
+    m = min(len(lim), len(unl), 250_000)
+    say("harvested %d inputs: %d limited, %d not" % (int(keep.sum()), len(lim), len(unl)))
+    assert m > 1000
+    sel = torch.cat([lim[torch.randperm(len(lim), generator=g, device="cuda")[:m]],
+                     unl[torch.randperm(len(unl), generator=g, device="cuda")[:m]]])
+    fx, tx = feat[sel].contiguous(), (phi[sel] / 1.25).contiguous()
+    h.mlp_init(11)
+    losses = h.mlp_train(fx, tx, epochs=4, batch=8192, lr=3e-3)
+    params = h.mlp_get()
+    say("trained: loss %.4f -> %.4f" % (losses[0], losses[-1]))
+    assert losses[-1] < losses[0]
+    h.close()
+    del feat, phi, valid, fx, tx, dev
+    ctx = lp.Context(cfg, precision="mixed", refine=True, refine_cond=1e3, estimator="mlp")
+    ctx.mlp_set(params)
+    dev = lp.state_to_device(st)
+    c0 = ctx.conservation(dev)
+    ctx.run(dev, 2)  # planning step and capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.run(dev, 98)
+    torch.cuda.synchronize()
+    dt_wall = time.perf_counter() - t0
+    assert ctx.check() == lp.OK
+    info = ctx.info()
+    c1 = ctx.conservation(dev)
+    out = lp.state_to_host(dev)
+    say("98 replayed steps in %.2f s: %.2f ms/step, %.3g particle-updates/s; t = %.4g; info %s" % (
+        dt_wall, 1e3 * dt_wall / 98, n * 98 / dt_wall, info["t"], info))
+    say("conservation before", c0, "after", c1)
+    assert info["error_bits"] == 0
+    assert out["V"].shape[0] == n and np.all(out["V"] > 0) and np.all(out["P"] > 0)
+    assert c1[0] == c0[0]
+    say("drift: x momentum %.3e (relative %.2e), z momentum %.3e, energy %.3e (relative %.2e)" % (
+        c1[1] - c0[1], (c1[1] - c0[1]) / c0[1], c1[3] - c0[3], c1[4] - c0[4], (c1[4] - c0[4]) / c0[4]))
+    assert abs(c1[1] - c0[1]) <= 1e-2 * abs(c0[1]) and abs(c1[3] - c0[3]) <= 1e-2 * abs(c0[1]), (c0, c1)
+    assert abs(c1[4] - c0[4]) <= 1e-2 * abs(c0[4]), (c0, c1)
+    # the network decides most particles of the last step
+    assert info["n_mlp"] > 0.5 * n, info
