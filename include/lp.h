@@ -115,13 +115,14 @@ typedef struct lp_info {
     int32_t max_count;      /* largest neighbour count of the last search */
     int32_t n_fallback;     /* particles solved by the FP64 pivoted-QR path in the last step */
     int64_t n_limited;      /* particles with phi < 1 in the last step */
-    uint32_t error_bits;    /* bit 0: capacity overflow, bit 1: numeric */
+    uint32_t error_bits;    /* bit 0: capacity overflow, bit 1: numeric, bit 2: inflow layer past cap */
     int32_t levels[2];      /* cell-grid levels used by the last search (coarsest, finest) */
     int64_t n_mlp;          /* LP_EST_MLP: particles whose phi came from the network in the last step */
     int64_t n_mlp_plain;    /* LP_EST_MLP: particles that fell back to the quotient estimator */
     int64_t n_refined;      /* LP_MIXED with refine: fits refined in the last step */
     int64_t n_list_builds;  /* full neighbour searches of the steps so far (LP_TUNE_LIST_SKIN: the
                                steps in between reuse their candidate lists) */
+    int64_t n_captures;     /* step graphs captured by lp_run / lp_run_open so far */
 } lp_info;
 
 /* Fill cfg with the defaults for the given dimension (gamma 1.4, cfl 0.5,
@@ -230,7 +231,9 @@ lp_status lp_gfd3(struct lp_ctx *ctx, void *stream, int64_t n, const double *x, 
 
 /* One time step (Sec. 2.2, steps 1-6) of the particle set p, in place:
  * dt > 0 is used as given, dt <= 0 selects cfl * min_i h_i / c_i.
- * Synchronises once (to size the cell grid).  Mass is never modified. */
+ * Synchronises once (to size the cell grid).  Mass is never modified.  A
+ * particle of zero mass is absent: it has no radius, no ghost and no
+ * neighbours, is neither updated nor counted in dt, and is left as it is. */
 lp_status lp_step(struct lp_ctx *ctx, void *stream, const lp_particles *p, double dt);
 
 /* Advance p by nsteps CFL-limited steps or until the accumulated time reaches
@@ -300,6 +303,47 @@ lp_status lp_reservoir_inflow(struct lp_ctx *ctx, void *stream, const lp_particl
 lp_status lp_inflow_layer(struct lp_ctx *ctx, void *stream, const lp_particles *p, int64_t cap, int32_t axis,
                           int32_t side, double spacing, double depth, double rho, double p_in, double u_n,
                           int64_t *n_new);
+
+/* Open boundaries of lp_run_open (Sec. 2.2, step 1).  Outflow: after each
+ * step, every particle with x_a < box_lo[a] for a bit a of out_lo_mask or
+ * x_a >= box_hi[a] for a bit a of out_hi_mask leaves (as lp_outflow).
+ * Inflow (in_every > 0): after every in_every-th step, and after the
+ * outflow, one layer as lp_inflow_layer writes it on face (in_axis, in_side)
+ * with the given spacing and depth; its state is rho, p_in, u_n when
+ * res_width <= 0, else the reservoir state that lp_reservoir_inflow computes
+ * at that moment for the layer of width res_width inside the face, from a
+ * reservoir at rest with pressure res_p and density res_rho. */
+typedef struct lp_open_bc {
+    uint32_t out_lo_mask, out_hi_mask;  /* outflow faces, bit a: axis a */
+    int32_t in_every;                   /* 0: no inflow */
+    int32_t in_axis, in_side;           /* inflow face (side 0: box_lo, 1: box_hi) */
+    double spacing, depth;              /* layer lattice spacing, distance of its plane inside the face */
+    double rho, p_in, u_n;              /* fixed state of entering particles (res_width <= 0) */
+    double res_width, res_p, res_rho;   /* reservoir (res_width > 0) */
+} lp_open_bc;
+
+/* lp_run with open boundaries inside the steps: each step as lp_run's (the
+ * same captured graph replays, one capture for the whole run while the grid
+ * and the ghost capacity serve), followed on the device by the outflow and,
+ * on every in_every-th step, the inflow layer of *bc (host).  Deleted
+ * particles are marked with zero mass and stay in their slots until the end
+ * of the call; layers are appended after the last slot in use.  At the end
+ * every array of p is compacted as lp_outflow does: the present particles
+ * keep their order, the layers after the particles that were there before.
+ * The result equals nsteps repetitions of lp_step, lp_outflow and, every
+ * in_every-th time, lp_reservoir_inflow and lp_inflow_layer (the reservoir
+ * pressure summed in another order: equal within rounding).
+ * p->n (>= 1) is the current count; every array of p (device) must hold cap
+ * entries (cap <= 2^30), and the mass array is written: entries p->n .. cap - 1
+ * are set to zero first (those slots are absent until a layer fills them),
+ * and a particle given with zero mass is absent and removed.  *n_out (host)
+ * receives the final count (0 when every particle left; the run then stops).
+ * LP_E_ARG for a bad count, cap, mask or inflow setting (nothing written).  A
+ * layer that does not fit in cap is not written and stops the run as an
+ * error of lp_run does; lp_check then reports LP_E_CAPACITY.  The arrays are
+ * compacted, and *n_out set, also when the run itself returns an error. */
+lp_status lp_run_open(struct lp_ctx *ctx, void *stream, const lp_particles *p, int64_t cap, const lp_open_bc *bc,
+                      int32_t nsteps, double t_end, int64_t *n_out);
 
 /* Synchronise and report kernel-side errors of all work since the last
  * check (LP_E_CAPACITY / LP_E_NUMERIC), then clear them. */

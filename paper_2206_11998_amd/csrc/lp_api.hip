@@ -36,7 +36,8 @@ struct lp_ctx {
         gfd_fields, hitd2, hitj, tflags, tlo, thi, prep_part, ovfq, der, lwst, wq, rq, rkeep,
         mfeat, mrates, mphi, mflag,                          // network-estimator staging
         theta, adam_m, adam_v, mgrad, mpart, mlosspart, mscal, // network parameters and training
-        cand, ccount, xb, Rb, fovfq, octc;                   // neighbour-list reuse
+        cand, ccount, xb, Rb, fovfq, octc,                   // neighbour-list reuse
+        openres;                                             // lp_run_open: reservoir partial sums
     int search_mode = 2;            // 0: lane group walking its cells, 1: LDS-staged tiles, 2: balanced lane group
     int solve_block = 256;
     DevScalars *sc = nullptr;       // device scalars
@@ -64,6 +65,8 @@ struct lp_ctx {
     hipStream_t cap_stream = nullptr;  // private stream to capture on (the caller's may be the null stream)
     lp_particles graph_p;
     uint64_t graph_gen = 0;         // workspace generation the graph was captured against
+    int64_t n_captures = 0;         // graphs captured so far
+    const OpenDev *open = nullptr;  // set while lp_run_open runs: its boundary stage ends every step
     uint64_t gen = 1;               // bumped by every reallocation and grid change
     double grid_margin = 0.0;       // bounding-box margin of planned grids (lp_run plans with headroom)
     int solve_mode = 0;             // LP_TUNE_SOLVE_MODE
@@ -96,7 +99,8 @@ static Buf lp_ctx::*const kBufs[] = {
     &lp_ctx::tflags, &lp_ctx::tlo, &lp_ctx::thi, &lp_ctx::prep_part, &lp_ctx::ovfq, &lp_ctx::der, &lp_ctx::lwst,
     &lp_ctx::wq, &lp_ctx::rq, &lp_ctx::rkeep, &lp_ctx::mfeat, &lp_ctx::mrates, &lp_ctx::mphi, &lp_ctx::mflag,
     &lp_ctx::theta, &lp_ctx::adam_m, &lp_ctx::adam_v, &lp_ctx::mgrad, &lp_ctx::mpart, &lp_ctx::mlosspart,
-    &lp_ctx::mscal, &lp_ctx::cand, &lp_ctx::ccount, &lp_ctx::xb, &lp_ctx::Rb, &lp_ctx::fovfq, &lp_ctx::octc};
+    &lp_ctx::mscal, &lp_ctx::cand, &lp_ctx::ccount, &lp_ctx::xb, &lp_ctx::Rb, &lp_ctx::fovfq, &lp_ctx::octc,
+    &lp_ctx::openres};
 constexpr int kNumBufs = (int)(sizeof kBufs / sizeof kBufs[0]);
 
 static lp_status fail(lp_ctx *c, lp_status s, const char *fmt, ...) {
@@ -613,16 +617,17 @@ static Ghosts ghost_view(lp_ctx *c) {
 // Cell-order layout of n_total particles: keys, counting sort, level tables.
 // gate (may be NULL): the cells are rebuilt only where *gate != 0 on the device
 static void build_cells(lp_ctx *c, hipStream_t st, const double *const x[3], const double *const gx[3], int n_real,
-                        int64_t n_total, const unsigned *gate = nullptr) {
+                        int64_t n_total, const unsigned *gate = nullptr, const double *m = nullptr) {
     const int D = c->dc.D;
     const DevGrid &g = c->grid;
     uint32_t *tabs = (uint32_t *)c->tables.p;
     uint32_t *finest = tabs + g.off[g.L_hi];
     uint64_t nfin = 1ull << (D * g.L_hi);
     launch_fill_u32(finest, nfin + 1, 0u, st, gate);
-    int *n_total_dev = &c->sc->n_total;
-    launch_keys(x, gx, n_real, n_total_dev, (int)n_total, g, D, (uint32_t *)c->key.p, (uint32_t *)c->slot.p, finest,
-                st, gate);
+    // the sort reads every real slot and ghost (n_in); absent particles (zero
+    // mass, m given) go after every present one
+    launch_keys(x, gx, n_real, &c->sc->n_in, (int)n_total, g, D, (uint32_t *)c->key.p, (uint32_t *)c->slot.p,
+                finest, st, gate, m);
     launch_scan_u32(finest, nfin, (uint32_t *)c->scan_tmp.p, nullptr, st, gate);
 }
 
@@ -740,7 +745,7 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
                            (const double *)c->r.p, gh, c->cap_ghost, st);
     const double *gx[3] = {gh.x[0], gh.x[1], gh.x[2]};
     const double *x[3] = {p->x[0], p->x[1], D == 3 ? p->x[2] : p->x[1]};
-    build_cells(c, st, x, gx, n, n_total, gate);
+    build_cells(c, st, x, gx, n, n_total, gate, p->m);
     Sorted srt = sorted_view(c, true);
     ScatterArgs sa;
     memset(&sa, 0, sizeof sa);
@@ -760,7 +765,7 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
         for (int q = 0; q < LP_REC; ++q) sa.rec_src[q] = D == 3 ? r3[q] : r2[q];
     }
     const uint32_t *start = (const uint32_t *)c->tables.p + c->grid.off[c->grid.L_hi];
-    launch_scatter(sa, n, &c->sc->n_total, (int)n_total, (const uint32_t *)c->key.p, (const uint32_t *)c->slot.p, start,
+    launch_scatter(sa, n, &c->sc->n_in, (int)n_total, (const uint32_t *)c->key.p, (const uint32_t *)c->slot.p, start,
                    srt.id, st);
     launch_coarsen((uint32_t *)c->tables.p, c->grid, D, &c->sc->n_total, st, gate);
     stage_mark(c, st, 1, false);
@@ -839,6 +844,7 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
                          (const int *)c->queue.p, (const int *)c->rq.p, st);
         stage_mark(c, st, 7, false);
     }
+    if (c->open) launch_open_end(soa, c->dc, *c->open, c->sc, st);  // lp_run_open: outflow, inflow
     launch_advance_time(c->sc, st);
     HIPCHK(c, hipGetLastError());
     return LP_OK;
@@ -899,6 +905,7 @@ static lp_status graph_prepare(lp_ctx *c, const lp_particles *p) {
     }
     c->graph_gen = c->gen;
     c->graph_p = *p;
+    ++c->n_captures;
     return LP_OK;
 }
 
@@ -988,7 +995,7 @@ extern "C" lp_status lp_neighbors(lp_ctx *c, void *stream, int64_t n, const doub
     sa.src[0] = x; sa.src[1] = y; sa.src[2] = D == 3 ? z : y; sa.src[3] = r;
     sa.dst[0] = srt.x[0]; sa.dst[1] = srt.x[1]; sa.dst[2] = srt.x[2]; sa.dst[3] = srt.r;
     const uint32_t *start = (const uint32_t *)c->tables.p + c->grid.off[c->grid.L_hi];
-    launch_scatter(sa, (int)n, &c->sc->n_total, (int)n, (const uint32_t *)c->key.p, (const uint32_t *)c->slot.p, start,
+    launch_scatter(sa, (int)n, &c->sc->n_in, (int)n, (const uint32_t *)c->key.p, (const uint32_t *)c->slot.p, start,
                    srt.id, st);
     launch_coarsen((uint32_t *)c->tables.p, c->grid, D, &c->sc->n_total, st);
     int ldn = list_ldn(c);
@@ -1112,7 +1119,7 @@ static lp_status gfd_run(lp_ctx *c, void *stream, int64_t n, const double *x, co
         }
     }
     const uint32_t *start = (const uint32_t *)c->tables.p + c->grid.off[c->grid.L_hi];
-    launch_scatter(sa, (int)n, &c->sc->n_total, (int)n, (const uint32_t *)c->key.p, (const uint32_t *)c->slot.p, start,
+    launch_scatter(sa, (int)n, &c->sc->n_in, (int)n, (const uint32_t *)c->key.p, (const uint32_t *)c->slot.p, start,
                    srt.id, st);
     launch_coarsen((uint32_t *)c->tables.p, c->grid, D, &c->sc->n_total, st);
     stage_mark(c, st, 1, false);
@@ -1217,6 +1224,25 @@ extern "C" lp_status lp_reservoir_inflow(lp_ctx *c, void *stream, const lp_parti
     return LP_OK;
 }
 
+// Lattice of an inflow layer on the face of `axis`: the other axes oth[0..D-2]
+// and the points along each (whole cells of the box, a cell short by rounding
+// alone counted; 1 for an absent second axis in 2D).  False when too many.
+static bool inflow_lattice(const lp_ctx *c, int axis, double spacing, int oth[2], int64_t cnt[2], int64_t *count) {
+    const int D = c->dc.D;
+    int no = 0;
+    oth[0] = oth[1] = 0;
+    cnt[0] = cnt[1] = 1;
+    for (int b = 0; b < D; ++b)
+        if (b != axis) oth[no++] = b;
+    for (int t = 0; t < no; ++t) {
+        const double k = floor((c->dc.hi[oth[t]] - c->dc.lo[oth[t]]) / spacing + 1e-9);
+        if (!(k <= (double)((int64_t)1 << 30))) return false;
+        cnt[t] = (int64_t)k;
+    }
+    *count = cnt[0] * cnt[1];
+    return *count <= ((int64_t)1 << 30);
+}
+
 extern "C" lp_status lp_inflow_layer(lp_ctx *c, void *stream, const lp_particles *p, int64_t cap, int32_t axis,
                                      int32_t side, double spacing, double depth, double rho, double p_in, double u_n,
                                      int64_t *n_new) {
@@ -1229,16 +1255,10 @@ extern "C" lp_status lp_inflow_layer(lp_ctx *c, void *stream, const lp_particles
     for (int a = 0; a < D; ++a)
         if (!p->x[a] || !p->u[a]) return fail(c, LP_E_ARG, "lp_inflow_layer: null array");
     if (!p->V || !p->P || !p->m) return fail(c, LP_E_ARG, "lp_inflow_layer: null array");
-    int oth[2] = {0, 0}, no = 0;
-    for (int b = 0; b < D; ++b)
-        if (b != axis) oth[no++] = b;
-    int64_t cnt[2] = {1, 1};
-    for (int t = 0; t < no; ++t) {
-        const double k = floor((c->dc.hi[oth[t]] - c->dc.lo[oth[t]]) / spacing + 1e-9);
-        if (!(k <= (double)((int64_t)1 << 30))) return fail(c, LP_E_ARG, "lp_inflow_layer: spacing too small");
-        cnt[t] = (int64_t)k;
-    }
-    const int64_t count = cnt[0] * cnt[1];
+    int oth[2];
+    int64_t cnt[2], count;
+    if (!inflow_lattice(c, axis, spacing, oth, cnt, &count))
+        return fail(c, LP_E_ARG, "lp_inflow_layer: spacing too small");
     if (p->n + count > cap)
         return fail(c, LP_E_CAPACITY, "lp_inflow_layer: %lld particles after the layer, capacity %lld",
                     (long long)(p->n + count), (long long)cap);
@@ -1252,6 +1272,103 @@ extern "C" lp_status lp_inflow_layer(lp_ctx *c, void *stream, const lp_particles
                         side == 0 ? u_n : -u_n, 1.0 / rho, p_in, mass, (hipStream_t)stream);
     HIPCHK(c, hipGetLastError());
     return LP_OK;
+}
+
+extern "C" lp_status lp_run_open(lp_ctx *c, void *stream, const lp_particles *p, int64_t cap, const lp_open_bc *bc,
+                                 int32_t nsteps, double t_end, int64_t *n_out) {
+    if (!c || !p || !bc || !n_out) return LP_E_ARG;
+    const int D = c->dc.D;
+    if (p->n < 1 || cap < p->n || cap > ((int64_t)1 << 30)) return fail(c, LP_E_ARG, "lp_run_open: bad n or cap");
+    if (nsteps < 0) return fail(c, LP_E_ARG, "nsteps < 0");
+    const uint32_t faces = (1u << D) - 1u;
+    if ((bc->out_lo_mask & ~faces) || (bc->out_hi_mask & ~faces))
+        return fail(c, LP_E_ARG, "lp_run_open: outflow mask names an axis past the dimension");
+    lp_particles q = *p;
+    q.n = cap;
+    lp_status s = check_particles(c, &q);
+    if (s != LP_OK) return s;
+    OpenDev o;
+    memset(&o, 0, sizeof o);
+    o.lo_mask = bc->out_lo_mask;
+    o.hi_mask = bc->out_hi_mask;
+    o.cap = cap;
+    o.res_blocks = 256;
+    if (bc->in_every > 0) {
+        const bool res = bc->res_width > 0.0;
+        if (bc->in_axis < 0 || bc->in_axis >= D || bc->in_side < 0 || bc->in_side > 1 || !(bc->spacing > 0.0) ||
+            !(bc->depth >= 0.0) ||
+            (res ? !(bc->res_p > 0.0) || !(bc->res_rho > 0.0)
+                 : !(bc->rho > 0.0) || !(bc->p_in > 0.0) || !isfinite(bc->u_n)))
+            return fail(c, LP_E_ARG, "lp_run_open: bad inflow face, spacing, depth or state");
+        int oth[2];
+        int64_t cnt[2];
+        if (!inflow_lattice(c, bc->in_axis, bc->spacing, oth, cnt, &o.count))
+            return fail(c, LP_E_ARG, "lp_run_open: spacing too small");
+        o.in_every = bc->in_every;
+        o.axis = bc->in_axis;
+        o.side = bc->in_side;
+        o.o0 = oth[0];
+        o.o1 = oth[1];
+        o.cnt0 = cnt[0];
+        o.spacing = bc->spacing;
+        o.xa = bc->in_side == 0 ? c->dc.lo[o.axis] + bc->depth : c->dc.hi[o.axis] - bc->depth;
+        if (res) {
+            o.res_width = bc->res_width;
+            o.res_face = bc->in_side == 0 ? c->dc.lo[o.axis] : c->dc.hi[o.axis];
+            o.res_p = bc->res_p;
+            o.res_rho = bc->res_rho;
+            o.gamma = c->dc.gamma;
+        } else {
+            // as lp_inflow_layer rounds them
+            o.un = bc->in_side == 0 ? bc->u_n : -bc->u_n;
+            o.V = 1.0 / bc->rho;
+            o.P = bc->p_in;
+            double mass = bc->rho;
+            for (int a = 0; a < D; ++a) mass = mass * bc->spacing;
+            o.mass = mass;
+        }
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (o.res_width > 0.0) {
+        ENSURE(c, c->openres, sizeof(double) * (2 * o.res_blocks + 4));
+        o.res_part = (double *)c->openres.p;
+    }
+    // the slots past p->n are absent until a layer fills them
+    if (cap > p->n) launch_fill_u32((uint32_t *)(p->m + p->n), 2 * (uint64_t)(cap - p->n), 0u, st);
+    if ((s = read_scalars(c, st)) != LP_OK) return s;
+    c->sc_host->n_hw = (int)p->n;
+    c->sc_host->open_k = 0ull;
+    c->sc_host->insert_now = 0u;
+    c->sc_host->pop_changed = 1u;  // lists built for other particles do not serve
+    HIPCHK(c, hipMemcpyAsync(c->sc, c->sc_host, sizeof(DevScalars), hipMemcpyHostToDevice, st));
+    // a graph of plain steps must not serve, nor this one outlive the call
+    ++c->gen;
+    c->open = &o;
+    const lp_status s_run = lp_run(c, stream, &q, nsteps, t_end);
+    c->open = nullptr;
+    ++c->gen;
+    // compaction of the slots in use (also after a failed run): present
+    // particles keep their order
+    if ((s = read_scalars(c, st)) != LP_OK) return s_run != LP_OK ? s_run : s;
+    const int64_t n = c->sc_host->n_hw;
+    ENSURE(c, c->gcnt, sizeof(uint32_t) * (n + 1));
+    ENSURE(c, c->scan_tmp, sizeof(uint32_t) * scan_tmp_words((uint64_t)n));
+    ENSURE(c, c->gfd_fields, out_stage_bytes(D, n));
+    lp_particles r = q;
+    r.n = n;
+    uint32_t *pos = (uint32_t *)c->gcnt.p;
+    launch_alive_keep(soa_of(&r), pos, st);
+    launch_scan_u32(pos, (uint64_t)n, (uint32_t *)c->scan_tmp.p, nullptr, st);
+    uint32_t kept = 0;
+    HIPCHK(c, hipMemcpyAsync(&kept, pos + n, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if ((int64_t)kept < n) {
+        launch_out_compact(soa_of(&r), D, pos, kept, (double *)c->gfd_fields.p, st);
+        HIPCHK(c, hipGetLastError());
+    }
+    *n_out = kept;
+    return s_run;
 }
 
 extern "C" lp_status lp_check(lp_ctx *c, void *stream) {
@@ -1268,6 +1385,7 @@ extern "C" lp_status lp_check(lp_ctx *c, void *stream) {
     }
     if (bits & 1u) return fail(c, LP_E_CAPACITY, "a neighbour list exceeded max_nb = %d", c->dc.max_nb);
     if (bits & 2u) return fail(c, LP_E_NUMERIC, "non-positive V or P after an update");
+    if (bits & 4u) return fail(c, LP_E_CAPACITY, "lp_run_open: an inflow layer did not fit in cap");
     return LP_OK;
 }
 
@@ -1291,6 +1409,7 @@ extern "C" lp_status lp_get_info(lp_ctx *c, void *stream, lp_info *out) {
     out->n_mlp_plain = (int64_t)c->sc_host->n_mlp_plain;
     out->n_refined = c->sc_host->n_refine;
     out->n_list_builds = (int64_t)c->sc_host->n_builds;
+    out->n_captures = c->n_captures;
     return LP_OK;
 }
 

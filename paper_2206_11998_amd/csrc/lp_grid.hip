@@ -21,6 +21,8 @@ static inline unsigned blocks_for(uint64_t n, int per = LP_BLOCK) {
 // ---------------------------------------------------------------------------
 __global__ void k_reset_scalars(DevScalars *sc, double dt_in, int n_real, int clear_halt) {
     sc->n_total = n_real;
+    sc->n_in = n_real;
+    sc->n_dead = 0;
     sc->min_hc = 0x7ff0000000000000ull;  // +inf
     sc->rmax = 0ull;
     sc->rmin = 0x7ff0000000000000ull;
@@ -55,9 +57,11 @@ __global__ void k_gate(DevScalars *sc, int n_real, long long cap_ghost, int stop
     if (sc->n_ghost > cap_ghost) sc->halt = 1u;
     if (sc->done || sc->halt || (stop_on_error && sc->error_bits)) {
         sc->n_total = 0;
+        sc->n_in = 0;  // nothing sorted either (the ghost count may exceed the arrays)
         sc->dt = 0.0;
     } else {
-        sc->n_total = n_real + sc->n_ghost;
+        sc->n_in = n_real + sc->n_ghost;
+        sc->n_total = n_real - sc->n_dead + sc->n_ghost;  // absent particles sort after every other
     }
 }
 
@@ -75,14 +79,22 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Per-block minima of (h/c, r, -r, x_a, -x_a) written to part[block * 9 + q];
-// k_prep_final folds the block results (order-free min, so exact).
+// Per-block minima of (h/c, r, -r, x_a, -x_a) written to part[block * PREP_W + q],
+// then the block's count of absent particles (zero mass: no radius, no part in
+// the minima); k_prep_final folds the block results (order-free min and an
+// integer count, so exact).
 #define PREP_Q 9
+#define PREP_W (PREP_Q + 1)
 __global__ void k_prep(Soa p, DevCfg cfg, double *h_out, double *r_out, double *part) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     double v[PREP_Q];
     for (int q = 0; q < PREP_Q; ++q) v[q] = INFINITY;
-    if (i < p.n) {
+    int dead = 0;
+    if (i < p.n && !(p.m[i] > 0.0)) {
+        h_out[i] = 0.0;
+        r_out[i] = 0.0;
+        dead = 1;
+    } else if (i < p.n) {
         double V = p.V[i], P = p.P[i], m = p.m[i];
         double mv = m * V;
         double h = cfg.D == 3 ? cbrt(mv) : sqrt(mv);
@@ -100,30 +112,46 @@ __global__ void k_prep(Soa p, DevCfg cfg, double *h_out, double *r_out, double *
         }
     }
     __shared__ double red[PREP_Q][LP_BLOCK / 64];
+    __shared__ int dred[LP_BLOCK / 64];
     for (int q = 0; q < PREP_Q; ++q) {
         double w = wave_min(v[q]);
         if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = w;
     }
+    for (int o = 32; o > 0; o >>= 1) dead += __shfl_xor(dead, o);
+    if ((threadIdx.x & 63) == 0) dred[threadIdx.x >> 6] = dead;
     __syncthreads();
     if (threadIdx.x < PREP_Q) {
         double w = red[threadIdx.x][0];
         for (int k = 1; k < LP_BLOCK / 64; ++k) w = fmin(w, red[threadIdx.x][k]);
-        part[(int64_t)blockIdx.x * PREP_Q + threadIdx.x] = w;
+        part[(int64_t)blockIdx.x * PREP_W + threadIdx.x] = w;
+    } else if (threadIdx.x == PREP_Q) {
+        int d = 0;
+        for (int k = 0; k < LP_BLOCK / 64; ++k) d += dred[k];
+        part[(int64_t)blockIdx.x * PREP_W + PREP_Q] = (double)d;
     }
 }
 
 __global__ void k_prep_final(const double *part, int nblocks, DevScalars *sc) {
     __shared__ double red[PREP_Q][1024 / 64];
+    __shared__ double dred[1024 / 64];
     double v[PREP_Q];
+    double dead = 0.0;  // integer-valued: exact in any order
     for (int q = 0; q < PREP_Q; ++q) v[q] = INFINITY;
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
-        for (int q = 0; q < PREP_Q; ++q) v[q] = fmin(v[q], part[(int64_t)b * PREP_Q + q]);
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+        for (int q = 0; q < PREP_Q; ++q) v[q] = fmin(v[q], part[(int64_t)b * PREP_W + q]);
+        dead += part[(int64_t)b * PREP_W + PREP_Q];
+    }
     for (int q = 0; q < PREP_Q; ++q) {
         double w = wave_min(v[q]);
         if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = w;
     }
+    for (int o = 32; o > 0; o >>= 1) dead += __shfl_xor(dead, o);
+    if ((threadIdx.x & 63) == 0) dred[threadIdx.x >> 6] = dead;
     __syncthreads();
     if (threadIdx.x == 0) {
+        double d = 0.0;
+        for (int k = 0; k < (int)(blockDim.x / 64); ++k) d += dred[k];
+        sc->n_dead = (int)d;
         double m[PREP_Q];
         for (int q = 0; q < PREP_Q; ++q) {
             m[q] = red[q][0];
@@ -148,13 +176,18 @@ void launch_prep(const Soa &p, const DevCfg &cfg, DevScalars *sc, double *h, dou
     CHECK_LAUNCH();
 }
 
-size_t prep_partial_words(int64_t n) { return (size_t)((n + LP_BLOCK - 1) / LP_BLOCK + 1) * PREP_Q; }
+size_t prep_partial_words(int64_t n) { return (size_t)((n + LP_BLOCK - 1) / LP_BLOCK + 1) * PREP_W; }
 
 // dt = cfl * min h/c unless given; with clip, the step is shortened so that t
 // does not pass t_end (and set to zero once t_end is reached).
 __global__ void k_dt(DevCfg cfg, DevScalars *sc, int clip) {
     double dt = sc->dt_in > 0.0 ? sc->dt_in : cfg.cfl * bits_dbl(sc->min_hc);
     sc->clipped = 0u;
+    if (sc->n_dead >= sc->n_total) {  // every particle absent (n_total holds the real count here)
+        sc->dt = 0.0;
+        sc->done = 1u;
+        return;
+    }
     if (clip && sc->t_end > 0.0) {
         double rem = sc->t_end - sc->t;
         if (!(rem > 0.0)) { dt = 0.0; sc->done = 1u; }
@@ -253,7 +286,7 @@ __global__ void k_ghost_count(Soa p, DevCfg cfg, DevScalars *sc, uint32_t *gcnt)
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p.n) return;
     double rmax = bits_dbl(sc->rmax);
-    gcnt[i] = (uint32_t)ghost_walls(cfg, p, i, rmax, nullptr);
+    gcnt[i] = p.m[i] > 0.0 ? (uint32_t)ghost_walls(cfg, p, i, rmax, nullptr) : 0u;  // absent: no ghost
 }
 
 void launch_ghost_count(const Soa &p, const DevCfg &cfg, DevScalars *sc, uint32_t *gcnt, hipStream_t st) {
@@ -318,31 +351,38 @@ void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st, const 
 template <int D>
 __global__ void k_keys(const double *x0, const double *x1, const double *x2, const double *g0, const double *g1,
                        const double *g2, int n_real, const int *n_total_dev, DevGrid g, uint32_t *key,
-                       uint32_t *slot, uint32_t *cnt, const unsigned *gate) {
+                       uint32_t *slot, uint32_t *cnt, const unsigned *gate, const double *m) {
     if (gate && *gate == 0u) return;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int n_total = *n_total_dev;
     if (i >= n_total) return;
-    double p[3];
-    if (i < n_real) { p[0] = x0[i]; p[1] = x1[i]; p[2] = D == 3 ? x2[i] : 0.0; }
-    else { int q = i - n_real; p[0] = g0[q]; p[1] = g1[q]; p[2] = D == 3 ? g2[q] : 0.0; }
-    int c[3] = {0, 0, 0};
-    for (int a = 0; a < D; ++a) c[a] = cell_coord(g, g.L_hi, a, p[a]);
-    uint32_t k = morton<D>(c);
+    uint32_t k;
+    if (m && i < n_real && !(m[i] > 0.0)) {
+        // absent: the bucket past the last finest cell, whose start the scan
+        // sets to the number of present particles
+        k = (uint32_t)(1ull << (D * g.L_hi));
+    } else {
+        double p[3];
+        if (i < n_real) { p[0] = x0[i]; p[1] = x1[i]; p[2] = D == 3 ? x2[i] : 0.0; }
+        else { int q = i - n_real; p[0] = g0[q]; p[1] = g1[q]; p[2] = D == 3 ? g2[q] : 0.0; }
+        int c[3] = {0, 0, 0};
+        for (int a = 0; a < D; ++a) c[a] = cell_coord(g, g.L_hi, a, p[a]);
+        k = morton<D>(c);
+    }
     key[i] = k;
     slot[i] = atomicAdd(&cnt[k], 1u);
 }
 
 void launch_keys(const double *const x[3], const double *const gx[3], int n_real, const int *n_total_dev,
                  int n_total_cap, const DevGrid &g, int D, uint32_t *key, uint32_t *slot, uint32_t *cnt,
-                 hipStream_t st, const unsigned *gate) {
+                 hipStream_t st, const unsigned *gate, const double *m) {
     dim3 grid(blocks_for(n_total_cap));
     if (D == 3)
         hipLaunchKernelGGL(k_keys<3>, grid, dim3(LP_BLOCK), 0, st, x[0], x[1], x[2], gx[0], gx[1], gx[2], n_real,
-                           n_total_dev, g, key, slot, cnt, gate);
+                           n_total_dev, g, key, slot, cnt, gate, m);
     else
         hipLaunchKernelGGL(k_keys<2>, grid, dim3(LP_BLOCK), 0, st, x[0], x[1], x[1], gx[0], gx[1], gx[1], n_real,
-                           n_total_dev, g, key, slot, cnt, gate);
+                           n_total_dev, g, key, slot, cnt, gate, m);
     CHECK_LAUNCH();
 }
 
@@ -559,6 +599,7 @@ __global__ __launch_bounds__(LP_BLOCK) void k_reuse_check(Soa p, DevCfg cfg, con
     double a = -INFINITY, d = 0.0;
     const double *xb[3] = {xb0, xb1, xb2};
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < p.n; i += gridDim.x * blockDim.x) {
+        if (!(p.m[i] > 0.0)) continue;  // absent
         double d2 = 0.0;
         for (int q = 0; q < cfg.D; ++q) {
             const double e = min_image(cfg, q, p.x[q][i] - xb[q][i]);
@@ -585,7 +626,7 @@ __global__ __launch_bounds__(LP_BLOCK) void k_reuse_check(Soa p, DevCfg cfg, con
 __global__ void k_reuse_decide(DevScalars *sc, int force) {
     unsigned rb = 0u;
     if (sc->n_total > 0) {
-        if (force || !sc->have_cand || sc->cand_short) rb = 1u;
+        if (force || !sc->have_cand || sc->cand_short || sc->pop_changed) rb = 1u;
         else {
             const unsigned long long ka = sc->reuse_a;
             const double a = (ka >> 63) ? bits_dbl(ka & 0x7fffffffffffffffull) : bits_dbl(~ka);
@@ -595,6 +636,7 @@ __global__ void k_reuse_decide(DevScalars *sc, int force) {
         }
     }
     sc->rebuild = rb;
+    if (sc->n_total > 0) sc->pop_changed = 0u;  // the cells of this step see the particles as they are
     if (rb) {
         sc->have_cand = 1u;
         sc->n_builds += 1ull;
@@ -802,12 +844,14 @@ void launch_inflow_layer(const Soa &p, const DevCfg &cfg, int64_t n0, int64_t co
 // count of the particles at distance 0 <= d < width inside the face, in a
 // fixed order (grid-stride per thread, then the wave, then the block's waves)
 __global__ __launch_bounds__(LP_BLOCK) void k_res_partial(const double *xa, const double *P, int n, int side,
-                                                         double face, double width, double *part) {
+                                                         double face, double width, double *part,
+                                                         const double *m, const unsigned *gate) {
+    if (gate && *gate == 0u) return;
     __shared__ double red[2][LP_BLOCK / 64];
     double sum = 0.0, cnt = 0.0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const double d = side == 0 ? xa[i] - face : face - xa[i];
-        if (d >= 0.0 && d < width) {
+        if (d >= 0.0 && d < width && (!m || m[i] > 0.0)) {  // m: absent particles do not count
             sum += P[i];
             cnt += 1.0;
         }
@@ -837,7 +881,8 @@ __global__ __launch_bounds__(LP_BLOCK) void k_res_partial(const double *xa, cons
 // (the reservoir's with an empty layer), the density of equal entropy and
 // the speed of equal enthalpy with the reservoir at rest
 __global__ void k_res_final(const double *part, int nblocks, double p_res, double rho_res, double gamma,
-                            double *out) {
+                            double *out, const unsigned *gate) {
+    if (gate && *gate == 0u) return;
     double sum = 0.0, cnt = 0.0;
     for (int b = 0; b < nblocks; ++b) {
         sum += part[2 * b];
@@ -855,7 +900,123 @@ __global__ void k_res_final(const double *part, int nblocks, double p_res, doubl
 
 void launch_reservoir(const double *xa, const double *P, int n, int side, double face, double width, double p_res,
                       double rho_res, double gamma, double *part, int nblocks, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_res_partial, dim3(nblocks), dim3(LP_BLOCK), 0, st, xa, P, n, side, face, width, part);
-    hipLaunchKernelGGL(k_res_final, dim3(1), dim3(1), 0, st, part, nblocks, p_res, rho_res, gamma, out);
+    hipLaunchKernelGGL(k_res_partial, dim3(nblocks), dim3(LP_BLOCK), 0, st, xa, P, n, side, face, width, part,
+                       (const double *)nullptr, (const unsigned *)nullptr);
+    hipLaunchKernelGGL(k_res_final, dim3(1), dim3(1), 0, st, part, nblocks, p_res, rho_res, gamma, out,
+                       (const unsigned *)nullptr);
+    CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------------------
+// Open boundaries inside the steps of lp_run_open (Sec. 2.2, step 1).  A
+// particle of zero mass is absent: no radius, no ghost, sorted after every
+// present particle, never updated.  At the end of a step that ran (n_total >
+// 0): every present particle past an outflow face gets mass 0; the step is
+// counted; after every in_every-th step one inflow layer is written at slot
+// n_hw (the state fixed, or the reservoir state of the layer inside the face
+// as lp_reservoir_inflow computes it) and n_hw advances.  Any deletion or
+// layer raises pop_changed, which makes the next step rebuild its lists.
+// ---------------------------------------------------------------------------
+__global__ void k_open_outflow(Soa p, DevCfg cfg, OpenDev o, DevScalars *sc) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sc->n_total > 0 && i < p.n && p.m[i] > 0.0) {
+        bool gone = false;
+        for (int a = 0; a < cfg.D; ++a) {
+            const double xa = p.x[a][i];
+            if (((o.lo_mask >> a) & 1u) && xa < cfg.lo[a]) gone = true;
+            if (((o.hi_mask >> a) & 1u) && xa >= cfg.hi[a]) gone = true;
+        }
+        if (gone) {
+            const_cast<double *>(p.m)[i] = 0.0;
+            any = 1;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && any) atomicOr(&sc->pop_changed, 1u);
+}
+
+__global__ void k_open_tick(DevScalars *sc, int every) {
+    if (sc->n_total == 0) {  // skipped step: nothing ran, nothing to add
+        sc->insert_now = 0u;
+        return;
+    }
+    sc->open_k += 1ull;
+    sc->insert_now = (every > 0 && sc->open_k % (unsigned long long)every == 0ull) ? 1u : 0u;
+}
+
+// lattice point q of the layer at slot n_hw + q, with the state given or from
+// the reservoir outputs: the same rounding as k_inflow_layer and lp_inflow_layer
+__global__ void k_open_inflow(Soa p, DevCfg cfg, OpenDev o, DevScalars *sc) {
+#pragma clang fp contract(off)
+    if (!sc->insert_now) return;
+    const int64_t n0 = sc->n_hw;
+    if (n0 + o.count > o.cap) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&sc->error_bits, 4u);
+        return;
+    }
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= o.count) return;
+    double un = o.un, V = o.V, P = o.P, mass = o.mass;
+    if (o.res_width > 0.0) {
+        const double *out = o.res_part + 2 * o.res_blocks;
+        const double rho = out[1];
+        P = out[0];
+        V = 1.0 / rho;
+        un = o.side == 0 ? out[2] : -out[2];
+        mass = rho;
+        for (int a = 0; a < cfg.D; ++a) mass = mass * o.spacing;
+    }
+    const int64_t i = n0 + q;
+    const int64_t k[2] = {q % o.cnt0, q / o.cnt0};
+    const int oth[2] = {o.o0, o.o1};
+    for (int a = 0; a < cfg.D; ++a) p.u[a][i] = 0.0;
+    p.x[o.axis][i] = o.xa;
+    p.u[o.axis][i] = un;
+    for (int t = 0; t < cfg.D - 1; ++t) {
+        const double off = ((double)k[t] + 0.5) * o.spacing;
+        p.x[oth[t]][i] = cfg.lo[oth[t]] + off;
+    }
+    p.V[i] = V;
+    p.P[i] = P;
+    const_cast<double *>(p.m)[i] = mass;
+    if (p.phi) p.phi[i] = 1.0f;
+    if (p.flags) p.flags[i] = 0;
+}
+
+__global__ void k_open_commit(OpenDev o, DevScalars *sc) {
+    if (sc->insert_now && sc->n_hw + o.count <= o.cap) {
+        sc->n_hw += (int)o.count;
+        if (o.count > 0) sc->pop_changed = 1u;
+    }
+}
+
+void launch_open_end(const Soa &p, const DevCfg &cfg, const OpenDev &o, DevScalars *sc, hipStream_t st) {
+    hipLaunchKernelGGL(k_open_outflow, dim3(blocks_for(p.n)), dim3(LP_BLOCK), 0, st, p, cfg, o, sc);
+    hipLaunchKernelGGL(k_open_tick, dim3(1), dim3(1), 0, st, sc, o.in_every);
+    if (o.in_every > 0 && o.count > 0) {
+        if (o.res_width > 0.0) {
+            const unsigned *gate = &sc->insert_now;
+            hipLaunchKernelGGL(k_res_partial, dim3(o.res_blocks), dim3(LP_BLOCK), 0, st, (const double *)p.x[o.axis],
+                               (const double *)p.P, p.n, o.side, o.res_face, o.res_width, o.res_part, p.m, gate);
+            hipLaunchKernelGGL(k_res_final, dim3(1), dim3(1), 0, st, (const double *)o.res_part, o.res_blocks,
+                               o.res_p, o.res_rho, o.gamma, o.res_part + 2 * o.res_blocks, gate);
+        }
+        const int64_t nb = (o.count + LP_BLOCK - 1) / LP_BLOCK;
+        hipLaunchKernelGGL(k_open_inflow, dim3((unsigned)nb), dim3(LP_BLOCK), 0, st, p, cfg, o, sc);
+        hipLaunchKernelGGL(k_open_commit, dim3(1), dim3(1), 0, st, o, sc);
+    }
+    CHECK_LAUNCH();
+}
+
+__global__ void k_alive_keep(Soa p, uint32_t *keep) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < p.n) keep[i] = p.m[i] > 0.0 ? 1u : 0u;
+}
+
+void launch_alive_keep(const Soa &p, uint32_t *keep, hipStream_t st) {
+    hipLaunchKernelGGL(k_alive_keep, dim3(blocks_for(p.n)), dim3(LP_BLOCK), 0, st, p, keep);
     CHECK_LAUNCH();
 }

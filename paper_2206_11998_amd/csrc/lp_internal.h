@@ -71,6 +71,27 @@ struct DevScalars {
     unsigned long long reuse_d;     // bits of max_i d_i
     unsigned long long n_builds;    // rebuilds so far
     unsigned int cand_short;        // the last rebuild found more candidates than max_nb for some particle
+    // particles of zero mass are absent (lp_run_open: deleted, or slots not yet filled)
+    int n_in;                       // real slots + ghosts: the extent the cell sort reads
+    int n_dead;                     // real slots of zero mass (k_prep); n_total = n_in - n_dead
+    int n_hw;                       // lp_run_open: slots in use (live or deleted); layers are appended here
+    unsigned int pop_changed;       // a particle was deleted or added since the last list build
+    unsigned long long open_k;      // lp_run_open: steps run
+    unsigned int insert_now;        // lp_run_open: this step ends with an inflow layer
+};
+
+// Open boundaries inside the steps of lp_run_open (device copy of the setup).
+struct OpenDev {
+    uint32_t lo_mask, hi_mask;      // outflow faces
+    int in_every;                   // a layer after every in_every-th step (0: no inflow)
+    int axis, side, o0, o1;         // inflow face and the other axes
+    int64_t count, cnt0;            // lattice points of a layer, along the first other axis
+    int64_t cap;                    // slots of the caller's arrays
+    double spacing, xa;             // lattice spacing, position of the layer's plane
+    double un, V, P, mass;          // fixed state of the entering particles (res_width <= 0)
+    double res_width, res_face, res_p, res_rho, gamma;  // res_width > 0: reservoir state at each layer
+    double *res_part;               // res_blocks x 2 partial sums, then 4 outputs (P_in, rho_in, u_in, count)
+    int res_blocks;
 };
 
 // Particle state in the caller's order (real particles only).
@@ -174,9 +195,11 @@ void launch_ghost_write(const Soa &p, const DevCfg &cfg, DevScalars *sc, const u
                         const double *h, const double *r, Ghosts g, int64_t cap_ghost, hipStream_t st);
 // gate (may be NULL): the kernels do nothing unless *gate != 0 (read on the device)
 void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st, const unsigned *gate = nullptr);
+// m (may be NULL): a real particle of zero mass is absent and goes to the bucket
+// past the last finest cell, i.e. after every present particle of the sort
 void launch_keys(const double *const x[3], const double *const gx[3], int n_real, const int *n_total_dev,
                  int n_total_cap, const DevGrid &g, int D, uint32_t *key, uint32_t *slot, uint32_t *cnt,
-                 hipStream_t st, const unsigned *gate = nullptr);
+                 hipStream_t st, const unsigned *gate = nullptr, const double *m = nullptr);
 // exclusive scan of n u32 values in place; out[n] receives the total; tmp needs scan_tmp_words(n)
 uint64_t scan_tmp_words(uint64_t n);
 void launch_scan_u32(uint32_t *data, uint64_t n, uint32_t *tmp, int *total_dev, hipStream_t st,
@@ -212,6 +235,11 @@ void launch_filter(const Sorted &s, const int *n_total_dev, int n_total_cap, int
 // the positions and r * rscale of every particle
 void launch_reuse(const Soa &p, const DevCfg &cfg, const double *r, double *const xb[3], double *Rb, int n,
                   double rscale, int force, DevScalars *sc, hipStream_t st);
+// end of a step of lp_run_open: outflow deletion (mass set to zero), the step
+// count, and on every in_every-th step an inflow layer appended at n_hw
+void launch_open_end(const Soa &p, const DevCfg &cfg, const OpenDev &o, DevScalars *sc, hipStream_t st);
+// keep[i] = 1 for a particle of positive mass in slots 0 .. n - 1
+void launch_alive_keep(const Soa &p, uint32_t *keep, hipStream_t st);
 void launch_search_tiles(const Sorted &s, const int *n_total_dev, int n_total_cap, int n_real,
                          const uint32_t *tables, const DevGrid &g, const DevCfg &cfg, double *hit_d2, int *hit_j,
                          int *nbr, int ldn, int *count, DevScalars *sc, const uint32_t *key, uint32_t *flags,

@@ -21,7 +21,7 @@ FLAG_LIMITED, FLAG_DEGENERATE, FLAG_VACUUM, FLAG_SUBSTITUTED, FLAG_FALLBACK, FLA
 
 EXPORTS = ["lp_config_default", "lp_create", "lp_destroy", "lp_workspace_bytes", "lp_set_workspace", "lp_neighbors",
            "lp_neighbors_noalloc", "lp_gfd", "lp_gfd3", "lp_outflow",
-           "lp_reservoir_inflow", "lp_inflow_layer", "lp_step", "lp_run",
+           "lp_reservoir_inflow", "lp_inflow_layer", "lp_step", "lp_run", "lp_run_open",
            "lp_conservation", "lp_check", "lp_get_info", "lp_set_time", "lp_profile", "lp_profile_read",
            "lp_set_tuning", "lp_get_tuning", "lp_autotune", "lp_train_cfg_default", "lp_features", "lp_mlp_init",
            "lp_mlp_set", "lp_mlp_get", "lp_mlp_forward", "lp_mlp_grad", "lp_mlp_train", "lp_status_str",
@@ -73,6 +73,16 @@ class Info(C.Structure):
         ("t", C.c_double), ("dt", C.c_double), ("n_ghost", C.c_int64), ("max_count", C.c_int32),
         ("n_fallback", C.c_int32), ("n_limited", C.c_int64), ("error_bits", C.c_uint32), ("levels", C.c_int32 * 2),
         ("n_mlp", C.c_int64), ("n_mlp_plain", C.c_int64), ("n_refined", C.c_int64), ("n_list_builds", C.c_int64),
+        ("n_captures", C.c_int64),
+    ]
+
+
+class OpenBC(C.Structure):
+    _fields_ = [
+        ("out_lo_mask", C.c_uint32), ("out_hi_mask", C.c_uint32), ("in_every", C.c_int32), ("in_axis", C.c_int32),
+        ("in_side", C.c_int32), ("spacing", C.c_double), ("depth", C.c_double), ("rho", C.c_double),
+        ("p_in", C.c_double), ("u_n", C.c_double), ("res_width", C.c_double), ("res_p", C.c_double),
+        ("res_rho", C.c_double),
     ]
 
 
@@ -117,6 +127,9 @@ def lib():
         L.lp_step.argtypes = [vp, vp, C.POINTER(Particles), dbl]
         L.lp_run.restype = i32
         L.lp_run.argtypes = [vp, vp, C.POINTER(Particles), i32, dbl]
+        L.lp_run_open.restype = i32
+        L.lp_run_open.argtypes = [vp, vp, C.POINTER(Particles), i64, C.POINTER(OpenBC), i32, dbl,
+                                  C.POINTER(C.c_int64)]
         L.lp_conservation.restype = i32
         L.lp_conservation.argtypes = [vp, vp, C.POINTER(Particles), C.POINTER(C.c_double)]
         L.lp_check.restype = i32
@@ -381,6 +394,24 @@ class Context:
         p = self._particles(s)
         self._raise(lib().lp_run(self._h, _stream_ptr(stream), C.byref(p), int(nsteps), float(t_end)))
 
+    def run_open(self, s: dict, n: int, nsteps: int, t_end: float = 0.0, out_lo_mask: int = 0, out_hi_mask: int = 0,
+                 in_every: int = 0, in_axis: int = 0, in_side: int = 0, spacing: float = 0.0, depth: float = 0.0,
+                 rho: float = 0.0, p_in: float = 0.0, u_n: float = 0.0, res_width: float = 0.0, res_p: float = 0.0,
+                 res_rho: float = 0.0, stream=None) -> int:
+        """lp_run with outflow faces and a periodic inflow layer inside the
+        steps; the first n entries of s are the particles, its arrays the
+        capacity.  Returns the count after the run (the arrays compacted)."""
+        p = self._particles(s)
+        cap = p.n
+        p.n = int(n)
+        bc = OpenBC(int(out_lo_mask), int(out_hi_mask), int(in_every), int(in_axis), int(in_side), float(spacing),
+                    float(depth), float(rho), float(p_in), float(u_n), float(res_width), float(res_p),
+                    float(res_rho))
+        n_out = C.c_int64(0)
+        self._raise(lib().lp_run_open(self._h, _stream_ptr(stream), C.byref(p), cap, C.byref(bc), int(nsteps),
+                                      float(t_end), C.byref(n_out)))
+        return n_out.value
+
     def conservation(self, s: dict, stream=None):
         p = self._particles(s)
         out = (C.c_double * 5)()
@@ -396,7 +427,7 @@ class Context:
         return {"t": inf.t, "dt": inf.dt, "n_ghost": inf.n_ghost, "max_count": inf.max_count,
                 "n_fallback": inf.n_fallback, "n_limited": inf.n_limited, "error_bits": inf.error_bits,
                 "levels": (inf.levels[0], inf.levels[1]), "n_mlp": inf.n_mlp, "n_mlp_plain": inf.n_mlp_plain,
-                "n_refined": inf.n_refined, "n_list_builds": inf.n_list_builds}
+                "n_refined": inf.n_refined, "n_list_builds": inf.n_list_builds, "n_captures": inf.n_captures}
 
     def set_time(self, t: float, stream=None):
         self._raise(lib().lp_set_time(self._h, _stream_ptr(stream), float(t)))

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2206_11998_amd import workloads as W
-from tests.gpu_util import say
+from tests.gpu_util import compare_states, say
 from tests.test_oracle_openbc import _cloud
 
 torch = pytest.importorskip("torch")
@@ -234,4 +234,141 @@ def test_outflow_and_inflow_layer_without_phi_and_flags(lp, oracle_lib, dim):
     for a in range(dim):
         assert np.array_equal(dev["x"][a][kept:n_new].cpu().numpy(), lay["x"][:, a])
         assert np.array_equal(dev["u"][a][kept:n_new].cpu().numpy(), lay["u"][:, a])
+    ctx.close()
+
+
+def _channel(n=32, u0=1.0, seed=5):
+    """2D channel, x open on both sides (no walls, free-surface treatment), y
+    periodic: a jittered n x n lattice of h = 1/n in uniform flow u0 along x
+    with a pressure pulse.  At u0 = 1 a column moves about h every two
+    steps, so a layer every second step at half a spacing inside the face
+    finds room."""
+    h = 1.0 / n
+    x, _ = W.jittered_lattice((n, n), h, 0.15, seed)
+    rho = np.ones(x.shape[0])
+    p = 1.0 + 0.1 * np.exp(-((x - 0.5) ** 2).sum(axis=1) / 0.02)
+    u = np.zeros_like(x)
+    u[:, 0] = u0
+    cfg = W.base_config("channel2d", 2, 2.5, [0.0, 0.0], [1.0, 1.0], [False, True], vacuum=True)
+    st = {"x": x, "u": u, "V": 1.0 / rho, "P": p, "m": rho * h * h}
+    return cfg, st, h
+
+
+def _oracle_open(oracle_lib, cfg, st, nsteps, lo_mask, hi_mask, every=0, axis=0, side=0, spacing=0.0, depth=0.0,
+                 rho=0.0, p_in=0.0, u_n=0.0, res=None):
+    """The oracle's sequence: each step, then the outflow, then on every
+    every-th step the inflow layer (fixed state, or res = (width, p_res,
+    rho_res): the reservoir state of that moment)."""
+    ref = {k: st[k].copy() for k in ("x", "u", "V", "P", "m")}
+    layers = 0
+    for k in range(1, nsteps + 1):
+        ref, info = oracle_lib.step(cfg, ref)
+        assert info["status"] == 0
+        ref = oracle_lib.outflow(cfg, ref, lo_mask, hi_mask)
+        if every and k % every == 0:
+            if res is not None:
+                out, rs = oracle_lib.reservoir_inflow(cfg, ref, axis, side, res[0], res[1], res[2])
+                assert rs == 0
+                p_in, rho, u_n = (float(v) for v in out[:3])
+            n = len(ref["V"])
+            lay, n_new, rs = oracle_lib.inflow_layer(cfg, n, n + 100000, axis, side, spacing, depth, rho, p_in, u_n)
+            assert rs == 0
+            ref = {q: np.concatenate([ref[q], lay[q]]) for q in ("x", "u", "V", "P", "m")}
+            layers += 1
+    return ref, layers
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_run_open_without_faces_equals_run(lp, precision):
+    """No outflow face and no inflow: lp_run_open on arrays with spare slots
+    gives lp_run's result bit for bit (the absent slots change no ranking)."""
+    say("run_open without faces", precision)
+    cfg, st, h = _channel()
+    n = len(st["V"])
+    a = lp.state_to_device(st)
+    ctx_a = lp.Context(cfg, precision=precision)
+    ctx_a.run(a, 6)
+    assert ctx_a.check() == lp.OK
+    b = lp.state_to_device(_capacity_state(st, n + 777, 2))
+    ctx_b = lp.Context(cfg, precision=precision)
+    assert ctx_b.run_open(b, n, 6) == n
+    assert ctx_b.check() == lp.OK
+    ga, gb = lp.state_to_host(a), lp.state_to_host(_head(b, n))
+    for key in ("x", "u", "V", "P", "m", "phi", "flags"):
+        assert np.array_equal(ga[key], gb[key]), key
+    assert ctx_b.info()["t"] == ctx_a.info()["t"]
+    ctx_a.close()
+    ctx_b.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-4)])
+def test_run_open_outflow_and_inflow_matches_oracle(lp, oracle_lib, precision, tol):
+    """Channel flow through an outflow face at x = 1 with a lattice layer of
+    the inflow state entering at x = 0 every second step, all inside one
+    lp_run_open call of 14 steps replaying one captured step, against the
+    oracle's step, outflow and layer sequence."""
+    say("run_open outflow + inflow", precision)
+    cfg, st, h = _channel()
+    n = len(st["V"])
+    kw = dict(every=2, axis=0, side=0, spacing=h, depth=0.5 * h, rho=1.0, p_in=1.0, u_n=1.0)
+    ref, layers = _oracle_open(oracle_lib, cfg, st, 14, 0, 1, **kw)
+    assert layers == 7 and len(ref["V"]) != n
+    dev = lp.state_to_device(_capacity_state(st, n + 7 * 32 + 5, 2))
+    ctx = lp.Context(cfg, precision=precision)
+    n_out = ctx.run_open(dev, n, 14, out_hi_mask=1, in_every=2, in_axis=0, in_side=0, spacing=h, depth=0.5 * h,
+                         rho=1.0, p_in=1.0, u_n=1.0)
+    assert ctx.check() == lp.OK
+    assert n_out == len(ref["V"])
+    info = ctx.info()
+    assert info["n_captures"] == 1, info
+    got = lp.state_to_host(_head(dev, n_out))
+    assert np.array_equal(got["m"], ref["m"])    # the same particles, in the same order
+    compare_states(got, ref, cfg, tol, "run_open " + precision)
+    ctx.close()
+
+
+def test_run_open_reservoir_matches_oracle(lp, oracle_lib):
+    """The layers take the reservoir state of the particles inside the inflow
+    face at the moment each is written (FP64, 1e-10: the layer's mean
+    pressure is summed in another order)."""
+    say("run_open reservoir inflow")
+    cfg, st, h = _channel(seed=6)
+    n = len(st["V"])
+    res = (2 * h, 1.3, 1.0)
+    ref, layers = _oracle_open(oracle_lib, cfg, st, 12, 0, 1, every=3, axis=0, side=0, spacing=h, depth=0.5 * h,
+                               res=res)
+    assert layers == 4
+    dev = lp.state_to_device(_capacity_state(st, n + 4 * 32, 2))
+    ctx = lp.Context(cfg, precision="fp64")
+    n_out = ctx.run_open(dev, n, 12, out_hi_mask=1, in_every=3, in_axis=0, in_side=0, spacing=h, depth=0.5 * h,
+                         res_width=res[0], res_p=res[1], res_rho=res[2])
+    assert ctx.check() == lp.OK
+    assert n_out == len(ref["V"])
+    compare_states(lp.state_to_host(_head(dev, n_out)), ref, cfg, 1e-10, "run_open reservoir")
+    ctx.close()
+
+
+def test_run_open_layer_past_capacity_stops(lp, oracle_lib):
+    """A layer that does not fit is not written: the run stops after that
+    step, lp_check reports the capacity error, and the arrays are compacted
+    to the particles of that step."""
+    say("run_open capacity")
+    cfg, st, h = _channel()
+    n = len(st["V"])
+    dev = lp.state_to_device(_capacity_state(st, n + 40, 2))     # one layer of 32 fits, two do not
+    ctx = lp.Context(cfg, precision="fp64")
+    kw = dict(in_every=2, in_axis=0, in_side=0, spacing=h, depth=0.5 * h, rho=1.0, p_in=1.0, u_n=1.0)
+    n_out = ctx.run_open(dev, n, 8, out_hi_mask=1, **kw)
+    assert ctx.check() == lp.E_CAPACITY
+    ref, layers = _oracle_open(oracle_lib, cfg, st, 4, 0, 1, every=2, axis=0, side=0, spacing=h, depth=0.5 * h,
+                               rho=1.0, p_in=1.0, u_n=1.0)
+    # steps 1-4 ran; the second layer (after step 4) was refused
+    ref2, _ = _oracle_open(oracle_lib, cfg, st, 3, 0, 1, every=2, axis=0, side=0, spacing=h, depth=0.5 * h,
+                           rho=1.0, p_in=1.0, u_n=1.0)
+    ref4 = oracle_lib.outflow(cfg, oracle_lib.step(cfg, ref2)[0], 0, 1)
+    assert n_out == len(ref4["V"]) == len(ref["V"]) - 32
+    compare_states(lp.state_to_host(_head(dev, n_out)), ref4, cfg, 1e-10, "run_open capacity")
+    with pytest.raises(lp.LpError) as e:
+        ctx.run_open(dev, n_out, 2, out_hi_mask=4)                  # no z axis in 2D
+    assert e.value.status == lp.E_ARG
     ctx.close()
