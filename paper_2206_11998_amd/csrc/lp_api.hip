@@ -625,7 +625,7 @@ static void build_cells(lp_ctx *c, hipStream_t st, const double *const x[3], con
     uint64_t nfin = 1ull << (D * g.L_hi);
     launch_fill_u32(finest, nfin + 1, 0u, st, gate);
     // the sort reads every real slot and ghost (n_in); absent particles (zero
-    // mass, m given) go after every present one
+    // mass, m given) are left out of the cell order
     launch_keys(x, gx, n_real, &c->sc->n_in, (int)n_total, g, D, (uint32_t *)c->key.p, (uint32_t *)c->slot.p,
                 finest, st, gate, m);
     launch_scan_u32(finest, nfin, (uint32_t *)c->scan_tmp.p, nullptr, st, gate);

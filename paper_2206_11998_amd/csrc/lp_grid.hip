@@ -61,7 +61,7 @@ __global__ void k_gate(DevScalars *sc, int n_real, long long cap_ghost, int stop
         sc->dt = 0.0;
     } else {
         sc->n_in = n_real + sc->n_ghost;
-        sc->n_total = n_real - sc->n_dead + sc->n_ghost;  // absent particles sort after every other
+        sc->n_total = n_real - sc->n_dead + sc->n_ghost;  // absent particles stay out of the cell order
     }
 }
 
@@ -356,19 +356,19 @@ __global__ void k_keys(const double *x0, const double *x1, const double *x2, con
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int n_total = *n_total_dev;
     if (i >= n_total) return;
-    uint32_t k;
     if (m && i < n_real && !(m[i] > 0.0)) {
-        // absent: the bucket past the last finest cell, whose start the scan
-        // sets to the number of present particles
-        k = (uint32_t)(1ull << (D * g.L_hi));
-    } else {
-        double p[3];
-        if (i < n_real) { p[0] = x0[i]; p[1] = x1[i]; p[2] = D == 3 ? x2[i] : 0.0; }
-        else { int q = i - n_real; p[0] = g0[q]; p[1] = g1[q]; p[2] = D == 3 ? g2[q] : 0.0; }
-        int c[3] = {0, 0, 0};
-        for (int a = 0; a < D; ++a) c[a] = cell_coord(g, g.L_hi, a, p[a]);
-        k = morton<D>(c);
+        // absent: no cell and no slot (k_scatter skips it); the cell order
+        // holds the present particles only
+        key[i] = LP_KEY_ABSENT;
+        slot[i] = 0u;
+        return;
     }
+    double p[3];
+    if (i < n_real) { p[0] = x0[i]; p[1] = x1[i]; p[2] = D == 3 ? x2[i] : 0.0; }
+    else { int q = i - n_real; p[0] = g0[q]; p[1] = g1[q]; p[2] = D == 3 ? g2[q] : 0.0; }
+    int c[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) c[a] = cell_coord(g, g.L_hi, a, p[a]);
+    const uint32_t k = morton<D>(c);
     key[i] = k;
     slot[i] = atomicAdd(&cnt[k], 1u);
 }
@@ -513,7 +513,9 @@ __global__ void k_scatter(ScatterArgs a, int n_real, const int *n_total_dev, con
                           const uint32_t *slot, const uint32_t *start, int *sorted_id) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= *n_total_dev) return;
-    uint32_t pos = start[key[i]] + slot[i];
+    const uint32_t ki = key[i];
+    if (ki == LP_KEY_ABSENT) return;
+    uint32_t pos = start[ki] + slot[i];
     sorted_id[pos] = i;
     bool real = i < n_real;
     double vals[12];
@@ -909,8 +911,8 @@ void launch_reservoir(const double *xa, const double *P, int n, int side, double
 
 // ---------------------------------------------------------------------------
 // Open boundaries inside the steps of lp_run_open (Sec. 2.2, step 1).  A
-// particle of zero mass is absent: no radius, no ghost, sorted after every
-// present particle, never updated.  At the end of a step that ran (n_total >
+// particle of zero mass is absent: no radius, no ghost, no place in the cell
+// order, never updated.  At the end of a step that ran (n_total >
 // 0): every present particle past an outflow face gets mass 0; the step is
 // counted; after every in_every-th step one inflow layer is written at slot
 // n_hw (the state fixed, or the reservoir state of the layer inside the face

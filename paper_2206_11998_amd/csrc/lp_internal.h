@@ -195,8 +195,10 @@ void launch_ghost_write(const Soa &p, const DevCfg &cfg, DevScalars *sc, const u
                         const double *h, const double *r, Ghosts g, int64_t cap_ghost, hipStream_t st);
 // gate (may be NULL): the kernels do nothing unless *gate != 0 (read on the device)
 void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st, const unsigned *gate = nullptr);
-// m (may be NULL): a real particle of zero mass is absent and goes to the bucket
-// past the last finest cell, i.e. after every present particle of the sort
+// m (may be NULL): a real particle of zero mass is absent: key LP_KEY_ABSENT, no
+// slot, and k_scatter leaves it out, so the cell order holds the present
+// particles (n_total of them) and nothing after them
+#define LP_KEY_ABSENT 0xFFFFFFFFu
 void launch_keys(const double *const x[3], const double *const gx[3], int n_real, const int *n_total_dev,
                  int n_total_cap, const DevGrid &g, int D, uint32_t *key, uint32_t *slot, uint32_t *cnt,
                  hipStream_t st, const unsigned *gate = nullptr, const double *m = nullptr);

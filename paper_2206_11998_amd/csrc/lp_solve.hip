@@ -2158,14 +2158,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const int m = real ? group_lw_select<D>(srt, cfg, nbr, ldn, s, k, xi, sel) : 0;
     __syncthreads();  // sel written by the group's lanes
     double a[ROWS][N3];
-    int jr[ROWS];  // the member in each of the lane's rows (rows past the stencil: the particle itself)
 #pragma unroll
     for (int c = 0; c < ROWS; ++c) {
         const int q = gl + 16 * c;
         const bool in = q < m;
-        jr[c] = in ? sel[q] : (real ? s : 0);
+        const int jrc = in ? sel[q] : (real ? s : 0);
         double dx[3];
-        displacement<D>(srt, cfg, jr[c], xi, dx);
+        displacement<D>(srt, cfg, jrc, xi, dx);
         double x[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int e = 0; e < D; ++e) x[e] = in ? dx[e] / r : 0.0;
@@ -2182,7 +2181,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         const double fi = real ? fs.f[f][s] : 0.0;
         double b[ROWS];
 #pragma unroll
-        for (int c = 0; c < ROWS; ++c) b[c] = real ? fs.f[f][jr[c]] - fi : 0.0;
+        for (int c = 0; c < ROWS; ++c) {
+            const int q = gl + 16 * c;
+            const int jrc = q < m ? sel[q] : (real ? s : 0);
+            b[c] = real ? fs.f[f][jrc] - fi : 0.0;
+        }
         group_qr_solve<N3, ROWS>(a, alpha_all[grp], tau_all[grp], b);
         if (cubic) {
 #pragma unroll
