@@ -214,7 +214,7 @@ __device__ __forceinline__ void unpack_rec(const RecRaw<F32REC> &r, double p[3],
 // t + 2 are in flight (every load is unconditional, with the index clamped
 // to the list, so that no load result passes through a branch).  body(j, dx,
 // f) gets the member's V, u_0..u_{D-1}, P.  Needs srt.rec.
-template <int D, bool F32REC = false, typename F>
+template <int D, bool F32REC = false, bool PER = true, typename F>
 __device__ __forceinline__ void for_lw_stencil_rec(const Sorted &srt, const DevCfg &cfg, const int *nbr, int ldn,
                                                    int s, int k, const double xi[3], F &&body,
                                                    const unsigned long long *octc = nullptr) {
@@ -237,7 +237,7 @@ __device__ __forceinline__ void for_lw_stencil_rec(const Sorted &srt, const DevC
         double p[3], f[D + 2];
         unpack_rec<D, F32REC>(cur, p, f);
         double dx[3];
-        disp_of<D>(cfg, p, xi, dx);
+        disp_of<D, PER>(cfg, p, xi, dx);
         if (k > cap) {
             int o = octant<D>(dx);
             int rho;
@@ -662,12 +662,13 @@ template <int D> struct NetLane {
     bool have;
 };
 
-template <int D, typename T, class DS>
+template <int D, typename T, bool PER = true, class DS>
 __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p, const DevCfg &cfg, DevScalars *sc,
                                                 const int *nbr, int ldn, int s, int i, int k, double dt,
                                                 const double xi[3], const double st[Dim<D>::NF], double h, double r,
                                                 const DS &ds, int lw_status, uint8_t flags,
-                                                const MlpStage *ms = nullptr, NetLane<D> *nl = nullptr) {
+                                                const MlpStage *ms = nullptr, NetLane<D> *nl = nullptr,
+                                                unsigned long long oct = ~0ull) {
     constexpr int NF = Dim<D>::NF, FP = D + 1, NGD = D * (D + 1) / 2;
     // V and P over the particle and its half-ball members (network inputs)
     T vmin = (T)st[0], vmax = (T)st[0], pmin = (T)st[FP], pmax = (T)st[FP];
@@ -687,6 +688,21 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
 #pragma unroll
         for (int q = 0; q < D; ++q) { Sl[q] = 0; Sr[q] = 0; }
         int nl = 0, nr = 0;
+        // the walk ends once both sides are as full as they can get: oct (the
+        // list's members per octant, 8 bits each, or ~0 when unknown) bounds
+        // the members left of the particle along a exactly (octant bit a
+        // clear) and those right of it from above (bit a set: dx_a >= 0)
+        int capl = ucap, capr = ucap;
+        if (oct != ~0ull) {
+            int cl = 0, cr = 0;
+#pragma unroll
+            for (int o = 0; o < (1 << D); ++o) {
+                const int c = (int)((oct >> (8 * o)) & 0xffull);
+                if ((o >> a) & 1) cr += c; else cl += c;
+            }
+            capl = cl < ucap ? cl : ucap;
+            capr = cr < ucap ? cr : ucap;
+        }
         const T fi[3] = {(T)st[0], (T)st[1 + a], (T)st[FP]};
         // a member of an open half-ball of axis a: accumulate it
         auto visit = [&](const double dx[3], const double fr[NF]) {
@@ -736,7 +752,7 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
             int jc = nb_at(nbr, ldn, s, 0), jn = nb_at(nbr, ldn, s, k > 1 ? 1 : 0);
             RecRaw<F32REC> rc;
             load_rec<D, F32REC>(srt, jc, rc);
-            for (int t = 0; t < k && (nl < ucap || nr < ucap); ++t) {
+            for (int t = 0; t < k && (nl < capl || nr < capr); ++t) {
                 const RecRaw<F32REC> cur = rc;
                 jc = jn;
                 load_rec<D, F32REC>(srt, jc, rc);
@@ -744,7 +760,7 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
                 double pj[3], fr[NF];
                 unpack_rec<D, F32REC>(cur, pj, fr);
                 double dx[3];
-                disp_of<D>(cfg, pj, xi, dx);
+                disp_of<D, PER>(cfg, pj, xi, dx);
                 const bool right = dx[a] > 0.0, left = dx[a] < 0.0;
                 if (!((right && nr < ucap) || (left && nl < ucap))) continue;
                 visit(dx, fr);
@@ -762,7 +778,7 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
             walk(std::false_type{});
         } else {
             int jn = k > 0 ? nb_at(nbr, ldn, s, 0) : 0;  // next index loaded one iteration ahead
-            for (int t = 0; t < k && (nl < ucap || nr < ucap); ++t) {
+            for (int t = 0; t < k && (nl < capl || nr < capr); ++t) {
                 const int j = jn;
                 if (t + 1 < k) jn = nb_at(nbr, ldn, s, t + 1);
                 double dx[3];
@@ -1022,7 +1038,8 @@ __device__ __forceinline__ bool lw_refine_tail(const SolveArgs &a, int s, int t,
         const double h = srt.h[s];
         const DerRegs<D> ds{grad, hess};
         return finish_particle<D, float>(srt, a.p, a.cfg, a.sc, a.nbr, a.ldn, s, srt.id[s], k, a.sc->dt, xi, st, h,
-                                         a.cfg.kappa * h, ds, 0, 0, a.ms.feat ? &a.ms : nullptr);
+                                         a.cfg.kappa * h, ds, 0, 0, a.ms.feat ? &a.ms : nullptr, nullptr,
+                                         a.octc ? a.octc[s] : ~0ull);
     } else {
         store_der<D>(a.der, a.ld, t, grad, hess);
         return false;
@@ -1036,7 +1053,7 @@ __device__ __forceinline__ bool lw_refine_tail(const SolveArgs &a, int s, int t,
 // result says whether the caller goes on to the update (false: not a real
 // particle, queued for the FP64 fallback, or queued for refinement, whose
 // kernel finishes the particle)
-template <int D, typename T, bool REFINE, bool REGS = false>
+template <int D, typename T, bool REFINE, bool REGS = false, bool PER = true>
 __device__ __forceinline__ bool lw_fit_one(const SolveArgs &a, int s, int t, float *bout = nullptr,
                                            double *inv_r_out = nullptr) {
     constexpr int NU = Dim<D>::NU, NF = Dim<D>::NF, NG = Dim<D>::NG, NS = Dim<D>::NS, FP = D + 1;
@@ -1090,7 +1107,7 @@ __device__ __forceinline__ bool lw_fit_one(const SolveArgs &a, int s, int t, flo
     // the FP64 record
     constexpr bool F32REC = std::is_same<T, float>::value;
     if (F32REC && srt.recf) {
-        for_lw_stencil_rec<D, F32REC>(
+        for_lw_stencil_rec<D, F32REC, PER>(
             srt, cfg, a.nbr, a.ldn, s, k, xi, [&](int, const double dx[3], const double fr[NF]) { member(dx, fr); },
             a.octc);
     } else if (srt.rec) {
@@ -1184,7 +1201,7 @@ __device__ __forceinline__ bool finish_one(const SolveArgs &a, int s, int t) {
     const double r = cfg.kappa * h;
     const DerMem<D> ds{a.der, a.ld, t};
     return finish_particle<D, T>(srt, a.p, cfg, a.sc, a.nbr, a.ldn, s, i, k, a.sc->dt, xi, st, h, r, ds, 0, 0,
-                                 a.ms.feat ? &a.ms : nullptr);
+                                 a.ms.feat ? &a.ms : nullptr, nullptr, a.octc ? a.octc[s] : ~0ull);
 }
 
 // Work distribution.  WQ_DIRECT: thread t of the grid serves cell-order
@@ -1251,7 +1268,8 @@ template <> struct FusedShared<true> {
     float feat[LP_BLOCK][MLP_IN + 1];  // padded rows: the tile loads spread over the banks
 };
 
-template <int D, int MODE, bool NET>
+// PER: some axis is periodic (else every displacement is a plain difference)
+template <int D, int MODE, bool NET, bool PER>
 __global__ __launch_bounds__(LP_BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void k_fit_finish(SolveArgs a) {
     constexpr int NF = Dim<D>::NF, NU = Dim<D>::NU, FP = D + 1;
     __shared__ FusedShared<NET> sh;
@@ -1268,7 +1286,7 @@ __global__ __launch_bounds__(LP_BLOCK) __attribute__((amdgpu_waves_per_eu(3))) v
     for_work<MODE>(a, a.sc->head[0], [&](int s, int t) {
         float B[NF * NU];
         double inv_r;
-        if (!lw_fit_one<D, float, false, true>(a, s, t, B, &inv_r)) return;
+        if (!lw_fit_one<D, float, false, true, PER>(a, s, t, B, &inv_r)) return;
         const Sorted &srt = a.srt;
         int k = a.count[s];
         if (k > a.cfg.max_nb) k = a.cfg.max_nb;
@@ -1280,9 +1298,9 @@ __global__ __launch_bounds__(LP_BLOCK) __attribute__((amdgpu_waves_per_eu(3))) v
         st[FP] = srt.P[s];
         const double h = srt.h[s];
         const DerCoef<D> ds{B, inv_r};
-        limited += finish_particle<D, float>(srt, a.p, a.cfg, a.sc, a.nbr, a.ldn, s, srt.id[s], k, a.sc->dt, xi,
-                                             st, h, a.cfg.kappa * h, ds, 0, 0, a.ms.feat ? &a.ms : nullptr,
-                                             NET ? &nl : nullptr)
+        limited += finish_particle<D, float, PER>(srt, a.p, a.cfg, a.sc, a.nbr, a.ldn, s, srt.id[s], k, a.sc->dt,
+                                                  xi, st, h, a.cfg.kappa * h, ds, 0, 0, a.ms.feat ? &a.ms : nullptr,
+                                                  NET ? &nl : nullptr, a.octc ? a.octc[s] : ~0ull)
                        ? 1
                        : 0;
         if (NET && nl.have) {
@@ -1404,14 +1422,26 @@ static void launch_solve_t(const SolveArgs &a, int n_total_cap, int block, void 
     gr = gr < 1 ? 1 : (gr > 4096 ? 4096 : gr);
     if constexpr (std::is_same<T, float>::value && !RF) {
         // FP32 fits refined where ill-conditioned (or not at all): fused
+        bool per = false;
+        for (int q = 0; q < D; ++q) per = per || a.cfg.periodic[q] != 0;
         if constexpr (MODE != WQ_PERSISTENT) {
-            if (a.ms.feat && a.ms.theta)
-                hipLaunchKernelGGL((k_fit_finish<D, MODE, true>), dim3(blocks), dim3(block), 0, st, a);
+            const bool net = a.ms.feat && a.ms.theta;
+            if (net && per)
+                hipLaunchKernelGGL((k_fit_finish<D, MODE, true, true>), dim3(blocks), dim3(block), 0, st, a);
+            else if (net)
+                hipLaunchKernelGGL((k_fit_finish<D, MODE, true, false>), dim3(blocks), dim3(block), 0, st, a);
+            else if (per)
+                hipLaunchKernelGGL((k_fit_finish<D, MODE, false, true>), dim3(blocks), dim3(block), 0, st, a);
             else
-                hipLaunchKernelGGL((k_fit_finish<D, MODE, false>), dim3(blocks), dim3(block), 0, st, a);
+                hipLaunchKernelGGL((k_fit_finish<D, MODE, false, false>), dim3(blocks), dim3(block), 0, st, a);
         } else {
-            const unsigned gff = persistent_grid((const void *)k_fit_finish<D, MODE, false>, block, n_total_cap);
-            hipLaunchKernelGGL((k_fit_finish<D, MODE, false>), dim3(gff), dim3(block), 0, st, a);
+            const void *kf = per ? (const void *)k_fit_finish<D, MODE, false, true>
+                                 : (const void *)k_fit_finish<D, MODE, false, false>;
+            const unsigned gff = persistent_grid(kf, block, n_total_cap);
+            if (per)
+                hipLaunchKernelGGL((k_fit_finish<D, MODE, false, true>), dim3(gff), dim3(block), 0, st, a);
+            else
+                hipLaunchKernelGGL((k_fit_finish<D, MODE, false, false>), dim3(gff), dim3(block), 0, st, a);
         }
         if (refine_queue) hipLaunchKernelGGL((k_lw_refine<D, true>), dim3(gr), dim3(64), 0, st, a);
         if (between) between(between_arg);
