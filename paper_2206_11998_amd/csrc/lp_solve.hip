@@ -155,6 +155,62 @@ __device__ __forceinline__ void for_lw_stencil(const Sorted &srt, const DevCfg &
     }
 }
 
+// for_lw_stencil with the positions and fields of the next PF entries in
+// flight (and the index after them): for the latency-bound refinement of a
+// few particles, whose lanes have registers to spare.  body(j, dx, f) gets the
+// member's V, u_0..u_{D-1}, P.  The loop is unrolled PF times, so that the
+// prefetched entries rotate without copies.
+template <int D, int PF, typename F>
+__device__ __forceinline__ void for_lw_stencil_deep(const Sorted &srt, const DevCfg &cfg, const int *nbr, int ldn,
+                                                    int s, int k, const double xi[3], F &&body,
+                                                    const unsigned long long *octc = nullptr) {
+    const int cap = cfg.lw_cap;
+    int Rstar = 1 << 30, rem = 0;
+    if (k > cap) lw_round_limit<D>(srt, cfg, nbr, ldn, s, k, xi, cap, octc, Rstar, rem);
+    if (k <= 0) return;
+    unsigned long long s03 = 0, s47 = 0;
+    int takenR = 0;
+    double rp[PF][3], rf[PF][D + 2];
+    int rj[PF];
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+        rj[q] = nb_at(nbr, ldn, s, q < k ? q : k - 1);
+        position_of<D>(srt, rj[q], rp[q]);
+        gather_fields<D>(srt, rj[q], rf[q]);
+    }
+    int jn = nb_at(nbr, ldn, s, PF < k ? PF : k - 1);  // index of entry t + PF
+    for (int t0 = 0; t0 < k; t0 += PF) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int t = t0 + u;
+            if (t < k) {
+                const int j = rj[u];
+                double p[3], f[D + 2];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) p[q] = rp[u][q];
+#pragma unroll
+                for (int q = 0; q < D + 2; ++q) f[q] = rf[u][q];
+                rj[u] = jn;
+                position_of<D>(srt, jn, rp[u]);
+                gather_fields<D>(srt, jn, rf[u]);
+                jn = nb_at(nbr, ldn, s, t + PF + 1 < k ? t + PF + 1 : k - 1);
+                double dx[3];
+                disp_of<D>(cfg, p, xi, dx);
+                bool take = true;
+                if (k > cap) {
+                    int o = octant<D>(dx);
+                    int rho;
+                    if (o < 4) { rho = (int)((s03 >> (16 * o)) & 0xffff); s03 += 1ull << (16 * o); }
+                    else { rho = (int)((s47 >> (16 * (o - 4))) & 0xffff); s47 += 1ull << (16 * (o - 4)); }
+                    take = rho < Rstar || (rho == Rstar && takenR < rem);
+                    if (rho == Rstar && take) ++takenR;
+                }
+                if (take) body(j, dx, f);
+            }
+        }
+    }
+}
+
 // Raw gather record of a neighbour as loaded: four 16-byte words of the FP64
 // record, or the three (2D: two) of the FP32-field record.
 template <bool F32REC> struct RecRaw;
@@ -662,7 +718,7 @@ template <int D> struct NetLane {
     bool have;
 };
 
-template <int D, typename T, bool PER = true, class DS>
+template <int D, typename T, bool PER = true, int PF = 1, class DS>
 __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p, const DevCfg &cfg, DevScalars *sc,
                                                 const int *nbr, int ldn, int s, int i, int k, double dt,
                                                 const double xi[3], const double st[Dim<D>::NF], double h, double r,
@@ -766,10 +822,40 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
                 visit(dx, fr);
             }
         };
+        // the same walk with the records of the next PF entries in flight
+        // (PF > 1: the refinement's few particles, registers to spare); the
+        // loop is unrolled PF times, so that the records rotate without copies
+        auto walk_deep = [&](auto f32rec) {
+            constexpr bool F32REC = decltype(f32rec)::value;
+            RecRaw<F32REC> ring[PF];
+#pragma unroll
+            for (int q = 0; q < PF; ++q) load_rec<D, F32REC>(srt, nb_at(nbr, ldn, s, q < k ? q : k - 1), ring[q]);
+            int jn = nb_at(nbr, ldn, s, PF < k ? PF : k - 1);  // index of entry t + PF
+            bool go = true;
+            for (int t0 = 0; t0 < k && go; t0 += PF) {
+#pragma unroll
+                for (int u = 0; u < PF; ++u) {
+                    const int t = t0 + u;
+                    go = go && t < k && (nl < capl || nr < capr);
+                    if (go) {
+                        const RecRaw<F32REC> cur = ring[u];
+                        load_rec<D, F32REC>(srt, jn, ring[u]);
+                        jn = nb_at(nbr, ldn, s, t + PF + 1 < k ? t + PF + 1 : k - 1);
+                        double pj[3], fr[NF];
+                        unpack_rec<D, F32REC>(cur, pj, fr);
+                        double dx[3];
+                        disp_of<D, PER>(cfg, pj, xi, dx);
+                        const bool right = dx[a] > 0.0, left = dx[a] < 0.0;
+                        if ((right && nr < ucap) || (left && nl < ucap)) visit(dx, fr);
+                    }
+                }
+            }
+        };
         bool walked = false;
         if constexpr (std::is_same<T, float>::value) {
             if (srt.recf && k > 0) {
-                walk(std::true_type{});
+                if constexpr (PF > 1) walk_deep(std::true_type{});
+                else walk(std::true_type{});
                 walked = true;
             }
         }
@@ -980,7 +1066,7 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
 // factor (R, 1/diag R), as the correction only needs working precision.  The
 // refined coefficients are stored as the particle's derivatives, or (FINISH)
 // go straight on to the particle's update; the result: limited.
-template <int D, bool FINISH>
+template <int D, bool FINISH, int PF = 1>
 __device__ __forceinline__ bool lw_refine_tail(const SolveArgs &a, int s, int t, int k, const double xi[3],
                                                const double st[Dim<D>::NF], double inv_r, const float G[Dim<D>::NG],
                                                const float inv[Dim<D>::NU], const float B[Dim<D>::NF * Dim<D>::NU]) {
@@ -1013,6 +1099,10 @@ __device__ __forceinline__ bool lw_refine_tail(const SolveArgs &a, int s, int t,
         for_lw_stencil_rec<D>(
             srt, a.cfg, a.nbr, a.ldn, s, k, xi, [&](int, const double dx[3], const double fj[NF]) { member(dx, fj); },
             a.octc);
+    } else if constexpr (PF > 1) {
+        for_lw_stencil_deep<D, PF>(
+            srt, a.cfg, a.nbr, a.ldn, s, k, xi, [&](int, const double dx[3], const double fj[NF]) { member(dx, fj); },
+            a.octc);
     } else {
         for_lw_stencil<D>(
             srt, a.cfg, a.nbr, a.ldn, s, k, xi,
@@ -1037,9 +1127,10 @@ __device__ __forceinline__ bool lw_refine_tail(const SolveArgs &a, int s, int t,
     if constexpr (FINISH) {
         const double h = srt.h[s];
         const DerRegs<D> ds{grad, hess};
-        return finish_particle<D, float>(srt, a.p, a.cfg, a.sc, a.nbr, a.ldn, s, srt.id[s], k, a.sc->dt, xi, st, h,
-                                         a.cfg.kappa * h, ds, 0, 0, a.ms.feat ? &a.ms : nullptr, nullptr,
-                                         a.octc ? a.octc[s] : ~0ull);
+        return finish_particle<D, float, true, PF>(srt, a.p, a.cfg, a.sc, a.nbr, a.ldn, s, srt.id[s], k, a.sc->dt,
+                                                   xi, st, h, a.cfg.kappa * h, ds, 0, 0,
+                                                   a.ms.feat ? &a.ms : nullptr, nullptr,
+                                                   a.octc ? a.octc[s] : ~0ull);
     } else {
         store_der<D>(a.der, a.ld, t, grad, hess);
         return false;
@@ -1376,7 +1467,7 @@ __global__ __launch_bounds__(LP_BLOCK) void k_lw_refine(SolveArgs a) {
         for (int q = 0; q < NU; ++q) inv[q] = keep[NG + q];
 #pragma unroll
         for (int q = 0; q < NF * NU; ++q) B[q] = keep[NG + NU + q];
-        limited += lw_refine_tail<D, FINISH>(a, s, t, k, xi, st, inv_r, G, inv, B) ? 1 : 0;
+        limited += lw_refine_tail<D, FINISH, 4>(a, s, t, k, xi, st, inv_r, G, inv, B) ? 1 : 0;
     }
     if (FINISH) block_add_limited(a.sc, limited);
 }
