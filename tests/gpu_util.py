@@ -68,3 +68,28 @@ def compare_phi(got_phi, ref_phi, fp64, tag=""):
     else:
         assert np.all(np.asarray(got_phi) >= 0.0) and np.all(np.asarray(got_phi) <= 1.25)
     return far
+
+
+def accuracy_phi(ns0, ns1, ex_V, ex_u, ex_P, V_scale, u_scale, P_scale):
+    """Per particle, the blend weight phi in [0, 1] whose step lands closest to
+    the exact state: the update is linear in phi, s(phi) = s0 - phi (s0 - s1)
+    with s0 the upwind (phi = 0) and s1 the Lax-Wendroff (phi = 1) result, so
+    the least-squares weight over V, u and P (each scaled) is
+    sum a b / sum b^2 with a = s0 - exact, b = s0 - s1, clipped to [0, 1].
+    NaN where the two results coincide (phi does not matter there).
+    Returns (phi, sum b^2)."""
+    D = ns0["u"].shape[1]
+    terms = [(ns0["V"], ns1["V"], ex_V, V_scale)]
+    terms += [(ns0["u"][:, q], ns1["u"][:, q], ex_u[:, q], u_scale) for q in range(D)]
+    terms += [(ns0["P"], ns1["P"], ex_P, P_scale)]
+    num = np.zeros(len(ex_V))
+    den = np.zeros(len(ex_V))
+    for s0, s1, ex, sc in terms:
+        a = (s0 - ex) / sc
+        b = (s0 - s1) / sc
+        num += a * b
+        den += b * b
+    phi = np.full(len(ex_V), np.nan)
+    ok = den > 1e-30
+    phi[ok] = np.clip(num[ok] / den[ok], 0.0, 1.0)
+    return phi, den

@@ -272,3 +272,127 @@ def test_trained_network_on_sod(lp):
     say("smooth wave: L1 distance of P to the quotient estimator's run: network %.3e, pure upwind %.3e; "
         "network decided %d of %d" % (d_mlp, d_uw, waves["mlp"][1]["n_mlp"], wst["V"].shape[0]))
     assert d_mlp < 0.25 * d_uw
+
+
+def _accuracy_harvest(lp, oracle_lib, cfg, st, exact, T, out):
+    """Inputs and accuracy labels (tests/gpu_util.accuracy_phi) of every step
+    of the quotient-estimator run to T: at each state, one step with phi = 0
+    and one with phi = 1 from it (same dt), scored against the exact state at
+    the end of the step."""
+    from tests.gpu_util import accuracy_phi
+
+    def clone(dev):
+        return {k: ([t.clone() for t in v] if isinstance(v, list) else v.clone()) for k, v in dev.items()}
+
+    ctx = lp.Context(cfg)
+    dev = lp.state_to_device(st)
+    V_s, P_s = st["V"].mean(), st["P"].mean()
+    u_s = np.sqrt(cfg["gamma"] * st["P"] * st["V"]).max()
+    t = 0.0
+    while t < T - 1e-12:
+        f, _, v = ctx.features(dev)
+        host = lp.state_to_host(dev)
+        dt = min(oracle_lib.timestep(cfg, {q: host[q] for q in ("x", "u", "V", "P", "m")}), T - t)
+        ends = []
+        for phi in (0.0, 1.0):
+            c = lp.Context(cfg, estimator="injected")
+            d = clone(dev)
+            d["phi"].fill_(phi)
+            c.step(d, dt)
+            assert c.check() == lp.OK
+            ends.append(lp.state_to_host(d))
+            c.close()
+        rho, u, p = exact(0.5 * (ends[0]["x"] + ends[1]["x"]), t + dt)
+        phi_star, _ = accuracy_phi(ends[0], ends[1], 1.0 / rho, u, p, V_s, u_s, P_s)
+        keep = (v.cpu().numpy() != 0) & np.isfinite(phi_star)
+        idx = torch.from_numpy(np.flatnonzero(keep)).cuda()
+        out.append((f[idx].clone(), torch.from_numpy(phi_star[keep]).float().cuda()))
+        ctx.step(dev, dt)
+        assert ctx.check() == lp.OK
+        t += dt
+    ctx.close()
+
+
+def _sod_exact(x, t):
+    ex = riemann.sample(x[:, 0], t, 0.5, 1.0, 0.0, 1.0, 0.125, 0.0, 0.1)
+    u = np.zeros((len(x), 3))
+    u[:, 0] = ex[:, 1]
+    return ex[:, 0], u, ex[:, 2]
+
+
+def _yee_l2(lp, oracle_lib, dx, T, **kw):
+    """L2 (RMS) errors of P and |u| of the Yee vortex at T against the exact
+    solution, steps as the oracle's timestep gives them."""
+    cfg, st = W.yee_vortex(dx)
+    ctx = lp.Context(cfg, estimator=kw.get("estimator", "plain"))
+    if kw.get("params") is not None:
+        ctx.mlp_set(kw["params"])
+    dev = lp.state_to_device(st)
+    t, n_mlp = 0.0, 0
+    while t < T - 1e-12:
+        host = lp.state_to_host(dev)
+        d = min(oracle_lib.timestep(cfg, {q: host[q] for q in ("x", "u", "V", "P", "m")}), T - t)
+        if kw.get("phi") is not None:
+            dev["phi"].fill_(kw["phi"])
+        ctx.step(dev, d)
+        assert ctx.check() == lp.OK
+        n_mlp += ctx.info()["n_mlp"]
+        t += d
+    s = lp.state_to_host(dev)
+    ctx.close()
+    rho, u, p = W.yee_exact(s["x"], T)
+    eu = np.sqrt(((s["u"] - u) ** 2).sum(axis=1))
+    return np.sqrt(((s["P"] - p) ** 2).mean()), np.sqrt((eu ** 2).mean()), n_mlp
+
+
+def test_network_trained_on_accuracy_targets(lp, oracle_lib):
+    """The network trained to reproduce accuracy, not the quotient estimator:
+    its targets are the blend weights that bring each step closest to the
+    exact solution (accuracy_phi), harvested along Sod tubes (seeds 21, 22)
+    and jittered Yee vortices at dx 0.25 and 0.3.  On resolutions and tubes
+    it has not seen, it must beat the quotient estimator's L2 error of P and
+    u on the Yee vortex at dx 0.2 (t = 8) and stay within 1.15x of its L1
+    error of rho and P on a Sod tube (seed 23, t = 0.1), deciding most
+    particles itself."""
+    harvest = []
+    for seed in (21, 22):
+        cfg, st = W.sod3d(n=128, ny=8, nz=8, seed=seed)
+        _accuracy_harvest(lp, oracle_lib, cfg, st, _sod_exact, 0.1, harvest)
+    n_sod = sum(len(h[1]) for h in harvest)
+    for dx, seed in ((0.25, 3), (0.3, 4)):
+        cfg, st = W.yee_vortex(dx, jitter=0.1, seed=seed)
+        _accuracy_harvest(lp, oracle_lib, cfg, st, W.yee_exact, 2.0, harvest)
+    feat = torch.cat([h[0] for h in harvest])
+    target = torch.cat([h[1] for h in harvest])
+    say("accuracy labels: %d Sod, %d Yee; mean phi* %.3f" % (n_sod, len(target) - n_sod, target.mean().item()))
+    # the Yee samples whole, the Sod samples thinned to four times as many
+    gen = torch.Generator().manual_seed(5)
+    n_yee = len(target) - n_sod
+    pick = torch.randperm(n_sod, generator=gen)[:min(4 * n_yee, n_sod)]
+    sel = torch.cat([pick, torch.arange(n_sod, len(target))])
+    sel = sel[torch.randperm(len(sel), generator=gen)].cuda()
+    fx, tx = feat[sel].contiguous(), (target[sel] / 1.25).contiguous()
+    cfg, st = W.sod3d(n=128, ny=8, nz=8, seed=23)
+    ctx = lp.Context(cfg)
+    ctx.mlp_init(7)
+    losses = ctx.mlp_train(fx, tx, epochs=40, batch=2048, lr=3e-3)
+    say("loss by epoch", np.round(losses[[0, 9, 19, 39]], 4))
+    assert losses[-1] < losses[0]
+    params = ctx.mlp_get()
+    ctx.close()
+    sod = {}
+    for name, kw in (("plain", {}), ("mlp", {"estimator": "mlp", "params": params})):
+        out, info, ok = _sod_run(lp, cfg, st, 0.1, **kw)
+        assert ok, name
+        sod[name] = (_sod_error(out), info)
+        say("unseen Sod, %-5s L1 rho %.5f  L1 p %.5f  network decided %d" % (
+            name, sod[name][0][0], sod[name][0][1], info["n_mlp"]))
+    assert sod["mlp"][1]["n_mlp"] > 0.5 * st["V"].shape[0]
+    assert sod["mlp"][0][0] <= 1.15 * sod["plain"][0][0] and sod["mlp"][0][1] <= 1.15 * sod["plain"][0][1]
+    yee = {}
+    for name, kw in (("plain", {}), ("mlp", {"estimator": "mlp", "params": params}),
+                     ("phi=1", {"estimator": "injected", "phi": 1.0})):
+        yee[name] = _yee_l2(lp, oracle_lib, 0.2, 8.0, **kw)
+        say("Yee dx 0.2, t = 8, %-5s L2 P %.5f  L2 u %.5f  network decisions %d" % ((name,) + yee[name]))
+    assert yee["mlp"][0] < yee["plain"][0] and yee["mlp"][1] < yee["plain"][1]
+    assert yee["mlp"][2] > 0

@@ -131,3 +131,30 @@ def test_features_of_constant_state_vanish(oracle_lib):
     n = st["V"].shape[0]
     out, _ = oracle_lib.step_subset(cfg, st, np.arange(n), features=True)
     assert np.all(out["feat"] == 0.0)
+
+
+def test_accuracy_phi_is_the_least_squares_blend():
+    """The accuracy label of the network's training (tests/gpu_util.py): on
+    random upwind / Lax-Wendroff / exact states it must equal a brute-force
+    minimisation over a fine phi grid of the scaled squared error, clip at 0
+    and 1, and be NaN where both results coincide."""
+    from tests.gpu_util import accuracy_phi
+    rng = np.random.default_rng(11)
+    n, D = 200, 3
+    s0 = {"V": rng.random(n) + 0.5, "u": rng.normal(size=(n, D)), "P": rng.random(n) + 0.5}
+    s1 = {"V": s0["V"] + 0.1 * rng.normal(size=n), "u": s0["u"] + 0.1 * rng.normal(size=(n, D)),
+          "P": s0["P"] + 0.1 * rng.normal(size=n)}
+    s1["V"][:3], s1["u"][:3], s1["P"][:3] = s0["V"][:3], s0["u"][:3], s0["P"][:3]   # phi irrelevant
+    ex = {"V": s0["V"] + 0.08 * rng.normal(size=n), "u": s0["u"] + 0.08 * rng.normal(size=(n, D)),
+          "P": s0["P"] + 0.08 * rng.normal(size=n)}
+    sc = (0.9, 1.7, 1.3)
+    phi, den = accuracy_phi(s0, s1, ex["V"], ex["u"], ex["P"], *sc)
+    assert np.all(np.isnan(phi[:3])) and np.all(den[:3] == 0.0)
+    grid = np.linspace(0.0, 1.0, 20001)
+    for i in range(3, n):
+        err = ((s0["V"][i] - grid * (s0["V"][i] - s1["V"][i]) - ex["V"][i]) / sc[0]) ** 2
+        for q in range(D):
+            err += ((s0["u"][i, q] - grid * (s0["u"][i, q] - s1["u"][i, q]) - ex["u"][i, q]) / sc[1]) ** 2
+        err += ((s0["P"][i] - grid * (s0["P"][i] - s1["P"][i]) - ex["P"][i]) / sc[2]) ** 2
+        assert abs(phi[i] - grid[np.argmin(err)]) <= 1e-4
+    assert np.any(phi[3:] == 0.0) and np.any(phi[3:] == 1.0) and np.any((phi > 0) & (phi < 1))
