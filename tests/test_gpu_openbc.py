@@ -372,3 +372,40 @@ def test_run_open_layer_past_capacity_stops(lp, oracle_lib):
         ctx.run_open(dev, n_out, 2, out_hi_mask=4)                  # no z axis in 2D
     assert e.value.status == lp.E_ARG
     ctx.close()
+
+
+def test_run_open_when_every_particle_leaves(lp):
+    """An outflow face behind every particle: the first step deletes them all,
+    the run stops there (time advanced by that step alone), nothing is
+    reported as an error, and the call returns a count of 0."""
+    say("run_open: every particle leaves")
+    cfg, st, h = _channel()
+    cfg = dict(cfg, box_hi=[1e-9, 1.0])
+    n = len(st["V"])
+    dev = lp.state_to_device(_capacity_state(st, n + 64, 2))
+    ctx = lp.Context(cfg, precision="fp64")
+    assert ctx.run_open(dev, n, 6, out_hi_mask=1) == 0
+    assert ctx.check() == lp.OK
+    info = ctx.info()
+    one = lp.Context(cfg, precision="fp64")
+    ref = lp.state_to_device(st)
+    one.step(ref)
+    assert info["t"] == one.info()["t"] > 0.0
+    ctx.close()
+    one.close()
+
+
+def test_run_open_zero_steps_keeps_the_particles(lp):
+    """nsteps = 0: nothing advances, the spare slots are marked absent and the
+    particles given come back as they were, in order."""
+    say("run_open: zero steps")
+    cfg, st, h = _channel()
+    n = len(st["V"])
+    dev = lp.state_to_device(_capacity_state(st, n + 10, 2))
+    ctx = lp.Context(cfg, precision="fp64")
+    assert ctx.run_open(dev, n, 0, out_hi_mask=1) == n
+    got = lp.state_to_host(_head(dev, n))
+    for key in ("x", "u", "V", "P", "m"):
+        assert np.array_equal(got[key], st[key]), key
+    assert np.all(dev["m"][n:].cpu().numpy() == 0.0)
+    ctx.close()
