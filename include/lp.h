@@ -151,8 +151,9 @@ lp_status lp_neighbors(struct lp_ctx *ctx, void *stream, int64_t n, const double
 /* Caller-owned workspace (the store/solver split of Sec. 2.2: the particle
  * store and the solver's scratch are separate objects).
  *
- * lp_workspace_bytes: the device bytes a time step (lp_step or lp_run) of the
- * particles p needs when every buffer comes from one caller block: the
+ * lp_workspace_bytes: the device bytes a time step (lp_step, lp_run or
+ * lp_run_open; for lp_run_open, p->n is the capacity: every slot is counted)
+ * of the particles p needs when every buffer comes from one caller block: the
  * radii, ghosts, cell tables of the grid planned for p (with lp_run's
  * headroom), cell-order copies, neighbour lists, derivatives and, per the
  * context's configuration, refinement, network and list-reuse buffers.

@@ -1354,7 +1354,15 @@ extern "C" lp_status lp_run_open(lp_ctx *c, void *stream, const lp_particles *p,
     const int64_t n = c->sc_host->n_hw;
     ENSURE(c, c->gcnt, sizeof(uint32_t) * (n + 1));
     ENSURE(c, c->scan_tmp, sizeof(uint32_t) * scan_tmp_words((uint64_t)n));
-    ENSURE(c, c->gfd_fields, out_stage_bytes(D, n));
+    // staging of the compaction: the cell-order arrays, which every step
+    // refills from the caller's arrays, when the run left them large enough
+    double *stage = nullptr;
+    if (c->sorted.p && c->sorted.bytes >= out_stage_bytes(D, n)) {
+        stage = (double *)c->sorted.p;
+    } else {
+        ENSURE(c, c->gfd_fields, out_stage_bytes(D, n));
+        stage = (double *)c->gfd_fields.p;
+    }
     lp_particles r = q;
     r.n = n;
     uint32_t *pos = (uint32_t *)c->gcnt.p;
@@ -1364,7 +1372,7 @@ extern "C" lp_status lp_run_open(lp_ctx *c, void *stream, const lp_particles *p,
     HIPCHK(c, hipMemcpyAsync(&kept, pos + n, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     if ((int64_t)kept < n) {
-        launch_out_compact(soa_of(&r), D, pos, kept, (double *)c->gfd_fields.p, st);
+        launch_out_compact(soa_of(&r), D, pos, kept, stage, st);
         HIPCHK(c, hipGetLastError());
     }
     *n_out = kept;
@@ -1723,6 +1731,7 @@ extern "C" lp_status lp_workspace_bytes(lp_ctx *c, void *stream, const lp_partic
     (void)ensure(c, c->prep_part, sizeof(double) * prep_partial_words(n));
     (void)ensure_capacity(c, n, want, true, mixed);
     if (c->mlp_ready || c->dc.est_mode == LP_EST_MLP) (void)mlp_alloc(c);
+    (void)ensure(c, c->openres, sizeof(double) * (2 * 256 + 4));  // lp_run_open's reservoir sums
     c->measure = false;
     c->cap_real = cr;
     c->cap_total = ct;

@@ -98,3 +98,32 @@ def test_network_parameters_move_into_the_workspace(lp):
     ctx.run(dev, 2)
     assert ctx.check() == lp.OK
     ctx.close()
+
+
+def test_open_run_on_caller_workspace_is_bit_identical(lp):
+    """lp_run_open (outflow and an inflow layer every second step, 14 steps)
+    on a block sized by lp_workspace_bytes for the capacity -- the slots past
+    the particles given absent, as the call makes them -- gives the
+    library-allocated run's result bit for bit, compaction included."""
+    from tests.test_gpu_openbc import _capacity_state, _channel, _head
+    cfg, st, h = _channel()
+    n = len(st["V"])
+    cap = n + 7 * 32 + 5
+    kw = dict(out_hi_mask=1, in_every=2, in_axis=0, in_side=0, spacing=h, depth=0.5 * h, rho=1.0, p_in=1.0, u_n=1.0)
+    res = []
+    for caller in (False, True):
+        ctx = lp.Context(cfg, precision="mixed", refine_cond=1e3)
+        dev = lp.state_to_device(_capacity_state(st, cap, 2))
+        if caller:
+            probe = {k: ([t.clone() for t in v] if isinstance(v, list) else v.clone()) for k, v in dev.items()}
+            probe["m"][n:] = 0.0
+            nbytes = ctx.workspace_bytes(probe)
+            block = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            ctx.set_workspace(block)
+            say("open run workspace: %d bytes for capacity %d" % (nbytes, cap))
+        n_out = ctx.run_open(dev, n, 14, **kw)
+        assert ctx.check() == lp.OK, lp.lib().lp_last_error(ctx._h)
+        res.append((n_out, lp.state_to_host(_head(dev, n_out))))
+        ctx.close()
+    assert res[0][0] == res[1][0]
+    _same(res[1][1], res[0][1], "open run")
