@@ -83,12 +83,15 @@ def cpu_model():
 
 
 def source_hash():
-    """Hash of the kernel sources: HBM counters committed under profiles/ are
-    only reported while the kernels they were taken on are unchanged."""
+    """Hash of the device sources (every file of csrc/ but lp_api.hip, the
+    host-only entry points): HBM counters committed under profiles/ are only
+    reported while the kernels they were taken on are unchanged."""
     import hashlib
     h = hashlib.sha256()
     src = os.path.join(ROOT, "paper_2206_11998_amd", "csrc")
     for f in sorted(os.listdir(src)):
+        if f == "lp_api.hip":
+            continue
         with open(os.path.join(src, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
