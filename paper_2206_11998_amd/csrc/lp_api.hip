@@ -760,6 +760,7 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
     sa.rec = srt.rec;
     sa.recf = srt.recf;
     sa.dim = D;
+    sa.m = p->m;
     {
         const int r3[LP_REC] = {0, 1, 2, 4, 5, 6, 7, 8}, r2[LP_REC] = {0, 1, 4, 5, 6, 8, -1, -1};
         for (int q = 0; q < LP_REC; ++q) sa.rec_src[q] = D == 3 ? r3[q] : r2[q];

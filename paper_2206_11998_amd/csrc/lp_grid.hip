@@ -518,9 +518,13 @@ __global__ void k_scatter(ScatterArgs a, int n_real, const int *n_total_dev, con
     uint32_t pos = start[ki] + slot[i];
     sorted_id[pos] = i;
     bool real = i < n_real;
+    // deleted since the cell order was built: it keeps its slot, out of every
+    // distance test (infinite coordinates) and with no radius (k_prep)
+    const bool gone = real && a.m && !(a.m[i] > 0.0);
     double vals[12];
     for (int d = 0; d < a.nd; ++d) {
         double v = real ? a.src[d][i] : (a.gsrc[d] ? a.gsrc[d][i - n_real] : 0.0);
+        if (gone && d < 3) v = INFINITY;
         vals[d] = v;
         a.dst[d][pos] = v;
     }
@@ -638,7 +642,14 @@ __global__ void k_reuse_decide(DevScalars *sc, int force) {
         }
     }
     sc->rebuild = rb;
-    if (sc->n_total > 0) sc->pop_changed = 0u;  // the cells of this step see the particles as they are
+    if (sc->n_total > 0) {
+        sc->pop_changed = 0u;  // the cells of this step see the particles as they are
+        // a rebuild orders the present particles; otherwise the order of the
+        // last build stands, particles deleted since then included (they are
+        // skipped by every kernel that takes a particle from it)
+        if (rb) sc->n_sorted = sc->n_total;
+        else sc->n_total = sc->n_sorted;
+    }
     if (rb) {
         sc->have_cand = 1u;
         sc->n_builds += 1ull;
@@ -920,9 +931,6 @@ void launch_reservoir(const double *xa, const double *P, int n, int side, double
 // layer raises pop_changed, which makes the next step rebuild its lists.
 // ---------------------------------------------------------------------------
 __global__ void k_open_outflow(Soa p, DevCfg cfg, OpenDev o, DevScalars *sc) {
-    __shared__ int any;
-    if (threadIdx.x == 0) any = 0;
-    __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (sc->n_total > 0 && i < p.n && p.m[i] > 0.0) {
         bool gone = false;
@@ -931,13 +939,8 @@ __global__ void k_open_outflow(Soa p, DevCfg cfg, OpenDev o, DevScalars *sc) {
             if (((o.lo_mask >> a) & 1u) && xa < cfg.lo[a]) gone = true;
             if (((o.hi_mask >> a) & 1u) && xa >= cfg.hi[a]) gone = true;
         }
-        if (gone) {
-            const_cast<double *>(p.m)[i] = 0.0;
-            any = 1;
-        }
+        if (gone) const_cast<double *>(p.m)[i] = 0.0;
     }
-    __syncthreads();
-    if (threadIdx.x == 0 && any) atomicOr(&sc->pop_changed, 1u);
 }
 
 __global__ void k_open_tick(DevScalars *sc, int every) {

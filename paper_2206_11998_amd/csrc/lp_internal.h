@@ -75,7 +75,8 @@ struct DevScalars {
     int n_in;                       // real slots + ghosts: the extent the cell sort reads
     int n_dead;                     // real slots of zero mass (k_prep); n_total = n_in - n_dead
     int n_hw;                       // lp_run_open: slots in use (live or deleted); layers are appended here
-    unsigned int pop_changed;       // a particle was deleted or added since the last list build
+    unsigned int pop_changed;       // a particle was added since the last list build
+    int n_sorted;                   // entries of the cell order of the last build (present then)
     unsigned long long open_k;      // lp_run_open: steps run
     unsigned int insert_now;        // lp_run_open: this step ends with an inflow layer
 };
@@ -177,6 +178,8 @@ struct ScatterArgs {
     float *recf;                    // FP32-field gather records (LP_RECF_BYTES each), or NULL
     int rec_src[LP_REC];            // value index of each record entry (-1: zero)
     int dim;                        // layout of the FP32-field record
+    const double *m;                // masses (caller order) or NULL: a real particle of zero mass that
+                                    // still holds a cell slot gets infinite coordinates (no one's neighbour)
 };
 
 // ---------------------------------------------------------------------------

@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void k_mlp_apply(const float *th, Sorted srt, 
         const int s = item(grp * 64 + l);
         const bool ok = s >= 0 && s < n_total;
         const int i = ok ? srt.id[s] : n_real;
-        const bool mine = ok && i < n_real;
+        const bool mine = ok && i < n_real && srt.h[s] > 0.0;  // not a deleted particle's slot
         // the update's operands are loaded before the network runs, so their
         // latency overlaps the matrix instructions
         double st[NF], lw[NF], uw[NF], xs[D];

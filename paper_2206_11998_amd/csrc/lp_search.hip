@@ -704,7 +704,8 @@ __global__ __launch_bounds__(LP_BLOCK) void k_filter_bal(Sorted srt, const int *
     const unsigned long long below = (1ull << lane) - 1ull;
     const int s = xcd_remap(blockIdx.x, gridDim.x) * PPB + grp;
     const int n_total = *n_total_dev;
-    const bool active = s < n_total && srt.id[s] < n_real;
+    // a particle deleted since the candidates were built has no radius
+    const bool active = s < n_total && srt.id[s] < n_real && srt.r[s] > 0.0;
     BalLds l = bal_lds<G>(smem, lcap, grp);
     int k = 0;
     double r2 = 0.0;

@@ -1152,7 +1152,8 @@ __device__ __forceinline__ bool lw_fit_one(const SolveArgs &a, int s, int t, flo
     const Sorted &srt = a.srt;
     const DevCfg &cfg = a.cfg;
     int i = srt.id[s];
-    if (i >= a.n_real) return false;
+    // ghosts, and particles deleted since the cell order was built (no radius)
+    if (i >= a.n_real || !(srt.h[s] > 0.0)) return false;
     int k = a.count[s];
     if (k > cfg.max_nb) k = cfg.max_nb;
     double xi[3] = {srt.x[0][s], srt.x[1][s], D == 3 ? srt.x[2][s] : 0.0};
@@ -1279,7 +1280,7 @@ __device__ __forceinline__ bool finish_one(const SolveArgs &a, int s, int t) {
     const Sorted &srt = a.srt;
     const DevCfg &cfg = a.cfg;
     int i = srt.id[s];
-    if (i >= a.n_real || a.lwst[s] != 0) return false;
+    if (i >= a.n_real || a.lwst[s] != 0 || !(srt.h[s] > 0.0)) return false;
     int k = a.count[s];
     if (k > cfg.max_nb) k = cfg.max_nb;
     double xi[3] = {srt.x[0][s], srt.x[1][s], D == 3 ? srt.x[2][s] : 0.0};
