@@ -275,10 +275,13 @@ def test_trained_network_on_sod(lp):
 
 
 def _accuracy_harvest(lp, oracle_lib, cfg, st, exact, T, out):
-    """Inputs and accuracy labels (tests/gpu_util.accuracy_phi) of every step
-    of the quotient-estimator run to T: at each state, one step with phi = 0
-    and one with phi = 1 from it (same dt), scored against the exact state at
-    the end of the step."""
+    """Inputs and accuracy labels of every step of the quotient-estimator run
+    to T: at each state, one step with phi = 0 and one with phi = 1 from it
+    (same dt), scored against the exact state at the end of the step.  The
+    label is 1 where the Lax-Wendroff result lands closer (in the scaled
+    squared error over V, u, P) than the upwind one, i.e. where the
+    least-squares blend weight of tests/gpu_util.accuracy_phi exceeds 1/2,
+    else 0."""
     from tests.gpu_util import accuracy_phi
 
     def clone(dev):
@@ -306,7 +309,8 @@ def _accuracy_harvest(lp, oracle_lib, cfg, st, exact, T, out):
         phi_star, _ = accuracy_phi(ends[0], ends[1], 1.0 / rho, u, p, V_s, u_s, P_s)
         keep = (v.cpu().numpy() != 0) & np.isfinite(phi_star)
         idx = torch.from_numpy(np.flatnonzero(keep)).cuda()
-        out.append((f[idx].clone(), torch.from_numpy(phi_star[keep]).float().cuda()))
+        label = (phi_star[keep] > 0.5).astype(np.float32)
+        out.append((f[idx].clone(), torch.from_numpy(label).cuda()))
         ctx.step(dev, dt)
         assert ctx.check() == lp.OK
         t += dt
@@ -347,8 +351,8 @@ def _yee_l2(lp, oracle_lib, dx, T, **kw):
 
 def test_network_trained_on_accuracy_targets(lp, oracle_lib):
     """The network trained to reproduce accuracy, not the quotient estimator:
-    its targets are the blend weights that bring each step closest to the
-    exact solution (accuracy_phi), harvested along Sod tubes (seeds 21, 22)
+    its targets say which pure update (upwind or Lax-Wendroff) brings each
+    step closer to the exact solution, harvested along Sod tubes (seeds 21, 22)
     and jittered Yee vortices at dx 0.25 and 0.3.  On resolutions and tubes
     it has not seen, it must beat the quotient estimator's L2 error of P and
     u on the Yee vortex at dx 0.2 (t = 8) and stay within 1.15x of its L1
@@ -364,7 +368,8 @@ def test_network_trained_on_accuracy_targets(lp, oracle_lib):
         _accuracy_harvest(lp, oracle_lib, cfg, st, W.yee_exact, 2.0, harvest)
     feat = torch.cat([h[0] for h in harvest])
     target = torch.cat([h[1] for h in harvest])
-    say("accuracy labels: %d Sod, %d Yee; mean phi* %.3f" % (n_sod, len(target) - n_sod, target.mean().item()))
+    say("accuracy labels: %d Sod, %d Yee; Lax-Wendroff closer for %.3f" % (n_sod, len(target) - n_sod,
+                                                                      target.mean().item()))
     # the Yee samples whole, the Sod samples thinned to four times as many
     gen = torch.Generator().manual_seed(5)
     n_yee = len(target) - n_sod
