@@ -376,7 +376,10 @@ def test_network_trained_on_accuracy_targets(lp, oracle_lib):
     pick = torch.randperm(n_sod, generator=gen)[:min(4 * n_yee, n_sod)]
     sel = torch.cat([pick, torch.arange(n_sod, len(target))])
     sel = sel[torch.randperm(len(sel), generator=gen)].cuda()
-    fx, tx = feat[sel].contiguous(), (target[sel] / 1.25).contiguous()
+    # targets 0 / 1: the network's output is the probability that the
+    # Lax-Wendroff update lands closer, and phi = min(1, 1.25 y) takes the
+    # full Lax-Wendroff update from a probability of 0.8 on
+    fx, tx = feat[sel].contiguous(), target[sel].contiguous()
     cfg, st = W.sod3d(n=128, ny=8, nz=8, seed=23)
     ctx = lp.Context(cfg)
     ctx.mlp_init(7)
@@ -399,5 +402,5 @@ def test_network_trained_on_accuracy_targets(lp, oracle_lib):
                      ("phi=1", {"estimator": "injected", "phi": 1.0})):
         yee[name] = _yee_l2(lp, oracle_lib, 0.2, 8.0, **kw)
         say("Yee dx 0.2, t = 8, %-5s L2 P %.5f  L2 u %.5f  network decisions %d" % ((name,) + yee[name]))
-    assert yee["mlp"][0] < yee["plain"][0] and yee["mlp"][1] < yee["plain"][1]
+    assert yee["mlp"][0] < 0.5 * yee["plain"][0] and yee["mlp"][1] < 0.5 * yee["plain"][1]
     assert yee["mlp"][2] > 0
