@@ -349,15 +349,14 @@ def _yee_l2(lp, oracle_lib, dx, T, **kw):
     return np.sqrt(((s["P"] - p) ** 2).mean()), np.sqrt((eu ** 2).mean()), n_mlp
 
 
-def test_network_trained_on_accuracy_targets(lp, oracle_lib):
-    """The network trained to reproduce accuracy, not the quotient estimator:
-    its targets say which pure update (upwind or Lax-Wendroff) brings each
-    step closer to the exact solution, harvested along Sod tubes (seeds 21, 22)
-    and jittered Yee vortices at dx 0.25 and 0.3.  On resolutions and tubes
-    it has not seen, it must beat the quotient estimator's L2 error of P and
-    u on the Yee vortex at dx 0.2 (t = 8) and stay within 1.15x of its L1
-    error of rho and P on a Sod tube (seed 23, t = 0.1), deciding most
-    particles itself."""
+_ACC = {}
+
+
+def _accuracy_network(lp, oracle_lib):
+    """Parameters of the network trained on accuracy labels (harvest and
+    training as the test below describes; once per module)."""
+    if "params" in _ACC:
+        return _ACC["params"]
     harvest = []
     for seed in (21, 22):
         cfg, st = W.sod3d(n=128, ny=8, nz=8, seed=seed)
@@ -380,14 +379,28 @@ def test_network_trained_on_accuracy_targets(lp, oracle_lib):
     # Lax-Wendroff update lands closer, and phi = min(1, 1.25 y) takes the
     # full Lax-Wendroff update from a probability of 0.8 on
     fx, tx = feat[sel].contiguous(), target[sel].contiguous()
-    cfg, st = W.sod3d(n=128, ny=8, nz=8, seed=23)
+    cfg, _ = W.sod3d(n=128, ny=8, nz=8, seed=23)
     ctx = lp.Context(cfg)
     ctx.mlp_init(7)
     losses = ctx.mlp_train(fx, tx, epochs=40, batch=2048, lr=3e-3)
     say("loss by epoch", np.round(losses[[0, 9, 19, 39]], 4))
     assert losses[-1] < losses[0]
-    params = ctx.mlp_get()
+    _ACC["params"] = ctx.mlp_get()
     ctx.close()
+    return _ACC["params"]
+
+
+def test_network_trained_on_accuracy_targets(lp, oracle_lib):
+    """The network trained to reproduce accuracy, not the quotient estimator:
+    its targets say which pure update (upwind or Lax-Wendroff) brings each
+    step closer to the exact solution, harvested along Sod tubes (seeds 21, 22)
+    and jittered Yee vortices at dx 0.25 and 0.3.  On resolutions and tubes
+    it has not seen, it must beat the quotient estimator's L2 error of P and
+    u on the Yee vortex at dx 0.2 (t = 8) and stay within 1.15x of its L1
+    error of rho and P on a Sod tube (seed 23, t = 0.1), deciding most
+    particles itself."""
+    params = _accuracy_network(lp, oracle_lib)
+    cfg, st = W.sod3d(n=128, ny=8, nz=8, seed=23)
     sod = {}
     for name, kw in (("plain", {}), ("mlp", {"estimator": "mlp", "params": params})):
         out, info, ok = _sod_run(lp, cfg, st, 0.1, **kw)
@@ -404,3 +417,39 @@ def test_network_trained_on_accuracy_targets(lp, oracle_lib):
         say("Yee dx 0.2, t = 8, %-5s L2 P %.5f  L2 u %.5f  network decisions %d" % ((name,) + yee[name]))
     assert yee["mlp"][0] < 0.5 * yee["plain"][0] and yee["mlp"][1] < 0.5 * yee["plain"][1]
     assert yee["mlp"][2] > 0
+
+
+def test_sedov_blast_with_the_accuracy_network(lp, oracle_lib):
+    """The blast (64 x 32 x 32, Gaussian deposit) with the network trained on
+    accuracy labels as the estimator: 50 graph-replayed mixed steps with every
+    V and P positive, mass unchanged, the network deciding most particles,
+    and the densest particle's radius within 15% of the self-similar blast
+    radius, as the oracle's quotient-estimator run is pinned."""
+    params = _accuracy_network(lp, oracle_lib)
+    cfg, st = W.sedov3d(nx=64)
+    h = 2.0 / 64
+    xc = np.array([32.5, 16.5, 16.5]) * h
+    for name, kw in (("quotient", {}), ("network", {"estimator": "mlp"})):
+        ctx = lp.Context(cfg, precision="mixed", refine_cond=1e3, **kw)
+        if name == "network":
+            ctx.mlp_set(params)
+        dev = lp.state_to_device(st)
+        m0 = ctx.conservation(dev)[0]
+        n_mlp = 0
+        for _ in range(5):
+            ctx.run(dev, 10)
+            assert ctx.check() == lp.OK, (name, lp.lib().lp_last_error(ctx._h))
+            n_mlp += ctx.info()["n_mlp"]
+        info = ctx.info()
+        out = lp.state_to_host(dev)
+        r = np.sqrt(((out["x"] - xc) ** 2).sum(axis=1))
+        R, R0 = r[np.argmax(1.0 / out["V"])], W.sedov_radius(info["t"])
+        say("sedov 64x32x32, %-8s t %.4f: radius of the densest particle %.4f, self-similar %.4f; "
+            "limited %d, network decisions in the last step of each run: %d" % (name, info["t"], R, R0,
+                                                                               info["n_limited"], n_mlp))
+        assert ctx.conservation(dev)[0] == m0
+        assert out["P"].min() > 0.0 and out["V"].min() > 0.0
+        assert R0 > 4 * h and abs(R / R0 - 1.0) < 0.15, name
+        if name == "network":
+            assert info["n_mlp"] > 0.5 * st["V"].shape[0]
+        ctx.close()
