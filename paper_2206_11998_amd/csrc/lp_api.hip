@@ -679,7 +679,14 @@ static lp_status step_impl(lp_ctx *c, hipStream_t st, const lp_particles *p, dou
     }
     stage_mark(c, st, 0, true);
     launch_reset_scalars(c->sc, dt_in, n, sync_levels ? 1 : 0, st);
-    launch_prep(soa, c->dc, c->sc, (double *)c->h.p, (double *)c->r.p, (double *)c->prep_part.p, st);
+    {
+        // the list-reuse check rides on the radii pass, where the last build's
+        // positions and radii cover these particles (else the step rebuilds)
+        const bool chk = reuse_on(c) && c->xb.p && c->Rb.p && c->cap_real >= n;
+        double *xbp[3] = {(double *)c->xb.p, (double *)c->xb.p + c->cap_real, (double *)c->xb.p + 2 * c->cap_real};
+        launch_prep(soa, c->dc, c->sc, (double *)c->h.p, (double *)c->r.p, (double *)c->prep_part.p, st,
+                    chk ? xbp : nullptr, chk ? (const double *)c->Rb.p : nullptr);
+    }
     launch_dt(c->dc, c->sc, clip_t_end, st);
     if (c->nwalls) {
         launch_ghost_count(soa, c->dc, c->sc, (uint32_t *)c->gcnt.p, st);

@@ -82,10 +82,14 @@ __device__ __forceinline__ double wave_max(double v) {
 // Per-block minima of (h/c, r, -r, x_a, -x_a) written to part[block * PREP_W + q],
 // then the block's count of absent particles (zero mass: no radius, no part in
 // the minima); k_prep_final folds the block results (order-free min and an
-// integer count, so exact).
-#define PREP_Q 9
+// integer count, so exact).  With the positions xb and enlarged radii Rb of
+// the last list build (list reuse), the same pass also reduces the reuse
+// check's a = max_i (r_i + d_i - R_i) and d = max_i d_i, d_i = |x_i - xb_i|
+// (minimum image), as minima of their negatives.
+#define PREP_Q 11
 #define PREP_W (PREP_Q + 1)
-__global__ void k_prep(Soa p, DevCfg cfg, double *h_out, double *r_out, double *part) {
+__global__ void k_prep(Soa p, DevCfg cfg, double *h_out, double *r_out, double *part, const double *xb0,
+                       const double *xb1, const double *xb2, const double *Rb) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     double v[PREP_Q];
     for (int q = 0; q < PREP_Q; ++q) v[q] = INFINITY;
@@ -109,6 +113,19 @@ __global__ void k_prep(Soa p, DevCfg cfg, double *h_out, double *r_out, double *
             double x = p.x[a][i];
             v[3 + a] = x;
             v[6 + a] = -x;
+        }
+        if (Rb) {
+            const double *xb[3] = {xb0, xb1, xb2};
+            double d2 = 0.0;
+            for (int a = 0; a < cfg.D; ++a) {
+                const double e = min_image(cfg, a, p.x[a][i] - xb[a][i]);
+                d2 += e * e;
+            }
+            const double di = sqrt(d2);
+            const double ai = r + di - Rb[i];
+            const bool bad = !(ai == ai) || !(di == di);  // NaN positions: rebuild
+            v[9] = bad ? -INFINITY : -ai;
+            v[10] = bad ? -INFINITY : -di;
         }
     }
     __shared__ double red[PREP_Q][LP_BLOCK / 64];
@@ -165,13 +182,19 @@ __global__ void k_prep_final(const double *part, int nblocks, DevScalars *sc) {
                 sc->xlo[a] = dbl_key(m[3 + a]);
                 sc->xhi[a] = dbl_key(-m[6 + a]);
             }
+        if (m[9] < INFINITY) {  // the reuse check ran (and some particle is present)
+            sc->reuse_a = dbl_key(-m[9]);
+            sc->reuse_d = dbl_bits(-m[10]);
+        }
     }
 }
 
 void launch_prep(const Soa &p, const DevCfg &cfg, DevScalars *sc, double *h, double *r, double *part,
-                 hipStream_t st) {
+                 hipStream_t st, double *const xb[3], const double *Rb) {
     unsigned nb = blocks_for(p.n);
-    hipLaunchKernelGGL(k_prep, dim3(nb), dim3(LP_BLOCK), 0, st, p, cfg, h, r, part);
+    const double *x0 = xb ? xb[0] : nullptr, *x1 = xb ? xb[1] : nullptr;
+    const double *x2 = xb ? (cfg.D == 3 ? xb[2] : xb[0]) : nullptr;
+    hipLaunchKernelGGL(k_prep, dim3(nb), dim3(LP_BLOCK), 0, st, p, cfg, h, r, part, x0, x1, x2, xb ? Rb : nullptr);
     hipLaunchKernelGGL(k_prep_final, dim3(1), dim3(1024), 0, st, part, (int)nb, sc);
     CHECK_LAUNCH();
 }
@@ -596,39 +619,9 @@ void launch_coarsen(uint32_t *tables, const DevGrid &g, int D, const int *n_tota
 // |x_j - x_i| < R_i at the rebuild, which the triangle inequality guarantees
 // when r_i + d_i + d_j < R_i for all i, j (d: displacement since the rebuild):
 // max_i (r_i + d_i - R_i) + max_j d_j < 0, checked with a margin of 1e-9 of
-// the smallest radius against rounding.
+// the smallest radius against rounding (the two maxima are reduced by k_prep
+// in the same pass as the radii).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(LP_BLOCK) void k_reuse_check(Soa p, DevCfg cfg, const double *r, const double *xb0,
-                                                          const double *xb1, const double *xb2, const double *Rb,
-                                                          DevScalars *sc) {
-    if (!sc->have_cand || sc->n_total == 0) return;
-    double a = -INFINITY, d = 0.0;
-    const double *xb[3] = {xb0, xb1, xb2};
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < p.n; i += gridDim.x * blockDim.x) {
-        if (!(p.m[i] > 0.0)) continue;  // absent
-        double d2 = 0.0;
-        for (int q = 0; q < cfg.D; ++q) {
-            const double e = min_image(cfg, q, p.x[q][i] - xb[q][i]);
-            d2 += e * e;
-        }
-        const double di = sqrt(d2);
-        const double ai = r[i] + di - Rb[i];
-        if (!(ai == ai) || !(di == di)) { a = INFINITY; d = INFINITY; }  // NaN positions: rebuild
-        a = fmax(a, ai);
-        d = fmax(d, di);
-    }
-    a = wave_max(a);
-    d = wave_max(d);
-    __shared__ double wa[LP_BLOCK / 64], wd[LP_BLOCK / 64];
-    if ((threadIdx.x & 63) == 0) { wa[threadIdx.x >> 6] = a; wd[threadIdx.x >> 6] = d; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int q = 1; q < LP_BLOCK / 64; ++q) { a = fmax(a, wa[q]); d = fmax(d, wd[q]); }
-        atomicMax(&sc->reuse_a, dbl_key(a));
-        atomicMax(&sc->reuse_d, dbl_bits(d));
-    }
-}
-
 __global__ void k_reuse_decide(DevScalars *sc, int force) {
     unsigned rb = 0u;
     if (sc->n_total > 0) {
@@ -674,9 +667,8 @@ __global__ void k_reuse_commit(Soa p, DevCfg cfg, const double *r, double *xb0, 
 void launch_reuse(const Soa &p, const DevCfg &cfg, const double *r, double *const xb[3], double *Rb, int n,
                   double rscale, int force, DevScalars *sc, hipStream_t st) {
     dim3 grid(blocks_for((uint64_t)n));
-    unsigned cb = blocks_for((uint64_t)n, 4 * LP_BLOCK);  // four particles per thread, one atomic pair per block
     double *x2 = cfg.D == 3 ? xb[2] : xb[0];
-    hipLaunchKernelGGL(k_reuse_check, dim3(cb), dim3(LP_BLOCK), 0, st, p, cfg, r, xb[0], xb[1], x2, Rb, sc);
+    // the check's maxima come from k_prep of the same step
     hipLaunchKernelGGL(k_reuse_decide, dim3(1), dim3(1), 0, st, sc, force);
     hipLaunchKernelGGL(k_reuse_commit, grid, dim3(LP_BLOCK), 0, st, p, cfg, r, xb[0], xb[1], x2, Rb, rscale, sc);
     CHECK_LAUNCH();

@@ -189,8 +189,10 @@ void launch_reset_scalars(DevScalars *sc, double dt_in, int n_real, int clear_ha
 void launch_gate(DevScalars *sc, int n_real, int64_t cap_ghost, int stop_on_error, hipStream_t st);
 void launch_rminmax(const double *r, const double *const x[3], int D, int n, DevScalars *sc, hipStream_t st);
 void launch_advance_time(DevScalars *sc, hipStream_t st);
+// xb, Rb (may be NULL): positions and enlarged radii of the last list build;
+// given, the pass also reduces the list-reuse check's maxima
 void launch_prep(const Soa &p, const DevCfg &cfg, DevScalars *sc, double *h, double *r, double *part,
-                 hipStream_t st);
+                 hipStream_t st, double *const xb[3] = nullptr, const double *Rb = nullptr);
 size_t prep_partial_words(int64_t n);
 void launch_dt(const DevCfg &cfg, DevScalars *sc, int clip_t_end, hipStream_t st);
 void launch_ghost_count(const Soa &p, const DevCfg &cfg, DevScalars *sc, uint32_t *gcnt, hipStream_t st);
