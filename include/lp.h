@@ -386,7 +386,7 @@ enum {
                                   planning step from the previous step's longest list, else a
                                   multiple of 8 in 8..128 */
     LP_TUNE_LIST_SKIN = 6,     /* neighbour-list reuse across time steps, in per mille of r: 0 = a full
-                                  search every step; s > 0 (default 150) = a full search within
+                                  search every step; s > 0 (default 250) = a full search within
                                   (1 + s/1000) r only when the last one may miss a neighbour (checked on
                                   the device each step from the displacements since that search and
                                   the growth of r), and in between the exact test d2 < r_i^2 and the

@@ -74,7 +74,7 @@ struct lp_ctx {
     bool want_stage = false;        // keep network-estimator staging allocated (lp_features)
     int queue_tile = 1024;          // LP_TUNE_QUEUE_TILE
     // neighbour-list reuse (LP_TUNE_LIST_SKIN): candidate radius (1 + skin/1000) r
-    int list_skin = 150;
+    int list_skin = 250;
     uint64_t reuse_gen = 0;         // workspace generation the device candidate set belongs to
     lp_particles reuse_p;           // particle arrays it was built for
     int reuse_skin = -1;            // skin it was built with
