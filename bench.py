@@ -258,6 +258,7 @@ def openbc_leg(lp, torch, cfg, st, log, no_cpu):
                            "achieved_gbs": 77.0 * (n_new - kept) / (lms * 1e-3) / 1e9}
     log("outflow: %d of %d kept in %.3f ms (%.0f GB/s algorithmic); inflow layer of %d in %.3f ms"
         % (kept, n, ms, achieved, n_new - kept, lms))
+    res["run_open"] = run_open_leg(lp, torch, cfg, st, log)
     if not no_cpu:
         try:
             import oracle
@@ -271,6 +272,42 @@ def openbc_leg(lp, torch, cfg, st, log, no_cpu):
             log("open-boundary oracle unavailable:", repr(exc))
     ctx.close()
     return res
+
+
+def run_open_leg(lp, torch, cfg, st, log, steps=20):
+    """lp_run_open on the workload with an outflow face at x = 0.2 (a cap of
+    the cloud leaves in the first step, then what the expansion carries across
+    the face every step): the mixed step with the deletions inside the
+    graph-replayed steps and the compaction at the end of the call.  Timed:
+    one call of `steps` steps (its planning step, capture and compaction
+    included) after a one-step call that removes the cap."""
+    n = st["V"].shape[0]
+    cap = n + 65536
+    full = {"x": np.zeros((cap, 3)), "u": np.zeros((cap, 3)), "V": np.ones(cap), "P": np.ones(cap),
+            "m": np.zeros(cap)}
+    for k in full:
+        full[k][:n] = st[k]
+    ocfg = dict(cfg, box_hi=[0.2] + list(cfg["box_hi"][1:]))
+    ctx = lp.Context(ocfg, precision="mixed", refine_cond=1e3)
+    dev = lp.state_to_device(full)
+    n1 = ctx.run_open(dev, n, 1, out_hi_mask=1)
+    i0 = ctx.info()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n2 = ctx.run_open(dev, n1, steps, out_hi_mask=1)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    i1 = ctx.info()
+    status = ctx.check()
+    ctx.close()
+    out = {"steps": steps, "ms_per_step": ms / steps, "n_before": int(n1), "n_after": int(n2),
+           "captures": int(i1["n_captures"] - i0["n_captures"]),
+           "list_builds": int(i1["n_list_builds"] - i0["n_list_builds"]), "status": int(status),
+           "note": "outflow face x >= 0.2 inside lp_run_open (mixed, refine_cond 1e3); one call, planning "
+                   "step and final compaction included"}
+    log("lp_run_open: %d steps in %.2f ms (%.3f ms/step), %d -> %d particles, %d capture(s), %d list builds"
+        % (steps, ms, ms / steps, n1, n2, out["captures"], out["list_builds"]))
+    return out
 
 
 def main():
