@@ -88,17 +88,23 @@ __device__ __forceinline__ double wave_max(double v) {
 // (minimum image), as minima of their negatives.
 #define PREP_Q 11
 #define PREP_W (PREP_Q + 1)
+#define PREP_PER 4  // particles per thread (the block reduction is paid once for them)
 __global__ void k_prep(Soa p, DevCfg cfg, double *h_out, double *r_out, double *part, const double *xb0,
                        const double *xb1, const double *xb2, const double *Rb) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
     double v[PREP_Q];
     for (int q = 0; q < PREP_Q; ++q) v[q] = INFINITY;
     int dead = 0;
-    if (i < p.n && !(p.m[i] > 0.0)) {
-        h_out[i] = 0.0;
-        r_out[i] = 0.0;
-        dead = 1;
-    } else if (i < p.n) {
+    const int base = blockIdx.x * blockDim.x * PREP_PER + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < PREP_PER; ++u) {
+        const int i = base + u * (int)blockDim.x;
+        if (i >= p.n) break;
+        if (!(p.m[i] > 0.0)) {
+            h_out[i] = 0.0;
+            r_out[i] = 0.0;
+            ++dead;
+            continue;
+        }
         double V = p.V[i], P = p.P[i], m = p.m[i];
         double mv = m * V;
         double h = cfg.D == 3 ? cbrt(mv) : sqrt(mv);
@@ -106,13 +112,13 @@ __global__ void k_prep(Soa p, DevCfg cfg, double *h_out, double *r_out, double *
         double r = cfg.kappa * h;
         h_out[i] = h;
         r_out[i] = r;
-        v[0] = h / c;
-        v[1] = r;
-        v[2] = -r;
+        v[0] = fmin(v[0], h / c);
+        v[1] = fmin(v[1], r);
+        v[2] = fmin(v[2], -r);
         for (int a = 0; a < cfg.D; ++a) {
             double x = p.x[a][i];
-            v[3 + a] = x;
-            v[6 + a] = -x;
+            v[3 + a] = fmin(v[3 + a], x);
+            v[6 + a] = fmin(v[6 + a], -x);
         }
         if (Rb) {
             const double *xb[3] = {xb0, xb1, xb2};
@@ -124,8 +130,8 @@ __global__ void k_prep(Soa p, DevCfg cfg, double *h_out, double *r_out, double *
             const double di = sqrt(d2);
             const double ai = r + di - Rb[i];
             const bool bad = !(ai == ai) || !(di == di);  // NaN positions: rebuild
-            v[9] = bad ? -INFINITY : -ai;
-            v[10] = bad ? -INFINITY : -di;
+            v[9] = fmin(v[9], bad ? -INFINITY : -ai);
+            v[10] = fmin(v[10], bad ? -INFINITY : -di);
         }
     }
     __shared__ double red[PREP_Q][LP_BLOCK / 64];
@@ -191,7 +197,7 @@ __global__ void k_prep_final(const double *part, int nblocks, DevScalars *sc) {
 
 void launch_prep(const Soa &p, const DevCfg &cfg, DevScalars *sc, double *h, double *r, double *part,
                  hipStream_t st, double *const xb[3], const double *Rb) {
-    unsigned nb = blocks_for(p.n);
+    unsigned nb = blocks_for(p.n, LP_BLOCK * PREP_PER);
     const double *x0 = xb ? xb[0] : nullptr, *x1 = xb ? xb[1] : nullptr;
     const double *x2 = xb ? (cfg.D == 3 ? xb[2] : xb[0]) : nullptr;
     hipLaunchKernelGGL(k_prep, dim3(nb), dim3(LP_BLOCK), 0, st, p, cfg, h, r, part, x0, x1, x2, xb ? Rb : nullptr);
