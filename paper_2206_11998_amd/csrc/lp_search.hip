@@ -731,7 +731,11 @@ __global__ __launch_bounds__(LP_BLOCK) void k_filter_bal(Sorted srt, const int *
         kc = kc < cfg.max_nb ? kc : cfg.max_nb;
         // indices of rounds t0 / t0 + 2G are in ja/jb and na/nb; slots past
         // the end read the particle itself (a valid index, never a hit)
-        auto index_at = [&](int t) -> int { return t < kc ? cand[list_at(ldc, s, t, cfg.max_nb)] : s; };
+        // entry t of the candidate list at cbase + t cstep (list_at's layouts)
+        const int64_t cbase = ldc > 0 ? (int64_t)s : ldc < 0 ? (int64_t)s * (-ldc)
+                                                            : (int64_t)(s >> 3) * (8 * cfg.max_nb) + (s & 7);
+        const int64_t cstep = ldc > 0 ? (int64_t)ldc : ldc < 0 ? 1 : 8;
+        auto index_at = [&](int t) -> int { return t < kc ? cand[cbase + t * cstep] : s; };
         int ja = index_at(lane), jb = index_at(lane + G);
         int na = index_at(lane + 2 * G), nb = index_at(lane + 3 * G);
         double pa[3] = {0.0, 0.0, 0.0}, pb[3] = {0.0, 0.0, 0.0};
