@@ -2120,8 +2120,22 @@ __device__ __forceinline__ int group_lw_select(const Sorted &srt, const DevCfg &
     return m;
 }
 
+// The rows of a 16-lane group's system, ROWS slots per lane: the first RR
+// in registers, the others (at most one) in LDS, column j of that slot at
+// l[64 j] (l: this lane's entry of a 64-lane array, so that the lanes of a
+// wave read consecutive words).  Indices fold to constants where the
+// callers' loops are unrolled.
+template <int N, int RR>
+struct GroupRows {
+    static constexpr int kRR = RR;
+    double r[RR][N];
+    double *l;
+    __device__ __forceinline__ double &operator()(int c, int j) { return c < RR ? r[c][j] : l[64 * j]; }
+    __device__ __forceinline__ double operator()(int c, int j) const { return c < RR ? r[c][j] : l[64 * j]; }
+};
+
 // Pivoted Householder QR of a 16-lane group's rows.  Row q of the system
-// (q < 16 ROWS; rows past the stencil are zero) is a[q / 16][.] of lane q % 16.
+// (q < 16 ROWS; rows past the stencil are zero) is a(q / 16, .) of lane q % 16.
 // The pivot is the remaining column of largest norm over the remaining rows.
 // Each dot product adds the lane's rows, then the 16 lanes (DPP row sums,
 // every lane of the wave takes part).  On return a holds R above the
@@ -2129,8 +2143,8 @@ __device__ __forceinline__ int group_lw_select(const Sorted &srt, const DevCfg &
 // diagonal); the group's LDS arrays hold the column order perm, R's diagonal
 // alpha and the reflector scales tau (written by lane 0).  Returns
 // |R11| / |Rnn|.
-template <int N, int ROWS>
-__device__ __forceinline__ double group_qrp(double a[ROWS][N], int *perm, double *alpha_out, double *tau_out) {
+template <int N, int ROWS, class M>
+__device__ __forceinline__ double group_qrp(M &a, int *perm, double *alpha_out, double *tau_out) {
     const int gl = threadIdx.x & 15;
     if (gl == 0)
         for (int j = 0; j < N; ++j) perm[j] = j;
@@ -2150,7 +2164,7 @@ __device__ __forceinline__ double group_qrp(double a[ROWS][N], int *perm, double
 #pragma clang loop unroll(full)
                 for (int c = 0; c < ROWS; ++c)
                     if (16 * c + 15 >= p)  // else every row of slot c is above p
-                        part[e] += (16 * c >= p || gl + 16 * c >= p) ? a[c][j] * a[c][j] : 0.0;
+                        part[e] += (16 * c >= p || gl + 16 * c >= p) ? a(c, j) * a(c, j) : 0.0;
             }
             row_sum16_k<3>(part);
 #pragma clang loop unroll(full)
@@ -2162,20 +2176,26 @@ __device__ __forceinline__ double group_qrp(double a[ROWS][N], int *perm, double
         }
         // best is the same in the 16 lanes of a group (groups differ); the
         // swap is written as selects, so that every column keeps a register
+        // (a slot in LDS swaps its two words by address)
 #pragma clang loop unroll(full)
         for (int j = p + 1; j < N; ++j) {
             const bool sw = j == best;
 #pragma clang loop unroll(full)
-            for (int c = 0; c < ROWS; ++c) {
-                const double t = a[c][p], u = a[c][j];
-                a[c][p] = sw ? u : t;
-                a[c][j] = sw ? t : u;
+            for (int c = 0; c < ROWS && c < M::kRR; ++c) {
+                const double t = a(c, p), u = a(c, j);
+                a(c, p) = sw ? u : t;
+                a(c, j) = sw ? t : u;
             }
         }
-        const double x0 = row_bcast16(a[p / 16][p], p % 16);
+        if constexpr (ROWS > M::kRR) {
+            const double t = a.l[64 * p], u = a.l[64 * best];
+            a.l[64 * p] = u;
+            a.l[64 * best] = t;
+        }
+        const double x0 = row_bcast16(a(p / 16, p), p % 16);
         double sg = 0.0;
 #pragma clang loop unroll(full)
-        for (int c = 0; c < ROWS; ++c) sg += gl + 16 * c > p ? a[c][p] * a[c][p] : 0.0;
+        for (int c = 0; c < ROWS; ++c) sg += gl + 16 * c > p ? a(c, p) * a(c, p) : 0.0;
         const double sigma = row_sum16(sg);
         const double normx = sqrt(x0 * x0 + sigma);
         // a zero column (normx = 0) leaves the rows as they are: tau = 0
@@ -2186,8 +2206,8 @@ __device__ __forceinline__ double group_qrp(double a[ROWS][N], int *perm, double
 #pragma clang loop unroll(full)
         for (int c = 0; c < ROWS; ++c) {
             const int q = gl + 16 * c;
-            v[c] = q == p ? v0 : (q > p ? a[c][p] : 0.0);
-            a[c][p] = q == p ? v0 : a[c][p];
+            v[c] = q == p ? v0 : (q > p ? a(c, p) : 0.0);
+            a(c, p) = q == p ? v0 : a(c, p);
         }
         // the reflector applied to the remaining columns, three at a time
 #pragma clang loop unroll(full)
@@ -2198,7 +2218,7 @@ __device__ __forceinline__ double group_qrp(double a[ROWS][N], int *perm, double
                 const int j = j0 + e < N ? j0 + e : N - 1;
                 d[e] = 0.0;
 #pragma clang loop unroll(full)
-                for (int c = 0; c < ROWS; ++c) d[e] += v[c] * a[c][j];
+                for (int c = 0; c < ROWS; ++c) d[e] += v[c] * a(c, j);
             }
             row_sum16_k<3>(d);
 #pragma clang loop unroll(full)
@@ -2206,7 +2226,7 @@ __device__ __forceinline__ double group_qrp(double a[ROWS][N], int *perm, double
                 if (j0 + e < N) {
                     const double w = d[e] * tau;
 #pragma clang loop unroll(full)
-                    for (int c = 0; c < ROWS; ++c) a[c][j0 + e] -= w * v[c];
+                    for (int c = 0; c < ROWS; ++c) a(c, j0 + e) -= w * v[c];
                 }
         }
         if (gl == 0) {
@@ -2227,20 +2247,20 @@ __device__ __forceinline__ double group_qrp(double a[ROWS][N], int *perm, double
 // Least squares for one right-hand side from group_qrp's factors: the
 // reflectors applied to b (row q in b[q / 16] of lane q % 16), then back
 // substitution; on return row p of b holds the solution for unknown perm[p].
-template <int N, int ROWS>
-__device__ __forceinline__ void group_qr_solve(const double a[ROWS][N], const double *alpha, const double *tau,
+template <int N, int ROWS, class M>
+__device__ __forceinline__ void group_qr_solve(const M &a, const double *alpha, const double *tau,
                                                double b[ROWS]) {
     const int gl = threadIdx.x & 15;
 #pragma unroll
     for (int p = 0; p < N; ++p) {
         double d = 0.0;
 #pragma unroll
-        for (int c = 0; c < ROWS; ++c) d += gl + 16 * c >= p ? a[c][p] * b[c] : 0.0;
+        for (int c = 0; c < ROWS; ++c) d += gl + 16 * c >= p ? a(c, p) * b[c] : 0.0;
         const double w = row_sum16(d) * tau[p];
 #pragma unroll
-        for (int c = 0; c < ROWS; ++c) b[c] -= gl + 16 * c >= p ? w * a[c][p] : 0.0;
+        for (int c = 0; c < ROWS; ++c) b[c] -= gl + 16 * c >= p ? w * a(c, p) : 0.0;
     }
-    // row p of R: alpha[p] on the diagonal, a[p / 16][j > p] of lane p % 16
+    // row p of R: alpha[p] on the diagonal, a(p / 16, j > p) of lane p % 16
 #pragma unroll
     for (int p = N - 1; p >= 0; --p) {
         const double dg = alpha[p];
@@ -2249,7 +2269,7 @@ __device__ __forceinline__ void group_qr_solve(const double a[ROWS][N], const do
         if (gl == p % 16) b[p / 16] = yp;
 #pragma unroll
         for (int c = 0; c < ROWS; ++c)
-            if (gl + 16 * c < p) b[c] -= a[c][p] * yp;
+            if (gl + 16 * c < p) b[c] -= a(c, p) * yp;
     }
 }
 
@@ -2263,6 +2283,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
                                              const int *count, int n, DevCfg cfg, DevScalars *sc, int *queue,
                                              double *deriv, uint8_t *status) {
     constexpr int N3 = Dim3<D>::NU, ROWS = 4;
+    // 3D: the fourth row slot of every lane in LDS (registers for the rest)
+    constexpr int RR = D == 3 ? 3 : 4;
+    __shared__ double row4[RR < ROWS ? N3 * 64 : 1];
     __shared__ int sel_all[4][64];
     __shared__ int perm_all[4][32];
     __shared__ double alpha_all[4][32], tau_all[4][32];
@@ -2279,7 +2302,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const double r = real ? srt.r[s] : 1.0;
     const int m = real ? group_lw_select<D>(srt, cfg, nbr, ldn, s, k, xi, sel) : 0;
     __syncthreads();  // sel written by the group's lanes
-    double a[ROWS][N3];
+    GroupRows<N3, RR> a;
+    a.l = row4 + (threadIdx.x & 63);
 #pragma unroll
     for (int c = 0; c < ROWS; ++c) {
         const int q = gl + 16 * c;
@@ -2293,7 +2317,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         double row[N3];
         third_order_row<D>(x, row);
 #pragma unroll
-        for (int u = 0; u < N3; ++u) a[c][u] = row[u];
+        for (int u = 0; u < N3; ++u) a(c, u) = row[u];
     }
     const double cond = group_qrp<N3, ROWS>(a, perm, alpha_all[grp], tau_all[grp]);
     __syncthreads();  // perm, alpha and tau written by lane 0 of each group
