@@ -160,7 +160,7 @@ __device__ __forceinline__ void for_lw_stencil(const Sorted &srt, const DevCfg &
 // few particles, whose lanes have registers to spare.  body(j, dx, f) gets the
 // member's V, u_0..u_{D-1}, P.  The loop is unrolled PF times, so that the
 // prefetched entries rotate without copies.
-template <int D, int PF, typename F>
+template <int D, int PF, bool PER = true, typename F>
 __device__ __forceinline__ void for_lw_stencil_deep(const Sorted &srt, const DevCfg &cfg, const int *nbr, int ldn,
                                                     int s, int k, const double xi[3], F &&body,
                                                     const unsigned long long *octc = nullptr) {
@@ -195,7 +195,7 @@ __device__ __forceinline__ void for_lw_stencil_deep(const Sorted &srt, const Dev
                 gather_fields<D>(srt, jn, rf[u]);
                 jn = nb_at(nbr, ldn, s, t + PF + 1 < k ? t + PF + 1 : k - 1);
                 double dx[3];
-                disp_of<D>(cfg, p, xi, dx);
+                disp_of<D, PER>(cfg, p, xi, dx);
                 bool take = true;
                 if (k > cap) {
                     int o = octant<D>(dx);
@@ -1066,7 +1066,7 @@ __device__ __forceinline__ bool finish_particle(const Sorted &srt, const Soa &p,
 // factor (R, 1/diag R), as the correction only needs working precision.  The
 // refined coefficients are stored as the particle's derivatives, or (FINISH)
 // go straight on to the particle's update; the result: limited.
-template <int D, bool FINISH, int PF = 1>
+template <int D, bool FINISH, int PF = 1, bool PER = true>
 __device__ __forceinline__ bool lw_refine_tail(const SolveArgs &a, int s, int t, int k, const double xi[3],
                                                const double st[Dim<D>::NF], double inv_r, const float G[Dim<D>::NG],
                                                const float inv[Dim<D>::NU], const float B[Dim<D>::NF * Dim<D>::NU]) {
@@ -1100,7 +1100,7 @@ __device__ __forceinline__ bool lw_refine_tail(const SolveArgs &a, int s, int t,
             srt, a.cfg, a.nbr, a.ldn, s, k, xi, [&](int, const double dx[3], const double fj[NF]) { member(dx, fj); },
             a.octc);
     } else if constexpr (PF > 1) {
-        for_lw_stencil_deep<D, PF>(
+        for_lw_stencil_deep<D, PF, PER>(
             srt, a.cfg, a.nbr, a.ldn, s, k, xi, [&](int, const double dx[3], const double fj[NF]) { member(dx, fj); },
             a.octc);
     } else {
@@ -1127,7 +1127,7 @@ __device__ __forceinline__ bool lw_refine_tail(const SolveArgs &a, int s, int t,
     if constexpr (FINISH) {
         const double h = srt.h[s];
         const DerRegs<D> ds{grad, hess};
-        return finish_particle<D, float, true, PF>(srt, a.p, a.cfg, a.sc, a.nbr, a.ldn, s, srt.id[s], k, a.sc->dt,
+        return finish_particle<D, float, PER, PF>(srt, a.p, a.cfg, a.sc, a.nbr, a.ldn, s, srt.id[s], k, a.sc->dt,
                                                    xi, st, h, a.cfg.kappa * h, ds, 0, 0,
                                                    a.ms.feat ? &a.ms : nullptr, nullptr,
                                                    a.octc ? a.octc[s] : ~0ull);
@@ -1442,8 +1442,8 @@ __global__ __launch_bounds__(LP_BLOCK) __attribute__((amdgpu_waves_per_eu(3))) v
 // the refinement step from the factor and FP32 solution the fit stored, so
 // that each result is the always-refining launch's; after the fused kernel
 // (FINISH) each refined particle is updated here.  Grid-stride over the
-// device-side queue length.
-template <int D, bool FINISH>
+// device-side queue length.  PER: some axis is periodic.
+template <int D, bool FINISH, bool PER = true>
 __global__ __launch_bounds__(LP_BLOCK) void k_lw_refine(SolveArgs a) {
     constexpr int NU = Dim<D>::NU, NF = Dim<D>::NF, NG = Dim<D>::NG, FP = D + 1;
     const int n = a.sc->n_refine;
@@ -1468,7 +1468,7 @@ __global__ __launch_bounds__(LP_BLOCK) void k_lw_refine(SolveArgs a) {
         for (int q = 0; q < NU; ++q) inv[q] = keep[NG + q];
 #pragma unroll
         for (int q = 0; q < NF * NU; ++q) B[q] = keep[NG + NU + q];
-        limited += lw_refine_tail<D, FINISH, 4>(a, s, t, k, xi, st, inv_r, G, inv, B) ? 1 : 0;
+        limited += lw_refine_tail<D, FINISH, 4, PER>(a, s, t, k, xi, st, inv_r, G, inv, B) ? 1 : 0;
     }
     if (FINISH) block_add_limited(a.sc, limited);
 }
@@ -1535,7 +1535,12 @@ static void launch_solve_t(const SolveArgs &a, int n_total_cap, int block, void 
             else
                 hipLaunchKernelGGL((k_fit_finish<D, MODE, false, false>), dim3(gff), dim3(block), 0, st, a);
         }
-        if (refine_queue) hipLaunchKernelGGL((k_lw_refine<D, true>), dim3(gr), dim3(64), 0, st, a);
+        if (refine_queue) {
+            if (per)
+                hipLaunchKernelGGL((k_lw_refine<D, true, true>), dim3(gr), dim3(64), 0, st, a);
+            else
+                hipLaunchKernelGGL((k_lw_refine<D, true, false>), dim3(gr), dim3(64), 0, st, a);
+        }
         if (between) between(between_arg);
         return;
     }
